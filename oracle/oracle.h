@@ -1,0 +1,83 @@
+/*
+ * PUFE assembly oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded FP64 CPU implementation of what the PUFE
+ * hot path computes (Pask & Sukumar, "Partition of unity finite element
+ * method for quantum mechanical materials calculations"):
+ *   - the enriched basis of the PUFE trial function (eq. psih / pufebasis),
+ *   - the adaptive per-element quadrature rule (section "Adaptive quadrature"),
+ *   - the Galerkin matrices H and S of the discrete generalized eigenproblem
+ *     (eq. disceig3d) under Bloch boundary conditions (eq. bloch, wbpspace),
+ *   - the adjoint of that assembly (dL/dV and dL/dtau for L = Re<P,H> + Re<Q,S>).
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this library.  It shares no code, header or table with the HIP library.
+ */
+#ifndef PUFE_ORACLE_H
+#define PUFE_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double lat[9];        /* rows a_1, a_2, a_3 (bohr) */
+    int mesh[3];          /* elements along each lattice vector */
+    int fe_order;         /* 1 trilinear, 2 triquadratic; 3 = 32-node serendipity topology only */
+    int n_atoms;
+    const double *pos;    /* n_atoms x 3 Cartesian */
+    const int *species;   /* n_atoms */
+    int n_enr;            /* enrichment descriptors */
+    const int *enr_species, *enr_l;
+    const double *enr_a, *enr_rc, *enr_re;
+    int q_n, q_nref, q_levels, q_mode;  /* q_mode 0 = geometric, 1 = error-driven */
+    double q_dist, q_tol;
+} or_problem;
+
+typedef struct or_state or_state;
+
+/* Returns 0 on success, a negative code on invalid input. */
+int or_setup(const or_problem *p, or_state **out);
+void or_free(or_state *s);
+/* sizes: [n_elem, n_vertex, n_dof, n_qp, n_fe_slots, max_nloc, n_leaves] */
+void or_sizes(const or_state *s, int64_t *out7);
+void or_dof_offset(const or_state *s, int64_t *out /* n_vertex+1 */);
+/* enriched functions of vertex v: (atom, desc, m) triples, returns count */
+int or_vertex_functions(const or_state *s, int64_t v, int *out /* 3*count */);
+void or_quadrature(const or_state *s, double *xyz, double *w, int64_t *elem_qp_off);
+/* leaves: level and integer coordinates at that level, element-major DFS */
+void or_leaves(const or_state *s, int *level, int *ijk, int64_t *elem_leaf_off);
+int or_element_nloc(const or_state *s, int64_t e);
+/* global dof and lattice shift (3 ints) of each local function of element e */
+void or_element_dofs(const or_state *s, int64_t e, int64_t *gdof, int *shift);
+/* real element matrices (nloc x nloc, row-major) from V at the element's qps */
+void or_element_matrices(const or_state *s, int64_t e, const double *V_elem,
+                         double *He, double *Se);
+/* dense complex Bloch-periodic H, S (N x N interleaved re,im), kappa reduced */
+void or_assemble_dense(const or_state *s, const double *V, const double *kappa,
+                       double *H, double *S);
+/* one (row vertex, col vertex) block of H and S, b_v x b_w complex */
+void or_assemble_block(const or_state *s, const double *V, const double *kappa,
+                       int64_t v, int64_t w, double *Hb, double *Sb);
+/* adjoint of the assembly; P, Q dense N x N complex (Q may be NULL) */
+void or_backward_dense(const or_state *s, const double *V, const double *kappa,
+                       const double *P, const double *Q, double *dLdV, double *dLdR);
+/* move the enrichment centres only (rule and enriched sets stay frozen) */
+void or_set_positions(or_state *s, const double *pos);
+/* basis of element e at reference point xi: values and Cartesian gradients */
+void or_basis_at(const or_state *s, int64_t e, const double *xi, double *val, double *grad);
+/* enrichment function value, gradient, Hessian at x */
+void or_enrichment(const or_state *s, int atom, int desc, int m, const double *x,
+                   double *val, double *grad, double *hess);
+/* building blocks exposed for the pins */
+void or_gauss_legendre(int n, double *x, double *w);
+void or_lagrange(int p, int j, double t, double *val, double *der);
+void or_solid_harmonic(int l, int m, const double *r, double *val, double *grad, double *hess);
+/* sparsity count: number of nonzero (i,j) pairs of S over the topology */
+int64_t or_pattern_nnz(const or_state *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,274 @@
+"""Seeded synthetic inputs for the PUFE assembly path.
+
+This module only *describes* problems (cells, meshes, atoms, enrichment
+descriptors, quadrature parameters, k-points) and draws the random numbers the
+workloads need (atomic jitter, adjoint factors).  It holds none of the
+method's arithmetic: no basis functions, quadrature rules or matrix elements.
+Both the HIP library (through its Python binding) and the CPU oracle consume
+the dictionaries built here.
+
+Problem dictionary keys
+-----------------------
+lattice      3x3 nested list, rows a_1, a_2, a_3 (bohr), right-handed.
+mesh         [n1, n2, n3] hexahedral elements along a_1, a_2, a_3.
+fe_order     1 (8-node trilinear) or 2 (27-node triquadratic Lagrange).
+atoms        list of Cartesian positions [x, y, z] (bohr).
+species      list of species indices, one per atom.
+species_info list of {"name", "Z", "rloc"} (used only by the potential).
+enrichments  list of {"species", "l", "a", "rc", "re"}: each descriptor adds
+             the 2l+1 functions r^l exp(-a r^2) (1-(r/rc)^2)^3 Y_lm around
+             every atom of that species, on every vertex closer than re.
+quad         {"n", "n_ref", "levels", "mode" ("geom"|"error"), "dist", "tol"}.
+kpts         list of reduced k-points kappa (k = sum kappa_i b_i).
+n_eig        number of lowest eigenpairs wanted.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+__all__ = [
+    "cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "small", "lih_table1",
+    "mp2", "kpts_cfg4", "jitter", "adjoint_factor", "with_lattice_constant",
+    "orthorhombic",
+]
+
+MP2 = [[sx * 0.25, sy * 0.25, sz * 0.25]
+       for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)]
+
+
+def mp2():
+    """Monkhorst-Pack 2x2x2 set in reduced coordinates: (+-1/4)^3, 8 points."""
+    return copy.deepcopy(MP2)
+
+
+def kpts_cfg4():
+    """Time-reversal-reduced MP 2x2x2 set (4 points) for the CeAl-like cell."""
+    return [[0.25, 0.25, 0.25], [0.25, 0.25, -0.25],
+            [0.25, -0.25, 0.25], [-0.25, 0.25, 0.25]]
+
+
+def jitter(n_atoms: int, sigma: float = 0.05, seed: int = 0) -> np.ndarray:
+    """Gaussian displacements N(0, sigma) per coordinate (PCG64, given seed),
+    drawn atom by atom in list order."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, sigma, size=(n_atoms, 3))
+
+
+def adjoint_factor(n: int, rank: int = 128, seed: int = 0) -> np.ndarray:
+    """C (n x rank) complex with entries CN(0, 1/n) from PCG64(seed).
+
+    The adjoint matrix used by the backward tests is P = C C^H, evaluated only
+    on the sparsity pattern of H.
+    """
+    rng = np.random.default_rng(seed)
+    s = math.sqrt(0.5 / n)
+    re = rng.normal(0.0, s, size=(n, rank))
+    im = rng.normal(0.0, s, size=(n, rank))
+    return re + 1j * im
+
+
+def cubic(a: float):
+    return [[a, 0.0, 0.0], [0.0, a, 0.0], [0.0, 0.0, a]]
+
+
+def orthorhombic(lattice) -> bool:
+    lat = np.asarray(lattice, float)
+    return bool(np.all(lat - np.diag(np.diag(lat)) == 0.0))
+
+
+def _problem(lattice, mesh, fe_order, atoms, species, species_info, enrichments,
+             quad, kpts, n_eig, name):
+    return {
+        "name": name,
+        "lattice": [list(map(float, r)) for r in lattice],
+        "mesh": list(map(int, mesh)),
+        "fe_order": int(fe_order),
+        "atoms": [list(map(float, p)) for p in atoms],
+        "species": list(map(int, species)),
+        "species_info": species_info,
+        "enrichments": enrichments,
+        "quad": quad,
+        "kpts": [list(map(float, k)) for k in kpts],
+        "n_eig": int(n_eig),
+        "potential": {"cutoff": 12.0},
+    }
+
+
+def cfg1():
+    """Single-atom cube: side 4.0, 4^3 trilinear, 5^3 Gauss, no refinement;
+    s enrichment a=1.0, rc=2.5, support radius 1.5; Gamma; 4 eigenpairs."""
+    return _problem(
+        cubic(4.0), [4, 4, 4], 1, [[0.0, 0.0, 0.0]], [0],
+        [{"name": "X", "Z": 1.0, "rloc": 0.5}],
+        [{"species": 0, "l": 0, "a": 1.0, "rc": 2.5, "re": 1.5}],
+        {"n": 5, "n_ref": 8, "levels": 0, "mode": "geom", "dist": 1.0, "tol": 1e-6},
+        [[0.0, 0.0, 0.0]], 4, "cfg1")
+
+
+LIH_ENR = [
+    {"species": 0, "l": 0, "a": 2.0, "rc": 3.0, "re": 2.0},   # Li s
+    {"species": 0, "l": 0, "a": 0.3, "rc": 3.0, "re": 2.0},   # Li s
+    {"species": 0, "l": 1, "a": 0.5, "rc": 3.0, "re": 2.0},   # Li p
+    {"species": 1, "l": 0, "a": 0.8, "rc": 3.0, "re": 2.0},   # H s
+]
+LIH_SPECIES = [{"name": "Li", "Z": 3.0, "rloc": 0.4},
+               {"name": "H", "Z": 1.0, "rloc": 0.4}]
+FCC = [(0.0, 0.0, 0.0), (0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0)]
+
+
+def _lih_reduced(cells=1):
+    """Reduced positions and species of the rock-salt LiH cell (or a cells^3
+    supercell of it), in the order Li0, H0, Li1, H1, ... per unit cell, unit
+    cells in lexicographic order (x fastest)."""
+    red, spc = [], []
+    for t3 in range(cells):
+        for t2 in range(cells):
+            for t1 in range(cells):
+                for f in FCC:
+                    li = np.array([(f[0] + t1), (f[1] + t2), (f[2] + t3)]) / cells
+                    h = li + np.array([0.5, 0.0, 0.0]) / cells
+                    red += [li, h]
+                    spc += [0, 1]
+    return np.array(red), spc
+
+
+def cfg2(a: float = 7.6, mesh=8):
+    """Rock-salt LiH-like cell (4 Li + 4 H), jittered N(0, 0.05) seed 0,
+    triquadratic mesh^3, 6^3 Gauss + 2 geometric octree levels within 1 bohr."""
+    red, spc = _lih_reduced(1)
+    pos = red * a + jitter(len(spc))
+    return _problem(
+        cubic(a), [mesh] * 3, 2, pos, spc, LIH_SPECIES, copy.deepcopy(LIH_ENR),
+        {"n": 6, "n_ref": 8, "levels": 2, "mode": "geom", "dist": 1.0, "tol": 1e-6},
+        [[0.0, 0.0, 0.0]], 16, "cfg2")
+
+
+def with_lattice_constant(prob, a: float):
+    """Same problem at lattice constant a: the reduced lattice positions scale,
+    the absolute jitter stays the same (the lattice-constant sweep)."""
+    a0 = prob["lattice"][0][0]
+    red, _ = _lih_reduced(1)
+    jit = np.asarray(prob["atoms"]) - red * a0
+    out = copy.deepcopy(prob)
+    out["lattice"] = cubic(a)
+    out["atoms"] = (red * a + jit).tolist()
+    out["name"] = f"{prob['name']}@a={a:.2f}"
+    return out
+
+
+def cfg3():
+    """The LiH-like cell at 11 lattice constants 6.80..8.40 with the 8-point
+    MP 2x2x2 k set: a list of 11 problems (88 assemblies)."""
+    base = cfg2()
+    out = []
+    for i in range(11):
+        a = round(6.8 + 0.16 * i, 10)
+        p = with_lattice_constant(base, a)
+        p["kpts"] = mp2()
+        out.append(p)
+    return out
+
+
+def cfg4():
+    """CsCl CeAl-like cell a=5.8: Ce at 0, Al at the body centre; 12^3
+    triquadratic, 8^3 Gauss + 3 octree levels within 1 bohr; Ce s,p,d,f x
+    {3.0, 0.4} (32 functions), Al s,p,d (0.6) (9 functions), rc = 4,
+    support radius 2.5; 4 k-points."""
+    a = 5.8
+    enr = []
+    for l in range(4):
+        for ex in (3.0, 0.4):
+            enr.append({"species": 0, "l": l, "a": ex, "rc": 4.0, "re": 2.5})
+    for l in range(3):
+        enr.append({"species": 1, "l": l, "a": 0.6, "rc": 4.0, "re": 2.5})
+    return _problem(
+        cubic(a), [12] * 3, 2, [[0.0, 0.0, 0.0], [a / 2, a / 2, a / 2]], [0, 1],
+        [{"name": "Ce", "Z": 12.0, "rloc": 0.3}, {"name": "Al", "Z": 3.0, "rloc": 0.3}],
+        enr,
+        {"n": 8, "n_ref": 10, "levels": 3, "mode": "geom", "dist": 1.0, "tol": 1e-6},
+        kpts_cfg4(), 16, "cfg4")
+
+
+def cfg5():
+    """2x2x2 supercell of the LiH-like cell (a = 15.2, 64 atoms, jittered
+    N(0, 0.05) seed 0), 16^3 triquadratic, same rule and enrichments; Gamma."""
+    a = 15.2
+    red, spc = _lih_reduced(2)
+    pos = red * a + jitter(len(spc))
+    return _problem(
+        cubic(a), [16] * 3, 2, pos, spc, LIH_SPECIES, copy.deepcopy(LIH_ENR),
+        {"n": 6, "n_ref": 8, "levels": 2, "mode": "geom", "dist": 1.0, "tol": 1e-6},
+        [[0.0, 0.0, 0.0]], 16, "cfg5")
+
+
+def small(kind: str = "lih", mesh=(2, 3, 2), fe_order: int = 2, levels: int = 1,
+          n: int = 3, a: float = 5.0, kpts=((0.0, 0.0, 0.0),), re: float = 1.6,
+          rc: float = 2.2, lattice=None):
+    """Small problems the oracle finishes in well under a second.
+
+    kind = "lih": the LiH-like two-species cell scaled to side a (4 Li + 4 H,
+    jittered); kind = "one": a single atom with one s and one p descriptor;
+    kind = "ceal": Ce/Al with s..f descriptors (many functions per element).
+    """
+    if lattice is None:
+        lattice = cubic(a)
+    lat = np.asarray(lattice, float)
+    if kind == "lih":
+        red, spc = _lih_reduced(1)
+        pos = red @ lat + jitter(len(spc))
+        enr = []
+        for e in LIH_ENR:
+            e = dict(e)
+            e["rc"], e["re"] = rc, re
+            enr.append(e)
+        info = LIH_SPECIES
+    elif kind == "one":
+        pos = np.array([[0.3, 0.2, 0.1]]) @ lat + 0.0
+        spc = [0]
+        enr = [{"species": 0, "l": 0, "a": 1.0, "rc": rc, "re": re},
+               {"species": 0, "l": 1, "a": 0.7, "rc": rc, "re": re}]
+        info = [{"name": "X", "Z": 1.0, "rloc": 0.5}]
+    elif kind == "ceal":
+        pos = np.array([[0.02, 0.01, 0.03], [0.51, 0.47, 0.55]]) @ lat
+        spc = [0, 1]
+        enr = []
+        for l in range(4):
+            for ex in (3.0, 0.4):
+                enr.append({"species": 0, "l": l, "a": ex, "rc": rc, "re": re})
+        for l in range(3):
+            enr.append({"species": 1, "l": l, "a": 0.6, "rc": rc, "re": re})
+        info = [{"name": "Ce", "Z": 12.0, "rloc": 0.3}, {"name": "Al", "Z": 3.0, "rloc": 0.3}]
+    else:
+        raise ValueError(kind)
+    return _problem(
+        lat, mesh, fe_order, pos, spc, info, enr,
+        {"n": n, "n_ref": n + 3, "levels": levels, "mode": "geom", "dist": 1.0,
+         "tol": 1e-6},
+        list(kpts), 4, f"small-{kind}")
+
+
+def lih_table1(re: float, cells: int = 1, mesh: int = 3, a: float = 4.63):
+    """The paper's LiH cubic cell for its sparsity table: Li at 0 (two s-type
+    enrichments), H at the body centre (one), a = 4.63 bohr; optionally a
+    cells^3 supercell (Li at the corners and H at the body centres of every
+    sub-cube)."""
+    pos, spc = [], []
+    for t3 in range(cells):
+        for t2 in range(cells):
+            for t1 in range(cells):
+                pos.append([t1 * a, t2 * a, t3 * a])
+                spc.append(0)
+                pos.append([(t1 + 0.5) * a, (t2 + 0.5) * a, (t3 + 0.5) * a])
+                spc.append(1)
+    enr = [{"species": 0, "l": 0, "a": 1.0, "rc": 2 * a, "re": re},
+           {"species": 0, "l": 0, "a": 0.5, "rc": 2 * a, "re": re},
+           {"species": 1, "l": 0, "a": 1.0, "rc": 2 * a, "re": re}]
+    if re <= 0:
+        enr = []
+    return _problem(
+        cubic(a * cells), [mesh] * 3, 3, pos, spc, LIH_SPECIES, enr,
+        {"n": 2, "n_ref": 3, "levels": 0, "mode": "geom", "dist": 0.0, "tol": 1e-6},
+        [[0.0, 0.0, 0.0]], 1, f"lih-table1-re{re}")
