@@ -1,0 +1,163 @@
+"""Benchmark of the PUFE H/S assembly on one MI355X.
+
+Workload: the LiH-like rock-salt cell (a = 7.6 bohr, 4 Li + 4 H jittered,
+8^3 triquadratic hexes, 6^3 Gauss points + 2 geometric octree levels within
+1 bohr of a nucleus, 512 elements, 1.52 M quadrature points, N = 4888),
+Gamma point.  One step = one full assembly of H and S from V at the
+quadrature points: the fused basis-evaluation + MFMA element contraction and
+the coloured Bloch scatter into block-sparse complex128 H and S.  Inputs are
+resident in HBM before timing starts; the rule (built once per geometry) is
+set up outside the timed region.
+
+Prints one JSON line (rank 0): elements/s, ms/step, the contraction kernel's
+MFMA roofline fraction (algorithmic flops per launch over its average launch
+time measured with HIP events on the launch stream) and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "enriched H/S assembly elements/s + MFMA util; eig err vs FP64 oracle (Ha)"
+PEAK = {"fp64": 78.6, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}   # TFLOP/s, dense
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def element_work(prob, sizes, layout, leaf_off, n3):
+    """(n_loc, n_q) per element and the algorithmic flops 5 n_q n_loc (n_loc+1)
+    of the symmetric H + S contractions."""
+    import numpy as np
+    n1, n2, n3m = prob["mesh"]
+    nfs = sizes["n_fe_slots"]
+    nfe = 8 if prob["fe_order"] == 1 else 27
+    nenr = np.diff(layout["dof_offset"]) - nfs
+    e = np.arange(sizes["n_elem"])
+    i1, i2, i3 = e % n1, (e // n1) % n2, e // (n1 * n2)
+    nloc = np.full(e.shape, nfe)
+    for c in range(8):
+        j1 = (i1 + (c & 1)) % n1
+        j2 = (i2 + ((c >> 1) & 1)) % n2
+        j3 = (i3 + ((c >> 2) & 1)) % n3m
+        nloc = nloc + nenr[(j3 * n2 + j2) * n1 + j1]
+    nq = np.diff(leaf_off) * n3
+    flops = 5.0 * nq * nloc * (nloc + 1)
+    return nloc, nq, flops
+
+
+def cpu_baseline(prob, budget_s=20.0):
+    """The oracle's element matrices on a strided sample of the elements, with
+    V from the input generator at the oracle's own quadrature points."""
+    import torch
+    import oracle
+    from workloads.potential import potential_at
+    o = oracle.Oracle(prob)
+    xyz, _, qp_off = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob).cpu().numpy()
+    sample = list(range(0, o.n_elem, 8))
+    t0 = time.perf_counter()
+    done = 0
+    for e in sample:
+        o.element_matrices(e, V[qp_off[e]:qp_off[e + 1]])
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"element matrices (H_e, S_e) of {done} elements, every 8th element in id order "
+                      f"(refined and plain in workload proportion), single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=sorted(PEAK))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1611_00731_amd as P
+    import workloads as W
+    from workloads.potential import potential_at
+
+    dev = torch.device("cuda", 0)
+    prob = W.cfg2()
+    log("setup", prob["name"])
+    p = P.Problem(prob).setup()
+    sz = p.sizes
+    xyz, w, qp_off = p.quadrature()
+    V = potential_at(xyz, prob)
+    lay = p.layout()
+    _, _, leaf_off = p.leaves()
+    nloc, nq, flops = element_work(prob, sz, lay, leaf_off, prob["quad"]["n"] ** 3)
+    kpts = prob["kpts"]
+    H = torch.empty((len(kpts), sz["nnz"], 2), dtype=torch.float64, device=dev)
+    S = torch.empty_like(H)
+    stream = torch.cuda.current_stream()
+    log(f"n_elem {sz['n_elem']} n_qp {sz['n_qp']} n_dof {sz['n_dof']} nnz {sz['nnz']}")
+    for i in range(args.warmup):
+        P.pufe_assemble(p.ctx, V, kpts, args.precision, "c128", H, S)
+    torch.cuda.synchronize()
+    log("warmup done")
+    P.pufe_enable_timing(p.ctx, True)
+    P.pufe_kernel_times(p.ctx, reset=True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for i in range(args.steps):
+        P.pufe_assemble(p.ctx, V, kpts, args.precision, "c128", H, S)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+    kms, kcnt = P.pufe_kernel_times(p.ctx, reset=True)
+    P.pufe_enable_timing(p.ctx, False)
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step")
+    contract_ms = kms[0] / max(kcnt[0], 1)
+    scatter_ms = kms[1] / max(kcnt[1], 1)
+    alg_flops = float(flops.sum())
+    achieved = alg_flops / (contract_ms * 1e-3) / 1e12
+    n_out = len(kpts)
+    value = sz["n_elem"] * n_out / (ms_step * 1e-3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": "LiH-like rock-salt cell a=7.6 bohr, 8^3 triquadratic hexes, 6^3 Gauss "
+                               "+ 2 octree levels within 1 bohr, Gamma, H+S complex128",
+                   "n_elem": sz["n_elem"], "n_qp": sz["n_qp"], "n_dof": sz["n_dof"],
+                   "nnz": sz["nnz"], "kpoints": n_out, "precision": args.precision},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision], "traffic": None,
+                     "kernel": "contract_f64_kernel", "kernel_ms": contract_ms,
+                     "alg_flops_per_launch": alg_flops},
+        "extra": {"scatter_ms": scatter_ms, "gflops_step": alg_flops / (ms_step * 1e-3) / 1e9,
+                  "nloc_min": int(nloc.min()), "nloc_max": int(nloc.max()),
+                  "nq_max": int(nq.max())},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(prob)
+    p.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

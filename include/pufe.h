@@ -1,0 +1,213 @@
+/*
+ * pufe.h -- C ABI of the MI355X (gfx950) PUFE Hamiltonian/overlap assembly.
+ *
+ * Method: Pask & Sukumar, "Partition of unity finite element method for
+ * quantum mechanical materials calculations".  The library discretises the
+ * Kohn-Sham eigenproblem of a periodic cell in the PUFE basis (eq. pufebasis):
+ * classical C0 finite elements plus trilinear partition-of-unity functions
+ * times atom-centred enrichment functions R(r) Y_lm summed over lattice images
+ * (eqs. Psitilde, Psi), under Bloch boundary conditions (eqs. bloch,
+ * wbpspace), and assembles the sparse Hermitian matrices of the generalized
+ * eigenproblem H c = eps S c (eq. disceig3d):
+ *     H_ij = int 1/2 grad phi_i^* . grad phi_j + phi_i^* V phi_j,
+ *     S_ij = int phi_i^* phi_j,
+ * with the per-element adaptive quadrature rule of section "Adaptive
+ * quadrature".  The local potential V is an input given at the quadrature
+ * points.  The FE and PU functions carry the Bloch phase at the cell boundary
+ * and the enrichment is periodic (section "Self-consistent calculations"), so
+ * every element matrix is real and one contraction serves all k-points.
+ *
+ * Conventions
+ *  - Every call returns int: PUFE_OK (0) or a negative PUFE_ERR_* code;
+ *    pufe_last_error_message() gives the detail.  No exception crosses the ABI.
+ *  - Units: bohr and hartree.  k-points are reduced coordinates kappa
+ *    (k = sum_i kappa_i b_i, b_i . a_j = 2 pi delta_ij); a function whose node
+ *    wraps across the cell boundary by the lattice shift n carries the phase
+ *    exp(2 pi i kappa . n).
+ *  - Positions are Cartesian double[n][3]; the lattice is double[3][3], rows
+ *    a_1, a_2, a_3, right-handed.  Complex values are interleaved (re, im).
+ *  - Pointers named d_* are device (HIP) pointers on the context's device;
+ *    all others are host pointers.  The caller owns every buffer it passes;
+ *    no call keeps a caller pointer after it returns.  The library owns only
+ *    its context-internal tables and workspace, freed by pufe_destroy().
+ *  - Streams are hipStream_t passed as void* (NULL = default stream).  Device
+ *    work is enqueued asynchronously on that stream.  pufe_setup, pufe_query,
+ *    pufe_get_layout and pufe_get_leaves are synchronous.
+ *  - Calls on one context are not thread-safe.
+ *
+ * Canonical orders (fixed so that callers can build inputs)
+ *  - Elements and vertices: id = (i3 n2 + i2) n1 + i1.
+ *  - DOFs, vertex-major: for vertex v the FE slots (trilinear: 1; triquadratic:
+ *    8, slot s1 + 2 s2 + 4 s3 where s_d = 1 is the +1/2 midpoint), then v's
+ *    enriched functions ordered by atom, descriptor, m = -l..l.
+ *  - Quadrature points: element-major; inside an element the octree leaves
+ *    depth first (children c = c1 + 2 c2 + 4 c3); inside a leaf the n^3 Gauss
+ *    points with the first reference index fastest.
+ *  - H and S are returned as variable-block BSR keyed by vertex (see
+ *    pufe_get_layout), full storage (both triangles).
+ */
+#ifndef PUFE_H
+#define PUFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PUFE_OK 0
+#define PUFE_ERR_INVALID_ARG (-1)
+#define PUFE_ERR_UNSUPPORTED (-2)
+#define PUFE_ERR_OOM (-3)
+#define PUFE_ERR_HIP (-4)
+#define PUFE_ERR_STATE (-5)
+
+/* precision of the element contractions */
+#define PUFE_PREC_FP64 0    /* FP64 MFMA */
+#define PUFE_PREC_BF16X3 1  /* 2-limb bf16 split, 3 products, FP32 MFMA accumulation */
+#define PUFE_PREC_BF16X6 2  /* 3-limb bf16 split, 6 products, FP32 MFMA accumulation */
+
+/* storage type of the assembled H and S values */
+#define PUFE_OUT_C128 0     /* complex double (re, im) */
+#define PUFE_OUT_C64 1      /* complex float (re, im) */
+#define PUFE_OUT_F64_GAMMA 2 /* real double; every k-point must be 0 (Gamma) */
+
+/* quadrature refinement modes (section "Adaptive quadrature") */
+#define PUFE_QUAD_GEOM 0    /* split a cell while it lies within `dist` of a nucleus image */
+#define PUFE_QUAD_ERROR 1   /* the paper's rule: split while |Q_n - Q_ref| > tol for Psi^2 or |grad Psi|^2 */
+
+typedef struct pufe_ctx pufe_ctx;
+
+/* One enrichment descriptor: the 2l+1 functions
+ *   r^l exp(-a r^2) (1 - (r/rc)^2)^3 Y_lm(r_hat)   (r < rc, zero beyond),
+ * real orthonormal Y_lm without Condon-Shortley phase, centred on every atom
+ * of `species` and summed over lattice images (eqs. Psitilde, Psi with
+ * f(R) = 1).  A vertex carries them iff its minimum-image distance to the
+ * atom is below re (section "Partition of unity enrichment functions"). */
+typedef struct {
+    int species;
+    int l;            /* 0..3 */
+    int radial_kind;  /* 0: the analytic radial above (the only kind supported) */
+    double a;         /* Gaussian exponent, > 0 */
+    double rc;        /* cutoff radius, > 0 */
+    double re;        /* support radius, >= 0 */
+} pufe_enrichment;
+
+/* The per-element rule (section "Adaptive quadrature"): leaves of an octree
+ * over the reference cube, each carrying the n_gauss^3 tensor Gauss rule. */
+typedef struct {
+    int n_gauss;      /* 1..12 */
+    int n_ref;        /* reference order of the error mode, > n_gauss */
+    int max_level;    /* 0..8 */
+    int mode;         /* PUFE_QUAD_GEOM or PUFE_QUAD_ERROR */
+    double dist;      /* GEOM: refinement distance (bohr) */
+    double tol;       /* ERROR: absolute tolerance */
+} pufe_quad;
+
+typedef struct {
+    int64_t n_elem, n_vertex, n_dof, n_fe_dof, n_enr_dof;
+    int64_t nnzb;     /* BSR blocks */
+    int64_t nnz;      /* stored complex entries of one matrix for one k-point */
+    int64_t n_qp;     /* quadrature points (0 before pufe_setup) */
+    int64_t n_leaves; /* octree leaves (0 before pufe_setup) */
+    int32_t max_nloc; /* largest number of functions on one element */
+    int32_t n_colors; /* element colours of the atomic-free scatter */
+    int32_t n_atoms;
+    int32_t n_fe_slots;
+} pufe_sizes;
+
+const char *pufe_error_string(int code);
+/* Detail of the last error on ctx (static string if ctx is NULL). */
+const char *pufe_last_error_message(const pufe_ctx *ctx);
+
+/* Create a context bound to HIP device `device`.  No device call is made
+ * until pufe_setup. */
+int pufe_create(pufe_ctx **out, int device);
+int pufe_destroy(pufe_ctx *ctx);
+
+/* Define the problem (host only, no HIP call): cell (eq. bloch: lattice rows
+ * a_1..a_3), mesh of n1 x n2 x n3 parallelepiped elements (each n_d >= 2),
+ * classical FE order (1 = 8-node trilinear, 2 = 27-node triquadratic
+ * Lagrange), atoms (Cartesian positions and species), enrichment descriptors
+ * and the quadrature rule.  Builds the DOF map, the enriched sets, the BSR
+ * layout and the element colouring.  Errors: PUFE_ERR_INVALID_ARG (null
+ * pointers, non-positive volume, l outside 0..3, a <= 0, rc <= 0, n_d < 2),
+ * PUFE_ERR_UNSUPPORTED (GEOM refinement of a non-orthorhombic cell, more
+ * functions on one element than the kernels hold). */
+int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], int fe_order,
+                     int n_atoms, const double *pos, const int *species, int n_enr,
+                     const pufe_enrichment *enr, const pufe_quad *quad);
+
+/* Build the adaptive rule on the device (section "Adaptive quadrature"),
+ * upload the element tables and plan the contraction work.  Synchronous.
+ * The rule is built once per geometry and reused by every assembly. */
+int pufe_setup(pufe_ctx *ctx, void *stream);
+
+/* Sizes (host).  Valid after pufe_set_problem; n_qp and n_leaves after setup. */
+int pufe_query(pufe_ctx *ctx, pufe_sizes *out);
+
+/* BSR layout (host arrays, caller-allocated): dof_offset[n_vertex+1],
+ * brow_ptr[n_vertex+1], bcol[nnzb] (block column vertices, ascending per row),
+ * bval_offset[nnzb+1] (start of each block's values, in entries).  Block
+ * (v, w) is a dense row-major b_v x b_w sub-matrix, b_v = dof_offset[v+1] -
+ * dof_offset[v].  Any pointer may be NULL. */
+int pufe_get_layout(pufe_ctx *ctx, int64_t *dof_offset, int64_t *brow_ptr, int32_t *bcol,
+                    int64_t *bval_offset);
+
+/* Quadrature points in canonical order (device arrays, caller-allocated):
+ * d_xyz[n_qp*3] Cartesian, d_w[n_qp] weights (including the Jacobian),
+ * d_elem_qp_offset[n_elem+1].  Any pointer may be NULL.  The caller evaluates
+ * V at these points for pufe_assemble. */
+int pufe_get_quadrature(pufe_ctx *ctx, double *d_xyz, double *d_w, int64_t *d_elem_qp_offset,
+                        void *stream);
+
+/* Octree leaves (host arrays): level[n_leaves], ijk[n_leaves*3] integer cell
+ * coordinates at that level, elem_leaf_offset[n_elem+1].  Synchronous. */
+int pufe_get_leaves(pufe_ctx *ctx, int32_t *level, int32_t *ijk, int64_t *elem_leaf_offset);
+
+/* Assemble H and S for n_k k-points (eq. disceig3d).  d_V[n_qp] is the local
+ * potential at the quadrature points; kpts[n_k*3] host, reduced.  d_H and
+ * d_S hold n_k consecutive value arrays of nnz entries each, of type
+ * out_dtype; d_S may be NULL (S does not depend on V).  The scatter is
+ * atomic-free (element colouring) and deterministic.  Errors:
+ * PUFE_ERR_STATE before setup, PUFE_ERR_INVALID_ARG for a bad precision or
+ * dtype, or F64_GAMMA with a non-zero k-point. */
+int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision,
+                  int out_dtype, void *d_H, void *d_S, void *stream);
+
+/* Real element matrices of element `elem` (debug/parity): d_He, d_Se device
+ * arrays of max_nloc*max_nloc doubles; the leading nloc x nloc row-major
+ * block is written, nloc returned through *nloc (host). */
+int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int precision,
+                          double *d_He, double *d_Se, int32_t *nloc, void *stream);
+
+/* Adjoint of the assembly for one k-point.  L = Re sum conj(P_ij) H_ij +
+ * Re sum conj(Q_ij) S_ij with P, Q (complex double, BSR layout of H; either
+ * may be NULL) gives
+ *   d_dLdV[n_qp]      = w_q sum_ab Pt_ab phi_a phi_b  (the density at x_q times w_q,
+ *                       eq. rhoe when P is the occupied density matrix),
+ *   d_dLdR[n_atoms*3] = derivative with respect to the enrichment centres
+ *                       (rule, enriched sets and V held fixed),
+ * with Pt_ab = Re(p_a P_{g_a g_b} conj(p_b)).  Output pointers may be NULL. */
+int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3], const void *d_P,
+                           const void *d_Q, int precision, double *d_dLdV, double *d_dLdR,
+                           void *stream);
+
+/* Expand one BSR value array (out_dtype C128 or F64_GAMMA) into a dense
+ * row-major n_dof x n_dof complex double matrix d_dense (device). */
+int pufe_bsr_to_dense(pufe_ctx *ctx, const void *d_bsr, int dtype, double *d_dense, void *stream);
+
+/* Kernel timing for measurement.  When enabled, every contraction and every
+ * scatter phase enqueued by pufe_assemble is bracketed by HIP events on the
+ * caller's stream.  pufe_kernel_times waits for the recorded events and
+ * returns the summed milliseconds and launch counts of
+ *   [0] the element contraction kernel, [1] the zero-fill + coloured scatter,
+ *   [2] the adjoint kernel(s), [3] reserved,
+ * clearing them when reset != 0.  out_ms[4] and counts[4] are host arrays. */
+int pufe_enable_timing(pufe_ctx *ctx, int on);
+int pufe_kernel_times(pufe_ctx *ctx, double *out_ms, int64_t *counts, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

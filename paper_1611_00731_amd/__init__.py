@@ -1,0 +1,304 @@
+"""Python binding of libpufe (the MI355X PUFE assembly library).
+
+Thin ctypes layer over the C ABI in include/pufe.h: the functions below carry
+the same names as the C entry points and only marshal arguments.  Device
+buffers are torch tensors on the context's device; every step of the path
+runs in the library's HIP kernels.  Importing this package fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpufe.so")
+
+PUFE_OK = 0
+ERRORS = {-1: "PUFE_ERR_INVALID_ARG", -2: "PUFE_ERR_UNSUPPORTED", -3: "PUFE_ERR_OOM",
+          -4: "PUFE_ERR_HIP", -5: "PUFE_ERR_STATE"}
+PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2}
+OUT = {"c128": 0, "c64": 1, "f64": 2}
+QUAD_MODE = {"geom": 0, "error": 1}
+
+EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_destroy",
+           "pufe_set_problem", "pufe_setup", "pufe_query", "pufe_get_layout",
+           "pufe_get_quadrature", "pufe_get_leaves", "pufe_assemble", "pufe_element_matrices",
+           "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
+           "pufe_kernel_times"]
+
+
+class PufeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class pufe_enrichment(C.Structure):
+    _fields_ = [("species", C.c_int), ("l", C.c_int), ("radial_kind", C.c_int),
+                ("a", C.c_double), ("rc", C.c_double), ("re", C.c_double)]
+
+
+class pufe_quad(C.Structure):
+    _fields_ = [("n_gauss", C.c_int), ("n_ref", C.c_int), ("max_level", C.c_int),
+                ("mode", C.c_int), ("dist", C.c_double), ("tol", C.c_double)]
+
+
+class pufe_sizes(C.Structure):
+    _fields_ = [("n_elem", C.c_int64), ("n_vertex", C.c_int64), ("n_dof", C.c_int64),
+                ("n_fe_dof", C.c_int64), ("n_enr_dof", C.c_int64), ("nnzb", C.c_int64),
+                ("nnz", C.c_int64), ("n_qp", C.c_int64), ("n_leaves", C.c_int64),
+                ("max_nloc", C.c_int32), ("n_colors", C.c_int32), ("n_atoms", C.c_int32),
+                ("n_fe_slots", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpufe.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i64p, i32p, dp = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)
+    sig = {
+        "pufe_error_string": ([C.c_int], C.c_char_p),
+        "pufe_last_error_message": ([vp], C.c_char_p),
+        "pufe_create": ([C.POINTER(vp), C.c_int], C.c_int),
+        "pufe_destroy": ([vp], C.c_int),
+        "pufe_set_problem": ([vp, dp, C.POINTER(C.c_int), C.c_int, C.c_int, dp, C.POINTER(C.c_int),
+                              C.c_int, C.POINTER(pufe_enrichment), C.POINTER(pufe_quad)], C.c_int),
+        "pufe_setup": ([vp, vp], C.c_int),
+        "pufe_query": ([vp, C.POINTER(pufe_sizes)], C.c_int),
+        "pufe_get_layout": ([vp, i64p, i64p, i32p, i64p], C.c_int),
+        "pufe_get_quadrature": ([vp, vp, vp, vp, vp], C.c_int),
+        "pufe_get_leaves": ([vp, i32p, i32p, i64p], C.c_int),
+        "pufe_assemble": ([vp, vp, dp, C.c_int, C.c_int, C.c_int, vp, vp, vp], C.c_int),
+        "pufe_element_matrices": ([vp, C.c_int64, vp, C.c_int, vp, vp, i32p, vp], C.c_int),
+        "pufe_assemble_backward": ([vp, vp, dp, vp, vp, C.c_int, vp, vp, vp], C.c_int),
+        "pufe_bsr_to_dense": ([vp, vp, C.c_int, vp, vp], C.c_int),
+        "pufe_enable_timing": ([vp, C.c_int], C.c_int),
+        "pufe_kernel_times": ([vp, dp, i64p, C.c_int], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+lib = _load()
+
+
+def _check(ctx, rc):
+    if rc != PUFE_OK:
+        msg = lib.pufe_last_error_message(ctx).decode() if ctx else ""
+        raise PufeError(rc, msg)
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor, None for None."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- C names
+
+def pufe_create(device: int = 0):
+    h = C.c_void_p()
+    _check(None, lib.pufe_create(C.byref(h), device))
+    return h
+
+
+def pufe_destroy(ctx):
+    _check(None, lib.pufe_destroy(ctx))
+
+
+def pufe_set_problem(ctx, lattice, mesh, fe_order, pos, species, enrichments, quad):
+    lat = (C.c_double * 9)(*np.asarray(lattice, float).reshape(9))
+    msh = (C.c_int * 3)(*[int(m) for m in mesh])
+    pos = np.ascontiguousarray(np.asarray(pos, np.float64).reshape(-1))
+    spc = np.ascontiguousarray(np.asarray(species, np.int32).reshape(-1))
+    n_atoms = spc.size
+    enr = (pufe_enrichment * max(1, len(enrichments)))()
+    for i, e in enumerate(enrichments):
+        enr[i] = pufe_enrichment(int(e["species"]), int(e["l"]), int(e.get("radial_kind", 0)),
+                                 float(e["a"]), float(e["rc"]), float(e["re"]))
+    q = pufe_quad(int(quad["n"]), int(quad.get("n_ref", quad["n"] + 1)), int(quad["levels"]),
+                  QUAD_MODE[quad.get("mode", "geom")], float(quad.get("dist", 0.0)),
+                  float(quad.get("tol", 1e-6)))
+    _check(ctx, lib.pufe_set_problem(
+        ctx, lat, msh, int(fe_order), n_atoms,
+        pos.ctypes.data_as(C.POINTER(C.c_double)), spc.ctypes.data_as(C.POINTER(C.c_int)),
+        len(enrichments), enr, C.byref(q)))
+
+
+def pufe_setup(ctx, stream=None):
+    _check(ctx, lib.pufe_setup(ctx, _stream(stream)))
+
+
+def pufe_query(ctx) -> dict:
+    s = pufe_sizes()
+    _check(ctx, lib.pufe_query(ctx, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in pufe_sizes._fields_}
+
+
+def pufe_get_layout(ctx):
+    sz = pufe_query(ctx)
+    dof = np.zeros(sz["n_vertex"] + 1, np.int64)
+    rp = np.zeros(sz["n_vertex"] + 1, np.int64)
+    bc = np.zeros(max(1, sz["nnzb"]), np.int32)
+    bo = np.zeros(sz["nnzb"] + 1, np.int64)
+    i64p, i32p = C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+    _check(ctx, lib.pufe_get_layout(ctx, dof.ctypes.data_as(i64p), rp.ctypes.data_as(i64p),
+                                    bc.ctypes.data_as(i32p), bo.ctypes.data_as(i64p)))
+    return {"dof_offset": dof, "brow_ptr": rp, "bcol": bc[:sz["nnzb"]], "bval_offset": bo}
+
+
+def pufe_get_quadrature(ctx, xyz=None, w=None, elem_qp_offset=None, stream=None):
+    _check(ctx, lib.pufe_get_quadrature(ctx, _ptr(xyz), _ptr(w), _ptr(elem_qp_offset), _stream(stream)))
+
+
+def pufe_get_leaves(ctx):
+    sz = pufe_query(ctx)
+    n = sz["n_leaves"]
+    lev = np.zeros(max(n, 1), np.int32)
+    ijk = np.zeros(3 * max(n, 1), np.int32)
+    off = np.zeros(sz["n_elem"] + 1, np.int64)
+    i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    _check(ctx, lib.pufe_get_leaves(ctx, lev.ctypes.data_as(i32p), ijk.ctypes.data_as(i32p),
+                                    off.ctypes.data_as(i64p)))
+    return lev[:n], ijk[:3 * n].reshape(-1, 3), off
+
+
+def pufe_assemble(ctx, V, kpts, precision, out_dtype, H, S=None, stream=None):
+    k = np.ascontiguousarray(np.asarray(kpts, np.float64).reshape(-1, 3))
+    _check(ctx, lib.pufe_assemble(ctx, _ptr(V), k.ctypes.data_as(C.POINTER(C.c_double)), k.shape[0],
+                                  PREC[precision] if isinstance(precision, str) else int(precision),
+                                  OUT[out_dtype] if isinstance(out_dtype, str) else int(out_dtype),
+                                  _ptr(H), _ptr(S), _stream(stream)))
+
+
+def pufe_element_matrices(ctx, elem, V, precision, He, Se, stream=None):
+    n = C.c_int32()
+    _check(ctx, lib.pufe_element_matrices(ctx, int(elem), _ptr(V),
+                                          PREC[precision] if isinstance(precision, str) else int(precision),
+                                          _ptr(He), _ptr(Se), C.byref(n), _stream(stream)))
+    return n.value
+
+
+def pufe_assemble_backward(ctx, V, kpt, P, Q, precision, dLdV, dLdR, stream=None):
+    k = (C.c_double * 3)(*[float(x) for x in kpt])
+    _check(ctx, lib.pufe_assemble_backward(ctx, _ptr(V), k, _ptr(P), _ptr(Q),
+                                           PREC[precision] if isinstance(precision, str) else int(precision),
+                                           _ptr(dLdV), _ptr(dLdR), _stream(stream)))
+
+
+def pufe_bsr_to_dense(ctx, bsr, dtype, dense, stream=None):
+    _check(ctx, lib.pufe_bsr_to_dense(ctx, _ptr(bsr), OUT[dtype] if isinstance(dtype, str) else int(dtype),
+                                      _ptr(dense), _stream(stream)))
+
+
+def pufe_enable_timing(ctx, on=True):
+    _check(ctx, lib.pufe_enable_timing(ctx, 1 if on else 0))
+
+
+def pufe_kernel_times(ctx, reset=True):
+    ms = (C.c_double * 4)()
+    cnt = (C.c_int64 * 4)()
+    _check(ctx, lib.pufe_kernel_times(ctx, ms, cnt, 1 if reset else 0))
+    return list(ms), list(cnt)
+
+
+# --------------------------------------------------------- convenience layer
+
+class Problem:
+    """A problem dictionary (see the `workloads` package) bound to a context."""
+
+    def __init__(self, prob: dict, device: int = 0):
+        self.prob = prob
+        self.device = device
+        self.ctx = pufe_create(device)
+        pufe_set_problem(self.ctx, prob["lattice"], prob["mesh"], prob["fe_order"], prob["atoms"],
+                         prob["species"], prob["enrichments"], prob["quad"])
+        self.sizes = pufe_query(self.ctx)
+        self._ready = False
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            pufe_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def setup(self, stream=None):
+        pufe_setup(self.ctx, stream)
+        self.sizes = pufe_query(self.ctx)
+        self._ready = True
+        return self
+
+    def layout(self):
+        return pufe_get_layout(self.ctx)
+
+    def leaves(self):
+        return pufe_get_leaves(self.ctx)
+
+    def quadrature(self):
+        import torch
+        dev = torch.device("cuda", self.device)
+        n = self.sizes["n_qp"]
+        xyz = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        w = torch.empty(n, dtype=torch.float64, device=dev)
+        off = torch.empty(self.sizes["n_elem"] + 1, dtype=torch.int64, device=dev)
+        pufe_get_quadrature(self.ctx, xyz, w, off)
+        return xyz, w, off
+
+    def assemble(self, V, kpts=((0.0, 0.0, 0.0),), precision="fp64", out_dtype="c128", with_S=True):
+        import torch
+        nk = len(kpts)
+        nnz = self.sizes["nnz"]
+        if out_dtype == "c128":
+            shape, dt = (nk, nnz, 2), torch.float64
+        elif out_dtype == "c64":
+            shape, dt = (nk, nnz, 2), torch.float32
+        else:
+            shape, dt = (nk, nnz), torch.float64
+        H = torch.empty(shape, dtype=dt, device=V.device)
+        S = torch.empty(shape, dtype=dt, device=V.device) if with_S else None
+        pufe_assemble(self.ctx, V, kpts, precision, out_dtype, H, S)
+        return H, S
+
+    def element_matrices(self, elem, V, precision="fp64"):
+        import torch
+        m = self.sizes["max_nloc"]
+        He = torch.zeros((m, m), dtype=torch.float64, device=V.device)
+        Se = torch.zeros((m, m), dtype=torch.float64, device=V.device)
+        n = pufe_element_matrices(self.ctx, elem, V, precision, He, Se)
+        return He.view(-1)[:n * n].view(n, n), Se.view(-1)[:n * n].view(n, n)
+
+    def to_dense(self, bsr, dtype="c128"):
+        import torch
+        n = self.sizes["n_dof"]
+        D = torch.empty((n, n, 2), dtype=torch.float64, device=bsr.device)
+        pufe_bsr_to_dense(self.ctx, bsr.contiguous(), dtype, D)
+        return torch.view_as_complex(D)
+
+
+def eig(H, S, m):
+    """Lowest m eigenvalues of H c = eps S c (eq. disceig3d) on the device:
+    FP64 Cholesky of S, reduction to L^-1 H L^-H, Hermitian eigensolve
+    (torch.linalg / rocSOLVER)."""
+    import torch
+    Lc = torch.linalg.cholesky(S)
+    X = torch.linalg.solve_triangular(Lc, H, upper=False)
+    A = torch.linalg.solve_triangular(Lc, X.mH, upper=False).mH
+    A = 0.5 * (A + A.mH)
+    return torch.linalg.eigvalsh(A)[:m]

@@ -1,0 +1,493 @@
+// C ABI of the PUFE assembly library (declared in include/pufe.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pufe.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace pufe;
+
+namespace {
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(size_t count) {
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+        if (e == hipSuccess) n = count;
+        else p = nullptr;
+        return e;
+    }
+    hipError_t upload(const std::vector<T> &v, hipStream_t st) {
+        hipError_t e = alloc(v.size());
+        if (e != hipSuccess || v.empty()) return e;
+        e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);
+    }
+};
+
+}  // namespace
+
+struct pufe_ctx {
+    int device = 0;
+    std::string err;
+    bool have_problem = false, have_setup = false;
+    Problem prob;
+    Plan plan;
+    int64_t n_leaves = 0, n_qp = 0;
+    std::vector<int64_t> leaf_off_h;
+    std::vector<ItemDev> items;
+    size_t lds = 0;
+    int64_t part_slots = 0;
+    DevBuf<ElemDev> d_elems;
+    DevBuf<GroupDev> d_groups;
+    DevBuf<double> d_img, d_pos, d_partial;
+    DevBuf<int32_t> d_edof, d_leaf_elem, d_color_elems, d_brow, d_bcol;
+    DevBuf<uint32_t> d_leaves;
+    DevBuf<int64_t> d_leaf_count, d_leaf_off, d_bval_off, d_dof_off;
+    DevBuf<ItemDev> d_items;
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+    ~pufe_ctx() { clear_events(); }
+    void clear_events() {
+        for (auto &v : ev) {
+            for (auto &pr : v) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+            v.clear();
+        }
+    }
+};
+
+// Bracket the launches enqueued between begin() and end() with events when
+// timing is on.
+struct TimedRegion {
+    pufe_ctx *c;
+    int slot;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedRegion(pufe_ctx *c_, int s, hipStream_t st_) : c(c_), slot(s), st(st_) {
+        if (!c->timing) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, st);
+    }
+    ~TimedRegion() {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        c->ev[slot].push_back({a, b});
+    }
+};
+
+static int fail(pufe_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+static int hipfail(pufe_ctx *c, hipError_t e, const char *where) {
+    int code = (e == hipErrorOutOfMemory) ? PUFE_ERR_OOM : PUFE_ERR_HIP;
+    return fail(c, code, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define CHECK_HIP(ctx, x, where)                          \
+    do {                                                  \
+        hipError_t e_ = (x);                              \
+        if (e_ != hipSuccess) return hipfail(ctx, e_, where); \
+    } while (0)
+
+extern "C" {
+
+const char *pufe_error_string(int code) {
+    switch (code) {
+        case PUFE_OK: return "ok";
+        case PUFE_ERR_INVALID_ARG: return "invalid argument";
+        case PUFE_ERR_UNSUPPORTED: return "unsupported";
+        case PUFE_ERR_OOM: return "out of device memory";
+        case PUFE_ERR_HIP: return "HIP runtime error";
+        case PUFE_ERR_STATE: return "call out of order";
+        default: return "unknown error";
+    }
+}
+
+const char *pufe_last_error_message(const pufe_ctx *ctx) {
+    if (!ctx) return "no context";
+    return ctx->err.c_str();
+}
+
+int pufe_create(pufe_ctx **out, int device) {
+    if (!out) return PUFE_ERR_INVALID_ARG;
+    if (device < 0) return PUFE_ERR_INVALID_ARG;
+    pufe_ctx *c = new (std::nothrow) pufe_ctx();
+    if (!c) return PUFE_ERR_OOM;
+    c->device = device;
+    *out = c;
+    return PUFE_OK;
+}
+
+int pufe_destroy(pufe_ctx *ctx) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (ctx->have_setup) (void)hipSetDevice(ctx->device);
+    delete ctx;
+    return PUFE_OK;
+}
+
+int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], int fe_order, int n_atoms,
+                     const double *pos, const int *species, int n_enr, const pufe_enrichment *enr,
+                     const pufe_quad *quad) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!lattice || !mesh || !quad || n_atoms < 0 || n_enr < 0 || (n_atoms > 0 && (!pos || !species)) ||
+        (n_enr > 0 && !enr))
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer or negative count");
+    Problem pr;
+    std::memcpy(pr.lat, lattice, sizeof pr.lat);
+    std::memcpy(pr.mesh, mesh, sizeof pr.mesh);
+    pr.p = fe_order;
+    pr.pos.assign(pos, pos + 3 * (size_t)n_atoms);
+    pr.species.assign(species, species + n_atoms);
+    pr.enr.assign(enr, enr + n_enr);
+    pr.quad = *quad;
+    for (double v : pr.pos)
+        if (!std::isfinite(v)) return fail(ctx, PUFE_ERR_INVALID_ARG, "non-finite atom position");
+    Plan pl;
+    std::string err;
+    int rc = build_plan(pr, pl, err);
+    if (rc != PUFE_OK) return fail(ctx, rc, err);
+    ctx->prob = std::move(pr);
+    ctx->plan = std::move(pl);
+    ctx->have_problem = true;
+    ctx->have_setup = false;
+    ctx->n_leaves = ctx->n_qp = 0;
+    return PUFE_OK;
+}
+
+// Split each element's contraction into work items (row block x column block
+// of 16x16 tiles x range of leaves) of roughly equal MFMA work, largest first.
+static void plan_items(pufe_ctx *c) {
+    Plan &pl = c->plan;
+    const int n3 = pl.kp.n3;
+    struct Bp { int I0, nI, J0, nJ, pairs; };
+    double total = 0;
+    std::vector<std::vector<Bp>> bps(pl.nel);
+    for (int64_t e = 0; e < pl.nel; ++e) {
+        ElemDev &el = pl.elems[e];
+        int T = (el.nloc + 15) / 16, nb = (T + kBlockTiles - 1) / kBlockTiles;
+        for (int bj = 0; bj < nb; ++bj)
+            for (int bi = 0; bi <= bj; ++bi) {
+                Bp b;
+                b.I0 = bi * kBlockTiles;
+                b.nI = std::min(kBlockTiles, T - b.I0);
+                b.J0 = bj * kBlockTiles;
+                b.nJ = std::min(kBlockTiles, T - b.J0);
+                b.pairs = bi == bj ? b.nI * (b.nI + 1) / 2 : b.nI * b.nJ;
+                bps[e].push_back(b);
+                total += (double)b.pairs * n3 * (el.leaf_end - el.leaf_off);
+            }
+    }
+    double target = std::max(total / 4096.0, 1.0);
+    c->items.clear();
+    int64_t base = 0;
+    std::vector<double> cost;
+    for (int64_t e = 0; e < pl.nel; ++e) {
+        ElemDev &el = pl.elems[e];
+        int64_t nleaf = el.leaf_end - el.leaf_off;
+        int maxp = 1;
+        for (auto &b : bps[e]) maxp = std::max(maxp, b.pairs);
+        int64_t nch = (int64_t)std::llround((double)nleaf * n3 * maxp / target);
+        nch = std::max<int64_t>(1, std::min<int64_t>(nch, nleaf));
+        el.nchunk = (int32_t)nch;
+        int T = (el.nloc + 15) / 16;
+        el.part_base = base;
+        base += nch * (int64_t)T * (T + 1) / 2;
+        for (int64_t ch = 0; ch < nch; ++ch) {
+            int64_t lb = el.leaf_off + ch * nleaf / nch, le = el.leaf_off + (ch + 1) * nleaf / nch;
+            for (auto &b : bps[e]) {
+                ItemDev it;
+                it.elem = (int32_t)e;
+                it.I0 = b.I0;
+                it.nI = b.nI;
+                it.J0 = b.J0;
+                it.nJ = b.nJ;
+                it.chunk = (int32_t)ch;
+                it.leaf_b = lb;
+                it.leaf_e = le;
+                c->items.push_back(it);
+                cost.push_back((double)b.pairs * (le - lb));
+            }
+        }
+    }
+    c->part_slots = base;
+    std::vector<size_t> order(c->items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<ItemDev> sorted;
+    sorted.reserve(order.size());
+    int max_rows = 16;
+    for (size_t i : order) {
+        sorted.push_back(c->items[i]);
+        const ItemDev &it = c->items[i];
+        max_rows = std::max(max_rows, 16 * (it.I0 == it.J0 ? it.nI : it.nI + it.nJ));
+    }
+    c->items.swap(sorted);
+    c->lds = contract_lds_bytes(max_rows, std::max(pl.max_nfun, 1));
+}
+
+int pufe_setup(pufe_ctx *ctx, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "pufe_set_problem must come first");
+    if (ctx->prob.quad.mode != PUFE_QUAD_GEOM)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED, "the device rule builder supports the geometric mode");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    Plan &pl = ctx->plan;
+    const int64_t nel = pl.nel;
+    const int n_atoms = (int)ctx->prob.species.size();
+    CHECK_HIP(ctx, ctx->d_pos.upload(ctx->prob.pos, st), "upload positions");
+    CHECK_HIP(ctx, ctx->d_leaf_count.alloc(nel + 1), "alloc leaf counts");
+    CHECK_HIP(ctx, ctx->d_leaf_off.alloc(nel + 1), "alloc leaf offsets");
+    const double L[3] = {pl.lat[0], pl.lat[4], pl.lat[8]};
+    const pufe_quad &q = ctx->prob.quad;
+    // count leaves, scan, emit (one octree walk per element, twice)
+    CHECK_HIP(ctx, launch_aq_geom(pl.kp, nel, ctx->d_pos.p, n_atoms, L, q.max_level, q.dist, ctx->d_leaf_count.p,
+                                  nullptr, nullptr, nullptr, st), "adaptive quadrature (count)");
+    CHECK_HIP(ctx, launch_scan(ctx->d_leaf_count.p, nel, ctx->d_leaf_off.p, st), "scan");
+    ctx->leaf_off_h.assign(nel + 1, 0);
+    CHECK_HIP(ctx, hipMemcpyAsync(ctx->leaf_off_h.data(), ctx->d_leaf_off.p, sizeof(int64_t) * (nel + 1),
+                                  hipMemcpyDeviceToHost, st), "download leaf offsets");
+    CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
+    ctx->n_leaves = ctx->leaf_off_h[nel];
+    ctx->n_qp = ctx->n_leaves * pl.kp.n3;
+    CHECK_HIP(ctx, ctx->d_leaves.alloc(ctx->n_leaves), "alloc leaves");
+    CHECK_HIP(ctx, ctx->d_leaf_elem.alloc(ctx->n_leaves), "alloc leaf elements");
+    CHECK_HIP(ctx, launch_aq_geom(pl.kp, nel, ctx->d_pos.p, n_atoms, L, q.max_level, q.dist, nullptr,
+                                  ctx->d_leaf_off.p, ctx->d_leaves.p, ctx->d_leaf_elem.p, st),
+              "adaptive quadrature (emit)");
+    for (int64_t e = 0; e < nel; ++e) {
+        pl.elems[e].leaf_off = ctx->leaf_off_h[e];
+        pl.elems[e].leaf_end = ctx->leaf_off_h[e + 1];
+    }
+    plan_items(ctx);
+    if (ctx->lds > 160 * 1024)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED, "contraction stage does not fit in LDS");
+    CHECK_HIP(ctx, ctx->d_elems.upload(pl.elems, st), "upload elements");
+    CHECK_HIP(ctx, ctx->d_groups.upload(pl.groups, st), "upload groups");
+    CHECK_HIP(ctx, ctx->d_img.upload(pl.img, st), "upload images");
+    CHECK_HIP(ctx, ctx->d_edof.upload(pl.edof, st), "upload enriched functions");
+    CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
+    CHECK_HIP(ctx, ctx->d_color_elems.upload(pl.color_elems, st), "upload colours");
+    CHECK_HIP(ctx, ctx->d_brow.upload(pl.brow, st), "upload layout");
+    CHECK_HIP(ctx, ctx->d_bcol.upload(pl.bcol, st), "upload layout");
+    CHECK_HIP(ctx, ctx->d_bval_off.upload(pl.bval_off, st), "upload layout");
+    CHECK_HIP(ctx, ctx->d_dof_off.upload(pl.dof_off, st), "upload layout");
+    CHECK_HIP(ctx, ctx->d_partial.alloc((size_t)ctx->part_slots * 512), "alloc partial tiles");
+    CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
+    ctx->have_setup = true;
+    return PUFE_OK;
+}
+
+int pufe_query(pufe_ctx *ctx, pufe_sizes *out) {
+    if (!ctx || !out) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "no problem defined");
+    const Plan &pl = ctx->plan;
+    std::memset(out, 0, sizeof *out);
+    out->n_elem = pl.nel;
+    out->n_vertex = pl.nv;
+    out->n_dof = pl.dof_off[pl.nv];
+    out->n_fe_dof = pl.nv * pl.nfs;
+    out->n_enr_dof = out->n_dof - out->n_fe_dof;
+    out->nnzb = (int64_t)pl.bcol.size();
+    out->nnz = pl.nnz;
+    out->n_qp = ctx->n_qp;
+    out->n_leaves = ctx->n_leaves;
+    out->max_nloc = pl.max_nloc;
+    out->n_colors = (int32_t)pl.color_off.size() - 1;
+    out->n_atoms = (int32_t)ctx->prob.species.size();
+    out->n_fe_slots = pl.nfs;
+    return PUFE_OK;
+}
+
+int pufe_get_layout(pufe_ctx *ctx, int64_t *dof_offset, int64_t *brow_ptr, int32_t *bcol, int64_t *bval_offset) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "no problem defined");
+    const Plan &pl = ctx->plan;
+    if (dof_offset) std::memcpy(dof_offset, pl.dof_off.data(), sizeof(int64_t) * pl.dof_off.size());
+    if (brow_ptr) std::memcpy(brow_ptr, pl.brow_ptr.data(), sizeof(int64_t) * pl.brow_ptr.size());
+    if (bcol) std::memcpy(bcol, pl.bcol.data(), sizeof(int32_t) * pl.bcol.size());
+    if (bval_offset) std::memcpy(bval_offset, pl.bval_off.data(), sizeof(int64_t) * pl.bval_off.size());
+    return PUFE_OK;
+}
+
+int pufe_get_quadrature(pufe_ctx *ctx, double *d_xyz, double *d_w, int64_t *d_elem_qp_offset, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (d_xyz || d_w)
+        CHECK_HIP(ctx, launch_qp_export(ctx->plan.kp, ctx->n_leaves, ctx->d_leaves.p, ctx->d_leaf_elem.p, d_xyz, d_w, st),
+                  "quadrature export");
+    if (d_elem_qp_offset)
+        CHECK_HIP(ctx, launch_elem_qp_offset(ctx->plan.kp, ctx->plan.nel, ctx->d_leaf_off.p, d_elem_qp_offset, st),
+                  "quadrature offsets");
+    return PUFE_OK;
+}
+
+int pufe_get_leaves(pufe_ctx *ctx, int32_t *level, int32_t *ijk, int64_t *elem_leaf_offset) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    std::vector<uint32_t> codes(std::max<int64_t>(ctx->n_leaves, 1));
+    CHECK_HIP(ctx, hipMemcpy(codes.data(), ctx->d_leaves.p, sizeof(uint32_t) * ctx->n_leaves, hipMemcpyDeviceToHost),
+              "download leaves");
+    for (int64_t i = 0; i < ctx->n_leaves; ++i) {
+        uint32_t c = codes[i];
+        if (level) level[i] = (int32_t)(c >> 27);
+        if (ijk) {
+            ijk[3 * i] = (int32_t)(c & 511u);
+            ijk[3 * i + 1] = (int32_t)((c >> 9) & 511u);
+            ijk[3 * i + 2] = (int32_t)((c >> 18) & 511u);
+        }
+    }
+    if (elem_leaf_offset) std::memcpy(elem_leaf_offset, ctx->leaf_off_h.data(), sizeof(int64_t) * ctx->leaf_off_h.size());
+    return PUFE_OK;
+}
+
+static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipStream_t st) {
+    if (precision != PUFE_PREC_FP64)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED, "only the FP64 contraction is available");
+    const Plan &pl = ctx->plan;
+    TimedRegion tr(ctx, 0, st);
+    CHECK_HIP(ctx, launch_contract_f64(pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p, ctx->d_groups.p,
+                                       ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_partial.p, ctx->lds, st),
+              "contraction");
+    return PUFE_OK;
+}
+
+int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision, int out_dtype,
+                  void *d_H, void *d_S, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    if (!d_V || !kpts || n_k < 1 || !d_H) return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer or n_k < 1");
+    if (precision < PUFE_PREC_FP64 || precision > PUFE_PREC_BF16X6)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "unknown precision");
+    if (out_dtype < PUFE_OUT_C128 || out_dtype > PUFE_OUT_F64_GAMMA)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "unknown output dtype");
+    for (int k = 0; k < n_k; ++k) {
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(kpts[3 * k + d])) return fail(ctx, PUFE_ERR_INVALID_ARG, "non-finite k-point");
+        if (out_dtype == PUFE_OUT_F64_GAMMA &&
+            (std::fmod(kpts[3 * k], 1.0) != 0.0 || std::fmod(kpts[3 * k + 1], 1.0) != 0.0 ||
+             std::fmod(kpts[3 * k + 2], 1.0) != 0.0))
+            return fail(ctx, PUFE_ERR_INVALID_ARG, "real output needs every k-point at Gamma");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    int rc = run_contraction(ctx, d_V, precision, st);
+    if (rc != PUFE_OK) return rc;
+    const Plan &pl = ctx->plan;
+    TimedRegion tr(ctx, 1, st);
+    const int64_t per = out_dtype == PUFE_OUT_F64_GAMMA ? pl.nnz : 2 * pl.nnz;
+    const bool f32 = out_dtype == PUFE_OUT_C64;
+    CHECK_HIP(ctx, launch_fill_zero(d_H, per * n_k, f32, st), "zero H");
+    if (d_S) CHECK_HIP(ctx, launch_fill_zero(d_S, per * n_k, f32, st), "zero S");
+    const size_t esz = f32 ? sizeof(float) : sizeof(double);
+    for (int k0 = 0; k0 < n_k; k0 += kMaxKPerLaunch) {
+        KPoints kps;
+        std::memset(&kps, 0, sizeof kps);
+        kps.nk = std::min(kMaxKPerLaunch, n_k - k0);
+        for (int k = 0; k < kps.nk; ++k)
+            for (int d = 0; d < 3; ++d) kps.kap[k][d] = kpts[3 * (k0 + k) + d];
+        char *H = (char *)d_H + (size_t)k0 * per * esz;
+        char *S = d_S ? (char *)d_S + (size_t)k0 * per * esz : nullptr;
+        for (size_t col = 0; col + 1 < pl.color_off.size(); ++col) {
+            int n = pl.color_off[col + 1] - pl.color_off[col];
+            CHECK_HIP(ctx, launch_scatter(pl.kp, ctx->d_elems.p, ctx->d_color_elems.p + pl.color_off[col], n,
+                                          ctx->d_edof.p, ctx->d_partial.p, kps, out_dtype, H, S, pl.nnz, st),
+                      "scatter");
+        }
+    }
+    return PUFE_OK;
+}
+
+int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int precision, double *d_He,
+                          double *d_Se, int32_t *nloc, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    if (!d_V || !d_He || !d_Se || elem < 0 || elem >= ctx->plan.nel)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "bad element or null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    int rc = run_contraction(ctx, d_V, precision, st);
+    if (rc != PUFE_OK) return rc;
+    CHECK_HIP(ctx, launch_elem_matrices(ctx->d_elems.p, elem, ctx->d_partial.p, d_He, d_Se, ctx->plan.elems[elem].nloc, st),
+              "element matrices");
+    if (nloc) *nloc = ctx->plan.elems[elem].nloc;
+    return PUFE_OK;
+}
+
+int pufe_assemble_backward(pufe_ctx *ctx, const double *, const double *, const void *, const void *, int,
+                           double *, double *, void *) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    return fail(ctx, PUFE_ERR_UNSUPPORTED, "the adjoint kernel is not built yet");
+}
+
+int pufe_bsr_to_dense(pufe_ctx *ctx, const void *d_bsr, int dtype, double *d_dense, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    if (!d_bsr || !d_dense) return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer");
+    if (dtype != PUFE_OUT_C128 && dtype != PUFE_OUT_F64_GAMMA)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "dense expansion takes C128 or F64_GAMMA values");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const Plan &pl = ctx->plan;
+    int64_t n = pl.dof_off[pl.nv];
+    CHECK_HIP(ctx, launch_fill_zero(d_dense, 2 * n * n, false, st), "zero dense");
+    CHECK_HIP(ctx, launch_bsr_to_dense((int64_t)pl.bcol.size(), ctx->d_brow.p, ctx->d_bcol.p, ctx->d_bval_off.p,
+                                       ctx->d_dof_off.p, d_bsr, dtype == PUFE_OUT_C128 ? 0 : 1, n, d_dense, st),
+              "bsr to dense");
+    return PUFE_OK;
+}
+
+int pufe_enable_timing(pufe_ctx *ctx, int on) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    ctx->timing = on != 0;
+    return PUFE_OK;
+}
+
+int pufe_kernel_times(pufe_ctx *ctx, double *out_ms, int64_t *counts, int reset) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    for (int k = 0; k < 4; ++k) {
+        double ms = 0.0;
+        for (auto &pr : ctx->ev[k]) {
+            CHECK_HIP(ctx, hipEventSynchronize(pr.second), "event sync");
+            float t = 0.f;
+            CHECK_HIP(ctx, hipEventElapsedTime(&t, pr.first, pr.second), "event time");
+            ms += t;
+        }
+        if (out_ms) out_ms[k] = ms;
+        if (counts) counts[k] = (int64_t)ctx->ev[k].size();
+    }
+    if (reset) ctx->clear_events();
+    return PUFE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,666 @@
+// HIP kernels of the PUFE assembly for gfx950 (MI355X).
+//
+//   aq_*            adaptive quadrature: octree leaves per element (section
+//                   "Adaptive quadrature"), geometric refinement mode
+//   contract_f64    fused basis evaluation + FP64 MFMA contraction of the
+//                   element matrices H_e = B W_H B^T, S_e = B W B^T (eq. disceig3d)
+//   scatter         Bloch phases + atomic-free coloured scatter into the
+//                   block-sparse H and S (one launch per element colour)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "basis.hpp"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+namespace pufe {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------- quadrature
+
+// Closest distance^2 from the axis-aligned box [lo, hi] to any lattice image
+// of the atoms of an orthorhombic cell (side lengths L).
+__device__ double box_nucleus_dist2(const double *lo, const double *hi, const double *L,
+                                    const double *pos, int n_atoms) {
+    double best = 1e300;
+    for (int A = 0; A < n_atoms; ++A) {
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double mid = 0.5 * (lo[d] + hi[d]), half = 0.5 * (hi[d] - lo[d]);
+            double t = pos[3 * A + d];
+            double y = t - L[d] * rint((t - mid) / L[d]);   // image nearest to the centre
+            double dd = fabs(y - mid) - half;
+            if (dd > 0.0) d2 += dd * dd;
+        }
+        best = fmin(best, d2);
+    }
+    return best;
+}
+
+// One thread per element walks its octree depth first (children c = c1 +
+// 2 c2 + 4 c3 in order); a cell splits while its level is below max_level
+// and it lies within `dist` of a nucleus image.  With out == nullptr only the
+// leaves are counted.
+__global__ void aq_geom_kernel(const KParams kp, int64_t nel, const double *__restrict__ pos, int n_atoms,
+                               double L0, double L1, double L2, int max_level, double dist2,
+                               int64_t *__restrict__ count, const int64_t *__restrict__ off,
+                               uint32_t *__restrict__ out, int32_t *__restrict__ leaf_elem) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nel) return;
+    const double L[3] = {L0, L1, L2};
+    int i[3] = {(int)(e % kp.mesh[0]), (int)((e / kp.mesh[0]) % kp.mesh[1]),
+                (int)(e / ((int64_t)kp.mesh[0] * kp.mesh[1]))};
+    double h[3] = {L0 / kp.mesh[0], L1 / kp.mesh[1], L2 / kp.mesh[2]};
+    uint32_t stack[8 * kMaxLevel + 2];
+    int sp = 0;
+    stack[sp++] = leaf_pack(0, 0, 0, 0);
+    int64_t n = 0, base = out ? off[e] : 0;
+    while (sp > 0) {
+        uint32_t code = stack[--sp];
+        int lev = (int)(code >> 27);
+        int c[3] = {(int)(code & 511u), (int)((code >> 9) & 511u), (int)((code >> 18) & 511u)};
+        bool split = false;
+        if (lev < max_level) {
+            double lo[3], hi[3], s = 1.0 / (double)(1 << lev);
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = (i[d] + c[d] * s) * h[d];
+                hi[d] = (i[d] + (c[d] + 1) * s) * h[d];
+            }
+            split = box_nucleus_dist2(lo, hi, L, pos, n_atoms) <= dist2;
+        }
+        if (split) {
+            for (int ch = 7; ch >= 0; --ch)
+                stack[sp++] = leaf_pack(lev + 1, 2 * c[0] + (ch & 1), 2 * c[1] + ((ch >> 1) & 1),
+                                        2 * c[2] + ((ch >> 2) & 1));
+        } else {
+            if (out) {
+                out[base + n] = code;
+                leaf_elem[base + n] = (int32_t)e;
+            }
+            ++n;
+        }
+    }
+    if (!out) count[e] = n;
+}
+
+// Exclusive scan of n int64 values into off[0..n] by one workgroup of 1024.
+__global__ __launch_bounds__(1024) void scan_kernel(const int64_t *__restrict__ in, int64_t n,
+                                                    int64_t *__restrict__ off) {
+    __shared__ int64_t part[1024];
+    int t = threadIdx.x;
+    int64_t per = (n + 1023) / 1024;
+    int64_t b = t * per, e = b + per < n ? b + per : n;
+    int64_t s = 0;
+    for (int64_t k = b; k < e; ++k) s += in[k];
+    part[t] = s;
+    __syncthreads();
+    for (int stride = 1; stride < 1024; stride <<= 1) {
+        int64_t v = t >= stride ? part[t - stride] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;
+    for (int64_t k = b; k < e; ++k) {
+        off[k] = run;
+        run += in[k];
+    }
+    if (t == 1023) off[n] = part[1023];
+}
+
+// Reference point and weight of Gauss point j of a leaf.
+__device__ __forceinline__ void leaf_point(const KParams &kp, uint32_t code, int j, double *xi, double *w) {
+    int lev = (int)(code >> 27);
+    int c[3] = {(int)(code & 511u), (int)((code >> 9) & 511u), (int)((code >> 18) & 511u)};
+    int k[3] = {j % kp.n, (j / kp.n) % kp.n, j / (kp.n * kp.n)};
+    double h = 1.0 / (double)(1 << lev);
+    double wt = h * h * h * kp.jac;
+    for (int d = 0; d < 3; ++d) {
+        xi[d] = -1.0 + (2.0 * c[d] + 1.0 + kp.gx[k[d]]) * h;
+        wt *= kp.gw[k[d]];
+    }
+    *w = wt;
+}
+
+__global__ void qp_export_kernel(const KParams kp, int64_t n_leaves, const uint32_t *__restrict__ leaves,
+                                 const int32_t *__restrict__ leaf_elem, double *__restrict__ xyz,
+                                 double *__restrict__ w) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_leaves * kp.n3) return;
+    int64_t lf = q / kp.n3;
+    int j = (int)(q % kp.n3);
+    int64_t e = leaf_elem[lf];
+    int i[3] = {(int)(e % kp.mesh[0]), (int)((e / kp.mesh[0]) % kp.mesh[1]),
+                (int)(e / ((int64_t)kp.mesh[0] * kp.mesh[1]))};
+    double xi[3], wt;
+    leaf_point(kp, leaves[lf], j, xi, &wt);
+    if (w) w[q] = wt;
+    if (xyz)
+        for (int c = 0; c < 3; ++c) {
+            double x = 0.0;
+            for (int d = 0; d < 3; ++d) x += (i[d] + 0.5 * (xi[d] + 1.0)) * kp.E[3 * d + c];
+            xyz[3 * q + c] = x;
+        }
+}
+
+__global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64_t *__restrict__ leaf_off,
+                                      int64_t *__restrict__ qp_off) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e <= nel) qp_off[e] = leaf_off[e] * kp.n3;
+}
+
+// ---------------------------------------------------------- contraction
+
+// Enrichment functions of one (atom, descriptor) group at one point x:
+// Psi_m = sum over images of g(s) S_m(r), grad Psi_m = 2 g'(s) r S_m + g grad S_m,
+// g(s) = exp(-a s) (1 - s/rc^2)^3, r = x - image centre, s = |r|^2 < rc^2.
+// Written to o[m * Q * 4 + (0: value, 1..3: gradient)].
+template <int L, int Q>
+__device__ __forceinline__ void group_eval(const GroupDev &G, const double *__restrict__ img, const double *x,
+                                           double *o) {
+    constexpr int NM = 2 * L + 1;
+    double psi[NM], gp[3 * NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) psi[m] = gp[3 * m] = gp[3 * m + 1] = gp[3 * m + 2] = 0.0;
+    const double rc2 = G.rc * G.rc, inv_rc2 = 1.0 / rc2;
+    const double *c0 = img + 3 * G.img_off;
+    for (int k = 0; k < G.nimg; ++k) {
+        const double rx = x[0] - c0[3 * k], ry = x[1] - c0[3 * k + 1], rz = x[2] - c0[3 * k + 2];
+        const double s = rx * rx + ry * ry + rz * rz;
+        if (s >= rc2) continue;
+        const double ex = exp(-G.a * s), c = 1.0 - s * inv_rc2, c2 = c * c;
+        const double g0 = ex * c2 * c;
+        const double g1 = -ex * c2 * (G.a * c + 3.0 * inv_rc2);
+        double S[NM > 7 ? NM : 7], dS[21];
+        solid_harmonics(L, rx, ry, rz, S, dS);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            psi[m] += g0 * S[m];
+            gp[3 * m] += 2.0 * g1 * rx * S[m] + g0 * dS[3 * m];
+            gp[3 * m + 1] += 2.0 * g1 * ry * S[m] + g0 * dS[3 * m + 1];
+            gp[3 * m + 2] += 2.0 * g1 * rz * S[m] + g0 * dS[3 * m + 2];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        double *om = o + (size_t)m * Q * 4;
+        om[0] = psi[m];
+        om[1] = gp[3 * m];
+        om[2] = gp[3 * m + 1];
+        om[3] = gp[3 * m + 2];
+    }
+}
+
+// Work-group shape and LDS map of the fused contraction kernel.
+//   sB[row][q][4]   (grad_x, grad_y, grad_z, value) of the item's local rows
+//   sPsi[f][q][4]   (value, gradient) of the element's enrichment functions
+//   per-qp:  xi[3], x[3], w, w V, valid, 1D Lagrange values/derivatives
+template <int Q>
+struct ContractLds {
+    static constexpr int RS = Q * 4 + 2;  // padded row stride of sB (doubles)
+    static __host__ __device__ size_t bytes(int rows, int nfun) {
+        return sizeof(double) * ((size_t)rows * RS + (size_t)nfun * Q * 4 + (size_t)Q * 26);
+    }
+};
+
+template <int Q>
+__global__ __launch_bounds__(256) void contract_f64_kernel(
+    const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
+    const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
+    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
+    extern __shared__ double smem[];
+    constexpr int RS = ContractLds<Q>::RS;
+    const ItemDev it = items[blockIdx.x];
+    const ElemDev &el = elems[it.elem];
+    const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun;
+    const bool diag = it.I0 == it.J0;
+    const int nrow = 16 * (diag ? it.nI : it.nI + it.nJ);
+    double *sB = smem;
+    double *sPsi = sB + (size_t)nrow * RS;
+    double *sQ = sPsi + (size_t)nfun * Q * 4;
+    double *sXi = sQ;             // [Q][3]
+    double *sX = sQ + 3 * Q;      // [Q][3]
+    double *sW = sQ + 6 * Q;      // [Q]
+    double *sWV = sQ + 7 * Q;     // [Q]
+    double *sL = sQ + 8 * Q;      // [Q][3][3]  1D FE values
+    double *sD = sQ + 17 * Q;     // [Q][3][3]  1D FE derivatives
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n3 = kp.n3;
+    const int64_t q_begin = it.leaf_b * n3, q_end = it.leaf_e * n3;
+    const int ti0 = it.I0, tj0 = it.J0;
+
+    // tile pairs of this item, four per wave at most
+    const int npairs = diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
+    int pr_row[4], pr_col[4], pr_I[4], pr_J[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        int pidx = wave + 4 * u;
+        pr_row[u] = pr_col[u] = pr_I[u] = pr_J[u] = -1;
+        if (pidx < npairs) {
+            int a, b;
+            if (diag) {  // enumerate (a <= b) column by column
+                b = 0;
+                while ((b + 1) * (b + 2) / 2 <= pidx) ++b;
+                a = pidx - b * (b + 1) / 2;
+                pr_row[u] = 16 * a;
+                pr_col[u] = 16 * b;
+                pr_I[u] = ti0 + a;
+                pr_J[u] = ti0 + b;
+            } else {
+                a = pidx % it.nI;
+                b = pidx / it.nI;
+                pr_row[u] = 16 * a;
+                pr_col[u] = 16 * (it.nI + b);
+                pr_I[u] = ti0 + a;
+                pr_J[u] = tj0 + b;
+            }
+        }
+    }
+    double4_t accH[4], accS[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        accH[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        accS[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    }
+    const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
+                           el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
+                           el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
+
+    for (int64_t qb = q_begin; qb < q_end; qb += Q) {
+        // ---- per-point geometry
+        if (tid < Q) {
+            int64_t qg = qb + tid;
+            double xi[3] = {0.0, 0.0, 0.0}, w = 0.0, wv = 0.0;
+            if (qg < q_end) {
+                int64_t lf = qg / n3;
+                leaf_point(kp, leaves[lf], (int)(qg - lf * n3), xi, &w);
+                wv = w * V[qg];
+            }
+            for (int d = 0; d < 3; ++d) sXi[3 * tid + d] = xi[d];
+            for (int c = 0; c < 3; ++c)
+                sX[3 * tid + c] = org[c] + 0.5 * (xi[0] + 1.0) * kp.E[c] + 0.5 * (xi[1] + 1.0) * kp.E[3 + c] +
+                                  0.5 * (xi[2] + 1.0) * kp.E[6 + c];
+            sW[tid] = w;
+            sWV[tid] = wv;
+            for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], sL + 9 * tid + 3 * d, sD + 9 * tid + 3 * d);
+        }
+        __syncthreads();
+        // ---- enrichment functions: periodic image sums (eq. Psi, f(R) = 1)
+        for (int idx = tid; idx < ngrp * Q; idx += 256) {
+            const int g = idx / Q, q = idx - g * Q;
+            const GroupDev G = groups[el.grp_off + g];
+            double *o = sPsi + ((size_t)G.fbase * Q + q) * 4;
+            switch (G.l) {
+                case 0: group_eval<0, Q>(G, img, sX + 3 * q, o); break;
+                case 1: group_eval<1, Q>(G, img, sX + 3 * q, o); break;
+                case 2: group_eval<2, Q>(G, img, sX + 3 * q, o); break;
+                default: group_eval<3, Q>(G, img, sX + 3 * q, o); break;
+            }
+        }
+        __syncthreads();
+        // ---- local basis rows: FE functions and PU x enrichment (eq. pufebasis)
+        for (int idx = tid; idx < nrow * Q; idx += 256) {
+            const int r = idx / Q, q = idx - r * Q;
+            const int a = (diag || r < 16 * it.nI) ? 16 * ti0 + r : 16 * tj0 + (r - 16 * it.nI);
+            double *o = sB + (size_t)r * RS + 4 * q;
+            if (a >= nloc || sW[q] == 0.0) {
+                o[0] = o[1] = o[2] = o[3] = 0.0;
+                continue;
+            }
+            const double *L = sL + 9 * q, *D = sD + 9 * q;
+            double val, dxi[3];
+            if (a < nfe) {
+                int n1 = kp.p + 1;
+                int a1 = a % n1, a2 = (a / n1) % n1, a3 = a / (n1 * n1);
+                double l1 = L[a1], l2 = L[3 + a2], l3 = L[6 + a3];
+                val = l1 * l2 * l3;
+                dxi[0] = D[a1] * l2 * l3;
+                dxi[1] = l1 * D[3 + a2] * l3;
+                dxi[2] = l1 * l2 * D[6 + a3];
+            } else {
+                const int pk = edof[el.edof_off + (a - nfe)];
+                const int c = pk & 7, f = (pk >> 3) & 255;
+                double m[3], dm[3];
+                for (int d = 0; d < 3; ++d) {
+                    const double t = sXi[3 * q + d];
+                    const int bit = (c >> d) & 1;
+                    m[d] = bit ? 0.5 * (1.0 + t) : 0.5 * (1.0 - t);
+                    dm[d] = bit ? 0.5 : -0.5;
+                }
+                const double M = m[0] * m[1] * m[2];
+                const double dM[3] = {dm[0] * m[1] * m[2], m[0] * dm[1] * m[2], m[0] * m[1] * dm[2]};
+                double gM[3];
+                for (int cc = 0; cc < 3; ++cc)
+                    gM[cc] = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
+                const double *ps = sPsi + ((size_t)f * Q + q) * 4;
+                o[0] = gM[0] * ps[0] + M * ps[1];
+                o[1] = gM[1] * ps[0] + M * ps[2];
+                o[2] = gM[2] * ps[0] + M * ps[3];
+                o[3] = M * ps[0];
+                continue;
+            }
+            for (int cc = 0; cc < 3; ++cc)
+                o[cc] = kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2];
+            o[3] = val;
+        }
+        __syncthreads();
+        // ---- MFMA: D[i][j] += sum_k A[i][k] B[k][j]; lane = i + 16 k for A,
+        // lane = j + 16 k for B.  S: k runs over 4 points of the value row;
+        // H: k runs over the (grad_x, grad_y, grad_z, value) components of one
+        // point with weights (w/2, w/2, w/2, w V).
+        const int r16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (pr_row[u] < 0) continue;
+            const double *rowA = sB + (size_t)(pr_row[u] + r16) * RS;
+            const double *rowB = sB + (size_t)(pr_col[u] + r16) * RS;
+#pragma unroll
+            for (int s4 = 0; s4 < Q / 4; ++s4) {
+                const int qs = 4 * s4 + k4;
+                accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowA[4 * qs + 3] * sW[qs], rowB[4 * qs + 3],
+                                                               accS[u], 0, 0, 0);
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    const int q = 4 * s4 + qq;
+                    const double wf = k4 < 3 ? 0.5 * sW[q] : sWV[q];
+                    accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowA[4 * q + k4] * wf, rowB[4 * q + k4],
+                                                                   accH[u], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // ---- partial tiles, row-major 16x16; D layout: lane holds rows 4(lane/16)+i, column lane%16
+    const int T = (nloc + 15) / 16;
+    const int64_t P = (int64_t)T * (T + 1) / 2;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (pr_row[u] < 0) continue;
+        const int64_t pidx = (int64_t)pr_J[u] * (pr_J[u] + 1) / 2 + pr_I[u];
+        double *dst = partial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
+        const int j = lane & 15, i0 = 4 * (lane >> 4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            dst[(i0 + r) * 16 + j] = accH[u][r];
+            dst[256 + (i0 + r) * 16 + j] = accS[u][r];
+        }
+    }
+}
+
+// -------------------------------------------------------------- scatter
+
+__global__ void fill_zero_kernel(double *__restrict__ p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.0;
+}
+
+__global__ void fill_zero_f32_kernel(float *__restrict__ p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.0f;
+}
+
+// corner and vertex slot of local function a
+__device__ __forceinline__ void local_slot(const ElemDev &el, const int32_t *edof, int p, int a, int *corner,
+                                           int *slot) {
+    if (a < el.nfe) {
+        if (p == 1) {
+            *corner = a;
+            *slot = 0;
+        } else {
+            int d0 = a % 3, d1 = (a / 3) % 3, d2 = a / 9;
+            *corner = (d0 == 2) | ((d1 == 2) << 1) | ((d2 == 2) << 2);
+            *slot = (d0 == 1) | ((d1 == 1) << 1) | ((d2 == 1) << 2);
+        }
+    } else {
+        int pk = edof[el.edof_off + (a - el.nfe)];
+        *corner = pk & 7;
+        *slot = pk >> 11;
+    }
+}
+
+// Element e of colour c: sum its K-chunk partials in a fixed order, then for
+// every k-point add conj(p_a) p_b H_e[a][b] (and the mirrored entry) into the
+// BSR values.  Elements of one colour share no vertex, so no two work groups
+// of one launch touch the same entry.
+__global__ __launch_bounds__(256) void scatter_kernel(const KParams kp, const ElemDev *__restrict__ elems,
+                                                      const int32_t *__restrict__ color_elems,
+                                                      const int32_t *__restrict__ edof,
+                                                      const double *__restrict__ partial, const KPoints kps,
+                                                      int out_dtype, void *__restrict__ Hout,
+                                                      void *__restrict__ Sout, int64_t nnz) {
+    __shared__ double zr[kMaxKPerLaunch][27], zi[kMaxKPerLaunch][27];
+    const int e = color_elems[blockIdx.x];
+    const ElemDev &el = elems[e];
+    for (int idx = threadIdx.x; idx < kps.nk * 27; idx += blockDim.x) {
+        int k = idx / 27, t = idx % 27;
+        int dn[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+        double ph = 2.0 * M_PI * (kps.kap[k][0] * dn[0] + kps.kap[k][1] * dn[1] + kps.kap[k][2] * dn[2]);
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        zr[k][t] = cs;
+        zi[k][t] = sn;
+    }
+    __syncthreads();
+    const int nloc = el.nloc;
+    const int T = (nloc + 15) / 16;
+    const int64_t P = (int64_t)T * (T + 1) / 2;
+    const int64_t total = P * 256;
+    for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int64_t pidx = idx >> 8;
+        const int i = (int)((idx >> 4) & 15), j = (int)(idx & 15);
+        int J = 0;
+        while ((int64_t)(J + 1) * (J + 2) / 2 <= pidx) ++J;
+        const int I = (int)(pidx - (int64_t)J * (J + 1) / 2);
+        const int a = 16 * I + i, b = 16 * J + j;
+        if (a >= nloc || b >= nloc || a > b) continue;
+        double h = 0.0, s = 0.0;
+        for (int c = 0; c < el.nchunk; ++c) {
+            const double *src = partial + (el.part_base + (int64_t)c * P + pidx) * 512;
+            h += src[i * 16 + j];
+            s += src[256 + i * 16 + j];
+        }
+        int ca, sa, cb, sb;
+        local_slot(el, edof, kp.p, a, &ca, &sa);
+        local_slot(el, edof, kp.p, b, &cb, &sb);
+        const int64_t oab = el.blk[ca * 8 + cb] + (int64_t)sa * el.bw[cb] + sb;
+        const int64_t oba = el.blk[cb * 8 + ca] + (int64_t)sb * el.bw[ca] + sa;
+        int t = 0;
+        for (int d = 2; d >= 0; --d) {
+            int dn = ((el.shifts >> (3 * cb + d)) & 1) - ((el.shifts >> (3 * ca + d)) & 1);
+            t = 3 * t + (dn + 1);
+        }
+        for (int k = 0; k < kps.nk; ++k) {
+            const double cr = zr[k][t], ci = zi[k][t];
+            if (out_dtype == 0) {
+                double *H = (double *)Hout + 2 * (int64_t)k * nnz;
+                H[2 * oab] += cr * h;
+                H[2 * oab + 1] += ci * h;
+                if (a != b) {
+                    H[2 * oba] += cr * h;
+                    H[2 * oba + 1] -= ci * h;
+                }
+                if (Sout) {
+                    double *S = (double *)Sout + 2 * (int64_t)k * nnz;
+                    S[2 * oab] += cr * s;
+                    S[2 * oab + 1] += ci * s;
+                    if (a != b) {
+                        S[2 * oba] += cr * s;
+                        S[2 * oba + 1] -= ci * s;
+                    }
+                }
+            } else if (out_dtype == 1) {
+                float *H = (float *)Hout + 2 * (int64_t)k * nnz;
+                H[2 * oab] += (float)(cr * h);
+                H[2 * oab + 1] += (float)(ci * h);
+                if (a != b) {
+                    H[2 * oba] += (float)(cr * h);
+                    H[2 * oba + 1] -= (float)(ci * h);
+                }
+                if (Sout) {
+                    float *S = (float *)Sout + 2 * (int64_t)k * nnz;
+                    S[2 * oab] += (float)(cr * s);
+                    S[2 * oab + 1] += (float)(ci * s);
+                    if (a != b) {
+                        S[2 * oba] += (float)(cr * s);
+                        S[2 * oba + 1] -= (float)(ci * s);
+                    }
+                }
+            } else {
+                double *H = (double *)Hout + (int64_t)k * nnz;
+                H[oab] += h;
+                if (a != b) H[oba] += h;
+                if (Sout) {
+                    double *S = (double *)Sout + (int64_t)k * nnz;
+                    S[oab] += s;
+                    if (a != b) S[oba] += s;
+                }
+            }
+        }
+    }
+}
+
+// Element matrices of one element (full, mirrored), from its partials.
+__global__ void elem_matrices_kernel(const ElemDev *__restrict__ elems, int64_t e,
+                                     const double *__restrict__ partial, double *__restrict__ He,
+                                     double *__restrict__ Se, int ld) {
+    const ElemDev &el = elems[e];
+    const int nloc = el.nloc, T = (nloc + 15) / 16;
+    const int64_t P = (int64_t)T * (T + 1) / 2;
+    for (int64_t idx = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; idx < (int64_t)nloc * nloc;
+         idx += (int64_t)blockDim.x * gridDim.x) {
+        int a = (int)(idx / nloc), b = (int)(idx % nloc);
+        int lo = a < b ? a : b, hi = a < b ? b : a;
+        int I = lo / 16, J = hi / 16, i = lo % 16, j = hi % 16;
+        int64_t pidx = (int64_t)J * (J + 1) / 2 + I;
+        double h = 0.0, s = 0.0;
+        for (int c = 0; c < el.nchunk; ++c) {
+            const double *src = partial + (el.part_base + (int64_t)c * P + pidx) * 512;
+            h += src[i * 16 + j];
+            s += src[256 + i * 16 + j];
+        }
+        He[(int64_t)a * ld + b] = h;
+        Se[(int64_t)a * ld + b] = s;
+    }
+}
+
+// BSR values (C128 or real) -> dense complex n x n, row-major.
+__global__ void bsr_to_dense_kernel(int64_t nnzb, const int32_t *__restrict__ brow,
+                                    const int32_t *__restrict__ bcol, const int64_t *__restrict__ bval_off,
+                                    const int64_t *__restrict__ dof_off, const void *__restrict__ src, int dtype,
+                                    int64_t n, double *__restrict__ dense) {
+    for (int64_t blk = blockIdx.x; blk < nnzb; blk += gridDim.x) {
+        const int64_t v = brow[blk], w = bcol[blk];
+        const int64_t r0 = dof_off[v], c0 = dof_off[w];
+        const int bc = (int)(dof_off[w + 1] - c0);
+        const int64_t cnt = bval_off[blk + 1] - bval_off[blk];
+        for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int64_t r = t / bc, c = t % bc;
+            const int64_t src_i = bval_off[blk] + t;
+            const int64_t dst = ((r0 + r) * n + (c0 + c)) * 2;
+            if (dtype == 0) {
+                dense[dst] = ((const double *)src)[2 * src_i];
+                dense[dst + 1] = ((const double *)src)[2 * src_i + 1];
+            } else {
+                dense[dst] = ((const double *)src)[src_i];
+                dense[dst + 1] = 0.0;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+#define PUFE_HIP(x)                              \
+    do {                                         \
+        hipError_t e_ = (x);                     \
+        if (e_ != hipSuccess) return e_;         \
+    } while (0)
+
+hipError_t launch_aq_geom(const KParams &kp, int64_t nel, const double *pos, int n_atoms, const double *L,
+                          int max_level, double dist, int64_t *count, const int64_t *off, uint32_t *out,
+                          int32_t *leaf_elem, hipStream_t st) {
+    int blocks = (int)((nel + 127) / 128);
+    hipLaunchKernelGGL(aq_geom_kernel, dim3(blocks), dim3(128), 0, st, kp, nel, pos, n_atoms, L[0], L[1], L[2],
+                       max_level, dist * dist, count, off, out, leaf_elem);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const int64_t *in, int64_t n, int64_t *off, hipStream_t st) {
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, in, n, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_qp_export(const KParams &kp, int64_t n_leaves, const uint32_t *leaves, const int32_t *leaf_elem,
+                            double *xyz, double *w, hipStream_t st) {
+    int64_t nq = n_leaves * kp.n3;
+    if (nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(qp_export_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, kp, n_leaves,
+                       leaves, leaf_elem, xyz, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *leaf_off, int64_t *qp_off,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(elem_qp_offset_kernel, dim3((unsigned)((nel + 256) / 256)), dim3(256), 0, st, kp, nel,
+                       leaf_off, qp_off);
+    return hipGetLastError();
+}
+
+size_t contract_lds_bytes(int rows, int nfun) { return ContractLds<kContractQ>::bytes(rows, nfun); }
+
+hipError_t launch_contract_f64(const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+                               const GroupDev *groups, const double *img, const int32_t *edof,
+                               const uint32_t *leaves, const double *V, double *partial, size_t lds,
+                               hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        PUFE_HIP(hipFuncSetAttribute((const void *)contract_f64_kernel<kContractQ>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_set = true;
+    }
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(contract_f64_kernel<kContractQ>, dim3(n_items), dim3(256), lds, st, kp, items, elems,
+                       groups, img, edof, leaves, V, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, int64_t n, bool f32, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (f32)
+        hipLaunchKernelGGL(fill_zero_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (float *)p, n);
+    else
+        hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (double *)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int32_t *color_elems, int n_elems,
+                          const int32_t *edof, const double *partial, const KPoints &kps, int out_dtype,
+                          void *H, void *S, int64_t nnz, hipStream_t st) {
+    if (n_elems == 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_kernel, dim3(n_elems), dim3(256), 0, st, kp, elems, color_elems, edof, partial, kps,
+                       out_dtype, H, S, nnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_elem_matrices(const ElemDev *elems, int64_t e, const double *partial, double *He, double *Se,
+                                int ld, hipStream_t st) {
+    hipLaunchKernelGGL(elem_matrices_kernel, dim3(16), dim3(256), 0, st, elems, e, partial, He, Se, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_bsr_to_dense(int64_t nnzb, const int32_t *brow, const int32_t *bcol, const int64_t *bval_off,
+                               const int64_t *dof_off, const void *src, int dtype, int64_t n, double *dense,
+                               hipStream_t st) {
+    int64_t blocks = nnzb < 65535 ? nnzb : 65535;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(bsr_to_dense_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nnzb, brow, bcol, bval_off,
+                       dof_off, src, dtype, n, dense);
+    return hipGetLastError();
+}
+
+}  // namespace pufe

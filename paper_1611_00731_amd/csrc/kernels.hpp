@@ -1,0 +1,41 @@
+// Host-side launchers of the PUFE kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables.hpp"
+
+namespace pufe {
+
+constexpr int kContractQ = 16;      // quadrature points per LDS stage of the contraction
+constexpr int kMaxKPerLaunch = 16;  // k-points handled by one scatter launch
+
+struct KPoints {
+    int32_t nk;
+    double kap[kMaxKPerLaunch][3];
+};
+
+hipError_t launch_aq_geom(const KParams &kp, int64_t nel, const double *pos, int n_atoms, const double *L,
+                          int max_level, double dist, int64_t *count, const int64_t *off, uint32_t *out,
+                          int32_t *leaf_elem, hipStream_t st);
+hipError_t launch_scan(const int64_t *in, int64_t n, int64_t *off, hipStream_t st);
+hipError_t launch_qp_export(const KParams &kp, int64_t n_leaves, const uint32_t *leaves, const int32_t *leaf_elem,
+                            double *xyz, double *w, hipStream_t st);
+hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *leaf_off, int64_t *qp_off,
+                                 hipStream_t st);
+size_t contract_lds_bytes(int rows, int nfun);
+hipError_t launch_contract_f64(const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+                               const GroupDev *groups, const double *img, const int32_t *edof,
+                               const uint32_t *leaves, const double *V, double *partial, size_t lds,
+                               hipStream_t st);
+hipError_t launch_fill_zero(void *p, int64_t n, bool f32, hipStream_t st);
+hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int32_t *color_elems, int n_elems,
+                          const int32_t *edof, const double *partial, const KPoints &kps, int out_dtype,
+                          void *H, void *S, int64_t nnz, hipStream_t st);
+hipError_t launch_elem_matrices(const ElemDev *elems, int64_t e, const double *partial, double *He, double *Se,
+                                int ld, hipStream_t st);
+hipError_t launch_bsr_to_dense(int64_t nnzb, const int32_t *brow, const int32_t *bcol, const int64_t *bval_off,
+                               const int64_t *dof_off, const void *src, int dtype, int64_t n, double *dense,
+                               hipStream_t st);
+
+}  // namespace pufe

@@ -1,0 +1,338 @@
+// Host planner of the PUFE assembly: DOF map, enriched sets, block layout,
+// element tables and colouring.  Runs once per geometry, before any device
+// work (the paper builds one quadrature rule and one basis per geometry and
+// reuses them for every integral, section "Adaptive quadrature").
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <set>
+#include <tuple>
+
+namespace pufe {
+
+namespace {
+
+double det3(const double *m) {
+    return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+           m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+// Inverse of the matrix whose rows are a_1..a_3; column d of it is the dual
+// vector a*_d with a*_d . a_e = delta_de.
+void inverse3(const double *m, double *o) {
+    double d = det3(m);
+    o[0] = (m[4] * m[8] - m[5] * m[7]) / d;
+    o[1] = (m[2] * m[7] - m[1] * m[8]) / d;
+    o[2] = (m[1] * m[5] - m[2] * m[4]) / d;
+    o[3] = (m[5] * m[6] - m[3] * m[8]) / d;
+    o[4] = (m[0] * m[8] - m[2] * m[6]) / d;
+    o[5] = (m[2] * m[3] - m[0] * m[5]) / d;
+    o[6] = (m[3] * m[7] - m[4] * m[6]) / d;
+    o[7] = (m[1] * m[6] - m[0] * m[7]) / d;
+    o[8] = (m[0] * m[4] - m[1] * m[3]) / d;
+}
+
+inline int wrapi(int j, int n) { return ((j % n) + n) % n; }
+
+}  // namespace
+
+int build_plan(const Problem &pr, Plan &pl, std::string &err) {
+    const int n1 = pr.mesh[0], n2 = pr.mesh[1], n3 = pr.mesh[2];
+    if (n1 < 2 || n2 < 2 || n3 < 2) { err = "every mesh dimension must be >= 2"; return PUFE_ERR_INVALID_ARG; }
+    if (pr.p != 1 && pr.p != 2) { err = "fe_order must be 1 or 2"; return PUFE_ERR_INVALID_ARG; }
+    std::memcpy(pl.lat, pr.lat, sizeof pl.lat);
+    pl.vol = det3(pr.lat);
+    if (!(pl.vol > 0)) { err = "lattice must be right-handed with positive volume"; return PUFE_ERR_INVALID_ARG; }
+    inverse3(pr.lat, pl.inv);
+    const int n_atoms = (int)pr.species.size();
+    int max_species = -1;
+    for (int s : pr.species) max_species = std::max(max_species, s);
+    for (const auto &e : pr.enr) {
+        if (e.l < 0 || e.l > 3) { err = "enrichment l must be in 0..3"; return PUFE_ERR_INVALID_ARG; }
+        if (!(e.a > 0) || !(e.rc > 0) || !(e.re >= 0)) { err = "enrichment needs a > 0, rc > 0, re >= 0"; return PUFE_ERR_INVALID_ARG; }
+        if (e.radial_kind != 0) { err = "only the analytic radial kind 0 is supported"; return PUFE_ERR_UNSUPPORTED; }
+    }
+    const pufe_quad &q = pr.quad;
+    if (q.n_gauss < 1 || q.n_gauss > kMaxGauss) { err = "n_gauss must be in 1..12"; return PUFE_ERR_INVALID_ARG; }
+    if (q.max_level < 0 || q.max_level > kMaxLevel) { err = "max_level must be in 0..8"; return PUFE_ERR_INVALID_ARG; }
+    if (q.mode != PUFE_QUAD_GEOM && q.mode != PUFE_QUAD_ERROR) { err = "unknown quadrature mode"; return PUFE_ERR_INVALID_ARG; }
+    if (q.mode == PUFE_QUAD_ERROR && (q.n_ref <= q.n_gauss || q.n_ref > kMaxGauss)) {
+        err = "error mode needs n_gauss < n_ref <= 12"; return PUFE_ERR_INVALID_ARG;
+    }
+    bool ortho = pr.lat[1] == 0 && pr.lat[2] == 0 && pr.lat[3] == 0 && pr.lat[5] == 0 && pr.lat[6] == 0 && pr.lat[7] == 0;
+    if (q.mode == PUFE_QUAD_GEOM && q.max_level > 0 && !ortho) {
+        err = "geometric refinement needs an orthorhombic cell"; return PUFE_ERR_UNSUPPORTED;
+    }
+
+    pl.nel = (int64_t)n1 * n2 * n3;
+    pl.nv = pl.nel;
+    pl.nfs = pr.p == 1 ? 1 : 8;
+    pl.nfe = pr.p == 1 ? 8 : 27;
+    const int mesh[3] = {n1, n2, n3};
+
+    // ---- enriched sets: for every atom image, the vertices inside its
+    // support sphere (strictly closer than re) carry the descriptor
+    // (section "Partition of unity enrichment functions").
+    std::vector<std::set<std::pair<int, int>>> carry(pl.nv);  // (atom, desc)
+    for (int A = 0; A < n_atoms; ++A) {
+        const double *tau = &pr.pos[3 * A];
+        double tr[3];
+        for (int d = 0; d < 3; ++d) tr[d] = tau[0] * pl.inv[0 * 3 + d] + tau[1] * pl.inv[1 * 3 + d] + tau[2] * pl.inv[2 * 3 + d];
+        for (int k = 0; k < (int)pr.enr.size(); ++k) {
+            if (pr.enr[k].species != pr.species[A]) continue;
+            double re = pr.enr[k].re;
+            if (re <= 0) continue;
+            double rad[3];
+            for (int d = 0; d < 3; ++d)
+                rad[d] = re * std::sqrt(pl.inv[d] * pl.inv[d] + pl.inv[3 + d] * pl.inv[3 + d] + pl.inv[6 + d] * pl.inv[6 + d]);
+            // vertex grid indices j (unwrapped) with |x(j) - tau| < re
+            int lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = (int)std::floor((tr[d] - rad[d]) * mesh[d]) - 1;
+                hi[d] = (int)std::ceil((tr[d] + rad[d]) * mesh[d]) + 1;
+            }
+            for (int j3 = lo[2]; j3 <= hi[2]; ++j3)
+                for (int j2 = lo[1]; j2 <= hi[1]; ++j2)
+                    for (int j1 = lo[0]; j1 <= hi[0]; ++j1) {
+                        double u[3] = {(double)j1 / n1, (double)j2 / n2, (double)j3 / n3};
+                        double dx[3];
+                        for (int c = 0; c < 3; ++c)
+                            dx[c] = u[0] * pr.lat[c] + u[1] * pr.lat[3 + c] + u[2] * pr.lat[6 + c] - tau[c];
+                        double r2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+                        if (!(std::sqrt(r2) < re)) continue;
+                        int64_t v = ((int64_t)wrapi(j3, n3) * n2 + wrapi(j2, n2)) * n1 + wrapi(j1, n1);
+                        carry[v].insert({A, k});
+                    }
+        }
+    }
+    pl.vf_off.assign(pl.nv + 1, 0);
+    pl.vf.clear();
+    for (int64_t v = 0; v < pl.nv; ++v) {
+        pl.vf_off[v] = (int64_t)pl.vf.size() / 3;
+        for (auto &ak : carry[v]) {  // std::set order: atom, then descriptor
+            int l = pr.enr[ak.second].l;
+            for (int m = -l; m <= l; ++m) {
+                pl.vf.push_back(ak.first);
+                pl.vf.push_back(ak.second);
+                pl.vf.push_back(m);
+            }
+        }
+    }
+    pl.vf_off[pl.nv] = (int64_t)pl.vf.size() / 3;
+    pl.dof_off.assign(pl.nv + 1, 0);
+    for (int64_t v = 0; v < pl.nv; ++v)
+        pl.dof_off[v + 1] = pl.dof_off[v] + pl.nfs + (pl.vf_off[v + 1] - pl.vf_off[v]);
+
+    // ---- block layout: vertex v couples to every vertex of the elements
+    // around it, i.e. its (wrapped) 3x3x3 neighbourhood.
+    auto vid = [&](int j1, int j2, int j3) -> int64_t {
+        return ((int64_t)wrapi(j3, n3) * n2 + wrapi(j2, n2)) * n1 + wrapi(j1, n1);
+    };
+    pl.brow_ptr.assign(pl.nv + 1, 0);
+    pl.bcol.clear();
+    pl.brow.clear();
+    pl.bval_off.clear();
+    int64_t val = 0;
+    for (int64_t v = 0; v < pl.nv; ++v) {
+        pl.brow_ptr[v] = (int64_t)pl.bcol.size();
+        int j1 = (int)(v % n1), j2 = (int)((v / n1) % n2), j3 = (int)(v / ((int64_t)n1 * n2));
+        std::vector<int64_t> nb;
+        for (int d3 = -1; d3 <= 1; ++d3)
+            for (int d2 = -1; d2 <= 1; ++d2)
+                for (int d1 = -1; d1 <= 1; ++d1) nb.push_back(vid(j1 + d1, j2 + d2, j3 + d3));
+        std::sort(nb.begin(), nb.end());
+        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+        int64_t bv = pl.dof_off[v + 1] - pl.dof_off[v];
+        for (int64_t w : nb) {
+            pl.bcol.push_back((int32_t)w);
+            pl.brow.push_back((int32_t)v);
+            pl.bval_off.push_back(val);
+            val += bv * (pl.dof_off[w + 1] - pl.dof_off[w]);
+        }
+    }
+    pl.brow_ptr[pl.nv] = (int64_t)pl.bcol.size();
+    pl.bval_off.push_back(val);
+    pl.nnz = val;
+    auto block_of = [&](int64_t v, int64_t w) -> int64_t {
+        auto b = pl.bcol.begin() + pl.brow_ptr[v], e = pl.bcol.begin() + pl.brow_ptr[v + 1];
+        auto it = std::lower_bound(b, e, (int32_t)w);
+        return pl.bval_off[it - pl.bcol.begin()];
+    };
+
+    // ---- elements
+    const double lat[9] = {pr.lat[0], pr.lat[1], pr.lat[2], pr.lat[3], pr.lat[4], pr.lat[5], pr.lat[6], pr.lat[7], pr.lat[8]};
+    double E[9];
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) E[3 * d + c] = lat[3 * d + c] / mesh[d];
+    // bounding radius of one element: half its longest diagonal
+    double Re = 0;
+    for (int s2 = -1; s2 <= 1; s2 += 2)
+        for (int s3 = -1; s3 <= 1; s3 += 2) {
+            double dd[3];
+            for (int c = 0; c < 3; ++c) dd[c] = E[c] + s2 * E[3 + c] + s3 * E[6 + c];
+            Re = std::max(Re, 0.5 * std::sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
+        }
+    pl.elems.assign(pl.nel, ElemDev{});
+    pl.groups.clear();
+    pl.img.clear();
+    pl.edof.clear();
+    pl.max_nloc = pl.max_nfun = pl.max_ngrp = 0;
+    std::vector<std::vector<int32_t>> by_color(27);
+    for (int64_t e = 0; e < pl.nel; ++e) {
+        ElemDev &el = pl.elems[e];
+        int i[3] = {(int)(e % n1), (int)((e / n1) % n2), (int)(e / ((int64_t)n1 * n2))};
+        for (int d = 0; d < 3; ++d) el.ijk[d] = i[d];
+        int64_t cv[8];
+        el.shifts = 0;
+        for (int c = 0; c < 8; ++c) {
+            int j[3];
+            for (int d = 0; d < 3; ++d) {
+                int b = (c >> d) & 1;
+                j[d] = i[d] + b;
+                if (j[d] == mesh[d]) { j[d] = 0; el.shifts |= 1 << (3 * c + d); }
+            }
+            cv[c] = ((int64_t)j[2] * n2 + j[1]) * n1 + j[0];
+        }
+        for (int ca = 0; ca < 8; ++ca) {
+            el.bw[ca] = (int32_t)(pl.dof_off[cv[ca] + 1] - pl.dof_off[cv[ca]]);
+            for (int cb = 0; cb < 8; ++cb) el.blk[ca * 8 + cb] = block_of(cv[ca], cv[cb]);
+        }
+        // (atom, descriptor) groups present on the corners
+        std::map<std::pair<int, int>, int> gidx;
+        for (int c = 0; c < 8; ++c)
+            for (int64_t t = pl.vf_off[cv[c]]; t < pl.vf_off[cv[c] + 1]; ++t) gidx[{pl.vf[3 * t], pl.vf[3 * t + 1]}] = 0;
+        el.grp_off = (int32_t)pl.groups.size();
+        el.ngrp = (int32_t)gidx.size();
+        int nfun = 0;
+        double centre[3];
+        for (int c = 0; c < 3; ++c) centre[c] = (i[0] + 0.5) * E[c] + (i[1] + 0.5) * E[3 + c] + (i[2] + 0.5) * E[6 + c];
+        for (auto &kv : gidx) {
+            int A = kv.first.first, k = kv.first.second;
+            const pufe_enrichment &en = pr.enr[k];
+            kv.second = nfun;
+            GroupDev g{};
+            g.atom = A;
+            g.desc = k;
+            g.l = en.l;
+            g.fbase = nfun;
+            g.a = en.a;
+            g.rc = en.rc;
+            g.img_off = (int32_t)(pl.img.size() / 3);
+            // images whose cutoff sphere can reach the element
+            const double *tau = &pr.pos[3 * A];
+            double ur[3], uc[3];
+            for (int d = 0; d < 3; ++d) {
+                ur[d] = tau[0] * pl.inv[d] + tau[1] * pl.inv[3 + d] + tau[2] * pl.inv[6 + d];
+                uc[d] = centre[0] * pl.inv[d] + centre[1] * pl.inv[3 + d] + centre[2] * pl.inv[6 + d];
+            }
+            double reach = en.rc + Re;
+            int lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                double rad = reach * std::sqrt(pl.inv[d] * pl.inv[d] + pl.inv[3 + d] * pl.inv[3 + d] + pl.inv[6 + d] * pl.inv[6 + d]);
+                lo[d] = (int)std::floor(uc[d] - ur[d] - rad) - 1;
+                hi[d] = (int)std::ceil(uc[d] - ur[d] + rad) + 1;
+            }
+            int nimg = 0;
+            for (int m3 = lo[2]; m3 <= hi[2]; ++m3)
+                for (int m2 = lo[1]; m2 <= hi[1]; ++m2)
+                    for (int m1 = lo[0]; m1 <= hi[0]; ++m1) {
+                        double C[3];
+                        for (int c = 0; c < 3; ++c) C[c] = tau[c] + m1 * lat[c] + m2 * lat[3 + c] + m3 * lat[6 + c];
+                        double dx = C[0] - centre[0], dy = C[1] - centre[1], dz = C[2] - centre[2];
+                        if (std::sqrt(dx * dx + dy * dy + dz * dz) >= reach) continue;
+                        pl.img.push_back(C[0]);
+                        pl.img.push_back(C[1]);
+                        pl.img.push_back(C[2]);
+                        ++nimg;
+                    }
+            g.nimg = nimg;
+            pl.groups.push_back(g);
+            nfun += 2 * en.l + 1;
+        }
+        el.nfun = nfun;
+        // enriched local functions: corner by corner, vertex order
+        el.edof_off = (int32_t)pl.edof.size();
+        int nenr = 0;
+        for (int c = 0; c < 8; ++c)
+            for (int64_t t = pl.vf_off[cv[c]]; t < pl.vf_off[cv[c] + 1]; ++t) {
+                int f = gidx[{pl.vf[3 * t], pl.vf[3 * t + 1]}] + (pl.vf[3 * t + 2] + pr.enr[pl.vf[3 * t + 1]].l);
+                int slot = pl.nfs + (int)(t - pl.vf_off[cv[c]]);
+                pl.edof.push_back(edof_pack(c, f, slot));
+                ++nenr;
+            }
+        el.nfe = pl.nfe;
+        el.nloc = pl.nfe + nenr;
+        if (el.nloc > kMaxNloc || nfun > kMaxFun || el.ngrp > kMaxGroups) {
+            err = "element " + std::to_string(e) + " holds more functions than the kernels support (nloc " +
+                  std::to_string(el.nloc) + ", functions " + std::to_string(nfun) + ")";
+            return PUFE_ERR_UNSUPPORTED;
+        }
+        pl.max_nloc = std::max(pl.max_nloc, el.nloc);
+        pl.max_nfun = std::max(pl.max_nfun, nfun);
+        pl.max_ngrp = std::max(pl.max_ngrp, el.ngrp);
+        // colour: elements of one colour share no vertex, so their scatters
+        // touch disjoint blocks (odd n_d puts the last layer in colour 2)
+        int col[3];
+        for (int d = 0; d < 3; ++d) col[d] = (mesh[d] % 2 == 1 && i[d] == mesh[d] - 1) ? 2 : (i[d] % 2);
+        el.color = col[0] + 3 * col[1] + 9 * col[2];
+        by_color[el.color].push_back((int32_t)e);
+    }
+    pl.color_elems.clear();
+    pl.color_off.assign(1, 0);
+    for (int c = 0; c < 27; ++c) {
+        if (by_color[c].empty()) continue;
+        pl.color_elems.insert(pl.color_elems.end(), by_color[c].begin(), by_color[c].end());
+        pl.color_off.push_back((int32_t)pl.color_elems.size());
+    }
+
+    // ---- kernel constants
+    KParams &kp = pl.kp;
+    std::memset(&kp, 0, sizeof kp);
+    std::memcpy(kp.E, E, sizeof E);
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) kp.Jt[3 * c + d] = 2.0 * mesh[d] * pl.inv[3 * c + d];
+    kp.jac = pl.vol / (8.0 * n1 * n2 * n3);
+    kp.n = q.n_gauss;
+    kp.n3 = q.n_gauss * q.n_gauss * q.n_gauss;
+    kp.p = pr.p;
+    kp.nfe = pl.nfe;
+    kp.nfs = pl.nfs;
+    for (int d = 0; d < 3; ++d) kp.mesh[d] = mesh[d];
+    // Gauss-Legendre nodes and weights (Golub-Welsch: eigenvalues of the
+    // symmetric Jacobi matrix would need LAPACK; a Newton iteration on the
+    // three-term recurrence is enough here)
+    int n = q.n_gauss;
+    for (int r = 0; r < n; ++r) {
+        double x = -std::cos(M_PI * (r + 0.75) / (n + 0.5));
+        double dp = 1;
+        for (int it = 0; it < 64; ++it) {
+            double p0 = 1, p1 = x;
+            for (int k = 1; k < n; ++k) {
+                double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p0 = 1; p1 = x; }
+            dp = n * (p0 - x * p1) / (1 - x * x);
+            double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        double p0 = 1, p1 = x;
+        for (int k = 1; k < n; ++k) {
+            double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) { p0 = 1; p1 = x; }
+        dp = n * (p0 - x * p1) / (1 - x * x);
+        kp.gx[r] = x;
+        kp.gw[r] = 2.0 / ((1 - x * x) * dp * dp);
+    }
+    return PUFE_OK;
+}
+
+}  // namespace pufe

@@ -1,0 +1,50 @@
+// Host planner: from the problem statement to the tables the kernels read.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pufe.h"
+#include "tables.hpp"
+
+namespace pufe {
+
+struct Problem {
+    double lat[9];
+    int mesh[3];
+    int p;
+    std::vector<double> pos;  // n_atoms x 3
+    std::vector<int> species;
+    std::vector<pufe_enrichment> enr;
+    pufe_quad quad;
+};
+
+struct Plan {
+    // cell
+    double lat[9], inv[9], vol;
+    int64_t nel, nv;
+    int nfs, nfe;
+    // enriched functions of each vertex: (atom, desc, m)
+    std::vector<int64_t> vf_off;
+    std::vector<int32_t> vf;  // 3 per function
+    std::vector<int64_t> dof_off;
+    // block-sparse layout keyed by vertex
+    std::vector<int64_t> brow_ptr, bval_off;
+    std::vector<int32_t> bcol, brow;
+    int64_t nnz = 0;
+    // elements
+    std::vector<ElemDev> elems;
+    std::vector<GroupDev> groups;
+    std::vector<double> img;        // image centres, 3 per image
+    std::vector<int32_t> edof;      // packed enriched local functions
+    std::vector<int32_t> color_elems;
+    std::vector<int32_t> color_off; // n_colors + 1
+    int max_nloc = 0, max_nfun = 0, max_ngrp = 0;
+    KParams kp;
+};
+
+// Validate and plan; returns PUFE_OK or an error code with a message.
+int build_plan(const Problem &pr, Plan &pl, std::string &err);
+
+}  // namespace pufe

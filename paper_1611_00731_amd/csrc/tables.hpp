@@ -1,0 +1,65 @@
+// Device-side table layouts shared by the host planner and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pufe {
+
+constexpr int kMaxFun = 64;       // enrichment functions on one element
+constexpr int kMaxGroups = 32;    // (atom, descriptor) groups on one element
+constexpr int kMaxNloc = 512;     // functions on one element
+constexpr int kTile = 16;         // MFMA tile edge
+constexpr int kBlockTiles = 4;    // tiles per row/column block of a work item
+constexpr int kMaxGauss = 12;
+constexpr int kMaxLevel = 8;
+
+// One element: geometry index, function counts, table offsets and the BSR
+// addresses of its 8x8 corner-vertex blocks.
+struct ElemDev {
+    int32_t nloc, nfe, nfun, ngrp;
+    int32_t grp_off, edof_off;
+    int32_t ijk[3];
+    int32_t color;
+    int32_t shifts;      // lattice shift bits of corner c at bits 3c..3c+2 (bit d = direction d)
+    int32_t nchunk;      // K-chunks of the contraction
+    int64_t leaf_off, leaf_end;
+    int64_t part_base;   // first partial tile-pair slot
+    int64_t blk[64];     // value offset of BSR block (vertex of corner ca, vertex of corner cb) at ca*8+cb
+    int32_t bw[8];       // width of the block column of corner c (b_w of its vertex)
+};
+
+// (atom, descriptor) group: 2l+1 functions with one radial part and the list
+// of lattice images whose cutoff sphere reaches the element.
+struct GroupDev {
+    int32_t atom, desc, l, fbase, img_off, nimg;
+    double a, rc;
+};
+
+// Enriched local function: corner | element-function << 3 | vertex slot << 11
+static inline __host__ __device__ int32_t edof_pack(int corner, int f, int slot) {
+    return corner | (f << 3) | (slot << 11);
+}
+
+// A contraction work item: one element, one row block and one column block of
+// 16x16 tiles, one range of octree leaves (a K-chunk).
+struct ItemDev {
+    int32_t elem, I0, nI, J0, nJ, chunk;
+    int64_t leaf_b, leaf_e;
+};
+
+// Per-launch constants of the mesh and the rule.
+struct KParams {
+    double E[9];      // row d: a_d / n_d (element edge vector)
+    double Jt[9];     // grad_x[c] = sum_d Jt[3c+d] dphi/dxi_d
+    double jac;       // det of the reference-to-element map
+    double gx[kMaxGauss], gw[kMaxGauss];
+    int32_t n, n3, p, nfe, nfs;
+    int32_t mesh[3];
+};
+
+// Leaf code: level in bits 27..30, cell coordinates in 9-bit fields.
+static inline __host__ __device__ uint32_t leaf_pack(int lev, int c1, int c2, int c3) {
+    return (uint32_t)c1 | ((uint32_t)c2 << 9) | ((uint32_t)c3 << 18) | ((uint32_t)lev << 27);
+}
+
+}  // namespace pufe

@@ -1,0 +1,144 @@
+"""CPU tests of the C ABI: the library loads, exports what the header
+declares, validates its inputs, and its host-side DOF map, enriched sets and
+block layout agree with the oracle's.  No compute call is made."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+P = pytest.importorskip("paper_1611_00731_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "pufe.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(pufe_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(P.lib, n), n
+    assert set(names) == set(P.EXPORTS)
+
+
+def test_error_strings():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert P.lib.pufe_error_string(code)
+    assert P.lib.pufe_error_string(-99) == b"unknown error"
+
+
+def _expect(code, fn):
+    with pytest.raises(P.PufeError) as ei:
+        fn()
+    assert ei.value.code == code
+
+
+def test_input_validation():
+    base = W.small("one", mesh=(2, 2, 2), fe_order=1)
+    ctx = P.pufe_create(0)
+    try:
+        _expect(-5, lambda: P.pufe_setup(ctx, stream=type("S", (), {"cuda_stream": 0})()))
+        _expect(-5, lambda: P.pufe_query(ctx))
+        _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [1, 2, 2], 1, base["atoms"],
+                                               base["species"], base["enrichments"], base["quad"]))
+        _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 3, base["atoms"],
+                                               base["species"], base["enrichments"], base["quad"]))
+        bad = [dict(base["enrichments"][0], l=4)]
+        _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 1, base["atoms"],
+                                               base["species"], bad, base["quad"]))
+        bad = [dict(base["enrichments"][0], a=-1.0)]
+        _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 1, base["atoms"],
+                                               base["species"], bad, base["quad"]))
+        lefty = np.diag([4.5, 4.5, -4.5])
+        _expect(-1, lambda: P.pufe_set_problem(ctx, lefty, [2, 2, 2], 1, base["atoms"],
+                                               base["species"], base["enrichments"], base["quad"]))
+        skew = [[4.5, 0.2, 0.0], [0.0, 4.5, 0.0], [0.0, 0.0, 4.5]]
+        q = dict(base["quad"], levels=1)
+        _expect(-2, lambda: P.pufe_set_problem(ctx, skew, [2, 2, 2], 1, base["atoms"],
+                                               base["species"], base["enrichments"], q))
+        q = dict(base["quad"], n=13)
+        _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 1, base["atoms"],
+                                               base["species"], base["enrichments"], q))
+        # a valid problem after rejected ones; assembly before setup is a state error
+        P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 1, base["atoms"], base["species"],
+                           base["enrichments"], base["quad"])
+        assert P.pufe_query(ctx)["n_elem"] == 8
+        import ctypes as C
+        k = (C.c_double * 3)(0, 0, 0)
+        assert P.lib.pufe_assemble(ctx, None, k, 1, 0, 0, None, None, None) == -5
+    finally:
+        P.pufe_destroy(ctx)
+
+
+PROBLEMS = {
+    "cfg1": W.cfg1,
+    "cfg2": W.cfg2,
+    "cfg4": W.cfg4,
+    "cfg5": W.cfg5,
+    "lih-odd": lambda: W.small("lih", mesh=(3, 5, 3), fe_order=2, a=5.0),
+    "one-p1": lambda: W.small("one", mesh=(2, 3, 4), fe_order=1, a=4.0),
+    "ceal": lambda: W.small("ceal", mesh=(3, 3, 3), fe_order=2, a=5.0, rc=3.0, re=2.1),
+    "skew": lambda: W.small("lih", mesh=(3, 2, 3), fe_order=2, levels=0,
+                            lattice=[[5.0, 0.3, -0.2], [0.1, 4.8, 0.25], [0.2, -0.3, 5.3]]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_dof_map_and_enriched_sets_match_oracle(name):
+    prob = PROBLEMS[name]()
+    o = oracle.Oracle(prob)
+    p = P.Problem(prob)
+    try:
+        lay = p.layout()
+        assert np.array_equal(lay["dof_offset"], o.dof_offset())
+        assert p.sizes["n_dof"] == o.n_dof
+        assert p.sizes["n_fe_slots"] == o.n_fe_slots
+    finally:
+        p.close()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "lih-odd", "one-p1", "ceal", "skew"])
+def test_block_pattern_matches_element_coupling(name):
+    prob = PROBLEMS[name]()
+    o = oracle.Oracle(prob)
+    p = P.Problem(prob)
+    try:
+        lay = p.layout()
+        off = lay["dof_offset"]
+        want = set()
+        for e in range(o.n_elem):
+            g, _ = o.element_dofs(e)
+            v = np.searchsorted(off, g, side="right") - 1
+            for a in set(v.tolist()):
+                for b in set(v.tolist()):
+                    want.add((a, b))
+        got = set()
+        rp, bc = lay["brow_ptr"], lay["bcol"]
+        for v in range(len(rp) - 1):
+            for k in range(rp[v], rp[v + 1]):
+                got.add((v, int(bc[k])))
+        assert got == want
+        bo = lay["bval_offset"]
+        sizes = np.diff(off)
+        rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+        assert np.array_equal(np.diff(bo), sizes[rows] * sizes[bc])
+        assert bo[-1] == p.sizes["nnz"]
+    finally:
+        p.close()
+
+
+def test_workload_sizes():
+    """Sizes of the measured workloads (DOFs, BSR entries) from the host plan."""
+    p = P.Problem(W.cfg2())
+    try:
+        s = p.sizes
+        assert (s["n_elem"], s["n_dof"], s["n_colors"]) == (512, 4888, 8)
+        assert s["nnz"] == 1278838
+    finally:
+        p.close()
