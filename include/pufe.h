@@ -193,6 +193,13 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
                            const void *d_Q, int precision, double *d_dLdV, double *d_dLdR,
                            void *stream);
 
+/* Move the enrichment centres to pos[n_atoms*3] (Cartesian) keeping the
+ * quadrature rule, the enriched sets and the layout of the original geometry
+ * (the frozen-basis derivative that pufe_assemble_backward computes).  Each
+ * centre may move at most 0.25 bohr from the position given to
+ * pufe_set_problem (PUFE_ERR_INVALID_ARG otherwise).  Synchronous. */
+int pufe_set_positions(pufe_ctx *ctx, const double *pos);
+
 /* Expand one BSR value array (out_dtype C128 or F64_GAMMA) into a dense
  * row-major n_dof x n_dof complex double matrix d_dense (device). */
 int pufe_bsr_to_dense(pufe_ctx *ctx, const void *d_bsr, int dtype, double *d_dense, void *stream);

@@ -69,6 +69,8 @@ def lib():
                                         _f64p, _f64p]
         L.or_backward_dense.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, C.c_void_p,
                                         _f64p, _f64p]
+        L.or_backward_element.argtypes = [C.c_void_p, C.c_int64, _f64p, _f64p, _f64p, C.c_void_p,
+                                          _f64p, _f64p]
         L.or_set_positions.argtypes = [C.c_void_p, _f64p]
         L.or_basis_at.argtypes = [C.c_void_p, C.c_int64, _f64p, _f64p, _f64p]
         L.or_enrichment.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _f64p,
@@ -209,6 +211,20 @@ class Oracle:
         lib().or_backward_dense(self.h, np.ascontiguousarray(V, np.float64),
                                 np.asarray(kappa, np.float64), Pr,
                                 None if Qr is None else Qr.ctypes.data, dV, dR)
+        return dV, dR.reshape(-1, 3)
+
+    def backward_element(self, e, V_elem, kappa, Ploc, Qloc=None):
+        """Adjoint contribution of element e from the entries P[g_a][g_b] of its
+        local functions (n x n complex)."""
+        n = Ploc.shape[0]
+        Pr = np.ascontiguousarray(np.stack([Ploc.real, Ploc.imag], -1))
+        Qr = None if Qloc is None else np.ascontiguousarray(np.stack([Qloc.real, Qloc.imag], -1))
+        nq = len(V_elem)
+        dV = np.zeros(nq)
+        dR = np.zeros(3 * self.n_atoms)
+        lib().or_backward_element(self.h, e, np.ascontiguousarray(V_elem, np.float64),
+                                  np.asarray(kappa, np.float64), Pr,
+                                  None if Qr is None else Qr.ctypes.data, dV, dR)
         return dV, dR.reshape(-1, 3)
 
     def set_positions(self, pos):

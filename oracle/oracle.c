@@ -974,6 +974,82 @@ void or_assemble_block(const or_state *s, const double *V, const double *kappa, 
  * its enrichment: d(M_c Psi)/dtau = -M_c grad Psi and
  * d(grad(M_c Psi))/dtau_k = -(grad M_c d_k Psi + M_c grad d_k Psi).
  * The quadrature rule, the enriched sets and V are held fixed. */
+/* The adjoint contribution of one element: Ploc and Qloc hold the entries
+ * P[g_a][g_b] (complex, n x n) of the element's local functions; Qloc may be
+ * NULL.  Adds w_q phi^T Pt phi to dLdV_elem[q] (element-local points) and the
+ * element's share of dL/dtau to dLdR. */
+static void backward_element(const or_state *s, int64_t e, const loc_fn *L, int n, const double *V,
+                             const double *kappa, const double *Ploc, const double *Qloc,
+                             double *dLdV, double *dLdR) {
+    double *Pt = malloc(sizeof(double) * n * n), *Qt = malloc(sizeof(double) * n * n);
+    double *val = malloc(sizeof(double) * n), *grad = malloc(sizeof(double) * 3 * n);
+    double *dval = malloc(sizeof(double) * 3 * n);   /* d phi_a / d tau_k */
+    double *dgrad = malloc(sizeof(double) * 9 * n);  /* d (d_j phi_a) / d tau_k at [9a + 3k + j] */
+    int64_t nq3 = (int64_t)s->q_n * s->q_n * s->q_n;
+    for (int a = 0; a < n; ++a) {
+        double par, pai;
+        phase(kappa, L[a].shift, &par, &pai);
+        for (int b = 0; b < n; ++b) {
+            double pbr, pbi;
+            phase(kappa, L[b].shift, &pbr, &pbi);
+            /* Re(p_a X conj(p_b)) = Re(X) Re(p_a conj p_b) - Im(X) Im(p_a conj p_b) */
+            double zr = par * pbr + pai * pbi, zi = pai * pbr - par * pbi;
+            int64_t idx = 2 * ((int64_t)a * n + b);
+            Pt[a * n + b] = Ploc[idx] * zr - Ploc[idx + 1] * zi;
+            Qt[a * n + b] = Qloc ? (Qloc[idx] * zr - Qloc[idx + 1] * zi) : 0.0;
+        }
+    }
+    int64_t q = 0;
+    for (int64_t lf = s->leaf_off[e]; lf < s->leaf_off[e + 1]; ++lf)
+        for (int64_t j = 0; j < nq3; ++j, ++q) {
+            double xi[3], w, x[3];
+            leaf_point(s, s->leaf_level[lf], s->leaf_ijk + 3 * lf, j, xi, &w);
+            basis_eval(s, e, L, n, xi, val, grad);
+            ref2phys(s, e, xi, x);
+            for (int a = 0; a < n; ++a) {
+                memset(dval + 3 * a, 0, sizeof(double) * 3);
+                memset(dgrad + 9 * a, 0, sizeof(double) * 9);
+                if (L[a].kind != 1) continue;
+                double M = 1.0, dxi[3] = {1.0, 1.0, 1.0}, gM[3], psi, gpsi[3], hpsi[9];
+                for (int d = 0; d < 3; ++d) {
+                    double lv, ld;
+                    or_lagrange(1, (L[a].corner >> d) & 1, xi[d], &lv, &ld);
+                    for (int k = 0; k < 3; ++k) dxi[k] *= (k == d) ? ld : lv;
+                    M *= lv;
+                }
+                ref_grad(s, dxi, gM);
+                or_enrichment(s, L[a].atom, L[a].desc, L[a].m, x, &psi, gpsi, hpsi);
+                for (int k = 0; k < 3; ++k) {
+                    dval[3 * a + k] = -M * gpsi[k];
+                    for (int jj = 0; jj < 3; ++jj)
+                        dgrad[9 * a + 3 * k + jj] = -(gM[jj] * gpsi[k] + M * hpsi[jj * 3 + k]);
+                }
+            }
+            double dv = 0.0;
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) dv += Pt[a * n + b] * val[a] * val[b];
+            dLdV[q] += w * dv;
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) {
+                    for (int side = 0; side < 2; ++side) {
+                        /* side 0 differentiates phi_a, side 1 differentiates phi_b */
+                        int d = side == 0 ? a : b, o = side == 0 ? b : a;
+                        if (L[d].kind != 1) continue;
+                        int A = L[d].atom;
+                        for (int k = 0; k < 3; ++k) {
+                            double gg = 0.0;
+                            for (int jj = 0; jj < 3; ++jj)
+                                gg += dgrad[9 * d + 3 * k + jj] * grad[3 * o + jj];
+                            double pv = dval[3 * d + k] * val[o];
+                            dLdR[3 * A + k] += w * (Pt[a * n + b] * (0.5 * gg + V[q] * pv)
+                                                    + Qt[a * n + b] * pv);
+                        }
+                    }
+                }
+        }
+    free(Pt); free(Qt); free(val); free(grad); free(dval); free(dgrad);
+}
+
 void or_backward_dense(const or_state *s, const double *V, const double *kappa, const double *P,
                        const double *Q, double *dLdV, double *dLdR) {
     int64_t N = s->ndof;
@@ -981,76 +1057,29 @@ void or_backward_dense(const or_state *s, const double *V, const double *kappa, 
     memset(dLdR, 0, sizeof(double) * 3 * s->n_atoms);
     int mx = max_locals(s);
     loc_fn *L = malloc(sizeof(loc_fn) * mx);
-    double *Pt = malloc(sizeof(double) * mx * mx), *Qt = malloc(sizeof(double) * mx * mx);
-    double *val = malloc(sizeof(double) * mx), *grad = malloc(sizeof(double) * 3 * mx);
-    double *dval = malloc(sizeof(double) * 3 * mx);   /* d phi_a / d tau_k */
-    double *dgrad = malloc(sizeof(double) * 9 * mx);  /* d (d_j phi_a) / d tau_k at [9a + 3k + j] */
-    int64_t nq3 = (int64_t)s->q_n * s->q_n * s->q_n;
+    double *Pl = malloc(sizeof(double) * 2 * mx * mx), *Ql = malloc(sizeof(double) * 2 * mx * mx);
     for (int64_t e = 0; e < s->nel; ++e) {
         int n = element_locals(s, e, L);
-        for (int a = 0; a < n; ++a) {
-            double par, pai;
-            phase(kappa, L[a].shift, &par, &pai);
-            for (int b = 0; b < n; ++b) {
-                double pbr, pbi;
-                phase(kappa, L[b].shift, &pbr, &pbi);
-                /* Re(p_a X conj(p_b)) = Re(X) Re(p_a conj p_b) - Im(X) Im(p_a conj p_b) */
-                double zr = par * pbr + pai * pbi, zi = pai * pbr - par * pbi;
-                int64_t idx = 2 * (L[a].g * N + L[b].g);
-                Pt[a * n + b] = P[idx] * zr - P[idx + 1] * zi;
-                Qt[a * n + b] = Q ? (Q[idx] * zr - Q[idx + 1] * zi) : 0.0;
-            }
-        }
-        int64_t q = s->qp_off[e];
-        for (int64_t lf = s->leaf_off[e]; lf < s->leaf_off[e + 1]; ++lf)
-            for (int64_t j = 0; j < nq3; ++j, ++q) {
-                double xi[3], w, x[3];
-                leaf_point(s, s->leaf_level[lf], s->leaf_ijk + 3 * lf, j, xi, &w);
-                basis_eval(s, e, L, n, xi, val, grad);
-                ref2phys(s, e, xi, x);
-                for (int a = 0; a < n; ++a) {
-                    memset(dval + 3 * a, 0, sizeof(double) * 3);
-                    memset(dgrad + 9 * a, 0, sizeof(double) * 9);
-                    if (L[a].kind != 1) continue;
-                    double M = 1.0, dxi[3] = {1.0, 1.0, 1.0}, gM[3], psi, gpsi[3], hpsi[9];
-                    for (int d = 0; d < 3; ++d) {
-                        double lv, ld;
-                        or_lagrange(1, (L[a].corner >> d) & 1, xi[d], &lv, &ld);
-                        for (int k = 0; k < 3; ++k) dxi[k] *= (k == d) ? ld : lv;
-                        M *= lv;
-                    }
-                    ref_grad(s, dxi, gM);
-                    or_enrichment(s, L[a].atom, L[a].desc, L[a].m, x, &psi, gpsi, hpsi);
-                    for (int k = 0; k < 3; ++k) {
-                        dval[3 * a + k] = -M * gpsi[k];
-                        for (int jj = 0; jj < 3; ++jj)
-                            dgrad[9 * a + 3 * k + jj] = -(gM[jj] * gpsi[k] + M * hpsi[jj * 3 + k]);
-                    }
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b)
+                for (int t = 0; t < 2; ++t) {
+                    Pl[2 * (a * n + b) + t] = P[2 * (L[a].g * N + L[b].g) + t];
+                    Ql[2 * (a * n + b) + t] = Q ? Q[2 * (L[a].g * N + L[b].g) + t] : 0.0;
                 }
-                double dv = 0.0;
-                for (int a = 0; a < n; ++a)
-                    for (int b = 0; b < n; ++b) dv += Pt[a * n + b] * val[a] * val[b];
-                dLdV[q] = w * dv;
-                for (int a = 0; a < n; ++a)
-                    for (int b = 0; b < n; ++b) {
-                        for (int side = 0; side < 2; ++side) {
-                            /* side 0 differentiates phi_a, side 1 differentiates phi_b */
-                            int d = side == 0 ? a : b, o = side == 0 ? b : a;
-                            if (L[d].kind != 1) continue;
-                            int A = L[d].atom;
-                            for (int k = 0; k < 3; ++k) {
-                                double gg = 0.0;
-                                for (int jj = 0; jj < 3; ++jj)
-                                    gg += dgrad[9 * d + 3 * k + jj] * grad[3 * o + jj];
-                                double pv = dval[3 * d + k] * val[o];
-                                dLdR[3 * A + k] += w * (Pt[a * n + b] * (0.5 * gg + V[q] * pv)
-                                                        + Qt[a * n + b] * pv);
-                            }
-                        }
-                    }
-            }
+        backward_element(s, e, L, n, V + s->qp_off[e], kappa, Pl, Q ? Ql : NULL,
+                         dLdV + s->qp_off[e], dLdR);
     }
-    free(L); free(Pt); free(Qt); free(val); free(grad); free(dval); free(dgrad);
+    free(L); free(Pl); free(Ql);
+}
+
+void or_backward_element(const or_state *s, int64_t e, const double *V_elem, const double *kappa,
+                         const double *Ploc, const double *Qloc, double *dLdV_elem, double *dLdR) {
+    loc_fn *L = malloc(sizeof(loc_fn) * max_locals(s));
+    int n = element_locals(s, e, L);
+    memset(dLdV_elem, 0, sizeof(double) * (s->qp_off[e + 1] - s->qp_off[e]));
+    memset(dLdR, 0, sizeof(double) * 3 * s->n_atoms);
+    backward_element(s, e, L, n, V_elem, kappa, Ploc, Qloc, dLdV_elem, dLdR);
+    free(L);
 }
 
 /* ----------------------------------------------------------- sparsity */

@@ -63,6 +63,11 @@ void or_assemble_block(const or_state *s, const double *V, const double *kappa,
 /* adjoint of the assembly; P, Q dense N x N complex (Q may be NULL) */
 void or_backward_dense(const or_state *s, const double *V, const double *kappa,
                        const double *P, const double *Q, double *dLdV, double *dLdR);
+/* adjoint contribution of element e: Ploc/Qloc are the entries P[g_a][g_b]
+ * (n x n complex) of its local functions, Qloc may be NULL; dLdV_elem gets the
+ * element's points, dLdR (n_atoms x 3) its share of the force */
+void or_backward_element(const or_state *s, int64_t e, const double *V_elem, const double *kappa,
+                         const double *Ploc, const double *Qloc, double *dLdV_elem, double *dLdR);
 /* move the enrichment centres only (rule and enriched sets stay frozen) */
 void or_set_positions(or_state *s, const double *pos);
 /* basis of element e at reference point xi: values and Cartesian gradients */

@@ -27,7 +27,7 @@ EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_
            "pufe_set_problem", "pufe_setup", "pufe_query", "pufe_get_layout",
            "pufe_get_quadrature", "pufe_get_leaves", "pufe_assemble", "pufe_element_matrices",
            "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
-           "pufe_kernel_times"]
+           "pufe_kernel_times", "pufe_set_positions"]
 
 
 class PufeError(RuntimeError):
@@ -77,6 +77,7 @@ def _load():
         "pufe_bsr_to_dense": ([vp, vp, C.c_int, vp, vp], C.c_int),
         "pufe_enable_timing": ([vp, C.c_int], C.c_int),
         "pufe_kernel_times": ([vp, dp, i64p, C.c_int], C.c_int),
+        "pufe_set_positions": ([vp, dp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -203,6 +204,11 @@ def pufe_bsr_to_dense(ctx, bsr, dtype, dense, stream=None):
                                       _ptr(dense), _stream(stream)))
 
 
+def pufe_set_positions(ctx, pos):
+    p = np.ascontiguousarray(np.asarray(pos, np.float64).reshape(-1))
+    _check(ctx, lib.pufe_set_positions(ctx, p.ctypes.data_as(C.POINTER(C.c_double))))
+
+
 def pufe_enable_timing(ctx, on=True):
     _check(ctx, lib.pufe_enable_timing(ctx, 1 if on else 0))
 
@@ -284,12 +290,70 @@ class Problem:
         n = pufe_element_matrices(self.ctx, elem, V, precision, He, Se)
         return He.view(-1)[:n * n].view(n, n), Se.view(-1)[:n * n].view(n, n)
 
+    def set_positions(self, pos):
+        pufe_set_positions(self.ctx, pos)
+
+    def backward(self, V, kpt, P=None, Q=None, want_dV=True, want_dR=True, precision="fp64"):
+        """dL/dV (n_qp) and dL/dR (n_atoms x 3) for L = Re<P, H> + Re<Q, S>;
+        P and Q are BSR value arrays (complex128 or (nnz, 2) float64)."""
+        import torch
+        dV = torch.empty(self.sizes["n_qp"], dtype=torch.float64, device=V.device) if want_dV else None
+        dR = torch.empty((self.sizes["n_atoms"], 3), dtype=torch.float64, device=V.device) if want_dR else None
+        pufe_assemble_backward(self.ctx, V, kpt, None if P is None else P.contiguous(),
+                               None if Q is None else Q.contiguous(), precision, dV, dR)
+        return dV, dR
+
     def to_dense(self, bsr, dtype="c128"):
         import torch
         n = self.sizes["n_dof"]
         D = torch.empty((n, n, 2), dtype=torch.float64, device=bsr.device)
         pufe_bsr_to_dense(self.ctx, bsr.contiguous(), dtype, D)
         return torch.view_as_complex(D)
+
+
+def _make_autograd():
+    import torch
+
+    class PUFEAssemble(torch.autograd.Function):
+        """H, S = PUFEAssemble.apply(problem, V, R, kpt): complex128 BSR values of
+        one k-point as functions of the potential V at the quadrature points and
+        of the enrichment centres R (n_atoms x 3; rule and enriched sets fixed).
+        The backward pass calls the adjoint kernels; for a real loss L the
+        incoming gradients are P = dL/dH and Q = dL/dS in torch's convention,
+        i.e. L = Re<P, H> + Re<Q, S> to first order."""
+
+        @staticmethod
+        def forward(ctx, problem, V, R, kpt):
+            problem.set_positions(R.detach().cpu().numpy())
+            nnz = problem.sizes["nnz"]
+            H = torch.empty(nnz, dtype=torch.complex128, device=V.device)
+            S = torch.empty(nnz, dtype=torch.complex128, device=V.device)
+            pufe_assemble(problem.ctx, V.detach().contiguous(), [kpt], "fp64", "c128", H, S)
+            ctx.problem = problem
+            ctx.kpt = tuple(float(k) for k in kpt)
+            ctx.R = R.detach().cpu().numpy()
+            ctx.R_device = R.device
+            ctx.save_for_backward(V)
+            return H, S
+
+        @staticmethod
+        def backward(ctx, gH, gS):
+            (V,) = ctx.saved_tensors
+            ctx.problem.set_positions(ctx.R)
+            dV, dR = ctx.problem.backward(V.detach().contiguous(), ctx.kpt, gH, gS)
+            return None, dV, dR.to(ctx.R_device), None
+
+    return PUFEAssemble
+
+
+class _Lazy:
+    cls = None
+
+
+def PUFEAssemble():
+    if _Lazy.cls is None:
+        _Lazy.cls = _make_autograd()
+    return _Lazy.cls
 
 
 def eig(H, S, m):

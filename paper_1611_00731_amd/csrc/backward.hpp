@@ -1,0 +1,24 @@
+// Host-side launchers of the adjoint kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables.hpp"
+
+namespace pufe {
+
+constexpr int kBackwardQ = 8;          // quadrature points per LDS stage of the adjoint
+constexpr int kBackwardMaxNloc = 96;   // largest element the adjoint kernel holds
+
+size_t backward_lds_bytes(int npad, int nfun);
+hipError_t launch_gather_adjoint(const KParams &kp, int64_t nel, const ElemDev *elems, const int32_t *edof,
+                                 const int64_t *pt_off, const double *P, const double *kpt, double *Pt,
+                                 hipStream_t st);
+hipError_t launch_backward(const KParams &kp, bool qmode, int n_items, const ItemDev *items, const ElemDev *elems,
+                           const GroupDev *groups, const double *img, const int32_t *edof, const uint32_t *leaves,
+                           const double *V, const int64_t *pt_off, const double *Pt, double *dLdV, double *fpart,
+                           int max_ngrp, size_t lds, hipStream_t st);
+hipError_t launch_force_reduce(int n_atoms, const int64_t *atom_ptr, const int64_t *atom_slots, const double *fP,
+                               const double *fQ, double *dLdR, hipStream_t st);
+
+}  // namespace pufe

@@ -55,6 +55,32 @@ __device__ __forceinline__ void solid_harmonics(int l, double x, double y, doubl
     }
 }
 
+// Hessians of the solid harmonics, 6 symmetric components per m
+// (xx, yy, zz, xy, xz, yz) at h[6 * (m + l) + c].
+__device__ __forceinline__ void solid_harmonics_hess(int l, double x, double y, double z, double *h) {
+    const int nm = 2 * l + 1;
+    for (int k = 0; k < 6 * nm; ++k) h[k] = 0.0;
+    if (l == 2) {
+        h[0 * 6 + 3] = Y2A;                                   // xy
+        h[1 * 6 + 5] = Y2A;                                   // yz
+        h[2 * 6 + 0] = -2.0 * Y2B; h[2 * 6 + 1] = -2.0 * Y2B; h[2 * 6 + 2] = 4.0 * Y2B;
+        h[3 * 6 + 4] = Y2A;                                   // xz
+        h[4 * 6 + 0] = 2.0 * Y2C; h[4 * 6 + 1] = -2.0 * Y2C;
+    } else if (l == 3) {
+        double *m;
+        m = h + 0 * 6; m[0] = 6.0 * Y3A * y; m[1] = -6.0 * Y3A * y; m[3] = 6.0 * Y3A * x;
+        m = h + 1 * 6; m[3] = Y3B * z; m[4] = Y3B * y; m[5] = Y3B * x;
+        m = h + 2 * 6; m[0] = -2.0 * Y3C * y; m[1] = -6.0 * Y3C * y; m[2] = 8.0 * Y3C * y;
+                       m[3] = -2.0 * Y3C * x; m[5] = 8.0 * Y3C * z;
+        m = h + 3 * 6; m[0] = -6.0 * Y3D * z; m[1] = -6.0 * Y3D * z; m[2] = 12.0 * Y3D * z;
+                       m[4] = -6.0 * Y3D * x; m[5] = -6.0 * Y3D * y;
+        m = h + 4 * 6; m[0] = -6.0 * Y3C * x; m[1] = -2.0 * Y3C * x; m[2] = 8.0 * Y3C * x;
+                       m[3] = -2.0 * Y3C * y; m[4] = 8.0 * Y3C * z;
+        m = h + 5 * 6; m[0] = 2.0 * Y3E * z; m[1] = -2.0 * Y3E * z; m[4] = 2.0 * Y3E * x; m[5] = -2.0 * Y3E * y;
+        m = h + 6 * 6; m[0] = 6.0 * Y3A * x; m[1] = -6.0 * Y3A * x; m[3] = -6.0 * Y3A * y;
+    }
+}
+
 // 1D Lagrange factors of order p (1 or 2) on the nodes -1, (0,) 1 of the
 // reference interval: values L[0..p] and derivatives D[0..p] at t.
 __device__ __forceinline__ void lagrange_1d(int p, double t, double *L, double *D) {

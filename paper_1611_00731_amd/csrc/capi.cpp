@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/pufe.h"
+#include "backward.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 
@@ -58,6 +59,7 @@ struct pufe_ctx {
     std::vector<int64_t> leaf_off_h;
     std::vector<ItemDev> items;
     size_t lds = 0;
+    int max_rows = 16;
     int64_t part_slots = 0;
     DevBuf<ElemDev> d_elems;
     DevBuf<GroupDev> d_groups;
@@ -66,6 +68,13 @@ struct pufe_ctx {
     DevBuf<uint32_t> d_leaves;
     DevBuf<int64_t> d_leaf_count, d_leaf_off, d_bval_off, d_dof_off;
     DevBuf<ItemDev> d_items;
+    // adjoint
+    bool have_bw = false;
+    std::vector<ItemDev> bw_items;
+    size_t bw_lds = 0;
+    DevBuf<ItemDev> d_bw_items;
+    DevBuf<int64_t> d_pt_off, d_atom_ptr, d_atom_slots;
+    DevBuf<double> d_Pt, d_fP, d_fQ;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
@@ -177,6 +186,7 @@ int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], 
     ctx->plan = std::move(pl);
     ctx->have_problem = true;
     ctx->have_setup = false;
+    ctx->have_bw = false;
     ctx->n_leaves = ctx->n_qp = 0;
     return PUFE_OK;
 }
@@ -249,6 +259,7 @@ static void plan_items(pufe_ctx *c) {
         max_rows = std::max(max_rows, 16 * (it.I0 == it.J0 ? it.nI : it.nI + it.nJ));
     }
     c->items.swap(sorted);
+    c->max_rows = max_rows;
     c->lds = contract_lds_bytes(max_rows, std::max(pl.max_nfun, 1));
 }
 
@@ -291,7 +302,7 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
         return fail(ctx, PUFE_ERR_UNSUPPORTED, "contraction stage does not fit in LDS");
     CHECK_HIP(ctx, ctx->d_elems.upload(pl.elems, st), "upload elements");
     CHECK_HIP(ctx, ctx->d_groups.upload(pl.groups, st), "upload groups");
-    CHECK_HIP(ctx, ctx->d_img.upload(pl.img, st), "upload images");
+    CHECK_HIP(ctx, ctx->d_img.upload(pl.img_cur, st), "upload images");
     CHECK_HIP(ctx, ctx->d_edof.upload(pl.edof, st), "upload enriched functions");
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_color_elems.upload(pl.color_elems, st), "upload colours");
@@ -372,9 +383,18 @@ int pufe_get_leaves(pufe_ctx *ctx, int32_t *level, int32_t *ijk, int64_t *elem_l
 }
 
 static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipStream_t st) {
-    if (precision != PUFE_PREC_FP64)
-        return fail(ctx, PUFE_ERR_UNSUPPORTED, "only the FP64 contraction is available");
     const Plan &pl = ctx->plan;
+    if (precision == PUFE_PREC_BF16X3 || precision == PUFE_PREC_BF16X6) {
+        const int nl = precision == PUFE_PREC_BF16X3 ? 2 : 3;
+        const size_t lds = split_lds_bytes(nl, ctx->max_rows, std::max(pl.max_nfun, 1));
+        if (lds > 160 * 1024) return fail(ctx, PUFE_ERR_UNSUPPORTED, "split stage does not fit in LDS");
+        TimedRegion tr(ctx, 0, st);
+        CHECK_HIP(ctx, launch_contract_split(nl, pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p,
+                                             ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V,
+                                             ctx->d_partial.p, lds, st),
+                  "split contraction");
+        return PUFE_OK;
+    }
     TimedRegion tr(ctx, 0, st);
     CHECK_HIP(ctx, launch_contract_f64(pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p, ctx->d_groups.p,
                                        ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_partial.p, ctx->lds, st),
@@ -444,10 +464,129 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
     return PUFE_OK;
 }
 
-int pufe_assemble_backward(pufe_ctx *ctx, const double *, const double *, const void *, const void *, int,
-                           double *, double *, void *) {
+// Plan the adjoint: one work item per (element, K-chunk of the forward
+// partition), the padded Ps blocks, and for each atom the list of per-item
+// group partial forces in a fixed order.
+static int plan_backward(pufe_ctx *c, hipStream_t st) {
+    Plan &pl = c->plan;
+    int max_npad = 16, max_nfun = 1;
+    std::vector<int64_t> pt_off(pl.nel + 1, 0);
+    for (int64_t e = 0; e < pl.nel; ++e) {
+        const ElemDev &el = pl.elems[e];
+        if (el.nloc > kBackwardMaxNloc)
+            return fail(c, PUFE_ERR_UNSUPPORTED, "the adjoint kernel holds elements of at most " +
+                                                     std::to_string(kBackwardMaxNloc) + " functions");
+        int npad = 16 * ((el.nloc + 15) / 16);
+        max_npad = std::max(max_npad, npad);
+        max_nfun = std::max(max_nfun, el.nfun);
+        pt_off[e + 1] = pt_off[e] + (int64_t)npad * npad;
+    }
+    c->bw_lds = backward_lds_bytes(max_npad, max_nfun);
+    if (c->bw_lds > 160 * 1024) return fail(c, PUFE_ERR_UNSUPPORTED, "adjoint stage does not fit in LDS");
+    c->bw_items.clear();
+    const int mg = std::max(pl.max_ngrp, 1);
+    std::vector<std::vector<int64_t>> slots(c->prob.species.size());
+    for (int64_t e = 0; e < pl.nel; ++e) {
+        const ElemDev &el = pl.elems[e];
+        int64_t nleaf = el.leaf_end - el.leaf_off, nch = el.nchunk;
+        for (int64_t ch = 0; ch < nch; ++ch) {
+            ItemDev it{};
+            it.elem = (int32_t)e;
+            it.chunk = (int32_t)ch;
+            it.leaf_b = el.leaf_off + ch * nleaf / nch;
+            it.leaf_e = el.leaf_off + (ch + 1) * nleaf / nch;
+            int64_t idx = (int64_t)c->bw_items.size();
+            c->bw_items.push_back(it);
+            for (int g = 0; g < el.ngrp; ++g) slots[pl.groups[el.grp_off + g].atom].push_back(idx * mg + g);
+        }
+    }
+    std::vector<int64_t> aptr(slots.size() + 1, 0), aslots;
+    for (size_t A = 0; A < slots.size(); ++A) {
+        aslots.insert(aslots.end(), slots[A].begin(), slots[A].end());
+        aptr[A + 1] = (int64_t)aslots.size();
+    }
+    CHECK_HIP(c, c->d_bw_items.upload(c->bw_items, st), "upload adjoint items");
+    CHECK_HIP(c, c->d_pt_off.upload(pt_off, st), "upload adjoint offsets");
+    CHECK_HIP(c, c->d_atom_ptr.upload(aptr, st), "upload atom lists");
+    CHECK_HIP(c, c->d_atom_slots.upload(aslots, st), "upload atom lists");
+    CHECK_HIP(c, c->d_Pt.alloc((size_t)pt_off[pl.nel]), "alloc adjoint blocks");
+    CHECK_HIP(c, c->d_fP.alloc(c->bw_items.size() * mg * 3), "alloc partial forces");
+    CHECK_HIP(c, c->d_fQ.alloc(c->bw_items.size() * mg * 3), "alloc partial forces");
+    c->have_bw = true;
+    return PUFE_OK;
+}
+
+int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3], const void *d_P, const void *d_Q,
+                           int precision, double *d_dLdV, double *d_dLdR, void *stream) {
     if (!ctx) return PUFE_ERR_INVALID_ARG;
-    return fail(ctx, PUFE_ERR_UNSUPPORTED, "the adjoint kernel is not built yet");
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    if (!d_V || !kpt) return fail(ctx, PUFE_ERR_INVALID_ARG, "null V or k-point");
+    if (precision != PUFE_PREC_FP64) return fail(ctx, PUFE_ERR_UNSUPPORTED, "the adjoint runs in FP64");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(kpt[d])) return fail(ctx, PUFE_ERR_INVALID_ARG, "non-finite k-point");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    if (!ctx->have_bw) {
+        int rc = plan_backward(ctx, st);
+        if (rc != PUFE_OK) return rc;
+    }
+    const Plan &pl = ctx->plan;
+    TimedRegion tr(ctx, 2, st);
+    const int mg = std::max(pl.max_ngrp, 1);
+    const int nit = (int)ctx->bw_items.size();
+    if (d_P) {
+        CHECK_HIP(ctx, launch_gather_adjoint(pl.kp, pl.nel, ctx->d_elems.p, ctx->d_edof.p, ctx->d_pt_off.p,
+                                             (const double *)d_P, kpt, ctx->d_Pt.p, st), "gather P");
+        CHECK_HIP(ctx, launch_backward(pl.kp, false, nit, ctx->d_bw_items.p, ctx->d_elems.p, ctx->d_groups.p,
+                                       ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_pt_off.p,
+                                       ctx->d_Pt.p, d_dLdV, ctx->d_fP.p, mg, ctx->bw_lds, st), "adjoint (P)");
+    } else if (d_dLdV) {
+        CHECK_HIP(ctx, launch_fill_zero(d_dLdV, ctx->n_qp, false, st), "zero dLdV");
+    }
+    if (d_Q) {
+        CHECK_HIP(ctx, launch_gather_adjoint(pl.kp, pl.nel, ctx->d_elems.p, ctx->d_edof.p, ctx->d_pt_off.p,
+                                             (const double *)d_Q, kpt, ctx->d_Pt.p, st), "gather Q");
+        CHECK_HIP(ctx, launch_backward(pl.kp, true, nit, ctx->d_bw_items.p, ctx->d_elems.p, ctx->d_groups.p,
+                                       ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_pt_off.p,
+                                       ctx->d_Pt.p, nullptr, ctx->d_fQ.p, mg, ctx->bw_lds, st), "adjoint (Q)");
+    }
+    if (d_dLdR)
+        CHECK_HIP(ctx, launch_force_reduce((int)ctx->prob.species.size(), ctx->d_atom_ptr.p, ctx->d_atom_slots.p,
+                                           d_P ? ctx->d_fP.p : nullptr, d_Q ? ctx->d_fQ.p : nullptr, d_dLdR, st),
+                  "force reduction");
+    return PUFE_OK;
+}
+
+int pufe_set_positions(pufe_ctx *ctx, const double *pos) {
+    if (!ctx || !pos) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "no problem defined");
+    Plan &pl = ctx->plan;
+    const size_t na = ctx->prob.species.size();
+    for (size_t A = 0; A < na; ++A) {
+        double d2 = 0;
+        for (int c = 0; c < 3; ++c) {
+            if (!std::isfinite(pos[3 * A + c])) return fail(ctx, PUFE_ERR_INVALID_ARG, "non-finite position");
+            double d = pos[3 * A + c] - ctx->prob.pos[3 * A + c];
+            d2 += d * d;
+        }
+        if (std::sqrt(d2) > kImageMargin)
+            return fail(ctx, PUFE_ERR_INVALID_ARG, "an enrichment centre moved farther than the image margin");
+    }
+    // shift every image centre of a group by its atom's displacement
+    for (const ElemDev &el : pl.elems)
+        for (int g = 0; g < el.ngrp; ++g) {
+            const GroupDev &G = pl.groups[el.grp_off + g];
+            for (int k = 0; k < G.nimg; ++k)
+                for (int c = 0; c < 3; ++c)
+                    pl.img_cur[3 * (G.img_off + k) + c] = pl.img[3 * (G.img_off + k) + c] +
+                                                          (pos[3 * G.atom + c] - ctx->prob.pos[3 * G.atom + c]);
+        }
+    if (ctx->have_setup) {
+        CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        CHECK_HIP(ctx, hipMemcpy(ctx->d_img.p, pl.img_cur.data(), sizeof(double) * pl.img_cur.size(),
+                                 hipMemcpyHostToDevice), "upload image centres");
+    }
+    return PUFE_OK;
 }
 
 int pufe_bsr_to_dense(pufe_ctx *ctx, const void *d_bsr, int dtype, double *d_dense, void *stream) {

@@ -10,6 +10,8 @@
 #include <stdint.h>
 
 #include "basis.hpp"
+#include "device_common.hpp"
+#include "enrich.hpp"
 #include "kernels.hpp"
 #include "tables.hpp"
 
@@ -109,20 +111,6 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int64_t *__restrict__ 
     if (t == 1023) off[n] = part[1023];
 }
 
-// Reference point and weight of Gauss point j of a leaf.
-__device__ __forceinline__ void leaf_point(const KParams &kp, uint32_t code, int j, double *xi, double *w) {
-    int lev = (int)(code >> 27);
-    int c[3] = {(int)(code & 511u), (int)((code >> 9) & 511u), (int)((code >> 18) & 511u)};
-    int k[3] = {j % kp.n, (j / kp.n) % kp.n, j / (kp.n * kp.n)};
-    double h = 1.0 / (double)(1 << lev);
-    double wt = h * h * h * kp.jac;
-    for (int d = 0; d < 3; ++d) {
-        xi[d] = -1.0 + (2.0 * c[d] + 1.0 + kp.gx[k[d]]) * h;
-        wt *= kp.gw[k[d]];
-    }
-    *w = wt;
-}
-
 __global__ void qp_export_kernel(const KParams kp, int64_t n_leaves, const uint32_t *__restrict__ leaves,
                                  const int32_t *__restrict__ leaf_elem, double *__restrict__ xyz,
                                  double *__restrict__ w) {
@@ -151,46 +139,6 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 }
 
 // ---------------------------------------------------------- contraction
-
-// Enrichment functions of one (atom, descriptor) group at one point x:
-// Psi_m = sum over images of g(s) S_m(r), grad Psi_m = 2 g'(s) r S_m + g grad S_m,
-// g(s) = exp(-a s) (1 - s/rc^2)^3, r = x - image centre, s = |r|^2 < rc^2.
-// Written to o[m * Q * 4 + (0: value, 1..3: gradient)].
-template <int L, int Q>
-__device__ __forceinline__ void group_eval(const GroupDev &G, const double *__restrict__ img, const double *x,
-                                           double *o) {
-    constexpr int NM = 2 * L + 1;
-    double psi[NM], gp[3 * NM];
-#pragma unroll
-    for (int m = 0; m < NM; ++m) psi[m] = gp[3 * m] = gp[3 * m + 1] = gp[3 * m + 2] = 0.0;
-    const double rc2 = G.rc * G.rc, inv_rc2 = 1.0 / rc2;
-    const double *c0 = img + 3 * G.img_off;
-    for (int k = 0; k < G.nimg; ++k) {
-        const double rx = x[0] - c0[3 * k], ry = x[1] - c0[3 * k + 1], rz = x[2] - c0[3 * k + 2];
-        const double s = rx * rx + ry * ry + rz * rz;
-        if (s >= rc2) continue;
-        const double ex = exp(-G.a * s), c = 1.0 - s * inv_rc2, c2 = c * c;
-        const double g0 = ex * c2 * c;
-        const double g1 = -ex * c2 * (G.a * c + 3.0 * inv_rc2);
-        double S[NM > 7 ? NM : 7], dS[21];
-        solid_harmonics(L, rx, ry, rz, S, dS);
-#pragma unroll
-        for (int m = 0; m < NM; ++m) {
-            psi[m] += g0 * S[m];
-            gp[3 * m] += 2.0 * g1 * rx * S[m] + g0 * dS[3 * m];
-            gp[3 * m + 1] += 2.0 * g1 * ry * S[m] + g0 * dS[3 * m + 1];
-            gp[3 * m + 2] += 2.0 * g1 * rz * S[m] + g0 * dS[3 * m + 2];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < NM; ++m) {
-        double *om = o + (size_t)m * Q * 4;
-        om[0] = psi[m];
-        om[1] = gp[3 * m];
-        om[2] = gp[3 * m + 1];
-        om[3] = gp[3 * m + 2];
-    }
-}
 
 // Work-group shape and LDS map of the fused contraction kernel.
 //   sB[row][q][4]   (grad_x, grad_y, grad_z, value) of the item's local rows
@@ -400,25 +348,6 @@ __global__ void fill_zero_f32_kernel(float *__restrict__ p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = 0.0f;
-}
-
-// corner and vertex slot of local function a
-__device__ __forceinline__ void local_slot(const ElemDev &el, const int32_t *edof, int p, int a, int *corner,
-                                           int *slot) {
-    if (a < el.nfe) {
-        if (p == 1) {
-            *corner = a;
-            *slot = 0;
-        } else {
-            int d0 = a % 3, d1 = (a / 3) % 3, d2 = a / 9;
-            *corner = (d0 == 2) | ((d1 == 2) << 1) | ((d2 == 2) << 2);
-            *slot = (d0 == 1) | ((d1 == 1) << 1) | ((d2 == 1) << 2);
-        }
-    } else {
-        int pk = edof[el.edof_off + (a - el.nfe)];
-        *corner = pk & 7;
-        *slot = pk >> 11;
-    }
 }
 
 // Element e of colour c: sum its K-chunk partials in a fixed order, then for

@@ -9,6 +9,7 @@ namespace pufe {
 
 constexpr int kContractQ = 16;      // quadrature points per LDS stage of the contraction
 constexpr int kMaxKPerLaunch = 16;  // k-points handled by one scatter launch
+constexpr int kSplitQ = 32;         // quadrature points per LDS stage of the split-bf16 contraction
 
 struct KPoints {
     int32_t nk;
@@ -28,6 +29,11 @@ hipError_t launch_contract_f64(const KParams &kp, int n_items, const ItemDev *it
                                const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st);
+size_t split_lds_bytes(int nlimb, int rows, int nfun);
+hipError_t launch_contract_split(int nlimb, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+                                 const GroupDev *groups, const double *img, const int32_t *edof,
+                                 const uint32_t *leaves, const double *V, double *partial, size_t lds,
+                                 hipStream_t st);
 hipError_t launch_fill_zero(void *p, int64_t n, bool f32, hipStream_t st);
 hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int32_t *color_elems, int n_elems,
                           const int32_t *edof, const double *partial, const KPoints &kps, int out_dtype,

@@ -228,7 +228,7 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
                 ur[d] = tau[0] * pl.inv[d] + tau[1] * pl.inv[3 + d] + tau[2] * pl.inv[6 + d];
                 uc[d] = centre[0] * pl.inv[d] + centre[1] * pl.inv[3 + d] + centre[2] * pl.inv[6 + d];
             }
-            double reach = en.rc + Re;
+            double reach = en.rc + Re + kImageMargin;
             int lo[3], hi[3];
             for (int d = 0; d < 3; ++d) {
                 double rad = reach * std::sqrt(pl.inv[d] * pl.inv[d] + pl.inv[3 + d] * pl.inv[3 + d] + pl.inv[6 + d] * pl.inv[6 + d]);
@@ -280,6 +280,22 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
         el.color = col[0] + 3 * col[1] + 9 * col[2];
         by_color[el.color].push_back((int32_t)e);
     }
+    pl.img_cur = pl.img;
+    // the scatter relies on elements of one colour sharing no vertex
+    {
+        std::vector<int32_t> owner(pl.nv * 27, -1);
+        for (int64_t e = 0; e < pl.nel; ++e) {
+            const ElemDev &el = pl.elems[e];
+            for (int c = 0; c < 8; ++c) {
+                int j[3];
+                for (int d = 0; d < 3; ++d) j[d] = (el.ijk[d] + ((c >> d) & 1)) % mesh[d];
+                int64_t v = ((int64_t)j[2] * n2 + j[1]) * n1 + j[0];
+                int32_t &o = owner[v * 27 + el.color];
+                if (o >= 0 && o != (int32_t)e) { err = "internal error: element colouring conflict"; return PUFE_ERR_INVALID_ARG; }
+                o = (int32_t)e;
+            }
+        }
+    }
     pl.color_elems.clear();
     pl.color_off.assign(1, 0);
     for (int c = 0; c < 27; ++c) {
@@ -301,9 +317,8 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     kp.nfe = pl.nfe;
     kp.nfs = pl.nfs;
     for (int d = 0; d < 3; ++d) kp.mesh[d] = mesh[d];
-    // Gauss-Legendre nodes and weights (Golub-Welsch: eigenvalues of the
-    // symmetric Jacobi matrix would need LAPACK; a Newton iteration on the
-    // three-term recurrence is enough here)
+    // Gauss-Legendre nodes (ascending) and weights: Newton iteration on the
+    // three-term Legendre recurrence from cosine initial guesses
     int n = q.n_gauss;
     for (int r = 0; r < n; ++r) {
         double x = -std::cos(M_PI * (r + 0.75) / (n + 0.5));

@@ -36,13 +36,18 @@ struct Plan {
     // elements
     std::vector<ElemDev> elems;
     std::vector<GroupDev> groups;
-    std::vector<double> img;        // image centres, 3 per image
+    std::vector<double> img;        // image centres at the planned positions, 3 per image
+    std::vector<double> img_cur;    // image centres at the current positions
     std::vector<int32_t> edof;      // packed enriched local functions
     std::vector<int32_t> color_elems;
     std::vector<int32_t> color_off; // n_colors + 1
     int max_nloc = 0, max_nfun = 0, max_ngrp = 0;
     KParams kp;
 };
+
+// Image lists keep every image within rc + this margin of an element, so the
+// enrichment centres may move by up to the margin without replanning.
+constexpr double kImageMargin = 0.25;
 
 // Validate and plan; returns PUFE_OK or an error code with a message.
 int build_plan(const Problem &pr, Plan &pl, std::string &err);

@@ -1,0 +1,168 @@
+"""GPU parity of the adjoint (assemble_backward) and its autograd wrapper.
+
+dL/dV is compared with the oracle point by point; dL/dR with the oracle on
+small cases and with central finite differences (h = 1e-4 bohr) of the GPU
+forward, rule and enriched sets frozen, at the 64-atom supercell size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1611_00731_amd as P  # noqa: E402
+from workloads.potential import potential_at  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def bsr_index(lay):
+    """Global (row, col) DOF of every stored BSR entry, in value order."""
+    off, rp, bc, bo = lay["dof_offset"], lay["brow_ptr"], lay["bcol"], lay["bval_offset"]
+    rows, cols = [], []
+    for v in range(len(rp) - 1):
+        bv = off[v + 1] - off[v]
+        for k in range(rp[v], rp[v + 1]):
+            w = bc[k]
+            bw = off[w + 1] - off[w]
+            r = np.repeat(np.arange(off[v], off[v + 1]), bw)
+            c = np.tile(np.arange(off[w], off[w + 1]), bv)
+            rows.append(r)
+            cols.append(c)
+    return np.concatenate(rows), np.concatenate(cols)
+
+
+def small_case():
+    prob = W.small("lih", mesh=(2, 3, 2), fe_order=2, levels=1, n=3, a=4.8, re=1.7, rc=2.1)
+    o = oracle.Oracle(prob)
+    xyz, w, off = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob).cpu().numpy()
+    Cp = W.adjoint_factor(o.n_dof, rank=6, seed=0)
+    Cq = W.adjoint_factor(o.n_dof, rank=3, seed=1)
+    return prob, o, V, Cp @ Cp.conj().T, Cq @ Cq.conj().T
+
+
+def test_backward_matches_oracle_small():
+    prob, o, V, Pd, Qd = small_case()
+    kap = (0.12, -0.24, 0.37)
+    say("backward small vs oracle")
+    dV_o, dR_o = o.backward_dense(V, kap, Pd, Qd)
+    p = P.Problem(prob).setup()
+    rows, cols = bsr_index(p.layout())
+    Pb = torch.from_numpy(Pd[rows, cols]).cuda()
+    Qb = torch.from_numpy(Qd[rows, cols]).cuda()
+    Vd = torch.from_numpy(V).cuda()
+    dV, dR = p.backward(Vd, kap, Pb, Qb)
+    assert rel(dV.cpu().numpy(), dV_o) < 1e-11
+    assert np.abs(dR.cpu().numpy() - dR_o).max() < 1e-11 * np.abs(dR_o).max()
+    # P only and Q only add up to both
+    dV1, dR1 = p.backward(Vd, kap, Pb, None)
+    dV2, dR2 = p.backward(Vd, kap, None, Qb)
+    assert torch.equal(dV1, dV) and torch.count_nonzero(dV2) == 0
+    assert torch.allclose(dR1 + dR2, dR, rtol=0, atol=1e-13 * float(dR.abs().max()))
+    # repeated calls are bitwise identical
+    dV3, dR3 = p.backward(Vd, kap, Pb, Qb)
+    assert torch.equal(dV3, dV) and torch.equal(dR3, dR)
+    p.close()
+
+
+def test_autograd_function_and_finite_differences():
+    prob, o, V, Pd, Qd = small_case()
+    kap = (0.25, 0.0, -0.13)
+    say("autograd + FD small")
+    p = P.Problem(prob).setup()
+    rows, cols = bsr_index(p.layout())
+    Pb = torch.from_numpy(Pd[rows, cols]).cuda()
+    Qb = torch.from_numpy(Qd[rows, cols]).cuda()
+    Fn = P.PUFEAssemble()
+    R0 = np.asarray(prob["atoms"], float)
+    Vt = torch.from_numpy(V).cuda().requires_grad_(True)
+    Rt = torch.tensor(R0, dtype=torch.float64, requires_grad=True)
+    H, S = Fn.apply(p, Vt, Rt, kap)
+    L = (Pb.conj() * H).real.sum() + (Qb.conj() * S).real.sum()
+    L.backward()
+    dV_o, dR_o = o.backward_dense(V, kap, Pd, Qd)
+    assert rel(Vt.grad.cpu().numpy(), dV_o) < 1e-11
+    assert np.abs(Rt.grad.cpu().numpy() - dR_o).max() < 1e-11 * np.abs(dR_o).max()
+
+    def loss(R):
+        p.set_positions(R)
+        with torch.no_grad():
+            H, S = p.assemble(torch.from_numpy(V).cuda(), [kap])
+        Hc = torch.view_as_complex(H[0])
+        Sc = torch.view_as_complex(S[0])
+        return float((Pb.conj() * Hc).real.sum() + (Qb.conj() * Sc).real.sum())
+
+    h = 1e-4
+    g = Rt.grad.cpu().numpy()
+    for A, k in [(0, 0), (1, 2), (5, 1), (6, 0)]:
+        Rp, Rm = R0.copy(), R0.copy()
+        Rp[A, k] += h
+        Rm[A, k] -= h
+        fd = (loss(Rp) - loss(Rm)) / (2 * h)
+        assert abs(fd - g[A, k]) < 1e-6 * max(1.0, np.abs(g).max()), (A, k, fd, g[A, k])
+    p.set_positions(R0)
+    p.close()
+
+
+def test_backward_cfg5_full_size():
+    """2x2x2 LiH-like supercell (64 atoms, 4096 elements, 12.1 M points),
+    rank-128 Hermitian PSD P on the pattern: dL/dV on sampled elements against
+    the oracle's per-element adjoint, dL/dR against central differences of the
+    GPU forward."""
+    prob = W.cfg5()
+    say("backward cfg5 full size")
+    o = oracle.Oracle(prob)
+    xyz, w, qoff = o.quadrature()
+    Vd = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    V = Vd.cpu().numpy()
+    p = P.Problem(prob).setup()
+    lay = p.layout()
+    N = p.sizes["n_dof"]
+    Cf = W.adjoint_factor(N, rank=128, seed=0)
+    Cd = torch.from_numpy(Cf).cuda()
+    rows, cols = bsr_index(lay)
+    rows_d = torch.from_numpy(rows).cuda()
+    cols_d = torch.from_numpy(cols).cuda()
+    Pb = torch.empty(len(rows), dtype=torch.complex128, device="cuda")
+    for s in range(0, len(rows), 1 << 20):
+        r, c = rows_d[s:s + (1 << 20)], cols_d[s:s + (1 << 20)]
+        Pb[s:s + (1 << 20)] = (Cd[r] * Cd[c].conj()).sum(-1)
+    dV, dR = p.backward(Vd, (0.0, 0.0, 0.0), Pb, None)
+    dVh = dV.cpu().numpy()
+    lev, _, loff = o.leaves()
+    refined = [e for e in range(o.n_elem) if loff[e + 1] - loff[e] > 1]
+    for e in [refined[0], refined[len(refined) // 2], 5, 1234, o.n_elem - 1]:
+        g, _ = o.element_dofs(e)
+        Ploc = Cf[g] @ Cf[g].conj().T
+        dv_o, _ = o.backward_element(e, V[qoff[e]:qoff[e + 1]], (0, 0, 0), Ploc)
+        assert rel(dVh[qoff[e]:qoff[e + 1]], dv_o) < 1e-11, e
+    R0 = np.asarray(prob["atoms"], float)
+
+    def loss(R):
+        p.set_positions(R)
+        H, _ = p.assemble(Vd, [(0, 0, 0)], with_S=False)
+        return float((Pb.conj() * torch.view_as_complex(H[0])).real.sum())
+
+    g = dR.cpu().numpy()
+    h = 1e-4
+    for A, k in [(0, 0), (13, 1), (40, 2), (63, 0)]:
+        Rp, Rm = R0.copy(), R0.copy()
+        Rp[A, k] += h
+        Rm[A, k] -= h
+        fd = (loss(Rp) - loss(Rm)) / (2 * h)
+        assert abs(fd - g[A, k]) < 1e-6 * np.abs(g).max(), (A, k, fd, g[A, k])
+    p.set_positions(R0)
+    p.close()

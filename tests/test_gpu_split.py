@@ -1,0 +1,99 @@
+"""Split-BF16 contractions against the FP64 oracle.
+
+bf16x6 (three limbs, six products, FP32 MFMA accumulation flushed to FP64
+every 32 points) must meet 1e-7 relative Frobenius on H and S and 1e-6 Ha on
+the eigenvalues.  bf16x3 (two limbs, three products) is held to the bound its
+~17-bit operands allow, and its measured error is printed.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1611_00731_amd as P  # noqa: E402
+from workloads.potential import potential_at  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name", ["lih", "ceal"])
+def test_split_small_vs_oracle(name):
+    if name == "lih":
+        prob = W.small("lih", mesh=(3, 2, 2), fe_order=2, levels=1, n=4, a=5.0)
+    else:
+        prob = W.small("ceal", mesh=(2, 2, 2), fe_order=2, levels=1, n=3, a=4.4, rc=3.0, re=2.4)
+    kap = (0.12, -0.24, 0.37)
+    say("split small", name)
+    o = oracle.Oracle(prob)
+    xyz, _, _ = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    Ho, So = o.assemble_dense(V.cpu().numpy(), kap)
+    p = P.Problem(prob).setup()
+    errs = {}
+    for prec in ("bf16x6", "bf16x3"):
+        H, S = p.assemble(V, [kap], precision=prec)
+        eh = rel(p.to_dense(H[0]).cpu().numpy(), Ho)
+        es = rel(p.to_dense(S[0]).cpu().numpy(), So)
+        errs[prec] = (eh, es)
+    say("errors", errs)
+    assert max(errs["bf16x6"]) < 1e-7
+    assert max(errs["bf16x3"]) < 5e-6
+    p.close()
+
+
+def test_split_cfg1_eigenvalues():
+    prob = W.cfg1()
+    say("split cfg1 eigenvalues")
+    o = oracle.Oracle(prob)
+    xyz, _, _ = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    Ho, So = o.assemble_dense(V.cpu().numpy())
+    ev_o = oracle.generalized_eigh(Ho, So, 4)
+    p = P.Problem(prob).setup()
+    H, S = p.assemble(V, precision="bf16x6")
+    ev = P.eig(p.to_dense(H[0]), p.to_dense(S[0]), 4).cpu().numpy()
+    assert np.abs(ev - ev_o).max() < 1e-6
+    p.close()
+
+
+def test_split_cfg2_full_size_eigenvalues():
+    """The LiH-like workload at full size: H/S errors of both split forms and
+    the lowest 16 eigenvalues against the oracle's dense FP64 assembly."""
+    prob = W.cfg2()
+    say("split cfg2 full size (oracle dense assembly, ~1 min)")
+    o = oracle.Oracle(prob)
+    xyz, _, _ = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    Ho, So = o.assemble_dense(V.cpu().numpy())
+    Ho, So = Ho.real, So.real
+    say("oracle assembled")
+    Hd = torch.from_numpy(Ho).cuda().to(torch.complex128)
+    Sd = torch.from_numpy(So).cuda().to(torch.complex128)
+    ev_o = P.eig(Hd, Sd, 16).cpu().numpy()   # dense FP64 solve of the oracle's matrices
+    say("oracle eigenvalues", ev_o[:4])
+    p = P.Problem(prob).setup()
+    for prec, tol_m in (("bf16x6", 1e-7), ("bf16x3", 5e-6)):
+        H, S = p.assemble(V, precision=prec)
+        Hg, Sg = p.to_dense(H[0]), p.to_dense(S[0])
+        eh = rel(Hg.real.cpu().numpy(), Ho)
+        es = rel(Sg.real.cpu().numpy(), So)
+        ev = P.eig(Hg, Sg, 16).cpu().numpy()
+        de = np.abs(ev - ev_o).max()
+        say(prec, "H", eh, "S", es, "eig", de)
+        assert eh < tol_m and es < tol_m
+        if prec == "bf16x6":
+            assert de < 1e-6
+    p.close()
