@@ -200,6 +200,23 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
  * pufe_set_problem (PUFE_ERR_INVALID_ARG otherwise).  Synchronous. */
 int pufe_set_positions(pufe_ctx *ctx, const double *pos);
 
+/* Batched assembly over several problems (for instance one per lattice
+ * constant of an equation-of-state sweep), all set up on the same device.
+ * pufe_batch_assemble runs, for every problem, the assembly of pufe_assemble
+ * at the same n_k k-points: one persistent contraction launch whose work
+ * groups pull the work items of all problems from one queue (largest first),
+ * then one atomic-free scatter launch per element colour covering all
+ * problems.  The sequence is captured once into a HIP graph and replayed;
+ * a call with different pointers, k-points, precision or dtype recaptures.
+ * d_V, d_H, d_S are host arrays of n device pointers (d_S may be NULL).  The
+ * contexts must outlive the batch and must not be set up again meanwhile. */
+typedef struct pufe_batch pufe_batch;
+int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n);
+int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *kpts, int n_k, int precision,
+                        int out_dtype, void *const *d_H, void *const *d_S, void *stream);
+int pufe_batch_destroy(pufe_batch *b);
+const char *pufe_batch_last_error_message(const pufe_batch *b);
+
 /* Expand one BSR value array (out_dtype C128 or F64_GAMMA) into a dense
  * row-major n_dof x n_dof complex double matrix d_dense (device). */
 int pufe_bsr_to_dense(pufe_ctx *ctx, const void *d_bsr, int dtype, double *d_dense, void *stream);

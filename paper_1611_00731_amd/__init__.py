@@ -27,7 +27,8 @@ EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_
            "pufe_set_problem", "pufe_setup", "pufe_query", "pufe_get_layout",
            "pufe_get_quadrature", "pufe_get_leaves", "pufe_assemble", "pufe_element_matrices",
            "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
-           "pufe_kernel_times", "pufe_set_positions"]
+           "pufe_kernel_times", "pufe_set_positions", "pufe_batch_create", "pufe_batch_assemble",
+           "pufe_batch_destroy", "pufe_batch_last_error_message"]
 
 
 class PufeError(RuntimeError):
@@ -78,6 +79,11 @@ def _load():
         "pufe_enable_timing": ([vp, C.c_int], C.c_int),
         "pufe_kernel_times": ([vp, dp, i64p, C.c_int], C.c_int),
         "pufe_set_positions": ([vp, dp], C.c_int),
+        "pufe_batch_create": ([C.POINTER(vp), C.POINTER(vp), C.c_int], C.c_int),
+        "pufe_batch_assemble": ([vp, C.POINTER(vp), dp, C.c_int, C.c_int, C.c_int, C.POINTER(vp),
+                                 C.POINTER(vp), vp], C.c_int),
+        "pufe_batch_destroy": ([vp], C.c_int),
+        "pufe_batch_last_error_message": ([vp], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -220,6 +226,33 @@ def pufe_kernel_times(ctx, reset=True):
     return list(ms), list(cnt)
 
 
+def pufe_batch_create(ctxs):
+    arr = (C.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    h = C.c_void_p()
+    rc = lib.pufe_batch_create(C.byref(h), arr, len(ctxs))
+    if rc != PUFE_OK:
+        raise PufeError(rc, "batch creation")
+    return h
+
+
+def pufe_batch_destroy(b):
+    _check(None, lib.pufe_batch_destroy(b))
+
+
+def pufe_batch_assemble(b, Vs, kpts, precision, out_dtype, Hs, Ss=None, stream=None):
+    n = len(Vs)
+    k = np.ascontiguousarray(np.asarray(kpts, np.float64).reshape(-1, 3))
+    v = (C.c_void_p * n)(*[t.data_ptr() for t in Vs])
+    h = (C.c_void_p * n)(*[t.data_ptr() for t in Hs])
+    s = None if Ss is None else (C.c_void_p * n)(*[t.data_ptr() for t in Ss])
+    rc = lib.pufe_batch_assemble(b, v, k.ctypes.data_as(C.POINTER(C.c_double)), k.shape[0],
+                                 PREC[precision] if isinstance(precision, str) else int(precision),
+                                 OUT[out_dtype] if isinstance(out_dtype, str) else int(out_dtype),
+                                 h, s, _stream(stream))
+    if rc != PUFE_OK:
+        raise PufeError(rc, lib.pufe_batch_last_error_message(b).decode())
+
+
 # --------------------------------------------------------- convenience layer
 
 class Problem:
@@ -309,6 +342,36 @@ class Problem:
         D = torch.empty((n, n, 2), dtype=torch.float64, device=bsr.device)
         pufe_bsr_to_dense(self.ctx, bsr.contiguous(), dtype, D)
         return torch.view_as_complex(D)
+
+
+class Batch:
+    """Several set-up problems assembled by one persistent, graph-captured launch."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        self.h = pufe_batch_create([p.ctx for p in self.problems])
+
+    def close(self):
+        if getattr(self, "h", None):
+            pufe_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc(self, nk, out_dtype="c128", device=None):
+        import torch
+        dt = torch.float32 if out_dtype == "c64" else torch.float64
+        last = () if out_dtype == "f64" else (2,)
+        Hs = [torch.empty((nk, p.sizes["nnz"]) + last, dtype=dt, device=device) for p in self.problems]
+        Ss = [torch.empty_like(h) for h in Hs]
+        return Hs, Ss
+
+    def assemble(self, Vs, kpts, Hs, Ss=None, precision="fp64", out_dtype="c128"):
+        pufe_batch_assemble(self.h, Vs, kpts, precision, out_dtype, Hs, Ss)
 
 
 def _make_autograd():

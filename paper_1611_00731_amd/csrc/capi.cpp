@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/pufe.h"
+#include "aq_error.hpp"
 #include "backward.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -232,7 +233,7 @@ static void plan_items(pufe_ctx *c) {
         for (int64_t ch = 0; ch < nch; ++ch) {
             int64_t lb = el.leaf_off + ch * nleaf / nch, le = el.leaf_off + (ch + 1) * nleaf / nch;
             for (auto &b : bps[e]) {
-                ItemDev it;
+                ItemDev it{};
                 it.elem = (int32_t)e;
                 it.I0 = b.I0;
                 it.nI = b.nI;
@@ -266,8 +267,6 @@ static void plan_items(pufe_ctx *c) {
 int pufe_setup(pufe_ctx *ctx, void *stream) {
     if (!ctx) return PUFE_ERR_INVALID_ARG;
     if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "pufe_set_problem must come first");
-    if (ctx->prob.quad.mode != PUFE_QUAD_GEOM)
-        return fail(ctx, PUFE_ERR_UNSUPPORTED, "the device rule builder supports the geometric mode");
     hipStream_t st = (hipStream_t)stream;
     CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     Plan &pl = ctx->plan;
@@ -278,21 +277,61 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_leaf_off.alloc(nel + 1), "alloc leaf offsets");
     const double L[3] = {pl.lat[0], pl.lat[4], pl.lat[8]};
     const pufe_quad &q = ctx->prob.quad;
-    // count leaves, scan, emit (one octree walk per element, twice)
-    CHECK_HIP(ctx, launch_aq_geom(pl.kp, nel, ctx->d_pos.p, n_atoms, L, q.max_level, q.dist, ctx->d_leaf_count.p,
-                                  nullptr, nullptr, nullptr, st), "adaptive quadrature (count)");
-    CHECK_HIP(ctx, launch_scan(ctx->d_leaf_count.p, nel, ctx->d_leaf_off.p, st), "scan");
     ctx->leaf_off_h.assign(nel + 1, 0);
-    CHECK_HIP(ctx, hipMemcpyAsync(ctx->leaf_off_h.data(), ctx->d_leaf_off.p, sizeof(int64_t) * (nel + 1),
-                                  hipMemcpyDeviceToHost, st), "download leaf offsets");
-    CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
-    ctx->n_leaves = ctx->leaf_off_h[nel];
+    if (q.mode == PUFE_QUAD_GEOM) {
+        // count leaves, scan, emit (one octree walk per element, twice)
+        CHECK_HIP(ctx, launch_aq_geom(pl.kp, nel, ctx->d_pos.p, n_atoms, L, q.max_level, q.dist, ctx->d_leaf_count.p,
+                                      nullptr, nullptr, nullptr, st), "adaptive quadrature (count)");
+        CHECK_HIP(ctx, launch_scan(ctx->d_leaf_count.p, nel, ctx->d_leaf_off.p, st), "scan");
+        CHECK_HIP(ctx, hipMemcpyAsync(ctx->leaf_off_h.data(), ctx->d_leaf_off.p, sizeof(int64_t) * (nel + 1),
+                                      hipMemcpyDeviceToHost, st), "download leaf offsets");
+        CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
+        ctx->n_leaves = ctx->leaf_off_h[nel];
+        CHECK_HIP(ctx, ctx->d_leaves.alloc(ctx->n_leaves), "alloc leaves");
+        CHECK_HIP(ctx, ctx->d_leaf_elem.alloc(ctx->n_leaves), "alloc leaf elements");
+        CHECK_HIP(ctx, launch_aq_geom(pl.kp, nel, ctx->d_pos.p, n_atoms, L, q.max_level, q.dist, nullptr,
+                                      ctx->d_leaf_off.p, ctx->d_leaves.p, ctx->d_leaf_elem.p, st),
+                  "adaptive quadrature (emit)");
+    } else {
+        // error-driven rule: the element tables are needed first
+        DevBuf<ElemDev> elems;
+        CHECK_HIP(ctx, elems.upload(pl.elems, st), "upload elements");
+        CHECK_HIP(ctx, ctx->d_groups.upload(pl.groups, st), "upload groups");
+        CHECK_HIP(ctx, ctx->d_img.upload(pl.img_cur, st), "upload images");
+        DevBuf<CellDev> cur, next;
+        DevBuf<int64_t> cnt, off;
+        DevBuf<uint64_t> nmask;
+        CHECK_HIP(ctx, cur.alloc(nel), "alloc cells");
+        CHECK_HIP(ctx, launch_aq_error_init(nel, elems.p, cur.p, st), "rule roots");
+        int64_t n = nel;
+        for (int lev = 0; lev < q.max_level; ++lev) {
+            CHECK_HIP(ctx, cnt.alloc(n + 1), "alloc counts");
+            CHECK_HIP(ctx, off.alloc(n + 1), "alloc offsets");
+            CHECK_HIP(ctx, nmask.alloc(n + 1), "alloc masks");
+            CHECK_HIP(ctx, launch_aq_error_test(pl.kp, elems.p, ctx->d_groups.p, ctx->d_img.p, cur.p, n, q.max_level,
+                                                q.tol, cnt.p, nmask.p, st), "rule test");
+            CHECK_HIP(ctx, launch_scan(cnt.p, n, off.p, st), "scan");
+            int64_t total = 0;
+            CHECK_HIP(ctx, hipMemcpyAsync(&total, off.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st), "download");
+            CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
+            if (total == n) break;   // no cell split at this level
+            CHECK_HIP(ctx, next.alloc(total), "alloc cells");
+            CHECK_HIP(ctx, launch_aq_error_expand(n, cur.p, off.p, nmask.p, next.p, st), "rule expand");
+            std::swap(cur.p, next.p);
+            std::swap(cur.n, next.n);
+            n = total;
+        }
+        ctx->n_leaves = n;
+        CHECK_HIP(ctx, ctx->d_leaves.alloc(n), "alloc leaves");
+        CHECK_HIP(ctx, ctx->d_leaf_elem.alloc(n), "alloc leaf elements");
+        CHECK_HIP(ctx, launch_aq_error_finish(n, cur.p, ctx->d_leaves.p, ctx->d_leaf_elem.p, ctx->d_leaf_count.p, st),
+                  "rule leaves");
+        CHECK_HIP(ctx, launch_scan(ctx->d_leaf_count.p, nel, ctx->d_leaf_off.p, st), "scan");
+        CHECK_HIP(ctx, hipMemcpyAsync(ctx->leaf_off_h.data(), ctx->d_leaf_off.p, sizeof(int64_t) * (nel + 1),
+                                      hipMemcpyDeviceToHost, st), "download leaf offsets");
+        CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
+    }
     ctx->n_qp = ctx->n_leaves * pl.kp.n3;
-    CHECK_HIP(ctx, ctx->d_leaves.alloc(ctx->n_leaves), "alloc leaves");
-    CHECK_HIP(ctx, ctx->d_leaf_elem.alloc(ctx->n_leaves), "alloc leaf elements");
-    CHECK_HIP(ctx, launch_aq_geom(pl.kp, nel, ctx->d_pos.p, n_atoms, L, q.max_level, q.dist, nullptr,
-                                  ctx->d_leaf_off.p, ctx->d_leaves.p, ctx->d_leaf_elem.p, st),
-              "adaptive quadrature (emit)");
     for (int64_t e = 0; e < nel; ++e) {
         pl.elems[e].leaf_off = ctx->leaf_off_h[e];
         pl.elems[e].leaf_end = ctx->leaf_off_h[e + 1];
@@ -628,5 +667,209 @@ int pufe_kernel_times(pufe_ctx *ctx, double *out_ms, int64_t *counts, int reset)
     if (reset) ctx->clear_events();
     return PUFE_OK;
 }
+
+struct pufe_batch {
+    std::vector<pufe_ctx *> ctxs;
+    int device = 0;
+    std::vector<ItemDev> items;
+    std::vector<std::vector<int2>> lists;   // per colour: (problem, element)
+    size_t lds_f64 = 0, lds_split[2] = {0, 0};
+    int grid_f64 = 0, grid_split[2] = {0, 0};
+    DevBuf<CtxDev> d_ctxs;
+    DevBuf<ItemDev> d_items;
+    DevBuf<int2> d_lists;
+    std::vector<int64_t> list_off;
+    DevBuf<int> d_counter;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> key;
+    std::string err;
+    ~pufe_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+static int bfail(pufe_batch *b, int code, const std::string &msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+#define CHECK_HIP_B(b, x, where)                                                               \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess)                                                                  \
+            return bfail(b, e_ == hipErrorOutOfMemory ? PUFE_ERR_OOM : PUFE_ERR_HIP,            \
+                         std::string(where) + ": " + hipGetErrorString(e_));                   \
+    } while (0)
+
+static double item_cost(const ItemDev &it, int n3) {
+    const int pairs = it.I0 == it.J0 ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
+    return (double)pairs * (double)(it.leaf_e - it.leaf_b) * n3;
+}
+
+int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
+    if (!out || !ctxs || n < 1) return PUFE_ERR_INVALID_ARG;
+    pufe_batch *b = new (std::nothrow) pufe_batch();
+    if (!b) return PUFE_ERR_OOM;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || !ctxs[i]->have_setup || ctxs[i]->device != ctxs[0]->device) {
+            delete b;
+            return PUFE_ERR_STATE;
+        }
+        b->ctxs.push_back(ctxs[i]);
+    }
+    b->device = ctxs[0]->device;
+    if (hipSetDevice(b->device) != hipSuccess) { delete b; return PUFE_ERR_HIP; }
+    std::vector<std::pair<double, size_t>> order;
+    int max_rows = 16, max_nfun = 1;
+    b->lists.assign(27, {});
+    for (int i = 0; i < n; ++i) {
+        pufe_ctx *c = ctxs[i];
+        for (const ItemDev &it0 : c->items) {
+            ItemDev it = it0;
+            it.ctx = i;
+            order.push_back({item_cost(it, c->plan.kp.n3), b->items.size()});
+            b->items.push_back(it);
+        }
+        max_rows = std::max(max_rows, c->max_rows);
+        max_nfun = std::max(max_nfun, c->plan.max_nfun);
+        for (int64_t e = 0; e < c->plan.nel; ++e) b->lists[c->plan.elems[e].color].push_back(make_int2(i, (int)e));
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &c) { return a.first > c.first; });
+    std::vector<ItemDev> sorted;
+    for (auto &o : order) sorted.push_back(b->items[o.second]);
+    b->items.swap(sorted);
+    std::vector<int2> flat;
+    b->list_off.assign(1, 0);
+    for (auto &l : b->lists) {
+        flat.insert(flat.end(), l.begin(), l.end());
+        b->list_off.push_back((int64_t)flat.size());
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || ncu < 1) ncu = 256;
+    b->lds_f64 = contract_lds_bytes(max_rows, max_nfun);
+    b->grid_f64 = ncu * persistent_blocks_per_cu(b->lds_f64);
+    for (int k = 0; k < 2; ++k) {
+        b->lds_split[k] = split_lds_bytes(k + 2, max_rows, max_nfun);
+        b->grid_split[k] = ncu * persistent_blocks_per_cu(b->lds_split[k]);
+    }
+    hipStream_t st = nullptr;
+    if (b->d_items.upload(b->items, st) != hipSuccess || b->d_lists.upload(flat, st) != hipSuccess ||
+        b->d_counter.alloc(1) != hipSuccess || b->d_ctxs.alloc(n) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return PUFE_ERR_OOM;
+    }
+    *out = b;
+    return PUFE_OK;
+}
+
+int pufe_batch_destroy(pufe_batch *b) {
+    if (!b) return PUFE_ERR_INVALID_ARG;
+    (void)hipSetDevice(b->device);
+    delete b;
+    return PUFE_OK;
+}
+
+int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *kpts, int n_k, int precision,
+                        int out_dtype, void *const *d_H, void *const *d_S, void *stream) {
+    if (!b) return PUFE_ERR_INVALID_ARG;
+    const int n = (int)b->ctxs.size();
+    if (!d_V || !d_H || !kpts || n_k < 1 || n_k > kMaxKPerLaunch)
+        return bfail(b, PUFE_ERR_INVALID_ARG, "null pointer or n_k outside 1..16");
+    if (precision < PUFE_PREC_FP64 || precision > PUFE_PREC_BF16X6 || out_dtype < PUFE_OUT_C128 ||
+        out_dtype > PUFE_OUT_F64_GAMMA)
+        return bfail(b, PUFE_ERR_INVALID_ARG, "unknown precision or dtype");
+    for (int i = 0; i < n; ++i)
+        if (!d_V[i] || !d_H[i]) return bfail(b, PUFE_ERR_INVALID_ARG, "null V or H pointer");
+    for (int k = 0; k < 3 * n_k; ++k) {
+        if (!std::isfinite(kpts[k])) return bfail(b, PUFE_ERR_INVALID_ARG, "non-finite k-point");
+        if (out_dtype == PUFE_OUT_F64_GAMMA && std::fmod(kpts[k], 1.0) != 0.0)
+            return bfail(b, PUFE_ERR_INVALID_ARG, "real output needs Gamma");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP_B(b, hipSetDevice(b->device), "hipSetDevice");
+    std::vector<uintptr_t> key;
+    key.push_back((uintptr_t)precision);
+    key.push_back((uintptr_t)out_dtype);
+    key.push_back((uintptr_t)n_k);
+    for (int i = 0; i < n; ++i) {
+        key.push_back((uintptr_t)d_V[i]);
+        key.push_back((uintptr_t)d_H[i]);
+        key.push_back((uintptr_t)(d_S ? d_S[i] : nullptr));
+    }
+    for (int k = 0; k < 3 * n_k; ++k) {
+        uint64_t bits;
+        std::memcpy(&bits, &kpts[k], sizeof bits);
+        key.push_back((uintptr_t)bits);
+    }
+    if (!b->exec || key != b->key) {
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        std::vector<CtxDev> cd(n);
+        for (int i = 0; i < n; ++i) {
+            pufe_ctx *c = b->ctxs[i];
+            cd[i].kp = c->plan.kp;
+            cd[i].elems = c->d_elems.p;
+            cd[i].groups = c->d_groups.p;
+            cd[i].img = c->d_img.p;
+            cd[i].edof = c->d_edof.p;
+            cd[i].leaves = c->d_leaves.p;
+            cd[i].V = d_V[i];
+            cd[i].partial = c->d_partial.p;
+            cd[i].H = d_H[i];
+            cd[i].S = d_S ? d_S[i] : nullptr;
+            cd[i].nnz = c->plan.nnz;
+        }
+        CHECK_HIP_B(b, hipMemcpy(b->d_ctxs.p, cd.data(), sizeof(CtxDev) * n, hipMemcpyHostToDevice), "upload tables");
+        KPoints kps;
+        std::memset(&kps, 0, sizeof kps);
+        kps.nk = n_k;
+        for (int k = 0; k < n_k; ++k)
+            for (int d = 0; d < 3; ++d) kps.kap[k][d] = kpts[3 * k + d];
+        CHECK_HIP_B(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        hipError_t e = hipSuccess;
+        if (precision == PUFE_PREC_FP64)
+            e = launch_contract_persistent(b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
+                                           b->grid_f64, b->lds_f64, b->cap);
+        else {
+            const int k = precision == PUFE_PREC_BF16X3 ? 0 : 1;
+            if (b->lds_split[k] > 160 * 1024) e = hipErrorInvalidValue;
+            else
+                e = launch_split_persistent(k + 2, b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
+                                            b->grid_split[k], b->lds_split[k], b->cap);
+        }
+        const bool f32 = out_dtype == PUFE_OUT_C64;
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            const int64_t per = (out_dtype == PUFE_OUT_F64_GAMMA ? 1 : 2) * b->ctxs[i]->plan.nnz * n_k;
+            e = launch_fill_zero(d_H[i], per, f32, b->cap);
+            if (e == hipSuccess && d_S && d_S[i]) e = launch_fill_zero(d_S[i], per, f32, b->cap);
+        }
+        for (size_t col = 0; col + 1 < b->list_off.size() && e == hipSuccess; ++col) {
+            const int cnt = (int)(b->list_off[col + 1] - b->list_off[col]);
+            e = launch_scatter_batch(b->d_ctxs.p, b->d_lists.p + b->list_off[col], cnt, kps, out_dtype, b->cap);
+        }
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return bfail(b, PUFE_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+        }
+        CHECK_HIP_B(b, e2, "end capture");
+        b->graph = g;
+        CHECK_HIP_B(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate graph");
+        b->key = key;
+    }
+    CHECK_HIP_B(b, hipGraphLaunch(b->exec, st), "graph launch");
+    return PUFE_OK;
+}
+
+const char *pufe_batch_last_error_message(const pufe_batch *b) { return b ? b->err.c_str() : "no batch"; }
 
 }  // extern "C"

@@ -12,11 +12,10 @@ namespace pufe {
 // Psi_m = sum over images of g(s) S_m(r), grad Psi_m = 2 g'(s) r S_m + g grad S_m,
 // g(s) = exp(-a s) (1 - s/rc^2)^3, r = x - image centre, s = |r|^2 < rc^2.
 // Written to o[m * Q * 4 + (0: value, 1..3: gradient)].
-template <int L, int Q>
-__device__ __forceinline__ void group_eval(const GroupDev &G, const double *__restrict__ img, const double *x,
-                                           double *o) {
+template <int L>
+__device__ __forceinline__ void group_eval_point(const GroupDev &G, const double *__restrict__ img, const double *x,
+                                                 double *psi, double *gp) {
     constexpr int NM = 2 * L + 1;
-    double psi[NM], gp[3 * NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) psi[m] = gp[3 * m] = gp[3 * m + 1] = gp[3 * m + 2] = 0.0;
     const double rc2 = G.rc * G.rc, inv_rc2 = 1.0 / rc2;
@@ -28,7 +27,7 @@ __device__ __forceinline__ void group_eval(const GroupDev &G, const double *__re
         const double ex = exp(-G.a * s), c = 1.0 - s * inv_rc2, c2 = c * c;
         const double g0 = ex * c2 * c;
         const double g1 = -ex * c2 * (G.a * c + 3.0 * inv_rc2);
-        double S[NM > 7 ? NM : 7], dS[21];
+        double S[7], dS[21];
         solid_harmonics(L, rx, ry, rz, S, dS);
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
@@ -38,6 +37,14 @@ __device__ __forceinline__ void group_eval(const GroupDev &G, const double *__re
             gp[3 * m + 2] += 2.0 * g1 * rz * S[m] + g0 * dS[3 * m + 2];
         }
     }
+}
+
+template <int L, int Q>
+__device__ __forceinline__ void group_eval(const GroupDev &G, const double *__restrict__ img, const double *x,
+                                           double *o) {
+    constexpr int NM = 2 * L + 1;
+    double psi[NM], gp[3 * NM];
+    group_eval_point<L>(G, img, x, psi, gp);
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
         double *om = o + (size_t)m * Q * 4;

@@ -153,13 +153,11 @@ struct ContractLds {
 };
 
 template <int Q>
-__global__ __launch_bounds__(256) void contract_f64_kernel(
-    const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
+__device__ __forceinline__ void contract_f64_item(
+    const KParams &kp, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
-    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
-    extern __shared__ double smem[];
+    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial, double *smem) {
     constexpr int RS = ContractLds<Q>::RS;
-    const ItemDev it = items[blockIdx.x];
     const ElemDev &el = elems[it.elem];
     const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun;
     const bool diag = it.I0 == it.J0;
@@ -336,6 +334,42 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(
     }
 }
 
+// One work group per work item.
+template <int Q>
+__global__ __launch_bounds__(256) void contract_f64_kernel(
+    const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
+    const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
+    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
+    extern __shared__ double smem[];
+    const ItemDev it = items[blockIdx.x];
+    contract_f64_item<Q>(kp, it, elems, groups, img, edof, leaves, V, partial, smem);
+}
+
+// Persistent form: a fixed grid of work groups pulls items (of several
+// problems) from one queue, largest first; every item writes its own partial
+// slots, so the result does not depend on which group ran it.
+template <int Q>
+__global__ __launch_bounds__(256) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
+                                                               const ItemDev *__restrict__ items, int n_items,
+                                                               int *__restrict__ counter) {
+    extern __shared__ double smem[];
+    __shared__ int s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= n_items) break;
+        const ItemDev it = items[idx];
+        const CtxDev &c = ctxs[it.ctx];
+        contract_f64_item<Q>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem);
+    }
+}
+
+__global__ void reset_counter_kernel(int *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
 // -------------------------------------------------------------- scatter
 
 __global__ void fill_zero_kernel(double *__restrict__ p, int64_t n) {
@@ -354,15 +388,10 @@ __global__ void fill_zero_f32_kernel(float *__restrict__ p, int64_t n) {
 // every k-point add conj(p_a) p_b H_e[a][b] (and the mirrored entry) into the
 // BSR values.  Elements of one colour share no vertex, so no two work groups
 // of one launch touch the same entry.
-__global__ __launch_bounds__(256) void scatter_kernel(const KParams kp, const ElemDev *__restrict__ elems,
-                                                      const int32_t *__restrict__ color_elems,
-                                                      const int32_t *__restrict__ edof,
-                                                      const double *__restrict__ partial, const KPoints kps,
-                                                      int out_dtype, void *__restrict__ Hout,
-                                                      void *__restrict__ Sout, int64_t nnz) {
+__device__ __forceinline__ void scatter_elem(const KParams &kp, const ElemDev &el, const int32_t *__restrict__ edof,
+                                             const double *__restrict__ partial, const KPoints &kps, int out_dtype,
+                                             void *__restrict__ Hout, void *__restrict__ Sout, int64_t nnz) {
     __shared__ double zr[kMaxKPerLaunch][27], zi[kMaxKPerLaunch][27];
-    const int e = color_elems[blockIdx.x];
-    const ElemDev &el = elems[e];
     for (int idx = threadIdx.x; idx < kps.nk * 27; idx += blockDim.x) {
         int k = idx / 27, t = idx % 27;
         int dn[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
@@ -449,6 +478,25 @@ __global__ __launch_bounds__(256) void scatter_kernel(const KParams kp, const El
             }
         }
     }
+}
+
+__global__ __launch_bounds__(256) void scatter_kernel(const KParams kp, const ElemDev *__restrict__ elems,
+                                                      const int32_t *__restrict__ color_elems,
+                                                      const int32_t *__restrict__ edof,
+                                                      const double *__restrict__ partial, const KPoints kps,
+                                                      int out_dtype, void *__restrict__ Hout,
+                                                      void *__restrict__ Sout, int64_t nnz) {
+    scatter_elem(kp, elems[color_elems[blockIdx.x]], edof, partial, kps, out_dtype, Hout, Sout, nnz);
+}
+
+// Batched scatter of one colour: entries (problem, element) of several
+// problems, each into its own output.
+__global__ __launch_bounds__(256) void scatter_batch_kernel(const CtxDev *__restrict__ ctxs,
+                                                            const int2 *__restrict__ list, const KPoints kps,
+                                                            int out_dtype) {
+    const int2 ce = list[blockIdx.x];
+    const CtxDev &c = ctxs[ce.x];
+    scatter_elem(c.kp, c.elems[ce.y], c.edof, c.partial, kps, out_dtype, c.H, c.S, c.nnz);
 }
 
 // Element matrices of one element (full, mirrored), from its partials.
@@ -553,6 +601,35 @@ hipError_t launch_contract_f64(const KParams &kp, int n_items, const ItemDev *it
     if (n_items == 0) return hipSuccess;
     hipLaunchKernelGGL(contract_f64_kernel<kContractQ>, dim3(n_items), dim3(256), lds, st, kp, items, elems,
                        groups, img, edof, leaves, V, partial);
+    return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(size_t lds) {
+    int per = (int)((160 * 1024) / (lds > 0 ? lds : 1));
+    if (per > 2) per = 2;  // 256 VGPRs per lane: one 4-wave group per SIMD set, two if LDS allows
+    return per < 1 ? 1 : per;
+}
+
+hipError_t launch_contract_persistent(const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
+                                      int grid, size_t lds, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        PUFE_HIP(hipFuncSetAttribute((const void *)contract_f64_persistent<kContractQ>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
+    PUFE_HIP(hipGetLastError());
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(contract_f64_persistent<kContractQ>, dim3(grid), dim3(256), lds, st, ctxs, items, n_items,
+                       counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_batch(const CtxDev *ctxs, const int2 *list, int n, const KPoints &kps, int out_dtype,
+                                hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_batch_kernel, dim3(n), dim3(256), 0, st, ctxs, list, kps, out_dtype);
     return hipGetLastError();
 }
 

@@ -34,6 +34,13 @@ hipError_t launch_contract_split(int nlimb, const KParams &kp, int n_items, cons
                                  const GroupDev *groups, const double *img, const int32_t *edof,
                                  const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                  hipStream_t st);
+int persistent_blocks_per_cu(size_t lds);
+hipError_t launch_contract_persistent(const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
+                                      int grid, size_t lds, hipStream_t st);
+hipError_t launch_split_persistent(int nlimb, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
+                                   int grid, size_t lds, hipStream_t st);
+hipError_t launch_scatter_batch(const CtxDev *ctxs, const int2 *list, int n, const KPoints &kps, int out_dtype,
+                                hipStream_t st);
 hipError_t launch_fill_zero(void *p, int64_t n, bool f32, hipStream_t st);
 hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int32_t *color_elems, int n_elems,
                           const int32_t *edof, const double *partial, const KPoints &kps, int out_dtype,

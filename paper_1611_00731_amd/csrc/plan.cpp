@@ -319,34 +319,31 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     for (int d = 0; d < 3; ++d) kp.mesh[d] = mesh[d];
     // Gauss-Legendre nodes (ascending) and weights: Newton iteration on the
     // three-term Legendre recurrence from cosine initial guesses
-    int n = q.n_gauss;
-    for (int r = 0; r < n; ++r) {
-        double x = -std::cos(M_PI * (r + 0.75) / (n + 0.5));
-        double dp = 1;
-        for (int it = 0; it < 64; ++it) {
-            double p0 = 1, p1 = x;
-            for (int k = 1; k < n; ++k) {
-                double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
-                p0 = p1;
-                p1 = p2;
+    auto gauss = [](int n, double *gx, double *gw) {
+        for (int r = 0; r < n; ++r) {
+            double x = -std::cos(M_PI * (r + 0.75) / (n + 0.5));
+            double dp = 1;
+            for (int it = 0; it < 65; ++it) {
+                double p0 = 1, p1 = x;
+                for (int k = 1; k < n; ++k) {
+                    double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+                    p0 = p1;
+                    p1 = p2;
+                }
+                if (n == 1) { p0 = 1; p1 = x; }
+                dp = n * (p0 - x * p1) / (1 - x * x);
+                if (it == 64) break;
+                double dx = p1 / dp;
+                x -= dx;
+                if (std::fabs(dx) < 1e-16) it = 63;   // one more pass refreshes dp at the root
             }
-            if (n == 1) { p0 = 1; p1 = x; }
-            dp = n * (p0 - x * p1) / (1 - x * x);
-            double dx = p1 / dp;
-            x -= dx;
-            if (std::fabs(dx) < 1e-16) break;
+            gx[r] = x;
+            gw[r] = 2.0 / ((1 - x * x) * dp * dp);
         }
-        double p0 = 1, p1 = x;
-        for (int k = 1; k < n; ++k) {
-            double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
-            p0 = p1;
-            p1 = p2;
-        }
-        if (n == 1) { p0 = 1; p1 = x; }
-        dp = n * (p0 - x * p1) / (1 - x * x);
-        kp.gx[r] = x;
-        kp.gw[r] = 2.0 / ((1 - x * x) * dp * dp);
-    }
+    };
+    gauss(q.n_gauss, kp.gx, kp.gw);
+    kp.nref = q.mode == PUFE_QUAD_ERROR ? q.n_ref : 0;
+    if (kp.nref > 0) gauss(kp.nref, kp.rx, kp.rw);
     return PUFE_OK;
 }
 

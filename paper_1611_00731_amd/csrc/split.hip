@@ -45,14 +45,13 @@ struct SplitLds {
 };
 
 template <int NL, int Q>
-__global__ __launch_bounds__(256) void contract_split_kernel(
-    const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
+__device__ __forceinline__ void contract_split_item(
+    const KParams &kp, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
-    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
+    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial,
+    unsigned char *smem_raw) {
     static_assert(Q == 32, "one S product covers 32 points");
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     constexpr int RSB = SplitLds<Q>::RSB;
-    const ItemDev it = items[blockIdx.x];
     const ElemDev &el = elems[it.elem];
     const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun;
     const bool diag = it.I0 == it.J0;
@@ -257,6 +256,64 @@ __global__ __launch_bounds__(256) void contract_split_kernel(
             dst[256 + (i0 + r) * 16 + j] = accS[u][r];
         }
     }
+}
+
+template <int NL, int Q>
+__global__ __launch_bounds__(256) void contract_split_kernel(
+    const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
+    const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
+    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const ItemDev it = items[blockIdx.x];
+    contract_split_item<NL, Q>(kp, it, elems, groups, img, edof, leaves, V, partial, smem_raw);
+}
+
+// Persistent queue form (see contract_f64_persistent).
+template <int NL, int Q>
+__global__ __launch_bounds__(256) void contract_split_persistent(const CtxDev *__restrict__ ctxs,
+                                                                 const ItemDev *__restrict__ items, int n_items,
+                                                                 int *__restrict__ counter) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    __shared__ int s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= n_items) break;
+        const ItemDev it = items[idx];
+        const CtxDev &c = ctxs[it.ctx];
+        contract_split_item<NL, Q>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem_raw);
+    }
+}
+
+__global__ void reset_counter_split_kernel(int *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+hipError_t launch_split_persistent(int nlimb, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
+                                   int grid, size_t lds, hipStream_t st) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)contract_split_persistent<2, kSplitQ>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void *)contract_split_persistent<3, kSplitQ>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(reset_counter_split_kernel, dim3(1), dim3(64), 0, st, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (n_items == 0) return hipSuccess;
+    if (nlimb == 2)
+        hipLaunchKernelGGL((contract_split_persistent<2, kSplitQ>), dim3(grid), dim3(256), lds, st, ctxs, items,
+                           n_items, counter);
+    else
+        hipLaunchKernelGGL((contract_split_persistent<3, kSplitQ>), dim3(grid), dim3(256), lds, st, ctxs, items,
+                           n_items, counter);
+    return hipGetLastError();
 }
 
 size_t split_lds_bytes(int nlimb, int rows, int nfun) { return SplitLds<kSplitQ>::bytes(nlimb, rows, nfun); }

@@ -45,6 +45,7 @@ static inline __host__ __device__ int32_t edof_pack(int corner, int f, int slot)
 struct ItemDev {
     int32_t elem, I0, nI, J0, nJ, chunk;
     int64_t leaf_b, leaf_e;
+    int32_t ctx;         // problem of a batched launch (0 otherwise)
 };
 
 // Per-launch constants of the mesh and the rule.
@@ -52,9 +53,35 @@ struct KParams {
     double E[9];      // row d: a_d / n_d (element edge vector)
     double Jt[9];     // grad_x[c] = sum_d Jt[3c+d] dphi/dxi_d
     double jac;       // det of the reference-to-element map
-    double gx[kMaxGauss], gw[kMaxGauss];
-    int32_t n, n3, p, nfe, nfs;
+    double gx[kMaxGauss], gw[kMaxGauss];   // base rule (n points)
+    double rx[kMaxGauss], rw[kMaxGauss];   // reference rule of the error mode (nref points)
+    int32_t n, n3, p, nfe, nfs, nref;
     int32_t mesh[3];
+};
+
+// Tables and buffers of one problem, for launches that cover several problems
+// (one per lattice constant of a sweep).
+struct CtxDev {
+    KParams kp;
+    const ElemDev *elems;
+    const GroupDev *groups;
+    const double *img;
+    const int32_t *edof;
+    const uint32_t *leaves;
+    const double *V;
+    double *partial;
+    void *H, *S;
+    int64_t nnz;
+};
+
+// Octree cell of the error-driven rule builder: element, leaf code, and the
+// bit mask of the element's enrichment functions still tested on it.
+struct CellDev {
+    uint64_t mask;
+    int32_t elem;
+    uint32_t code;
+    int32_t open;   // 1 while the cell may still split
+    int32_t pad;
 };
 
 // Leaf code: level in bits 27..30, cell coordinates in 9-bit fields.

@@ -1,0 +1,104 @@
+"""The persistent, graph-captured batch over lattice constants and k-points
+against the oracle, and graph replays against each other."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1611_00731_amd as P  # noqa: E402
+from workloads.potential import potential_at  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_batch_small_sweep_vs_oracle():
+    base = W.small("lih", mesh=(2, 3, 2), fe_order=2, levels=1, n=3, a=5.0)
+    probs = [W.with_lattice_constant(base, a) for a in (4.6, 5.0, 5.4)]
+    kpts = W.mp2()[:3]
+    say("batch small sweep")
+    oracles, Vs, ps = [], [], []
+    for pr in probs:
+        o = oracle.Oracle(pr)
+        xyz, _, _ = o.quadrature()
+        oracles.append(o)
+        Vs.append(potential_at(torch.from_numpy(xyz).cuda(), pr))
+        ps.append(P.Problem(pr).setup())
+    b = P.Batch(ps)
+    Hs, Ss = b.alloc(len(kpts), device="cuda")
+    b.assemble(Vs, kpts, Hs, Ss)
+    torch.cuda.synchronize()
+    for i, (o, p) in enumerate(zip(oracles, ps)):
+        for k, kap in enumerate(kpts):
+            Ho, So = o.assemble_dense(Vs[i].cpu().numpy(), kap)
+            assert rel(p.to_dense(Hs[i][k]).cpu().numpy(), Ho) < 1e-12
+            assert rel(p.to_dense(Ss[i][k]).cpu().numpy(), So) < 1e-12
+    # replays with eager work in between stay identical
+    ref = [h.clone() for h in Hs]
+    for _ in range(3):
+        for h in Hs:
+            h.fill_(7.0)
+        torch.cuda.synchronize()
+        b.assemble(Vs, kpts, Hs, Ss)
+        torch.cuda.synchronize()
+        for h, r in zip(Hs, ref):
+            assert torch.equal(h, r)
+    # split precision through the same batch
+    b.assemble(Vs, kpts, Hs, Ss, precision="bf16x6")
+    torch.cuda.synchronize()
+    Ho, So = oracles[1].assemble_dense(Vs[1].cpu().numpy(), kpts[2])
+    assert rel(ps[1].to_dense(Hs[1][2]).cpu().numpy(), Ho) < 1e-7
+    b.close()
+    for p in ps:
+        p.close()
+
+
+def test_batch_cfg3_full_size_sampled():
+    """The 11 lattice constants x 8 k-points sweep (88 assemblies in one
+    persistent launch): sampled BSR blocks against the oracle."""
+    probs = W.cfg3()
+    kpts = W.mp2()
+    say("batch cfg3 full size")
+    ps, Vs, oracles, Vh = [], [], [], []
+    for pr in probs:
+        o = oracle.Oracle(pr)
+        xyz, _, _ = o.quadrature()
+        V = potential_at(torch.from_numpy(xyz).cuda(), pr)
+        oracles.append(o)
+        Vs.append(V)
+        Vh.append(V.cpu().numpy())
+        ps.append(P.Problem(pr).setup())
+    b = P.Batch(ps)
+    Hs, Ss = b.alloc(len(kpts), device="cuda")
+    b.assemble(Vs, kpts, Hs, Ss)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    for i in (0, 5, 10):
+        lay = ps[i].layout()
+        off = lay["dof_offset"]
+        for k in (0, 3, 7):
+            v = int(rng.integers(0, len(off) - 1))
+            kk = int(rng.integers(lay["brow_ptr"][v], lay["brow_ptr"][v + 1]))
+            w = int(lay["bcol"][kk])
+            Hb, Sb = oracles[i].assemble_block(Vh[i], kpts[k], v, w)
+            b0, b1 = lay["bval_offset"][kk], lay["bval_offset"][kk + 1]
+            shape = (off[v + 1] - off[v], off[w + 1] - off[w])
+            Hg = Hs[i][k, b0:b1].cpu().numpy()
+            Sg = Ss[i][k, b0:b1].cpu().numpy()
+            assert rel((Hg[:, 0] + 1j * Hg[:, 1]).reshape(shape), Hb) < 1e-12
+            assert rel((Sg[:, 0] + 1j * Sg[:, 1]).reshape(shape), Sb) < 1e-12
+    b.close()
+    for p in ps:
+        p.close()

@@ -49,7 +49,16 @@ def check_rule(p, o, xyz, w):
     assert np.abs(gw.cpu().numpy() - w).max() < 1e-15 * max(1.0, w.max()) * 10
 
 
+def _error_mode(prob, n=3, n_ref=6, levels=3, tol=1e-6):
+    prob["quad"] = {"n": n, "n_ref": n_ref, "levels": levels, "mode": "error", "dist": 0.0, "tol": tol}
+    return prob
+
+
 SMALL = {
+    "lih-error": (lambda: _error_mode(W.small("lih", mesh=(2, 2, 3), fe_order=2, a=4.8, re=1.6, rc=2.0)),
+                  [(0.0, 0.0, 0.0), (0.1, -0.2, 0.3)]),
+    "ceal-error": (lambda: _error_mode(W.small("ceal", mesh=(2, 2, 2), fe_order=1, a=4.4, rc=2.6, re=2.0),
+                                       n=2, n_ref=4, levels=2, tol=1e-5), [(0.0, 0.0, 0.0)]),
     "cfg1": (W.cfg1, [(0.0, 0.0, 0.0), (0.1, 0.2, -0.3)]),
     "lih-p2-l1": (lambda: W.small("lih", mesh=(3, 2, 2), fe_order=2, levels=1, n=3, a=5.0),
                   [(0.0, 0.0, 0.0), (0.12, -0.24, 0.37), (0.25, 0.25, -0.25)]),
