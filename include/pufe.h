@@ -200,6 +200,14 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
  * pufe_set_problem (PUFE_ERR_INVALID_ARG otherwise).  Synchronous. */
 int pufe_set_positions(pufe_ctx *ctx, const double *pos);
 
+/* Autotuner: time the contraction of this problem for candidate work-item
+ * granularities (number of K-chunk items) and tile-block sizes (2..4 tiles of
+ * 16 rows per work item side), keep the fastest and record it in the JSON
+ * file cache_path (keyed by GPU architecture, precision and problem
+ * signature; NULL = no cache).  A cached entry is applied without timing.
+ * Synchronous; re-plans the work items of ctx. */
+int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path);
+
 /* Batched assembly over several problems (for instance one per lattice
  * constant of an equation-of-state sweep), all set up on the same device.
  * pufe_batch_assemble runs, for every problem, the assembly of pufe_assemble

@@ -28,7 +28,7 @@ EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_
            "pufe_get_quadrature", "pufe_get_leaves", "pufe_assemble", "pufe_element_matrices",
            "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
            "pufe_kernel_times", "pufe_set_positions", "pufe_batch_create", "pufe_batch_assemble",
-           "pufe_batch_destroy", "pufe_batch_last_error_message"]
+           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune"]
 
 
 class PufeError(RuntimeError):
@@ -84,6 +84,7 @@ def _load():
                                  C.POINTER(vp), vp], C.c_int),
         "pufe_batch_destroy": ([vp], C.c_int),
         "pufe_batch_last_error_message": ([vp], C.c_char_p),
+        "pufe_tune": ([vp, C.c_int, C.c_char_p], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -224,6 +225,11 @@ def pufe_kernel_times(ctx, reset=True):
     cnt = (C.c_int64 * 4)()
     _check(ctx, lib.pufe_kernel_times(ctx, ms, cnt, 1 if reset else 0))
     return list(ms), list(cnt)
+
+
+def pufe_tune(ctx, precision="fp64", cache_path=None):
+    _check(ctx, lib.pufe_tune(ctx, PREC[precision] if isinstance(precision, str) else int(precision),
+                              None if cache_path is None else str(cache_path).encode()))
 
 
 def pufe_batch_create(ctxs):

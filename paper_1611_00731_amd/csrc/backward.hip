@@ -232,9 +232,10 @@ __global__ __launch_bounds__(256) void backward_kernel(
                         const double b = sB[(size_t)(4 * kb + k4) * RS + 16 * J + r16];
                         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                     }
-                    const int i0 = 16 * I + 4 * (lane >> 4);
+                    // FP64 16x16x4 accumulator: register r of lane l is row (l / 16) + 4 r
+                    const int i0 = 16 * I + (lane >> 4);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) sU[(size_t)(i0 + r) * RS + 16 * J + r16] = acc[r];
+                    for (int r = 0; r < 4; ++r) sU[(size_t)(i0 + 4 * r) * RS + 16 * J + r16] = acc[r];
                 }
             }
         }
@@ -324,6 +325,14 @@ __global__ void force_reduce_kernel(int n_atoms, const int64_t *__restrict__ ato
     for (int c = 0; c < 3; ++c) dLdR[3 * A + c] = f[c];
 }
 
+hipError_t init_backward_attributes() {
+    hipError_t e = hipFuncSetAttribute((const void *)backward_kernel<kBackwardQ, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)backward_kernel<kBackwardQ, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+}
+
 size_t backward_lds_bytes(int npad, int nfun) { return BackwardLds<kBackwardQ>::bytes(npad, nfun); }
 
 hipError_t launch_gather_adjoint(const KParams &kp, int64_t nel, const ElemDev *elems, const int32_t *edof,
@@ -338,16 +347,6 @@ hipError_t launch_backward(const KParams &kp, bool qmode, int n_items, const Ite
                            const GroupDev *groups, const double *img, const int32_t *edof, const uint32_t *leaves,
                            const double *V, const int64_t *pt_off, const double *Pt, double *dLdV, double *fpart,
                            int max_ngrp, size_t lds, hipStream_t st) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)backward_kernel<kBackwardQ, false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)backward_kernel<kBackwardQ, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
     if (n_items == 0) return hipSuccess;
     if (qmode)
         hipLaunchKernelGGL((backward_kernel<kBackwardQ, true>), dim3(n_items), dim3(256), lds, st, kp, items, elems,

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -58,17 +59,19 @@ struct pufe_ctx {
     Plan plan;
     int64_t n_leaves = 0, n_qp = 0;
     std::vector<int64_t> leaf_off_h;
-    std::vector<ItemDev> items;
+    std::vector<ItemDev> items, items_split;
     size_t lds = 0;
-    int max_rows = 16;
+    int max_rows = 16, max_rows_split = 16;
     int64_t part_slots = 0;
+    double tune_items = 4096.0;
+    int tune_block = kBlockTiles;
     DevBuf<ElemDev> d_elems;
     DevBuf<GroupDev> d_groups;
     DevBuf<double> d_img, d_pos, d_partial;
     DevBuf<int32_t> d_edof, d_leaf_elem, d_color_elems, d_brow, d_bcol;
     DevBuf<uint32_t> d_leaves;
     DevBuf<int64_t> d_leaf_count, d_leaf_off, d_bval_off, d_dof_off;
-    DevBuf<ItemDev> d_items;
+    DevBuf<ItemDev> d_items, d_items_split;
     // adjoint
     bool have_bw = false;
     std::vector<ItemDev> bw_items;
@@ -192,76 +195,85 @@ int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], 
     return PUFE_OK;
 }
 
-// Split each element's contraction into work items (row block x column block
-// of 16x16 tiles x range of leaves) of roughly equal MFMA work, largest first.
-static void plan_items(pufe_ctx *c) {
+// Split each element's contraction into K-chunks (ranges of leaves) of about
+// equal MFMA work; the chunking fixes the layout of the partial tiles and does
+// not depend on how the tile pairs of a chunk are grouped into work items.
+static void plan_chunks(pufe_ctx *c, double target_items) {
     Plan &pl = c->plan;
     const int n3 = pl.kp.n3;
-    struct Bp { int I0, nI, J0, nJ, pairs; };
     double total = 0;
-    std::vector<std::vector<Bp>> bps(pl.nel);
-    for (int64_t e = 0; e < pl.nel; ++e) {
-        ElemDev &el = pl.elems[e];
-        int T = (el.nloc + 15) / 16, nb = (T + kBlockTiles - 1) / kBlockTiles;
-        for (int bj = 0; bj < nb; ++bj)
-            for (int bi = 0; bi <= bj; ++bi) {
-                Bp b;
-                b.I0 = bi * kBlockTiles;
-                b.nI = std::min(kBlockTiles, T - b.I0);
-                b.J0 = bj * kBlockTiles;
-                b.nJ = std::min(kBlockTiles, T - b.J0);
-                b.pairs = bi == bj ? b.nI * (b.nI + 1) / 2 : b.nI * b.nJ;
-                bps[e].push_back(b);
-                total += (double)b.pairs * n3 * (el.leaf_end - el.leaf_off);
-            }
+    for (const ElemDev &el : pl.elems) {
+        const int T = (el.nloc + 15) / 16;
+        total += (double)T * (T + 1) / 2 * n3 * (el.leaf_end - el.leaf_off);
     }
-    double target = std::max(total / 4096.0, 1.0);
-    c->items.clear();
+    const double target = std::max(total / target_items, 1.0);
     int64_t base = 0;
-    std::vector<double> cost;
-    for (int64_t e = 0; e < pl.nel; ++e) {
-        ElemDev &el = pl.elems[e];
-        int64_t nleaf = el.leaf_end - el.leaf_off;
-        int maxp = 1;
-        for (auto &b : bps[e]) maxp = std::max(maxp, b.pairs);
-        int64_t nch = (int64_t)std::llround((double)nleaf * n3 * maxp / target);
+    for (ElemDev &el : pl.elems) {
+        const int T = (el.nloc + 15) / 16;
+        const int64_t P = (int64_t)T * (T + 1) / 2, nleaf = el.leaf_end - el.leaf_off;
+        int64_t nch = (int64_t)std::llround((double)nleaf * n3 * P / target);
         nch = std::max<int64_t>(1, std::min<int64_t>(nch, nleaf));
         el.nchunk = (int32_t)nch;
-        int T = (el.nloc + 15) / 16;
         el.part_base = base;
-        base += nch * (int64_t)T * (T + 1) / 2;
-        for (int64_t ch = 0; ch < nch; ++ch) {
-            int64_t lb = el.leaf_off + ch * nleaf / nch, le = el.leaf_off + (ch + 1) * nleaf / nch;
-            for (auto &b : bps[e]) {
-                ItemDev it{};
-                it.elem = (int32_t)e;
-                it.I0 = b.I0;
-                it.nI = b.nI;
-                it.J0 = b.J0;
-                it.nJ = b.nJ;
-                it.chunk = (int32_t)ch;
-                it.leaf_b = lb;
-                it.leaf_e = le;
-                c->items.push_back(it);
-                cost.push_back((double)b.pairs * (le - lb));
-            }
-        }
+        base += nch * P;
     }
     c->part_slots = base;
-    std::vector<size_t> order(c->items.size());
+}
+
+// Work items (row block x column block of 16x16 tiles x K-chunk), largest
+// MFMA work first.
+static std::vector<ItemDev> make_items(const pufe_ctx *c, int block_tiles, int *max_rows) {
+    const Plan &pl = c->plan;
+    std::vector<ItemDev> items;
+    std::vector<double> cost;
+    for (int64_t e = 0; e < pl.nel; ++e) {
+        const ElemDev &el = pl.elems[e];
+        const int T = (el.nloc + 15) / 16, nb = (T + block_tiles - 1) / block_tiles;
+        const int64_t nleaf = el.leaf_end - el.leaf_off, nch = el.nchunk;
+        for (int64_t ch = 0; ch < nch; ++ch) {
+            const int64_t lb = el.leaf_off + ch * nleaf / nch, le = el.leaf_off + (ch + 1) * nleaf / nch;
+            for (int bj = 0; bj < nb; ++bj)
+                for (int bi = 0; bi <= bj; ++bi) {
+                    ItemDev it{};
+                    it.elem = (int32_t)e;
+                    it.I0 = bi * block_tiles;
+                    it.nI = std::min(block_tiles, T - it.I0);
+                    it.J0 = bj * block_tiles;
+                    it.nJ = std::min(block_tiles, T - it.J0);
+                    it.chunk = (int32_t)ch;
+                    it.leaf_b = lb;
+                    it.leaf_e = le;
+                    const int pairs = bi == bj ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
+                    items.push_back(it);
+                    cost.push_back((double)pairs * (le - lb));
+                }
+        }
+    }
+    std::vector<size_t> order(items.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
     std::vector<ItemDev> sorted;
     sorted.reserve(order.size());
-    int max_rows = 16;
+    int rows = 16;
     for (size_t i : order) {
-        sorted.push_back(c->items[i]);
-        const ItemDev &it = c->items[i];
-        max_rows = std::max(max_rows, 16 * (it.I0 == it.J0 ? it.nI : it.nI + it.nJ));
+        sorted.push_back(items[i]);
+        rows = std::max(rows, 16 * (items[i].I0 == items[i].J0 ? items[i].nI : items[i].nI + items[i].nJ));
     }
-    c->items.swap(sorted);
-    c->max_rows = max_rows;
-    c->lds = contract_lds_bytes(max_rows, std::max(pl.max_nfun, 1));
+    *max_rows = rows;
+    return sorted;
+}
+
+static void plan_items(pufe_ctx *c, double target_items, int block_tiles) {
+    plan_chunks(c, target_items);
+    const int nfun = std::max(c->plan.max_nfun, 1);
+    c->items = make_items(c, block_tiles, &c->max_rows);
+    c->lds = contract_lds_bytes(c->max_rows, nfun);
+    // the split stage keeps bf16 limbs of every row: use the largest tile
+    // block whose three-limb stage fits in LDS
+    for (int b = block_tiles; b >= 1; --b) {
+        c->items_split = make_items(c, b, &c->max_rows_split);
+        if (split_lds_bytes(3, c->max_rows_split, nfun) <= kMaxDynLds) break;
+    }
 }
 
 int pufe_setup(pufe_ctx *ctx, void *stream) {
@@ -269,6 +281,15 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "pufe_set_problem must come first");
     hipStream_t st = (hipStream_t)stream;
     CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    {
+        hipError_t ea = init_contract_attributes();
+        if (ea == hipSuccess) ea = init_split_attributes();
+        if (ea == hipSuccess) ea = init_backward_attributes();
+        if (ea != hipSuccess) {
+            (void)hipGetLastError();   // do not leave the error for the caller's next HIP call
+            return hipfail(ctx, ea, "kernel attributes");
+        }
+    }
     Plan &pl = ctx->plan;
     const int64_t nel = pl.nel;
     const int n_atoms = (int)ctx->prob.species.size();
@@ -336,14 +357,15 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
         pl.elems[e].leaf_off = ctx->leaf_off_h[e];
         pl.elems[e].leaf_end = ctx->leaf_off_h[e + 1];
     }
-    plan_items(ctx);
-    if (ctx->lds > 160 * 1024)
+    plan_items(ctx, ctx->tune_items, ctx->tune_block);
+    if (ctx->lds > kMaxDynLds)
         return fail(ctx, PUFE_ERR_UNSUPPORTED, "contraction stage does not fit in LDS");
     CHECK_HIP(ctx, ctx->d_elems.upload(pl.elems, st), "upload elements");
     CHECK_HIP(ctx, ctx->d_groups.upload(pl.groups, st), "upload groups");
     CHECK_HIP(ctx, ctx->d_img.upload(pl.img_cur, st), "upload images");
     CHECK_HIP(ctx, ctx->d_edof.upload(pl.edof, st), "upload enriched functions");
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
+    CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_color_elems.upload(pl.color_elems, st), "upload colours");
     CHECK_HIP(ctx, ctx->d_brow.upload(pl.brow, st), "upload layout");
     CHECK_HIP(ctx, ctx->d_bcol.upload(pl.bcol, st), "upload layout");
@@ -425,10 +447,10 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
     const Plan &pl = ctx->plan;
     if (precision == PUFE_PREC_BF16X3 || precision == PUFE_PREC_BF16X6) {
         const int nl = precision == PUFE_PREC_BF16X3 ? 2 : 3;
-        const size_t lds = split_lds_bytes(nl, ctx->max_rows, std::max(pl.max_nfun, 1));
-        if (lds > 160 * 1024) return fail(ctx, PUFE_ERR_UNSUPPORTED, "split stage does not fit in LDS");
+        const size_t lds = split_lds_bytes(nl, ctx->max_rows_split, std::max(pl.max_nfun, 1));
+        if (lds > kMaxDynLds) return fail(ctx, PUFE_ERR_UNSUPPORTED, "split stage does not fit in LDS");
         TimedRegion tr(ctx, 0, st);
-        CHECK_HIP(ctx, launch_contract_split(nl, pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p,
+        CHECK_HIP(ctx, launch_contract_split(nl, pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p, ctx->d_elems.p,
                                              ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V,
                                              ctx->d_partial.p, lds, st),
                   "split contraction");
@@ -521,7 +543,7 @@ static int plan_backward(pufe_ctx *c, hipStream_t st) {
         pt_off[e + 1] = pt_off[e] + (int64_t)npad * npad;
     }
     c->bw_lds = backward_lds_bytes(max_npad, max_nfun);
-    if (c->bw_lds > 160 * 1024) return fail(c, PUFE_ERR_UNSUPPORTED, "adjoint stage does not fit in LDS");
+    if (c->bw_lds > kMaxDynLds) return fail(c, PUFE_ERR_UNSUPPORTED, "adjoint stage does not fit in LDS");
     c->bw_items.clear();
     const int mg = std::max(pl.max_ngrp, 1);
     std::vector<std::vector<int64_t>> slots(c->prob.species.size());
@@ -668,15 +690,123 @@ int pufe_kernel_times(pufe_ctx *ctx, double *out_ms, int64_t *counts, int reset)
     return PUFE_OK;
 }
 
+// Upload the element table, work items and partial buffer of the current plan.
+static int upload_items(pufe_ctx *ctx, hipStream_t st) {
+    CHECK_HIP(ctx, ctx->d_elems.upload(ctx->plan.elems, st), "upload elements");
+    CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
+    CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
+    CHECK_HIP(ctx, ctx->d_partial.alloc((size_t)ctx->part_slots * 512), "alloc partial tiles");
+    ctx->have_bw = false;
+    return PUFE_OK;
+}
+
+int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    if (precision < PUFE_PREC_FP64 || precision > PUFE_PREC_BF16X6)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "unknown precision");
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const Plan &pl = ctx->plan;
+    int64_t sum_nloc = 0;
+    for (const ElemDev &el : pl.elems) sum_nloc += el.nloc;
+    char key[256];
+    hipDeviceProp_t prop;
+    CHECK_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device), "device properties");
+    std::snprintf(key, sizeof key, "%s|prec%d|nel%lld|leaves%lld|n3_%d|nloc%lld|maxnloc%d", prop.gcnArchName, precision,
+                  (long long)pl.nel, (long long)ctx->n_leaves, pl.kp.n3, (long long)sum_nloc, pl.max_nloc);
+    // cached choice?
+    std::string text;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "rb")) {
+            char buf[4096];
+            size_t r;
+            while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, r);
+            std::fclose(f);
+        }
+        std::string pat = std::string("\"") + key + "\": {\"items\": ";
+        size_t at = text.find(pat);
+        if (at != std::string::npos) {
+            double items = 0;
+            int block = 0;
+            if (std::sscanf(text.c_str() + at + pat.size(), "%lf, \"block\": %d", &items, &block) == 2 && items > 0 &&
+                block >= 1 && block <= kBlockTiles) {
+                ctx->tune_items = items;
+                ctx->tune_block = block;
+                plan_items(ctx, items, block);
+                return upload_items(ctx, nullptr);
+            }
+        }
+    }
+    DevBuf<double> V;
+    CHECK_HIP(ctx, V.alloc(std::max<int64_t>(ctx->n_qp, 1)), "alloc timing input");
+    CHECK_HIP(ctx, hipMemset(V.p, 0, sizeof(double) * V.n), "zero timing input");
+    hipEvent_t a, b;
+    CHECK_HIP(ctx, hipEventCreate(&a), "event");
+    CHECK_HIP(ctx, hipEventCreate(&b), "event");
+    double best = 1e300, best_items = ctx->tune_items;
+    int best_block = ctx->tune_block;
+    const double cand_items[] = {1024, 2048, 4096, 8192, 16384};
+    const bool saved = ctx->timing;
+    ctx->timing = false;
+    for (int block = 2; block <= kBlockTiles; ++block)
+        for (double items : cand_items) {
+            plan_items(ctx, items, block);
+            if (ctx->lds > kMaxDynLds) continue;
+            int rc = upload_items(ctx, nullptr);
+            if (rc != PUFE_OK) break;
+            rc = run_contraction(ctx, V.p, precision, nullptr);   // warm-up
+            if (rc != PUFE_OK) break;
+            CHECK_HIP(ctx, hipEventRecord(a, nullptr), "event");
+            for (int r = 0; r < 3; ++r) run_contraction(ctx, V.p, precision, nullptr);
+            CHECK_HIP(ctx, hipEventRecord(b, nullptr), "event");
+            CHECK_HIP(ctx, hipEventSynchronize(b), "event");
+            float ms = 0;
+            CHECK_HIP(ctx, hipEventElapsedTime(&ms, a, b), "event");
+            if (ms < best) {
+                best = ms;
+                best_items = items;
+                best_block = block;
+            }
+        }
+    ctx->timing = saved;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    ctx->tune_items = best_items;
+    ctx->tune_block = best_block;
+    plan_items(ctx, best_items, best_block);
+    int rc = upload_items(ctx, nullptr);
+    if (rc != PUFE_OK) return rc;
+    if (cache_path) {
+        // append or insert the entry into a flat JSON object
+        char entry[512];
+        std::snprintf(entry, sizeof entry, "\"%s\": {\"items\": %.0f, \"block\": %d, \"ms\": %.4f}", key, best_items,
+                      best_block, best / 3.0);
+        size_t close = text.rfind('}');
+        std::string out;
+        if (close == std::string::npos || text.find('{') == std::string::npos)
+            out = std::string("{\n  ") + entry + "\n}\n";
+        else {
+            std::string head = text.substr(0, close);
+            while (!head.empty() && (head.back() == '\n' || head.back() == ' ')) head.pop_back();
+            out = head + (head.back() == '{' ? "\n  " : ",\n  ") + entry + "\n}\n";
+        }
+        if (FILE *f = std::fopen(cache_path, "wb")) {
+            std::fwrite(out.data(), 1, out.size(), f);
+            std::fclose(f);
+        }
+    }
+    return PUFE_OK;
+}
+
 struct pufe_batch {
     std::vector<pufe_ctx *> ctxs;
     int device = 0;
-    std::vector<ItemDev> items;
+    std::vector<ItemDev> items, items_split;
     std::vector<std::vector<int2>> lists;   // per colour: (problem, element)
     size_t lds_f64 = 0, lds_split[2] = {0, 0};
     int grid_f64 = 0, grid_split[2] = {0, 0};
     DevBuf<CtxDev> d_ctxs;
-    DevBuf<ItemDev> d_items;
+    DevBuf<ItemDev> d_items, d_items_split;
     DevBuf<int2> d_lists;
     std::vector<int64_t> list_off;
     DevBuf<int> d_counter;
@@ -723,26 +853,32 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     b->device = ctxs[0]->device;
     if (hipSetDevice(b->device) != hipSuccess) { delete b; return PUFE_ERR_HIP; }
-    std::vector<std::pair<double, size_t>> order;
-    int max_rows = 16, max_nfun = 1;
+    int max_rows = 16, max_rows_split = 16, max_nfun = 1;
     b->lists.assign(27, {});
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<std::pair<double, size_t>> order;
+        std::vector<ItemDev> all;
+        for (int i = 0; i < n; ++i) {
+            pufe_ctx *c = ctxs[i];
+            for (const ItemDev &it0 : pass == 0 ? c->items : c->items_split) {
+                ItemDev it = it0;
+                it.ctx = i;
+                order.push_back({item_cost(it, c->plan.kp.n3), all.size()});
+                all.push_back(it);
+            }
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &c) { return a.first > c.first; });
+        std::vector<ItemDev> &dst = pass == 0 ? b->items : b->items_split;
+        for (auto &o : order) dst.push_back(all[o.second]);
+    }
     for (int i = 0; i < n; ++i) {
         pufe_ctx *c = ctxs[i];
-        for (const ItemDev &it0 : c->items) {
-            ItemDev it = it0;
-            it.ctx = i;
-            order.push_back({item_cost(it, c->plan.kp.n3), b->items.size()});
-            b->items.push_back(it);
-        }
         max_rows = std::max(max_rows, c->max_rows);
+        max_rows_split = std::max(max_rows_split, c->max_rows_split);
         max_nfun = std::max(max_nfun, c->plan.max_nfun);
         for (int64_t e = 0; e < c->plan.nel; ++e) b->lists[c->plan.elems[e].color].push_back(make_int2(i, (int)e));
     }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &c) { return a.first > c.first; });
-    std::vector<ItemDev> sorted;
-    for (auto &o : order) sorted.push_back(b->items[o.second]);
-    b->items.swap(sorted);
     std::vector<int2> flat;
     b->list_off.assign(1, 0);
     for (auto &l : b->lists) {
@@ -754,11 +890,12 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     b->lds_f64 = contract_lds_bytes(max_rows, max_nfun);
     b->grid_f64 = ncu * persistent_blocks_per_cu(b->lds_f64);
     for (int k = 0; k < 2; ++k) {
-        b->lds_split[k] = split_lds_bytes(k + 2, max_rows, max_nfun);
+        b->lds_split[k] = split_lds_bytes(k + 2, max_rows_split, max_nfun);
         b->grid_split[k] = ncu * persistent_blocks_per_cu(b->lds_split[k]);
     }
     hipStream_t st = nullptr;
-    if (b->d_items.upload(b->items, st) != hipSuccess || b->d_lists.upload(flat, st) != hipSuccess ||
+    if (b->d_items.upload(b->items, st) != hipSuccess || b->d_items_split.upload(b->items_split, st) != hipSuccess ||
+        b->d_lists.upload(flat, st) != hipSuccess ||
         b->d_counter.alloc(1) != hipSuccess || b->d_ctxs.alloc(n) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
         delete b;
@@ -840,9 +977,9 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
                                            b->grid_f64, b->lds_f64, b->cap);
         else {
             const int k = precision == PUFE_PREC_BF16X3 ? 0 : 1;
-            if (b->lds_split[k] > 160 * 1024) e = hipErrorInvalidValue;
+            if (b->lds_split[k] > kMaxDynLds) e = hipErrorInvalidValue;
             else
-                e = launch_split_persistent(k + 2, b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
+                e = launch_split_persistent(k + 2, b->d_ctxs.p, b->d_items_split.p, (int)b->items_split.size(), b->d_counter.p,
                                             b->grid_split[k], b->lds_split[k], b->cap);
         }
         const bool f32 = out_dtype == PUFE_OUT_C64;

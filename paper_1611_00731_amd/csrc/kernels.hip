@@ -317,7 +317,8 @@ __device__ __forceinline__ void contract_f64_item(
         }
         __syncthreads();
     }
-    // ---- partial tiles, row-major 16x16; D layout: lane holds rows 4(lane/16)+i, column lane%16
+    // ---- partial tiles, row-major 16x16.  FP64 16x16x4 accumulator layout:
+    // register r of lane l holds D[(l / 16) + 4 r][l % 16].
     const int T = (nloc + 15) / 16;
     const int64_t P = (int64_t)T * (T + 1) / 2;
 #pragma unroll
@@ -325,11 +326,11 @@ __device__ __forceinline__ void contract_f64_item(
         if (pr_row[u] < 0) continue;
         const int64_t pidx = (int64_t)pr_J[u] * (pr_J[u] + 1) / 2 + pr_I[u];
         double *dst = partial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
-        const int j = lane & 15, i0 = 4 * (lane >> 4);
+        const int j = lane & 15, i0 = lane >> 4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            dst[(i0 + r) * 16 + j] = accH[u][r];
-            dst[256 + (i0 + r) * 16 + j] = accS[u][r];
+            dst[(i0 + 4 * r) * 16 + j] = accH[u][r];
+            dst[256 + (i0 + 4 * r) * 16 + j] = accS[u][r];
         }
     }
 }
@@ -592,32 +593,30 @@ hipError_t launch_contract_f64(const KParams &kp, int n_items, const ItemDev *it
                                const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        PUFE_HIP(hipFuncSetAttribute((const void *)contract_f64_kernel<kContractQ>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_set = true;
-    }
     if (n_items == 0) return hipSuccess;
     hipLaunchKernelGGL(contract_f64_kernel<kContractQ>, dim3(n_items), dim3(256), lds, st, kp, items, elems,
                        groups, img, edof, leaves, V, partial);
     return hipGetLastError();
 }
 
+// Dynamic LDS above the default limit must be enabled per kernel before any
+// launch (and before any graph capture).
+hipError_t init_contract_attributes() {
+    PUFE_HIP(hipFuncSetAttribute((const void *)contract_f64_kernel<kContractQ>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
+    PUFE_HIP(hipFuncSetAttribute((const void *)contract_f64_persistent<kContractQ>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
+    return hipSuccess;
+}
+
 int persistent_blocks_per_cu(size_t lds) {
-    int per = (int)((160 * 1024) / (lds > 0 ? lds : 1));
+    int per = (int)(kMaxDynLds / (lds > 0 ? lds : 1));
     if (per > 2) per = 2;  // 256 VGPRs per lane: one 4-wave group per SIMD set, two if LDS allows
     return per < 1 ? 1 : per;
 }
 
 hipError_t launch_contract_persistent(const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                       int grid, size_t lds, hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        PUFE_HIP(hipFuncSetAttribute((const void *)contract_f64_persistent<kContractQ>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_set = true;
-    }
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
     PUFE_HIP(hipGetLastError());
     if (n_items == 0) return hipSuccess;

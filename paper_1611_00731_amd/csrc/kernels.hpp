@@ -24,6 +24,8 @@ hipError_t launch_qp_export(const KParams &kp, int64_t n_leaves, const uint32_t 
                             double *xyz, double *w, hipStream_t st);
 hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *leaf_off, int64_t *qp_off,
                                  hipStream_t st);
+hipError_t init_contract_attributes();
+hipError_t init_split_attributes();
 size_t contract_lds_bytes(int rows, int nfun);
 hipError_t launch_contract_f64(const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
                                const GroupDev *groups, const double *img, const int32_t *edof,

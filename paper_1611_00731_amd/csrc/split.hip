@@ -293,16 +293,6 @@ __global__ void reset_counter_split_kernel(int *counter) {
 
 hipError_t launch_split_persistent(int nlimb, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                    int grid, size_t lds, hipStream_t st) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)contract_split_persistent<2, kSplitQ>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)contract_split_persistent<3, kSplitQ>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
     hipLaunchKernelGGL(reset_counter_split_kernel, dim3(1), dim3(64), 0, st, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -316,22 +306,23 @@ hipError_t launch_split_persistent(int nlimb, const CtxDev *ctxs, const ItemDev 
     return hipGetLastError();
 }
 
+hipError_t init_split_attributes() {
+    const void *ks[4] = {(const void *)contract_split_kernel<2, kSplitQ>, (const void *)contract_split_kernel<3, kSplitQ>,
+                         (const void *)contract_split_persistent<2, kSplitQ>,
+                         (const void *)contract_split_persistent<3, kSplitQ>};
+    for (const void *k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 size_t split_lds_bytes(int nlimb, int rows, int nfun) { return SplitLds<kSplitQ>::bytes(nlimb, rows, nfun); }
 
 hipError_t launch_contract_split(int nlimb, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
                                  const GroupDev *groups, const double *img, const int32_t *edof,
                                  const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                  hipStream_t st) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)contract_split_kernel<2, kSplitQ>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)contract_split_kernel<3, kSplitQ>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
     if (n_items == 0) return hipSuccess;
     if (nlimb == 2)
         hipLaunchKernelGGL((contract_split_kernel<2, kSplitQ>), dim3(n_items), dim3(256), lds, st, kp, items, elems,

@@ -102,3 +102,31 @@ def test_batch_cfg3_full_size_sampled():
     b.close()
     for p in ps:
         p.close()
+
+
+def test_autotuner_cache_and_parity(tmp_path):
+    prob = W.small("lih", mesh=(3, 2, 2), fe_order=2, levels=1, n=3, a=5.0)
+    say("autotuner")
+    o = oracle.Oracle(prob)
+    xyz, _, _ = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    cache = tmp_path / "tune.json"
+    p = P.Problem(prob).setup()
+    P.pufe_tune(p.ctx, "fp64", str(cache))
+    import json
+    entries = json.loads(cache.read_text())
+    assert len(entries) == 1
+    (k, v), = entries.items()
+    assert "gfx950" in k and v["block"] in (2, 3, 4) and v["items"] > 0
+    kap = (0.12, -0.24, 0.37)
+    H, S = p.assemble(V, [kap])
+    Ho, So = o.assemble_dense(V.cpu().numpy(), kap)
+    assert rel(p.to_dense(H[0]).cpu().numpy(), Ho) < 1e-12
+    # a second context reads the cached choice
+    p2 = P.Problem(prob).setup()
+    P.pufe_tune(p2.ctx, "fp64", str(cache))
+    assert json.loads(cache.read_text()) == entries
+    H2, _ = p2.assemble(V, [kap])
+    assert torch.equal(H2, H)
+    p.close()
+    p2.close()

@@ -80,16 +80,16 @@ def test_split_cfg2_full_size_eigenvalues():
     Ho, So = o.assemble_dense(V.cpu().numpy())
     Ho, So = Ho.real, So.real
     say("oracle assembled")
-    Hd = torch.from_numpy(Ho).cuda().to(torch.complex128)
-    Sd = torch.from_numpy(So).cuda().to(torch.complex128)
-    ev_o = P.eig(Hd, Sd, 16).cpu().numpy()   # dense FP64 solve of the oracle's matrices
+    Hd = torch.from_numpy(Ho).cuda()
+    Sd = torch.from_numpy(So).cuda()
+    ev_o = P.eig(Hd, Sd, 16).cpu().numpy()   # dense FP64 solve of the oracle's (real, Gamma) matrices
     say("oracle eigenvalues", ev_o[:4])
     p = P.Problem(prob).setup()
     for prec, tol_m in (("bf16x6", 1e-7), ("bf16x3", 5e-6)):
         H, S = p.assemble(V, precision=prec)
-        Hg, Sg = p.to_dense(H[0]), p.to_dense(S[0])
-        eh = rel(Hg.real.cpu().numpy(), Ho)
-        es = rel(Sg.real.cpu().numpy(), So)
+        Hg, Sg = p.to_dense(H[0]).real.contiguous(), p.to_dense(S[0]).real.contiguous()
+        eh = rel(Hg.cpu().numpy(), Ho)
+        es = rel(Sg.cpu().numpy(), So)
         ev = P.eig(Hg, Sg, 16).cpu().numpy()
         de = np.abs(ev - ev_o).max()
         say(prec, "H", eh, "S", es, "eig", de)
