@@ -69,6 +69,8 @@ struct pufe_ctx {
     DevBuf<GroupDev> d_groups;
     DevBuf<double> d_img, d_pos, d_partial;
     DevBuf<int32_t> d_edof, d_leaf_elem, d_color_elems, d_brow, d_bcol;
+    DevBuf<int2> d_scat;
+    DevBuf<double2> d_ztab;
     DevBuf<uint32_t> d_leaves;
     DevBuf<int64_t> d_leaf_count, d_leaf_off, d_bval_off, d_dof_off;
     DevBuf<ItemDev> d_items, d_items_split;
@@ -367,6 +369,8 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_color_elems.upload(pl.color_elems, st), "upload colours");
+    CHECK_HIP(ctx, ctx->d_scat.upload(pl.scat, st), "upload scatter list");
+    CHECK_HIP(ctx, ctx->d_ztab.alloc(kMaxKPerLaunch * 27), "alloc phase table");
     CHECK_HIP(ctx, ctx->d_brow.upload(pl.brow, st), "upload layout");
     CHECK_HIP(ctx, ctx->d_bcol.upload(pl.bcol, st), "upload layout");
     CHECK_HIP(ctx, ctx->d_bval_off.upload(pl.bval_off, st), "upload layout");
@@ -457,7 +461,7 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
         return PUFE_OK;
     }
     TimedRegion tr(ctx, 0, st);
-    CHECK_HIP(ctx, launch_contract_f64(pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p, ctx->d_groups.p,
+    CHECK_HIP(ctx, launch_contract_f64(pl.max_l, pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p, ctx->d_groups.p,
                                        ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_partial.p, ctx->lds, st),
               "contraction");
     return PUFE_OK;
@@ -499,10 +503,11 @@ int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k,
             for (int d = 0; d < 3; ++d) kps.kap[k][d] = kpts[3 * (k0 + k) + d];
         char *H = (char *)d_H + (size_t)k0 * per * esz;
         char *S = d_S ? (char *)d_S + (size_t)k0 * per * esz : nullptr;
-        for (size_t col = 0; col + 1 < pl.color_off.size(); ++col) {
-            int n = pl.color_off[col + 1] - pl.color_off[col];
-            CHECK_HIP(ctx, launch_scatter(pl.kp, ctx->d_elems.p, ctx->d_color_elems.p + pl.color_off[col], n,
-                                          ctx->d_edof.p, ctx->d_partial.p, kps, out_dtype, H, S, pl.nnz, st),
+        CHECK_HIP(ctx, launch_phase_table(kps, ctx->d_ztab.p, st), "phase table");
+        for (size_t col = 0; col + 1 < pl.scat_off.size(); ++col) {
+            const int n = (int)(pl.scat_off[col + 1] - pl.scat_off[col]);
+            CHECK_HIP(ctx, launch_scatter(pl.kp, ctx->d_elems.p, ctx->d_scat.p + pl.scat_off[col], n, ctx->d_edof.p,
+                                          ctx->d_partial.p, ctx->d_ztab.p, kps.nk, out_dtype, H, S, pl.nnz, st),
                       "scatter");
         }
     }
@@ -802,12 +807,14 @@ struct pufe_batch {
     std::vector<pufe_ctx *> ctxs;
     int device = 0;
     std::vector<ItemDev> items, items_split;
-    std::vector<std::vector<int2>> lists;   // per colour: (problem, element)
+    std::vector<std::vector<int4>> lists;   // per colour: (problem, element, tile pair)
     size_t lds_f64 = 0, lds_split[2] = {0, 0};
+    int max_l = 0;
     int grid_f64 = 0, grid_split[2] = {0, 0};
     DevBuf<CtxDev> d_ctxs;
     DevBuf<ItemDev> d_items, d_items_split;
-    DevBuf<int2> d_lists;
+    DevBuf<int4> d_lists;
+    DevBuf<double2> d_ztab;
     std::vector<int64_t> list_off;
     DevBuf<int> d_counter;
     hipStream_t cap = nullptr;
@@ -877,9 +884,14 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         max_rows = std::max(max_rows, c->max_rows);
         max_rows_split = std::max(max_rows_split, c->max_rows_split);
         max_nfun = std::max(max_nfun, c->plan.max_nfun);
-        for (int64_t e = 0; e < c->plan.nel; ++e) b->lists[c->plan.elems[e].color].push_back(make_int2(i, (int)e));
+        b->max_l = std::max(b->max_l, c->plan.max_l);
+        for (int64_t e = 0; e < c->plan.nel; ++e) {
+            const int T = (c->plan.elems[e].nloc + 15) / 16;
+            for (int pp = 0; pp < T * (T + 1) / 2; ++pp)
+                b->lists[c->plan.elems[e].color].push_back(make_int4(i, (int)e, pp, 0));
+        }
     }
-    std::vector<int2> flat;
+    std::vector<int4> flat;
     b->list_off.assign(1, 0);
     for (auto &l : b->lists) {
         flat.insert(flat.end(), l.begin(), l.end());
@@ -897,6 +909,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     if (b->d_items.upload(b->items, st) != hipSuccess || b->d_items_split.upload(b->items_split, st) != hipSuccess ||
         b->d_lists.upload(flat, st) != hipSuccess ||
         b->d_counter.alloc(1) != hipSuccess || b->d_ctxs.alloc(n) != hipSuccess ||
+        b->d_ztab.alloc(kMaxKPerLaunch * 27) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
         delete b;
         return PUFE_ERR_OOM;
@@ -973,7 +986,7 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
         CHECK_HIP_B(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
         hipError_t e = hipSuccess;
         if (precision == PUFE_PREC_FP64)
-            e = launch_contract_persistent(b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
+            e = launch_contract_persistent(b->max_l, b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
                                            b->grid_f64, b->lds_f64, b->cap);
         else {
             const int k = precision == PUFE_PREC_BF16X3 ? 0 : 1;
@@ -988,9 +1001,11 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
             e = launch_fill_zero(d_H[i], per, f32, b->cap);
             if (e == hipSuccess && d_S && d_S[i]) e = launch_fill_zero(d_S[i], per, f32, b->cap);
         }
+        if (e == hipSuccess) e = launch_phase_table(kps, b->d_ztab.p, b->cap);
         for (size_t col = 0; col + 1 < b->list_off.size() && e == hipSuccess; ++col) {
             const int cnt = (int)(b->list_off[col + 1] - b->list_off[col]);
-            e = launch_scatter_batch(b->d_ctxs.p, b->d_lists.p + b->list_off[col], cnt, kps, out_dtype, b->cap);
+            e = launch_scatter_batch(b->d_ctxs.p, b->d_lists.p + b->list_off[col], cnt, b->d_ztab.p, n_k, out_dtype,
+                                     b->cap);
         }
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->cap, &g);

@@ -143,16 +143,30 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 // Work-group shape and LDS map of the fused contraction kernel.
 //   sB[row][q][4]   (grad_x, grad_y, grad_z, value) of the item's local rows
 //   sPsi[f][q][4]   (value, gradient) of the element's enrichment functions
-//   per-qp:  xi[3], x[3], w, w V, valid, 1D Lagrange values/derivatives
+//   per-qp:  xi[3], x[3], w, w V, 1D Lagrange values/derivatives
+//   the element's enriched-function table and (atom, descriptor) groups
 template <int Q>
 struct ContractLds {
     static constexpr int RS = Q * 4 + 2;  // padded row stride of sB (doubles)
     static __host__ __device__ size_t bytes(int rows, int nfun) {
-        return sizeof(double) * ((size_t)rows * RS + (size_t)nfun * Q * 4 + (size_t)Q * 26);
+        return sizeof(double) * ((size_t)rows * RS + (size_t)nfun * Q * 4 + (size_t)Q * 26) +
+               sizeof(int32_t) * kMaxNloc + sizeof(GroupDev) * kMaxGroups;
     }
 };
 
-template <int Q>
+// Enrichment functions of one group at one stage point, for groups up to LMAX.
+template <int LMAX, int Q>
+__device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double *__restrict__ img, const double *x,
+                                                double *o) {
+    switch (G.l) {
+        case 0: group_eval<0, Q>(G, img, x, o); break;
+        case 1: if (LMAX >= 1) group_eval<1, Q>(G, img, x, o); break;
+        case 2: if (LMAX >= 2) group_eval<2, Q>(G, img, x, o); break;
+        default: if (LMAX >= 3) group_eval<3, Q>(G, img, x, o); break;
+    }
+}
+
+template <int Q, int LMAX>
 __device__ __forceinline__ void contract_f64_item(
     const KParams &kp, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
@@ -171,19 +185,24 @@ __device__ __forceinline__ void contract_f64_item(
     double *sWV = sQ + 7 * Q;     // [Q]
     double *sL = sQ + 8 * Q;      // [Q][3][3]  1D FE values
     double *sD = sQ + 17 * Q;     // [Q][3][3]  1D FE derivatives
+    int32_t *sEd = (int32_t *)(sQ + 26 * Q);
+    GroupDev *sG = (GroupDev *)(sEd + kMaxNloc);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n3 = kp.n3;
     const int64_t q_begin = it.leaf_b * n3, q_end = it.leaf_e * n3;
     const int ti0 = it.I0, tj0 = it.J0;
+    for (int k = tid; k < nloc - nfe; k += 256) sEd[k] = edof[el.edof_off + k];
+    for (int g = tid; g < ngrp; g += 256) sG[g] = groups[el.grp_off + g];
 
-    // tile pairs of this item, four per wave at most
+    // tile pairs of this item, round-robin over the four waves
     const int npairs = diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
+    const int nu = npairs > wave ? (npairs - wave + 3) / 4 : 0;   // pairs of this wave (uniform)
     int pr_row[4], pr_col[4], pr_I[4], pr_J[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        int pidx = wave + 4 * u;
-        pr_row[u] = pr_col[u] = pr_I[u] = pr_J[u] = -1;
-        if (pidx < npairs) {
+        const int pidx = wave + 4 * u;
+        pr_row[u] = pr_col[u] = pr_I[u] = pr_J[u] = 0;
+        if (u < nu) {
             int a, b;
             if (diag) {  // enumerate (a <= b) column by column
                 b = 0;
@@ -212,14 +231,15 @@ __device__ __forceinline__ void contract_f64_item(
     const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
                            el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
                            el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
+    const int r16 = lane & 15, k4 = lane >> 4;
 
     for (int64_t qb = q_begin; qb < q_end; qb += Q) {
         // ---- per-point geometry
         if (tid < Q) {
-            int64_t qg = qb + tid;
+            const int64_t qg = qb + tid;
             double xi[3] = {0.0, 0.0, 0.0}, w = 0.0, wv = 0.0;
             if (qg < q_end) {
-                int64_t lf = qg / n3;
+                const int64_t lf = qg / n3;
                 leaf_point(kp, leaves[lf], (int)(qg - lf * n3), xi, &w);
                 wv = w * V[qg];
             }
@@ -235,14 +255,8 @@ __device__ __forceinline__ void contract_f64_item(
         // ---- enrichment functions: periodic image sums (eq. Psi, f(R) = 1)
         for (int idx = tid; idx < ngrp * Q; idx += 256) {
             const int g = idx / Q, q = idx - g * Q;
-            const GroupDev G = groups[el.grp_off + g];
-            double *o = sPsi + ((size_t)G.fbase * Q + q) * 4;
-            switch (G.l) {
-                case 0: group_eval<0, Q>(G, img, sX + 3 * q, o); break;
-                case 1: group_eval<1, Q>(G, img, sX + 3 * q, o); break;
-                case 2: group_eval<2, Q>(G, img, sX + 3 * q, o); break;
-                default: group_eval<3, Q>(G, img, sX + 3 * q, o); break;
-            }
+            const GroupDev &G = sG[g];
+            group_eval_upto<LMAX, Q>(G, img, sX + 3 * q, sPsi + ((size_t)G.fbase * Q + q) * 4);
         }
         __syncthreads();
         // ---- local basis rows: FE functions and PU x enrichment (eq. pufebasis)
@@ -254,18 +268,21 @@ __device__ __forceinline__ void contract_f64_item(
                 o[0] = o[1] = o[2] = o[3] = 0.0;
                 continue;
             }
-            const double *L = sL + 9 * q, *D = sD + 9 * q;
-            double val, dxi[3];
+            double dxi[3], val;
             if (a < nfe) {
-                int n1 = kp.p + 1;
-                int a1 = a % n1, a2 = (a / n1) % n1, a3 = a / (n1 * n1);
-                double l1 = L[a1], l2 = L[3 + a2], l3 = L[6 + a3];
+                const double *L = sL + 9 * q, *D = sD + 9 * q;
+                const int n1 = kp.p + 1;
+                const int a1 = a % n1, a2 = (a / n1) % n1, a3 = a / (n1 * n1);
+                const double l1 = L[a1], l2 = L[3 + a2], l3 = L[6 + a3];
                 val = l1 * l2 * l3;
                 dxi[0] = D[a1] * l2 * l3;
                 dxi[1] = l1 * D[3 + a2] * l3;
                 dxi[2] = l1 * l2 * D[6 + a3];
+                for (int cc = 0; cc < 3; ++cc)
+                    o[cc] = kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2];
+                o[3] = val;
             } else {
-                const int pk = edof[el.edof_off + (a - nfe)];
+                const int pk = sEd[a - nfe];
                 const int c = pk & 7, f = (pk >> 3) & 255;
                 double m[3], dm[3];
                 for (int d = 0; d < 3; ++d) {
@@ -276,43 +293,41 @@ __device__ __forceinline__ void contract_f64_item(
                 }
                 const double M = m[0] * m[1] * m[2];
                 const double dM[3] = {dm[0] * m[1] * m[2], m[0] * dm[1] * m[2], m[0] * m[1] * dm[2]};
-                double gM[3];
-                for (int cc = 0; cc < 3; ++cc)
-                    gM[cc] = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
                 const double *ps = sPsi + ((size_t)f * Q + q) * 4;
-                o[0] = gM[0] * ps[0] + M * ps[1];
-                o[1] = gM[1] * ps[0] + M * ps[2];
-                o[2] = gM[2] * ps[0] + M * ps[3];
+                for (int cc = 0; cc < 3; ++cc) {
+                    const double gM = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
+                    o[cc] = gM * ps[0] + M * ps[1 + cc];
+                }
                 o[3] = M * ps[0];
-                continue;
             }
-            for (int cc = 0; cc < 3; ++cc)
-                o[cc] = kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2];
-            o[3] = val;
         }
         __syncthreads();
         // ---- MFMA: D[i][j] += sum_k A[i][k] B[k][j]; lane = i + 16 k for A,
         // lane = j + 16 k for B.  S: k runs over 4 points of the value row;
         // H: k runs over the (grad_x, grad_y, grad_z, value) components of one
-        // point with weights (w/2, w/2, w/2, w V).
-        const int r16 = lane & 15, k4 = lane >> 4;
+        // point with weights (w/2, w/2, w/2, w V).  The wave's tile pairs are
+        // independent accumulators, interleaved so consecutive MFMAs do not
+        // wait on each other.
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (pr_row[u] < 0) continue;
-            const double *rowA = sB + (size_t)(pr_row[u] + r16) * RS;
-            const double *rowB = sB + (size_t)(pr_col[u] + r16) * RS;
+        for (int s4 = 0; s4 < Q / 4; ++s4) {
+            const int qs = 4 * s4 + k4;
+            const double ws = sW[qs];
 #pragma unroll
-            for (int s4 = 0; s4 < Q / 4; ++s4) {
-                const int qs = 4 * s4 + k4;
-                accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowA[4 * qs + 3] * sW[qs], rowB[4 * qs + 3],
-                                                               accS[u], 0, 0, 0);
+            for (int u = 0; u < 4; ++u)
+                if (u < nu)
+                    accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        sB[(size_t)(pr_row[u] + r16) * RS + 4 * qs + 3] * ws,
+                        sB[(size_t)(pr_col[u] + r16) * RS + 4 * qs + 3], accS[u], 0, 0, 0);
 #pragma unroll
-                for (int qq = 0; qq < 4; ++qq) {
-                    const int q = 4 * s4 + qq;
-                    const double wf = k4 < 3 ? 0.5 * sW[q] : sWV[q];
-                    accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowA[4 * q + k4] * wf, rowB[4 * q + k4],
-                                                                   accH[u], 0, 0, 0);
-                }
+            for (int qq = 0; qq < 4; ++qq) {
+                const int q = 4 * s4 + qq;
+                const double wf = k4 < 3 ? 0.5 * sW[q] : sWV[q];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u < nu)
+                        accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            sB[(size_t)(pr_row[u] + r16) * RS + 4 * q + k4] * wf,
+                            sB[(size_t)(pr_col[u] + r16) * RS + 4 * q + k4], accH[u], 0, 0, 0);
             }
         }
         __syncthreads();
@@ -323,7 +338,7 @@ __device__ __forceinline__ void contract_f64_item(
     const int64_t P = (int64_t)T * (T + 1) / 2;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        if (pr_row[u] < 0) continue;
+        if (u >= nu) continue;
         const int64_t pidx = (int64_t)pr_J[u] * (pr_J[u] + 1) / 2 + pr_I[u];
         double *dst = partial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
         const int j = lane & 15, i0 = lane >> 4;
@@ -336,20 +351,20 @@ __device__ __forceinline__ void contract_f64_item(
 }
 
 // One work group per work item.
-template <int Q>
+template <int Q, int LMAX>
 __global__ __launch_bounds__(256) void contract_f64_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
     extern __shared__ double smem[];
     const ItemDev it = items[blockIdx.x];
-    contract_f64_item<Q>(kp, it, elems, groups, img, edof, leaves, V, partial, smem);
+    contract_f64_item<Q, LMAX>(kp, it, elems, groups, img, edof, leaves, V, partial, smem);
 }
 
 // Persistent form: a fixed grid of work groups pulls items (of several
 // problems) from one queue, largest first; every item writes its own partial
 // slots, so the result does not depend on which group ran it.
-template <int Q>
+template <int Q, int LMAX>
 __global__ __launch_bounds__(256) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
                                                                const ItemDev *__restrict__ items, int n_items,
                                                                int *__restrict__ counter) {
@@ -363,7 +378,7 @@ __global__ __launch_bounds__(256) void contract_f64_persistent(const CtxDev *__r
         if (idx >= n_items) break;
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
-        contract_f64_item<Q>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem);
+        contract_f64_item<Q, LMAX>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem);
     }
 }
 
@@ -385,119 +400,122 @@ __global__ void fill_zero_f32_kernel(float *__restrict__ p, int64_t n) {
     for (; i < n; i += stride) p[i] = 0.0f;
 }
 
-// Element e of colour c: sum its K-chunk partials in a fixed order, then for
-// every k-point add conj(p_a) p_b H_e[a][b] (and the mirrored entry) into the
-// BSR values.  Elements of one colour share no vertex, so no two work groups
-// of one launch touch the same entry.
-__device__ __forceinline__ void scatter_elem(const KParams &kp, const ElemDev &el, const int32_t *__restrict__ edof,
-                                             const double *__restrict__ partial, const KPoints &kps, int out_dtype,
+// Phase table z[k][t] = exp(2 pi i kappa_k . dn), dn = (t % 3, t / 3 % 3, t / 9) - 1:
+// the factor conj(p_a) p_b of a local pair whose corners differ by the
+// lattice shift dn (the Bloch phase factors at the cell boundary).
+__global__ void phase_table_kernel(const KPoints kps, double2 *__restrict__ z) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kps.nk * 27) return;
+    const int k = idx / 27, t = idx % 27;
+    const int dn[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+    double sn, cs;
+    sincos(2.0 * M_PI * (kps.kap[k][0] * dn[0] + kps.kap[k][1] * dn[1] + kps.kap[k][2] * dn[2]), &sn, &cs);
+    z[idx] = make_double2(cs, sn);
+}
+
+// One upper tile pair (I, J) of one element: each thread owns one entry
+// (a, b), a <= b, sums its K-chunk partials in chunk order, and for every
+// k-point adds conj(p_a) p_b H_e[a][b] at (g_a, g_b) and the conjugate at
+// (g_b, g_a).  The elements of one launch share no vertex (one colour), so
+// no two threads of a launch touch the same entry.
+__device__ __forceinline__ void scatter_tile(const KParams &kp, const ElemDev &el, int pidx,
+                                             const int32_t *__restrict__ edof, const double *__restrict__ partial,
+                                             const double2 *__restrict__ z, int nk, int out_dtype,
                                              void *__restrict__ Hout, void *__restrict__ Sout, int64_t nnz) {
-    __shared__ double zr[kMaxKPerLaunch][27], zi[kMaxKPerLaunch][27];
-    for (int idx = threadIdx.x; idx < kps.nk * 27; idx += blockDim.x) {
-        int k = idx / 27, t = idx % 27;
-        int dn[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
-        double ph = 2.0 * M_PI * (kps.kap[k][0] * dn[0] + kps.kap[k][1] * dn[1] + kps.kap[k][2] * dn[2]);
-        double sn, cs;
-        sincos(ph, &sn, &cs);
-        zr[k][t] = cs;
-        zi[k][t] = sn;
-    }
-    __syncthreads();
     const int nloc = el.nloc;
+    int J = 0;
+    while ((J + 1) * (J + 2) / 2 <= pidx) ++J;
+    const int I = pidx - J * (J + 1) / 2;
+    const int i = (int)(threadIdx.x >> 4), j = (int)(threadIdx.x & 15);
+    const int a = 16 * I + i, b = 16 * J + j;
+    if (a >= nloc || b >= nloc || a > b) return;
     const int T = (nloc + 15) / 16;
     const int64_t P = (int64_t)T * (T + 1) / 2;
-    const int64_t total = P * 256;
-    for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int64_t pidx = idx >> 8;
-        const int i = (int)((idx >> 4) & 15), j = (int)(idx & 15);
-        int J = 0;
-        while ((int64_t)(J + 1) * (J + 2) / 2 <= pidx) ++J;
-        const int I = (int)(pidx - (int64_t)J * (J + 1) / 2);
-        const int a = 16 * I + i, b = 16 * J + j;
-        if (a >= nloc || b >= nloc || a > b) continue;
-        double h = 0.0, s = 0.0;
-        for (int c = 0; c < el.nchunk; ++c) {
-            const double *src = partial + (el.part_base + (int64_t)c * P + pidx) * 512;
-            h += src[i * 16 + j];
-            s += src[256 + i * 16 + j];
-        }
-        int ca, sa, cb, sb;
-        local_slot(el, edof, kp.p, a, &ca, &sa);
-        local_slot(el, edof, kp.p, b, &cb, &sb);
-        const int64_t oab = el.blk[ca * 8 + cb] + (int64_t)sa * el.bw[cb] + sb;
-        const int64_t oba = el.blk[cb * 8 + ca] + (int64_t)sb * el.bw[ca] + sa;
-        int t = 0;
-        for (int d = 2; d >= 0; --d) {
-            int dn = ((el.shifts >> (3 * cb + d)) & 1) - ((el.shifts >> (3 * ca + d)) & 1);
-            t = 3 * t + (dn + 1);
-        }
-        for (int k = 0; k < kps.nk; ++k) {
-            const double cr = zr[k][t], ci = zi[k][t];
-            if (out_dtype == 0) {
-                double *H = (double *)Hout + 2 * (int64_t)k * nnz;
-                H[2 * oab] += cr * h;
-                H[2 * oab + 1] += ci * h;
+    double h = 0.0, s = 0.0;
+    for (int c = 0; c < el.nchunk; ++c) {
+        const double *src = partial + (el.part_base + (int64_t)c * P + pidx) * 512;
+        h += src[i * 16 + j];
+        s += src[256 + i * 16 + j];
+    }
+    int ca, sa, cb, sb;
+    local_slot(el, edof, kp.p, a, &ca, &sa);
+    local_slot(el, edof, kp.p, b, &cb, &sb);
+    const int64_t oab = el.blk[ca * 8 + cb] + (int64_t)sa * el.bw[cb] + sb;
+    const int64_t oba = el.blk[cb * 8 + ca] + (int64_t)sb * el.bw[ca] + sa;
+    int t = 0;
+    for (int d = 2; d >= 0; --d) {
+        const int dn = ((el.shifts >> (3 * cb + d)) & 1) - ((el.shifts >> (3 * ca + d)) & 1);
+        t = 3 * t + (dn + 1);
+    }
+    for (int k = 0; k < nk; ++k) {
+        const double2 zz = z[k * 27 + t];
+        const double cr = zz.x, ci = zz.y;
+        if (out_dtype == 0) {
+            double *H = (double *)Hout + 2 * (int64_t)k * nnz;
+            H[2 * oab] += cr * h;
+            H[2 * oab + 1] += ci * h;
+            if (a != b) {
+                H[2 * oba] += cr * h;
+                H[2 * oba + 1] -= ci * h;
+            }
+            if (Sout) {
+                double *S = (double *)Sout + 2 * (int64_t)k * nnz;
+                S[2 * oab] += cr * s;
+                S[2 * oab + 1] += ci * s;
                 if (a != b) {
-                    H[2 * oba] += cr * h;
-                    H[2 * oba + 1] -= ci * h;
+                    S[2 * oba] += cr * s;
+                    S[2 * oba + 1] -= ci * s;
                 }
-                if (Sout) {
-                    double *S = (double *)Sout + 2 * (int64_t)k * nnz;
-                    S[2 * oab] += cr * s;
-                    S[2 * oab + 1] += ci * s;
-                    if (a != b) {
-                        S[2 * oba] += cr * s;
-                        S[2 * oba + 1] -= ci * s;
-                    }
-                }
-            } else if (out_dtype == 1) {
-                float *H = (float *)Hout + 2 * (int64_t)k * nnz;
-                H[2 * oab] += (float)(cr * h);
-                H[2 * oab + 1] += (float)(ci * h);
+            }
+        } else if (out_dtype == 1) {
+            float *H = (float *)Hout + 2 * (int64_t)k * nnz;
+            H[2 * oab] += (float)(cr * h);
+            H[2 * oab + 1] += (float)(ci * h);
+            if (a != b) {
+                H[2 * oba] += (float)(cr * h);
+                H[2 * oba + 1] -= (float)(ci * h);
+            }
+            if (Sout) {
+                float *S = (float *)Sout + 2 * (int64_t)k * nnz;
+                S[2 * oab] += (float)(cr * s);
+                S[2 * oab + 1] += (float)(ci * s);
                 if (a != b) {
-                    H[2 * oba] += (float)(cr * h);
-                    H[2 * oba + 1] -= (float)(ci * h);
+                    S[2 * oba] += (float)(cr * s);
+                    S[2 * oba + 1] -= (float)(ci * s);
                 }
-                if (Sout) {
-                    float *S = (float *)Sout + 2 * (int64_t)k * nnz;
-                    S[2 * oab] += (float)(cr * s);
-                    S[2 * oab + 1] += (float)(ci * s);
-                    if (a != b) {
-                        S[2 * oba] += (float)(cr * s);
-                        S[2 * oba + 1] -= (float)(ci * s);
-                    }
-                }
-            } else {
-                double *H = (double *)Hout + (int64_t)k * nnz;
-                H[oab] += h;
-                if (a != b) H[oba] += h;
-                if (Sout) {
-                    double *S = (double *)Sout + (int64_t)k * nnz;
-                    S[oab] += s;
-                    if (a != b) S[oba] += s;
-                }
+            }
+        } else {
+            double *H = (double *)Hout + (int64_t)k * nnz;
+            H[oab] += h;
+            if (a != b) H[oba] += h;
+            if (Sout) {
+                double *S = (double *)Sout + (int64_t)k * nnz;
+                S[oab] += s;
+                if (a != b) S[oba] += s;
             }
         }
     }
 }
 
 __global__ __launch_bounds__(256) void scatter_kernel(const KParams kp, const ElemDev *__restrict__ elems,
-                                                      const int32_t *__restrict__ color_elems,
+                                                      const int2 *__restrict__ list,
                                                       const int32_t *__restrict__ edof,
-                                                      const double *__restrict__ partial, const KPoints kps,
-                                                      int out_dtype, void *__restrict__ Hout,
-                                                      void *__restrict__ Sout, int64_t nnz) {
-    scatter_elem(kp, elems[color_elems[blockIdx.x]], edof, partial, kps, out_dtype, Hout, Sout, nnz);
+                                                      const double *__restrict__ partial,
+                                                      const double2 *__restrict__ z, int nk, int out_dtype,
+                                                      void *__restrict__ Hout, void *__restrict__ Sout, int64_t nnz) {
+    const int2 ep = list[blockIdx.x];
+    scatter_tile(kp, elems[ep.x], ep.y, edof, partial, z, nk, out_dtype, Hout, Sout, nnz);
 }
 
-// Batched scatter of one colour: entries (problem, element) of several
+// Batched scatter of one colour: (problem, element, tile pair) of several
 // problems, each into its own output.
 __global__ __launch_bounds__(256) void scatter_batch_kernel(const CtxDev *__restrict__ ctxs,
-                                                            const int2 *__restrict__ list, const KPoints kps,
+                                                            const int4 *__restrict__ list,
+                                                            const double2 *__restrict__ z, int nk,
                                                             int out_dtype) {
-    const int2 ce = list[blockIdx.x];
+    const int4 ce = list[blockIdx.x];
     const CtxDev &c = ctxs[ce.x];
-    scatter_elem(c.kp, c.elems[ce.y], c.edof, c.partial, kps, out_dtype, c.H, c.S, c.nnz);
+    scatter_tile(c.kp, c.elems[ce.y], ce.z, c.edof, c.partial, z, nk, out_dtype, c.H, c.S, c.nnz);
 }
 
 // Element matrices of one element (full, mirrored), from its partials.
@@ -589,23 +607,27 @@ hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *
 
 size_t contract_lds_bytes(int rows, int nfun) { return ContractLds<kContractQ>::bytes(rows, nfun); }
 
-hipError_t launch_contract_f64(const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+hipError_t launch_contract_f64(int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
                                const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st) {
     if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(contract_f64_kernel<kContractQ>, dim3(n_items), dim3(256), lds, st, kp, items, elems,
-                       groups, img, edof, leaves, V, partial);
+    if (lmax <= 1)
+        hipLaunchKernelGGL((contract_f64_kernel<kContractQ, 1>), dim3(n_items), dim3(256), lds, st, kp, items, elems,
+                           groups, img, edof, leaves, V, partial);
+    else
+        hipLaunchKernelGGL((contract_f64_kernel<kContractQ, 3>), dim3(n_items), dim3(256), lds, st, kp, items, elems,
+                           groups, img, edof, leaves, V, partial);
     return hipGetLastError();
 }
 
 // Dynamic LDS above the default limit must be enabled per kernel before any
 // launch (and before any graph capture).
 hipError_t init_contract_attributes() {
-    PUFE_HIP(hipFuncSetAttribute((const void *)contract_f64_kernel<kContractQ>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
-    PUFE_HIP(hipFuncSetAttribute((const void *)contract_f64_persistent<kContractQ>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
+    const void *ks[4] = {(const void *)contract_f64_kernel<kContractQ, 1>, (const void *)contract_f64_kernel<kContractQ, 3>,
+                         (const void *)contract_f64_persistent<kContractQ, 1>,
+                         (const void *)contract_f64_persistent<kContractQ, 3>};
+    for (const void *k : ks) PUFE_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
     return hipSuccess;
 }
 
@@ -615,20 +637,29 @@ int persistent_blocks_per_cu(size_t lds) {
     return per < 1 ? 1 : per;
 }
 
-hipError_t launch_contract_persistent(const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
+hipError_t launch_contract_persistent(int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                       int grid, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
     PUFE_HIP(hipGetLastError());
     if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(contract_f64_persistent<kContractQ>, dim3(grid), dim3(256), lds, st, ctxs, items, n_items,
-                       counter);
+    if (lmax <= 1)
+        hipLaunchKernelGGL((contract_f64_persistent<kContractQ, 1>), dim3(grid), dim3(256), lds, st, ctxs, items,
+                           n_items, counter);
+    else
+        hipLaunchKernelGGL((contract_f64_persistent<kContractQ, 3>), dim3(grid), dim3(256), lds, st, ctxs, items,
+                           n_items, counter);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_batch(const CtxDev *ctxs, const int2 *list, int n, const KPoints &kps, int out_dtype,
-                                hipStream_t st) {
+hipError_t launch_phase_table(const KPoints &kps, double2 *z, hipStream_t st) {
+    hipLaunchKernelGGL(phase_table_kernel, dim3((kps.nk * 27 + 127) / 128), dim3(128), 0, st, kps, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_batch(const CtxDev *ctxs, const int4 *list, int n, const double2 *z, int nk,
+                                int out_dtype, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(scatter_batch_kernel, dim3(n), dim3(256), 0, st, ctxs, list, kps, out_dtype);
+    hipLaunchKernelGGL(scatter_batch_kernel, dim3(n), dim3(256), 0, st, ctxs, list, z, nk, out_dtype);
     return hipGetLastError();
 }
 
@@ -643,12 +674,12 @@ hipError_t launch_fill_zero(void *p, int64_t n, bool f32, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int32_t *color_elems, int n_elems,
-                          const int32_t *edof, const double *partial, const KPoints &kps, int out_dtype,
-                          void *H, void *S, int64_t nnz, hipStream_t st) {
-    if (n_elems == 0) return hipSuccess;
-    hipLaunchKernelGGL(scatter_kernel, dim3(n_elems), dim3(256), 0, st, kp, elems, color_elems, edof, partial, kps,
-                       out_dtype, H, S, nnz);
+hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int2 *list, int n, const int32_t *edof,
+                          const double *partial, const double2 *z, int nk, int out_dtype, void *H, void *S,
+                          int64_t nnz, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_kernel, dim3(n), dim3(256), 0, st, kp, elems, list, edof, partial, z, nk, out_dtype, H,
+                       S, nnz);
     return hipGetLastError();
 }
 

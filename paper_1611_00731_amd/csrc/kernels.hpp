@@ -27,7 +27,7 @@ hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *
 hipError_t init_contract_attributes();
 hipError_t init_split_attributes();
 size_t contract_lds_bytes(int rows, int nfun);
-hipError_t launch_contract_f64(const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+hipError_t launch_contract_f64(int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
                                const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st);
@@ -37,16 +37,17 @@ hipError_t launch_contract_split(int nlimb, const KParams &kp, int n_items, cons
                                  const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                  hipStream_t st);
 int persistent_blocks_per_cu(size_t lds);
-hipError_t launch_contract_persistent(const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
+hipError_t launch_contract_persistent(int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                       int grid, size_t lds, hipStream_t st);
 hipError_t launch_split_persistent(int nlimb, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                    int grid, size_t lds, hipStream_t st);
-hipError_t launch_scatter_batch(const CtxDev *ctxs, const int2 *list, int n, const KPoints &kps, int out_dtype,
-                                hipStream_t st);
+hipError_t launch_phase_table(const KPoints &kps, double2 *z, hipStream_t st);
+hipError_t launch_scatter_batch(const CtxDev *ctxs, const int4 *list, int n, const double2 *z, int nk,
+                                int out_dtype, hipStream_t st);
 hipError_t launch_fill_zero(void *p, int64_t n, bool f32, hipStream_t st);
-hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int32_t *color_elems, int n_elems,
-                          const int32_t *edof, const double *partial, const KPoints &kps, int out_dtype,
-                          void *H, void *S, int64_t nnz, hipStream_t st);
+hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int2 *list, int n, const int32_t *edof,
+                          const double *partial, const double2 *z, int nk, int out_dtype, void *H, void *S,
+                          int64_t nnz, hipStream_t st);
 hipError_t launch_elem_matrices(const ElemDev *elems, int64_t e, const double *partial, double *He, double *Se,
                                 int ld, hipStream_t st);
 hipError_t launch_bsr_to_dense(int64_t nnzb, const int32_t *brow, const int32_t *bcol, const int64_t *bval_off,

@@ -180,6 +180,8 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     pl.img.clear();
     pl.edof.clear();
     pl.max_nloc = pl.max_nfun = pl.max_ngrp = 0;
+    pl.max_l = 0;
+    for (const auto &en : pr.enr) pl.max_l = std::max(pl.max_l, en.l);
     std::vector<std::vector<int32_t>> by_color(27);
     for (int64_t e = 0; e < pl.nel; ++e) {
         ElemDev &el = pl.elems[e];
@@ -298,10 +300,17 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     }
     pl.color_elems.clear();
     pl.color_off.assign(1, 0);
+    pl.scat.clear();
+    pl.scat_off.assign(1, 0);
     for (int c = 0; c < 27; ++c) {
         if (by_color[c].empty()) continue;
         pl.color_elems.insert(pl.color_elems.end(), by_color[c].begin(), by_color[c].end());
         pl.color_off.push_back((int32_t)pl.color_elems.size());
+        for (int32_t e : by_color[c]) {
+            const int T = (pl.elems[e].nloc + 15) / 16;
+            for (int p = 0; p < T * (T + 1) / 2; ++p) pl.scat.push_back(make_int2(e, p));
+        }
+        pl.scat_off.push_back((int64_t)pl.scat.size());
     }
 
     // ---- kernel constants

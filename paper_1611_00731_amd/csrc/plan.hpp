@@ -41,7 +41,10 @@ struct Plan {
     std::vector<int32_t> edof;      // packed enriched local functions
     std::vector<int32_t> color_elems;
     std::vector<int32_t> color_off; // n_colors + 1
+    std::vector<int2> scat;         // (element, upper tile pair), colour by colour
+    std::vector<int64_t> scat_off;  // n_colors + 1
     int max_nloc = 0, max_nfun = 0, max_ngrp = 0;
+    int max_l = 0;                  // largest angular momentum of any descriptor
     KParams kp;
 };
 
