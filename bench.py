@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=sorted(PEAK))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
@@ -100,6 +101,10 @@ def main():
     prob = W.cfg2()
     log("setup", prob["name"])
     p = P.Problem(prob).setup()
+    if not args.no_tune:
+        log("autotune")
+        P.pufe_tune(p.ctx, args.precision, os.path.join(ROOT, "gpurun_out", "tune_cache.json")
+                    if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
     sz = p.sizes
     xyz, w, qp_off = p.quadrature()
     V = potential_at(xyz, prob)
@@ -152,6 +157,21 @@ def main():
                   "nloc_min": int(nloc.min()), "nloc_max": int(nloc.max()),
                   "nq_max": int(nq.max())},
     }
+    # the split-precision forms on the same inputs (context for the FP64 line)
+    for prec in ("bf16x6", "bf16x3"):
+        if prec == args.precision:
+            continue
+        P.pufe_assemble(p.ctx, V, kpts, prec, "c128", H, S)
+        P.pufe_enable_timing(p.ctx, True)
+        P.pufe_kernel_times(p.ctx, reset=True)
+        for i in range(5):
+            P.pufe_assemble(p.ctx, V, kpts, prec, "c128", H, S)
+        kms2, kc2 = P.pufe_kernel_times(p.ctx, reset=True)
+        P.pufe_enable_timing(p.ctx, False)
+        cms = kms2[0] / max(kc2[0], 1)
+        out["extra"][f"{prec}_contract_ms"] = cms
+        out["extra"][f"{prec}_tflops"] = alg_flops / (cms * 1e-3) / 1e12
+        out["extra"][f"{prec}_frac_of_effective_peak"] = alg_flops / (cms * 1e-3) / 1e12 / PEAK[prec]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob)

@@ -431,7 +431,12 @@ def eig(H, S, m):
     (torch.linalg / rocSOLVER)."""
     import torch
     Lc = torch.linalg.cholesky(S)
-    X = torch.linalg.solve_triangular(Lc, H, upper=False)
-    A = torch.linalg.solve_triangular(Lc, X.mH, upper=False).mH
+
+    def lsolve(B, chunk=1024):   # L^-1 B, a block of right-hand sides at a time
+        return torch.cat([torch.linalg.solve_triangular(Lc, B[:, i:i + chunk].contiguous(), upper=False)
+                          for i in range(0, B.shape[1], chunk)], dim=1)
+
+    X = lsolve(H)
+    A = lsolve(X.mH.contiguous()).mH
     A = 0.5 * (A + A.mH)
     return torch.linalg.eigvalsh(A)[:m]

@@ -65,6 +65,8 @@ struct pufe_ctx {
     int64_t part_slots = 0;
     double tune_items = 4096.0;
     int tune_block = kBlockTiles;
+    int contract_q = 16;            // points per LDS stage of the FP64 contraction (16 or 32)
+    int max_item_leaves = 1;
     DevBuf<ElemDev> d_elems;
     DevBuf<GroupDev> d_groups;
     DevBuf<double> d_img, d_pos, d_partial;
@@ -224,13 +226,16 @@ static void plan_chunks(pufe_ctx *c, double target_items) {
 
 // Work items (row block x column block of 16x16 tiles x K-chunk), largest
 // MFMA work first.
-static std::vector<ItemDev> make_items(const pufe_ctx *c, int block_tiles, int *max_rows) {
+static std::vector<ItemDev> make_items(const pufe_ctx *c, int block_tiles, int *max_rows, int *max_leaves) {
     const Plan &pl = c->plan;
     std::vector<ItemDev> items;
     std::vector<double> cost;
     for (int64_t e = 0; e < pl.nel; ++e) {
         const ElemDev &el = pl.elems[e];
-        const int T = (el.nloc + 15) / 16, nb = (T + block_tiles - 1) / block_tiles;
+        const int T = (el.nloc + 15) / 16;
+        // up to 5 tiles fit one diagonal block (15 tile pairs over 4 waves)
+        const int bt = (T <= 5 && block_tiles >= 4) ? T : block_tiles;
+        const int nb = (T + bt - 1) / bt;
         const int64_t nleaf = el.leaf_end - el.leaf_off, nch = el.nchunk;
         for (int64_t ch = 0; ch < nch; ++ch) {
             const int64_t lb = el.leaf_off + ch * nleaf / nch, le = el.leaf_off + (ch + 1) * nleaf / nch;
@@ -238,10 +243,10 @@ static std::vector<ItemDev> make_items(const pufe_ctx *c, int block_tiles, int *
                 for (int bi = 0; bi <= bj; ++bi) {
                     ItemDev it{};
                     it.elem = (int32_t)e;
-                    it.I0 = bi * block_tiles;
-                    it.nI = std::min(block_tiles, T - it.I0);
-                    it.J0 = bj * block_tiles;
-                    it.nJ = std::min(block_tiles, T - it.J0);
+                    it.I0 = bi * bt;
+                    it.nI = std::min(bt, T - it.I0);
+                    it.J0 = bj * bt;
+                    it.nJ = std::min(bt, T - it.J0);
                     it.chunk = (int32_t)ch;
                     it.leaf_b = lb;
                     it.leaf_e = le;
@@ -256,24 +261,31 @@ static std::vector<ItemDev> make_items(const pufe_ctx *c, int block_tiles, int *
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
     std::vector<ItemDev> sorted;
     sorted.reserve(order.size());
-    int rows = 16;
+    int rows = 16, leaves = 1;
     for (size_t i : order) {
         sorted.push_back(items[i]);
         rows = std::max(rows, 16 * (items[i].I0 == items[i].J0 ? items[i].nI : items[i].nI + items[i].nJ));
+        leaves = std::max(leaves, (int)(items[i].leaf_e - items[i].leaf_b));
     }
     *max_rows = rows;
+    if (max_leaves) *max_leaves = leaves;
     return sorted;
 }
 
 static void plan_items(pufe_ctx *c, double target_items, int block_tiles) {
     plan_chunks(c, target_items);
     const int nfun = std::max(c->plan.max_nfun, 1);
-    c->items = make_items(c, block_tiles, &c->max_rows);
-    c->lds = contract_lds_bytes(c->max_rows, nfun);
+    c->items = make_items(c, block_tiles, &c->max_rows, &c->max_item_leaves);
+    const int n3 = c->plan.kp.n3;
+    c->lds = contract_lds_bytes(c->contract_q, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
+    if (c->lds > kMaxDynLds && c->contract_q == 32) {
+        c->contract_q = 16;
+        c->lds = contract_lds_bytes(16, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
+    }
     // the split stage keeps bf16 limbs of every row: use the largest tile
     // block whose three-limb stage fits in LDS
     for (int b = block_tiles; b >= 1; --b) {
-        c->items_split = make_items(c, b, &c->max_rows_split);
+        c->items_split = make_items(c, b, &c->max_rows_split, nullptr);
         if (split_lds_bytes(3, c->max_rows_split, nfun) <= kMaxDynLds) break;
     }
 }
@@ -461,7 +473,7 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
         return PUFE_OK;
     }
     TimedRegion tr(ctx, 0, st);
-    CHECK_HIP(ctx, launch_contract_f64(pl.max_l, pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p, ctx->d_groups.p,
+    CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p, ctx->d_groups.p,
                                        ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_partial.p, ctx->lds, st),
               "contraction");
     return PUFE_OK;
@@ -732,11 +744,12 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
         size_t at = text.find(pat);
         if (at != std::string::npos) {
             double items = 0;
-            int block = 0;
-            if (std::sscanf(text.c_str() + at + pat.size(), "%lf, \"block\": %d", &items, &block) == 2 && items > 0 &&
-                block >= 1 && block <= kBlockTiles) {
+            int block = 0, qv = 0;
+            if (std::sscanf(text.c_str() + at + pat.size(), "%lf, \"block\": %d, \"q\": %d", &items, &block, &qv) == 3 &&
+                items > 0 && block >= 1 && block <= kBlockTiles && (qv == 16 || qv == 32)) {
                 ctx->tune_items = items;
                 ctx->tune_block = block;
+                ctx->contract_q = qv;
                 plan_items(ctx, items, block);
                 return upload_items(ctx, nullptr);
             }
@@ -753,10 +766,13 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
     const double cand_items[] = {1024, 2048, 4096, 8192, 16384};
     const bool saved = ctx->timing;
     ctx->timing = false;
+    int best_q = ctx->contract_q;
+    for (int qv : {16, 32})
     for (int block = 2; block <= kBlockTiles; ++block)
         for (double items : cand_items) {
+            ctx->contract_q = qv;
             plan_items(ctx, items, block);
-            if (ctx->lds > kMaxDynLds) continue;
+            if (ctx->lds > kMaxDynLds || ctx->contract_q != qv) continue;
             int rc = upload_items(ctx, nullptr);
             if (rc != PUFE_OK) break;
             rc = run_contraction(ctx, V.p, precision, nullptr);   // warm-up
@@ -771,6 +787,7 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
                 best = ms;
                 best_items = items;
                 best_block = block;
+                best_q = qv;
             }
         }
     ctx->timing = saved;
@@ -778,14 +795,15 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
     (void)hipEventDestroy(b);
     ctx->tune_items = best_items;
     ctx->tune_block = best_block;
+    ctx->contract_q = best_q;
     plan_items(ctx, best_items, best_block);
     int rc = upload_items(ctx, nullptr);
     if (rc != PUFE_OK) return rc;
     if (cache_path) {
         // append or insert the entry into a flat JSON object
         char entry[512];
-        std::snprintf(entry, sizeof entry, "\"%s\": {\"items\": %.0f, \"block\": %d, \"ms\": %.4f}", key, best_items,
-                      best_block, best / 3.0);
+        std::snprintf(entry, sizeof entry, "\"%s\": {\"items\": %.0f, \"block\": %d, \"q\": %d, \"ms\": %.4f}", key,
+                      best_items, best_block, best_q, best / 3.0);
         size_t close = text.rfind('}');
         std::string out;
         if (close == std::string::npos || text.find('{') == std::string::npos)
@@ -809,7 +827,7 @@ struct pufe_batch {
     std::vector<ItemDev> items, items_split;
     std::vector<std::vector<int4>> lists;   // per colour: (problem, element, tile pair)
     size_t lds_f64 = 0, lds_split[2] = {0, 0};
-    int max_l = 0;
+    int max_l = 0, q = 16;
     int grid_f64 = 0, grid_split[2] = {0, 0};
     DevBuf<CtxDev> d_ctxs;
     DevBuf<ItemDev> d_items, d_items_split;
@@ -860,7 +878,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     b->device = ctxs[0]->device;
     if (hipSetDevice(b->device) != hipSuccess) { delete b; return PUFE_ERR_HIP; }
-    int max_rows = 16, max_rows_split = 16, max_nfun = 1;
+    int max_rows = 16, max_rows_split = 16, max_nfun = 1, max_img = 0, max_leaves = 1, max_n3 = 1;
     b->lists.assign(27, {});
     for (int pass = 0; pass < 2; ++pass) {
         std::vector<std::pair<double, size_t>> order;
@@ -884,6 +902,9 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         max_rows = std::max(max_rows, c->max_rows);
         max_rows_split = std::max(max_rows_split, c->max_rows_split);
         max_nfun = std::max(max_nfun, c->plan.max_nfun);
+        max_img = std::max(max_img, c->plan.max_img);
+        max_leaves = std::max(max_leaves, c->max_item_leaves);
+        max_n3 = std::max(max_n3, c->plan.kp.n3);
         b->max_l = std::max(b->max_l, c->plan.max_l);
         for (int64_t e = 0; e < c->plan.nel; ++e) {
             const int T = (c->plan.elems[e].nloc + 15) / 16;
@@ -899,7 +920,8 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || ncu < 1) ncu = 256;
-    b->lds_f64 = contract_lds_bytes(max_rows, max_nfun);
+    b->q = 16;
+    b->lds_f64 = contract_lds_bytes(b->q, max_rows, max_nfun, max_img, max_leaves, max_n3);
     b->grid_f64 = ncu * persistent_blocks_per_cu(b->lds_f64);
     for (int k = 0; k < 2; ++k) {
         b->lds_split[k] = split_lds_bytes(k + 2, max_rows_split, max_nfun);
@@ -986,7 +1008,7 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
         CHECK_HIP_B(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
         hipError_t e = hipSuccess;
         if (precision == PUFE_PREC_FP64)
-            e = launch_contract_persistent(b->max_l, b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
+            e = launch_contract_persistent(b->q, b->max_l, b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
                                            b->grid_f64, b->lds_f64, b->cap);
         else {
             const int k = precision == PUFE_PREC_BF16X3 ? 0 : 1;

@@ -140,19 +140,32 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 
 // ---------------------------------------------------------- contraction
 
-// Work-group shape and LDS map of the fused contraction kernel.
-//   sB[row][q][4]   (grad_x, grad_y, grad_z, value) of the item's local rows
-//   sPsi[f][q][4]   (value, gradient) of the element's enrichment functions
-//   per-qp:  xi[3], x[3], w, w V, 1D Lagrange values/derivatives
-//   the element's enriched-function table and (atom, descriptor) groups
+// LDS map of the fused contraction kernel (laid out per work item):
+//   sB[row][q][5]     weighted operands of the item's local rows:
+//                     sqrt(w/2) d_x phi, sqrt(w/2) d_y phi, sqrt(w/2) d_z phi,
+//                     sqrt(w) phi, V sqrt(w) phi
+//   sPsi[f][q][4]     (value, gradient) of the element's enrichment functions
+//   sGeo[2][q][GEO]   per-point geometry, double buffered across stages
+//   sImg, sG, sEd     image centres, groups, enriched-function table
+//   sLeaf, sPt, sGx   leaf codes of the item, Gauss point digits, Gauss rule
 template <int Q>
 struct ContractLds {
-    static constexpr int RS = Q * 4 + 2;  // padded row stride of sB (doubles)
-    static __host__ __device__ size_t bytes(int rows, int nfun) {
-        return sizeof(double) * ((size_t)rows * RS + (size_t)nfun * Q * 4 + (size_t)Q * 26) +
-               sizeof(int32_t) * kMaxNloc + sizeof(GroupDev) * kMaxGroups;
+    static constexpr int RS = Q * 5 + 1;  // padded row stride of sB (doubles)
+    static constexpr int GEO = 56;        // doubles of geometry per point
+    static __host__ __device__ size_t bytes(int rows, int nfun, int nimg, int nleaf, int n3) {
+        return sizeof(double) * ((size_t)rows * RS + (size_t)nfun * Q * 4 + 2 * (size_t)Q * GEO + (size_t)nimg * 3 +
+                                 2 * kMaxGauss) +
+               sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc + sizeof(uint32_t) * ((size_t)nleaf + n3) +
+               64;
     }
 };
+
+// Geometry record of one point (offsets into GEO doubles)
+//   0..2 xi, 3..5 x, 6 sqrt(w/2), 7 sqrt(w), 8 V sqrt(w), 9 valid,
+//   10..18 1D FE values L[d][0..2], 19..27 derivatives D[d][0..2],
+//   28..35 PU values M_c, 36..59 would not fit: PU gradients are rebuilt per row
+//   from the 1D linear factors stored at 28..35 (M_c) and 36..41 (m_d^0, m_d^1)
+enum { G_XI = 0, G_X = 3, G_SW2 = 6, G_SW = 7, G_VSW = 8, G_OK = 9, G_L = 10, G_D = 19, G_M = 28, G_M1 = 36 };
 
 // Enrichment functions of one group at one stage point, for groups up to LMAX.
 template <int LMAX, int Q>
@@ -166,33 +179,118 @@ __device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double 
     }
 }
 
+// Geometry of stage point q (global point index qg of the item) into g[GEO].
+__device__ __forceinline__ void stage_geometry(const KParams &kp, const double *org, const uint32_t *sLeaf,
+                                               const uint32_t *sPt, const double *sGx, const double *sGw,
+                                               uint32_t li, uint32_t nli, uint32_t n3, double v, double *g) {
+    double xi[3] = {0.0, 0.0, 0.0}, w = 0.0;
+    if (li < nli) {
+        const uint32_t lf = li / n3, j = li - lf * n3;
+        const uint32_t code = sLeaf[lf], pt = sPt[j];
+        const int lev = (int)(code >> 27);
+        const double h = 1.0 / (double)(1u << lev);
+        const int c[3] = {(int)(code & 511u), (int)((code >> 9) & 511u), (int)((code >> 18) & 511u)};
+        const int k[3] = {(int)(pt & 255u), (int)((pt >> 8) & 255u), (int)(pt >> 16)};
+        w = h * h * h * kp.jac;
+        for (int d = 0; d < 3; ++d) {
+            xi[d] = -1.0 + (2.0 * c[d] + 1.0 + sGx[k[d]]) * h;
+            w *= sGw[k[d]];
+        }
+    }
+    for (int d = 0; d < 3; ++d) g[G_XI + d] = xi[d];
+    for (int cc = 0; cc < 3; ++cc)
+        g[G_X + cc] = org[cc] + 0.5 * (xi[0] + 1.0) * kp.E[cc] + 0.5 * (xi[1] + 1.0) * kp.E[3 + cc] +
+                      0.5 * (xi[2] + 1.0) * kp.E[6 + cc];
+    const double sw = sqrt(w);
+    g[G_SW2] = sqrt(0.5 * w);
+    g[G_SW] = sw;
+    g[G_VSW] = v * sw;
+    g[G_OK] = w != 0.0 ? 1.0 : 0.0;
+    for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], g + G_L + 3 * d, g + G_D + 3 * d);
+    double m[3][2];
+    for (int d = 0; d < 3; ++d) {
+        m[d][0] = 0.5 * (1.0 - xi[d]);
+        m[d][1] = 0.5 * (1.0 + xi[d]);
+        g[G_M1 + 2 * d] = m[d][0];
+        g[G_M1 + 2 * d + 1] = m[d][1];
+    }
+    for (int c8 = 0; c8 < 8; ++c8) g[G_M + c8] = m[0][c8 & 1] * m[1][(c8 >> 1) & 1] * m[2][c8 >> 2];
+}
+
+// MFMA stage for a wave owning NU tile pairs.  S: k runs over 4 points of
+// the sqrt(w) phi component; H: k runs over the 4 components of one point,
+// A = (g_x, g_y, g_z, V u), B = (g_x, g_y, g_z, u).  All fragments of a step
+// are loaded before its MFMAs.
+template <int Q, int NU>
+__device__ __forceinline__ void mfma_stage(const double *__restrict__ sB, const int *pr_row, const int *pr_col,
+                                           int r16, int k4, double4_t *accH, double4_t *accS) {
+    constexpr int RS = ContractLds<Q>::RS;
+    const int ka = k4 < 3 ? k4 : 4;
+#pragma unroll
+    for (int s4 = 0; s4 < Q / 4; ++s4) {
+        double aS[NU], bS[NU], aH[4][NU], bH[4][NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const double *ra = sB + (size_t)(pr_row[u] + r16) * RS;
+            const double *rb = sB + (size_t)(pr_col[u] + r16) * RS;
+            aS[u] = ra[5 * (4 * s4 + k4) + 3];
+            bS[u] = rb[5 * (4 * s4 + k4) + 3];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                aH[qq][u] = ra[5 * (4 * s4 + qq) + ka];
+                bH[qq][u] = rb[5 * (4 * s4 + qq) + k4];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aS[u], bS[u], accS[u], 0, 0, 0);
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+                accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aH[qq][u], bH[qq][u], accH[u], 0, 0, 0);
+    }
+}
+
 template <int Q, int LMAX>
 __device__ __forceinline__ void contract_f64_item(
     const KParams &kp, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial, double *smem) {
     constexpr int RS = ContractLds<Q>::RS;
+    constexpr int GEO = ContractLds<Q>::GEO;
     const ElemDev &el = elems[it.elem];
     const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun;
     const bool diag = it.I0 == it.J0;
     const int nrow = 16 * (diag ? it.nI : it.nI + it.nJ);
+    const int img0 = ngrp > 0 ? groups[el.grp_off].img_off : 0;
+    const int nimg = ngrp > 0 ? groups[el.grp_off + ngrp - 1].img_off + groups[el.grp_off + ngrp - 1].nimg - img0 : 0;
+    const uint32_t n3 = (uint32_t)kp.n3, n = (uint32_t)kp.n;
     double *sB = smem;
     double *sPsi = sB + (size_t)nrow * RS;
-    double *sQ = sPsi + (size_t)nfun * Q * 4;
-    double *sXi = sQ;             // [Q][3]
-    double *sX = sQ + 3 * Q;      // [Q][3]
-    double *sW = sQ + 6 * Q;      // [Q]
-    double *sWV = sQ + 7 * Q;     // [Q]
-    double *sL = sQ + 8 * Q;      // [Q][3][3]  1D FE values
-    double *sD = sQ + 17 * Q;     // [Q][3][3]  1D FE derivatives
-    int32_t *sEd = (int32_t *)(sQ + 26 * Q);
-    GroupDev *sG = (GroupDev *)(sEd + kMaxNloc);
+    double *sGeo = sPsi + (size_t)nfun * Q * 4;              // [2][Q][GEO]
+    double *sImg = sGeo + 2 * (size_t)Q * GEO;
+    double *sGx = sImg + 3 * (size_t)nimg, *sGw = sGx + kMaxGauss;
+    GroupDev *sG = (GroupDev *)(sGw + kMaxGauss);
+    int32_t *sEd = (int32_t *)(sG + kMaxGroups);
+    uint32_t *sLeaf = (uint32_t *)(sEd + kMaxNloc);
+    uint32_t *sPt = sLeaf + (it.leaf_e - it.leaf_b);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n3 = kp.n3;
-    const int64_t q_begin = it.leaf_b * n3, q_end = it.leaf_e * n3;
+    const int64_t q_begin = it.leaf_b * (int64_t)n3, q_end = it.leaf_e * (int64_t)n3;
+    const uint32_t nli = (uint32_t)(q_end - q_begin);
     const int ti0 = it.I0, tj0 = it.J0;
     for (int k = tid; k < nloc - nfe; k += 256) sEd[k] = edof[el.edof_off + k];
-    for (int g = tid; g < ngrp; g += 256) sG[g] = groups[el.grp_off + g];
+    for (int g = tid; g < ngrp; g += 256) {
+        GroupDev G = groups[el.grp_off + g];
+        G.img_off -= img0;   // rebased onto sImg
+        sG[g] = G;
+    }
+    for (int k = tid; k < 3 * nimg; k += 256) sImg[k] = img[3 * (size_t)img0 + k];
+    for (int64_t k = tid; k < it.leaf_e - it.leaf_b; k += 256) sLeaf[k] = leaves[it.leaf_b + k];
+    for (uint32_t j = tid; j < n3; j += 256) sPt[j] = (j % n) | (((j / n) % n) << 8) | ((j / (n * n)) << 16);
+    if (tid < kp.n) {
+        sGx[tid] = kp.gx[tid];
+        sGw[tid] = kp.gw[tid];
+    }
 
     // tile pairs of this item, round-robin over the four waves
     const int npairs = diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
@@ -232,103 +330,92 @@ __device__ __forceinline__ void contract_f64_item(
                            el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
                            el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
     const int r16 = lane & 15, k4 = lane >> 4;
+    __syncthreads();
+    // geometry of the first stage; V of the next stage is prefetched
+    if (tid < Q) {
+        const double v = (uint32_t)tid < nli ? V[q_begin + tid] : 0.0;
+        stage_geometry(kp, org, sLeaf, sPt, sGx, sGw, (uint32_t)tid, nli, n3, v, sGeo + (size_t)tid * GEO);
+    }
+    __syncthreads();
 
-    for (int64_t qb = q_begin; qb < q_end; qb += Q) {
-        // ---- per-point geometry
-        if (tid < Q) {
-            const int64_t qg = qb + tid;
-            double xi[3] = {0.0, 0.0, 0.0}, w = 0.0, wv = 0.0;
-            if (qg < q_end) {
-                const int64_t lf = qg / n3;
-                leaf_point(kp, leaves[lf], (int)(qg - lf * n3), xi, &w);
-                wv = w * V[qg];
-            }
-            for (int d = 0; d < 3; ++d) sXi[3 * tid + d] = xi[d];
-            for (int c = 0; c < 3; ++c)
-                sX[3 * tid + c] = org[c] + 0.5 * (xi[0] + 1.0) * kp.E[c] + 0.5 * (xi[1] + 1.0) * kp.E[3 + c] +
-                                  0.5 * (xi[2] + 1.0) * kp.E[6 + c];
-            sW[tid] = w;
-            sWV[tid] = wv;
-            for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], sL + 9 * tid + 3 * d, sD + 9 * tid + 3 * d);
-        }
-        __syncthreads();
-        // ---- enrichment functions: periodic image sums (eq. Psi, f(R) = 1)
+    int buf = 0;
+    for (uint32_t lb = 0; lb < nli; lb += Q, buf ^= 1) {
+        const double *geo = sGeo + (size_t)buf * Q * GEO;
+        const double vnext = (tid < Q && lb + Q + tid < nli) ? V[q_begin + lb + Q + tid] : 0.0;
+        // ---- enrichment functions (eq. Psi, f(R) = 1) for (group, point) pairs
         for (int idx = tid; idx < ngrp * Q; idx += 256) {
             const int g = idx / Q, q = idx - g * Q;
             const GroupDev &G = sG[g];
-            group_eval_upto<LMAX, Q>(G, img, sX + 3 * q, sPsi + ((size_t)G.fbase * Q + q) * 4);
+            group_eval_upto<LMAX, Q>(G, sImg, geo + (size_t)q * GEO + G_X, sPsi + ((size_t)G.fbase * Q + q) * 4);
         }
         __syncthreads();
-        // ---- local basis rows: FE functions and PU x enrichment (eq. pufebasis)
+        // ---- weighted local basis rows (eq. pufebasis)
         for (int idx = tid; idx < nrow * Q; idx += 256) {
             const int r = idx / Q, q = idx - r * Q;
             const int a = (diag || r < 16 * it.nI) ? 16 * ti0 + r : 16 * tj0 + (r - 16 * it.nI);
-            double *o = sB + (size_t)r * RS + 4 * q;
-            if (a >= nloc || sW[q] == 0.0) {
-                o[0] = o[1] = o[2] = o[3] = 0.0;
+            const double *g = geo + (size_t)q * GEO;
+            double *o = sB + (size_t)r * RS + 5 * q;
+            if (a >= nloc || g[G_OK] == 0.0) {
+                o[0] = o[1] = o[2] = o[3] = o[4] = 0.0;
                 continue;
             }
-            double dxi[3], val;
+            double val, dxi[3];
             if (a < nfe) {
-                const double *L = sL + 9 * q, *D = sD + 9 * q;
-                const int n1 = kp.p + 1;
-                const int a1 = a % n1, a2 = (a / n1) % n1, a3 = a / (n1 * n1);
-                const double l1 = L[a1], l2 = L[3 + a2], l3 = L[6 + a3];
+                int a1, a2, a3;
+                if (kp.p == 2) {
+                    a1 = a % 3;
+                    a2 = (a / 3) % 3;
+                    a3 = a / 9;
+                } else {
+                    a1 = a & 1;
+                    a2 = (a >> 1) & 1;
+                    a3 = a >> 2;
+                }
+                const double l1 = g[G_L + a1], l2 = g[G_L + 3 + a2], l3 = g[G_L + 6 + a3];
                 val = l1 * l2 * l3;
-                dxi[0] = D[a1] * l2 * l3;
-                dxi[1] = l1 * D[3 + a2] * l3;
-                dxi[2] = l1 * l2 * D[6 + a3];
-                for (int cc = 0; cc < 3; ++cc)
-                    o[cc] = kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2];
-                o[3] = val;
+                dxi[0] = g[G_D + a1] * l2 * l3;
+                dxi[1] = l1 * g[G_D + 3 + a2] * l3;
+                dxi[2] = l1 * l2 * g[G_D + 6 + a3];
             } else {
                 const int pk = sEd[a - nfe];
                 const int c = pk & 7, f = (pk >> 3) & 255;
-                double m[3], dm[3];
-                for (int d = 0; d < 3; ++d) {
-                    const double t = sXi[3 * q + d];
-                    const int bit = (c >> d) & 1;
-                    m[d] = bit ? 0.5 * (1.0 + t) : 0.5 * (1.0 - t);
-                    dm[d] = bit ? 0.5 : -0.5;
-                }
-                const double M = m[0] * m[1] * m[2];
-                const double dM[3] = {dm[0] * m[1] * m[2], m[0] * dm[1] * m[2], m[0] * m[1] * dm[2]};
+                const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
+                const double m0 = g[G_M1 + b0], m1 = g[G_M1 + 2 + b1], m2 = g[G_M1 + 4 + b2];
+                const double M = g[G_M + c];
                 const double *ps = sPsi + ((size_t)f * Q + q) * 4;
-                for (int cc = 0; cc < 3; ++cc) {
-                    const double gM = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
-                    o[cc] = gM * ps[0] + M * ps[1 + cc];
-                }
-                o[3] = M * ps[0];
+                const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2,
+                                      m0 * m1 * (b2 ? 0.5 : -0.5)};
+                val = M * ps[0];
+                // grad(M Psi) = grad M Psi + M grad Psi; grad M via Jt
+                double gx[3];
+                for (int cc = 0; cc < 3; ++cc)
+                    gx[cc] = (kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2]) * ps[0] +
+                             M * ps[1 + cc];
+                const double s2 = g[G_SW2];
+                o[0] = s2 * gx[0];
+                o[1] = s2 * gx[1];
+                o[2] = s2 * gx[2];
+                o[3] = g[G_SW] * val;
+                o[4] = g[G_VSW] * val;
+                continue;
             }
+            const double s2 = g[G_SW2];
+            for (int cc = 0; cc < 3; ++cc)
+                o[cc] = s2 * (kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2]);
+            o[3] = g[G_SW] * val;
+            o[4] = g[G_VSW] * val;
         }
         __syncthreads();
-        // ---- MFMA: D[i][j] += sum_k A[i][k] B[k][j]; lane = i + 16 k for A,
-        // lane = j + 16 k for B.  S: k runs over 4 points of the value row;
-        // H: k runs over the (grad_x, grad_y, grad_z, value) components of one
-        // point with weights (w/2, w/2, w/2, w V).  The wave's tile pairs are
-        // independent accumulators, interleaved so consecutive MFMAs do not
-        // wait on each other.
-#pragma unroll
-        for (int s4 = 0; s4 < Q / 4; ++s4) {
-            const int qs = 4 * s4 + k4;
-            const double ws = sW[qs];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (u < nu)
-                    accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                        sB[(size_t)(pr_row[u] + r16) * RS + 4 * qs + 3] * ws,
-                        sB[(size_t)(pr_col[u] + r16) * RS + 4 * qs + 3], accS[u], 0, 0, 0);
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int q = 4 * s4 + qq;
-                const double wf = k4 < 3 ? 0.5 * sW[q] : sWV[q];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (u < nu)
-                        accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                            sB[(size_t)(pr_row[u] + r16) * RS + 4 * q + k4] * wf,
-                            sB[(size_t)(pr_col[u] + r16) * RS + 4 * q + k4], accH[u], 0, 0, 0);
-            }
+        // ---- geometry of the next stage (other buffer), then the MFMAs
+        if (tid < Q && lb + Q < nli)
+            stage_geometry(kp, org, sLeaf, sPt, sGx, sGw, lb + Q + tid, nli, n3, vnext,
+                           sGeo + (size_t)(buf ^ 1) * Q * GEO + (size_t)tid * GEO);
+        switch (nu) {
+            case 4: mfma_stage<Q, 4>(sB, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 3: mfma_stage<Q, 3>(sB, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 2: mfma_stage<Q, 2>(sB, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 1: mfma_stage<Q, 1>(sB, pr_row, pr_col, r16, k4, accH, accS); break;
+            default: break;
         }
         __syncthreads();
     }
@@ -605,28 +692,37 @@ hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *
     return hipGetLastError();
 }
 
-size_t contract_lds_bytes(int rows, int nfun) { return ContractLds<kContractQ>::bytes(rows, nfun); }
+size_t contract_lds_bytes(int q, int rows, int nfun, int nimg, int nleaf, int n3) {
+    return q == 32 ? ContractLds<32>::bytes(rows, nfun, nimg, nleaf, n3)
+                   : ContractLds<16>::bytes(rows, nfun, nimg, nleaf, n3);
+}
 
-hipError_t launch_contract_f64(int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
-                               const GroupDev *groups, const double *img, const int32_t *edof,
+hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, const ItemDev *items,
+                               const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st) {
     if (n_items == 0) return hipSuccess;
-    if (lmax <= 1)
-        hipLaunchKernelGGL((contract_f64_kernel<kContractQ, 1>), dim3(n_items), dim3(256), lds, st, kp, items, elems,
-                           groups, img, edof, leaves, V, partial);
-    else
-        hipLaunchKernelGGL((contract_f64_kernel<kContractQ, 3>), dim3(n_items), dim3(256), lds, st, kp, items, elems,
-                           groups, img, edof, leaves, V, partial);
+#define PUFE_PLAIN(QQ, LL)                                                                                       \
+    hipLaunchKernelGGL((contract_f64_kernel<QQ, LL>), dim3(n_items), dim3(256), lds, st, kp, items, elems, groups, \
+                       img, edof, leaves, V, partial)
+    if (q == 32) {
+        if (lmax <= 1) PUFE_PLAIN(32, 1);
+        else PUFE_PLAIN(32, 3);
+    } else {
+        if (lmax <= 1) PUFE_PLAIN(16, 1);
+        else PUFE_PLAIN(16, 3);
+    }
+#undef PUFE_PLAIN
     return hipGetLastError();
 }
 
 // Dynamic LDS above the default limit must be enabled per kernel before any
 // launch (and before any graph capture).
 hipError_t init_contract_attributes() {
-    const void *ks[4] = {(const void *)contract_f64_kernel<kContractQ, 1>, (const void *)contract_f64_kernel<kContractQ, 3>,
-                         (const void *)contract_f64_persistent<kContractQ, 1>,
-                         (const void *)contract_f64_persistent<kContractQ, 3>};
+    const void *ks[8] = {(const void *)contract_f64_kernel<16, 1>, (const void *)contract_f64_kernel<16, 3>,
+                         (const void *)contract_f64_kernel<32, 1>, (const void *)contract_f64_kernel<32, 3>,
+                         (const void *)contract_f64_persistent<16, 1>, (const void *)contract_f64_persistent<16, 3>,
+                         (const void *)contract_f64_persistent<32, 1>, (const void *)contract_f64_persistent<32, 3>};
     for (const void *k : ks) PUFE_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
     return hipSuccess;
 }
@@ -637,17 +733,22 @@ int persistent_blocks_per_cu(size_t lds) {
     return per < 1 ? 1 : per;
 }
 
-hipError_t launch_contract_persistent(int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
-                                      int grid, size_t lds, hipStream_t st) {
+hipError_t launch_contract_persistent(int q, int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items,
+                                      int *counter, int grid, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
     PUFE_HIP(hipGetLastError());
     if (n_items == 0) return hipSuccess;
-    if (lmax <= 1)
-        hipLaunchKernelGGL((contract_f64_persistent<kContractQ, 1>), dim3(grid), dim3(256), lds, st, ctxs, items,
-                           n_items, counter);
-    else
-        hipLaunchKernelGGL((contract_f64_persistent<kContractQ, 3>), dim3(grid), dim3(256), lds, st, ctxs, items,
-                           n_items, counter);
+#define PUFE_PERSIST(QQ, LL)                                                                                      \
+    hipLaunchKernelGGL((contract_f64_persistent<QQ, LL>), dim3(grid), dim3(256), lds, st, ctxs, items, n_items, \
+                       counter)
+    if (q == 32) {
+        if (lmax <= 1) PUFE_PERSIST(32, 1);
+        else PUFE_PERSIST(32, 3);
+    } else {
+        if (lmax <= 1) PUFE_PERSIST(16, 1);
+        else PUFE_PERSIST(16, 3);
+    }
+#undef PUFE_PERSIST
     return hipGetLastError();
 }
 

@@ -26,9 +26,9 @@ hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *
                                  hipStream_t st);
 hipError_t init_contract_attributes();
 hipError_t init_split_attributes();
-size_t contract_lds_bytes(int rows, int nfun);
-hipError_t launch_contract_f64(int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
-                               const GroupDev *groups, const double *img, const int32_t *edof,
+size_t contract_lds_bytes(int q, int rows, int nfun, int nimg, int nleaf, int n3);
+hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, const ItemDev *items,
+                               const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st);
 size_t split_lds_bytes(int nlimb, int rows, int nfun);
@@ -37,8 +37,8 @@ hipError_t launch_contract_split(int nlimb, const KParams &kp, int n_items, cons
                                  const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                  hipStream_t st);
 int persistent_blocks_per_cu(size_t lds);
-hipError_t launch_contract_persistent(int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
-                                      int grid, size_t lds, hipStream_t st);
+hipError_t launch_contract_persistent(int q, int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items,
+                                      int *counter, int grid, size_t lds, hipStream_t st);
 hipError_t launch_split_persistent(int nlimb, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                    int grid, size_t lds, hipStream_t st);
 hipError_t launch_phase_table(const KPoints &kps, double2 *z, hipStream_t st);

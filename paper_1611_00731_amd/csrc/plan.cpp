@@ -181,6 +181,7 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     pl.edof.clear();
     pl.max_nloc = pl.max_nfun = pl.max_ngrp = 0;
     pl.max_l = 0;
+    pl.max_img = 0;
     for (const auto &en : pr.enr) pl.max_l = std::max(pl.max_l, en.l);
     std::vector<std::vector<int32_t>> by_color(27);
     for (int64_t e = 0; e < pl.nel; ++e) {
@@ -255,6 +256,7 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
             nfun += 2 * en.l + 1;
         }
         el.nfun = nfun;
+        if (el.ngrp > 0) pl.max_img = std::max(pl.max_img, (int)(pl.img.size() / 3) - pl.groups[el.grp_off].img_off);
         // enriched local functions: corner by corner, vertex order
         el.edof_off = (int32_t)pl.edof.size();
         int nenr = 0;

@@ -45,6 +45,7 @@ struct Plan {
     std::vector<int64_t> scat_off;  // n_colors + 1
     int max_nloc = 0, max_nfun = 0, max_ngrp = 0;
     int max_l = 0;                  // largest angular momentum of any descriptor
+    int max_img = 0;                // most image centres of one element's groups
     KParams kp;
 };
 
