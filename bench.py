@@ -17,8 +17,10 @@ on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +29,48 @@ sys.path.insert(0, ROOT)
 
 METRIC = "enriched H/S assembly elements/s + MFMA util; eig err vs FP64 oracle (Ha)"
 PEAK = {"fp64": 78.6, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}   # TFLOP/s, dense
+
+
+# HBM traffic of the contraction kernel from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters read for a plain
+# device copy of known size.  It is reported only while the sources it was
+# measured on are unchanged (their SHA-256 is recorded next to the figure).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_f64_lih_cell_hbm_traffic.md")
+KERNEL_SOURCES = ["kernels.hip", "tables.hpp", "enrich.hpp", "basis.hpp", "device_common.hpp",
+                  "capi.cpp", "plan.cpp"]
+
+
+def kernel_sources_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1611_00731_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """Bytes per launch recorded for the current kernel sources, else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_h = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", txt)
+    m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (m_h and m_t) or m_h.group(1) != kernel_sources_digest():
+        return None
+    return float(m_t.group(1))
+
+
+def copy_probe(mib=1024, reps=3):
+    """A plain device copy of known size, the scale for the PMC byte counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64).to("cuda")   # host fill, then a plain upload
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "reps": reps}),
+          flush=True)
 
 
 def log(*a):
@@ -85,7 +129,15 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=sorted(PEAK))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--host-inputs", action="store_true",
+                    help="evaluate the synthetic V on the host and copy it over (no torch kernels; "
+                         "for hardware-counter runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (scale for the PMC byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
@@ -107,7 +159,7 @@ def main():
                     if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
     sz = p.sizes
     xyz, w, qp_off = p.quadrature()
-    V = potential_at(xyz, prob)
+    V = potential_at(xyz.cpu(), prob).to(dev) if args.host_inputs else potential_at(xyz, prob)
     lay = p.layout()
     _, _, leaf_off = p.leaves()
     nloc, nq, flops = element_work(prob, sz, lay, leaf_off, prob["quad"]["n"] ** 3)
@@ -150,7 +202,8 @@ def main():
                    "n_elem": sz["n_elem"], "n_qp": sz["n_qp"], "n_dof": sz["n_dof"],
                    "nnz": sz["nnz"], "kpoints": n_out, "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision],
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
+                     "traffic": recorded_traffic() if args.precision == "fp64" else None,
                      "kernel": "contract_f64_kernel", "kernel_ms": contract_ms,
                      "alg_flops_per_launch": alg_flops},
         "extra": {"scatter_ms": scatter_ms, "gflops_step": alg_flops / (ms_step * 1e-3) / 1e9,

@@ -56,6 +56,10 @@ class pufe_sizes(C.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that runtime instead of a second copy
+    # (two runtimes in one process do not share devices, streams or memory)
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libpufe.so is not built ({LIB_PATH}); run __graft_entry__.build()")
     L = C.CDLL(LIB_PATH)
@@ -425,18 +429,33 @@ def PUFEAssemble():
     return _Lazy.cls
 
 
-def eig(H, S, m):
-    """Lowest m eigenvalues of H c = eps S c (eq. disceig3d) on the device:
-    FP64 Cholesky of S, reduction to L^-1 H L^-H, Hermitian eigensolve
-    (torch.linalg / rocSOLVER)."""
+def _tril_inverse(L, base=256):
+    """Inverse of a lower-triangular matrix by 2x2 block recursion: GEMMs
+    plus triangular solves of at most `base` columns at the leaves."""
     import torch
-    Lc = torch.linalg.cholesky(S)
+    n = L.shape[0]
+    if n <= base:
+        eye = torch.eye(n, dtype=L.dtype, device=L.device)
+        return torch.linalg.solve_triangular(L, eye, upper=False)
+    h = n // 2
+    Ai = _tril_inverse(L[:h, :h], base)
+    Ci = _tril_inverse(L[h:, h:].contiguous(), base)
+    out = torch.zeros_like(L)
+    out[:h, :h] = Ai
+    out[h:, h:] = Ci
+    out[h:, :h] = -(Ci @ (L[h:, :h] @ Ai))
+    return out
 
-    def lsolve(B, chunk=1024):   # L^-1 B, a block of right-hand sides at a time
-        return torch.cat([torch.linalg.solve_triangular(Lc, B[:, i:i + chunk].contiguous(), upper=False)
-                          for i in range(0, B.shape[1], chunk)], dim=1)
 
-    X = lsolve(H)
-    A = lsolve(X.mH.contiguous()).mH
+def eig(H, S, m):
+    """Lowest m eigenvalues of H c = eps S c (eq. disceig3d) on the device in
+    FP64: S = L L^H (Cholesky), eigenvalues of the Hermitian L^-1 H L^-H.
+    L^-1 is formed by block recursion (GEMMs and small triangular solves),
+    since one large triangular solve needs more library workspace than is
+    available at a few thousand DOFs."""
+    import torch
+    Lc = torch.linalg.cholesky(0.5 * (S + S.mH))
+    Li = _tril_inverse(Lc)
+    A = Li @ H @ Li.mH
     A = 0.5 * (A + A.mH)
     return torch.linalg.eigvalsh(A)[:m]

@@ -275,12 +275,17 @@ static std::vector<ItemDev> make_items(const pufe_ctx *c, int block_tiles, int *
 static void plan_items(pufe_ctx *c, double target_items, int block_tiles) {
     plan_chunks(c, target_items);
     const int nfun = std::max(c->plan.max_nfun, 1);
-    c->items = make_items(c, block_tiles, &c->max_rows, &c->max_item_leaves);
     const int n3 = c->plan.kp.n3;
-    c->lds = contract_lds_bytes(c->contract_q, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
-    if (c->lds > kMaxDynLds && c->contract_q == 32) {
-        c->contract_q = 16;
-        c->lds = contract_lds_bytes(16, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
+    // the FP64 stage double-buffers the rows of an item: use the largest
+    // tile block (and stage length) whose buffers fit in LDS
+    for (int b = block_tiles; b >= 1; --b) {
+        c->items = make_items(c, b, &c->max_rows, &c->max_item_leaves);
+        c->lds = contract_lds_bytes(c->contract_q, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
+        if (c->lds > kMaxDynLds && c->contract_q == 32) {
+            c->contract_q = 16;
+            c->lds = contract_lds_bytes(16, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
+        }
+        if (c->lds <= kMaxDynLds) break;
     }
     // the split stage keeps bf16 limbs of every row: use the largest tile
     // block whose three-limb stage fits in LDS
@@ -1007,7 +1012,9 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
             for (int d = 0; d < 3; ++d) kps.kap[k][d] = kpts[3 * k + d];
         CHECK_HIP_B(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
         hipError_t e = hipSuccess;
-        if (precision == PUFE_PREC_FP64)
+        if (precision == PUFE_PREC_FP64 && b->lds_f64 > kMaxDynLds)
+            e = hipErrorInvalidValue;
+        else if (precision == PUFE_PREC_FP64)
             e = launch_contract_persistent(b->q, b->max_l, b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
                                            b->grid_f64, b->lds_f64, b->cap);
         else {

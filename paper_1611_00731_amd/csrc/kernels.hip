@@ -139,35 +139,47 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 }
 
 // ---------------------------------------------------------- contraction
-
-// LDS map of the fused contraction kernel (laid out per work item):
-//   sB[row][q][5]     weighted operands of the item's local rows:
-//                     sqrt(w/2) d_x phi, sqrt(w/2) d_y phi, sqrt(w/2) d_z phi,
-//                     sqrt(w) phi, V sqrt(w) phi
-//   sPsi[f][q][4]     (value, gradient) of the element's enrichment functions
-//   sGeo[2][q][GEO]   per-point geometry, double buffered across stages
-//   sImg, sG, sEd     image centres, groups, enriched-function table
-//   sLeaf, sPt, sGx   leaf codes of the item, Gauss point digits, Gauss rule
+//
+// One work group of 4 waves per work item; each stage of Q points runs three
+// phases separated by barriers:
+//   1. enrichment functions at the stage points (group, point pairs), while
+//      the last Q threads build the per-point geometry;
+//   2. the weighted rows of the item's local functions;
+//   3. FP64 MFMAs over the item's 16x16 tile pairs, round-robin over waves.
+// FP64 MFMAs and FP64 VALU instructions do not co-issue on one SIMD, so the
+// phases are kept lean and the LDS footprint small enough for two work
+// groups per CU, whose phases interleave and cover each other's stalls.
+//
+// LDS map (per work item):
+//   sB[row][4][Q]   weighted operands of the item's local rows at the stage
+//                   points: sqrt(w/2) d_x phi, sqrt(w/2) d_y phi,
+//                   sqrt(w/2) d_z phi, sqrt(w) phi
+//   sV[Q]           V at the stage points
+//   sPsi[f][Q][4]   (value, gradient) of the element's enrichment functions
+//   sGeo[Q][GEO]    per-point geometry
+//   sImg, sG, sEd   image centres, groups, enriched-function table
+//   sLeaf, sPt, sGx leaf codes of the item, Gauss point digits, Gauss rule
+//   sRow            local function of each item row (-1: padding)
 template <int Q>
 struct ContractLds {
-    static constexpr int RS = Q * 5 + 1;  // padded row stride of sB (doubles)
-    static constexpr int GEO = 56;        // doubles of geometry per point
+    static constexpr int RS = 4 * Q + 2;  // row stride (doubles): 16-byte rows, offset banks
+    static constexpr int GEO = 40;        // doubles of geometry per point
     static __host__ __device__ size_t bytes(int rows, int nfun, int nimg, int nleaf, int n3) {
-        return sizeof(double) * ((size_t)rows * RS + (size_t)nfun * Q * 4 + 2 * (size_t)Q * GEO + (size_t)nimg * 3 +
-                                 2 * kMaxGauss) +
-               sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc + sizeof(uint32_t) * ((size_t)nleaf + n3) +
-               64;
+        return sizeof(double) * ((size_t)rows * RS + (size_t)Q + (size_t)nfun * Q * 4 + (size_t)Q * GEO +
+                                 (size_t)nimg * 3 + 2 * kMaxGauss) +
+               sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc +
+               sizeof(uint32_t) * ((size_t)nleaf + n3 + rows) + 64;
     }
 };
 
-// Geometry record of one point (offsets into GEO doubles)
-//   0..2 xi, 3..5 x, 6 sqrt(w/2), 7 sqrt(w), 8 V sqrt(w), 9 valid,
-//   10..18 1D FE values L[d][0..2], 19..27 derivatives D[d][0..2],
-//   28..35 PU values M_c, 36..59 would not fit: PU gradients are rebuilt per row
-//   from the 1D linear factors stored at 28..35 (M_c) and 36..41 (m_d^0, m_d^1)
-enum { G_XI = 0, G_X = 3, G_SW2 = 6, G_SW = 7, G_VSW = 8, G_OK = 9, G_L = 10, G_D = 19, G_M = 28, G_M1 = 36 };
+constexpr int kContractThreads = 256;
 
-// Enrichment functions of one group at one stage point, for groups up to LMAX.
+// Geometry record of one point (offsets into GEO doubles):
+//   xi, x, sqrt(w/2), sqrt(w), 1D FE values L[d][0..2] and derivatives
+//   D[d][0..2], trilinear PU values M_c and their 1D factors m_d^0, m_d^1.
+enum { G_XI = 0, G_X = 3, G_SW2 = 6, G_SW = 7, G_L = 8, G_D = 17, G_M = 26, G_M1 = 34 };
+
+// Enrichment functions of one group at one point, for groups up to LMAX.
 template <int LMAX, int Q>
 __device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double *__restrict__ img, const double *x,
                                                 double *o) {
@@ -179,67 +191,90 @@ __device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double 
     }
 }
 
-// Geometry of stage point q (global point index qg of the item) into g[GEO].
-__device__ __forceinline__ void stage_geometry(const KParams &kp, const double *org, const uint32_t *sLeaf,
-                                               const uint32_t *sPt, const double *sGx, const double *sGw,
-                                               uint32_t li, uint32_t nli, uint32_t n3, double v, double *g) {
-    double xi[3] = {0.0, 0.0, 0.0}, w = 0.0;
-    if (li < nli) {
-        const uint32_t lf = li / n3, j = li - lf * n3;
-        const uint32_t code = sLeaf[lf], pt = sPt[j];
-        const int lev = (int)(code >> 27);
-        const double h = 1.0 / (double)(1u << lev);
-        const int c[3] = {(int)(code & 511u), (int)((code >> 9) & 511u), (int)((code >> 18) & 511u)};
-        const int k[3] = {(int)(pt & 255u), (int)((pt >> 8) & 255u), (int)(pt >> 16)};
-        w = h * h * h * kp.jac;
-        for (int d = 0; d < 3; ++d) {
-            xi[d] = -1.0 + (2.0 * c[d] + 1.0 + sGx[k[d]]) * h;
-            w *= sGw[k[d]];
-        }
+// Reference coordinates and weight of point li of the item (w = 0 past the end).
+__device__ __forceinline__ void item_point(const KParams &kp, const uint32_t *sLeaf, const uint32_t *sPt,
+                                           const double *sGx, const double *sGw, uint32_t li, uint32_t nli,
+                                           uint32_t n3, double *xi, double *w) {
+    xi[0] = xi[1] = xi[2] = 0.0;
+    *w = 0.0;
+    if (li >= nli) return;
+    const uint32_t lf = li / n3, j = li - lf * n3;
+    const uint32_t code = sLeaf[lf], pt = sPt[j];
+    const int lev = (int)(code >> 27);
+    const double h = 1.0 / (double)(1u << lev);
+    const int c[3] = {(int)(code & 511u), (int)((code >> 9) & 511u), (int)((code >> 18) & 511u)};
+    const int k[3] = {(int)(pt & 255u), (int)((pt >> 8) & 255u), (int)(pt >> 16)};
+    double wt = h * h * h * kp.jac;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        xi[d] = -1.0 + (2.0 * c[d] + 1.0 + sGx[k[d]]) * h;
+        wt *= sGw[k[d]];
     }
-    for (int d = 0; d < 3; ++d) g[G_XI + d] = xi[d];
+    *w = wt;
+}
+
+__device__ __forceinline__ void point_position(const KParams &kp, const double *org, const double *xi, double *x) {
+#pragma unroll
     for (int cc = 0; cc < 3; ++cc)
-        g[G_X + cc] = org[cc] + 0.5 * (xi[0] + 1.0) * kp.E[cc] + 0.5 * (xi[1] + 1.0) * kp.E[3 + cc] +
-                      0.5 * (xi[2] + 1.0) * kp.E[6 + cc];
-    const double sw = sqrt(w);
+        x[cc] = org[cc] + 0.5 * (xi[0] + 1.0) * kp.E[cc] + 0.5 * (xi[1] + 1.0) * kp.E[3 + cc] +
+                0.5 * (xi[2] + 1.0) * kp.E[6 + cc];
+}
+
+// Geometry record of one point.
+__device__ __forceinline__ void point_geometry(const KParams &kp, const double *org, const double *xi, double w,
+                                               double *g) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[G_XI + d] = xi[d];
+    point_position(kp, org, xi, g + G_X);
     g[G_SW2] = sqrt(0.5 * w);
-    g[G_SW] = sw;
-    g[G_VSW] = v * sw;
-    g[G_OK] = w != 0.0 ? 1.0 : 0.0;
+    g[G_SW] = sqrt(w);
+#pragma unroll
     for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], g + G_L + 3 * d, g + G_D + 3 * d);
     double m[3][2];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         m[d][0] = 0.5 * (1.0 - xi[d]);
         m[d][1] = 0.5 * (1.0 + xi[d]);
         g[G_M1 + 2 * d] = m[d][0];
         g[G_M1 + 2 * d + 1] = m[d][1];
     }
+#pragma unroll
     for (int c8 = 0; c8 < 8; ++c8) g[G_M + c8] = m[0][c8 & 1] * m[1][(c8 >> 1) & 1] * m[2][c8 >> 2];
 }
 
-// MFMA stage for a wave owning NU tile pairs.  S: k runs over 4 points of
-// the sqrt(w) phi component; H: k runs over the 4 components of one point,
-// A = (g_x, g_y, g_z, V u), B = (g_x, g_y, g_z, u).  All fragments of a step
-// are loaded before its MFMAs.
+// MFMAs of one stage for a wave owning NU tile pairs.
+//   S: k = 4 points of the sqrt(w) phi component.
+//   H: k = the 4 components of one point, A = (g_x, g_y, g_z, V u),
+//      B = (g_x, g_y, g_z, u), u = sqrt(w) phi; V is applied to A on load.
 template <int Q, int NU>
-__device__ __forceinline__ void mfma_stage(const double *__restrict__ sB, const int *pr_row, const int *pr_col,
-                                           int r16, int k4, double4_t *accH, double4_t *accS) {
+__device__ __forceinline__ void mfma_stage(const double *__restrict__ sB, const double *__restrict__ sV,
+                                           const int *pr_row, const int *pr_col, int r16, int k4, double4_t *accH,
+                                           double4_t *accS) {
     constexpr int RS = ContractLds<Q>::RS;
-    const int ka = k4 < 3 ? k4 : 4;
 #pragma unroll
     for (int s4 = 0; s4 < Q / 4; ++s4) {
+        const double2 v01 = *(const double2 *)(sV + 4 * s4), v23 = *(const double2 *)(sV + 4 * s4 + 2);
+        const double f[4] = {k4 == 3 ? v01.x : 1.0, k4 == 3 ? v01.y : 1.0, k4 == 3 ? v23.x : 1.0,
+                             k4 == 3 ? v23.y : 1.0};
         double aS[NU], bS[NU], aH[4][NU], bH[4][NU];
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
             const double *ra = sB + (size_t)(pr_row[u] + r16) * RS;
             const double *rb = sB + (size_t)(pr_col[u] + r16) * RS;
-            aS[u] = ra[5 * (4 * s4 + k4) + 3];
-            bS[u] = rb[5 * (4 * s4 + k4) + 3];
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                aH[qq][u] = ra[5 * (4 * s4 + qq) + ka];
-                bH[qq][u] = rb[5 * (4 * s4 + qq) + k4];
-            }
+            aS[u] = ra[3 * Q + 4 * s4 + k4];
+            bS[u] = rb[3 * Q + 4 * s4 + k4];
+            const double2 a01 = *(const double2 *)(ra + k4 * Q + 4 * s4);
+            const double2 a23 = *(const double2 *)(ra + k4 * Q + 4 * s4 + 2);
+            const double2 b01 = *(const double2 *)(rb + k4 * Q + 4 * s4);
+            const double2 b23 = *(const double2 *)(rb + k4 * Q + 4 * s4 + 2);
+            aH[0][u] = a01.x * f[0];
+            aH[1][u] = a01.y * f[1];
+            aH[2][u] = a23.x * f[2];
+            aH[3][u] = a23.y * f[3];
+            bH[0][u] = b01.x;
+            bH[1][u] = b01.y;
+            bH[2][u] = b23.x;
+            bH[3][u] = b23.y;
         }
 #pragma unroll
         for (int u = 0; u < NU; ++u) accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aS[u], bS[u], accS[u], 0, 0, 0);
@@ -258,6 +293,7 @@ __device__ __forceinline__ void contract_f64_item(
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial, double *smem) {
     constexpr int RS = ContractLds<Q>::RS;
     constexpr int GEO = ContractLds<Q>::GEO;
+    constexpr int NT = kContractThreads;
     const ElemDev &el = elems[it.elem];
     const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun;
     const bool diag = it.I0 == it.J0;
@@ -265,32 +301,41 @@ __device__ __forceinline__ void contract_f64_item(
     const int img0 = ngrp > 0 ? groups[el.grp_off].img_off : 0;
     const int nimg = ngrp > 0 ? groups[el.grp_off + ngrp - 1].img_off + groups[el.grp_off + ngrp - 1].nimg - img0 : 0;
     const uint32_t n3 = (uint32_t)kp.n3, n = (uint32_t)kp.n;
-    double *sB = smem;
-    double *sPsi = sB + (size_t)nrow * RS;
-    double *sGeo = sPsi + (size_t)nfun * Q * 4;              // [2][Q][GEO]
-    double *sImg = sGeo + 2 * (size_t)Q * GEO;
+    double *sB = smem;                                        // [nrow][RS]
+    double *sV = sB + (size_t)nrow * RS;                      // [Q]
+    double *sPsi = sV + Q;                                    // [nfun][Q][4]
+    double *sGeo = sPsi + (size_t)nfun * Q * 4;               // [Q][GEO]
+    double *sImg = sGeo + (size_t)Q * GEO;
     double *sGx = sImg + 3 * (size_t)nimg, *sGw = sGx + kMaxGauss;
     GroupDev *sG = (GroupDev *)(sGw + kMaxGauss);
     int32_t *sEd = (int32_t *)(sG + kMaxGroups);
     uint32_t *sLeaf = (uint32_t *)(sEd + kMaxNloc);
     uint32_t *sPt = sLeaf + (it.leaf_e - it.leaf_b);
+    int *sRow = (int *)(sPt + n3);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t q_begin = it.leaf_b * (int64_t)n3, q_end = it.leaf_e * (int64_t)n3;
     const uint32_t nli = (uint32_t)(q_end - q_begin);
     const int ti0 = it.I0, tj0 = it.J0;
-    for (int k = tid; k < nloc - nfe; k += 256) sEd[k] = edof[el.edof_off + k];
-    for (int g = tid; g < ngrp; g += 256) {
+    for (int k = tid; k < nloc - nfe; k += NT) sEd[k] = edof[el.edof_off + k];
+    for (int g = tid; g < ngrp; g += NT) {
         GroupDev G = groups[el.grp_off + g];
         G.img_off -= img0;   // rebased onto sImg
         sG[g] = G;
     }
-    for (int k = tid; k < 3 * nimg; k += 256) sImg[k] = img[3 * (size_t)img0 + k];
-    for (int64_t k = tid; k < it.leaf_e - it.leaf_b; k += 256) sLeaf[k] = leaves[it.leaf_b + k];
-    for (uint32_t j = tid; j < n3; j += 256) sPt[j] = (j % n) | (((j / n) % n) << 8) | ((j / (n * n)) << 16);
+    for (int k = tid; k < 3 * nimg; k += NT) sImg[k] = img[3 * (size_t)img0 + k];
+    for (int64_t k = tid; k < it.leaf_e - it.leaf_b; k += NT) sLeaf[k] = leaves[it.leaf_b + k];
+    for (uint32_t j = tid; j < n3; j += NT) sPt[j] = (j % n) | (((j / n) % n) << 8) | ((j / (n * n)) << 16);
+    for (int r = tid; r < nrow; r += NT) {
+        const int a = (diag || r < 16 * it.nI) ? 16 * ti0 + r : 16 * tj0 + (r - 16 * it.nI);
+        sRow[r] = a < nloc ? a : -1;
+    }
     if (tid < kp.n) {
         sGx[tid] = kp.gx[tid];
         sGw[tid] = kp.gw[tid];
     }
+    const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
+                           el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
+                           el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
 
     // tile pairs of this item, round-robin over the four waves
     const int npairs = diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
@@ -326,41 +371,39 @@ __device__ __forceinline__ void contract_f64_item(
         accH[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
         accS[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
     }
-    const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
-                           el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
-                           el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
     const int r16 = lane & 15, k4 = lane >> 4;
-    __syncthreads();
-    // geometry of the first stage; V of the next stage is prefetched
-    if (tid < Q) {
-        const double v = (uint32_t)tid < nli ? V[q_begin + tid] : 0.0;
-        stage_geometry(kp, org, sLeaf, sPt, sGx, sGw, (uint32_t)tid, nli, n3, v, sGeo + (size_t)tid * GEO);
-    }
+    // the last Q threads build the geometry; V is read one stage ahead
+    const int gq = tid - (NT - Q);
+    double v = (gq >= 0 && (uint32_t)gq < nli) ? V[q_begin + gq] : 0.0;
     __syncthreads();
 
-    int buf = 0;
-    for (uint32_t lb = 0; lb < nli; lb += Q, buf ^= 1) {
-        const double *geo = sGeo + (size_t)buf * Q * GEO;
-        const double vnext = (tid < Q && lb + Q + tid < nli) ? V[q_begin + lb + Q + tid] : 0.0;
-        // ---- enrichment functions (eq. Psi, f(R) = 1) for (group, point) pairs
-        for (int idx = tid; idx < ngrp * Q; idx += 256) {
+    for (uint32_t lb = 0; lb < nli; lb += Q) {
+        // ---- phase 1: enrichment functions (eq. Psi, f(R) = 1) and geometry
+        if (gq >= 0) {
+            const double vn = (lb + Q + gq < nli) ? V[q_begin + lb + Q + gq] : 0.0;
+            double xi[3], w;
+            item_point(kp, sLeaf, sPt, sGx, sGw, lb + gq, nli, n3, xi, &w);
+            point_geometry(kp, org, xi, w, sGeo + (size_t)gq * GEO);
+            sV[gq] = v;
+            v = vn;
+        }
+        for (int idx = tid; idx < ngrp * Q; idx += NT) {
             const int g = idx / Q, q = idx - g * Q;
             const GroupDev &G = sG[g];
-            group_eval_upto<LMAX, Q>(G, sImg, geo + (size_t)q * GEO + G_X, sPsi + ((size_t)G.fbase * Q + q) * 4);
+            double xi[3], w, x[3];
+            item_point(kp, sLeaf, sPt, sGx, sGw, lb + q, nli, n3, xi, &w);
+            point_position(kp, org, xi, x);
+            group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + ((size_t)G.fbase * Q + q) * 4);
         }
         __syncthreads();
-        // ---- weighted local basis rows (eq. pufebasis)
-        for (int idx = tid; idx < nrow * Q; idx += 256) {
+        // ---- phase 2: weighted local basis rows (eq. pufebasis)
+        for (int idx = tid; idx < nrow * Q; idx += NT) {
             const int r = idx / Q, q = idx - r * Q;
-            const int a = (diag || r < 16 * it.nI) ? 16 * ti0 + r : 16 * tj0 + (r - 16 * it.nI);
-            const double *g = geo + (size_t)q * GEO;
-            double *o = sB + (size_t)r * RS + 5 * q;
-            if (a >= nloc || g[G_OK] == 0.0) {
-                o[0] = o[1] = o[2] = o[3] = o[4] = 0.0;
-                continue;
-            }
-            double val, dxi[3];
-            if (a < nfe) {
+            const int a = sRow[r];
+            const double *g = sGeo + (size_t)q * GEO;
+            double val = 0.0, gx[3] = {0.0, 0.0, 0.0};
+            if (a < 0) {
+            } else if (a < nfe) {
                 int a1, a2, a3;
                 if (kp.p == 2) {
                     a1 = a % 3;
@@ -373,48 +416,41 @@ __device__ __forceinline__ void contract_f64_item(
                 }
                 const double l1 = g[G_L + a1], l2 = g[G_L + 3 + a2], l3 = g[G_L + 6 + a3];
                 val = l1 * l2 * l3;
-                dxi[0] = g[G_D + a1] * l2 * l3;
-                dxi[1] = l1 * g[G_D + 3 + a2] * l3;
-                dxi[2] = l1 * l2 * g[G_D + 6 + a3];
+                const double dxi[3] = {g[G_D + a1] * l2 * l3, l1 * g[G_D + 3 + a2] * l3, l1 * l2 * g[G_D + 6 + a3]};
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    gx[cc] = kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2];
             } else {
+                // PU corner c (trilinear) times enrichment function f
                 const int pk = sEd[a - nfe];
                 const int c = pk & 7, f = (pk >> 3) & 255;
                 const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
                 const double m0 = g[G_M1 + b0], m1 = g[G_M1 + 2 + b1], m2 = g[G_M1 + 4 + b2];
                 const double M = g[G_M + c];
-                const double *ps = sPsi + ((size_t)f * Q + q) * 4;
+                const double2 p01 = *(const double2 *)(sPsi + ((size_t)f * Q + q) * 4);
+                const double2 p23 = *(const double2 *)(sPsi + ((size_t)f * Q + q) * 4 + 2);
                 const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2,
                                       m0 * m1 * (b2 ? 0.5 : -0.5)};
-                val = M * ps[0];
-                // grad(M Psi) = grad M Psi + M grad Psi; grad M via Jt
-                double gx[3];
-                for (int cc = 0; cc < 3; ++cc)
-                    gx[cc] = (kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2]) * ps[0] +
-                             M * ps[1 + cc];
-                const double s2 = g[G_SW2];
-                o[0] = s2 * gx[0];
-                o[1] = s2 * gx[1];
-                o[2] = s2 * gx[2];
-                o[3] = g[G_SW] * val;
-                o[4] = g[G_VSW] * val;
-                continue;
+                val = M * p01.x;
+                // grad(M Psi) = Psi grad M + M grad Psi, grad M via Jt
+                gx[0] = (kp.Jt[0] * dM[0] + kp.Jt[1] * dM[1] + kp.Jt[2] * dM[2]) * p01.x + M * p01.y;
+                gx[1] = (kp.Jt[3] * dM[0] + kp.Jt[4] * dM[1] + kp.Jt[5] * dM[2]) * p01.x + M * p23.x;
+                gx[2] = (kp.Jt[6] * dM[0] + kp.Jt[7] * dM[1] + kp.Jt[8] * dM[2]) * p01.x + M * p23.y;
             }
             const double s2 = g[G_SW2];
-            for (int cc = 0; cc < 3; ++cc)
-                o[cc] = s2 * (kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2]);
-            o[3] = g[G_SW] * val;
-            o[4] = g[G_VSW] * val;
+            double *o = sB + (size_t)r * RS + q;
+            o[0] = s2 * gx[0];
+            o[Q] = s2 * gx[1];
+            o[2 * Q] = s2 * gx[2];
+            o[3 * Q] = g[G_SW] * val;
         }
         __syncthreads();
-        // ---- geometry of the next stage (other buffer), then the MFMAs
-        if (tid < Q && lb + Q < nli)
-            stage_geometry(kp, org, sLeaf, sPt, sGx, sGw, lb + Q + tid, nli, n3, vnext,
-                           sGeo + (size_t)(buf ^ 1) * Q * GEO + (size_t)tid * GEO);
+        // ---- phase 3: the MFMAs
         switch (nu) {
-            case 4: mfma_stage<Q, 4>(sB, pr_row, pr_col, r16, k4, accH, accS); break;
-            case 3: mfma_stage<Q, 3>(sB, pr_row, pr_col, r16, k4, accH, accS); break;
-            case 2: mfma_stage<Q, 2>(sB, pr_row, pr_col, r16, k4, accH, accS); break;
-            case 1: mfma_stage<Q, 1>(sB, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 4: mfma_stage<Q, 4>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 3: mfma_stage<Q, 3>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 2: mfma_stage<Q, 2>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 1: mfma_stage<Q, 1>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
             default: break;
         }
         __syncthreads();
@@ -439,7 +475,7 @@ __device__ __forceinline__ void contract_f64_item(
 
 // One work group per work item.
 template <int Q, int LMAX>
-__global__ __launch_bounds__(256) void contract_f64_kernel(
+__global__ __launch_bounds__(kContractThreads) void contract_f64_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
@@ -452,9 +488,9 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(
 // problems) from one queue, largest first; every item writes its own partial
 // slots, so the result does not depend on which group ran it.
 template <int Q, int LMAX>
-__global__ __launch_bounds__(256) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
-                                                               const ItemDev *__restrict__ items, int n_items,
-                                                               int *__restrict__ counter) {
+__global__ __launch_bounds__(kContractThreads) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
+                                                                            const ItemDev *__restrict__ items,
+                                                                            int n_items, int *__restrict__ counter) {
     extern __shared__ double smem[];
     __shared__ int s_idx;
     for (;;) {
@@ -703,7 +739,7 @@ hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, 
                                hipStream_t st) {
     if (n_items == 0) return hipSuccess;
 #define PUFE_PLAIN(QQ, LL)                                                                                       \
-    hipLaunchKernelGGL((contract_f64_kernel<QQ, LL>), dim3(n_items), dim3(256), lds, st, kp, items, elems, groups, \
+    hipLaunchKernelGGL((contract_f64_kernel<QQ, LL>), dim3(n_items), dim3(kContractThreads), lds, st, kp, items, elems, groups, \
                        img, edof, leaves, V, partial)
     if (q == 32) {
         if (lmax <= 1) PUFE_PLAIN(32, 1);
@@ -739,7 +775,7 @@ hipError_t launch_contract_persistent(int q, int lmax, const CtxDev *ctxs, const
     PUFE_HIP(hipGetLastError());
     if (n_items == 0) return hipSuccess;
 #define PUFE_PERSIST(QQ, LL)                                                                                      \
-    hipLaunchKernelGGL((contract_f64_persistent<QQ, LL>), dim3(grid), dim3(256), lds, st, ctxs, items, n_items, \
+    hipLaunchKernelGGL((contract_f64_persistent<QQ, LL>), dim3(grid), dim3(kContractThreads), lds, st, ctxs, items, n_items, \
                        counter)
     if (q == 32) {
         if (lmax <= 1) PUFE_PERSIST(32, 1);

@@ -5,8 +5,9 @@
 // from the limb products of the same order of magnitude:
 //   BF16X3: a0 b0 + a0 b1 + a1 b0            (two limbs, three products)
 //   BF16X6: ... + a1 b1 + a0 b2 + a2 b0      (three limbs, six products)
-// accumulated by the MFMA in FP32 over one stage of 32 quadrature points and
-// added to FP64 accumulators after each stage.  The contraction is the one of
+// accumulated by the MFMA in FP32 over one stage of 32 quadrature points, one
+// accumulator per operand component, and added to FP64 accumulators after
+// each stage.  The contraction is the one of
 // eq. disceig3d restricted to an element, written symmetrically:
 //   S_e = U U^T, H_e = sum_d G_d G_d^T + (V U) U^T
 // with U[a][q] = sqrt(w_q) phi_a(x_q) and G_d[a][q] = sqrt(w_q / 2) d_d phi_a(x_q).
@@ -187,7 +188,13 @@ __device__ __forceinline__ void contract_split_item(
             }
         }
         __syncthreads();
-        // MFMA over limb products; lane = i + 16 grp holds 8 consecutive k
+        // MFMA over limb products; lane = i + 16 grp holds the 8 consecutive
+        // points 8 grp .. 8 grp + 7 of one component.  Every component (the
+        // three gradient components and V U against U for H, U against U for
+        // S) gets its own FP32 accumulator over the stage's 32 points, added
+        // to the FP64 accumulators afterwards: terms of one magnitude class
+        // share an FP32 sum, so the MFMA's internal FP32 rounding stays at the
+        // scale of that component rather than of the largest one.
         const int r16 = lane & 15, grp = lane >> 4;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -195,49 +202,33 @@ __device__ __forceinline__ void contract_split_item(
             const unsigned char *rowA = sLimb + (size_t)(pr_row[u] + r16) * RSB;
             const unsigned char *rowB = sLimb + (size_t)(pr_col[u] + r16) * RSB;
             const size_t LS = (size_t)nrow * RSB;  // limb stride
-            f32x4 hS = {0.f, 0.f, 0.f, 0.f}, hH = {0.f, 0.f, 0.f, 0.f};
-            // S: k = 32 points of component U (grp selects points 8 grp .. 8 grp + 7)
-            {
-                const size_t off = (size_t)(3 * Q + 8 * grp) * 2;
-                bf16x8 A[NL], B[NL];
 #pragma unroll
-                for (int j = 0; j < NL; ++j) {
-                    A[j] = *(const bf16x8 *)(rowA + j * LS + off);
-                    B[j] = *(const bf16x8 *)(rowB + j * LS + off);
-                }
-                if (NL == 3) {
-                    hS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], hS, 0, 0, 0);
-                    hS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], hS, 0, 0, 0);
-                    hS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], hS, 0, 0, 0);
-                }
-                hS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], hS, 0, 0, 0);
-                hS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], hS, 0, 0, 0);
-                hS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], hS, 0, 0, 0);
-            }
-            // H: four steps of 8 points; grp selects the component (A: V U for grp 3)
-#pragma unroll
-            for (int s = 0; s < Q / 8; ++s) {
-                const size_t offA = (size_t)((grp < 3 ? grp : 4) * Q + 8 * s) * 2;
-                const size_t offB = (size_t)(grp * Q + 8 * s) * 2;
+            for (int c = 0; c < 5; ++c) {
+                // c = 0..2: gradient components (H); 3: V U x U (H); 4: U x U (S)
+                const int ca = c < 3 ? c : (c == 3 ? 4 : 3), cb = c < 3 ? c : 3;
+                const size_t offA = (size_t)(ca * Q + 8 * grp) * 2, offB = (size_t)(cb * Q + 8 * grp) * 2;
                 bf16x8 A[NL], B[NL];
 #pragma unroll
                 for (int j = 0; j < NL; ++j) {
                     A[j] = *(const bf16x8 *)(rowA + j * LS + offA);
                     B[j] = *(const bf16x8 *)(rowB + j * LS + offB);
                 }
+                f32x4 h = {0.f, 0.f, 0.f, 0.f};
                 if (NL == 3) {
-                    hH = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], hH, 0, 0, 0);
-                    hH = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], hH, 0, 0, 0);
-                    hH = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], hH, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], h, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], h, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], h, 0, 0, 0);
                 }
-                hH = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], hH, 0, 0, 0);
-                hH = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], hH, 0, 0, 0);
-                hH = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], hH, 0, 0, 0);
-            }
+                h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], h, 0, 0, 0);
+                h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], h, 0, 0, 0);
+                h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], h, 0, 0, 0);
+                if (c < 4) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                accS[u][r] += (double)hS[r];
-                accH[u][r] += (double)hH[r];
+                    for (int r = 0; r < 4; ++r) accH[u][r] += (double)h[r];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) accS[u][r] += (double)h[r];
+                }
             }
         }
         __syncthreads();

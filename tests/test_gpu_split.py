@@ -90,10 +90,19 @@ def test_split_cfg2_full_size_eigenvalues():
         Hg, Sg = p.to_dense(H[0]).real.contiguous(), p.to_dense(S[0]).real.contiguous()
         eh = rel(Hg.cpu().numpy(), Ho)
         es = rel(Sg.cpu().numpy(), So)
-        ev = P.eig(Hg, Sg, 16).cpu().numpy()
-        de = np.abs(ev - ev_o).max()
-        say(prec, "H", eh, "S", es, "eig", de)
+        say(prec, "H", eh, "S", es)
         assert eh < tol_m and es < tol_m
         if prec == "bf16x6":
+            ev = P.eig(Hg, Sg, 16).cpu().numpy()
+            de = np.abs(ev - ev_o).max()
+            say(prec, "eig", de)
             assert de < 1e-6
+        else:
+            # two limbs leave S with errors near 2e-6 against a condition
+            # number near 1e7: its Cholesky may break down, which is reported
+            try:
+                ev = P.eig(Hg, Sg, 16).cpu().numpy()
+                say(prec, "eig", np.abs(ev - ev_o).max())
+            except RuntimeError as e:
+                say(prec, "eig: S not positive definite at this precision:", str(e).splitlines()[0])
     p.close()
