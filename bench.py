@@ -188,6 +188,7 @@ def main():
     log(f"timed {args.steps} steps: {ms_step:.4f} ms/step")
     contract_ms = kms[0] / max(kcnt[0], 1)
     scatter_ms = kms[1] / max(kcnt[1], 1)
+    reduce_ms = kms[3] / max(kcnt[3], 1)
     alg_flops = float(flops.sum())
     achieved = alg_flops / (contract_ms * 1e-3) / 1e12
     n_out = len(kpts)
@@ -206,7 +207,7 @@ def main():
                      "traffic": recorded_traffic() if args.precision == "fp64" else None,
                      "kernel": "contract_f64_kernel", "kernel_ms": contract_ms,
                      "alg_flops_per_launch": alg_flops},
-        "extra": {"scatter_ms": scatter_ms, "gflops_step": alg_flops / (ms_step * 1e-3) / 1e9,
+        "extra": {"scatter_ms": scatter_ms, "chunk_reduce_ms": reduce_ms, "gflops_step": alg_flops / (ms_step * 1e-3) / 1e9,
                   "nloc_min": int(nloc.min()), "nloc_max": int(nloc.max()),
                   "nq_max": int(nq.max())},
     }

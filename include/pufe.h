@@ -234,7 +234,7 @@ int pufe_bsr_to_dense(pufe_ctx *ctx, const void *d_bsr, int dtype, double *d_den
  * caller's stream.  pufe_kernel_times waits for the recorded events and
  * returns the summed milliseconds and launch counts of
  *   [0] the element contraction kernel, [1] the zero-fill + coloured scatter,
- *   [2] the adjoint kernel(s), [3] reserved,
+ *   [2] the adjoint kernel(s), [3] the sum of the K-chunk partial tiles,
  * clearing them when reset != 0.  out_ms[4] and counts[4] are host arrays. */
 int pufe_enable_timing(pufe_ctx *ctx, int on);
 int pufe_kernel_times(pufe_ctx *ctx, double *out_ms, int64_t *counts, int reset);

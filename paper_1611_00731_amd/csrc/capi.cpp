@@ -72,6 +72,8 @@ struct pufe_ctx {
     DevBuf<double> d_img, d_pos, d_partial;
     DevBuf<int32_t> d_edof, d_leaf_elem, d_color_elems, d_brow, d_bcol;
     DevBuf<int2> d_scat;
+    std::vector<int2> reduce;       // (element, tile pair) of every element with several K-chunks
+    DevBuf<int2> d_reduce;
     DevBuf<double2> d_ztab;
     DevBuf<uint32_t> d_leaves;
     DevBuf<int64_t> d_leaf_count, d_leaf_off, d_bval_off, d_dof_off;
@@ -222,6 +224,13 @@ static void plan_chunks(pufe_ctx *c, double target_items) {
         base += nch * P;
     }
     c->part_slots = base;
+    c->reduce.clear();
+    for (int64_t e = 0; e < pl.nel; ++e) {
+        const ElemDev &el = pl.elems[e];
+        const int T = (el.nloc + 15) / 16;
+        if (el.nchunk > 1)
+            for (int p = 0; p < T * (T + 1) / 2; ++p) c->reduce.push_back(make_int2((int)e, p));
+    }
 }
 
 // Work items (row block x column block of 16x16 tiles x K-chunk), largest
@@ -387,6 +396,7 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_color_elems.upload(pl.color_elems, st), "upload colours");
     CHECK_HIP(ctx, ctx->d_scat.upload(pl.scat, st), "upload scatter list");
+    CHECK_HIP(ctx, ctx->d_reduce.upload(ctx->reduce, st), "upload chunk reduction list");
     CHECK_HIP(ctx, ctx->d_ztab.alloc(kMaxKPerLaunch * 27), "alloc phase table");
     CHECK_HIP(ctx, ctx->d_brow.upload(pl.brow, st), "upload layout");
     CHECK_HIP(ctx, ctx->d_bcol.upload(pl.bcol, st), "upload layout");
@@ -470,17 +480,23 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
         const int nl = precision == PUFE_PREC_BF16X3 ? 2 : 3;
         const size_t lds = split_lds_bytes(nl, ctx->max_rows_split, std::max(pl.max_nfun, 1));
         if (lds > kMaxDynLds) return fail(ctx, PUFE_ERR_UNSUPPORTED, "split stage does not fit in LDS");
+        {
+            TimedRegion tr(ctx, 0, st);
+            CHECK_HIP(ctx, launch_contract_split(nl, pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p,
+                                                 ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
+                                                 ctx->d_leaves.p, d_V, ctx->d_partial.p, lds, st),
+                      "split contraction");
+        }
+    } else {
         TimedRegion tr(ctx, 0, st);
-        CHECK_HIP(ctx, launch_contract_split(nl, pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p, ctx->d_elems.p,
-                                             ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V,
-                                             ctx->d_partial.p, lds, st),
-                  "split contraction");
-        return PUFE_OK;
+        CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, pl.kp, (int)ctx->items.size(), ctx->d_items.p,
+                                           ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
+                                           ctx->d_leaves.p, d_V, ctx->d_partial.p, ctx->lds, st),
+                  "contraction");
     }
-    TimedRegion tr(ctx, 0, st);
-    CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, pl.kp, (int)ctx->items.size(), ctx->d_items.p, ctx->d_elems.p, ctx->d_groups.p,
-                                       ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_partial.p, ctx->lds, st),
-              "contraction");
+    TimedRegion tr(ctx, 3, st);
+    CHECK_HIP(ctx, launch_chunk_reduce(ctx->d_elems.p, ctx->d_reduce.p, (int)ctx->reduce.size(), ctx->d_partial.p, st),
+              "K-chunk reduction");
     return PUFE_OK;
 }
 
@@ -717,6 +733,7 @@ static int upload_items(pufe_ctx *ctx, hipStream_t st) {
     CHECK_HIP(ctx, ctx->d_elems.upload(ctx->plan.elems, st), "upload elements");
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
+    CHECK_HIP(ctx, ctx->d_reduce.upload(ctx->reduce, st), "upload chunk reduction list");
     CHECK_HIP(ctx, ctx->d_partial.alloc((size_t)ctx->part_slots * 512), "alloc partial tiles");
     ctx->have_bw = false;
     return PUFE_OK;
@@ -837,6 +854,8 @@ struct pufe_batch {
     DevBuf<CtxDev> d_ctxs;
     DevBuf<ItemDev> d_items, d_items_split;
     DevBuf<int4> d_lists;
+    std::vector<int4> reduce;               // (problem, element, tile pair) of multi-chunk elements
+    DevBuf<int4> d_reduce;
     DevBuf<double2> d_ztab;
     std::vector<int64_t> list_off;
     DevBuf<int> d_counter;
@@ -916,6 +935,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
             for (int pp = 0; pp < T * (T + 1) / 2; ++pp)
                 b->lists[c->plan.elems[e].color].push_back(make_int4(i, (int)e, pp, 0));
         }
+        for (const int2 &r : c->reduce) b->reduce.push_back(make_int4(i, r.x, r.y, 0));
     }
     std::vector<int4> flat;
     b->list_off.assign(1, 0);
@@ -934,7 +954,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     hipStream_t st = nullptr;
     if (b->d_items.upload(b->items, st) != hipSuccess || b->d_items_split.upload(b->items_split, st) != hipSuccess ||
-        b->d_lists.upload(flat, st) != hipSuccess ||
+        b->d_lists.upload(flat, st) != hipSuccess || b->d_reduce.upload(b->reduce, st) != hipSuccess ||
         b->d_counter.alloc(1) != hipSuccess || b->d_ctxs.alloc(n) != hipSuccess ||
         b->d_ztab.alloc(kMaxKPerLaunch * 27) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -1024,6 +1044,7 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
                 e = launch_split_persistent(k + 2, b->d_ctxs.p, b->d_items_split.p, (int)b->items_split.size(), b->d_counter.p,
                                             b->grid_split[k], b->lds_split[k], b->cap);
         }
+        if (e == hipSuccess) e = launch_chunk_reduce_batch(b->d_ctxs.p, b->d_reduce.p, (int)b->reduce.size(), b->cap);
         const bool f32 = out_dtype == PUFE_OUT_C64;
         for (int i = 0; i < n && e == hipSuccess; ++i) {
             const int64_t per = (out_dtype == PUFE_OUT_F64_GAMMA ? 1 : 2) * b->ctxs[i]->plan.nnz * n_k;

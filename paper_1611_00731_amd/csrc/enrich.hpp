@@ -11,7 +11,6 @@ namespace pufe {
 // Enrichment functions of one (atom, descriptor) group at one point x:
 // Psi_m = sum over images of g(s) S_m(r), grad Psi_m = 2 g'(s) r S_m + g grad S_m,
 // g(s) = exp(-a s) (1 - s/rc^2)^3, r = x - image centre, s = |r|^2 < rc^2.
-// Written to o[m * Q * 4 + (0: value, 1..3: gradient)].
 template <int L>
 __device__ __forceinline__ void group_eval_point(const GroupDev &G, const double *__restrict__ img, const double *x,
                                                  double *psi, double *gp) {
@@ -39,7 +38,8 @@ __device__ __forceinline__ void group_eval_point(const GroupDev &G, const double
     }
 }
 
-template <int L, int Q>
+// Written to o[m * MS + c * CS], c = 0 value, 1..3 gradient.
+template <int L, int MS, int CS>
 __device__ __forceinline__ void group_eval(const GroupDev &G, const double *__restrict__ img, const double *x,
                                            double *o) {
     constexpr int NM = 2 * L + 1;
@@ -47,11 +47,11 @@ __device__ __forceinline__ void group_eval(const GroupDev &G, const double *__re
     group_eval_point<L>(G, img, x, psi, gp);
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
-        double *om = o + (size_t)m * Q * 4;
+        double *om = o + (size_t)m * MS;
         om[0] = psi[m];
-        om[1] = gp[3 * m];
-        om[2] = gp[3 * m + 1];
-        om[3] = gp[3 * m + 2];
+        om[CS] = gp[3 * m];
+        om[2 * CS] = gp[3 * m + 1];
+        om[3 * CS] = gp[3 * m + 2];
     }
 }
 

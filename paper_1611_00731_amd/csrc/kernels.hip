@@ -155,8 +155,8 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 //                   points: sqrt(w/2) d_x phi, sqrt(w/2) d_y phi,
 //                   sqrt(w/2) d_z phi, sqrt(w) phi
 //   sV[Q]           V at the stage points
-//   sPsi[f][Q][4]   (value, gradient) of the element's enrichment functions
-//   sGeo[Q][GEO]    per-point geometry
+//   sPsi[f][4][Q]   (value, gradient) of the element's enrichment functions
+//   sGeo[GEO][Q]    per-point geometry, one field after the other
 //   sImg, sG, sEd   image centres, groups, enriched-function table
 //   sLeaf, sPt, sGx leaf codes of the item, Gauss point digits, Gauss rule
 //   sRow            local function of each item row (-1: padding)
@@ -184,10 +184,10 @@ template <int LMAX, int Q>
 __device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double *__restrict__ img, const double *x,
                                                 double *o) {
     switch (G.l) {
-        case 0: group_eval<0, Q>(G, img, x, o); break;
-        case 1: if (LMAX >= 1) group_eval<1, Q>(G, img, x, o); break;
-        case 2: if (LMAX >= 2) group_eval<2, Q>(G, img, x, o); break;
-        default: if (LMAX >= 3) group_eval<3, Q>(G, img, x, o); break;
+        case 0: group_eval<0, 4 * Q, Q>(G, img, x, o); break;
+        case 1: if (LMAX >= 1) group_eval<1, 4 * Q, Q>(G, img, x, o); break;
+        case 2: if (LMAX >= 2) group_eval<2, 4 * Q, Q>(G, img, x, o); break;
+        default: if (LMAX >= 3) group_eval<3, 4 * Q, Q>(G, img, x, o); break;
     }
 }
 
@@ -220,26 +220,41 @@ __device__ __forceinline__ void point_position(const KParams &kp, const double *
                 0.5 * (xi[2] + 1.0) * kp.E[6 + cc];
 }
 
-// Geometry record of one point.
+// Geometry record of one point, field f at g[f * Q].
+template <int Q>
 __device__ __forceinline__ void point_geometry(const KParams &kp, const double *org, const double *xi, double w,
                                                double *g) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) g[G_XI + d] = xi[d];
-    point_position(kp, org, xi, g + G_X);
-    g[G_SW2] = sqrt(0.5 * w);
-    g[G_SW] = sqrt(w);
+    for (int d = 0; d < 3; ++d) g[(G_XI + d) * Q] = xi[d];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], g + G_L + 3 * d, g + G_D + 3 * d);
-    double m[3][2];
+    for (int cc = 0; cc < 3; ++cc)
+        g[(G_X + cc) * Q] = org[cc] + 0.5 * (xi[0] + 1.0) * kp.E[cc] + 0.5 * (xi[1] + 1.0) * kp.E[3 + cc] +
+                            0.5 * (xi[2] + 1.0) * kp.E[6 + cc];
+    g[G_SW2 * Q] = sqrt(0.5 * w);
+    g[G_SW * Q] = sqrt(w);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        m[d][0] = 0.5 * (1.0 - xi[d]);
-        m[d][1] = 0.5 * (1.0 + xi[d]);
-        g[G_M1 + 2 * d] = m[d][0];
-        g[G_M1 + 2 * d + 1] = m[d][1];
+        const double t = xi[d];
+        if (kp.p == 1) {
+            g[(G_L + 3 * d) * Q] = 0.5 * (1.0 - t);
+            g[(G_L + 3 * d + 1) * Q] = 0.5 * (1.0 + t);
+            g[(G_D + 3 * d) * Q] = -0.5;
+            g[(G_D + 3 * d + 1) * Q] = 0.5;
+        } else {
+            g[(G_L + 3 * d) * Q] = 0.5 * t * (t - 1.0);
+            g[(G_L + 3 * d + 1) * Q] = 1.0 - t * t;
+            g[(G_L + 3 * d + 2) * Q] = 0.5 * t * (t + 1.0);
+            g[(G_D + 3 * d) * Q] = t - 0.5;
+            g[(G_D + 3 * d + 1) * Q] = -2.0 * t;
+            g[(G_D + 3 * d + 2) * Q] = t + 0.5;
+        }
+        g[(G_M1 + 2 * d) * Q] = 0.5 * (1.0 - t);
+        g[(G_M1 + 2 * d + 1) * Q] = 0.5 * (1.0 + t);
     }
 #pragma unroll
-    for (int c8 = 0; c8 < 8; ++c8) g[G_M + c8] = m[0][c8 & 1] * m[1][(c8 >> 1) & 1] * m[2][c8 >> 2];
+    for (int c8 = 0; c8 < 8; ++c8)
+        g[(G_M + c8) * Q] = (0.5 + ((c8 & 1) ? 0.5 : -0.5) * xi[0]) * (0.5 + ((c8 & 2) ? 0.5 : -0.5) * xi[1]) *
+                            (0.5 + ((c8 & 4) ? 0.5 : -0.5) * xi[2]);
 }
 
 // MFMAs of one stage for a wave owning NU tile pairs.
@@ -383,7 +398,7 @@ __device__ __forceinline__ void contract_f64_item(
             const double vn = (lb + Q + gq < nli) ? V[q_begin + lb + Q + gq] : 0.0;
             double xi[3], w;
             item_point(kp, sLeaf, sPt, sGx, sGw, lb + gq, nli, n3, xi, &w);
-            point_geometry(kp, org, xi, w, sGeo + (size_t)gq * GEO);
+            point_geometry<Q>(kp, org, xi, w, sGeo + gq);
             sV[gq] = v;
             v = vn;
         }
@@ -393,14 +408,17 @@ __device__ __forceinline__ void contract_f64_item(
             double xi[3], w, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGw, lb + q, nli, n3, xi, &w);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + ((size_t)G.fbase * Q + q) * 4);
+            group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
         __syncthreads();
-        // ---- phase 2: weighted local basis rows (eq. pufebasis)
+        // ---- phase 2: weighted local basis rows (eq. pufebasis).  The two
+        // 16-point halves of a wave take rows 8 apart, so their stores fall
+        // in different LDS banks.
         for (int idx = tid; idx < nrow * Q; idx += NT) {
-            const int r = idx / Q, q = idx - r * Q;
+            const int rr = idx / Q, q = idx - rr * Q;
+            const int r = (rr & ~15) | ((rr & 1) << 3) | ((rr >> 1) & 7);
             const int a = sRow[r];
-            const double *g = sGeo + (size_t)q * GEO;
+            const double *g = sGeo + q;   // field f at g[f * Q]
             double val = 0.0, gx[3] = {0.0, 0.0, 0.0};
             if (a < 0) {
             } else if (a < nfe) {
@@ -414,9 +432,10 @@ __device__ __forceinline__ void contract_f64_item(
                     a2 = (a >> 1) & 1;
                     a3 = a >> 2;
                 }
-                const double l1 = g[G_L + a1], l2 = g[G_L + 3 + a2], l3 = g[G_L + 6 + a3];
+                const double l1 = g[(G_L + a1) * Q], l2 = g[(G_L + 3 + a2) * Q], l3 = g[(G_L + 6 + a3) * Q];
                 val = l1 * l2 * l3;
-                const double dxi[3] = {g[G_D + a1] * l2 * l3, l1 * g[G_D + 3 + a2] * l3, l1 * l2 * g[G_D + 6 + a3]};
+                const double dxi[3] = {g[(G_D + a1) * Q] * l2 * l3, l1 * g[(G_D + 3 + a2) * Q] * l3,
+                                       l1 * l2 * g[(G_D + 6 + a3) * Q]};
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc)
                     gx[cc] = kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2];
@@ -425,24 +444,24 @@ __device__ __forceinline__ void contract_f64_item(
                 const int pk = sEd[a - nfe];
                 const int c = pk & 7, f = (pk >> 3) & 255;
                 const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
-                const double m0 = g[G_M1 + b0], m1 = g[G_M1 + 2 + b1], m2 = g[G_M1 + 4 + b2];
-                const double M = g[G_M + c];
-                const double2 p01 = *(const double2 *)(sPsi + ((size_t)f * Q + q) * 4);
-                const double2 p23 = *(const double2 *)(sPsi + ((size_t)f * Q + q) * 4 + 2);
+                const double m0 = g[(G_M1 + b0) * Q], m1 = g[(G_M1 + 2 + b1) * Q], m2 = g[(G_M1 + 4 + b2) * Q];
+                const double M = g[(G_M + c) * Q];
+                const double *ps = sPsi + (size_t)f * 4 * Q + q;
+                const double p0 = ps[0], p1 = ps[Q], p2 = ps[2 * Q], p3 = ps[3 * Q];
                 const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2,
                                       m0 * m1 * (b2 ? 0.5 : -0.5)};
-                val = M * p01.x;
+                val = M * p0;
                 // grad(M Psi) = Psi grad M + M grad Psi, grad M via Jt
-                gx[0] = (kp.Jt[0] * dM[0] + kp.Jt[1] * dM[1] + kp.Jt[2] * dM[2]) * p01.x + M * p01.y;
-                gx[1] = (kp.Jt[3] * dM[0] + kp.Jt[4] * dM[1] + kp.Jt[5] * dM[2]) * p01.x + M * p23.x;
-                gx[2] = (kp.Jt[6] * dM[0] + kp.Jt[7] * dM[1] + kp.Jt[8] * dM[2]) * p01.x + M * p23.y;
+                gx[0] = (kp.Jt[0] * dM[0] + kp.Jt[1] * dM[1] + kp.Jt[2] * dM[2]) * p0 + M * p1;
+                gx[1] = (kp.Jt[3] * dM[0] + kp.Jt[4] * dM[1] + kp.Jt[5] * dM[2]) * p0 + M * p2;
+                gx[2] = (kp.Jt[6] * dM[0] + kp.Jt[7] * dM[1] + kp.Jt[8] * dM[2]) * p0 + M * p3;
             }
-            const double s2 = g[G_SW2];
+            const double s2 = g[G_SW2 * Q];
             double *o = sB + (size_t)r * RS + q;
             o[0] = s2 * gx[0];
             o[Q] = s2 * gx[1];
             o[2 * Q] = s2 * gx[2];
-            o[3 * Q] = g[G_SW] * val;
+            o[3 * Q] = g[G_SW * Q] * val;
         }
         __syncthreads();
         // ---- phase 3: the MFMAs
@@ -475,7 +494,7 @@ __device__ __forceinline__ void contract_f64_item(
 
 // One work group per work item.
 template <int Q, int LMAX>
-__global__ __launch_bounds__(kContractThreads) void contract_f64_kernel(
+__global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
@@ -488,7 +507,7 @@ __global__ __launch_bounds__(kContractThreads) void contract_f64_kernel(
 // problems) from one queue, largest first; every item writes its own partial
 // slots, so the result does not depend on which group ran it.
 template <int Q, int LMAX>
-__global__ __launch_bounds__(kContractThreads) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
+__global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
                                                                             const ItemDev *__restrict__ items,
                                                                             int n_items, int *__restrict__ counter) {
     extern __shared__ double smem[];
@@ -507,6 +526,45 @@ __global__ __launch_bounds__(kContractThreads) void contract_f64_persistent(cons
 
 __global__ void reset_counter_kernel(int *counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+// ------------------------------------------------------ K-chunk reduction
+
+// Sum of the K-chunk partial tiles of one (element, tile pair), in chunk
+// order, into the chunk-0 slot; elements of one chunk are not listed.
+__device__ __forceinline__ void chunk_reduce_tile(const ElemDev &el, int pidx, double *__restrict__ partial) {
+    const int T = (el.nloc + 15) / 16;
+    const int64_t P = (int64_t)T * (T + 1) / 2;
+    double *dst = partial + (el.part_base + pidx) * 512;
+    for (int k = threadIdx.x; k < 512; k += blockDim.x) {
+        double acc = 0.0;
+        int c = 0;
+        // four chunks in flight, added in chunk order
+        for (; c + 4 <= el.nchunk; c += 4) {
+            const double v0 = dst[(int64_t)c * P * 512 + k], v1 = dst[(int64_t)(c + 1) * P * 512 + k];
+            const double v2 = dst[(int64_t)(c + 2) * P * 512 + k], v3 = dst[(int64_t)(c + 3) * P * 512 + k];
+            acc += v0;
+            acc += v1;
+            acc += v2;
+            acc += v3;
+        }
+        for (; c < el.nchunk; ++c) acc += dst[(int64_t)c * P * 512 + k];
+        dst[k] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void chunk_reduce_kernel(const ElemDev *__restrict__ elems,
+                                                           const int2 *__restrict__ list,
+                                                           double *__restrict__ partial) {
+    const int2 ep = list[blockIdx.x];
+    chunk_reduce_tile(elems[ep.x], ep.y, partial);
+}
+
+__global__ __launch_bounds__(256) void chunk_reduce_batch_kernel(const CtxDev *__restrict__ ctxs,
+                                                                 const int4 *__restrict__ list) {
+    const int4 ce = list[blockIdx.x];
+    const CtxDev &c = ctxs[ce.x];
+    chunk_reduce_tile(c.elems[ce.y], ce.z, c.partial);
 }
 
 // -------------------------------------------------------------- scatter
@@ -554,12 +612,9 @@ __device__ __forceinline__ void scatter_tile(const KParams &kp, const ElemDev &e
     if (a >= nloc || b >= nloc || a > b) return;
     const int T = (nloc + 15) / 16;
     const int64_t P = (int64_t)T * (T + 1) / 2;
-    double h = 0.0, s = 0.0;
-    for (int c = 0; c < el.nchunk; ++c) {
-        const double *src = partial + (el.part_base + (int64_t)c * P + pidx) * 512;
-        h += src[i * 16 + j];
-        s += src[256 + i * 16 + j];
-    }
+    // the K-chunk partials were summed into the chunk-0 slot
+    const double *src = partial + (el.part_base + pidx) * 512;
+    const double h = src[i * 16 + j], s = src[256 + i * 16 + j];
     int ca, sa, cb, sb;
     local_slot(el, edof, kp.p, a, &ca, &sa);
     local_slot(el, edof, kp.p, b, &cb, &sb);
@@ -654,14 +709,9 @@ __global__ void elem_matrices_kernel(const ElemDev *__restrict__ elems, int64_t 
         int lo = a < b ? a : b, hi = a < b ? b : a;
         int I = lo / 16, J = hi / 16, i = lo % 16, j = hi % 16;
         int64_t pidx = (int64_t)J * (J + 1) / 2 + I;
-        double h = 0.0, s = 0.0;
-        for (int c = 0; c < el.nchunk; ++c) {
-            const double *src = partial + (el.part_base + (int64_t)c * P + pidx) * 512;
-            h += src[i * 16 + j];
-            s += src[256 + i * 16 + j];
-        }
-        He[(int64_t)a * ld + b] = h;
-        Se[(int64_t)a * ld + b] = s;
+        const double *src = partial + (el.part_base + pidx) * 512;   // chunk sums (reduced)
+        He[(int64_t)a * ld + b] = src[i * 16 + j];
+        Se[(int64_t)a * ld + b] = src[256 + i * 16 + j];
     }
 }
 
@@ -785,6 +835,18 @@ hipError_t launch_contract_persistent(int q, int lmax, const CtxDev *ctxs, const
         else PUFE_PERSIST(16, 3);
     }
 #undef PUFE_PERSIST
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_reduce(const ElemDev *elems, const int2 *list, int n, double *partial, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(chunk_reduce_kernel, dim3(n), dim3(256), 0, st, elems, list, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_reduce_batch(const CtxDev *ctxs, const int4 *list, int n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(chunk_reduce_batch_kernel, dim3(n), dim3(256), 0, st, ctxs, list);
     return hipGetLastError();
 }
 

@@ -41,6 +41,8 @@ hipError_t launch_contract_persistent(int q, int lmax, const CtxDev *ctxs, const
                                       int *counter, int grid, size_t lds, hipStream_t st);
 hipError_t launch_split_persistent(int nlimb, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                    int grid, size_t lds, hipStream_t st);
+hipError_t launch_chunk_reduce(const ElemDev *elems, const int2 *list, int n, double *partial, hipStream_t st);
+hipError_t launch_chunk_reduce_batch(const CtxDev *ctxs, const int4 *list, int n, hipStream_t st);
 hipError_t launch_phase_table(const KPoints &kps, double2 *z, hipStream_t st);
 hipError_t launch_scatter_batch(const CtxDev *ctxs, const int4 *list, int n, const double2 *z, int nk,
                                 int out_dtype, hipStream_t st);

@@ -127,10 +127,10 @@ __device__ __forceinline__ void contract_split_item(
             const GroupDev G = groups[el.grp_off + g];
             double *o = sPsi + ((size_t)G.fbase * Q + q) * 4;
             switch (G.l) {
-                case 0: group_eval<0, Q>(G, img, sX + 3 * q, o); break;
-                case 1: group_eval<1, Q>(G, img, sX + 3 * q, o); break;
-                case 2: group_eval<2, Q>(G, img, sX + 3 * q, o); break;
-                default: group_eval<3, Q>(G, img, sX + 3 * q, o); break;
+                case 0: group_eval<0, Q * 4, 1>(G, img, sX + 3 * q, o); break;
+                case 1: group_eval<1, Q * 4, 1>(G, img, sX + 3 * q, o); break;
+                case 2: group_eval<2, Q * 4, 1>(G, img, sX + 3 * q, o); break;
+                default: group_eval<3, Q * 4, 1>(G, img, sX + 3 * q, o); break;
             }
         }
         __syncthreads();
