@@ -121,6 +121,113 @@ def cpu_baseline(prob, budget_s=20.0):
                       f"(refined and plain in workload proportion), single thread, {dt:.1f} s"}
 
 
+def bsr_rows_cols(lay):
+    """Global (row, col) DOF of every stored BSR value, in value order."""
+    import numpy as np
+    off, rp, bc = lay["dof_offset"], lay["brow_ptr"], lay["bcol"]
+    rows, cols = [], []
+    for v in range(len(rp) - 1):
+        bv = off[v + 1] - off[v]
+        for k in range(rp[v], rp[v + 1]):
+            w = bc[k]
+            bw = off[w + 1] - off[w]
+            rows.append(np.repeat(np.arange(off[v], off[v + 1]), bw))
+            cols.append(np.tile(np.arange(off[w], off[w + 1]), bv))
+    return np.concatenate(rows), np.concatenate(cols)
+
+
+def leg_batch(reps=5):
+    """The persistent, graph-captured batch over the lattice-constant sweep
+    (11 LiH-like cells a = 6.8 .. 8.4 bohr x 8 Monkhorst-Pack k-points, 88
+    complex128 H and S), FP64: replays timed with HIP events."""
+    import torch
+    import paper_1611_00731_amd as P
+    import workloads as W
+    from workloads.potential import potential_at
+    probs, kpts = W.cfg3(), W.mp2()
+    ps, Vs, flops, nel = [], [], 0.0, 0
+    for pr in probs:
+        p = P.Problem(pr).setup()
+        xyz, _, _ = p.quadrature()
+        Vs.append(potential_at(xyz, pr))
+        lay = p.layout()
+        _, _, leaf_off = p.leaves()
+        _, _, f = element_work(pr, p.sizes, lay, leaf_off, pr["quad"]["n"] ** 3)
+        flops += float(f.sum())
+        nel += p.sizes["n_elem"]
+        ps.append(p)
+    b = P.Batch(ps)
+    Hs, Ss = b.alloc(len(kpts), device="cuda")
+    b.assemble(Vs, kpts, Hs, Ss)            # capture
+    b.assemble(Vs, kpts, Hs, Ss)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(st)
+    for _ in range(reps):
+        b.assemble(Vs, kpts, Hs, Ss)
+    t1.record(st)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    out = {"workload": "11 lattice constants x 8 k-points (88 outputs), one graph replay", "ms": ms,
+           "elements_per_s": nel * len(kpts) / (ms * 1e-3), "unique_contractions_per_s": nel / (ms * 1e-3),
+           "alg_tflops_whole_batch": flops / (ms * 1e-3) / 1e12,
+           "frac_of_fp64_peak_whole_batch": flops / (ms * 1e-3) / 1e12 / PEAK["fp64"]}
+    b.close()
+    for p in ps:
+        p.close()
+    return out
+
+
+def leg_backward(reps=3):
+    """assemble_backward on the 2x2x2 LiH-like supercell (64 atoms, 4096
+    elements, 12.1 M points) with a rank-128 Hermitian PSD adjoint P on the
+    pattern: dL/dV at every point and dL/dR for all atoms, FP64."""
+    import numpy as np
+    import torch
+    import paper_1611_00731_amd as P
+    import workloads as W
+    from workloads.potential import potential_at
+    prob = W.cfg5()
+    p = P.Problem(prob).setup()
+    xyz, _, _ = p.quadrature()
+    V = potential_at(xyz, prob)
+    lay = p.layout()
+    _, _, leaf_off = p.leaves()
+    nloc, nq, _ = element_work(prob, p.sizes, lay, leaf_off, prob["quad"]["n"] ** 3)
+    Cd = torch.from_numpy(W.adjoint_factor(p.sizes["n_dof"], rank=128, seed=0)).cuda()
+    rows, cols = bsr_rows_cols(lay)
+    rows_d, cols_d = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+    Pb = torch.empty(len(rows), dtype=torch.complex128, device="cuda")
+    for s0 in range(0, len(rows), 1 << 20):
+        r, c = rows_d[s0:s0 + (1 << 20)], cols_d[s0:s0 + (1 << 20)]
+        Pb[s0:s0 + (1 << 20)] = (Cd[r] * Cd[c].conj()).sum(-1)
+    del Cd, rows_d, cols_d
+    p.backward(V, (0.0, 0.0, 0.0), Pb, None)
+    torch.cuda.synchronize()
+    P.pufe_enable_timing(p.ctx, True)
+    P.pufe_kernel_times(p.ctx, reset=True)
+    st = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(st)
+    for _ in range(reps):
+        p.backward(V, (0.0, 0.0, 0.0), Pb, None)
+    t1.record(st)
+    torch.cuda.synchronize()
+    kms, kc = P.pufe_kernel_times(p.ctx, reset=True)
+    P.pufe_enable_timing(p.ctx, False)
+    ms = t0.elapsed_time(t1) / reps
+    # P~ [grad phi; phi] at every point: 8 n_q n_loc^2 flops
+    flops = float((8.0 * nq * nloc.astype(float) ** 2).sum())
+    kern = kms[2] / max(kc[2], 1)
+    out = {"workload": "64-atom LiH-like supercell, 4096 elements, rank-128 adjoint, dL/dV + dL/dR",
+           "ms": ms, "adjoint_kernels_ms": kern, "elements_per_s": p.sizes["n_elem"] / (ms * 1e-3),
+           "alg_flops": flops, "alg_tflops_adjoint_kernels": flops / (kern * 1e-3) / 1e12,
+           "frac_of_fp64_peak": flops / (kern * 1e-3) / 1e12 / PEAK["fp64"]}
+    p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +236,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=sorted(PEAK))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the batch (lattice sweep) and adjoint measurement legs")
     ap.add_argument("--host-inputs", action="store_true",
                     help="evaluate the synthetic V on the host and copy it over (no torch kernels; "
                          "for hardware-counter runs)")
@@ -226,10 +335,15 @@ def main():
         out["extra"][f"{prec}_contract_ms"] = cms
         out["extra"][f"{prec}_tflops"] = alg_flops / (cms * 1e-3) / 1e12
         out["extra"][f"{prec}_frac_of_effective_peak"] = alg_flops / (cms * 1e-3) / 1e12 / PEAK[prec]
+    p.close()
+    if not args.no_rows and args.precision == "fp64":
+        log("batch leg (lattice sweep)")
+        out["extra"]["batch_sweep"] = leg_batch()
+        log("adjoint leg (64-atom supercell)")
+        out["extra"]["adjoint"] = leg_backward()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob)
-    p.close()
     print(json.dumps(out), flush=True)
 
 

@@ -171,3 +171,63 @@ def test_cfg2_full_size_sampled_blocks():
             Sg = (Sh[b0:b1, 0] + 1j * Sh[b0:b1, 1]).reshape(shape)
             assert rel(Hg, Hb) < TOL and rel(Sg, Sb) < TOL, (v, wv)
     p.close()
+
+
+def test_cfg4_full_size_sampled():
+    """The CeAl-like workload at full size (1728 elements, 27.3 M points,
+    N = 37,891, n_loc up to 283: items of several row and column blocks):
+    rule equality, element matrices of the unrefined element with the most
+    functions and of the least refined octree element, and BSR blocks around
+    vertices whose elements are all unrefined, at one k-point."""
+    prob = W.cfg4()
+    kap = tuple(prob["kpts"][1])
+    say("cfg4 full size")
+    o = oracle.Oracle(prob)
+    xyz, w, off = o.quadrature()
+    p = P.Problem(prob).setup()
+    check_rule(p, o, xyz, w)
+    Vd = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    Vh = Vd.cpu().numpy()
+    del xyz, w
+    lev, _, loff = o.leaves()
+    nleaf = np.diff(loff)
+    nloc = np.array([o.element_dofs(e)[0].size for e in range(o.n_elem)])
+    plain = np.flatnonzero(nleaf == 1)
+    refined = np.flatnonzero(nleaf > 1)
+    e_big = int(plain[np.argmax(nloc[plain])])
+    e_ref = int(refined[np.argmin(nleaf[refined])])
+    say("cfg4 elements", e_big, "n_loc", nloc[e_big], "|", e_ref, "leaves", nleaf[e_ref], "n_loc", nloc[e_ref])
+    for e in (e_big, e_ref):
+        He, Se = p.element_matrices(e, Vd)
+        Ho, So = o.element_matrices(e, Vh[off[e]:off[e + 1]])
+        assert rel(He.cpu().numpy(), Ho) < TOL and rel(Se.cpu().numpy(), So) < TOL, e
+    H, S = p.assemble(Vd, [kap])
+    lay = p.layout()
+    Hh, Sh = H[0].cpu().numpy(), S[0].cpu().numpy()
+    del H, S
+    n1, n2, n3 = prob["mesh"]
+
+    def all_plain(v):
+        i, j, k = v % n1, (v // n1) % n2, v // (n1 * n2)
+        return all(nleaf[((i - a) % n1) + n1 * (((j - b) % n2) + n2 * ((k - c) % n3))] == 1
+                   for a in (0, 1) for b in (0, 1) for c in (0, 1))
+
+    off_d = lay["dof_offset"]
+    cand = [v for v in range(o.n_vertex) if all_plain(v)]
+    width = np.diff(off_d)
+    rng = np.random.default_rng(11)
+    vs = [max(cand, key=lambda v: width[v])] + list(rng.choice(cand, 2, replace=False))
+    for v in vs:
+        v = int(v)
+        for kk in (lay["brow_ptr"][v], lay["brow_ptr"][v + 1] - 1):
+            wv = int(lay["bcol"][kk])
+            if not all_plain(wv):
+                continue
+            Hb, Sb = o.assemble_block(Vh, kap, v, wv)
+            b0, b1 = lay["bval_offset"][kk], lay["bval_offset"][kk + 1]
+            shape = (off_d[v + 1] - off_d[v], off_d[wv + 1] - off_d[wv])
+            Hg = (Hh[b0:b1, 0] + 1j * Hh[b0:b1, 1]).reshape(shape)
+            Sg = (Sh[b0:b1, 0] + 1j * Sh[b0:b1, 1]).reshape(shape)
+            say("cfg4 block", v, wv, shape)
+            assert rel(Hg, Hb) < TOL and rel(Sg, Sb) < TOL, (v, wv)
+    p.close()
