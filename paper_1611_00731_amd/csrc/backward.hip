@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, const int64_t *__restrict__ pt_off,
     const double *__restrict__ Pt, double *__restrict__ dLdV, double *__restrict__ fpart, int max_ngrp) {
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) double smem[];
     constexpr int RS = BackwardLds<Q>::RS;
     const ItemDev it = items[blockIdx.x];
     const ElemDev &el = elems[it.elem];

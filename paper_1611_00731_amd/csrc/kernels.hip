@@ -19,6 +19,9 @@ namespace pufe {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// Global-memory pointer qualifier (address space 1 of the AMDGPU target).
+#define PUFE_GLOBAL __attribute__((address_space(1)))
+
 // ------------------------------------------------------------- quadrature
 
 // Closest distance^2 from the axis-aligned box [lo, hi] to any lattice image
@@ -191,8 +194,29 @@ __device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double 
     }
 }
 
+// The per-launch constants the inner loops use, copied out of KParams into
+// registers once per item (KParams of a batched launch lives in global memory).
+struct KLocal {
+    double E[9], Jt[9], jac;
+    int p, n, n3;
+};
+
+__device__ __forceinline__ KLocal load_klocal(const KParams &kp) {
+    KLocal k;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        k.E[i] = kp.E[i];
+        k.Jt[i] = kp.Jt[i];
+    }
+    k.jac = kp.jac;
+    k.p = kp.p;
+    k.n = kp.n;
+    k.n3 = kp.n3;
+    return k;
+}
+
 // Reference coordinates and weight of point li of the item (w = 0 past the end).
-__device__ __forceinline__ void item_point(const KParams &kp, const uint32_t *sLeaf, const uint32_t *sPt,
+__device__ __forceinline__ void item_point(const KLocal &kp, const uint32_t *sLeaf, const uint32_t *sPt,
                                            const double *sGx, const double *sGw, uint32_t li, uint32_t nli,
                                            uint32_t n3, double *xi, double *w) {
     xi[0] = xi[1] = xi[2] = 0.0;
@@ -213,7 +237,7 @@ __device__ __forceinline__ void item_point(const KParams &kp, const uint32_t *sL
     *w = wt;
 }
 
-__device__ __forceinline__ void point_position(const KParams &kp, const double *org, const double *xi, double *x) {
+__device__ __forceinline__ void point_position(const KLocal &kp, const double *org, const double *xi, double *x) {
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
         x[cc] = org[cc] + 0.5 * (xi[0] + 1.0) * kp.E[cc] + 0.5 * (xi[1] + 1.0) * kp.E[3 + cc] +
@@ -222,7 +246,7 @@ __device__ __forceinline__ void point_position(const KParams &kp, const double *
 
 // Geometry record of one point, field f at g[f * Q].
 template <int Q>
-__device__ __forceinline__ void point_geometry(const KParams &kp, const double *org, const double *xi, double w,
+__device__ __forceinline__ void point_geometry(const KLocal &kp, const double *org, const double *xi, double w,
                                                double *g) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) g[(G_XI + d) * Q] = xi[d];
@@ -257,7 +281,8 @@ __device__ __forceinline__ void point_geometry(const KParams &kp, const double *
                             (0.5 + ((c8 & 4) ? 0.5 : -0.5) * xi[2]);
 }
 
-// MFMAs of one stage for a wave owning NU tile pairs.
+// MFMAs of one stage for a wave owning NU tile pairs, one pair at a time
+// (the four H products of a pair accumulate back to back).
 //   S: k = 4 points of the sqrt(w) phi component.
 //   H: k = the 4 components of one point, A = (g_x, g_y, g_z, V u),
 //      B = (g_x, g_y, g_z, u), u = sqrt(w) phi; V is applied to A on load.
@@ -271,50 +296,50 @@ __device__ __forceinline__ void mfma_stage(const double *__restrict__ sB, const 
         const double2 v01 = *(const double2 *)(sV + 4 * s4), v23 = *(const double2 *)(sV + 4 * s4 + 2);
         const double f[4] = {k4 == 3 ? v01.x : 1.0, k4 == 3 ? v01.y : 1.0, k4 == 3 ? v23.x : 1.0,
                              k4 == 3 ? v23.y : 1.0};
-        double aS[NU], bS[NU], aH[4][NU], bH[4][NU];
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
             const double *ra = sB + (size_t)(pr_row[u] + r16) * RS;
             const double *rb = sB + (size_t)(pr_col[u] + r16) * RS;
-            aS[u] = ra[3 * Q + 4 * s4 + k4];
-            bS[u] = rb[3 * Q + 4 * s4 + k4];
+            const double aS = ra[3 * Q + 4 * s4 + k4], bS = rb[3 * Q + 4 * s4 + k4];
             const double2 a01 = *(const double2 *)(ra + k4 * Q + 4 * s4);
             const double2 a23 = *(const double2 *)(ra + k4 * Q + 4 * s4 + 2);
             const double2 b01 = *(const double2 *)(rb + k4 * Q + 4 * s4);
             const double2 b23 = *(const double2 *)(rb + k4 * Q + 4 * s4 + 2);
-            aH[0][u] = a01.x * f[0];
-            aH[1][u] = a01.y * f[1];
-            aH[2][u] = a23.x * f[2];
-            aH[3][u] = a23.y * f[3];
-            bH[0][u] = b01.x;
-            bH[1][u] = b01.y;
-            bH[2][u] = b23.x;
-            bH[3][u] = b23.y;
+            accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aS, bS, accS[u], 0, 0, 0);
+            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x * f[0], b01.x, accH[u], 0, 0, 0);
+            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y * f[1], b01.y, accH[u], 0, 0, 0);
+            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x * f[2], b23.x, accH[u], 0, 0, 0);
+            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y * f[3], b23.y, accH[u], 0, 0, 0);
         }
-#pragma unroll
-        for (int u = 0; u < NU; ++u) accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aS[u], bS[u], accS[u], 0, 0, 0);
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq)
-#pragma unroll
-            for (int u = 0; u < NU; ++u)
-                accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aH[qq][u], bH[qq][u], accH[u], 0, 0, 0);
     }
 }
 
 template <int Q, int LMAX>
 __device__ __forceinline__ void contract_f64_item(
-    const KParams &kp, const ItemDev &it, const ElemDev *__restrict__ elems,
+    const KParams &kpg, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial, double *smem) {
     constexpr int RS = ContractLds<Q>::RS;
     constexpr int GEO = ContractLds<Q>::GEO;
     constexpr int NT = kContractThreads;
-    const ElemDev &el = elems[it.elem];
+    const KLocal kp = load_klocal(kpg);
+    // The table pointers of a batched launch are read from memory, so the
+    // compiler cannot tell that they address global memory; typed as such,
+    // their loads are global rather than flat instructions (a flat load in
+    // flight would also hold up every wait on LDS traffic).
+    const PUFE_GLOBAL ElemDev *gElems = (const PUFE_GLOBAL ElemDev *)elems;
+    const PUFE_GLOBAL GroupDev *gGroups = (const PUFE_GLOBAL GroupDev *)groups;
+    const PUFE_GLOBAL double *gImg = (const PUFE_GLOBAL double *)img;
+    const PUFE_GLOBAL int32_t *gEdof = (const PUFE_GLOBAL int32_t *)edof;
+    const PUFE_GLOBAL uint32_t *gLeaves = (const PUFE_GLOBAL uint32_t *)leaves;
+    const PUFE_GLOBAL double *gV = (const PUFE_GLOBAL double *)V;
+    PUFE_GLOBAL double *gPartial = (PUFE_GLOBAL double *)partial;
+    const PUFE_GLOBAL ElemDev &el = gElems[it.elem];
     const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun;
     const bool diag = it.I0 == it.J0;
     const int nrow = 16 * (diag ? it.nI : it.nI + it.nJ);
-    const int img0 = ngrp > 0 ? groups[el.grp_off].img_off : 0;
-    const int nimg = ngrp > 0 ? groups[el.grp_off + ngrp - 1].img_off + groups[el.grp_off + ngrp - 1].nimg - img0 : 0;
+    const int img0 = ngrp > 0 ? gGroups[el.grp_off].img_off : 0;
+    const int nimg = ngrp > 0 ? gGroups[el.grp_off + ngrp - 1].img_off + gGroups[el.grp_off + ngrp - 1].nimg - img0 : 0;
     const uint32_t n3 = (uint32_t)kp.n3, n = (uint32_t)kp.n;
     double *sB = smem;                                        // [nrow][RS]
     double *sV = sB + (size_t)nrow * RS;                      // [Q]
@@ -331,22 +356,30 @@ __device__ __forceinline__ void contract_f64_item(
     const int64_t q_begin = it.leaf_b * (int64_t)n3, q_end = it.leaf_e * (int64_t)n3;
     const uint32_t nli = (uint32_t)(q_end - q_begin);
     const int ti0 = it.I0, tj0 = it.J0;
-    for (int k = tid; k < nloc - nfe; k += NT) sEd[k] = edof[el.edof_off + k];
+    for (int k = tid; k < nloc - nfe; k += NT) sEd[k] = gEdof[el.edof_off + k];
     for (int g = tid; g < ngrp; g += NT) {
-        GroupDev G = groups[el.grp_off + g];
-        G.img_off -= img0;   // rebased onto sImg
+        const PUFE_GLOBAL GroupDev &Gg = gGroups[el.grp_off + g];
+        GroupDev G;
+        G.atom = Gg.atom;
+        G.desc = Gg.desc;
+        G.l = Gg.l;
+        G.fbase = Gg.fbase;
+        G.img_off = Gg.img_off - img0;   // rebased onto sImg
+        G.nimg = Gg.nimg;
+        G.a = Gg.a;
+        G.rc = Gg.rc;
         sG[g] = G;
     }
-    for (int k = tid; k < 3 * nimg; k += NT) sImg[k] = img[3 * (size_t)img0 + k];
-    for (int64_t k = tid; k < it.leaf_e - it.leaf_b; k += NT) sLeaf[k] = leaves[it.leaf_b + k];
+    for (int k = tid; k < 3 * nimg; k += NT) sImg[k] = gImg[3 * (size_t)img0 + k];
+    for (int64_t k = tid; k < it.leaf_e - it.leaf_b; k += NT) sLeaf[k] = gLeaves[it.leaf_b + k];
     for (uint32_t j = tid; j < n3; j += NT) sPt[j] = (j % n) | (((j / n) % n) << 8) | ((j / (n * n)) << 16);
     for (int r = tid; r < nrow; r += NT) {
         const int a = (diag || r < 16 * it.nI) ? 16 * ti0 + r : 16 * tj0 + (r - 16 * it.nI);
         sRow[r] = a < nloc ? a : -1;
     }
     if (tid < kp.n) {
-        sGx[tid] = kp.gx[tid];
-        sGw[tid] = kp.gw[tid];
+        sGx[tid] = kpg.gx[tid];
+        sGw[tid] = kpg.gw[tid];
     }
     const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
                            el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
@@ -389,13 +422,13 @@ __device__ __forceinline__ void contract_f64_item(
     const int r16 = lane & 15, k4 = lane >> 4;
     // the last Q threads build the geometry; V is read one stage ahead
     const int gq = tid - (NT - Q);
-    double v = (gq >= 0 && (uint32_t)gq < nli) ? V[q_begin + gq] : 0.0;
+    double v = (gq >= 0 && (uint32_t)gq < nli) ? gV[q_begin + gq] : 0.0;
     __syncthreads();
 
     for (uint32_t lb = 0; lb < nli; lb += Q) {
         // ---- phase 1: enrichment functions (eq. Psi, f(R) = 1) and geometry
         if (gq >= 0) {
-            const double vn = (lb + Q + gq < nli) ? V[q_begin + lb + Q + gq] : 0.0;
+            const double vn = (lb + Q + gq < nli) ? gV[q_begin + lb + Q + gq] : 0.0;
             double xi[3], w;
             item_point(kp, sLeaf, sPt, sGx, sGw, lb + gq, nli, n3, xi, &w);
             point_geometry<Q>(kp, org, xi, w, sGeo + gq);
@@ -482,7 +515,7 @@ __device__ __forceinline__ void contract_f64_item(
     for (int u = 0; u < 4; ++u) {
         if (u >= nu) continue;
         const int64_t pidx = (int64_t)pr_J[u] * (pr_J[u] + 1) / 2 + pr_I[u];
-        double *dst = partial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
+        PUFE_GLOBAL double *dst = gPartial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
         const int j = lane & 15, i0 = lane >> 4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -498,7 +531,7 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) double smem[];
     const ItemDev it = items[blockIdx.x];
     contract_f64_item<Q, LMAX>(kp, it, elems, groups, img, edof, leaves, V, partial, smem);
 }
@@ -510,7 +543,7 @@ template <int Q, int LMAX>
 __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
                                                                             const ItemDev *__restrict__ items,
                                                                             int n_items, int *__restrict__ counter) {
-    extern __shared__ double smem[];
+    extern __shared__ __attribute__((aligned(16))) double smem[];
     __shared__ int s_idx;
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
