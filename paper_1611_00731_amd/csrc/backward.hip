@@ -53,8 +53,8 @@ __global__ __launch_bounds__(256) void gather_adjoint_kernel(const KParams kp, c
     }
 }
 
-// Enrichment functions of a group with gradients and Hessians:
-// o[m * Q * 10 + (0 value, 1..3 gradient, 4..9 Hessian xx yy zz xy xz yz)].
+// Enrichment functions of a group with gradients and Hessians at one point:
+// o[(m * 10 + c) * Q], c = 0 value, 1..3 gradient, 4..9 Hessian xx yy zz xy xz yz.
 // Hessian of g(s) S(r): 4 g'' r r^T S + 2 g' (S I + r grad S^T + grad S r^T) + g Hess S.
 template <int L, int Q>
 __device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double *__restrict__ img, const double *x,
@@ -96,17 +96,67 @@ __device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double 
 #pragma unroll
     for (int m = 0; m < NM; ++m)
 #pragma unroll
-        for (int c = 0; c < 10; ++c) o[(size_t)m * Q * 10 + c] = acc[m][c];
+        for (int c = 0; c < 10; ++c) o[(size_t)(m * 10 + c) * Q] = acc[m][c];
 }
 
+// LDS map of the adjoint (per work item):
+//   sP[npad][RSP]   Ps (or Qs) of the element, RSP = npad + 1
+//   sB[npad][RSB]   B = [d_x phi, d_y phi, d_z phi, phi] at the stage points,
+//                   column c * Q + q
+//   sU[npad][RSB]   U = Ps B
+//   sPsi[f][10][Q]  value, gradient and Hessian of the enrichment functions
+//   sGeo[GEO][Q]    per-point geometry, field-major
+//   sC[r][Q][3]     force contributions of enriched row r at the stage points
+//                   (in the space of sB, which is free by then)
+//   sG, sEd, sImg   groups, enriched-function table, image centres
 template <int Q>
 struct BackwardLds {
-    static constexpr int RS = Q * 4 + 2;
-    static __host__ __device__ size_t bytes(int npad, int nfun) {
-        return sizeof(double) * ((size_t)npad * (npad + 2) + 2 * (size_t)npad * RS + (size_t)nfun * Q * 10 +
-                                 (size_t)Q * 26);
+    static constexpr int RSB = 4 * Q + 2;   // 16-byte rows
+    static constexpr int GEO = 40;
+    static_assert(RSB >= 3 * Q, "force contributions reuse the rows of sB");
+    static __host__ __device__ size_t bytes(int npad, int nfun, int nimg) {
+        return sizeof(double) * ((size_t)npad * (npad + 1) + 2 * (size_t)npad * RSB + (size_t)nfun * Q * 10 +
+                                 (size_t)Q * GEO + (size_t)nimg * 3) +
+               sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc + 64;
     }
 };
+
+// geometry fields (index f at sGeo[f * Q + q])
+enum { B_XI = 0, B_X = 3, B_W = 6, B_V = 7, B_L = 8, B_D = 17, B_M = 26, B_M1 = 34 };
+
+// U tiles (I, J) of one wave, NU at a time: U = Ps B over K = npad.
+template <int NU>
+__device__ __forceinline__ void backward_mfma(const double *__restrict__ sP, const double *__restrict__ sB,
+                                              double *__restrict__ sU, int RSP, int RSB, int T, int NJ, int wave,
+                                              int lane) {
+    const int r16 = lane & 15, k4 = lane >> 4;
+    int I[NU], J[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int t = wave + 4 * u;
+        I[u] = t / NJ;
+        J[u] = t - I[u] * NJ;
+    }
+    double4_t acc[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) acc[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < 4 * T; ++kb) {
+        double a[NU], b[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            a[u] = sP[(size_t)(16 * I[u] + r16) * RSP + 4 * kb + k4];
+            b[u] = sB[(size_t)(4 * kb + k4) * RSB + 16 * J[u] + r16];
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u], 0, 0, 0);
+    }
+    // FP64 16x16x4 accumulator: register r of lane l is row (l / 16) + 4 r, column l % 16
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            sU[(size_t)(16 * I[u] + k4 + 4 * r) * RSB + 16 * J[u] + r16] = acc[u][r];
+}
 
 // One work group per (element, range of leaves).  QMODE = false: the P pass
 // (density and the gradient/potential force terms); QMODE = true: the Q pass
@@ -118,186 +168,232 @@ __global__ __launch_bounds__(256) void backward_kernel(
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, const int64_t *__restrict__ pt_off,
     const double *__restrict__ Pt, double *__restrict__ dLdV, double *__restrict__ fpart, int max_ngrp) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
-    constexpr int RS = BackwardLds<Q>::RS;
+    constexpr int RSB = BackwardLds<Q>::RSB;
+    constexpr int NT = 256;
+    static_assert(NT / Q >= 32 && (NT / Q) % 32 == 0, "dL/dV uses 32 lanes per point");
     const ItemDev it = items[blockIdx.x];
     const ElemDev &el = elems[it.elem];
-    const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun;
-    const int T = (nloc + 15) / 16, npad = 16 * T, RSP = npad + 2;
+    const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun, nenr = nloc - nfe;
+    const int T = (nloc + 15) / 16, npad = 16 * T, RSP = npad + 1, NJ = (4 * Q) / 16;
+    const int img0 = ngrp > 0 ? groups[el.grp_off].img_off : 0;
+    const int nimg = ngrp > 0 ? groups[el.grp_off + ngrp - 1].img_off + groups[el.grp_off + ngrp - 1].nimg - img0 : 0;
     double *sP = smem;
     double *sB = sP + (size_t)npad * RSP;
-    double *sU = sB + (size_t)npad * RS;
-    double *sPsi = sU + (size_t)npad * RS;
-    double *sQ = sPsi + (size_t)nfun * Q * 10;
-    double *sXi = sQ, *sX = sQ + 3 * Q, *sW = sQ + 6 * Q, *sV = sQ + 7 * Q, *sL = sQ + 8 * Q, *sD = sQ + 17 * Q;
+    double *sU = sB + (size_t)npad * RSB;
+    double *sPsi = sU + (size_t)npad * RSB;
+    double *sGeo = sPsi + (size_t)nfun * Q * 10;
+    double *sC = sB;   // [nenr][Q][3], written after the density phase has read sB
+    double *sImg = sGeo + (size_t)Q * BackwardLds<Q>::GEO;
+    GroupDev *sG = (GroupDev *)(sImg + 3 * (size_t)nimg);
+    int32_t *sEd = (int32_t *)(sG + kMaxGroups);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n3 = kp.n3;
     const int64_t q_begin = it.leaf_b * n3, q_end = it.leaf_e * n3;
     const double *src = Pt + pt_off[it.elem];
-    for (int idx = tid; idx < npad * npad; idx += 256) {
+    for (int idx = tid; idx < npad * npad; idx += NT) {
         const int a = idx / npad, b = idx - a * npad;
         sP[(size_t)a * RSP + b] = src[idx];
     }
+    for (int k = tid; k < nenr; k += NT) sEd[k] = edof[el.edof_off + k];
+    for (int g = tid; g < ngrp; g += NT) {
+        GroupDev G = groups[el.grp_off + g];
+        G.img_off -= img0;   // rebased onto sImg
+        sG[g] = G;
+    }
+    for (int k = tid; k < 3 * nimg; k += NT) sImg[k] = img[3 * (size_t)img0 + k];
     const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
                            el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
                            el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
-    // force accumulation: thread t owns enriched row nfe + t
-    const int arow = nfe + tid;
-    const bool own = arow < nloc;
-    int corner = 0, fidx = 0;
-    if (own) {
-        const int pk = edof[el.edof_off + tid];
-        corner = pk & 7;
-        fidx = (pk >> 3) & 255;
-    }
+    // force accumulation: thread t owns enriched row nfe + t (rows of one
+    // stage are summed over its points in order, then over the stages)
     double facc[3] = {0.0, 0.0, 0.0};
+    const int ntile = T * NJ;
+    const int nu = ntile > wave ? (ntile - wave + 3) / 4 : 0;
+    const int gq = tid - (NT - Q);   // the last Q threads build the geometry
     __syncthreads();
 
     for (int64_t qb = q_begin; qb < q_end; qb += Q) {
-        if (tid < Q) {
-            const int64_t qg = qb + tid;
+        // ---- phase 1: geometry, enrichment functions with Hessians, and the
+        // previous stage's force contributions folded into the row sums
+        if (tid < nenr && qb > q_begin)
+            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) facc[k] += sC[((size_t)tid * Q + q) * 3 + k];
+        if (gq >= 0) {
+            const int64_t qg = qb + gq;
             double xi[3] = {0.0, 0.0, 0.0}, w = 0.0, vq = 0.0;
             if (qg < q_end) {
                 const int64_t lf = qg / n3;
                 leaf_point(kp, leaves[lf], (int)(qg - lf * n3), xi, &w);
                 vq = V[qg];
             }
-            for (int d = 0; d < 3; ++d) sXi[3 * tid + d] = xi[d];
-            for (int c = 0; c < 3; ++c)
-                sX[3 * tid + c] = org[c] + 0.5 * (xi[0] + 1.0) * kp.E[c] + 0.5 * (xi[1] + 1.0) * kp.E[3 + c] +
-                                  0.5 * (xi[2] + 1.0) * kp.E[6 + c];
-            sW[tid] = w;
-            sV[tid] = vq;
-            for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], sL + 9 * tid + 3 * d, sD + 9 * tid + 3 * d);
-        }
-        __syncthreads();
-        for (int idx = tid; idx < ngrp * Q; idx += 256) {
-            const int g = idx / Q, q = idx - g * Q;
-            const GroupDev G = groups[el.grp_off + g];
-            double *o = sPsi + ((size_t)G.fbase * Q + q) * 10;
-            switch (G.l) {
-                case 0: group_eval_hess<0, Q>(G, img, sX + 3 * q, o); break;
-                case 1: group_eval_hess<1, Q>(G, img, sX + 3 * q, o); break;
-                case 2: group_eval_hess<2, Q>(G, img, sX + 3 * q, o); break;
-                default: group_eval_hess<3, Q>(G, img, sX + 3 * q, o); break;
-            }
-        }
-        __syncthreads();
-        // basis rows (grad_x, grad_y, grad_z, value) for all local functions
-        for (int idx = tid; idx < npad * Q; idx += 256) {
-            const int a = idx / Q, q = idx - a * Q;
-            double *o = sB + (size_t)a * RS + 4 * q;
-            if (a >= nloc || sW[q] == 0.0) {
-                o[0] = o[1] = o[2] = o[3] = 0.0;
-                continue;
-            }
-            if (a < nfe) {
-                const double *L = sL + 9 * q, *D = sD + 9 * q;
-                const int n1 = kp.p + 1;
-                const int a1 = a % n1, a2 = (a / n1) % n1, a3 = a / (n1 * n1);
-                const double l1 = L[a1], l2 = L[3 + a2], l3 = L[6 + a3];
-                const double dxi[3] = {D[a1] * l2 * l3, l1 * D[3 + a2] * l3, l1 * l2 * D[6 + a3]};
-                for (int c = 0; c < 3; ++c)
-                    o[c] = kp.Jt[3 * c] * dxi[0] + kp.Jt[3 * c + 1] * dxi[1] + kp.Jt[3 * c + 2] * dxi[2];
-                o[3] = l1 * l2 * l3;
-            } else {
-                const int pk = edof[el.edof_off + (a - nfe)];
-                const int c = pk & 7, f = (pk >> 3) & 255;
-                double m[3], dm[3];
-                for (int d = 0; d < 3; ++d) {
-                    const double t = sXi[3 * q + d];
-                    const int bit = (c >> d) & 1;
-                    m[d] = bit ? 0.5 * (1.0 + t) : 0.5 * (1.0 - t);
-                    dm[d] = bit ? 0.5 : -0.5;
-                }
-                const double M = m[0] * m[1] * m[2];
-                const double dM[3] = {dm[0] * m[1] * m[2], m[0] * dm[1] * m[2], m[0] * m[1] * dm[2]};
-                const double *ps = sPsi + ((size_t)f * Q + q) * 10;
-                for (int cc = 0; cc < 3; ++cc) {
-                    const double gM = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
-                    o[cc] = gM * ps[0] + M * ps[1 + cc];
-                }
-                o[3] = M * ps[0];
-            }
-        }
-        __syncthreads();
-        // U[a][(q, c)] = sum_b Ps[a][b] B[b][(q, c)]: row tiles over waves,
-        // K = npad in steps of 4, columns (q, c) in tiles of 16.
-        {
-            const int r16 = lane & 15, k4 = lane >> 4;
-            for (int I = wave; I < T; I += 4) {
-                for (int J = 0; J < (4 * Q) / 16; ++J) {
-                    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-                    for (int kb = 0; kb < 4 * T; ++kb) {
-                        const double a = sP[(size_t)(16 * I + r16) * RSP + 4 * kb + k4];
-                        const double b = sB[(size_t)(4 * kb + k4) * RS + 16 * J + r16];
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-                    }
-                    // FP64 16x16x4 accumulator: register r of lane l is row (l / 16) + 4 r
-                    const int i0 = 16 * I + (lane >> 4);
+            double *g = sGeo + gq;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) sU[(size_t)(i0 + 4 * r) * RS + 16 * J + r16] = acc[r];
-                }
+            for (int d = 0; d < 3; ++d) {
+                g[(B_XI + d) * Q] = xi[d];
+                g[(B_X + d) * Q] = org[d] + 0.5 * (xi[0] + 1.0) * kp.E[d] + 0.5 * (xi[1] + 1.0) * kp.E[3 + d] +
+                                   0.5 * (xi[2] + 1.0) * kp.E[6 + d];
+            }
+            g[B_W * Q] = w;
+            g[B_V * Q] = vq;
+            double Lv[9], Dv[9];
+            for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], Lv + 3 * d, Dv + 3 * d);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                g[(B_L + k) * Q] = Lv[k];
+                g[(B_D + k) * Q] = Dv[k];
+            }
+            double m[3][2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                m[d][0] = 0.5 * (1.0 - xi[d]);
+                m[d][1] = 0.5 * (1.0 + xi[d]);
+                g[(B_M1 + 2 * d) * Q] = m[d][0];
+                g[(B_M1 + 2 * d + 1) * Q] = m[d][1];
+            }
+#pragma unroll
+            for (int c8 = 0; c8 < 8; ++c8) g[(B_M + c8) * Q] = m[0][c8 & 1] * m[1][(c8 >> 1) & 1] * m[2][c8 >> 2];
+        }
+        for (int idx = tid; idx < ngrp * Q; idx += NT) {
+            const int gi = idx / Q, q = idx - gi * Q;
+            const GroupDev &G = sG[gi];
+            const int64_t qg = qb + q;
+            double xi[3] = {0.0, 0.0, 0.0}, w = 0.0, x[3];
+            if (qg < q_end) {
+                const int64_t lf = qg / n3;
+                leaf_point(kp, leaves[lf], (int)(qg - lf * n3), xi, &w);
+            }
+            for (int d = 0; d < 3; ++d)
+                x[d] = org[d] + 0.5 * (xi[0] + 1.0) * kp.E[d] + 0.5 * (xi[1] + 1.0) * kp.E[3 + d] +
+                       0.5 * (xi[2] + 1.0) * kp.E[6 + d];
+            double *o = sPsi + (size_t)G.fbase * 10 * Q + q;
+            switch (G.l) {
+                case 0: group_eval_hess<0, Q>(G, sImg, x, o); break;
+                case 1: group_eval_hess<1, Q>(G, sImg, x, o); break;
+                case 2: group_eval_hess<2, Q>(G, sImg, x, o); break;
+                default: group_eval_hess<3, Q>(G, sImg, x, o); break;
             }
         }
         __syncthreads();
-        if (!QMODE && dLdV != nullptr && tid < Q) {
-            const int64_t qg = qb + tid;
-            if (qg < q_end) {
+        // ---- phase 2: basis rows (grad_x, grad_y, grad_z, value), unweighted
+        for (int idx = tid; idx < npad * Q; idx += NT) {
+            const int a = idx / Q, q = idx - a * Q;
+            const double *g = sGeo + q;
+            double gx[3] = {0.0, 0.0, 0.0}, val = 0.0;
+            if (a < nloc && g[B_W * Q] != 0.0) {
+                if (a < nfe) {
+                    const int n1 = kp.p + 1;
+                    const int a1 = a % n1, a2 = (a / n1) % n1, a3 = a / (n1 * n1);
+                    const double l1 = g[(B_L + a1) * Q], l2 = g[(B_L + 3 + a2) * Q], l3 = g[(B_L + 6 + a3) * Q];
+                    const double dxi[3] = {g[(B_D + a1) * Q] * l2 * l3, l1 * g[(B_D + 3 + a2) * Q] * l3,
+                                           l1 * l2 * g[(B_D + 6 + a3) * Q]};
+                    for (int c = 0; c < 3; ++c)
+                        gx[c] = kp.Jt[3 * c] * dxi[0] + kp.Jt[3 * c + 1] * dxi[1] + kp.Jt[3 * c + 2] * dxi[2];
+                    val = l1 * l2 * l3;
+                } else {
+                    const int pk = sEd[a - nfe];
+                    const int c = pk & 7, f = (pk >> 3) & 255;
+                    const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
+                    const double m0 = g[(B_M1 + b0) * Q], m1 = g[(B_M1 + 2 + b1) * Q], m2 = g[(B_M1 + 4 + b2) * Q];
+                    const double M = g[(B_M + c) * Q];
+                    const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2,
+                                          m0 * m1 * (b2 ? 0.5 : -0.5)};
+                    const double *ps = sPsi + (size_t)f * 10 * Q + q;
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const double gM = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
+                        gx[cc] = gM * ps[0] + M * ps[(1 + cc) * Q];
+                    }
+                    val = M * ps[0];
+                }
+            }
+            double *o = sB + (size_t)a * RSB + q;
+            o[0] = gx[0];
+            o[Q] = gx[1];
+            o[2 * Q] = gx[2];
+            o[3 * Q] = val;
+        }
+        __syncthreads();
+        // ---- phase 3: U = Ps B on the MFMAs, output tiles round-robin over waves
+        switch (nu) {
+            case 1: backward_mfma<1>(sP, sB, sU, RSP, RSB, T, NJ, wave, lane); break;
+            case 2: backward_mfma<2>(sP, sB, sU, RSP, RSB, T, NJ, wave, lane); break;
+            case 3: backward_mfma<3>(sP, sB, sU, RSP, RSB, T, NJ, wave, lane); break;
+            default: break;
+        }
+        __syncthreads();
+        // ---- phase 4: density dL/dV_q = w_q sum_a phi_a (Ps phi)_a, 32 lanes per point
+        if (!QMODE && dLdV != nullptr) {
+            const int q = tid >> 5, j = tid & 31;
+            if (q < Q) {
                 double s = 0.0;
-                for (int a = 0; a < nloc; ++a) s += sB[(size_t)a * RS + 4 * tid + 3] * sU[(size_t)a * RS + 4 * tid + 3];
-                dLdV[qg] = sW[tid] * s;
+                for (int a = j; a < nloc; a += 32) s += sB[(size_t)a * RSB + 3 * Q + q] * sU[(size_t)a * RSB + 3 * Q + q];
+#pragma unroll
+                for (int off = 16; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+                const int64_t qg = qb + q;
+                if (j == 0 && qg < q_end) dLdV[qg] = sGeo[B_W * Q + q] * s;
             }
         }
-        if (own) {
-            for (int q = 0; q < Q; ++q) {
-                const double w = sW[q];
-                if (w == 0.0) continue;
-                double m[3], dm[3];
-                for (int d = 0; d < 3; ++d) {
-                    const double t = sXi[3 * q + d];
-                    const int bit = (corner >> d) & 1;
-                    m[d] = bit ? 0.5 * (1.0 + t) : 0.5 * (1.0 - t);
-                    dm[d] = bit ? 0.5 : -0.5;
-                }
-                const double M = m[0] * m[1] * m[2];
-                const double dM[3] = {dm[0] * m[1] * m[2], m[0] * dm[1] * m[2], m[0] * m[1] * dm[2]};
+        __syncthreads();
+        // ---- phase 5: force contributions of every (enriched row, point)
+        for (int idx = tid; idx < nenr * Q; idx += NT) {
+            const int r = idx / Q, q = idx - r * Q;
+            const double *g = sGeo + q;
+            const double w = g[B_W * Q];
+            double cf[3] = {0.0, 0.0, 0.0};
+            if (w != 0.0) {
+                const int pk = sEd[r];
+                const int corner = pk & 7, f = (pk >> 3) & 255;
+                const int b0 = corner & 1, b1 = (corner >> 1) & 1, b2 = corner >> 2;
+                const double m0 = g[(B_M1 + b0) * Q], m1 = g[(B_M1 + 2 + b1) * Q], m2 = g[(B_M1 + 4 + b2) * Q];
+                const double M = g[(B_M + corner) * Q];
+                const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2,
+                                      m0 * m1 * (b2 ? 0.5 : -0.5)};
                 double gM[3];
                 for (int cc = 0; cc < 3; ++cc)
                     gM[cc] = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
-                const double *ps = sPsi + ((size_t)fidx * Q + q) * 10;
-                const double gp[3] = {ps[1], ps[2], ps[3]};
+                const double *ps = sPsi + (size_t)f * 10 * Q + q;
+                const double gp[3] = {ps[Q], ps[2 * Q], ps[3 * Q]};
                 // Hessian entries H[j][k] from (xx yy zz xy xz yz)
-                const double Hs[3][3] = {{ps[4], ps[7], ps[8]}, {ps[7], ps[5], ps[9]}, {ps[8], ps[9], ps[6]}};
-                const double *U = sU + (size_t)arow * RS + 4 * q;
-                const double u = U[3];
+                const double Hs[3][3] = {{ps[4 * Q], ps[7 * Q], ps[8 * Q]},
+                                         {ps[7 * Q], ps[5 * Q], ps[9 * Q]},
+                                         {ps[8 * Q], ps[9 * Q], ps[6 * Q]}};
+                const double *U = sU + (size_t)(nfe + r) * RSB + q;
+                const double u = U[3 * Q];
                 for (int k = 0; k < 3; ++k) {
-                    const double dphi = -M * gp[k];
+                    const double dphi = -M * gp[k];   // d phi'/d tau_k
                     double c;
                     if (QMODE) {
                         c = 2.0 * dphi * u;
                     } else {
                         double gg = 0.0;
-                        for (int j = 0; j < 3; ++j) gg += -(gM[j] * gp[k] + M * Hs[j][k]) * U[j];
-                        c = gg + 2.0 * sV[q] * dphi * u;
+                        for (int jj = 0; jj < 3; ++jj) gg += -(gM[jj] * gp[k] + M * Hs[jj][k]) * U[jj * Q];
+                        c = gg + 2.0 * g[B_V * Q] * dphi * u;
                     }
-                    facc[k] += w * c;
+                    cf[k] = w * c;
                 }
             }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sC[((size_t)r * Q + q) * 3 + k] = cf[k];
         }
         __syncthreads();
     }
+    if (tid < nenr && q_end > q_begin)
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) facc[k] += sC[((size_t)tid * Q + q) * 3 + k];
     // per-group sums of the row forces, rows in order
     double *sF = sB;
-    if (own)
+    __syncthreads();
+    if (tid < nenr)
         for (int k = 0; k < 3; ++k) sF[3 * tid + k] = facc[k];
     __syncthreads();
     if (tid < max_ngrp) {
         double f[3] = {0.0, 0.0, 0.0};
         if (tid < ngrp) {
-            const GroupDev G = groups[el.grp_off + tid];
+            const GroupDev G = sG[tid];
             const int f0 = G.fbase, f1 = G.fbase + 2 * G.l + 1;
-            for (int t = 0; t < nloc - nfe; ++t) {
-                const int ff = (edof[el.edof_off + t] >> 3) & 255;
+            for (int t = 0; t < nenr; ++t) {
+                const int ff = (sEd[t] >> 3) & 255;
                 if (ff >= f0 && ff < f1)
                     for (int k = 0; k < 3; ++k) f[k] += sF[3 * t + k];
             }
@@ -333,7 +429,7 @@ hipError_t init_backward_attributes() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
 }
 
-size_t backward_lds_bytes(int npad, int nfun) { return BackwardLds<kBackwardQ>::bytes(npad, nfun); }
+size_t backward_lds_bytes(int npad, int nfun, int nimg) { return BackwardLds<kBackwardQ>::bytes(npad, nfun, nimg); }
 
 hipError_t launch_gather_adjoint(const KParams &kp, int64_t nel, const ElemDev *elems, const int32_t *edof,
                                  const int64_t *pt_off, const double *P, const double *kpt, double *Pt,

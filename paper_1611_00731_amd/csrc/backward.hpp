@@ -11,7 +11,7 @@ constexpr int kBackwardQ = 8;          // quadrature points per LDS stage of the
 constexpr int kBackwardMaxNloc = 96;   // largest element the adjoint kernel holds
 
 hipError_t init_backward_attributes();
-size_t backward_lds_bytes(int npad, int nfun);
+size_t backward_lds_bytes(int npad, int nfun, int nimg);
 hipError_t launch_gather_adjoint(const KParams &kp, int64_t nel, const ElemDev *elems, const int32_t *edof,
                                  const int64_t *pt_off, const double *P, const double *kpt, double *Pt,
                                  hipStream_t st);

@@ -580,7 +580,7 @@ static int plan_backward(pufe_ctx *c, hipStream_t st) {
         max_nfun = std::max(max_nfun, el.nfun);
         pt_off[e + 1] = pt_off[e] + (int64_t)npad * npad;
     }
-    c->bw_lds = backward_lds_bytes(max_npad, max_nfun);
+    c->bw_lds = backward_lds_bytes(max_npad, max_nfun, std::max(pl.max_img, 1));
     if (c->bw_lds > kMaxDynLds) return fail(c, PUFE_ERR_UNSUPPORTED, "adjoint stage does not fit in LDS");
     c->bw_items.clear();
     const int mg = std::max(pl.max_ngrp, 1);
