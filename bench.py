@@ -36,7 +36,7 @@ PEAK = {"fp64": 78.6, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}   # TFLOP/s, d
 # device copy of known size.  It is reported only while the sources it was
 # measured on are unchanged (their SHA-256 is recorded next to the figure).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_f64_lih_cell_hbm_traffic.md")
-KERNEL_SOURCES = ["kernels.hip", "tables.hpp", "enrich.hpp", "basis.hpp", "device_common.hpp",
+KERNEL_SOURCES = ["kernels.hip", "stage.hpp", "tables.hpp", "enrich.hpp", "basis.hpp", "device_common.hpp",
                   "capi.cpp", "plan.cpp"]
 
 

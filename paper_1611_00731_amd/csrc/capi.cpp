@@ -61,7 +61,7 @@ struct pufe_ctx {
     std::vector<int64_t> leaf_off_h;
     std::vector<ItemDev> items, items_split;
     size_t lds = 0;
-    int max_rows = 16, max_rows_split = 16;
+    int max_rows = 16, max_rows_split = 16, max_item_leaves_split = 1;
     int64_t part_slots = 0;
     double tune_items = 4096.0;
     int tune_block = kBlockTiles;
@@ -299,8 +299,9 @@ static void plan_items(pufe_ctx *c, double target_items, int block_tiles) {
     // the split stage keeps bf16 limbs of every row: use the largest tile
     // block whose three-limb stage fits in LDS
     for (int b = block_tiles; b >= 1; --b) {
-        c->items_split = make_items(c, b, &c->max_rows_split, nullptr);
-        if (split_lds_bytes(3, c->max_rows_split, nfun) <= kMaxDynLds) break;
+        c->items_split = make_items(c, b, &c->max_rows_split, &c->max_item_leaves_split);
+        if (split_lds_bytes(3, c->max_rows_split, nfun, c->plan.max_img, c->max_item_leaves_split, n3) <= kMaxDynLds)
+            break;
     }
 }
 
@@ -478,11 +479,12 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
     const Plan &pl = ctx->plan;
     if (precision == PUFE_PREC_BF16X3 || precision == PUFE_PREC_BF16X6) {
         const int nl = precision == PUFE_PREC_BF16X3 ? 2 : 3;
-        const size_t lds = split_lds_bytes(nl, ctx->max_rows_split, std::max(pl.max_nfun, 1));
+        const size_t lds = split_lds_bytes(nl, ctx->max_rows_split, std::max(pl.max_nfun, 1), pl.max_img,
+                                           ctx->max_item_leaves_split, pl.kp.n3);
         if (lds > kMaxDynLds) return fail(ctx, PUFE_ERR_UNSUPPORTED, "split stage does not fit in LDS");
         {
             TimedRegion tr(ctx, 0, st);
-            CHECK_HIP(ctx, launch_contract_split(nl, pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p,
+            CHECK_HIP(ctx, launch_contract_split(nl, pl.max_l, pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p,
                                                  ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                                  ctx->d_leaves.p, d_V, ctx->d_partial.p, lds, st),
                       "split contraction");
@@ -902,7 +904,8 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     b->device = ctxs[0]->device;
     if (hipSetDevice(b->device) != hipSuccess) { delete b; return PUFE_ERR_HIP; }
-    int max_rows = 16, max_rows_split = 16, max_nfun = 1, max_img = 0, max_leaves = 1, max_n3 = 1;
+    int max_rows = 16, max_rows_split = 16, max_nfun = 1, max_img = 0, max_leaves = 1, max_leaves_split = 1,
+        max_n3 = 1;
     b->lists.assign(27, {});
     for (int pass = 0; pass < 2; ++pass) {
         std::vector<std::pair<double, size_t>> order;
@@ -928,6 +931,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         max_nfun = std::max(max_nfun, c->plan.max_nfun);
         max_img = std::max(max_img, c->plan.max_img);
         max_leaves = std::max(max_leaves, c->max_item_leaves);
+        max_leaves_split = std::max(max_leaves_split, c->max_item_leaves_split);
         max_n3 = std::max(max_n3, c->plan.kp.n3);
         b->max_l = std::max(b->max_l, c->plan.max_l);
         for (int64_t e = 0; e < c->plan.nel; ++e) {
@@ -949,7 +953,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     b->lds_f64 = contract_lds_bytes(b->q, max_rows, max_nfun, max_img, max_leaves, max_n3);
     b->grid_f64 = ncu * persistent_blocks_per_cu(b->lds_f64);
     for (int k = 0; k < 2; ++k) {
-        b->lds_split[k] = split_lds_bytes(k + 2, max_rows_split, max_nfun);
+        b->lds_split[k] = split_lds_bytes(k + 2, max_rows_split, max_nfun, max_img, max_leaves_split, max_n3);
         b->grid_split[k] = ncu * persistent_blocks_per_cu(b->lds_split[k]);
     }
     hipStream_t st = nullptr;
@@ -1041,7 +1045,7 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
             const int k = precision == PUFE_PREC_BF16X3 ? 0 : 1;
             if (b->lds_split[k] > kMaxDynLds) e = hipErrorInvalidValue;
             else
-                e = launch_split_persistent(k + 2, b->d_ctxs.p, b->d_items_split.p, (int)b->items_split.size(), b->d_counter.p,
+                e = launch_split_persistent(k + 2, b->max_l, b->d_ctxs.p, b->d_items_split.p, (int)b->items_split.size(), b->d_counter.p,
                                             b->grid_split[k], b->lds_split[k], b->cap);
         }
         if (e == hipSuccess) e = launch_chunk_reduce_batch(b->d_ctxs.p, b->d_reduce.p, (int)b->reduce.size(), b->cap);

@@ -5,19 +5,21 @@
 // from the limb products of the same order of magnitude:
 //   BF16X3: a0 b0 + a0 b1 + a1 b0            (two limbs, three products)
 //   BF16X6: ... + a1 b1 + a0 b2 + a2 b0      (three limbs, six products)
-// accumulated by the MFMA in FP32 over one stage of 32 quadrature points, one
-// accumulator per operand component, and added to FP64 accumulators after
-// each stage.  The contraction is the one of
-// eq. disceig3d restricted to an element, written symmetrically:
+// One MFMA sums 32 points of one operand component; every component (the
+// three gradient components and V u for H, u for S) has its own FP32
+// accumulator per 32-point stage, added to FP64 accumulators after each
+// stage, so the MFMA's FP32 rounding stays at the scale of that component.
+// The contraction is the one of eq. disceig3d restricted to an element,
+// written symmetrically:
 //   S_e = U U^T, H_e = sum_d G_d G_d^T + (V U) U^T
 // with U[a][q] = sqrt(w_q) phi_a(x_q) and G_d[a][q] = sqrt(w_q / 2) d_d phi_a(x_q).
+// The per-point geometry, the enrichment functions and the FP64 basis rows
+// are built as in the FP64 kernel (stage.hpp) and split into limbs in LDS.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "basis.hpp"
-#include "device_common.hpp"
-#include "enrich.hpp"
 #include "kernels.hpp"
+#include "stage.hpp"
 #include "tables.hpp"
 
 namespace pufe {
@@ -26,46 +28,120 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+constexpr int kSplitThreads = 256;
+
 // FP32 -> bf16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ uint16_t bf16_bits(float f) {
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
     uint32_t u = __float_as_uint(f);
     u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return u >> 16;
 }
 
-__device__ __forceinline__ double bf16_value(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
 
-// LDS map: limbs[j][row][comp][q] (bf16 bits, comp = grad_x, grad_y, grad_z,
-// U, V U), then the FP64 enrichment functions and per-point geometry.
+// Limbs of x: the first from the FP64 value, the others from the residual,
+// which is exact in FP64 and carried on in FP32 (its FP32 rounding, below
+// 2^-32 |x|, is far under the last limb).
+template <int NL>
+__device__ __forceinline__ void split_limbs(double x, uint32_t *h) {
+    h[0] = bf16_bits((float)x);
+    float r = (float)(x - (double)bf16_float(h[0]));
+#pragma unroll
+    for (int j = 1; j < NL; ++j) {
+        h[j] = bf16_bits(r);
+        r -= bf16_float(h[j]);
+    }
+}
+
+// LDS map (per work item):
+//   sLimb[j][row][5][Q]  bf16 limb j of the weighted operands sqrt(w/2) d_x phi,
+//                        sqrt(w/2) d_y phi, sqrt(w/2) d_z phi, sqrt(w) phi,
+//                        V sqrt(w) phi (row stride RSB bytes)
+//   sV[Q], sPsi[f][4][Q], sGeo[GEO][Q], sImg, sGx, sGw   (FP64)
+//   sG, sEd, sLeaf, sPt, sRow
 template <int Q>
 struct SplitLds {
-    static constexpr int RSB = 5 * Q * 2 + 16;  // bytes per row and limb (padded)
-    static __host__ __device__ size_t bytes(int nlimb, int rows, int nfun) {
-        return (size_t)nlimb * rows * RSB + sizeof(double) * ((size_t)nfun * Q * 4 + (size_t)Q * 28);
+    static constexpr int RSB = 5 * Q * 2 + 16;  // bytes per row and limb: 16-byte rows, 20-word bank offset
+    static constexpr int GEO = 40;
+    static __host__ __device__ size_t bytes(int nlimb, int rows, int nfun, int nimg, int nleaf, int n3) {
+        return (size_t)nlimb * rows * RSB +
+               sizeof(double) * ((size_t)Q + (size_t)nfun * Q * 4 + (size_t)Q * GEO + (size_t)nimg * 3 +
+                                 2 * kMaxGauss) +
+               sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc +
+               sizeof(uint32_t) * ((size_t)nleaf + n3 + rows) + 64;
     }
 };
 
-template <int NL, int Q>
+template <int NL, int Q, int LMAX>
 __device__ __forceinline__ void contract_split_item(
-    const KParams &kp, const ItemDev &it, const ElemDev *__restrict__ elems,
+    const KParams &kpg, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial,
     unsigned char *smem_raw) {
-    static_assert(Q == 32, "one S product covers 32 points");
+    static_assert(Q == 32, "one MFMA covers the 32 points of a stage");
     constexpr int RSB = SplitLds<Q>::RSB;
-    const ElemDev &el = elems[it.elem];
+    constexpr int GEO = SplitLds<Q>::GEO;
+    constexpr int NT = kSplitThreads;
+    const KLocal kp = load_klocal(kpg);
+    const PUFE_GLOBAL ElemDev *gElems = (const PUFE_GLOBAL ElemDev *)elems;
+    const PUFE_GLOBAL GroupDev *gGroups = (const PUFE_GLOBAL GroupDev *)groups;
+    const PUFE_GLOBAL double *gImg = (const PUFE_GLOBAL double *)img;
+    const PUFE_GLOBAL int32_t *gEdof = (const PUFE_GLOBAL int32_t *)edof;
+    const PUFE_GLOBAL uint32_t *gLeaves = (const PUFE_GLOBAL uint32_t *)leaves;
+    const PUFE_GLOBAL double *gV = (const PUFE_GLOBAL double *)V;
+    PUFE_GLOBAL double *gPartial = (PUFE_GLOBAL double *)partial;
+    const PUFE_GLOBAL ElemDev &el = gElems[it.elem];
     const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun;
     const bool diag = it.I0 == it.J0;
     const int nrow = 16 * (diag ? it.nI : it.nI + it.nJ);
-    unsigned char *sLimb = smem_raw;
-    double *sPsi = (double *)(smem_raw + (size_t)NL * nrow * RSB);
-    double *sQ = sPsi + (size_t)nfun * Q * 4;
-    double *sXi = sQ, *sX = sQ + 3 * Q, *sW = sQ + 6 * Q, *sVq = sQ + 7 * Q, *sL = sQ + 8 * Q, *sD = sQ + 17 * Q;
-    double *sSw = sQ + 26 * Q, *sSw2 = sQ + 27 * Q;
+    const int img0 = ngrp > 0 ? gGroups[el.grp_off].img_off : 0;
+    const int nimg = ngrp > 0 ? gGroups[el.grp_off + ngrp - 1].img_off + gGroups[el.grp_off + ngrp - 1].nimg - img0 : 0;
+    const uint32_t n3 = (uint32_t)kp.n3, n = (uint32_t)kp.n;
+    unsigned char *sLimb = smem_raw;                                          // [NL][nrow][RSB]
+    double *sV = (double *)(smem_raw + (size_t)NL * nrow * RSB);              // [Q]
+    double *sPsi = sV + Q;                                                    // [nfun][4][Q]
+    double *sGeo = sPsi + (size_t)nfun * Q * 4;                               // [GEO][Q]
+    double *sImg = sGeo + (size_t)Q * GEO;
+    double *sGx = sImg + 3 * (size_t)nimg, *sGw = sGx + kMaxGauss;
+    GroupDev *sG = (GroupDev *)(sGw + kMaxGauss);
+    int32_t *sEd = (int32_t *)(sG + kMaxGroups);
+    uint32_t *sLeaf = (uint32_t *)(sEd + kMaxNloc);
+    uint32_t *sPt = sLeaf + (it.leaf_e - it.leaf_b);
+    int *sRow = (int *)(sPt + n3);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n3 = kp.n3;
-    const int64_t q_begin = it.leaf_b * n3, q_end = it.leaf_e * n3;
+    const int64_t q_begin = it.leaf_b * (int64_t)n3, q_end = it.leaf_e * (int64_t)n3;
+    const uint32_t nli = (uint32_t)(q_end - q_begin);
     const int ti0 = it.I0, tj0 = it.J0;
+    for (int k = tid; k < nloc - nfe; k += NT) sEd[k] = gEdof[el.edof_off + k];
+    for (int g = tid; g < ngrp; g += NT) {
+        const PUFE_GLOBAL GroupDev &Gg = gGroups[el.grp_off + g];
+        GroupDev G;
+        G.atom = Gg.atom;
+        G.desc = Gg.desc;
+        G.l = Gg.l;
+        G.fbase = Gg.fbase;
+        G.img_off = Gg.img_off - img0;   // rebased onto sImg
+        G.nimg = Gg.nimg;
+        G.a = Gg.a;
+        G.rc = Gg.rc;
+        sG[g] = G;
+    }
+    for (int k = tid; k < 3 * nimg; k += NT) sImg[k] = gImg[3 * (size_t)img0 + k];
+    for (int64_t k = tid; k < it.leaf_e - it.leaf_b; k += NT) sLeaf[k] = gLeaves[it.leaf_b + k];
+    for (uint32_t j = tid; j < n3; j += NT) sPt[j] = (j % n) | (((j / n) % n) << 8) | ((j / (n * n)) << 16);
+    for (int r = tid; r < nrow; r += NT) {
+        const int a = (diag || r < 16 * it.nI) ? 16 * ti0 + r : 16 * tj0 + (r - 16 * it.nI);
+        sRow[r] = a < nloc ? a : -1;
+    }
+    if (tid < kp.n) {
+        sGx[tid] = kpg.gx[tid];
+        sGw[tid] = kpg.gw[tid];
+    }
+    const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
+                           el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
+                           el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
+
+    // tile pairs of this item, round-robin over the four waves
     const int npairs = diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
     int pr_row[4], pr_col[4], pr_I[4], pr_J[4];
 #pragma unroll
@@ -74,7 +150,7 @@ __device__ __forceinline__ void contract_split_item(
         pr_row[u] = pr_col[u] = pr_I[u] = pr_J[u] = -1;
         if (pidx < npairs) {
             int a, b;
-            if (diag) {
+            if (diag) {  // enumerate (a <= b) column by column
                 b = 0;
                 while ((b + 1) * (b + 2) / 2 <= pidx) ++b;
                 a = pidx - b * (b + 1) / 2;
@@ -98,148 +174,106 @@ __device__ __forceinline__ void contract_split_item(
         accH[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
         accS[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
     }
-    const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
-                           el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
-                           el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
+    // the last Q threads build the geometry; V is read one stage ahead
+    const int gq = tid - (NT - Q);
+    double v = (gq >= 0 && (uint32_t)gq < nli) ? gV[q_begin + gq] : 0.0;
+    __syncthreads();
 
-    for (int64_t qb = q_begin; qb < q_end; qb += Q) {
-        if (tid < Q) {
-            const int64_t qg = qb + tid;
-            double xi[3] = {0.0, 0.0, 0.0}, w = 0.0, vq = 0.0;
-            if (qg < q_end) {
-                const int64_t lf = qg / n3;
-                leaf_point(kp, leaves[lf], (int)(qg - lf * n3), xi, &w);
-                vq = V[qg];
-            }
-            for (int d = 0; d < 3; ++d) sXi[3 * tid + d] = xi[d];
-            for (int c = 0; c < 3; ++c)
-                sX[3 * tid + c] = org[c] + 0.5 * (xi[0] + 1.0) * kp.E[c] + 0.5 * (xi[1] + 1.0) * kp.E[3 + c] +
-                                  0.5 * (xi[2] + 1.0) * kp.E[6 + c];
-            sW[tid] = w;
-            sVq[tid] = vq;
-            sSw[tid] = sqrt(w);
-            sSw2[tid] = sqrt(0.5 * w);
-            for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], sL + 9 * tid + 3 * d, sD + 9 * tid + 3 * d);
+    for (uint32_t lb = 0; lb < nli; lb += Q) {
+        // ---- phase 1: enrichment functions (eq. Psi, f(R) = 1) and geometry
+        if (gq >= 0) {
+            const double vn = (lb + Q + gq < nli) ? gV[q_begin + lb + Q + gq] : 0.0;
+            double xi[3], w;
+            item_point(kp, sLeaf, sPt, sGx, sGw, lb + gq, nli, n3, xi, &w);
+            point_geometry<Q>(kp, org, xi, w, sGeo + gq);
+            sV[gq] = v;
+            v = vn;
         }
-        __syncthreads();
-        for (int idx = tid; idx < ngrp * Q; idx += 256) {
+        for (int idx = tid; idx < ngrp * Q; idx += NT) {
             const int g = idx / Q, q = idx - g * Q;
-            const GroupDev G = groups[el.grp_off + g];
-            double *o = sPsi + ((size_t)G.fbase * Q + q) * 4;
-            switch (G.l) {
-                case 0: group_eval<0, Q * 4, 1>(G, img, sX + 3 * q, o); break;
-                case 1: group_eval<1, Q * 4, 1>(G, img, sX + 3 * q, o); break;
-                case 2: group_eval<2, Q * 4, 1>(G, img, sX + 3 * q, o); break;
-                default: group_eval<3, Q * 4, 1>(G, img, sX + 3 * q, o); break;
-            }
+            const GroupDev &G = sG[g];
+            double xi[3], w, x[3];
+            item_point(kp, sLeaf, sPt, sGx, sGw, lb + q, nli, n3, xi, &w);
+            point_position(kp, org, xi, x);
+            group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
         __syncthreads();
-        // rows: weighted operands, split into limbs
-        for (int idx = tid; idx < nrow * Q; idx += 256) {
-            const int r = idx / Q, q = idx - r * Q;
-            const int a = (diag || r < 16 * it.nI) ? 16 * ti0 + r : 16 * tj0 + (r - 16 * it.nI);
-            double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            if (a < nloc && sW[q] != 0.0) {
-                double val, g[3];
-                if (a < nfe) {
-                    const double *L = sL + 9 * q, *D = sD + 9 * q;
-                    const int n1 = kp.p + 1;
-                    const int a1 = a % n1, a2 = (a / n1) % n1, a3 = a / (n1 * n1);
-                    const double l1 = L[a1], l2 = L[3 + a2], l3 = L[6 + a3];
-                    const double dxi[3] = {D[a1] * l2 * l3, l1 * D[3 + a2] * l3, l1 * l2 * D[6 + a3]};
-                    val = l1 * l2 * l3;
-                    for (int c = 0; c < 3; ++c)
-                        g[c] = kp.Jt[3 * c] * dxi[0] + kp.Jt[3 * c + 1] * dxi[1] + kp.Jt[3 * c + 2] * dxi[2];
-                } else {
-                    const int pk = edof[el.edof_off + (a - nfe)];
-                    const int c = pk & 7, f = (pk >> 3) & 255;
-                    double m[3], dm[3];
-                    for (int d = 0; d < 3; ++d) {
-                        const double t = sXi[3 * q + d];
-                        const int bit = (c >> d) & 1;
-                        m[d] = bit ? 0.5 * (1.0 + t) : 0.5 * (1.0 - t);
-                        dm[d] = bit ? 0.5 : -0.5;
-                    }
-                    const double M = m[0] * m[1] * m[2];
-                    const double dM[3] = {dm[0] * m[1] * m[2], m[0] * dm[1] * m[2], m[0] * m[1] * dm[2]};
-                    const double *ps = sPsi + ((size_t)f * Q + q) * 4;
-                    for (int cc = 0; cc < 3; ++cc) {
-                        const double gM = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
-                        g[cc] = gM * ps[0] + M * ps[1 + cc];
-                    }
-                    val = M * ps[0];
-                }
-                const double s2 = sSw2[q], s1 = sSw[q];
-                v[0] = s2 * g[0];
-                v[1] = s2 * g[1];
-                v[2] = s2 * g[2];
-                v[3] = s1 * val;
-                v[4] = sVq[q] * v[3];
+        // ---- phase 2: weighted rows at two adjacent points per thread, split
+        // into limbs and stored as bf16 pairs
+        for (int idx = tid; idx < nrow * (Q / 2); idx += NT) {
+            const int r = idx / (Q / 2), q0 = 2 * (idx - r * (Q / 2));
+            const int a = sRow[r];
+            uint32_t hv[2][5][NL];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int q = q0 + t;
+                const double *g = sGeo + q;
+                double val, gx[3];
+                local_row<Q>(kp, g, sPsi + q, sEd, a, nfe, &val, gx);
+                const double s2 = g[G_SW2 * Q], u = g[G_SW * Q] * val;
+                const double comp[5] = {s2 * gx[0], s2 * gx[1], s2 * gx[2], u, sV[q] * u};
+#pragma unroll
+                for (int c = 0; c < 5; ++c) split_limbs<NL>(comp[c], hv[t][c]);
             }
 #pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                double x = v[c];
+            for (int j = 0; j < NL; ++j)
 #pragma unroll
-                for (int j = 0; j < NL; ++j) {
-                    const uint16_t h = bf16_bits((float)x);
-                    *(uint16_t *)(sLimb + ((size_t)j * nrow + r) * RSB + (size_t)(c * Q + q) * 2) = h;
-                    x -= bf16_value(h);
-                }
-            }
+                for (int c = 0; c < 5; ++c)
+                    *(uint32_t *)(sLimb + ((size_t)j * nrow + r) * RSB + (size_t)(c * Q + q0) * 2) =
+                        hv[0][c][j] | (hv[1][c][j] << 16);
         }
         __syncthreads();
-        // MFMA over limb products; lane = i + 16 grp holds the 8 consecutive
-        // points 8 grp .. 8 grp + 7 of one component.  Every component (the
-        // three gradient components and V U against U for H, U against U for
-        // S) gets its own FP32 accumulator over the stage's 32 points, added
-        // to the FP64 accumulators afterwards: terms of one magnitude class
-        // share an FP32 sum, so the MFMA's internal FP32 rounding stays at the
-        // scale of that component rather than of the largest one.
-        const int r16 = lane & 15, grp = lane >> 4;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (pr_row[u] < 0) continue;
-            const unsigned char *rowA = sLimb + (size_t)(pr_row[u] + r16) * RSB;
-            const unsigned char *rowB = sLimb + (size_t)(pr_col[u] + r16) * RSB;
+        // ---- phase 3: MFMAs over limb products; lane = i + 16 grp holds the 8
+        // consecutive points 8 grp .. 8 grp + 7 of one component
+        {
+            const int r16 = lane & 15, grp = lane >> 4;
             const size_t LS = (size_t)nrow * RSB;  // limb stride
 #pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                // c = 0..2: gradient components (H); 3: V U x U (H); 4: U x U (S)
-                const int ca = c < 3 ? c : (c == 3 ? 4 : 3), cb = c < 3 ? c : 3;
-                const size_t offA = (size_t)(ca * Q + 8 * grp) * 2, offB = (size_t)(cb * Q + 8 * grp) * 2;
-                bf16x8 A[NL], B[NL];
+            for (int u = 0; u < 4; ++u) {
+                if (pr_row[u] < 0) continue;
+                const unsigned char *rowA = sLimb + (size_t)(pr_row[u] + r16) * RSB;
+                const unsigned char *rowB = sLimb + (size_t)(pr_col[u] + r16) * RSB;
 #pragma unroll
-                for (int j = 0; j < NL; ++j) {
-                    A[j] = *(const bf16x8 *)(rowA + j * LS + offA);
-                    B[j] = *(const bf16x8 *)(rowB + j * LS + offB);
-                }
-                f32x4 h = {0.f, 0.f, 0.f, 0.f};
-                if (NL == 3) {
-                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], h, 0, 0, 0);
-                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], h, 0, 0, 0);
-                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], h, 0, 0, 0);
-                }
-                h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], h, 0, 0, 0);
-                h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], h, 0, 0, 0);
-                h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], h, 0, 0, 0);
-                if (c < 4) {
+                for (int c = 0; c < 5; ++c) {
+                    // c = 0..2: gradient components (H); 3: V U x U (H); 4: U x U (S)
+                    const int ca = c < 3 ? c : (c == 3 ? 4 : 3), cb = c < 3 ? c : 3;
+                    const size_t offA = (size_t)(ca * Q + 8 * grp) * 2, offB = (size_t)(cb * Q + 8 * grp) * 2;
+                    bf16x8 A[NL], B[NL];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) accH[u][r] += (double)h[r];
-                } else {
+                    for (int j = 0; j < NL; ++j) {
+                        A[j] = *(const bf16x8 *)(rowA + j * LS + offA);
+                        B[j] = *(const bf16x8 *)(rowB + j * LS + offB);
+                    }
+                    f32x4 h = {0.f, 0.f, 0.f, 0.f};
+                    if (NL == 3) {
+                        h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], h, 0, 0, 0);
+                        h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], h, 0, 0, 0);
+                        h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], h, 0, 0, 0);
+                    }
+                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], h, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], h, 0, 0, 0);
+                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], h, 0, 0, 0);
+                    if (c < 4) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) accS[u][r] += (double)h[r];
+                        for (int r = 0; r < 4; ++r) accH[u][r] += (double)h[r];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) accS[u][r] += (double)h[r];
+                    }
                 }
             }
         }
         __syncthreads();
     }
+    // ---- partial tiles, row-major 16x16.  bf16 16x16x32 accumulator layout:
+    // register r of lane l holds D[4 (l / 16) + r][l % 16].
     const int T = (nloc + 15) / 16;
     const int64_t P = (int64_t)T * (T + 1) / 2;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         if (pr_row[u] < 0) continue;
         const int64_t pidx = (int64_t)pr_J[u] * (pr_J[u] + 1) / 2 + pr_I[u];
-        double *dst = partial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
+        PUFE_GLOBAL double *dst = gPartial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
         const int j = lane & 15, i0 = 4 * (lane >> 4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -249,21 +283,21 @@ __device__ __forceinline__ void contract_split_item(
     }
 }
 
-template <int NL, int Q>
-__global__ __launch_bounds__(256) void contract_split_kernel(
+template <int NL, int Q, int LMAX>
+__global__ __launch_bounds__(kSplitThreads) void contract_split_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const ItemDev it = items[blockIdx.x];
-    contract_split_item<NL, Q>(kp, it, elems, groups, img, edof, leaves, V, partial, smem_raw);
+    contract_split_item<NL, Q, LMAX>(kp, it, elems, groups, img, edof, leaves, V, partial, smem_raw);
 }
 
 // Persistent queue form (see contract_f64_persistent).
-template <int NL, int Q>
-__global__ __launch_bounds__(256) void contract_split_persistent(const CtxDev *__restrict__ ctxs,
-                                                                 const ItemDev *__restrict__ items, int n_items,
-                                                                 int *__restrict__ counter) {
+template <int NL, int Q, int LMAX>
+__global__ __launch_bounds__(kSplitThreads) void contract_split_persistent(const CtxDev *__restrict__ ctxs,
+                                                                           const ItemDev *__restrict__ items,
+                                                                           int n_items, int *__restrict__ counter) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ int s_idx;
     for (;;) {
@@ -274,7 +308,8 @@ __global__ __launch_bounds__(256) void contract_split_persistent(const CtxDev *_
         if (idx >= n_items) break;
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
-        contract_split_item<NL, Q>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem_raw);
+        contract_split_item<NL, Q, LMAX>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial,
+                                         smem_raw);
     }
 }
 
@@ -282,25 +317,37 @@ __global__ void reset_counter_split_kernel(int *counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
-hipError_t launch_split_persistent(int nlimb, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
-                                   int grid, size_t lds, hipStream_t st) {
+#define PUFE_SPLIT_DISPATCH(KERNEL, NLIMB, LM, ...)                                      \
+    do {                                                                                \
+        if (NLIMB == 2) {                                                               \
+            if (LM <= 1) hipLaunchKernelGGL((KERNEL<2, kSplitQ, 1>), __VA_ARGS__);      \
+            else hipLaunchKernelGGL((KERNEL<2, kSplitQ, 3>), __VA_ARGS__);              \
+        } else {                                                                        \
+            if (LM <= 1) hipLaunchKernelGGL((KERNEL<3, kSplitQ, 1>), __VA_ARGS__);      \
+            else hipLaunchKernelGGL((KERNEL<3, kSplitQ, 3>), __VA_ARGS__);              \
+        }                                                                               \
+    } while (0)
+
+hipError_t launch_split_persistent(int nlimb, int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items,
+                                   int *counter, int grid, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(reset_counter_split_kernel, dim3(1), dim3(64), 0, st, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
-    if (nlimb == 2)
-        hipLaunchKernelGGL((contract_split_persistent<2, kSplitQ>), dim3(grid), dim3(256), lds, st, ctxs, items,
-                           n_items, counter);
-    else
-        hipLaunchKernelGGL((contract_split_persistent<3, kSplitQ>), dim3(grid), dim3(256), lds, st, ctxs, items,
-                           n_items, counter);
+    PUFE_SPLIT_DISPATCH(contract_split_persistent, nlimb, lmax, dim3(grid), dim3(kSplitThreads), lds, st, ctxs,
+                        items, n_items, counter);
     return hipGetLastError();
 }
 
 hipError_t init_split_attributes() {
-    const void *ks[4] = {(const void *)contract_split_kernel<2, kSplitQ>, (const void *)contract_split_kernel<3, kSplitQ>,
-                         (const void *)contract_split_persistent<2, kSplitQ>,
-                         (const void *)contract_split_persistent<3, kSplitQ>};
+    const void *ks[8] = {(const void *)contract_split_kernel<2, kSplitQ, 1>,
+                         (const void *)contract_split_kernel<2, kSplitQ, 3>,
+                         (const void *)contract_split_kernel<3, kSplitQ, 1>,
+                         (const void *)contract_split_kernel<3, kSplitQ, 3>,
+                         (const void *)contract_split_persistent<2, kSplitQ, 1>,
+                         (const void *)contract_split_persistent<2, kSplitQ, 3>,
+                         (const void *)contract_split_persistent<3, kSplitQ, 1>,
+                         (const void *)contract_split_persistent<3, kSplitQ, 3>};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
         if (e != hipSuccess) return e;
@@ -308,20 +355,20 @@ hipError_t init_split_attributes() {
     return hipSuccess;
 }
 
-size_t split_lds_bytes(int nlimb, int rows, int nfun) { return SplitLds<kSplitQ>::bytes(nlimb, rows, nfun); }
+size_t split_lds_bytes(int nlimb, int rows, int nfun, int nimg, int nleaf, int n3) {
+    return SplitLds<kSplitQ>::bytes(nlimb, rows, nfun, nimg, nleaf, n3);
+}
 
-hipError_t launch_contract_split(int nlimb, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
-                                 const GroupDev *groups, const double *img, const int32_t *edof,
+hipError_t launch_contract_split(int nlimb, int lmax, const KParams &kp, int n_items, const ItemDev *items,
+                                 const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                  const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                  hipStream_t st) {
     if (n_items == 0) return hipSuccess;
-    if (nlimb == 2)
-        hipLaunchKernelGGL((contract_split_kernel<2, kSplitQ>), dim3(n_items), dim3(256), lds, st, kp, items, elems,
-                           groups, img, edof, leaves, V, partial);
-    else
-        hipLaunchKernelGGL((contract_split_kernel<3, kSplitQ>), dim3(n_items), dim3(256), lds, st, kp, items, elems,
-                           groups, img, edof, leaves, V, partial);
+    PUFE_SPLIT_DISPATCH(contract_split_kernel, nlimb, lmax, dim3(n_items), dim3(kSplitThreads), lds, st, kp, items,
+                        elems, groups, img, edof, leaves, V, partial);
     return hipGetLastError();
 }
+
+#undef PUFE_SPLIT_DISPATCH
 
 }  // namespace pufe

@@ -1,0 +1,167 @@
+// Device building blocks shared by the FP64 and split-precision contraction
+// kernels: per-point geometry of a work item's stage, the enrichment
+// functions of a group, and the unweighted local basis functions (FE, and PU
+// times enrichment) with their gradients (eq. pufebasis).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "enrich.hpp"
+#include "tables.hpp"
+
+// Global-memory pointer qualifier (address space 1 of the AMDGPU target).
+#define PUFE_GLOBAL __attribute__((address_space(1)))
+
+namespace pufe {
+
+// Geometry record of one point (offsets into GEO doubles):
+//   xi, x, sqrt(w/2), sqrt(w), 1D FE values L[d][0..2] and derivatives
+//   D[d][0..2], trilinear PU values M_c and their 1D factors m_d^0, m_d^1.
+enum { G_XI = 0, G_X = 3, G_SW2 = 6, G_SW = 7, G_L = 8, G_D = 17, G_M = 26, G_M1 = 34 };
+
+// Enrichment functions of one group at one point, for groups up to LMAX.
+template <int LMAX, int Q>
+__device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double *__restrict__ img, const double *x,
+                                                double *o) {
+    switch (G.l) {
+        case 0: group_eval<0, 4 * Q, Q>(G, img, x, o); break;
+        case 1: if (LMAX >= 1) group_eval<1, 4 * Q, Q>(G, img, x, o); break;
+        case 2: if (LMAX >= 2) group_eval<2, 4 * Q, Q>(G, img, x, o); break;
+        default: if (LMAX >= 3) group_eval<3, 4 * Q, Q>(G, img, x, o); break;
+    }
+}
+
+// The per-launch constants the inner loops use, copied out of KParams into
+// registers once per item (KParams of a batched launch lives in global memory).
+struct KLocal {
+    double E[9], Jt[9], jac;
+    int p, n, n3;
+};
+
+__device__ __forceinline__ KLocal load_klocal(const KParams &kp) {
+    KLocal k;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        k.E[i] = kp.E[i];
+        k.Jt[i] = kp.Jt[i];
+    }
+    k.jac = kp.jac;
+    k.p = kp.p;
+    k.n = kp.n;
+    k.n3 = kp.n3;
+    return k;
+}
+
+// Reference coordinates and weight of point li of the item (w = 0 past the end).
+__device__ __forceinline__ void item_point(const KLocal &kp, const uint32_t *sLeaf, const uint32_t *sPt,
+                                           const double *sGx, const double *sGw, uint32_t li, uint32_t nli,
+                                           uint32_t n3, double *xi, double *w) {
+    xi[0] = xi[1] = xi[2] = 0.0;
+    *w = 0.0;
+    if (li >= nli) return;
+    const uint32_t lf = li / n3, j = li - lf * n3;
+    const uint32_t code = sLeaf[lf], pt = sPt[j];
+    const int lev = (int)(code >> 27);
+    const double h = 1.0 / (double)(1u << lev);
+    const int c[3] = {(int)(code & 511u), (int)((code >> 9) & 511u), (int)((code >> 18) & 511u)};
+    const int k[3] = {(int)(pt & 255u), (int)((pt >> 8) & 255u), (int)(pt >> 16)};
+    double wt = h * h * h * kp.jac;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        xi[d] = -1.0 + (2.0 * c[d] + 1.0 + sGx[k[d]]) * h;
+        wt *= sGw[k[d]];
+    }
+    *w = wt;
+}
+
+__device__ __forceinline__ void point_position(const KLocal &kp, const double *org, const double *xi, double *x) {
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+        x[cc] = org[cc] + 0.5 * (xi[0] + 1.0) * kp.E[cc] + 0.5 * (xi[1] + 1.0) * kp.E[3 + cc] +
+                0.5 * (xi[2] + 1.0) * kp.E[6 + cc];
+}
+
+// Geometry record of one point, field f at g[f * Q].
+template <int Q>
+__device__ __forceinline__ void point_geometry(const KLocal &kp, const double *org, const double *xi, double w,
+                                               double *g) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[(G_XI + d) * Q] = xi[d];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+        g[(G_X + cc) * Q] = org[cc] + 0.5 * (xi[0] + 1.0) * kp.E[cc] + 0.5 * (xi[1] + 1.0) * kp.E[3 + cc] +
+                            0.5 * (xi[2] + 1.0) * kp.E[6 + cc];
+    g[G_SW2 * Q] = sqrt(0.5 * w);
+    g[G_SW * Q] = sqrt(w);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double t = xi[d];
+        if (kp.p == 1) {
+            g[(G_L + 3 * d) * Q] = 0.5 * (1.0 - t);
+            g[(G_L + 3 * d + 1) * Q] = 0.5 * (1.0 + t);
+            g[(G_D + 3 * d) * Q] = -0.5;
+            g[(G_D + 3 * d + 1) * Q] = 0.5;
+        } else {
+            g[(G_L + 3 * d) * Q] = 0.5 * t * (t - 1.0);
+            g[(G_L + 3 * d + 1) * Q] = 1.0 - t * t;
+            g[(G_L + 3 * d + 2) * Q] = 0.5 * t * (t + 1.0);
+            g[(G_D + 3 * d) * Q] = t - 0.5;
+            g[(G_D + 3 * d + 1) * Q] = -2.0 * t;
+            g[(G_D + 3 * d + 2) * Q] = t + 0.5;
+        }
+        g[(G_M1 + 2 * d) * Q] = 0.5 * (1.0 - t);
+        g[(G_M1 + 2 * d + 1) * Q] = 0.5 * (1.0 + t);
+    }
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8)
+        g[(G_M + c8) * Q] = (0.5 + ((c8 & 1) ? 0.5 : -0.5) * xi[0]) * (0.5 + ((c8 & 2) ? 0.5 : -0.5) * xi[1]) *
+                            (0.5 + ((c8 & 4) ? 0.5 : -0.5) * xi[2]);
+}
+
+// Value and gradient (physical coordinates) of local function a at the point
+// whose geometry record starts at g (field f at g[f * Q]); ps points to the
+// element's enrichment table at that point (function f, component c at
+// ps[(4 f + c) * Q]).  a < 0 (padding row) gives zeros.
+template <int Q>
+__device__ __forceinline__ void local_row(const KLocal &kp, const double *g, const double *ps, const int32_t *sEd,
+                                          int a, int nfe, double *val, double *gx) {
+    *val = 0.0;
+    gx[0] = gx[1] = gx[2] = 0.0;
+    if (a < 0) return;
+    if (a < nfe) {
+        int a1, a2, a3;
+        if (kp.p == 2) {
+            a1 = a % 3;
+            a2 = (a / 3) % 3;
+            a3 = a / 9;
+        } else {
+            a1 = a & 1;
+            a2 = (a >> 1) & 1;
+            a3 = a >> 2;
+        }
+        const double l1 = g[(G_L + a1) * Q], l2 = g[(G_L + 3 + a2) * Q], l3 = g[(G_L + 6 + a3) * Q];
+        *val = l1 * l2 * l3;
+        const double dxi[3] = {g[(G_D + a1) * Q] * l2 * l3, l1 * g[(G_D + 3 + a2) * Q] * l3,
+                               l1 * l2 * g[(G_D + 6 + a3) * Q]};
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            gx[cc] = kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2];
+        return;
+    }
+    // PU corner c (trilinear) times enrichment function f
+    const int pk = sEd[a - nfe];
+    const int c = pk & 7, f = (pk >> 3) & 255;
+    const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
+    const double m0 = g[(G_M1 + b0) * Q], m1 = g[(G_M1 + 2 + b1) * Q], m2 = g[(G_M1 + 4 + b2) * Q];
+    const double M = g[(G_M + c) * Q];
+    const double *pf = ps + (size_t)f * 4 * Q;
+    const double p0 = pf[0], p1 = pf[Q], p2 = pf[2 * Q], p3 = pf[3 * Q];
+    const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2, m0 * m1 * (b2 ? 0.5 : -0.5)};
+    *val = M * p0;
+    // grad(M Psi) = Psi grad M + M grad Psi, grad M via Jt
+    gx[0] = (kp.Jt[0] * dM[0] + kp.Jt[1] * dM[1] + kp.Jt[2] * dM[2]) * p0 + M * p1;
+    gx[1] = (kp.Jt[3] * dM[0] + kp.Jt[4] * dM[1] + kp.Jt[5] * dM[2]) * p0 + M * p2;
+    gx[2] = (kp.Jt[6] * dM[0] + kp.Jt[7] * dM[1] + kp.Jt[8] * dM[2]) * p0 + M * p3;
+}
+
+}  // namespace pufe
