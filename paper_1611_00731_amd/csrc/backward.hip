@@ -100,23 +100,22 @@ __device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double 
 }
 
 // LDS map of the adjoint (per work item):
-//   sP[npad][RSP]   Ps (or Qs) of the element, RSP = npad + 1
-//   sB[npad][RSB]   B = [d_x phi, d_y phi, d_z phi, phi] at the stage points,
-//                   column c * Q + q
-//   sU[npad][RSB]   U = Ps B
-//   sPsi[f][10][Q]  value, gradient and Hessian of the enrichment functions
-//   sGeo[GEO][Q]    per-point geometry, field-major
-//   sC[r][Q][3]     force contributions of enriched row r at the stage points
-//                   (in the space of sB, which is free by then)
-//   sG, sEd, sImg   groups, enriched-function table, image centres
+//   sP[npad][RSP]    Ps (or Qs) of the element, RSP = npad + 1
+//   sB[npad][4][Q]   B = [d_x phi, d_y phi, d_z phi, phi] at the stage points
+//   sUe[nenr][4][Q]  U = Ps B on the enriched rows (the only ones the force needs)
+//   sPsi[f][10][Q]   value, gradient and Hessian of the enrichment functions
+//   sGeo[GEO][Q]     per-point geometry, field-major
+//   sC[r][Q][3]      force contributions of enriched row r at the stage points
+//                    (in the space of sB, which is free by then)
+//   sImg, sG, sEd    image centres, groups, enriched-function table
 template <int Q>
 struct BackwardLds {
     static constexpr int RSB = 4 * Q + 2;   // 16-byte rows
     static constexpr int GEO = 40;
     static_assert(RSB >= 3 * Q, "force contributions reuse the rows of sB");
-    static __host__ __device__ size_t bytes(int npad, int nfun, int nimg) {
-        return sizeof(double) * ((size_t)npad * (npad + 1) + 2 * (size_t)npad * RSB + (size_t)nfun * Q * 10 +
-                                 (size_t)Q * GEO + (size_t)nimg * 3) +
+    static __host__ __device__ size_t bytes(int npad, int nenr, int nfun, int nimg) {
+        return sizeof(double) * ((size_t)npad * (npad + 1) + (size_t)npad * RSB + (size_t)nenr * RSB +
+                                 (size_t)nfun * Q * 10 + (size_t)Q * GEO + (size_t)nimg * 3) +
                sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc + 64;
     }
 };
@@ -124,38 +123,59 @@ struct BackwardLds {
 // geometry fields (index f at sGeo[f * Q + q])
 enum { B_XI = 0, B_X = 3, B_W = 6, B_V = 7, B_L = 8, B_D = 17, B_M = 26, B_M1 = 34 };
 
-// U tiles (I, J) of one wave, NU at a time: U = Ps B over K = npad.
-template <int NU>
+// U = Ps B for operand component c (one per wave), all T row tiles at once:
+// output tile I covers rows 16 I .. 16 I + 15 and the Q = 16 stage points of
+// component c, K = npad.  The U rows of the enriched functions go to sUe; the
+// wave holding the value component (c = 3) also forms the density
+// dL/dV_q = w_q sum_a phi_a (Ps phi)_a from its accumulators.
+template <int T, int Q, bool DENS>
 __device__ __forceinline__ void backward_mfma(const double *__restrict__ sP, const double *__restrict__ sB,
-                                              double *__restrict__ sU, int RSP, int RSB, int T, int NJ, int wave,
-                                              int lane) {
+                                              double *__restrict__ sUe, const double *__restrict__ sGeo, int RSP,
+                                              int nloc, int nfe, int c, int lane, int64_t qb, int64_t q_end,
+                                              double *__restrict__ dLdV) {
+    static_assert(Q == 16, "one output tile spans the stage");
+    constexpr int RSB = BackwardLds<Q>::RSB;
     const int r16 = lane & 15, k4 = lane >> 4;
-    int I[NU], J[NU];
+    double4_t acc[T];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        const int t = wave + 4 * u;
-        I[u] = t / NJ;
-        J[u] = t - I[u] * NJ;
-    }
-    double4_t acc[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) acc[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int I = 0; I < T; ++I) acc[I] = (double4_t){0.0, 0.0, 0.0, 0.0};
     for (int kb = 0; kb < 4 * T; ++kb) {
-        double a[NU], b[NU];
+        const double b = sB[(size_t)(4 * kb + k4) * RSB + c * Q + r16];
+        double a[T];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            a[u] = sP[(size_t)(16 * I[u] + r16) * RSP + 4 * kb + k4];
-            b[u] = sB[(size_t)(4 * kb + k4) * RSB + 16 * J[u] + r16];
-        }
+        for (int I = 0; I < T; ++I) a[I] = sP[(size_t)(16 * I + r16) * RSP + 4 * kb + k4];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u], 0, 0, 0);
+        for (int I = 0; I < T; ++I) acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], b, acc[I], 0, 0, 0);
     }
-    // FP64 16x16x4 accumulator: register r of lane l is row (l / 16) + 4 r, column l % 16
+    // FP64 16x16x4 accumulator: register r of lane l is row (l / 16) + 4 r, column (point) l % 16
+    double dens = 0.0;
 #pragma unroll
-    for (int u = 0; u < NU; ++u)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            sU[(size_t)(16 * I[u] + k4 + 4 * r) * RSB + 16 * J[u] + r16] = acc[u][r];
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * I + k4 + 4 * r;
+            if (row >= nfe && row < nloc) sUe[(size_t)(row - nfe) * RSB + c * Q + r16] = acc[I][r];
+            if (DENS && row < nloc) dens += sB[(size_t)row * RSB + 3 * Q + r16] * acc[I][r];
+        }
+    if (DENS) {
+        dens += __shfl_xor(dens, 16, 64);
+        dens += __shfl_xor(dens, 32, 64);
+        const int64_t qg = qb + r16;
+        if (k4 == 0 && qg < q_end) dLdV[qg] = sGeo[B_W * Q + r16] * dens;
+    }
+}
+
+template <int Q, bool DENS>
+__device__ __forceinline__ void backward_mfma_dispatch(int T, const double *sP, const double *sB, double *sUe,
+                                                       const double *sGeo, int RSP, int nloc, int nfe, int c,
+                                                       int lane, int64_t qb, int64_t q_end, double *dLdV) {
+    switch (T) {
+        case 1: backward_mfma<1, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
+        case 2: backward_mfma<2, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
+        case 3: backward_mfma<3, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
+        case 4: backward_mfma<4, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
+        default: backward_mfma<5, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
+    }
 }
 
 // One work group per (element, range of leaves).  QMODE = false: the P pass
@@ -170,19 +190,18 @@ __global__ __launch_bounds__(256) void backward_kernel(
     extern __shared__ __attribute__((aligned(16))) double smem[];
     constexpr int RSB = BackwardLds<Q>::RSB;
     constexpr int NT = 256;
-    static_assert(NT / Q >= 32 && (NT / Q) % 32 == 0, "dL/dV uses 32 lanes per point");
     const ItemDev it = items[blockIdx.x];
     const ElemDev &el = elems[it.elem];
     const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun, nenr = nloc - nfe;
-    const int T = (nloc + 15) / 16, npad = 16 * T, RSP = npad + 1, NJ = (4 * Q) / 16;
+    const int T = (nloc + 15) / 16, npad = 16 * T, RSP = npad + 1;
     const int img0 = ngrp > 0 ? groups[el.grp_off].img_off : 0;
     const int nimg = ngrp > 0 ? groups[el.grp_off + ngrp - 1].img_off + groups[el.grp_off + ngrp - 1].nimg - img0 : 0;
     double *sP = smem;
     double *sB = sP + (size_t)npad * RSP;
-    double *sU = sB + (size_t)npad * RSB;
-    double *sPsi = sU + (size_t)npad * RSB;
+    double *sUe = sB + (size_t)npad * RSB;
+    double *sPsi = sUe + (size_t)nenr * RSB;
     double *sGeo = sPsi + (size_t)nfun * Q * 10;
-    double *sC = sB;   // [nenr][Q][3], written after the density phase has read sB
+    double *sC = sB;   // [nenr][Q][3], written after the MFMA phase has read sB
     double *sImg = sGeo + (size_t)Q * BackwardLds<Q>::GEO;
     GroupDev *sG = (GroupDev *)(sImg + 3 * (size_t)nimg);
     int32_t *sEd = (int32_t *)(sG + kMaxGroups);
@@ -207,8 +226,6 @@ __global__ __launch_bounds__(256) void backward_kernel(
     // force accumulation: thread t owns enriched row nfe + t (rows of one
     // stage are summed over its points in order, then over the stages)
     double facc[3] = {0.0, 0.0, 0.0};
-    const int ntile = T * NJ;
-    const int nu = ntile > wave ? (ntile - wave + 3) / 4 : 0;
     const int gq = tid - (NT - Q);   // the last Q threads build the geometry
     __syncthreads();
 
@@ -313,28 +330,14 @@ __global__ __launch_bounds__(256) void backward_kernel(
             o[3 * Q] = val;
         }
         __syncthreads();
-        // ---- phase 3: U = Ps B on the MFMAs, output tiles round-robin over waves
-        switch (nu) {
-            case 1: backward_mfma<1>(sP, sB, sU, RSP, RSB, T, NJ, wave, lane); break;
-            case 2: backward_mfma<2>(sP, sB, sU, RSP, RSB, T, NJ, wave, lane); break;
-            case 3: backward_mfma<3>(sP, sB, sU, RSP, RSB, T, NJ, wave, lane); break;
-            default: break;
-        }
+        // ---- phase 3: U = Ps B on the MFMAs, one operand component per wave;
+        // the value component also gives the density
+        if (!QMODE && dLdV != nullptr && wave == 3)
+            backward_mfma_dispatch<Q, true>(T, sP, sB, sUe, sGeo, RSP, nloc, nfe, wave, lane, qb, q_end, dLdV);
+        else
+            backward_mfma_dispatch<Q, false>(T, sP, sB, sUe, sGeo, RSP, nloc, nfe, wave, lane, qb, q_end, dLdV);
         __syncthreads();
-        // ---- phase 4: density dL/dV_q = w_q sum_a phi_a (Ps phi)_a, 32 lanes per point
-        if (!QMODE && dLdV != nullptr) {
-            const int q = tid >> 5, j = tid & 31;
-            if (q < Q) {
-                double s = 0.0;
-                for (int a = j; a < nloc; a += 32) s += sB[(size_t)a * RSB + 3 * Q + q] * sU[(size_t)a * RSB + 3 * Q + q];
-#pragma unroll
-                for (int off = 16; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-                const int64_t qg = qb + q;
-                if (j == 0 && qg < q_end) dLdV[qg] = sGeo[B_W * Q + q] * s;
-            }
-        }
-        __syncthreads();
-        // ---- phase 5: force contributions of every (enriched row, point)
+        // ---- phase 4: force contributions of every (enriched row, point)
         for (int idx = tid; idx < nenr * Q; idx += NT) {
             const int r = idx / Q, q = idx - r * Q;
             const double *g = sGeo + q;
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
                 const double Hs[3][3] = {{ps[4 * Q], ps[7 * Q], ps[8 * Q]},
                                          {ps[7 * Q], ps[5 * Q], ps[9 * Q]},
                                          {ps[8 * Q], ps[9 * Q], ps[6 * Q]}};
-                const double *U = sU + (size_t)(nfe + r) * RSB + q;
+                const double *U = sUe + (size_t)r * RSB + q;
                 const double u = U[3 * Q];
                 for (int k = 0; k < 3; ++k) {
                     const double dphi = -M * gp[k];   // d phi'/d tau_k
@@ -429,7 +432,9 @@ hipError_t init_backward_attributes() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
 }
 
-size_t backward_lds_bytes(int npad, int nfun, int nimg) { return BackwardLds<kBackwardQ>::bytes(npad, nfun, nimg); }
+size_t backward_lds_bytes(int npad, int nenr, int nfun, int nimg) {
+    return BackwardLds<kBackwardQ>::bytes(npad, nenr, nfun, nimg);
+}
 
 hipError_t launch_gather_adjoint(const KParams &kp, int64_t nel, const ElemDev *elems, const int32_t *edof,
                                  const int64_t *pt_off, const double *P, const double *kpt, double *Pt,

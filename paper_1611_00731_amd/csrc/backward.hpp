@@ -7,11 +7,11 @@
 
 namespace pufe {
 
-constexpr int kBackwardQ = 8;          // quadrature points per LDS stage of the adjoint
-constexpr int kBackwardMaxNloc = 96;   // largest element the adjoint kernel holds
+constexpr int kBackwardQ = 16;         // quadrature points per LDS stage of the adjoint
+constexpr int kBackwardMaxNloc = 80;   // largest element the adjoint kernel holds (5 row tiles)
 
 hipError_t init_backward_attributes();
-size_t backward_lds_bytes(int npad, int nfun, int nimg);
+size_t backward_lds_bytes(int npad, int nenr, int nfun, int nimg);
 hipError_t launch_gather_adjoint(const KParams &kp, int64_t nel, const ElemDev *elems, const int32_t *edof,
                                  const int64_t *pt_off, const double *P, const double *kpt, double *Pt,
                                  hipStream_t st);

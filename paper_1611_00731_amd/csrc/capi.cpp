@@ -570,7 +570,7 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
 // group partial forces in a fixed order.
 static int plan_backward(pufe_ctx *c, hipStream_t st) {
     Plan &pl = c->plan;
-    int max_npad = 16, max_nfun = 1;
+    int max_npad = 16, max_nfun = 1, max_nenr = 1;
     std::vector<int64_t> pt_off(pl.nel + 1, 0);
     for (int64_t e = 0; e < pl.nel; ++e) {
         const ElemDev &el = pl.elems[e];
@@ -580,9 +580,10 @@ static int plan_backward(pufe_ctx *c, hipStream_t st) {
         int npad = 16 * ((el.nloc + 15) / 16);
         max_npad = std::max(max_npad, npad);
         max_nfun = std::max(max_nfun, el.nfun);
+        max_nenr = std::max(max_nenr, el.nloc - el.nfe);
         pt_off[e + 1] = pt_off[e] + (int64_t)npad * npad;
     }
-    c->bw_lds = backward_lds_bytes(max_npad, max_nfun, std::max(pl.max_img, 1));
+    c->bw_lds = backward_lds_bytes(max_npad, max_nenr, max_nfun, std::max(pl.max_img, 1));
     if (c->bw_lds > kMaxDynLds) return fail(c, PUFE_ERR_UNSUPPORTED, "adjoint stage does not fit in LDS");
     c->bw_items.clear();
     const int mg = std::max(pl.max_ngrp, 1);

@@ -271,6 +271,9 @@ __device__ __forceinline__ void contract_f64_item(
         const int a = (diag || r < 16 * it.nI) ? 16 * ti0 + r : 16 * tj0 + (r - 16 * it.nI);
         sRow[r] = a < nloc ? a : -1;
     }
+    // rows past the element's functions are the tail of the last tile
+    const int nreal = diag ? min(nrow, nloc - 16 * ti0) : 16 * it.nI + min(16 * it.nJ, nloc - 16 * tj0);
+    for (int k = tid; k < (nrow - nreal) * RS; k += NT) sB[(size_t)nreal * RS + k] = 0.0;
     if (tid < kp.n) {
         sGx[tid] = kpg.gx[tid];
         sGw[tid] = kpg.gw[tid];
@@ -338,12 +341,11 @@ __device__ __forceinline__ void contract_f64_item(
             group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
         __syncthreads();
-        // ---- phase 2: weighted local basis rows (eq. pufebasis).  The two
-        // 16-point halves of a wave take rows 8 apart, so their stores fall
-        // in different LDS banks.
-        for (int idx = tid; idx < nrow * Q; idx += NT) {
-            const int rr = idx / Q, q = idx - rr * Q;
-            const int r = (rr & ~15) | ((rr & 1) << 3) | ((rr >> 1) & 7);
+        // ---- phase 2: weighted local basis rows (eq. pufebasis) of the
+        // item's functions (the padding rows past them stay zero)
+#pragma unroll 2
+        for (int idx = tid; idx < nreal * Q; idx += NT) {
+            const int r = idx / Q, q = idx - r * Q;
             const int a = sRow[r];
             const double *g = sGeo + q;   // field f at g[f * Q]
             double val, gx[3];
