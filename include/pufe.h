@@ -201,8 +201,9 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
 int pufe_set_positions(pufe_ctx *ctx, const double *pos);
 
 /* Autotuner: time the contraction of this problem for candidate work-item
- * granularities (number of K-chunk items) and tile-block sizes (2..4 tiles of
- * 16 rows per work item side), keep the fastest and record it in the JSON
+ * granularities (number of K-chunk items), tile-block sizes (2..4 tiles of
+ * 16 rows per work item side) and stage lengths (16, 24 or 32 quadrature
+ * points per LDS stage), keep the fastest and record it in the JSON
  * file cache_path (keyed by GPU architecture, precision and problem
  * signature; NULL = no cache).  A cached entry is applied without timing.
  * Synchronous; re-plans the work items of ctx. */

@@ -65,7 +65,7 @@ struct pufe_ctx {
     int64_t part_slots = 0;
     double tune_items = 4096.0;
     int tune_block = kBlockTiles;
-    int contract_q = 16;            // points per LDS stage of the FP64 contraction (16 or 32)
+    int contract_q = 24;            // points per LDS stage of the FP64 contraction (16, 24 or 32)
     int max_item_leaves = 1;
     DevBuf<ElemDev> d_elems;
     DevBuf<GroupDev> d_groups;
@@ -290,7 +290,7 @@ static void plan_items(pufe_ctx *c, double target_items, int block_tiles) {
     for (int b = block_tiles; b >= 1; --b) {
         c->items = make_items(c, b, &c->max_rows, &c->max_item_leaves);
         c->lds = contract_lds_bytes(c->contract_q, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
-        if (c->lds > kMaxDynLds && c->contract_q == 32) {
+        if (c->lds > kMaxDynLds && c->contract_q > 16) {   // shorter stages before smaller blocks
             c->contract_q = 16;
             c->lds = contract_lds_bytes(16, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
         }
@@ -771,7 +771,7 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
             double items = 0;
             int block = 0, qv = 0;
             if (std::sscanf(text.c_str() + at + pat.size(), "%lf, \"block\": %d, \"q\": %d", &items, &block, &qv) == 3 &&
-                items > 0 && block >= 1 && block <= kBlockTiles && (qv == 16 || qv == 32)) {
+                items > 0 && block >= 1 && block <= kBlockTiles && contract_q_supported(qv)) {
                 ctx->tune_items = items;
                 ctx->tune_block = block;
                 ctx->contract_q = qv;
@@ -792,7 +792,7 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
     const bool saved = ctx->timing;
     ctx->timing = false;
     int best_q = ctx->contract_q;
-    for (int qv : {16, 32})
+    for (int qv : {16, 24, 32})
     for (int block = 2; block <= kBlockTiles; ++block)
         for (double items : cand_items) {
             ctx->contract_q = qv;
@@ -950,8 +950,13 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || ncu < 1) ncu = 256;
-    b->q = 16;
+    // 24-point stages when two work groups still share a CU, else 16
+    b->q = 24;
     b->lds_f64 = contract_lds_bytes(b->q, max_rows, max_nfun, max_img, max_leaves, max_n3);
+    if (persistent_blocks_per_cu(b->lds_f64) < 2) {
+        b->q = 16;
+        b->lds_f64 = contract_lds_bytes(b->q, max_rows, max_nfun, max_img, max_leaves, max_n3);
+    }
     b->grid_f64 = ncu * persistent_blocks_per_cu(b->lds_f64);
     for (int k = 0; k < 2; ++k) {
         b->lds_split[k] = split_lds_bytes(k + 2, max_rows_split, max_nfun, max_img, max_leaves_split, max_n3);

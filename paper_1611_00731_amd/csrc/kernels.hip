@@ -673,9 +673,14 @@ hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *
 }
 
 size_t contract_lds_bytes(int q, int rows, int nfun, int nimg, int nleaf, int n3) {
-    return q == 32 ? ContractLds<32>::bytes(rows, nfun, nimg, nleaf, n3)
-                   : ContractLds<16>::bytes(rows, nfun, nimg, nleaf, n3);
+    switch (q) {
+        case 32: return ContractLds<32>::bytes(rows, nfun, nimg, nleaf, n3);
+        case 24: return ContractLds<24>::bytes(rows, nfun, nimg, nleaf, n3);
+        default: return ContractLds<16>::bytes(rows, nfun, nimg, nleaf, n3);
+    }
 }
+
+bool contract_q_supported(int q) { return q == 16 || q == 24 || q == 32; }
 
 hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, const ItemDev *items,
                                const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
@@ -688,6 +693,9 @@ hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, 
     if (q == 32) {
         if (lmax <= 1) PUFE_PLAIN(32, 1);
         else PUFE_PLAIN(32, 3);
+    } else if (q == 24) {
+        if (lmax <= 1) PUFE_PLAIN(24, 1);
+        else PUFE_PLAIN(24, 3);
     } else {
         if (lmax <= 1) PUFE_PLAIN(16, 1);
         else PUFE_PLAIN(16, 3);
@@ -699,16 +707,18 @@ hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, 
 // Dynamic LDS above the default limit must be enabled per kernel before any
 // launch (and before any graph capture).
 hipError_t init_contract_attributes() {
-    const void *ks[8] = {(const void *)contract_f64_kernel<16, 1>, (const void *)contract_f64_kernel<16, 3>,
-                         (const void *)contract_f64_kernel<32, 1>, (const void *)contract_f64_kernel<32, 3>,
-                         (const void *)contract_f64_persistent<16, 1>, (const void *)contract_f64_persistent<16, 3>,
-                         (const void *)contract_f64_persistent<32, 1>, (const void *)contract_f64_persistent<32, 3>};
+    const void *ks[12] = {(const void *)contract_f64_kernel<16, 1>, (const void *)contract_f64_kernel<16, 3>,
+                          (const void *)contract_f64_kernel<24, 1>, (const void *)contract_f64_kernel<24, 3>,
+                          (const void *)contract_f64_kernel<32, 1>, (const void *)contract_f64_kernel<32, 3>,
+                          (const void *)contract_f64_persistent<16, 1>, (const void *)contract_f64_persistent<16, 3>,
+                          (const void *)contract_f64_persistent<24, 1>, (const void *)contract_f64_persistent<24, 3>,
+                          (const void *)contract_f64_persistent<32, 1>, (const void *)contract_f64_persistent<32, 3>};
     for (const void *k : ks) PUFE_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
     return hipSuccess;
 }
 
 int persistent_blocks_per_cu(size_t lds) {
-    int per = (int)(kMaxDynLds / (lds > 0 ? lds : 1));
+    int per = (int)((size_t)160 * 1024 / (lds > 0 ? lds : 1));   // the CU's LDS
     if (per > 2) per = 2;  // 256 VGPRs per lane: one 4-wave group per SIMD set, two if LDS allows
     return per < 1 ? 1 : per;
 }
@@ -724,6 +734,9 @@ hipError_t launch_contract_persistent(int q, int lmax, const CtxDev *ctxs, const
     if (q == 32) {
         if (lmax <= 1) PUFE_PERSIST(32, 1);
         else PUFE_PERSIST(32, 3);
+    } else if (q == 24) {
+        if (lmax <= 1) PUFE_PERSIST(24, 1);
+        else PUFE_PERSIST(24, 3);
     } else {
         if (lmax <= 1) PUFE_PERSIST(16, 1);
         else PUFE_PERSIST(16, 3);

@@ -27,6 +27,7 @@ hipError_t launch_elem_qp_offset(const KParams &kp, int64_t nel, const int64_t *
 hipError_t init_contract_attributes();
 hipError_t init_split_attributes();
 size_t contract_lds_bytes(int q, int rows, int nfun, int nimg, int nleaf, int n3);
+bool contract_q_supported(int q);
 hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, const ItemDev *items,
                                const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
