@@ -112,7 +112,7 @@ template <int Q>
 struct BackwardLds {
     static constexpr int RSB = 4 * Q + 2;   // 16-byte rows
     static constexpr int GEO = 40;
-    static_assert(RSB >= 3 * Q, "force contributions reuse the rows of sB");
+    static_assert(RSB >= 3 * Q, "force contributions reuse the rows of sB");   // and stay below row nloc
     static __host__ __device__ size_t bytes(int npad, int nenr, int nfun, int nimg) {
         return sizeof(double) * ((size_t)npad * (npad + 1) + (size_t)npad * RSB + (size_t)nenr * RSB +
                                  (size_t)nfun * Q * 10 + (size_t)Q * GEO + (size_t)nimg * 3) +
@@ -214,6 +214,9 @@ __global__ __launch_bounds__(256) void backward_kernel(
         sP[(size_t)a * RSP + b] = src[idx];
     }
     for (int k = tid; k < nenr; k += NT) sEd[k] = edof[el.edof_off + k];
+    // the padding rows of B stay zero (the force buffer sC lies within the
+    // first nloc rows)
+    for (int k = tid; k < (npad - nloc) * RSB; k += NT) sB[(size_t)nloc * RSB + k] = 0.0;
     for (int g = tid; g < ngrp; g += NT) {
         GroupDev G = groups[el.grp_off + g];
         G.img_off -= img0;   // rebased onto sImg
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
         }
         __syncthreads();
         // ---- phase 2: basis rows (grad_x, grad_y, grad_z, value), unweighted
-        for (int idx = tid; idx < npad * Q; idx += NT) {
+        for (int idx = tid; idx < nloc * Q; idx += NT) {
             const int a = idx / Q, q = idx - a * Q;
             const double *g = sGeo + q;
             double gx[3] = {0.0, 0.0, 0.0}, val = 0.0;

@@ -590,7 +590,9 @@ static int plan_backward(pufe_ctx *c, hipStream_t st) {
     std::vector<std::vector<int64_t>> slots(c->prob.species.size());
     for (int64_t e = 0; e < pl.nel; ++e) {
         const ElemDev &el = pl.elems[e];
-        int64_t nleaf = el.leaf_end - el.leaf_off, nch = el.nchunk;
+        // twice the forward's K-chunks (at most one per leaf): the adjoint's
+        // stages cost more, and finer items balance the refined elements
+        int64_t nleaf = el.leaf_end - el.leaf_off, nch = std::min<int64_t>(2 * el.nchunk, nleaf);
         for (int64_t ch = 0; ch < nch; ++ch) {
             ItemDev it{};
             it.elem = (int32_t)e;
