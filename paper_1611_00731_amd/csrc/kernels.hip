@@ -519,27 +519,43 @@ __device__ __forceinline__ void scatter_tile(const KParams &kp, const ElemDev &e
         const int dn = ((el.shifts >> (3 * cb + d)) & 1) - ((el.shifts >> (3 * ca + d)) & 1);
         t = 3 * t + (dn + 1);
     }
+    if (out_dtype == 0) {
+        // complex128: four k-points at a time, all loads before the stores
+        // (the k-point arrays are disjoint), so their latencies overlap
+        double2 *H2 = (double2 *)Hout, *S2 = (double2 *)Sout;
+        for (int k0 = 0; k0 < nk; k0 += 4) {
+            double2 zk[4], hab[4], hba[4], sab[4], sba[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k0 + u >= nk) break;
+                const int64_t base = (int64_t)(k0 + u) * nnz;
+                zk[u] = z[(k0 + u) * 27 + t];
+                hab[u] = H2[base + oab];
+                if (a != b) hba[u] = H2[base + oba];
+                if (Sout) {
+                    sab[u] = S2[base + oab];
+                    if (a != b) sba[u] = S2[base + oba];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k0 + u >= nk) break;
+                const int64_t base = (int64_t)(k0 + u) * nnz;
+                const double cr = zk[u].x, ci = zk[u].y;
+                H2[base + oab] = make_double2(hab[u].x + cr * h, hab[u].y + ci * h);
+                if (a != b) H2[base + oba] = make_double2(hba[u].x + cr * h, hba[u].y - ci * h);
+                if (Sout) {
+                    S2[base + oab] = make_double2(sab[u].x + cr * s, sab[u].y + ci * s);
+                    if (a != b) S2[base + oba] = make_double2(sba[u].x + cr * s, sba[u].y - ci * s);
+                }
+            }
+        }
+        return;
+    }
     for (int k = 0; k < nk; ++k) {
         const double2 zz = z[k * 27 + t];
         const double cr = zz.x, ci = zz.y;
-        if (out_dtype == 0) {
-            double *H = (double *)Hout + 2 * (int64_t)k * nnz;
-            H[2 * oab] += cr * h;
-            H[2 * oab + 1] += ci * h;
-            if (a != b) {
-                H[2 * oba] += cr * h;
-                H[2 * oba + 1] -= ci * h;
-            }
-            if (Sout) {
-                double *S = (double *)Sout + 2 * (int64_t)k * nnz;
-                S[2 * oab] += cr * s;
-                S[2 * oab + 1] += ci * s;
-                if (a != b) {
-                    S[2 * oba] += cr * s;
-                    S[2 * oba + 1] -= ci * s;
-                }
-            }
-        } else if (out_dtype == 1) {
+        if (out_dtype == 1) {
             float *H = (float *)Hout + 2 * (int64_t)k * nnz;
             H[2 * oab] += (float)(cr * h);
             H[2 * oab + 1] += (float)(ci * h);
