@@ -188,7 +188,8 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
  *                       eq. rhoe when P is the occupied density matrix),
  *   d_dLdR[n_atoms*3] = derivative with respect to the enrichment centres
  *                       (rule, enriched sets and V held fixed),
- * with Pt_ab = Re(p_a P_{g_a g_b} conj(p_b)).  Output pointers may be NULL. */
+ * with Pt_ab = Re(p_a P_{g_a g_b} conj(p_b)).  Output pointers may be NULL.
+ * Elements of more than 80 local functions give PUFE_ERR_UNSUPPORTED. */
 int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3], const void *d_P,
                            const void *d_Q, int precision, double *d_dLdV, double *d_dLdR,
                            void *stream);
