@@ -228,6 +228,54 @@ def leg_backward(reps=3):
     return out
 
 
+def leg_cfg4(reps=2):
+    """One assembly of the CeAl-like cell (CsCl a = 5.8 bohr, 12^3 triquadratic
+    hexes, 8^3 Gauss + 3 octree levels within 1 bohr, 41 enrichment functions
+    per atom pair, n_loc up to 283) at 4 k-points, complex128 H and S, FP64."""
+    import torch
+    import paper_1611_00731_amd as P
+    import workloads as W
+    from workloads.potential import potential_at
+    prob = W.cfg4()
+    p = P.Problem(prob).setup()
+    xyz, _, _ = p.quadrature()
+    V = potential_at(xyz, prob)
+    del xyz
+    lay = p.layout()
+    _, _, leaf_off = p.leaves()
+    nloc, nq, flops = element_work(prob, p.sizes, lay, leaf_off, prob["quad"]["n"] ** 3)
+    kpts = prob["kpts"]
+    sz = p.sizes
+    H = torch.empty((len(kpts), sz["nnz"], 2), dtype=torch.float64, device="cuda")
+    S = torch.empty_like(H)
+    P.pufe_assemble(p.ctx, V, kpts, "fp64", "c128", H, S)
+    torch.cuda.synchronize()
+    P.pufe_enable_timing(p.ctx, True)
+    P.pufe_kernel_times(p.ctx, reset=True)
+    st = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(st)
+    for _ in range(reps):
+        P.pufe_assemble(p.ctx, V, kpts, "fp64", "c128", H, S)
+    t1.record(st)
+    torch.cuda.synchronize()
+    kms, kc = P.pufe_kernel_times(p.ctx, reset=True)
+    P.pufe_enable_timing(p.ctx, False)
+    ms = t0.elapsed_time(t1) / reps
+    cms = kms[0] / max(kc[0], 1)
+    alg = float(flops.sum())
+    out = {"workload": "CeAl-like CsCl cell a=5.8 bohr, 12^3 triquadratic hexes, 8^3 Gauss + 3 octree levels, "
+                       "4 k-points, H+S complex128",
+           "n_elem": sz["n_elem"], "n_qp": sz["n_qp"], "n_dof": sz["n_dof"], "nnz": sz["nnz"],
+           "nloc_max": int(nloc.max()), "ms": ms, "elements_per_s": sz["n_elem"] * len(kpts) / (ms * 1e-3),
+           "contract_ms": cms, "alg_flops": alg, "alg_tflops_contraction": alg / (cms * 1e-3) / 1e12,
+           "frac_of_fp64_peak": alg / (cms * 1e-3) / 1e12 / PEAK["fp64"],
+           "scatter_ms_per_assembly": kms[1] / reps, "chunk_reduce_ms": kms[3] / reps}
+    del H, S
+    p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,6 +389,8 @@ def main():
         out["extra"]["batch_sweep"] = leg_batch()
         log("adjoint leg (64-atom supercell)")
         out["extra"]["adjoint"] = leg_backward()
+        log("CeAl-like cell leg")
+        out["extra"]["ceal_cell"] = leg_cfg4()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob)

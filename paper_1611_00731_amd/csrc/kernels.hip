@@ -169,7 +169,7 @@ struct ContractLds {
         return sizeof(double) * ((size_t)rows * RS + (size_t)Q + (size_t)nfun * Q * 4 + (size_t)Q * GEO +
                                  (size_t)nimg * 3 + 2 * kMaxGauss) +
                sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc +
-               sizeof(uint32_t) * ((size_t)nleaf + n3 + rows) + 64;
+               sizeof(uint32_t) * ((size_t)nleaf + n3 + rows + 16) + 64;
     }
 };
 
@@ -212,7 +212,8 @@ template <int Q, int LMAX>
 __device__ __forceinline__ void contract_f64_item(
     const KParams &kpg, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
-    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial, double *smem) {
+    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial, double *smem,
+    int rot) {
     constexpr int RS = ContractLds<Q>::RS;
     constexpr int GEO = ContractLds<Q>::GEO;
     constexpr int NT = kContractThreads;
@@ -246,11 +247,17 @@ __device__ __forceinline__ void contract_f64_item(
     uint32_t *sLeaf = (uint32_t *)(sEd + kMaxNloc);
     uint32_t *sPt = sLeaf + (it.leaf_e - it.leaf_b);
     int *sRow = (int *)(sPt + n3);
+    int *sCS = sRow + nrow;   // [9] PU corner starts in sEd (whole-element items)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t q_begin = it.leaf_b * (int64_t)n3, q_end = it.leaf_e * (int64_t)n3;
     const uint32_t nli = (uint32_t)(q_end - q_begin);
     const int ti0 = it.I0, tj0 = it.J0;
     for (int k = tid; k < nloc - nfe; k += NT) sEd[k] = gEdof[el.edof_off + k];
+    // an item holding every row of its element evaluates them in groups that
+    // share a point's geometry (FE functions by (a2, a3), enriched ones by
+    // PU corner); other items take one row at a time
+    const bool whole = diag && ti0 == 0 && 16 * it.nI >= nloc;
+    if (whole) corner_starts(gEdof + el.edof_off, nloc - nfe, sCS, tid, NT);
     for (int g = tid; g < ngrp; g += NT) {
         const PUFE_GLOBAL GroupDev &Gg = gGroups[el.grp_off + g];
         GroupDev G;
@@ -282,13 +289,17 @@ __device__ __forceinline__ void contract_f64_item(
                            el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
                            el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
 
-    // tile pairs of this item, round-robin over the four waves
+    // tile pairs of this item, round-robin over the four waves starting at
+    // wave rot: when the pairs do not divide by four, work groups sharing a
+    // CU then load its four SIMDs' MFMA units unevenly in different ways
+    // rather than all on the same SIMDs
     const int npairs = diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
-    const int nu = npairs > wave ? (npairs - wave + 3) / 4 : 0;   // pairs of this wave (uniform)
+    const int vw = (wave - rot) & 3;
+    const int nu = npairs > vw ? (npairs - vw + 3) / 4 : 0;   // pairs of this wave (uniform)
     int pr_row[4], pr_col[4], pr_I[4], pr_J[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int pidx = wave + 4 * u;
+        const int pidx = vw + 4 * u;
         pr_row[u] = pr_col[u] = pr_I[u] = pr_J[u] = 0;
         if (u < nu) {
             int a, b;
@@ -343,6 +354,36 @@ __device__ __forceinline__ void contract_f64_item(
         __syncthreads();
         // ---- phase 2: weighted local basis rows (eq. pufebasis) of the
         // item's functions (the padding rows past them stay zero)
+        if (whole) {
+            const int n1 = kp.p + 1;
+            for (int idx = tid; idx < n1 * n1 * Q; idx += NT) {
+                const int u = idx / Q, q = idx - u * Q;
+                double *o = sB + q;
+                auto put = [&](int a, double x, double y, double z, double w) {
+                    double *r = o + (size_t)a * RS;
+                    r[0] = x;
+                    r[Q] = y;
+                    r[2 * Q] = z;
+                    r[3 * Q] = w;
+                };
+                if (n1 == 3)
+                    fe_unit<Q, 3>(kp, sGeo + q, u % 3, u / 3, put);
+                else
+                    fe_unit<Q, 2>(kp, sGeo + q, u & 1, u >> 1, put);
+            }
+            for (int idx = tid; idx < 8 * Q; idx += NT) {
+                const int c = idx / Q, q = idx - c * Q;
+                double *o = sB + q;
+                auto put = [&](int a, double x, double y, double z, double w) {
+                    double *r = o + (size_t)a * RS;
+                    r[0] = x;
+                    r[Q] = y;
+                    r[2 * Q] = z;
+                    r[3 * Q] = w;
+                };
+                pu_unit<Q>(kp, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
+            }
+        } else
 #pragma unroll 2
         for (int idx = tid; idx < nreal * Q; idx += NT) {
             const int r = idx / Q, q = idx - r * Q;
@@ -394,7 +435,8 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
     const ItemDev it = items[blockIdx.x];
-    contract_f64_item<Q, LMAX>(kp, it, elems, groups, img, edof, leaves, V, partial, smem);
+    contract_f64_item<Q, LMAX>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
+                               (blockIdx.x ^ (blockIdx.x >> 3) ^ (blockIdx.x >> 5) ^ (blockIdx.x >> 8)) & 3);
 }
 
 // Persistent form: a fixed grid of work groups pulls items (of several
@@ -414,7 +456,7 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
         if (idx >= n_items) break;
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
-        contract_f64_item<Q, LMAX>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem);
+        contract_f64_item<Q, LMAX>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem, idx & 3);
     }
 }
 

@@ -164,4 +164,65 @@ __device__ __forceinline__ void local_row(const KLocal &kp, const double *g, con
     gx[2] = (kp.Jt[6] * dM[0] + kp.Jt[7] * dM[1] + kp.Jt[8] * dM[2]) * p0 + M * p3;
 }
 
+// Weighted rows of whole elements, grouped so that one thread reuses the
+// geometry of its point over several rows.  out(a, x, y, z, u) receives, for
+// local function a, sqrt(w/2) grad phi_a (x, y, z) and sqrt(w) phi_a (u).
+//
+// fe_unit: the N1 FE functions a = a1 + N1 a2 + N1^2 a3, a1 = 0 .. N1 - 1
+// (N1 = p + 1 nodes per direction), of one (a2, a3).
+template <int Q, int N1, class Out>
+__device__ __forceinline__ void fe_unit(const KLocal &kp, const double *g, int a2, int a3, Out &&out) {
+    const double s2 = g[G_SW2 * Q], sw = g[G_SW * Q];
+    const double L2 = g[(G_L + 3 + a2) * Q], D2 = g[(G_D + 3 + a2) * Q];
+    const double L3 = g[(G_L + 6 + a3) * Q], D3 = g[(G_D + 6 + a3) * Q];
+    const double p = L2 * L3, pd2 = D2 * L3, pd3 = L2 * D3, pw = sw * p;
+    double sJ[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sJ[i] = s2 * kp.Jt[i];
+#pragma unroll
+    for (int a1 = 0; a1 < N1; ++a1) {
+        const double l1 = g[(G_L + a1) * Q], d1 = g[(G_D + a1) * Q];
+        const double x0 = d1 * p, x1 = l1 * pd2, x2 = l1 * pd3;
+        out(a1 + N1 * a2 + N1 * N1 * a3, sJ[0] * x0 + sJ[1] * x1 + sJ[2] * x2, sJ[3] * x0 + sJ[4] * x1 + sJ[5] * x2,
+            sJ[6] * x0 + sJ[7] * x1 + sJ[8] * x2, l1 * pw);
+    }
+}
+
+// pu_unit: the enriched functions M_c Psi_f of PU corner c, entries
+// kb .. ke - 1 of the element's enriched table (local functions nfe + k);
+// ps points to the element's enrichment table at the point.
+template <int Q, class Out>
+__device__ __forceinline__ void pu_unit(const KLocal &kp, const double *g, const double *ps, const int32_t *sEd, int c,
+                                        int kb, int ke, int nfe, Out &&out) {
+    const double s2 = g[G_SW2 * Q], sw = g[G_SW * Q];
+    const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
+    const double m0 = g[(G_M1 + b0) * Q], m1 = g[(G_M1 + 2 + b1) * Q], m2 = g[(G_M1 + 4 + b2) * Q];
+    const double M = g[(G_M + c) * Q];
+    const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2, m0 * m1 * (b2 ? 0.5 : -0.5)};
+    // grad(M Psi) = Psi grad M + M grad Psi, grad M via Jt
+    double jm[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+        jm[cc] = s2 * (kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2]);
+    const double sM = s2 * M, wM = sw * M;
+    for (int k = kb; k < ke; ++k) {
+        const int f = (sEd[k] >> 3) & 255;
+        const double *pf = ps + (size_t)f * 4 * Q;
+        const double p0 = pf[0], p1 = pf[Q], p2 = pf[2 * Q], p3 = pf[3 * Q];
+        out(nfe + k, jm[0] * p0 + sM * p1, jm[1] * p0 + sM * p2, jm[2] * p0 + sM * p3, wM * p0);
+    }
+}
+
+// Start of each PU corner's entries in an element's enriched table, which
+// lists them corner by corner: cs[c] .. cs[c + 1] - 1 belong to corner c
+// (cs[8] = number of entries).  Cooperative over the work group; ne =
+// number of entries, ed = the table in global memory.
+__device__ __forceinline__ void corner_starts(const PUFE_GLOBAL int32_t *ed, int ne, int *cs, int tid, int nt) {
+    for (int k = tid; k <= ne; k += nt) {
+        const int ck = k < ne ? (ed[k] & 7) : 8;
+        const int cp = k > 0 ? (ed[k - 1] & 7) : -1;
+        for (int c = cp + 1; c <= ck; ++c) cs[c] = k;
+    }
+}
+
 }  // namespace pufe
