@@ -175,35 +175,32 @@ struct ContractLds {
 
 constexpr int kContractThreads = 256;
 
-// MFMAs of one stage for a wave owning NU tile pairs, one pair at a time
-// (the four H products of a pair accumulate back to back).
-//   S: k = 4 points of the sqrt(w) phi component.
-//   H: k = the 4 components of one point, A = (g_x, g_y, g_z, V u),
-//      B = (g_x, g_y, g_z, u), u = sqrt(w) phi; V is applied to A on load.
+// MFMAs of one stage for a wave owning NU tile pairs.  Every product sums
+// k = 4 consecutive points of one operand component (lane l supplies row
+// l % 16 at point 4 s4 + l / 16), five per pair and 4 points:
+//   S   += u u^T,  H += u (V u)^T + g_x g_x^T + g_y g_y^T + g_z g_z^T,
+// with u = sqrt(w) phi and g = sqrt(w/2) grad phi; V scales the B operand
+// on load (one multiply per pair and step).
 template <int Q, int NU>
 __device__ __forceinline__ void mfma_stage(const double *__restrict__ sB, const double *__restrict__ sV,
                                            const int *pr_row, const int *pr_col, int r16, int k4, double4_t *accH,
                                            double4_t *accS) {
     constexpr int RS = ContractLds<Q>::RS;
-#pragma unroll
+#pragma unroll 1
     for (int s4 = 0; s4 < Q / 4; ++s4) {
-        const double2 v01 = *(const double2 *)(sV + 4 * s4), v23 = *(const double2 *)(sV + 4 * s4 + 2);
-        const double f[4] = {k4 == 3 ? v01.x : 1.0, k4 == 3 ? v01.y : 1.0, k4 == 3 ? v23.x : 1.0,
-                             k4 == 3 ? v23.y : 1.0};
+        const int o = 4 * s4 + k4;
+        const double vq = sV[o];
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            const double *ra = sB + (size_t)(pr_row[u] + r16) * RS;
-            const double *rb = sB + (size_t)(pr_col[u] + r16) * RS;
-            const double aS = ra[3 * Q + 4 * s4 + k4], bS = rb[3 * Q + 4 * s4 + k4];
-            const double2 a01 = *(const double2 *)(ra + k4 * Q + 4 * s4);
-            const double2 a23 = *(const double2 *)(ra + k4 * Q + 4 * s4 + 2);
-            const double2 b01 = *(const double2 *)(rb + k4 * Q + 4 * s4);
-            const double2 b23 = *(const double2 *)(rb + k4 * Q + 4 * s4 + 2);
-            accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aS, bS, accS[u], 0, 0, 0);
-            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x * f[0], b01.x, accH[u], 0, 0, 0);
-            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y * f[1], b01.y, accH[u], 0, 0, 0);
-            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x * f[2], b23.x, accH[u], 0, 0, 0);
-            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y * f[3], b23.y, accH[u], 0, 0, 0);
+            const double *ra = sB + (size_t)(pr_row[u] + r16) * RS + o;
+            const double *rb = sB + (size_t)(pr_col[u] + r16) * RS + o;
+            const double au = ra[3 * Q], bu = rb[3 * Q];
+            const double ax = ra[0], bx = rb[0], ay = ra[Q], by = rb[Q], az = ra[2 * Q], bz = rb[2 * Q];
+            accS[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(au, bu, accS[u], 0, 0, 0);
+            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(au, bu * vq, accH[u], 0, 0, 0);
+            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bx, accH[u], 0, 0, 0);
+            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, by, accH[u], 0, 0, 0);
+            accH[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(az, bz, accH[u], 0, 0, 0);
         }
     }
 }
