@@ -205,6 +205,52 @@ __device__ __forceinline__ void mfma_stage(const double *__restrict__ sB, const 
     }
 }
 
+// Tail pairs of a whole-element item: the last tile holds nt <= 8 real
+// rows, so the pair (tile I, last tile) runs on v_mfma_f64_4x4x4f64, whose
+// four blocks take the four 4-row groups of tile I against 4 tail columns
+// (TG groups of 4 columns).  4x4x4 operand lane l = 16 k + 4 b + i holds
+// A_b[i][k] (here row 4 b + i of tile I, i.e. row l % 16, at point k) and
+// B_b[k][j] with j = l % 4 (the same tail column for every block); result
+// lane l holds D_b[l / 16][l % 4], b = (l / 4) % 4.
+template <int Q, int MT, int TG>
+__device__ __forceinline__ void mfma_tail_stage(const double *__restrict__ sB, const double *__restrict__ sV,
+                                                const int *tl_row, int tail_row0, int r16, int k4, int lane,
+                                                double (*tH)[2], double (*tS)[2]) {
+    constexpr int RS = ContractLds<Q>::RS;
+#pragma unroll 1
+    for (int s4 = 0; s4 < Q / 4; ++s4) {
+        const int o = 4 * s4 + k4;
+        const double vq = sV[o];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            const double *ra = sB + (size_t)(tl_row[t] + r16) * RS + o;
+            const double au = ra[3 * Q], ax = ra[0], ay = ra[Q], az = ra[2 * Q];
+#pragma unroll
+            for (int g = 0; g < TG; ++g) {
+                const double *rb = sB + (size_t)(tail_row0 + 4 * g + (lane & 3)) * RS + o;
+                const double bu = rb[3 * Q], bx = rb[0], by = rb[Q], bz = rb[2 * Q];
+                tS[t][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(au, bu, tS[t][g], 0, 0, 0);
+                tH[t][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(au, bu * vq, tH[t][g], 0, 0, 0);
+                tH[t][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(ax, bx, tH[t][g], 0, 0, 0);
+                tH[t][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(ay, by, tH[t][g], 0, 0, 0);
+                tH[t][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(az, bz, tH[t][g], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int Q, int TG>
+__device__ __forceinline__ void mfma_tail_dispatch(int mt, const double *sB, const double *sV, const int *tl_row,
+                                                   int tail_row0, int r16, int k4, int lane, double (*tH)[2],
+                                                   double (*tS)[2]) {
+    switch (mt) {
+        case 3: mfma_tail_stage<Q, 3, TG>(sB, sV, tl_row, tail_row0, r16, k4, lane, tH, tS); break;
+        case 2: mfma_tail_stage<Q, 2, TG>(sB, sV, tl_row, tail_row0, r16, k4, lane, tH, tS); break;
+        case 1: mfma_tail_stage<Q, 1, TG>(sB, sV, tl_row, tail_row0, r16, k4, lane, tH, tS); break;
+        default: break;
+    }
+}
+
 template <int Q, int LMAX>
 __device__ __forceinline__ void contract_f64_item(
     const KParams &kpg, const ItemDev &it, const ElemDev *__restrict__ elems,
@@ -290,9 +336,50 @@ __device__ __forceinline__ void contract_f64_item(
     // wave rot: when the pairs do not divide by four, work groups sharing a
     // CU then load its four SIMDs' MFMA units unevenly in different ways
     // rather than all on the same SIMDs
-    const int npairs = diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ;
+    //
+    // Whole-element items whose last tile holds at most 8 real rows take the
+    // pairs (I, last tile) as tail pairs on the 4x4x4 MFMA (a quarter or half
+    // the cost of a full pair), handed one by one to the least loaded wave;
+    // the remaining pairs are the full pairs of the other tiles.
+    const int T = (nloc + 15) / 16;
+    const int ntail = nloc - 16 * (T - 1);
+    // (compiled for enrichments up to l = 1 only: with l up to 3 the extra
+    // accumulators would push the kernel into register spills)
+    constexpr bool kTail = LMAX <= 1;
+    const int tg = (kTail && whole && T >= 2) ? (ntail <= 4 ? 1 : (ntail <= 8 ? 2 : 0)) : 0;
+    const int npairs = tg ? (T - 1) * T / 2 : (diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ);
     const int vw = (wave - rot) & 3;
     const int nu = npairs > vw ? (npairs - vw + 3) / 4 : 0;   // pairs of this wave (uniform)
+    constexpr int MAXT = 3;   // tail pairs per wave (at most 5 tail pairs per item)
+    int mt = 0, tl_row[MAXT] = {0, 0, 0}, tl_I[MAXT] = {0, 0, 0};
+    if (tg) {
+        // loads in quarter pairs; ties go to the higher virtual wave, which
+        // holds fewer full pairs
+        int l0 = 4 * (npairs > 0 ? (npairs + 3) / 4 : 0), l1 = 4 * (npairs > 1 ? (npairs + 2) / 4 : 0);
+        int l2 = 4 * (npairs > 2 ? (npairs + 1) / 4 : 0), l3 = 4 * (npairs > 3 ? npairs / 4 : 0);
+        for (int I = 0; I < T; ++I) {
+            int best = 3, lb = l3;
+            if (l2 < lb) { best = 2; lb = l2; }
+            if (l1 < lb) { best = 1; lb = l1; }
+            if (l0 < lb) { best = 0; lb = l0; }
+            l0 += best == 0 ? tg : 0;
+            l1 += best == 1 ? tg : 0;
+            l2 += best == 2 ? tg : 0;
+            l3 += best == 3 ? tg : 0;
+            if (best == vw && mt < MAXT) {
+#pragma unroll
+                for (int t = 0; t < MAXT; ++t)
+                    if (t == mt) {
+                        tl_row[t] = 16 * I;
+                        tl_I[t] = I;
+                    }
+                ++mt;
+            }
+        }
+    }
+    double tH[MAXT][2], tS[MAXT][2];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) tH[t][0] = tH[t][1] = tS[t][0] = tS[t][1] = 0.0;
     int pr_row[4], pr_col[4], pr_I[4], pr_J[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -404,12 +491,35 @@ __device__ __forceinline__ void contract_f64_item(
             case 1: mfma_stage<Q, 1>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
             default: break;
         }
+        if (tg == 1)
+            mfma_tail_dispatch<Q, 1>(mt, sB, sV, tl_row, 16 * (T - 1), r16, k4, lane, tH, tS);
+        else if (tg == 2)
+            mfma_tail_dispatch<Q, 2>(mt, sB, sV, tl_row, 16 * (T - 1), r16, k4, lane, tH, tS);
         __syncthreads();
     }
     // ---- partial tiles, row-major 16x16.  FP64 16x16x4 accumulator layout:
     // register r of lane l holds D[(l / 16) + 4 r][l % 16].
-    const int T = (nloc + 15) / 16;
     const int64_t P = (int64_t)T * (T + 1) / 2;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        if (t >= mt) continue;
+        const int64_t pidx = (int64_t)(T - 1) * T / 2 + tl_I[t];
+        PUFE_GLOBAL double *dst = gPartial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
+        const int row = 4 * ((lane >> 2) & 3) + (lane >> 4);
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+            if (g < tg) {
+                dst[row * 16 + 4 * g + (lane & 3)] = tH[t][g];
+                dst[256 + row * 16 + 4 * g + (lane & 3)] = tS[t][g];
+            }
+        // columns past the tail groups hold no function: zeros
+        const int w = 16 - 4 * tg;
+        for (int e = lane; e < 16 * w; e += 64) {
+            const int zr = e / w, zc = 4 * tg + e % w;
+            dst[zr * 16 + zc] = 0.0;
+            dst[256 + zr * 16 + zc] = 0.0;
+        }
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         if (u >= nu) continue;

@@ -173,6 +173,36 @@ def test_cfg2_full_size_sampled_blocks():
     p.close()
 
 
+def test_cfg2_element_matrices_every_nloc():
+    """Element matrices of the LiH-like workload at full size, one element per
+    distinct n_loc (the most refined of each), against the oracle.  The set
+    spans last tiles with at most 4 and with 5..8 real rows (the tail pairs
+    of whole-element items) and fuller last tiles, on 3, 4 and 5 tiles."""
+    prob = W.cfg2()
+    say("cfg2 element matrices, every n_loc")
+    o = oracle.Oracle(prob)
+    xyz, w, off = o.quadrature()
+    Vh = potential_at(torch.from_numpy(xyz).cuda(), prob).cpu().numpy()
+    p = P.Problem(prob).setup()
+    Vd = torch.from_numpy(Vh).cuda()
+    nloc = np.array([o.element_dofs(e)[0].size for e in range(o.n_elem)])
+    nq = np.diff(off)
+    picks = {}
+    for e in range(o.n_elem):
+        n = int(nloc[e])
+        if n not in picks or nq[e] > nq[picks[n]]:
+            picks[n] = e
+    tails = {(n - 16 * ((n + 15) // 16 - 1)) for n in picks}
+    assert any(t <= 4 for t in tails) and any(4 < t <= 8 for t in tails) and any(t > 8 for t in tails)
+    for n, e in sorted(picks.items()):
+        say("element", e, "n_loc", n, "points", int(nq[e]))
+        He, Se = p.element_matrices(e, Vd)
+        Ho, So = o.element_matrices(e, Vh[off[e]:off[e + 1]])
+        assert rel(He.cpu().numpy(), Ho) < TOL, (e, n, rel(He.cpu().numpy(), Ho))
+        assert rel(Se.cpu().numpy(), So) < TOL, (e, n, rel(Se.cpu().numpy(), So))
+    p.close()
+
+
 def test_cfg4_full_size_sampled():
     """The CeAl-like workload at full size (1728 elements, 27.3 M points,
     N = 37,891, n_loc up to 283: items of several row and column blocks):
