@@ -284,8 +284,8 @@ __device__ __forceinline__ void contract_f64_item(
     double *sPsi = sV + Q;                                    // [nfun][Q][4]
     double *sGeo = sPsi + (size_t)nfun * Q * 4;               // [Q][GEO]
     double *sImg = sGeo + (size_t)Q * GEO;
-    double *sGx = sImg + 3 * (size_t)nimg, *sGw = sGx + kMaxGauss;
-    GroupDev *sG = (GroupDev *)(sGw + kMaxGauss);
+    double *sGx = sImg + 3 * (size_t)nimg, *sGs = sGx + kMaxGauss;   // square roots of the 1D Gauss weights
+    GroupDev *sG = (GroupDev *)(sGs + kMaxGauss);
     int32_t *sEd = (int32_t *)(sG + kMaxGroups);
     uint32_t *sLeaf = (uint32_t *)(sEd + kMaxNloc);
     uint32_t *sPt = sLeaf + (it.leaf_e - it.leaf_b);
@@ -326,7 +326,7 @@ __device__ __forceinline__ void contract_f64_item(
     for (int k = tid; k < (nrow - nreal) * RS; k += NT) sB[(size_t)nreal * RS + k] = 0.0;
     if (tid < kp.n) {
         sGx[tid] = kpg.gx[tid];
-        sGw[tid] = kpg.gw[tid];
+        sGs[tid] = sqrt(kpg.gw[tid]);
     }
     const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
                            el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
@@ -421,17 +421,17 @@ __device__ __forceinline__ void contract_f64_item(
         // ---- phase 1: enrichment functions (eq. Psi, f(R) = 1) and geometry
         if (gq >= 0) {
             const double vn = (lb + Q + gq < nli) ? gV[q_begin + lb + Q + gq] : 0.0;
-            double xi[3], w;
-            item_point(kp, sLeaf, sPt, sGx, sGw, lb + gq, nli, n3, xi, &w);
-            point_geometry<Q>(kp, org, xi, w, sGeo + gq);
+            double xi[3], sw;
+            item_point(kp, sLeaf, sPt, sGx, sGs, lb + gq, nli, n3, xi, &sw);
+            point_geometry<Q>(kp, org, xi, sw, sGeo + gq);
             sV[gq] = v;
             v = vn;
         }
         for (int idx = tid; idx < ngrp * Q; idx += NT) {
             const int g = idx / Q, q = idx - g * Q;
             const GroupDev &G = sG[g];
-            double xi[3], w, x[3];
-            item_point(kp, sLeaf, sPt, sGx, sGw, lb + q, nli, n3, xi, &w);
+            double xi[3], sw, x[3];
+            item_point(kp, sLeaf, sPt, sGx, sGs, lb + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
             group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }

@@ -57,7 +57,7 @@ __device__ __forceinline__ void split_limbs(double x, uint32_t *h) {
 //   sLimb[j][row][5][Q]  bf16 limb j of the weighted operands sqrt(w/2) d_x phi,
 //                        sqrt(w/2) d_y phi, sqrt(w/2) d_z phi, sqrt(w) phi,
 //                        V sqrt(w) phi (row stride RSB bytes)
-//   sV[Q], sPsi[f][4][Q], sGeo[GEO][Q], sImg, sGx, sGw   (FP64)
+//   sV[Q], sPsi[f][4][Q], sGeo[GEO][Q], sImg, sGx, sGs   (FP64)
 //   sG, sEd, sLeaf, sPt, sRow
 template <int Q>
 struct SplitLds {
@@ -102,8 +102,8 @@ __device__ __forceinline__ void contract_split_item(
     double *sPsi = sV + Q;                                                    // [nfun][4][Q]
     double *sGeo = sPsi + (size_t)nfun * Q * 4;                               // [GEO][Q]
     double *sImg = sGeo + (size_t)Q * GEO;
-    double *sGx = sImg + 3 * (size_t)nimg, *sGw = sGx + kMaxGauss;
-    GroupDev *sG = (GroupDev *)(sGw + kMaxGauss);
+    double *sGx = sImg + 3 * (size_t)nimg, *sGs = sGx + kMaxGauss;   // square roots of the 1D Gauss weights
+    GroupDev *sG = (GroupDev *)(sGs + kMaxGauss);
     int32_t *sEd = (int32_t *)(sG + kMaxGroups);
     uint32_t *sLeaf = (uint32_t *)(sEd + kMaxNloc);
     uint32_t *sPt = sLeaf + (it.leaf_e - it.leaf_b);
@@ -135,7 +135,7 @@ __device__ __forceinline__ void contract_split_item(
     }
     if (tid < kp.n) {
         sGx[tid] = kpg.gx[tid];
-        sGw[tid] = kpg.gw[tid];
+        sGs[tid] = sqrt(kpg.gw[tid]);
     }
     const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
                            el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
@@ -183,17 +183,17 @@ __device__ __forceinline__ void contract_split_item(
         // ---- phase 1: enrichment functions (eq. Psi, f(R) = 1) and geometry
         if (gq >= 0) {
             const double vn = (lb + Q + gq < nli) ? gV[q_begin + lb + Q + gq] : 0.0;
-            double xi[3], w;
-            item_point(kp, sLeaf, sPt, sGx, sGw, lb + gq, nli, n3, xi, &w);
-            point_geometry<Q>(kp, org, xi, w, sGeo + gq);
+            double xi[3], sw;
+            item_point(kp, sLeaf, sPt, sGx, sGs, lb + gq, nli, n3, xi, &sw);
+            point_geometry<Q>(kp, org, xi, sw, sGeo + gq);
             sV[gq] = v;
             v = vn;
         }
         for (int idx = tid; idx < ngrp * Q; idx += NT) {
             const int g = idx / Q, q = idx - g * Q;
             const GroupDev &G = sG[g];
-            double xi[3], w, x[3];
-            item_point(kp, sLeaf, sPt, sGx, sGw, lb + q, nli, n3, xi, &w);
+            double xi[3], sw, x[3];
+            item_point(kp, sLeaf, sPt, sGx, sGs, lb + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
             group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }

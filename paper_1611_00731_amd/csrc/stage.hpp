@@ -34,8 +34,9 @@ __device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double 
 // The per-launch constants the inner loops use, copied out of KParams into
 // registers once per item (KParams of a batched launch lives in global memory).
 struct KLocal {
-    double E[9], Jt[9], jac;
+    double E[9], Jt[9], jac, sjac;
     int p, n, n3;
+    bool jdiag;   // Jt diagonal (orthogonal cell axes)
 };
 
 __device__ __forceinline__ KLocal load_klocal(const KParams &kp) {
@@ -46,18 +47,24 @@ __device__ __forceinline__ KLocal load_klocal(const KParams &kp) {
         k.Jt[i] = kp.Jt[i];
     }
     k.jac = kp.jac;
+    k.sjac = sqrt(kp.jac);
+    k.jdiag = kp.Jt[1] == 0.0 && kp.Jt[2] == 0.0 && kp.Jt[3] == 0.0 && kp.Jt[5] == 0.0 && kp.Jt[6] == 0.0 &&
+              kp.Jt[7] == 0.0;
     k.p = kp.p;
     k.n = kp.n;
     k.n3 = kp.n3;
     return k;
 }
 
-// Reference coordinates and weight of point li of the item (w = 0 past the end).
+// Reference coordinates of point li of the item and the square root of its
+// weight, sw = sqrt(w); sGs holds the square roots of the 1D Gauss weights,
+// so that sw = h^(3/2) sqrt(det J) prod_d sqrt(w_d) needs no square root per
+// point (sw = 0 past the end).
 __device__ __forceinline__ void item_point(const KLocal &kp, const uint32_t *sLeaf, const uint32_t *sPt,
-                                           const double *sGx, const double *sGw, uint32_t li, uint32_t nli,
-                                           uint32_t n3, double *xi, double *w) {
+                                           const double *sGx, const double *sGs, uint32_t li, uint32_t nli,
+                                           uint32_t n3, double *xi, double *sw) {
     xi[0] = xi[1] = xi[2] = 0.0;
-    *w = 0.0;
+    *sw = 0.0;
     if (li >= nli) return;
     const uint32_t lf = li / n3, j = li - lf * n3;
     const uint32_t code = sLeaf[lf], pt = sPt[j];
@@ -65,13 +72,14 @@ __device__ __forceinline__ void item_point(const KLocal &kp, const uint32_t *sLe
     const double h = 1.0 / (double)(1u << lev);
     const int c[3] = {(int)(code & 511u), (int)((code >> 9) & 511u), (int)((code >> 18) & 511u)};
     const int k[3] = {(int)(pt & 255u), (int)((pt >> 8) & 255u), (int)(pt >> 16)};
-    double wt = h * h * h * kp.jac;
+    // h^(3/2) = 2^(-3 lev / 2)
+    double s = ldexp((lev & 1) ? M_SQRT2 : 1.0, -((3 * lev + (lev & 1)) >> 1)) * kp.sjac;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         xi[d] = -1.0 + (2.0 * c[d] + 1.0 + sGx[k[d]]) * h;
-        wt *= sGw[k[d]];
+        s *= sGs[k[d]];
     }
-    *w = wt;
+    *sw = s;
 }
 
 __device__ __forceinline__ void point_position(const KLocal &kp, const double *org, const double *xi, double *x) {
@@ -83,7 +91,7 @@ __device__ __forceinline__ void point_position(const KLocal &kp, const double *o
 
 // Geometry record of one point, field f at g[f * Q].
 template <int Q>
-__device__ __forceinline__ void point_geometry(const KLocal &kp, const double *org, const double *xi, double w,
+__device__ __forceinline__ void point_geometry(const KLocal &kp, const double *org, const double *xi, double sw,
                                                double *g) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) g[(G_XI + d) * Q] = xi[d];
@@ -91,8 +99,8 @@ __device__ __forceinline__ void point_geometry(const KLocal &kp, const double *o
     for (int cc = 0; cc < 3; ++cc)
         g[(G_X + cc) * Q] = org[cc] + 0.5 * (xi[0] + 1.0) * kp.E[cc] + 0.5 * (xi[1] + 1.0) * kp.E[3 + cc] +
                             0.5 * (xi[2] + 1.0) * kp.E[6 + cc];
-    g[G_SW2 * Q] = sqrt(0.5 * w);
-    g[G_SW * Q] = sqrt(w);
+    g[G_SW2 * Q] = M_SQRT1_2 * sw;
+    g[G_SW * Q] = sw;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double t = xi[d];
@@ -176,6 +184,15 @@ __device__ __forceinline__ void fe_unit(const KLocal &kp, const double *g, int a
     const double L2 = g[(G_L + 3 + a2) * Q], D2 = g[(G_D + 3 + a2) * Q];
     const double L3 = g[(G_L + 6 + a3) * Q], D3 = g[(G_D + 6 + a3) * Q];
     const double p = L2 * L3, pd2 = D2 * L3, pd3 = L2 * D3, pw = sw * p;
+    if (kp.jdiag) {   // gradient = diag(Jt) times the reference gradient
+        const double p0 = s2 * kp.Jt[0] * p, q1 = s2 * kp.Jt[4] * pd2, q2 = s2 * kp.Jt[8] * pd3;
+#pragma unroll
+        for (int a1 = 0; a1 < N1; ++a1) {
+            const double l1 = g[(G_L + a1) * Q], d1 = g[(G_D + a1) * Q];
+            out(a1 + N1 * a2 + N1 * N1 * a3, d1 * p0, l1 * q1, l1 * q2, l1 * pw);
+        }
+        return;
+    }
     double sJ[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) sJ[i] = s2 * kp.Jt[i];
