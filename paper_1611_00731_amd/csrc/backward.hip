@@ -14,6 +14,7 @@
 #include "backward.hpp"
 #include "basis.hpp"
 #include "device_common.hpp"
+#include "stage.hpp"
 #include "tables.hpp"
 
 namespace pufe {
@@ -116,12 +117,15 @@ struct BackwardLds {
     static __host__ __device__ size_t bytes(int npad, int nenr, int nfun, int nimg) {
         return sizeof(double) * ((size_t)npad * (npad + 1) + (size_t)npad * RSB + (size_t)nenr * RSB +
                                  (size_t)nfun * Q * 10 + (size_t)Q * GEO + (size_t)nimg * 3) +
-               sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc + 64;
+               sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * (kMaxNloc + 16) + 64;
     }
 };
 
 // geometry fields (index f at sGeo[f * Q + q])
 enum { B_XI = 0, B_X = 3, B_W = 6, B_V = 7, B_L = 8, B_D = 17, B_M = 26, B_M1 = 34 };
+// the shape-function fields sit where the grouped row helpers read them, and
+// the weight at the field those helpers test in their unweighted form
+static_assert(B_L == G_L && B_D == G_D && B_M == G_M && B_M1 == G_M1 && B_W == 6, "geometry layout");
 
 // U = Ps B for operand component c (one per wave), all T row tiles at once:
 // output tile I covers rows 16 I .. 16 I + 15 and the Q = 16 stage points of
@@ -205,6 +209,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
     double *sImg = sGeo + (size_t)Q * BackwardLds<Q>::GEO;
     GroupDev *sG = (GroupDev *)(sImg + 3 * (size_t)nimg);
     int32_t *sEd = (int32_t *)(sG + kMaxGroups);
+    int *sCS = sEd + kMaxNloc;   // [9] PU corner starts in sEd
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n3 = kp.n3;
     const int64_t q_begin = it.leaf_b * n3, q_end = it.leaf_e * n3;
@@ -214,6 +219,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
         sP[(size_t)a * RSP + b] = src[idx];
     }
     for (int k = tid; k < nenr; k += NT) sEd[k] = edof[el.edof_off + k];
+    corner_starts((const PUFE_GLOBAL int32_t *)(edof + el.edof_off), nenr, sCS, tid, NT);
     // the padding rows of B stay zero (the force buffer sC lies within the
     // first nloc rows)
     for (int k = tid; k < (npad - nloc) * RSB; k += NT) sB[(size_t)nloc * RSB + k] = 0.0;
@@ -226,6 +232,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
     const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
                            el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
                            el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
+    const KLocal kl = load_klocal(kp);
     // force accumulation: thread t owns enriched row nfe + t (rows of one
     // stage are summed over its points in order, then over the stages)
     double facc[3] = {0.0, 0.0, 0.0};
@@ -296,41 +303,29 @@ __global__ __launch_bounds__(256) void backward_kernel(
         }
         __syncthreads();
         // ---- phase 2: basis rows (grad_x, grad_y, grad_z, value), unweighted
-        for (int idx = tid; idx < nloc * Q; idx += NT) {
-            const int a = idx / Q, q = idx - a * Q;
-            const double *g = sGeo + q;
-            double gx[3] = {0.0, 0.0, 0.0}, val = 0.0;
-            if (a < nloc && g[B_W * Q] != 0.0) {
-                if (a < nfe) {
-                    const int n1 = kp.p + 1;
-                    const int a1 = a % n1, a2 = (a / n1) % n1, a3 = a / (n1 * n1);
-                    const double l1 = g[(B_L + a1) * Q], l2 = g[(B_L + 3 + a2) * Q], l3 = g[(B_L + 6 + a3) * Q];
-                    const double dxi[3] = {g[(B_D + a1) * Q] * l2 * l3, l1 * g[(B_D + 3 + a2) * Q] * l3,
-                                           l1 * l2 * g[(B_D + 6 + a3) * Q]};
-                    for (int c = 0; c < 3; ++c)
-                        gx[c] = kp.Jt[3 * c] * dxi[0] + kp.Jt[3 * c + 1] * dxi[1] + kp.Jt[3 * c + 2] * dxi[2];
-                    val = l1 * l2 * l3;
+        // (zero past the item's last point), in groups sharing the point's
+        // geometry: FE functions by (a2, a3), enriched ones by PU corner
+        {
+            const int n1 = kp.p + 1;
+            for (int idx = tid; idx < (n1 * n1 + 8) * Q; idx += NT) {
+                const int u = idx / Q, q = idx - u * Q;
+                double *o = sB + q;
+                auto put = [&](int a, double x, double y, double z, double w) {
+                    double *r = o + (size_t)a * RSB;
+                    r[0] = x;
+                    r[Q] = y;
+                    r[2 * Q] = z;
+                    r[3 * Q] = w;
+                };
+                if (u >= n1 * n1) {
+                    const int c = u - n1 * n1;
+                    pu_unit<Q, 10, true>(kl, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
+                } else if (n1 == 3) {
+                    fe_unit<Q, 3, true>(kl, sGeo + q, u % 3, u / 3, put);
                 } else {
-                    const int pk = sEd[a - nfe];
-                    const int c = pk & 7, f = (pk >> 3) & 255;
-                    const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
-                    const double m0 = g[(B_M1 + b0) * Q], m1 = g[(B_M1 + 2 + b1) * Q], m2 = g[(B_M1 + 4 + b2) * Q];
-                    const double M = g[(B_M + c) * Q];
-                    const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2,
-                                          m0 * m1 * (b2 ? 0.5 : -0.5)};
-                    const double *ps = sPsi + (size_t)f * 10 * Q + q;
-                    for (int cc = 0; cc < 3; ++cc) {
-                        const double gM = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
-                        gx[cc] = gM * ps[0] + M * ps[(1 + cc) * Q];
-                    }
-                    val = M * ps[0];
+                    fe_unit<Q, 2, true>(kl, sGeo + q, u & 1, u >> 1, put);
                 }
             }
-            double *o = sB + (size_t)a * RSB + q;
-            o[0] = gx[0];
-            o[Q] = gx[1];
-            o[2 * Q] = gx[2];
-            o[3 * Q] = val;
         }
         __syncthreads();
         // ---- phase 3: U = Ps B on the MFMAs, one operand component per wave;

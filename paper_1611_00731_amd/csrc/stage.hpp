@@ -172,15 +172,27 @@ __device__ __forceinline__ void local_row(const KLocal &kp, const double *g, con
     gx[2] = (kp.Jt[6] * dM[0] + kp.Jt[7] * dM[1] + kp.Jt[8] * dM[2]) * p0 + M * p3;
 }
 
-// Weighted rows of whole elements, grouped so that one thread reuses the
-// geometry of its point over several rows.  out(a, x, y, z, u) receives, for
-// local function a, sqrt(w/2) grad phi_a (x, y, z) and sqrt(w) phi_a (u).
-//
+// Rows of whole elements, grouped so that one thread reuses the geometry of
+// its point over several rows.  out(a, x, y, z, u) receives, for local
+// function a, sqrt(w/2) grad phi_a (x, y, z) and sqrt(w) phi_a (u); with
+// MASKED the rows are unweighted, grad phi_a and phi_a, and zero where field
+// 6 of the geometry record (the weight, in that layout) is zero.
+template <int Q, bool MASKED>
+__device__ __forceinline__ void row_weights(const double *g, double *s2, double *sw) {
+    if (MASKED) {
+        *s2 = *sw = g[6 * Q] != 0.0 ? 1.0 : 0.0;
+    } else {
+        *s2 = g[G_SW2 * Q];
+        *sw = g[G_SW * Q];
+    }
+}
+
 // fe_unit: the N1 FE functions a = a1 + N1 a2 + N1^2 a3, a1 = 0 .. N1 - 1
 // (N1 = p + 1 nodes per direction), of one (a2, a3).
-template <int Q, int N1, class Out>
+template <int Q, int N1, bool MASKED = false, class Out>
 __device__ __forceinline__ void fe_unit(const KLocal &kp, const double *g, int a2, int a3, Out &&out) {
-    const double s2 = g[G_SW2 * Q], sw = g[G_SW * Q];
+    double s2, sw;
+    row_weights<Q, MASKED>(g, &s2, &sw);
     const double L2 = g[(G_L + 3 + a2) * Q], D2 = g[(G_D + 3 + a2) * Q];
     const double L3 = g[(G_L + 6 + a3) * Q], D3 = g[(G_D + 6 + a3) * Q];
     const double p = L2 * L3, pd2 = D2 * L3, pd3 = L2 * D3, pw = sw * p;
@@ -207,11 +219,13 @@ __device__ __forceinline__ void fe_unit(const KLocal &kp, const double *g, int a
 
 // pu_unit: the enriched functions M_c Psi_f of PU corner c, entries
 // kb .. ke - 1 of the element's enriched table (local functions nfe + k);
-// ps points to the element's enrichment table at the point.
-template <int Q, class Out>
+// ps points to the element's enrichment table at the point (function f,
+// component c at ps[(PS f + c) * Q], value and gradient first).
+template <int Q, int PS = 4, bool MASKED = false, class Out>
 __device__ __forceinline__ void pu_unit(const KLocal &kp, const double *g, const double *ps, const int32_t *sEd, int c,
                                         int kb, int ke, int nfe, Out &&out) {
-    const double s2 = g[G_SW2 * Q], sw = g[G_SW * Q];
+    double s2, sw;
+    row_weights<Q, MASKED>(g, &s2, &sw);
     const int b0 = c & 1, b1 = (c >> 1) & 1, b2 = c >> 2;
     const double m0 = g[(G_M1 + b0) * Q], m1 = g[(G_M1 + 2 + b1) * Q], m2 = g[(G_M1 + 4 + b2) * Q];
     const double M = g[(G_M + c) * Q];
@@ -224,7 +238,7 @@ __device__ __forceinline__ void pu_unit(const KLocal &kp, const double *g, const
     const double sM = s2 * M, wM = sw * M;
     for (int k = kb; k < ke; ++k) {
         const int f = (sEd[k] >> 3) & 255;
-        const double *pf = ps + (size_t)f * 4 * Q;
+        const double *pf = ps + (size_t)f * PS * Q;
         const double p0 = pf[0], p1 = pf[Q], p2 = pf[2 * Q], p3 = pf[3 * Q];
         out(nfe + k, jm[0] * p0 + sM * p1, jm[1] * p0 + sM * p2, jm[2] * p0 + sM * p3, wM * p0);
     }
