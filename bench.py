@@ -60,6 +60,30 @@ def recorded_traffic():
     return float(m_t.group(1))
 
 
+# Lowest eigenvalues of the LiH-like cell from the FP64 CPU oracle (dense
+# assembly, LAPACK solve), written by tests/golden/make_lih_cell_eigenvalues.py.
+GOLDEN_EIGS = os.path.join(ROOT, "tests", "golden", "lih_cell_eigenvalues.txt")
+
+
+def golden_eigenvalues():
+    import numpy as np
+    return np.loadtxt(GOLDEN_EIGS, comments="#")
+
+
+def eig_error(P, p, H, S, ev_ref):
+    """max |eps - eps_oracle| (Ha) over the lowest eigenvalues of the
+    assembled Gamma-point H, S (device FP64 Cholesky + Hermitian solve);
+    None with the reason when S is not numerically positive definite."""
+    import numpy as np
+    Hd = p.to_dense(H[0]).real.contiguous()
+    Sd = p.to_dense(S[0]).real.contiguous()
+    try:
+        ev = P.eig(Hd, Sd, len(ev_ref)).cpu().numpy()
+    except RuntimeError as e:
+        return None, str(e).splitlines()[0][:120]
+    return float(np.abs(ev - ev_ref).max()), None
+
+
 def copy_probe(mib=1024, reps=3):
     """A plain device copy of known size, the scale for the PMC byte counters."""
     import torch
@@ -368,6 +392,16 @@ def main():
                   "nloc_min": int(nloc.min()), "nloc_max": int(nloc.max()),
                   "nq_max": int(nq.max())},
     }
+    # eigenvalue error of the assembled matrices against the FP64 oracle
+    # (outside the timed region)
+    ev_ref = golden_eigenvalues()
+    eig = {"n_eig": int(len(ev_ref)), "unit": "Ha",
+           "reference": "FP64 CPU oracle, dense LAPACK solve (tests/golden/lih_cell_eigenvalues.txt)"}
+    err, why = eig_error(P, p, H, S, ev_ref)
+    eig[args.precision] = err
+    if why:
+        eig[args.precision + "_note"] = why
+    log(f"eigenvalue error {args.precision}: {err}")
     # the split-precision forms on the same inputs (context for the FP64 line)
     for prec in ("bf16x6", "bf16x3"):
         if prec == args.precision:
@@ -383,6 +417,12 @@ def main():
         out["extra"][f"{prec}_contract_ms"] = cms
         out["extra"][f"{prec}_tflops"] = alg_flops / (cms * 1e-3) / 1e12
         out["extra"][f"{prec}_frac_of_effective_peak"] = alg_flops / (cms * 1e-3) / 1e12 / PEAK[prec]
+        err, why = eig_error(P, p, H, S, ev_ref)
+        eig[prec] = err
+        if why:
+            eig[prec + "_note"] = why
+        log(f"eigenvalue error {prec}: {err}")
+    out["eig_err"] = eig
     p.close()
     if not args.no_rows and args.precision == "fp64":
         log("batch leg (lattice sweep)")

@@ -142,3 +142,16 @@ def test_workload_sizes():
         assert s["nnz"] == 1278838
     finally:
         p.close()
+
+
+def test_golden_lih_cell_eigenvalues_file():
+    """The stored oracle eigenvalues of the LiH-like cell (read by the GPU
+    eigenvalue test and the benchmark): one per wanted eigenpair, finite and
+    ascending."""
+    import os
+    import numpy as np
+    import workloads as W
+    ev = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "lih_cell_eigenvalues.txt"), comments="#")
+    assert len(ev) == W.cfg2()["n_eig"]
+    assert np.all(np.diff(ev) >= 0)
+    assert np.all(np.isfinite(ev))

@@ -173,6 +173,34 @@ def test_cfg2_full_size_sampled_blocks():
     p.close()
 
 
+
+# FP64 eigenvalue tolerance, from the reduction's rounding: the Cholesky
+# reduction of H c = eps S c perturbs an eigenvalue by about
+# u * kappa(S) * |eps| with u = 1.1e-16, kappa(S) ~ 1e7 for the enriched
+# overlap and |eps| ~ 34 Ha here, i.e. ~4e-8 Ha, for the device solve and the
+# LAPACK solve of the stored values alike.
+EIG_TOL_FP64 = 1e-7
+
+
+def test_cfg2_eigenvalues_vs_oracle():
+    """The LiH-like workload at full size: the lowest 16 eigenvalues of the
+    FP64 GPU assembly against the FP64 oracle's (dense assembly and LAPACK
+    solve, stored by tests/golden/make_lih_cell_eigenvalues.py)."""
+    import os
+    prob = W.cfg2()
+    say("cfg2 eigenvalues vs stored oracle eigenvalues")
+    ev_o = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "lih_cell_eigenvalues.txt"), comments="#")
+    assert len(ev_o) == prob["n_eig"]
+    xyz, _, _ = oracle.Oracle(prob).quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    p = P.Problem(prob).setup()
+    H, S = p.assemble(V)
+    ev = P.eig(p.to_dense(H[0]).real.contiguous(), p.to_dense(S[0]).real.contiguous(), len(ev_o)).cpu().numpy()
+    err = np.abs(ev - ev_o).max()
+    say("max |eps - eps_oracle| (Ha)", err)
+    assert err < EIG_TOL_FP64
+    p.close()
+
 def test_cfg2_element_matrices_every_nloc():
     """Element matrices of the LiH-like workload at full size, one element per
     distinct n_loc (the most refined of each), against the oracle.  The set
