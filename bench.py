@@ -84,6 +84,24 @@ def eig_error(P, p, H, S, ev_ref):
     return float(np.abs(ev - ev_ref).max()), None
 
 
+MFMA_FILE = os.path.join(ROOT, "profiles", "contract_f64_lih_cell_mfma_counters.md")
+
+
+def recorded_mfma():
+    """(MFMA busy fraction, executed MFMA flop per launch) of the FP64
+    contraction from the rocprofv3 counter pass recorded for the current
+    kernel sources, else (None, None)."""
+    if not os.path.exists(MFMA_FILE):
+        return None, None
+    txt = open(MFMA_FILE).read()
+    m_h = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", txt)
+    m_b = re.search(r"mfma_busy_frac:\s*([0-9.eE+-]+)", txt)
+    m_x = re.search(r"mfma_executed_flops_per_launch:\s*([0-9.eE+-]+)", txt)
+    if not (m_h and m_b and m_x) or m_h.group(1) != kernel_sources_digest():
+        return None, None
+    return float(m_b.group(1)), float(m_x.group(1))
+
+
 def copy_probe(mib=1024, reps=3):
     """A plain device copy of known size, the scale for the PMC byte counters."""
     import torch
@@ -312,7 +330,10 @@ def main():
                     help="skip the batch (lattice sweep) and adjoint measurement legs")
     ap.add_argument("--host-inputs", action="store_true",
                     help="evaluate the synthetic V on the host and copy it over (no torch kernels; "
-                         "for hardware-counter runs)")
+                         "for hardware-counter runs); implies --no-eig")
+    ap.add_argument("--no-eig", action="store_true",
+                    help="skip the device eigensolves of the eigenvalue-error fields (the dense "
+                         "solver library does not run under hardware-counter collection)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (scale for the PMC byte counters)")
     args = ap.parse_args()
@@ -392,16 +413,24 @@ def main():
                   "nloc_min": int(nloc.min()), "nloc_max": int(nloc.max()),
                   "nq_max": int(nq.max())},
     }
+    if args.precision == "fp64":
+        # MFMA pipe utilisation from the recorded counter pass (SQ_VALU_MFMA_BUSY_CYCLES
+        # over the kernel's SIMD cycles) and the executed MFMA flops, padding included
+        busy, executed = recorded_mfma()
+        out["roofline"]["mfma_busy_frac"] = busy
+        out["roofline"]["mfma_executed_flops_per_launch"] = executed
     # eigenvalue error of the assembled matrices against the FP64 oracle
     # (outside the timed region)
+    do_eig = not (args.no_eig or args.host_inputs)
     ev_ref = golden_eigenvalues()
     eig = {"n_eig": int(len(ev_ref)), "unit": "Ha",
            "reference": "FP64 CPU oracle, dense LAPACK solve (tests/golden/lih_cell_eigenvalues.txt)"}
-    err, why = eig_error(P, p, H, S, ev_ref)
-    eig[args.precision] = err
-    if why:
-        eig[args.precision + "_note"] = why
-    log(f"eigenvalue error {args.precision}: {err}")
+    if do_eig:
+        err, why = eig_error(P, p, H, S, ev_ref)
+        eig[args.precision] = err
+        if why:
+            eig[args.precision + "_note"] = why
+        log(f"eigenvalue error {args.precision}: {err}")
     # the split-precision forms on the same inputs (context for the FP64 line)
     for prec in ("bf16x6", "bf16x3"):
         if prec == args.precision:
@@ -417,12 +446,14 @@ def main():
         out["extra"][f"{prec}_contract_ms"] = cms
         out["extra"][f"{prec}_tflops"] = alg_flops / (cms * 1e-3) / 1e12
         out["extra"][f"{prec}_frac_of_effective_peak"] = alg_flops / (cms * 1e-3) / 1e12 / PEAK[prec]
-        err, why = eig_error(P, p, H, S, ev_ref)
-        eig[prec] = err
-        if why:
-            eig[prec + "_note"] = why
-        log(f"eigenvalue error {prec}: {err}")
-    out["eig_err"] = eig
+        if do_eig:
+            err, why = eig_error(P, p, H, S, ev_ref)
+            eig[prec] = err
+            if why:
+                eig[prec + "_note"] = why
+            log(f"eigenvalue error {prec}: {err}")
+    if do_eig:
+        out["eig_err"] = eig
     p.close()
     if not args.no_rows and args.precision == "fp64":
         log("batch leg (lattice sweep)")
