@@ -30,26 +30,30 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kSplitThreads = 256;
 
-// FP32 -> bf16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ uint32_t bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values -> a packed pair of bf16 (low half: the first), rounded to
+// nearest even by the hardware conversion (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+    const f32x2 f = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
 }
 
-__device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
-
-// Limbs of x: the first from the FP64 value, the others from the residual,
-// which is exact in FP64 and carried on in FP32 (its FP32 rounding, below
-// 2^-32 |x|, is far under the last limb).
+// Limbs of two values x0, x1 (adjacent points of one row and component) as
+// packed bf16 pairs: the first limb from the FP64 values, the others from the
+// residuals, which are exact in FP64 and carried on in FP32 (their FP32
+// rounding, below 2^-32 |x|, is far under the last limb).
 template <int NL>
-__device__ __forceinline__ void split_limbs(double x, uint32_t *h) {
-    h[0] = bf16_bits((float)x);
-    float r = (float)(x - (double)bf16_float(h[0]));
+__device__ __forceinline__ void split_limbs2(double x0, double x1, uint32_t *h) {
+    h[0] = bf16_pair((float)x0, (float)x1);
+    float r0 = (float)(x0 - (double)__uint_as_float(h[0] << 16));
+    float r1 = (float)(x1 - (double)__uint_as_float(h[0] & 0xffff0000u));
 #pragma unroll
     for (int j = 1; j < NL; ++j) {
-        h[j] = bf16_bits(r);
-        r -= bf16_float(h[j]);
+        h[j] = bf16_pair(r0, r1);
+        r0 -= __uint_as_float(h[j] << 16);
+        r1 -= __uint_as_float(h[j] & 0xffff0000u);
     }
 }
 
@@ -203,7 +207,7 @@ __device__ __forceinline__ void contract_split_item(
         for (int idx = tid; idx < nrow * (Q / 2); idx += NT) {
             const int r = idx / (Q / 2), q0 = 2 * (idx - r * (Q / 2));
             const int a = sRow[r];
-            uint32_t hv[2][5][NL];
+            double comp[2][5];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const int q = q0 + t;
@@ -211,16 +215,20 @@ __device__ __forceinline__ void contract_split_item(
                 double val, gx[3];
                 local_row<Q>(kp, g, sPsi + q, sEd, a, nfe, &val, gx);
                 const double s2 = g[G_SW2 * Q], u = g[G_SW * Q] * val;
-                const double comp[5] = {s2 * gx[0], s2 * gx[1], s2 * gx[2], u, sV[q] * u};
-#pragma unroll
-                for (int c = 0; c < 5; ++c) split_limbs<NL>(comp[c], hv[t][c]);
+                comp[t][0] = s2 * gx[0];
+                comp[t][1] = s2 * gx[1];
+                comp[t][2] = s2 * gx[2];
+                comp[t][3] = u;
+                comp[t][4] = sV[q] * u;
             }
 #pragma unroll
-            for (int j = 0; j < NL; ++j)
+            for (int c = 0; c < 5; ++c) {
+                uint32_t hp[NL];
+                split_limbs2<NL>(comp[0][c], comp[1][c], hp);
 #pragma unroll
-                for (int c = 0; c < 5; ++c)
-                    *(uint32_t *)(sLimb + ((size_t)j * nrow + r) * RSB + (size_t)(c * Q + q0) * 2) =
-                        hv[0][c][j] | (hv[1][c][j] << 16);
+                for (int j = 0; j < NL; ++j)
+                    *(uint32_t *)(sLimb + ((size_t)j * nrow + r) * RSB + (size_t)(c * Q + q0) * 2) = hp[j];
+            }
         }
         __syncthreads();
         // ---- phase 3: MFMAs over limb products; lane = i + 16 grp holds the 8

@@ -289,3 +289,25 @@ def test_cfg4_full_size_sampled():
             say("cfg4 block", v, wv, shape)
             assert rel(Hg, Hb) < TOL and rel(Sg, Sb) < TOL, (v, wv)
     p.close()
+
+
+@pytest.mark.parametrize("p,mesh,kappa", [(1, (4, 3, 5), (0.1, -0.23, 0.37)),
+                                           (2, (3, 2, 2), (0.12, -0.24, 0.37)),
+                                           (2, (2, 3, 2), (0.0, 0.0, 0.0))])
+def test_empty_lattice_closed_form(p, mesh, kappa):
+    """The degenerate case with no enrichment (no groups, classical FE only)
+    and V = 0: the lowest eigenvalues of the GPU assembly are sums of the 1D
+    Bloch FE dispersions over the three axes, halved (the discrete |k+G|^2/2
+    of an empty lattice), a closed form independent of the oracle."""
+    from test_oracle_pins import _eig1d, bare, diag
+    L = (3.0, 3.3, 2.7)
+    prob = bare(diag(*L), mesh, p, n=3)
+    say("empty lattice", p, mesh, kappa)
+    pp = P.Problem(prob).setup()
+    V = torch.zeros(pp.sizes["n_qp"], dtype=torch.float64, device="cuda")
+    H, S = pp.assemble(V, [kappa])
+    ev = P.eig(pp.to_dense(H[0]), pp.to_dense(S[0]), 12).cpu().numpy()
+    lam = [_eig1d(mesh[d], L[d] / mesh[d], p, kappa[d]) for d in range(3)]
+    allev = np.sort((lam[0][:, None, None] + lam[1][None, :, None] + lam[2][None, None, :]).ravel() / 2)
+    assert np.abs(ev - allev[:12]).max() < 1e-11 * max(1, allev[11])
+    pp.close()
