@@ -186,7 +186,7 @@ def leg_batch(reps=5):
     import paper_1611_00731_amd as P
     import workloads as W
     from workloads.potential import potential_at
-    probs, kpts = W.cfg3(), W.mp2()
+    probs, kpts = W.lih_lattice_sweep(), W.mp2()
     ps, Vs, flops, nel = [], [], 0.0, 0
     for pr in probs:
         p = P.Problem(pr).setup()
@@ -230,7 +230,7 @@ def leg_backward(reps=3):
     import paper_1611_00731_amd as P
     import workloads as W
     from workloads.potential import potential_at
-    prob = W.cfg5()
+    prob = W.lih_supercell()
     p = P.Problem(prob).setup()
     xyz, _, _ = p.quadrature()
     V = potential_at(xyz, prob)
@@ -270,7 +270,7 @@ def leg_backward(reps=3):
     return out
 
 
-def leg_cfg4(reps=2):
+def leg_ceal_cell(reps=2):
     """One assembly of the CeAl-like cell (CsCl a = 5.8 bohr, 12^3 triquadratic
     hexes, 8^3 Gauss + 3 octree levels within 1 bohr, 41 enrichment functions
     per atom pair, n_loc up to 283) at 4 k-points, complex128 H and S, FP64."""
@@ -278,7 +278,7 @@ def leg_cfg4(reps=2):
     import paper_1611_00731_amd as P
     import workloads as W
     from workloads.potential import potential_at
-    prob = W.cfg4()
+    prob = W.ceal_cell()
     p = P.Problem(prob).setup()
     xyz, _, _ = p.quadrature()
     V = potential_at(xyz, prob)
@@ -352,7 +352,7 @@ def main():
     from workloads.potential import potential_at
 
     dev = torch.device("cuda", 0)
-    prob = W.cfg2()
+    prob = W.lih_cell()
     log("setup", prob["name"])
     p = P.Problem(prob).setup()
     if not args.no_tune:
@@ -461,7 +461,7 @@ def main():
         log("adjoint leg (64-atom supercell)")
         out["extra"]["adjoint"] = leg_backward()
         log("CeAl-like cell leg")
-        out["extra"]["ceal_cell"] = leg_cfg4()
+        out["extra"]["ceal_cell"] = leg_ceal_cell()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob)

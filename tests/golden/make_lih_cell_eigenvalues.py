@@ -24,7 +24,7 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lih_cell_eigenva
 
 
 def main():
-    prob = W.cfg2()
+    prob = W.lih_cell()
     m = prob["n_eig"]
     t0 = time.time()
     o = oracle.Oracle(prob)

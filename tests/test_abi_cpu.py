@@ -77,10 +77,10 @@ def test_input_validation():
 
 
 PROBLEMS = {
-    "cfg1": W.cfg1,
-    "cfg2": W.cfg2,
-    "cfg4": W.cfg4,
-    "cfg5": W.cfg5,
+    "single_atom_cube": W.single_atom_cube,
+    "lih_cell": W.lih_cell,
+    "ceal_cell": W.ceal_cell,
+    "lih_supercell": W.lih_supercell,
     "lih-odd": lambda: W.small("lih", mesh=(3, 5, 3), fe_order=2, a=5.0),
     "one-p1": lambda: W.small("one", mesh=(2, 3, 4), fe_order=1, a=4.0),
     "ceal": lambda: W.small("ceal", mesh=(3, 3, 3), fe_order=2, a=5.0, rc=3.0, re=2.1),
@@ -103,7 +103,7 @@ def test_dof_map_and_enriched_sets_match_oracle(name):
         p.close()
 
 
-@pytest.mark.parametrize("name", ["cfg1", "lih-odd", "one-p1", "ceal", "skew"])
+@pytest.mark.parametrize("name", ["single_atom_cube", "lih-odd", "one-p1", "ceal", "skew"])
 def test_block_pattern_matches_element_coupling(name):
     prob = PROBLEMS[name]()
     o = oracle.Oracle(prob)
@@ -135,7 +135,7 @@ def test_block_pattern_matches_element_coupling(name):
 
 def test_workload_sizes():
     """Sizes of the measured workloads (DOFs, BSR entries) from the host plan."""
-    p = P.Problem(W.cfg2())
+    p = P.Problem(W.lih_cell())
     try:
         s = p.sizes
         assert (s["n_elem"], s["n_dof"], s["n_colors"]) == (512, 4888, 8)
@@ -152,6 +152,6 @@ def test_golden_lih_cell_eigenvalues_file():
     import numpy as np
     import workloads as W
     ev = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "lih_cell_eigenvalues.txt"), comments="#")
-    assert len(ev) == W.cfg2()["n_eig"]
+    assert len(ev) == W.lih_cell()["n_eig"]
     assert np.all(np.diff(ev) >= 0)
     assert np.all(np.isfinite(ev))

@@ -117,13 +117,13 @@ def test_autograd_function_and_finite_differences():
     p.close()
 
 
-def test_backward_cfg5_full_size():
+def test_backward_lih_supercell_full_size():
     """2x2x2 LiH-like supercell (64 atoms, 4096 elements, 12.1 M points),
     rank-128 Hermitian PSD P on the pattern: dL/dV on sampled elements against
     the oracle's per-element adjoint, dL/dR against central differences of the
     GPU forward."""
-    prob = W.cfg5()
-    say("backward cfg5 full size")
+    prob = W.lih_supercell()
+    say("backward lih_supercell full size")
     o = oracle.Oracle(prob)
     xyz, w, qoff = o.quadrature()
     Vd = potential_at(torch.from_numpy(xyz).cuda(), prob)

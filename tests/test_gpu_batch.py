@@ -65,12 +65,12 @@ def test_batch_small_sweep_vs_oracle():
         p.close()
 
 
-def test_batch_cfg3_full_size_sampled():
+def test_batch_lih_lattice_sweep_full_size_sampled():
     """The 11 lattice constants x 8 k-points sweep (88 assemblies in one
     persistent launch): sampled BSR blocks against the oracle."""
-    probs = W.cfg3()
+    probs = W.lih_lattice_sweep()
     kpts = W.mp2()
-    say("batch cfg3 full size")
+    say("batch lih_lattice_sweep full size")
     ps, Vs, oracles, Vh = [], [], [], []
     for pr in probs:
         o = oracle.Oracle(pr)

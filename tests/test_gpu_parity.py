@@ -59,7 +59,7 @@ SMALL = {
                   [(0.0, 0.0, 0.0), (0.1, -0.2, 0.3)]),
     "ceal-error": (lambda: _error_mode(W.small("ceal", mesh=(2, 2, 2), fe_order=1, a=4.4, rc=2.6, re=2.0),
                                        n=2, n_ref=4, levels=2, tol=1e-5), [(0.0, 0.0, 0.0)]),
-    "cfg1": (W.cfg1, [(0.0, 0.0, 0.0), (0.1, 0.2, -0.3)]),
+    "single_atom_cube": (W.single_atom_cube, [(0.0, 0.0, 0.0), (0.1, 0.2, -0.3)]),
     "lih-p2-l1": (lambda: W.small("lih", mesh=(3, 2, 2), fe_order=2, levels=1, n=3, a=5.0),
                   [(0.0, 0.0, 0.0), (0.12, -0.24, 0.37), (0.25, 0.25, -0.25)]),
     "lih-odd-p1": (lambda: W.small("lih", mesh=(3, 3, 2), fe_order=1, levels=2, n=2, a=4.6),
@@ -129,9 +129,9 @@ def test_output_dtypes_gamma_and_c64():
     p.close()
 
 
-def test_cfg1_eigenvalues():
-    prob = W.cfg1()
-    say("cfg1 eigenvalues")
+def test_single_atom_cube_eigenvalues():
+    prob = W.single_atom_cube()
+    say("single_atom_cube eigenvalues")
     o, xyz, w, off, V = oracle_inputs(prob)
     Ho, So = o.assemble_dense(V)
     ev_o = oracle.generalized_eigh(Ho, So, 4)
@@ -142,12 +142,12 @@ def test_cfg1_eigenvalues():
     p.close()
 
 
-def test_cfg2_full_size_sampled_blocks():
+def test_lih_cell_full_size_sampled_blocks():
     """The LiH-like workload at full size (512 elements, 1.52 M points): rule
     equality, and sampled BSR blocks (near and far from nuclei) against the
     oracle's block assembly."""
-    prob = W.cfg2()
-    say("cfg2 full size")
+    prob = W.lih_cell()
+    say("lih_cell full size")
     o = oracle.Oracle(prob)
     xyz, w, off = o.quadrature()
     p = P.Problem(prob).setup()
@@ -182,13 +182,13 @@ def test_cfg2_full_size_sampled_blocks():
 EIG_TOL_FP64 = 1e-7
 
 
-def test_cfg2_eigenvalues_vs_oracle():
+def test_lih_cell_eigenvalues_vs_oracle():
     """The LiH-like workload at full size: the lowest 16 eigenvalues of the
     FP64 GPU assembly against the FP64 oracle's (dense assembly and LAPACK
     solve, stored by tests/golden/make_lih_cell_eigenvalues.py)."""
     import os
-    prob = W.cfg2()
-    say("cfg2 eigenvalues vs stored oracle eigenvalues")
+    prob = W.lih_cell()
+    say("lih_cell eigenvalues vs stored oracle eigenvalues")
     ev_o = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "lih_cell_eigenvalues.txt"), comments="#")
     assert len(ev_o) == prob["n_eig"]
     xyz, _, _ = oracle.Oracle(prob).quadrature()
@@ -201,13 +201,13 @@ def test_cfg2_eigenvalues_vs_oracle():
     assert err < EIG_TOL_FP64
     p.close()
 
-def test_cfg2_element_matrices_every_nloc():
+def test_lih_cell_element_matrices_every_nloc():
     """Element matrices of the LiH-like workload at full size, one element per
     distinct n_loc (the most refined of each), against the oracle.  The set
     spans last tiles with at most 4 and with 5..8 real rows (the tail pairs
     of whole-element items) and fuller last tiles, on 3, 4 and 5 tiles."""
-    prob = W.cfg2()
-    say("cfg2 element matrices, every n_loc")
+    prob = W.lih_cell()
+    say("lih_cell element matrices, every n_loc")
     o = oracle.Oracle(prob)
     xyz, w, off = o.quadrature()
     Vh = potential_at(torch.from_numpy(xyz).cuda(), prob).cpu().numpy()
@@ -231,15 +231,15 @@ def test_cfg2_element_matrices_every_nloc():
     p.close()
 
 
-def test_cfg4_full_size_sampled():
+def test_ceal_cell_full_size_sampled():
     """The CeAl-like workload at full size (1728 elements, 27.3 M points,
     N = 37,891, n_loc up to 283: items of several row and column blocks):
     rule equality, element matrices of the unrefined element with the most
     functions and of the least refined octree element, and BSR blocks around
     vertices whose elements are all unrefined, at one k-point."""
-    prob = W.cfg4()
+    prob = W.ceal_cell()
     kap = tuple(prob["kpts"][1])
-    say("cfg4 full size")
+    say("ceal_cell full size")
     o = oracle.Oracle(prob)
     xyz, w, off = o.quadrature()
     p = P.Problem(prob).setup()
@@ -254,7 +254,7 @@ def test_cfg4_full_size_sampled():
     refined = np.flatnonzero(nleaf > 1)
     e_big = int(plain[np.argmax(nloc[plain])])
     e_ref = int(refined[np.argmin(nleaf[refined])])
-    say("cfg4 elements", e_big, "n_loc", nloc[e_big], "|", e_ref, "leaves", nleaf[e_ref], "n_loc", nloc[e_ref])
+    say("ceal_cell elements", e_big, "n_loc", nloc[e_big], "|", e_ref, "leaves", nleaf[e_ref], "n_loc", nloc[e_ref])
     for e in (e_big, e_ref):
         He, Se = p.element_matrices(e, Vd)
         Ho, So = o.element_matrices(e, Vh[off[e]:off[e + 1]])
@@ -286,7 +286,7 @@ def test_cfg4_full_size_sampled():
             shape = (off_d[v + 1] - off_d[v], off_d[wv + 1] - off_d[wv])
             Hg = (Hh[b0:b1, 0] + 1j * Hh[b0:b1, 1]).reshape(shape)
             Sg = (Sh[b0:b1, 0] + 1j * Sh[b0:b1, 1]).reshape(shape)
-            say("cfg4 block", v, wv, shape)
+            say("ceal_cell block", v, wv, shape)
             assert rel(Hg, Hb) < TOL and rel(Sg, Sb) < TOL, (v, wv)
     p.close()
 

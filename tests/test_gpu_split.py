@@ -54,9 +54,9 @@ def test_split_small_vs_oracle(name):
     p.close()
 
 
-def test_split_cfg1_eigenvalues():
-    prob = W.cfg1()
-    say("split cfg1 eigenvalues")
+def test_split_single_atom_cube_eigenvalues():
+    prob = W.single_atom_cube()
+    say("split single_atom_cube eigenvalues")
     o = oracle.Oracle(prob)
     xyz, _, _ = o.quadrature()
     V = potential_at(torch.from_numpy(xyz).cuda(), prob)
@@ -69,11 +69,11 @@ def test_split_cfg1_eigenvalues():
     p.close()
 
 
-def test_split_cfg2_full_size_eigenvalues():
+def test_split_lih_cell_full_size_eigenvalues():
     """The LiH-like workload at full size: H/S errors of both split forms and
     the lowest 16 eigenvalues against the oracle's dense FP64 assembly."""
-    prob = W.cfg2()
-    say("split cfg2 full size (oracle dense assembly, ~1 min)")
+    prob = W.lih_cell()
+    say("split lih_cell full size (oracle dense assembly, ~1 min)")
     o = oracle.Oracle(prob)
     xyz, _, _ = o.quadrature()
     V = potential_at(torch.from_numpy(xyz).cuda(), prob)

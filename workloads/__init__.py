@@ -30,8 +30,8 @@ import math
 import numpy as np
 
 __all__ = [
-    "cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "small", "lih_table1",
-    "mp2", "kpts_cfg4", "jitter", "adjoint_factor", "with_lattice_constant",
+    "single_atom_cube", "lih_cell", "lih_lattice_sweep", "ceal_cell", "lih_supercell", "small", "lih_table1",
+    "mp2", "ceal_kpoints", "jitter", "adjoint_factor", "with_lattice_constant",
     "orthorhombic",
 ]
 
@@ -44,7 +44,7 @@ def mp2():
     return copy.deepcopy(MP2)
 
 
-def kpts_cfg4():
+def ceal_kpoints():
     """Time-reversal-reduced MP 2x2x2 set (4 points) for the CeAl-like cell."""
     return [[0.25, 0.25, 0.25], [0.25, 0.25, -0.25],
             [0.25, -0.25, 0.25], [-0.25, 0.25, 0.25]]
@@ -97,7 +97,7 @@ def _problem(lattice, mesh, fe_order, atoms, species, species_info, enrichments,
     }
 
 
-def cfg1():
+def single_atom_cube():
     """Single-atom cube: side 4.0, 4^3 trilinear, 5^3 Gauss, no refinement;
     s enrichment a=1.0, rc=2.5, support radius 1.5; Gamma; 4 eigenpairs."""
     return _problem(
@@ -105,7 +105,7 @@ def cfg1():
         [{"name": "X", "Z": 1.0, "rloc": 0.5}],
         [{"species": 0, "l": 0, "a": 1.0, "rc": 2.5, "re": 1.5}],
         {"n": 5, "n_ref": 8, "levels": 0, "mode": "geom", "dist": 1.0, "tol": 1e-6},
-        [[0.0, 0.0, 0.0]], 4, "cfg1")
+        [[0.0, 0.0, 0.0]], 4, "single_atom_cube")
 
 
 LIH_ENR = [
@@ -135,7 +135,7 @@ def _lih_reduced(cells=1):
     return np.array(red), spc
 
 
-def cfg2(a: float = 7.6, mesh=8):
+def lih_cell(a: float = 7.6, mesh=8):
     """Rock-salt LiH-like cell (4 Li + 4 H), jittered N(0, 0.05) seed 0,
     triquadratic mesh^3, 6^3 Gauss + 2 geometric octree levels within 1 bohr."""
     red, spc = _lih_reduced(1)
@@ -143,7 +143,7 @@ def cfg2(a: float = 7.6, mesh=8):
     return _problem(
         cubic(a), [mesh] * 3, 2, pos, spc, LIH_SPECIES, copy.deepcopy(LIH_ENR),
         {"n": 6, "n_ref": 8, "levels": 2, "mode": "geom", "dist": 1.0, "tol": 1e-6},
-        [[0.0, 0.0, 0.0]], 16, "cfg2")
+        [[0.0, 0.0, 0.0]], 16, "lih_cell")
 
 
 def with_lattice_constant(prob, a: float):
@@ -159,10 +159,10 @@ def with_lattice_constant(prob, a: float):
     return out
 
 
-def cfg3():
+def lih_lattice_sweep():
     """The LiH-like cell at 11 lattice constants 6.80..8.40 with the 8-point
     MP 2x2x2 k set: a list of 11 problems (88 assemblies)."""
-    base = cfg2()
+    base = lih_cell()
     out = []
     for i in range(11):
         a = round(6.8 + 0.16 * i, 10)
@@ -172,7 +172,7 @@ def cfg3():
     return out
 
 
-def cfg4():
+def ceal_cell():
     """CsCl CeAl-like cell a=5.8: Ce at 0, Al at the body centre; 12^3
     triquadratic, 8^3 Gauss + 3 octree levels within 1 bohr; Ce s,p,d,f x
     {3.0, 0.4} (32 functions), Al s,p,d (0.6) (9 functions), rc = 4,
@@ -189,10 +189,10 @@ def cfg4():
         [{"name": "Ce", "Z": 12.0, "rloc": 0.3}, {"name": "Al", "Z": 3.0, "rloc": 0.3}],
         enr,
         {"n": 8, "n_ref": 10, "levels": 3, "mode": "geom", "dist": 1.0, "tol": 1e-6},
-        kpts_cfg4(), 16, "cfg4")
+        ceal_kpoints(), 16, "ceal_cell")
 
 
-def cfg5():
+def lih_supercell():
     """2x2x2 supercell of the LiH-like cell (a = 15.2, 64 atoms, jittered
     N(0, 0.05) seed 0), 16^3 triquadratic, same rule and enrichments; Gamma."""
     a = 15.2
@@ -201,7 +201,7 @@ def cfg5():
     return _problem(
         cubic(a), [16] * 3, 2, pos, spc, LIH_SPECIES, copy.deepcopy(LIH_ENR),
         {"n": 6, "n_ref": 8, "levels": 2, "mode": "geom", "dist": 1.0, "tol": 1e-6},
-        [[0.0, 0.0, 0.0]], 16, "cfg5")
+        [[0.0, 0.0, 0.0]], 16, "lih_supercell")
 
 
 def small(kind: str = "lih", mesh=(2, 3, 2), fe_order: int = 2, levels: int = 1,
