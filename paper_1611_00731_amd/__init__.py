@@ -61,7 +61,7 @@ def _load():
     # (two runtimes in one process do not share devices, streams or memory)
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libpufe.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        raise ImportError(f"libpufe.so is not built ({LIB_PATH}); run python -m paper_1611_00731_amd.build")
     L = C.CDLL(LIB_PATH)
     vp, i64p, i32p, dp = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)
     sig = {
