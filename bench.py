@@ -228,7 +228,8 @@ def leg_batch(reps=5):
 def leg_backward(reps=3):
     """assemble_backward on the 2x2x2 LiH-like supercell (64 atoms, 4096
     elements, 12.1 M points) with a rank-128 Hermitian PSD adjoint P on the
-    pattern: dL/dV at every point and dL/dR for all atoms, FP64."""
+    pattern: dL/dV at every point and dL/dR for all atoms, FP64 and both split
+    forms (errors against the FP64 result)."""
     import numpy as np
     import torch
     import paper_1611_00731_amd as P
@@ -249,27 +250,37 @@ def leg_backward(reps=3):
         r, c = rows_d[s0:s0 + (1 << 20)], cols_d[s0:s0 + (1 << 20)]
         Pb[s0:s0 + (1 << 20)] = (Cd[r] * Cd[c].conj()).sum(-1)
     del Cd, rows_d, cols_d
-    p.backward(V, (0.0, 0.0, 0.0), Pb, None)
-    torch.cuda.synchronize()
-    P.pufe_enable_timing(p.ctx, True)
-    P.pufe_kernel_times(p.ctx, reset=True)
     st = torch.cuda.current_stream()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record(st)
-    for _ in range(reps):
-        p.backward(V, (0.0, 0.0, 0.0), Pb, None)
-    t1.record(st)
-    torch.cuda.synchronize()
-    kms, kc = P.pufe_kernel_times(p.ctx, reset=True)
-    P.pufe_enable_timing(p.ctx, False)
-    ms = t0.elapsed_time(t1) / reps
     # P~ [grad phi; phi] at every point: 8 n_q n_loc^2 flops
     flops = float((8.0 * nq * nloc.astype(float) ** 2).sum())
-    kern = kms[2] / max(kc[2], 1)
+
+    def timed(prec):
+        dV, dR = p.backward(V, (0.0, 0.0, 0.0), Pb, None, precision=prec)
+        torch.cuda.synchronize()
+        P.pufe_enable_timing(p.ctx, True)
+        P.pufe_kernel_times(p.ctx, reset=True)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(st)
+        for _ in range(reps):
+            p.backward(V, (0.0, 0.0, 0.0), Pb, None, precision=prec)
+        t1.record(st)
+        torch.cuda.synchronize()
+        kms, kc = P.pufe_kernel_times(p.ctx, reset=True)
+        P.pufe_enable_timing(p.ctx, False)
+        return dV, dR, t0.elapsed_time(t1) / reps, kms[2] / max(kc[2], 1)
+
+    dV, dR, ms, kern = timed("fp64")
     out = {"workload": "64-atom LiH-like supercell, 4096 elements, rank-128 adjoint, dL/dV + dL/dR",
            "ms": ms, "adjoint_kernels_ms": kern, "elements_per_s": p.sizes["n_elem"] / (ms * 1e-3),
            "alg_flops": flops, "alg_tflops_adjoint_kernels": flops / (kern * 1e-3) / 1e12,
            "frac_of_fp64_peak": flops / (kern * 1e-3) / 1e12 / PEAK["fp64"]}
+    # split-precision forms of U = P~ B, errors against the FP64 result
+    for prec in ("bf16x6", "bf16x3"):
+        dVs, dRs, ms_s, kern_s = timed(prec)
+        out[prec] = {"ms": ms_s, "adjoint_kernels_ms": kern_s,
+                     "alg_tflops_adjoint_kernels": flops / (kern_s * 1e-3) / 1e12,
+                     "dLdV_rel_err_vs_fp64": float((dVs - dV).norm() / dV.norm()),
+                     "dLdR_max_err_rel_vs_fp64": float((dRs - dR).abs().max() / dR.abs().max())}
     p.close()
     return out
 

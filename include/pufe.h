@@ -189,7 +189,12 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
  *   d_dLdR[n_atoms*3] = derivative with respect to the enrichment centres
  *                       (rule, enriched sets and V held fixed),
  * with Pt_ab = Re(p_a P_{g_a g_b} conj(p_b)).  Output pointers may be NULL.
- * Elements of more than 80 local functions give PUFE_ERR_UNSUPPORTED. */
+ * precision: PUFE_PREC_FP64, or PUFE_PREC_BF16X3 / PUFE_PREC_BF16X6 for the
+ * split-precision form, in which the dense product U = Pt [grad phi; phi]
+ * runs on BF16 MFMAs from two or three bf16 limbs per operand with FP32 sums
+ * (the rest of the adjoint stays FP64).  Elements of more than 80 local
+ * functions give PUFE_ERR_UNSUPPORTED; an unknown precision
+ * PUFE_ERR_INVALID_ARG. */
 int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3], const void *d_P,
                            const void *d_Q, int precision, double *d_dLdV, double *d_dLdR,
                            void *stream);

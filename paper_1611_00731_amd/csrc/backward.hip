@@ -16,6 +16,7 @@
 #include "device_common.hpp"
 #include "stage.hpp"
 #include "tables.hpp"
+#include "limbs.hpp"
 
 namespace pufe {
 
@@ -101,7 +102,8 @@ __device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double 
 }
 
 // LDS map of the adjoint (per work item):
-//   sP[npad][RSP]    Ps (or Qs) of the element, RSP = npad + 1
+//   sP[npad][RSP]    Ps (or Qs) of the element, RSP = npad + 1 (FP64 form), or
+//                    its bf16 limbs sPL[limb][npad][limb_row_bytes] (split form)
 //   sB[npad][4][Q]   B = [d_x phi, d_y phi, d_z phi, phi] at the stage points
 //   sUe[nenr][4][Q]  U = Ps B on the enriched rows (the only ones the force needs)
 //   sPsi[f][10][Q]   value, gradient and Hessian of the enrichment functions
@@ -114,8 +116,15 @@ struct BackwardLds {
     static constexpr int RSB = 4 * Q + 2;   // 16-byte rows
     static constexpr int GEO = 40;
     static_assert(RSB >= 3 * Q, "force contributions reuse the rows of sB");   // and stay below row nloc
+    // row stride in bytes of the bf16 limbs of Ps (16-byte rows, offset banks)
+    static __host__ __device__ int limb_row_bytes(int npad) { return 2 * npad + 16; }
+    // doubles of the Ps region: the FP64 block, or up to three limb blocks
+    static __host__ __device__ size_t p_doubles(int npad) {
+        const size_t f = (size_t)npad * (npad + 1), l = (3 * (size_t)npad * limb_row_bytes(npad) + 7) / 8;
+        return f > l ? f : l;
+    }
     static __host__ __device__ size_t bytes(int npad, int nenr, int nfun, int nimg) {
-        return sizeof(double) * ((size_t)npad * (npad + 1) + (size_t)npad * RSB + (size_t)nenr * RSB +
+        return sizeof(double) * (p_doubles(npad) + (size_t)npad * RSB + (size_t)nenr * RSB +
                                  (size_t)nfun * Q * 10 + (size_t)Q * GEO + (size_t)nimg * 3) +
                sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * (kMaxNloc + 16) + 64;
     }
@@ -169,23 +178,87 @@ __device__ __forceinline__ void backward_mfma(const double *__restrict__ sP, con
     }
 }
 
-template <int Q, bool DENS>
+// Split-precision form of backward_mfma: Ps comes as NL bf16 limbs (split
+// once per item), B is split into limbs in registers as its FP64 rows are
+// read, and U = Ps B is summed from the kept limb products on
+// v_mfma_f32_16x16x32_bf16 in FP32, K-blocks of 32 functions (the block past
+// npad reads zeros).  Lane l = i + 16 g supplies row i of the A tile at
+// functions 8 g .. 8 g + 7 of the block and those functions at point i of B;
+// result register r of lane l is row 4 (l / 16) + r, point l % 16.
+template <int T, int Q, bool DENS, int NL>
+__device__ __forceinline__ void backward_mfma_split(const unsigned char *__restrict__ sPL, const double *__restrict__ sB,
+                                                    double *__restrict__ sUe, const double *__restrict__ sGeo,
+                                                    int RSP, int nloc, int nfe, int c, int lane, int64_t qb,
+                                                    int64_t q_end, double *__restrict__ dLdV) {
+    static_assert(Q == 16, "one output tile spans the stage");
+    constexpr int RSB = BackwardLds<Q>::RSB;
+    constexpr int npad = 16 * T;
+    const int r16 = lane & 15, g4 = lane >> 4;
+    f32x4 acc[T];
+#pragma unroll
+    for (int I = 0; I < T; ++I) acc[I] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < npad; kb += 32) {
+        const int b0 = kb + 8 * g4;
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = b0 + i < npad ? sB[(size_t)(b0 + i) * RSB + c * Q + r16] : 0.0;
+        bf16x8 Bl[NL];
+        split_limbs8<NL>(v, Bl);
+        const int RPL = BackwardLds<Q>::limb_row_bytes(npad);
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+            bf16x8 Al[NL];
+#pragma unroll
+            for (int j = 0; j < NL; ++j)
+                Al[j] = b0 < npad ? *(const bf16x8 *)(sPL + ((size_t)j * npad + 16 * I + r16) * RPL + 2 * b0)
+                                  : (bf16x8){};
+            acc[I] = mfma_limbs<NL>(Al, Bl, acc[I]);
+        }
+    }
+    double dens = 0.0;
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * I + 4 * g4 + r;
+            const double u = (double)acc[I][r];
+            if (row >= nfe && row < nloc) sUe[(size_t)(row - nfe) * RSB + c * Q + r16] = u;
+            if (DENS && row < nloc) dens += sB[(size_t)row * RSB + 3 * Q + r16] * u;
+        }
+    if (DENS) {
+        dens += __shfl_xor(dens, 16, 64);
+        dens += __shfl_xor(dens, 32, 64);
+        const int64_t qg = qb + r16;
+        if (g4 == 0 && qg < q_end) dLdV[qg] = sGeo[B_W * Q + r16] * dens;
+    }
+}
+
+template <int Q, bool DENS, int NL>
 __device__ __forceinline__ void backward_mfma_dispatch(int T, const double *sP, const double *sB, double *sUe,
                                                        const double *sGeo, int RSP, int nloc, int nfe, int c,
                                                        int lane, int64_t qb, int64_t q_end, double *dLdV) {
+#define PUFE_BWM(TT)                                                                                     \
+    if constexpr (NL == 0)                                                                               \
+        backward_mfma<TT, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV);         \
+    else                                                                                                 \
+        backward_mfma_split<TT, Q, DENS, NL>((const unsigned char *)sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, \
+                                             q_end, dLdV)
     switch (T) {
-        case 1: backward_mfma<1, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
-        case 2: backward_mfma<2, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
-        case 3: backward_mfma<3, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
-        case 4: backward_mfma<4, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
-        default: backward_mfma<5, Q, DENS>(sP, sB, sUe, sGeo, RSP, nloc, nfe, c, lane, qb, q_end, dLdV); break;
+        case 1: PUFE_BWM(1); break;
+        case 2: PUFE_BWM(2); break;
+        case 3: PUFE_BWM(3); break;
+        case 4: PUFE_BWM(4); break;
+        default: PUFE_BWM(5); break;
     }
+#undef PUFE_BWM
 }
 
 // One work group per (element, range of leaves).  QMODE = false: the P pass
 // (density and the gradient/potential force terms); QMODE = true: the Q pass
-// (overlap force term only).
-template <int Q, bool QMODE>
+// (overlap force term only).  NL = 0: U = Ps B on FP64 MFMAs; NL = 2 or 3:
+// split-precision U from 2 or 3 bf16 limbs per operand (bf16x3, bf16x6).
+template <int Q, bool QMODE, int NL>
 __global__ __launch_bounds__(256) void backward_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
@@ -201,7 +274,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
     const int img0 = ngrp > 0 ? groups[el.grp_off].img_off : 0;
     const int nimg = ngrp > 0 ? groups[el.grp_off + ngrp - 1].img_off + groups[el.grp_off + ngrp - 1].nimg - img0 : 0;
     double *sP = smem;
-    double *sB = sP + (size_t)npad * RSP;
+    double *sB = sP + BackwardLds<Q>::p_doubles(npad);
     double *sUe = sB + (size_t)npad * RSB;
     double *sPsi = sUe + (size_t)nenr * RSB;
     double *sGeo = sPsi + (size_t)nfun * Q * 10;
@@ -214,9 +287,22 @@ __global__ __launch_bounds__(256) void backward_kernel(
     const int n3 = kp.n3;
     const int64_t q_begin = it.leaf_b * n3, q_end = it.leaf_e * n3;
     const double *src = Pt + pt_off[it.elem];
-    for (int idx = tid; idx < npad * npad; idx += NT) {
-        const int a = idx / npad, b = idx - a * npad;
-        sP[(size_t)a * RSP + b] = src[idx];
+    if constexpr (NL == 0) {
+        for (int idx = tid; idx < npad * npad; idx += NT) {
+            const int a = idx / npad, b = idx - a * npad;
+            sP[(size_t)a * RSP + b] = src[idx];
+        }
+    } else {
+        // bf16 limbs of Ps, split once per item (two adjacent entries per thread)
+        unsigned char *sPL = (unsigned char *)sP;
+        const int RPL = BackwardLds<Q>::limb_row_bytes(npad), hp = npad / 2;
+        for (int idx = tid; idx < npad * hp; idx += NT) {
+            const int a = idx / hp, b = 2 * (idx - a * hp);
+            uint32_t h[NL];
+            split_limbs2<NL>(src[(size_t)a * npad + b], src[(size_t)a * npad + b + 1], h);
+#pragma unroll
+            for (int j = 0; j < NL; ++j) *(uint32_t *)(sPL + ((size_t)j * npad + a) * RPL + 2 * b) = h[j];
+        }
     }
     for (int k = tid; k < nenr; k += NT) sEd[k] = edof[el.edof_off + k];
     corner_starts((const PUFE_GLOBAL int32_t *)(edof + el.edof_off), nenr, sCS, tid, NT);
@@ -331,9 +417,9 @@ __global__ __launch_bounds__(256) void backward_kernel(
         // ---- phase 3: U = Ps B on the MFMAs, one operand component per wave;
         // the value component also gives the density
         if (!QMODE && dLdV != nullptr && wave == 3)
-            backward_mfma_dispatch<Q, true>(T, sP, sB, sUe, sGeo, RSP, nloc, nfe, wave, lane, qb, q_end, dLdV);
+            backward_mfma_dispatch<Q, true, NL>(T, sP, sB, sUe, sGeo, RSP, nloc, nfe, wave, lane, qb, q_end, dLdV);
         else
-            backward_mfma_dispatch<Q, false>(T, sP, sB, sUe, sGeo, RSP, nloc, nfe, wave, lane, qb, q_end, dLdV);
+            backward_mfma_dispatch<Q, false, NL>(T, sP, sB, sUe, sGeo, RSP, nloc, nfe, wave, lane, qb, q_end, dLdV);
         __syncthreads();
         // ---- phase 4: force contributions of every (enriched row, point)
         for (int idx = tid; idx < nenr * Q; idx += NT) {
@@ -423,11 +509,17 @@ __global__ void force_reduce_kernel(int n_atoms, const int64_t *__restrict__ ato
 }
 
 hipError_t init_backward_attributes() {
-    hipError_t e = hipFuncSetAttribute((const void *)backward_kernel<kBackwardQ, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)backward_kernel<kBackwardQ, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+    const void *ks[6] = {(const void *)backward_kernel<kBackwardQ, false, 0>,
+                         (const void *)backward_kernel<kBackwardQ, true, 0>,
+                         (const void *)backward_kernel<kBackwardQ, false, 2>,
+                         (const void *)backward_kernel<kBackwardQ, true, 2>,
+                         (const void *)backward_kernel<kBackwardQ, false, 3>,
+                         (const void *)backward_kernel<kBackwardQ, true, 3>};
+    for (const void *k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 size_t backward_lds_bytes(int npad, int nenr, int nfun, int nimg) {
@@ -442,17 +534,25 @@ hipError_t launch_gather_adjoint(const KParams &kp, int64_t nel, const ElemDev *
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const KParams &kp, bool qmode, int n_items, const ItemDev *items, const ElemDev *elems,
-                           const GroupDev *groups, const double *img, const int32_t *edof, const uint32_t *leaves,
-                           const double *V, const int64_t *pt_off, const double *Pt, double *dLdV, double *fpart,
-                           int max_ngrp, size_t lds, hipStream_t st) {
+hipError_t launch_backward(const KParams &kp, bool qmode, int nl, int n_items, const ItemDev *items,
+                           const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
+                           const uint32_t *leaves, const double *V, const int64_t *pt_off, const double *Pt,
+                           double *dLdV, double *fpart, int max_ngrp, size_t lds, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
-    if (qmode)
-        hipLaunchKernelGGL((backward_kernel<kBackwardQ, true>), dim3(n_items), dim3(256), lds, st, kp, items, elems,
-                           groups, img, edof, leaves, V, pt_off, Pt, dLdV, fpart, max_ngrp);
-    else
-        hipLaunchKernelGGL((backward_kernel<kBackwardQ, false>), dim3(n_items), dim3(256), lds, st, kp, items, elems,
-                           groups, img, edof, leaves, V, pt_off, Pt, dLdV, fpart, max_ngrp);
+    if (nl != 0 && nl != 2 && nl != 3) return hipErrorInvalidValue;
+#define PUFE_BWK(QM, NLV)                                                                                    \
+    hipLaunchKernelGGL((backward_kernel<kBackwardQ, QM, NLV>), dim3(n_items), dim3(256), lds, st, kp, items, \
+                       elems, groups, img, edof, leaves, V, pt_off, Pt, dLdV, fpart, max_ngrp)
+    if (qmode) {
+        if (nl == 0) PUFE_BWK(true, 0);
+        else if (nl == 2) PUFE_BWK(true, 2);
+        else PUFE_BWK(true, 3);
+    } else {
+        if (nl == 0) PUFE_BWK(false, 0);
+        else if (nl == 2) PUFE_BWK(false, 2);
+        else PUFE_BWK(false, 3);
+    }
+#undef PUFE_BWK
     return hipGetLastError();
 }
 

@@ -625,7 +625,9 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
     if (!ctx) return PUFE_ERR_INVALID_ARG;
     if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
     if (!d_V || !kpt) return fail(ctx, PUFE_ERR_INVALID_ARG, "null V or k-point");
-    if (precision != PUFE_PREC_FP64) return fail(ctx, PUFE_ERR_UNSUPPORTED, "the adjoint runs in FP64");
+    if (precision < PUFE_PREC_FP64 || precision > PUFE_PREC_BF16X6)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "unknown precision");
+    const int nl = precision == PUFE_PREC_BF16X3 ? 2 : (precision == PUFE_PREC_BF16X6 ? 3 : 0);
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(kpt[d])) return fail(ctx, PUFE_ERR_INVALID_ARG, "non-finite k-point");
     hipStream_t st = (hipStream_t)stream;
@@ -641,7 +643,7 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
     if (d_P) {
         CHECK_HIP(ctx, launch_gather_adjoint(pl.kp, pl.nel, ctx->d_elems.p, ctx->d_edof.p, ctx->d_pt_off.p,
                                              (const double *)d_P, kpt, ctx->d_Pt.p, st), "gather P");
-        CHECK_HIP(ctx, launch_backward(pl.kp, false, nit, ctx->d_bw_items.p, ctx->d_elems.p, ctx->d_groups.p,
+        CHECK_HIP(ctx, launch_backward(pl.kp, false, nl, nit, ctx->d_bw_items.p, ctx->d_elems.p, ctx->d_groups.p,
                                        ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_pt_off.p,
                                        ctx->d_Pt.p, d_dLdV, ctx->d_fP.p, mg, ctx->bw_lds, st), "adjoint (P)");
     } else if (d_dLdV) {
@@ -650,7 +652,7 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
     if (d_Q) {
         CHECK_HIP(ctx, launch_gather_adjoint(pl.kp, pl.nel, ctx->d_elems.p, ctx->d_edof.p, ctx->d_pt_off.p,
                                              (const double *)d_Q, kpt, ctx->d_Pt.p, st), "gather Q");
-        CHECK_HIP(ctx, launch_backward(pl.kp, true, nit, ctx->d_bw_items.p, ctx->d_elems.p, ctx->d_groups.p,
+        CHECK_HIP(ctx, launch_backward(pl.kp, true, nl, nit, ctx->d_bw_items.p, ctx->d_elems.p, ctx->d_groups.p,
                                        ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_pt_off.p,
                                        ctx->d_Pt.p, nullptr, ctx->d_fQ.p, mg, ctx->bw_lds, st), "adjoint (Q)");
     }

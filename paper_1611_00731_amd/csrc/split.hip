@@ -19,43 +19,15 @@
 #include <stdint.h>
 
 #include "kernels.hpp"
+#include "limbs.hpp"
 #include "stage.hpp"
 #include "tables.hpp"
 
 namespace pufe {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kSplitThreads = 256;
-
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-
-// Two FP32 values -> a packed pair of bf16 (low half: the first), rounded to
-// nearest even by the hardware conversion (v_cvt_pk_bf16_f32).
-__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
-    const f32x2 f = {a, b};
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
-}
-
-// Limbs of two values x0, x1 (adjacent points of one row and component) as
-// packed bf16 pairs: the first limb from the FP64 values, the others from the
-// residuals, which are exact in FP64 and carried on in FP32 (their FP32
-// rounding, below 2^-32 |x|, is far under the last limb).
-template <int NL>
-__device__ __forceinline__ void split_limbs2(double x0, double x1, uint32_t *h) {
-    h[0] = bf16_pair((float)x0, (float)x1);
-    float r0 = (float)(x0 - (double)__uint_as_float(h[0] << 16));
-    float r1 = (float)(x1 - (double)__uint_as_float(h[0] & 0xffff0000u));
-#pragma unroll
-    for (int j = 1; j < NL; ++j) {
-        h[j] = bf16_pair(r0, r1);
-        r0 -= __uint_as_float(h[j] << 16);
-        r1 -= __uint_as_float(h[j] & 0xffff0000u);
-    }
-}
 
 // LDS map (per work item):
 //   sLimb[j][row][5][Q]  bf16 limb j of the weighted operands sqrt(w/2) d_x phi,
@@ -252,15 +224,7 @@ __device__ __forceinline__ void contract_split_item(
                         A[j] = *(const bf16x8 *)(rowA + j * LS + offA);
                         B[j] = *(const bf16x8 *)(rowB + j * LS + offB);
                     }
-                    f32x4 h = {0.f, 0.f, 0.f, 0.f};
-                    if (NL == 3) {
-                        h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0], h, 0, 0, 0);
-                        h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2], h, 0, 0, 0);
-                        h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1], h, 0, 0, 0);
-                    }
-                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1], h, 0, 0, 0);
-                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0], h, 0, 0, 0);
-                    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0], h, 0, 0, 0);
+                    const f32x4 h = mfma_limbs<NL>(A, B, (f32x4){0.f, 0.f, 0.f, 0.f});
                     if (c < 4) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) accH[u][r] += (double)h[r];

@@ -2,7 +2,8 @@
 
 dL/dV is compared with the oracle point by point; dL/dR with the oracle on
 small cases and with central finite differences (h = 1e-4 bohr) of the GPU
-forward, rule and enriched sets frozen, at the 64-atom supercell size.
+forward, rule and enriched sets frozen, at the 64-atom supercell size; the
+split-precision forms likewise, to the bounds their limbs allow.
 """
 import numpy as np
 import pytest
@@ -157,6 +158,13 @@ def test_backward_lih_supercell_full_size():
         return float((Pb.conj() * torch.view_as_complex(H[0])).real.sum())
 
     g = dR.cpu().numpy()
+    # the split form at full size (bf16x6): dL/dV against the FP64 result,
+    # dL/dR against the same central differences
+    dVs, dRs = p.backward(Vd, (0.0, 0.0, 0.0), Pb, None, precision="bf16x6")
+    es = rel(dVs.cpu().numpy(), dVh)
+    say("bf16x6 dL/dV rel. error vs FP64", es)
+    assert es < SPLIT_TOL["bf16x6"]
+    gs = dRs.cpu().numpy()
     h = 1e-4
     for A, k in [(0, 0), (13, 1), (40, 2), (63, 0)]:
         Rp, Rm = R0.copy(), R0.copy()
@@ -164,5 +172,34 @@ def test_backward_lih_supercell_full_size():
         Rm[A, k] -= h
         fd = (loss(Rp) - loss(Rm)) / (2 * h)
         assert abs(fd - g[A, k]) < 1e-6 * np.abs(g).max(), (A, k, fd, g[A, k])
+        say("bf16x6 dL/dR vs FD", A, k, abs(fd - gs[A, k]) / np.abs(g).max())
+        assert abs(fd - gs[A, k]) < 1e-6 * np.abs(g).max() + SPLIT_TOL["bf16x6"] * np.abs(g).max()
     p.set_positions(R0)
+    p.close()
+
+
+# Split-precision adjoint tolerances (relative): U = Ps B is summed from the
+# kept bf16 limb products in FP32, which leaves about 2^-24 per product with
+# three limbs (the FP32 sums) and about 3 * 2^-18 with two (the dropped
+# limb products and residuals); the bounds allow ten times that for the sums.
+SPLIT_TOL = {"bf16x6": 1e-6, "bf16x3": 1e-4}
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+def test_backward_split_matches_oracle_small(prec):
+    """Split-precision adjoint (bf16 limbs of Ps and of the basis rows on the
+    BF16 MFMAs) against the FP64 oracle: dL/dV and dL/dR, P and Q passes."""
+    prob, o, V, Pd, Qd = small_case()
+    kap = (0.12, -0.24, 0.37)
+    say("backward split small vs oracle", prec)
+    dV_o, dR_o = o.backward_dense(V, kap, Pd, Qd)
+    p = P.Problem(prob).setup()
+    rows, cols = bsr_index(p.layout())
+    Pb = torch.from_numpy(Pd[rows, cols]).cuda()
+    Qb = torch.from_numpy(Qd[rows, cols]).cuda()
+    dV, dR = p.backward(torch.from_numpy(V).cuda(), kap, Pb, Qb, precision=prec)
+    ev = rel(dV.cpu().numpy(), dV_o)
+    er = np.abs(dR.cpu().numpy() - dR_o).max() / np.abs(dR_o).max()
+    say(prec, "dL/dV", ev, "dL/dR", er)
+    assert ev < SPLIT_TOL[prec] and er < SPLIT_TOL[prec]
     p.close()
