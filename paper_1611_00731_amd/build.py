@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpufe.so")
 SOURCES = ["capi.cpp", "plan.cpp", "kernels.hip", "backward.hip", "split.hip", "aq_error.hip"]
-HEADERS = ["tables.hpp", "plan.hpp", "kernels.hpp", "basis.hpp", "backward.hpp", "device_common.hpp", "enrich.hpp", "aq_error.hpp"]
+HEADERS = ["tables.hpp", "plan.hpp", "kernels.hpp", "basis.hpp", "backward.hpp", "device_common.hpp", "enrich.hpp",
+           "aq_error.hpp", "stage.hpp", "limbs.hpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
