@@ -855,9 +855,13 @@ struct pufe_batch {
     int device = 0;
     std::vector<ItemDev> items, items_split;
     std::vector<std::vector<int4>> lists;   // per colour: (problem, element, tile pair)
-    size_t lds_f64 = 0, lds_split[2] = {0, 0};
-    int max_l = 0, q = 16;
-    int grid_f64 = 0, grid_split[2] = {0, 0};
+    // FP64 items in up to two classes, each a persistent launch of its own:
+    // class 0 holds the problems whose stages fit two work groups per CU at
+    // 24 points, class 1 the rest (items [item_off[c], item_off[c + 1]))
+    size_t lds_f64[2] = {0, 0}, lds_split[2] = {0, 0};
+    int max_l = 0, q[2] = {24, 16};
+    int grid_f64[2] = {0, 0}, grid_split[2] = {0, 0};
+    int64_t item_off[3] = {0, 0, 0};
     DevBuf<CtxDev> d_ctxs;
     DevBuf<ItemDev> d_items, d_items_split;
     DevBuf<int4> d_lists;
@@ -909,15 +913,38 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     b->device = ctxs[0]->device;
     if (hipSetDevice(b->device) != hipSuccess) { delete b; return PUFE_ERR_HIP; }
-    int max_rows = 16, max_rows_split = 16, max_nfun = 1, max_img = 0, max_leaves = 1, max_leaves_split = 1,
-        max_n3 = 1;
+    int max_rows_split = 16, max_nfun = 1, max_img = 0, max_leaves_split = 1, max_n3 = 1;
     b->lists.assign(27, {});
-    for (int pass = 0; pass < 2; ++pass) {
+    // FP64 classes: problems in order of their own 24-point stage size join
+    // class 0 while the class's combined stage still fits two work groups
+    // per CU; the others form class 1
+    std::vector<int> cls(n, 1);
+    {
+        std::vector<std::pair<size_t, int>> by_lds;
+        for (int i = 0; i < n; ++i) {
+            const pufe_ctx *c = ctxs[i];
+            by_lds.push_back({contract_lds_bytes(24, c->max_rows, std::max(c->plan.max_nfun, 1), c->plan.max_img,
+                                                 c->max_item_leaves, c->plan.kp.n3), i});
+        }
+        std::stable_sort(by_lds.begin(), by_lds.end());
+        int r = 16, f = 1, im = 0, lv = 1, n3 = 1;
+        for (const auto &pr : by_lds) {
+            const pufe_ctx *c = ctxs[pr.second];
+            const int r2 = std::max(r, c->max_rows), f2 = std::max(f, c->plan.max_nfun), im2 = std::max(im, c->plan.max_img);
+            const int lv2 = std::max(lv, c->max_item_leaves), n32 = std::max(n3, c->plan.kp.n3);
+            if (persistent_blocks_per_cu(contract_lds_bytes(24, r2, f2, im2, lv2, n32)) < 2) continue;
+            r = r2, f = f2, im = im2, lv = lv2, n3 = n32;
+            cls[pr.second] = 0;
+        }
+    }
+    for (int pass = 0; pass < 3; ++pass) {
+        // pass 0, 1: FP64 items of class 0, 1; pass 2: split items
         std::vector<std::pair<double, size_t>> order;
         std::vector<ItemDev> all;
         for (int i = 0; i < n; ++i) {
             pufe_ctx *c = ctxs[i];
-            for (const ItemDev &it0 : pass == 0 ? c->items : c->items_split) {
+            if (pass < 2 && cls[i] != pass) continue;
+            for (const ItemDev &it0 : pass < 2 ? c->items : c->items_split) {
                 ItemDev it = it0;
                 it.ctx = i;
                 order.push_back({item_cost(it, c->plan.kp.n3), all.size()});
@@ -926,16 +953,22 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         }
         std::stable_sort(order.begin(), order.end(),
                          [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &c) { return a.first > c.first; });
-        std::vector<ItemDev> &dst = pass == 0 ? b->items : b->items_split;
+        std::vector<ItemDev> &dst = pass < 2 ? b->items : b->items_split;
         for (auto &o : order) dst.push_back(all[o.second]);
+        if (pass < 2) b->item_off[pass + 1] = (int64_t)b->items.size();
     }
+    int cr[2] = {16, 16}, cf[2] = {1, 1}, ci[2] = {0, 0}, cl[2] = {1, 1}, cn3[2] = {1, 1};
     for (int i = 0; i < n; ++i) {
         pufe_ctx *c = ctxs[i];
-        max_rows = std::max(max_rows, c->max_rows);
+        const int k = cls[i];
+        cr[k] = std::max(cr[k], c->max_rows);
+        cf[k] = std::max(cf[k], c->plan.max_nfun);
+        ci[k] = std::max(ci[k], c->plan.max_img);
+        cl[k] = std::max(cl[k], c->max_item_leaves);
+        cn3[k] = std::max(cn3[k], c->plan.kp.n3);
         max_rows_split = std::max(max_rows_split, c->max_rows_split);
         max_nfun = std::max(max_nfun, c->plan.max_nfun);
         max_img = std::max(max_img, c->plan.max_img);
-        max_leaves = std::max(max_leaves, c->max_item_leaves);
         max_leaves_split = std::max(max_leaves_split, c->max_item_leaves_split);
         max_n3 = std::max(max_n3, c->plan.kp.n3);
         b->max_l = std::max(b->max_l, c->plan.max_l);
@@ -954,14 +987,17 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || ncu < 1) ncu = 256;
-    // 24-point stages when two work groups still share a CU, else 16
-    b->q = 24;
-    b->lds_f64 = contract_lds_bytes(b->q, max_rows, max_nfun, max_img, max_leaves, max_n3);
-    if (persistent_blocks_per_cu(b->lds_f64) < 2) {
-        b->q = 16;
-        b->lds_f64 = contract_lds_bytes(b->q, max_rows, max_nfun, max_img, max_leaves, max_n3);
+    // class 0: 24-point stages, two work groups per CU; class 1: 24-point
+    // stages when two work groups still share a CU, else 16
+    for (int k = 0; k < 2; ++k) {
+        b->q[k] = 24;
+        b->lds_f64[k] = contract_lds_bytes(24, cr[k], cf[k], ci[k], cl[k], cn3[k]);
+        if (k == 1 && persistent_blocks_per_cu(b->lds_f64[k]) < 2) {
+            b->q[k] = 16;
+            b->lds_f64[k] = contract_lds_bytes(16, cr[k], cf[k], ci[k], cl[k], cn3[k]);
+        }
+        b->grid_f64[k] = ncu * persistent_blocks_per_cu(b->lds_f64[k]);
     }
-    b->grid_f64 = ncu * persistent_blocks_per_cu(b->lds_f64);
     for (int k = 0; k < 2; ++k) {
         b->lds_split[k] = split_lds_bytes(k + 2, max_rows_split, max_nfun, max_img, max_leaves_split, max_n3);
         b->grid_split[k] = ncu * persistent_blocks_per_cu(b->lds_split[k]);
@@ -1046,12 +1082,19 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
             for (int d = 0; d < 3; ++d) kps.kap[k][d] = kpts[3 * k + d];
         CHECK_HIP_B(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
         hipError_t e = hipSuccess;
-        if (precision == PUFE_PREC_FP64 && b->lds_f64 > kMaxDynLds)
-            e = hipErrorInvalidValue;
-        else if (precision == PUFE_PREC_FP64)
-            e = launch_contract_persistent(b->q, b->max_l, b->d_ctxs.p, b->d_items.p, (int)b->items.size(), b->d_counter.p,
-                                           b->grid_f64, b->lds_f64, b->cap);
-        else {
+        if (precision == PUFE_PREC_FP64) {
+            // one persistent launch per class (the queue counter is reset by each)
+            for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+                const int cnt = (int)(b->item_off[k + 1] - b->item_off[k]);
+                if (cnt == 0) continue;
+                if (b->lds_f64[k] > kMaxDynLds) {
+                    e = hipErrorInvalidValue;
+                    break;
+                }
+                e = launch_contract_persistent(b->q[k], b->max_l, b->d_ctxs.p, b->d_items.p + b->item_off[k], cnt,
+                                               b->d_counter.p, b->grid_f64[k], b->lds_f64[k], b->cap);
+            }
+        } else {
             const int k = precision == PUFE_PREC_BF16X3 ? 0 : 1;
             if (b->lds_split[k] > kMaxDynLds) e = hipErrorInvalidValue;
             else
