@@ -365,8 +365,11 @@ def main():
 
     import paper_1611_00731_amd as P
     import workloads as W
+    from paper_1611_00731_amd import build as libbuild
     from workloads.potential import potential_at
 
+    if libbuild.stale():
+        log("warning: libpufe.so is older than its sources; rebuild before trusting these numbers")
     dev = torch.device("cuda", 0)
     prob = W.lih_cell()
     log("setup", prob["name"])
