@@ -86,6 +86,8 @@ PROBLEMS = {
     "ceal": lambda: W.small("ceal", mesh=(3, 3, 3), fe_order=2, a=5.0, rc=3.0, re=2.1),
     "skew": lambda: W.small("lih", mesh=(3, 2, 3), fe_order=2, levels=0,
                             lattice=[[5.0, 0.3, -0.2], [0.1, 4.8, 0.25], [0.2, -0.3, 5.3]]),
+    "random-1": lambda: W.random_small(1),
+    "random-7": lambda: W.random_small(7),
 }
 
 

@@ -311,3 +311,27 @@ def test_empty_lattice_closed_form(p, mesh, kappa):
     allev = np.sort((lam[0][:, None, None] + lam[1][None, :, None] + lam[2][None, None, :]).ravel() / 2)
     assert np.abs(ev - allev[:12]).max() < 1e-11 * max(1, allev[11])
     pp.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_problems(seed):
+    """Seeded random small problems (kind, mesh, element order, rule, cell
+    shear, radii, two random k-points): the FP64 assembly against the oracle's
+    dense assembly, the rule bit for bit, and the bf16x6 form to its bound."""
+    prob = W.random_small(seed)
+    say("random", seed, prob["mesh"], "p", prob["fe_order"], "levels", prob["quad"]["levels"],
+        "n", prob["quad"]["n"], "atoms", len(prob["atoms"]))
+    o, xyz, w, off, V = oracle_inputs(prob)
+    p = P.Problem(prob).setup()
+    check_rule(p, o, xyz, w)
+    Vd = torch.from_numpy(V).cuda()
+    kpts = prob["kpts"]
+    H, S = p.assemble(Vd, kpts)
+    Hs, Ss = p.assemble(Vd, kpts, precision="bf16x6")
+    for k, kap in enumerate(kpts):
+        Ho, So = o.assemble_dense(V, kap)
+        assert rel(p.to_dense(H[k]).cpu().numpy(), Ho) < TOL, (seed, kap)
+        assert rel(p.to_dense(S[k]).cpu().numpy(), So) < TOL, (seed, kap)
+        assert rel(p.to_dense(Hs[k]).cpu().numpy(), Ho) < 1e-7, (seed, kap)
+        assert rel(p.to_dense(Ss[k]).cpu().numpy(), So) < 1e-7, (seed, kap)
+    p.close()

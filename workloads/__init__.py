@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "single_atom_cube", "lih_cell", "lih_lattice_sweep", "ceal_cell", "lih_supercell", "small", "lih_table1",
     "mp2", "ceal_kpoints", "jitter", "adjoint_factor", "with_lattice_constant",
-    "orthorhombic",
+    "orthorhombic", "random_small",
 ]
 
 MP2 = [[sx * 0.25, sy * 0.25, sz * 0.25]
@@ -249,6 +249,33 @@ def small(kind: str = "lih", mesh=(2, 3, 2), fe_order: int = 2, levels: int = 1,
          "tol": 1e-6},
         list(kpts), 4, f"small-{kind}")
 
+
+
+def random_small(seed: int):
+    """A seeded random small problem for parity sweeps (the oracle finishes it
+    in about a second): kind, mesh, element order, rule depth and Gauss order,
+    cell size and shape (a small random shear of a cube; sheared cells take
+    the unrefined rule), enrichment radii and two random k-points."""
+    rng = np.random.default_rng(1000 + seed)
+    kind = ["lih", "one", "ceal"][int(rng.integers(0, 3))]
+    mesh = [int(m) for m in rng.integers(2, 4, size=3)]
+    if kind == "ceal":
+        mesh[2] = 2
+    fe_order = int(rng.integers(1, 3))
+    n = int(rng.integers(2, 5))
+    a = float(rng.uniform(4.4, 5.2))
+    skew = bool(rng.integers(0, 2))
+    lattice = a * (np.eye(3) + (rng.uniform(-0.06, 0.06, size=(3, 3)) if skew else 0.0))
+    levels = 0 if skew else int(rng.integers(0, 2))
+    if kind == "ceal":
+        rc, re = float(rng.uniform(2.6, 3.0)), float(rng.uniform(2.0, 2.4))
+    else:
+        rc, re = float(rng.uniform(2.0, 2.4)), float(rng.uniform(1.4, 1.8))
+    kpts = [list(map(float, rng.uniform(-0.5, 0.5, size=3))) for _ in range(2)]
+    prob = small(kind, mesh=tuple(mesh), fe_order=fe_order, levels=levels, n=n, a=a, kpts=kpts,
+                 re=re, rc=rc, lattice=lattice.tolist())
+    prob["name"] = f"random-{seed}"
+    return prob
 
 def lih_table1(re: float, cells: int = 1, mesh: int = 3, a: float = 4.63):
     """The paper's LiH cubic cell for its sparsity table: Li at 0 (two s-type
