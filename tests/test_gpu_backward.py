@@ -203,3 +203,31 @@ def test_backward_split_matches_oracle_small(prec):
     say(prec, "dL/dV", ev, "dL/dR", er)
     assert ev < SPLIT_TOL[prec] and er < SPLIT_TOL[prec]
     p.close()
+
+
+@pytest.mark.parametrize("seed", [0, 3, 4, 7])
+def test_backward_random_small_problems(seed):
+    """The adjoint on seeded random small problems (elements of at most 80
+    functions), FP64 and bf16x6, against the oracle at a random k-point."""
+    prob = W.random_small(seed)
+    o = oracle.Oracle(prob)
+    xyz, _, _ = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob).cpu().numpy()
+    Cp = W.adjoint_factor(o.n_dof, rank=5, seed=seed)
+    Cq = W.adjoint_factor(o.n_dof, rank=2, seed=seed + 100)
+    Pd, Qd = Cp @ Cp.conj().T, Cq @ Cq.conj().T
+    kap = prob["kpts"][1]
+    say("backward random", seed, prob["mesh"], "p", prob["fe_order"], "k", kap)
+    dV_o, dR_o = o.backward_dense(V, kap, Pd, Qd)
+    p = P.Problem(prob).setup()
+    rows, cols = bsr_index(p.layout())
+    Pb = torch.from_numpy(Pd[rows, cols]).cuda()
+    Qb = torch.from_numpy(Qd[rows, cols]).cuda()
+    Vd = torch.from_numpy(V).cuda()
+    for prec, tol in (("fp64", 1e-11), ("bf16x6", SPLIT_TOL["bf16x6"])):
+        dV, dR = p.backward(Vd, kap, Pb, Qb, precision=prec)
+        ev = rel(dV.cpu().numpy(), dV_o)
+        er = np.abs(dR.cpu().numpy() - dR_o).max() / np.abs(dR_o).max()
+        say(prec, "dL/dV", ev, "dL/dR", er)
+        assert ev < tol and er < tol, (seed, prec)
+    p.close()
