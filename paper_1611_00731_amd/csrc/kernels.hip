@@ -155,7 +155,7 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 //   sB[row][4][Q]   weighted operands of the item's local rows at the stage
 //                   points: sqrt(w/2) d_x phi, sqrt(w/2) d_y phi,
 //                   sqrt(w/2) d_z phi, sqrt(w) phi
-//   sV[Q]           V at the stage points
+//   sV[2][Q]        V at the stage points, two buffers for alternate stages
 //   sPsi[f][4][Q]   (value, gradient) of the element's enrichment functions
 //   sGeo[GEO][Q]    per-point geometry, one field after the other
 //   sImg, sG, sEd   image centres, groups, enriched-function table
@@ -166,7 +166,7 @@ struct ContractLds {
     static constexpr int RS = 4 * Q + 2;  // row stride (doubles): 16-byte rows, offset banks
     static constexpr int GEO = 40;        // doubles of geometry per point
     static __host__ __device__ size_t bytes(int rows, int nfun, int nimg, int nleaf, int n3) {
-        return sizeof(double) * ((size_t)rows * RS + (size_t)Q + (size_t)nfun * Q * 4 + (size_t)Q * GEO +
+        return sizeof(double) * ((size_t)rows * RS + 2 * (size_t)Q + (size_t)nfun * Q * 4 + (size_t)Q * GEO +
                                  (size_t)nimg * 3 + 2 * kMaxGauss) +
                sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc +
                sizeof(uint32_t) * ((size_t)nleaf + n3 + rows + 16) + 64;
@@ -280,8 +280,8 @@ __device__ __forceinline__ void contract_f64_item(
     const int nimg = ngrp > 0 ? gGroups[el.grp_off + ngrp - 1].img_off + gGroups[el.grp_off + ngrp - 1].nimg - img0 : 0;
     const uint32_t n3 = (uint32_t)kp.n3, n = (uint32_t)kp.n;
     double *sB = smem;                                        // [nrow][RS]
-    double *sV = sB + (size_t)nrow * RS;                      // [Q]
-    double *sPsi = sV + Q;                                    // [nfun][Q][4]
+    double *sV = sB + (size_t)nrow * RS;                      // [2][Q], alternate stages
+    double *sPsi = sV + 2 * Q;                                // [nfun][Q][4]
     double *sGeo = sPsi + (size_t)nfun * Q * 4;               // [Q][GEO]
     double *sImg = sGeo + (size_t)Q * GEO;
     double *sGx = sImg + 3 * (size_t)nimg, *sGs = sGx + kMaxGauss;   // square roots of the 1D Gauss weights
@@ -415,27 +415,32 @@ __device__ __forceinline__ void contract_f64_item(
     // the last Q threads build the geometry; V is read one stage ahead
     const int gq = tid - (NT - Q);
     double v = (gq >= 0 && (uint32_t)gq < nli) ? gV[q_begin + gq] : 0.0;
-    __syncthreads();
-
-    for (uint32_t lb = 0; lb < nli; lb += Q) {
-        // ---- phase 1: enrichment functions (eq. Psi, f(R) = 1) and geometry
+    // phase 1 of the stage starting at lbx: enrichment functions (eq. Psi,
+    // f(R) = 1) and geometry, and V of that stage into the buffer vb
+    auto phase1 = [&](uint32_t lbx, double *vb) {
         if (gq >= 0) {
-            const double vn = (lb + Q + gq < nli) ? gV[q_begin + lb + Q + gq] : 0.0;
+            const double vn = (lbx + Q + gq < nli) ? gV[q_begin + lbx + Q + gq] : 0.0;
             double xi[3], sw;
-            item_point(kp, sLeaf, sPt, sGx, sGs, lb + gq, nli, n3, xi, &sw);
+            item_point(kp, sLeaf, sPt, sGx, sGs, lbx + gq, nli, n3, xi, &sw);
             point_geometry<Q>(kp, org, xi, sw, sGeo + gq);
-            sV[gq] = v;
+            vb[gq] = v;
             v = vn;
         }
         for (int idx = tid; idx < ngrp * Q; idx += NT) {
             const int g = idx / Q, q = idx - g * Q;
             const GroupDev &G = sG[g];
             double xi[3], sw, x[3];
-            item_point(kp, sLeaf, sPt, sGx, sGs, lb + q, nli, n3, xi, &sw);
+            item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
             group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
-        __syncthreads();
+    };
+    __syncthreads();
+    if (nli > 0) phase1(0, sV);
+    __syncthreads();
+
+    for (uint32_t lb = 0, st = 0; lb < nli; lb += Q, st ^= 1) {
+        double *sVc = sV + st * Q;
         // ---- phase 2: weighted local basis rows (eq. pufebasis) of the
         // item's functions (the padding rows past them stay zero)
         if (whole) {
@@ -483,18 +488,22 @@ __device__ __forceinline__ void contract_f64_item(
             o[3 * Q] = g[G_SW * Q] * val;
         }
         __syncthreads();
-        // ---- phase 3: the MFMAs
+        // ---- phase 3: the MFMAs of this stage (V from its buffer), then
+        // phase 1 of the next stage, in one barrier interval: phase 3 reads
+        // only the rows and V, phase 1 writes the enrichment table, the
+        // geometry and the other V buffer
         switch (nu) {
-            case 4: mfma_stage<Q, 4>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
-            case 3: mfma_stage<Q, 3>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
-            case 2: mfma_stage<Q, 2>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
-            case 1: mfma_stage<Q, 1>(sB, sV, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 4: mfma_stage<Q, 4>(sB, sVc, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 3: mfma_stage<Q, 3>(sB, sVc, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 2: mfma_stage<Q, 2>(sB, sVc, pr_row, pr_col, r16, k4, accH, accS); break;
+            case 1: mfma_stage<Q, 1>(sB, sVc, pr_row, pr_col, r16, k4, accH, accS); break;
             default: break;
         }
         if (tg == 1)
-            mfma_tail_dispatch<Q, 1>(mt, sB, sV, tl_row, 16 * (T - 1), r16, k4, lane, tH, tS);
+            mfma_tail_dispatch<Q, 1>(mt, sB, sVc, tl_row, 16 * (T - 1), r16, k4, lane, tH, tS);
         else if (tg == 2)
-            mfma_tail_dispatch<Q, 2>(mt, sB, sV, tl_row, 16 * (T - 1), r16, k4, lane, tH, tS);
+            mfma_tail_dispatch<Q, 2>(mt, sB, sVc, tl_row, 16 * (T - 1), r16, k4, lane, tH, tS);
+        if (lb + Q < nli) phase1(lb + Q, sV + (st ^ 1) * Q);
         __syncthreads();
     }
     // ---- partial tiles, row-major 16x16.  FP64 16x16x4 accumulator layout:
