@@ -155,12 +155,13 @@ __device__ __forceinline__ void contract_split_item(
     double v = (gq >= 0 && (uint32_t)gq < nli) ? gV[q_begin + gq] : 0.0;
     __syncthreads();
 
-    for (uint32_t lb = 0; lb < nli; lb += Q) {
-        // ---- phase 1: enrichment functions (eq. Psi, f(R) = 1) and geometry
+    // phase 1 of the stage starting at lbx: enrichment functions (eq. Psi,
+    // f(R) = 1), geometry and V
+    auto phase1 = [&](uint32_t lbx) {
         if (gq >= 0) {
-            const double vn = (lb + Q + gq < nli) ? gV[q_begin + lb + Q + gq] : 0.0;
+            const double vn = (lbx + Q + gq < nli) ? gV[q_begin + lbx + Q + gq] : 0.0;
             double xi[3], sw;
-            item_point(kp, sLeaf, sPt, sGx, sGs, lb + gq, nli, n3, xi, &sw);
+            item_point(kp, sLeaf, sPt, sGx, sGs, lbx + gq, nli, n3, xi, &sw);
             point_geometry<Q>(kp, org, xi, sw, sGeo + gq);
             sV[gq] = v;
             v = vn;
@@ -169,11 +170,14 @@ __device__ __forceinline__ void contract_split_item(
             const int g = idx / Q, q = idx - g * Q;
             const GroupDev &G = sG[g];
             double xi[3], sw, x[3];
-            item_point(kp, sLeaf, sPt, sGx, sGs, lb + q, nli, n3, xi, &sw);
+            item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
             group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
-        __syncthreads();
+    };
+    if (nli > 0) phase1(0);
+    __syncthreads();
+    for (uint32_t lb = 0; lb < nli; lb += Q) {
         // ---- phase 2: weighted rows at two adjacent points per thread, split
         // into limbs and stored as bf16 pairs
         for (int idx = tid; idx < nrow * (Q / 2); idx += NT) {
@@ -203,7 +207,8 @@ __device__ __forceinline__ void contract_split_item(
             }
         }
         __syncthreads();
-        // ---- phase 3: MFMAs over limb products; lane = i + 16 grp holds the 8
+        // ---- phase 3 of this stage and phase 1 of the next share one barrier
+        // interval (phase 3 reads only the limbs); MFMAs over limb products; lane = i + 16 grp holds the 8
         // consecutive points 8 grp .. 8 grp + 7 of one component
         {
             const int r16 = lane & 15, grp = lane >> 4;
@@ -235,6 +240,7 @@ __device__ __forceinline__ void contract_split_item(
                 }
             }
         }
+        if (lb + Q < nli) phase1(lb + Q);
         __syncthreads();
     }
     // ---- partial tiles, row-major 16x16.  bf16 16x16x32 accumulator layout:
