@@ -527,8 +527,6 @@ int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k,
     TimedRegion tr(ctx, 1, st);
     const int64_t per = out_dtype == PUFE_OUT_F64_GAMMA ? pl.nnz : 2 * pl.nnz;
     const bool f32 = out_dtype == PUFE_OUT_C64;
-    CHECK_HIP(ctx, launch_fill_zero(d_H, per * n_k, f32, st), "zero H");
-    if (d_S) CHECK_HIP(ctx, launch_fill_zero(d_S, per * n_k, f32, st), "zero S");
     const size_t esz = f32 ? sizeof(float) : sizeof(double);
     for (int k0 = 0; k0 < n_k; k0 += kMaxKPerLaunch) {
         KPoints kps;
@@ -538,7 +536,12 @@ int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k,
             for (int d = 0; d < 3; ++d) kps.kap[k][d] = kpts[3 * (k0 + k) + d];
         char *H = (char *)d_H + (size_t)k0 * per * esz;
         char *S = d_S ? (char *)d_S + (size_t)k0 * per * esz : nullptr;
-        CHECK_HIP(ctx, launch_phase_table(kps, ctx->d_ztab.p, st), "phase table");
+        // the first pass zeroes every output (all k-points) with its phase table
+        if (k0 == 0)
+            CHECK_HIP(ctx, launch_prepare_outputs(d_H, d_S, (int64_t)(per * n_k * esz), kps, ctx->d_ztab.p, st),
+                      "zero outputs and phase table");
+        else
+            CHECK_HIP(ctx, launch_phase_table(kps, ctx->d_ztab.p, st), "phase table");
         for (size_t col = 0; col + 1 < pl.scat_off.size(); ++col) {
             const int n = (int)(pl.scat_off[col + 1] - pl.scat_off[col]);
             CHECK_HIP(ctx, launch_scatter(pl.kp, ctx->d_elems.p, ctx->d_scat.p + pl.scat_off[col], n, ctx->d_edof.p,

@@ -636,14 +636,32 @@ __global__ void fill_zero_f32_kernel(float *__restrict__ p, int64_t n) {
 // Phase table z[k][t] = exp(2 pi i kappa_k . dn), dn = (t % 3, t / 3 % 3, t / 9) - 1:
 // the factor conj(p_a) p_b of a local pair whose corners differ by the
 // lattice shift dn (the Bloch phase factors at the cell boundary).
-__global__ void phase_table_kernel(const KPoints kps, double2 *__restrict__ z) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= kps.nk * 27) return;
+__device__ __forceinline__ void phase_entry(const KPoints &kps, int idx, double2 *__restrict__ z) {
     const int k = idx / 27, t = idx % 27;
     const int dn[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
     double sn, cs;
     sincos(2.0 * M_PI * (kps.kap[k][0] * dn[0] + kps.kap[k][1] * dn[1] + kps.kap[k][2] * dn[2]), &sn, &cs);
     z[idx] = make_double2(cs, sn);
+}
+
+__global__ void phase_table_kernel(const KPoints kps, double2 *__restrict__ z) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kps.nk * 27) return;
+    phase_entry(kps, idx, z);
+}
+
+// Zero fill of the H and S outputs of an assembly (nw 8-byte words each; S
+// may be null; zero bits serve every output type) and, in the first work
+// group, the phase table of its k-points: one launch ahead of the scatter.
+__global__ void prepare_outputs_kernel(double *__restrict__ H, double *__restrict__ S, int64_t nw, const KPoints kps,
+                                       double2 *__restrict__ z) {
+    if (blockIdx.x == 0)
+        for (int idx = threadIdx.x; idx < kps.nk * 27; idx += blockDim.x) phase_entry(kps, idx, z);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) {
+        H[i] = 0.0;
+        if (S) S[i] = 0.0;
+    }
 }
 
 // One upper tile pair (I, J) of one element: each thread owns one entry
@@ -940,6 +958,17 @@ hipError_t launch_scatter_batch(const CtxDev *ctxs, const int4 *list, int n, con
                                 int out_dtype, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(scatter_batch_kernel, dim3(n), dim3(256), 0, st, ctxs, list, z, nk, out_dtype);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_outputs(void *H, void *S, int64_t bytes, const KPoints &kps, double2 *z, hipStream_t st) {
+    if (bytes % 8 != 0) return hipErrorInvalidValue;
+    const int64_t nw = bytes / 8;
+    int64_t blocks = (nw + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(prepare_outputs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (double *)H, (double *)S, nw,
+                       kps, z);
     return hipGetLastError();
 }
 

@@ -48,6 +48,8 @@ hipError_t launch_phase_table(const KPoints &kps, double2 *z, hipStream_t st);
 hipError_t launch_scatter_batch(const CtxDev *ctxs, const int4 *list, int n, const double2 *z, int nk,
                                 int out_dtype, hipStream_t st);
 hipError_t launch_fill_zero(void *p, int64_t n, bool f32, hipStream_t st);
+// zero H and S (bytes each, a multiple of 8; S may be null) and the phase table of kps, one launch
+hipError_t launch_prepare_outputs(void *H, void *S, int64_t bytes, const KPoints &kps, double2 *z, hipStream_t st);
 hipError_t launch_scatter(const KParams &kp, const ElemDev *elems, const int2 *list, int n, const int32_t *edof,
                           const double *partial, const double2 *z, int nk, int out_dtype, void *H, void *S,
                           int64_t nnz, hipStream_t st);
