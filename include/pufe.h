@@ -218,10 +218,11 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path);
 /* Batched assembly over several problems (for instance one per lattice
  * constant of an equation-of-state sweep), all set up on the same device.
  * pufe_batch_assemble runs, for every problem, the assembly of pufe_assemble
- * at the same n_k k-points: one persistent contraction launch whose work
- * groups pull the work items of all problems from one queue (largest first),
- * then one atomic-free scatter launch per element colour covering all
- * problems.  The sequence is captured once into a HIP graph and replayed;
+ * at the same n_k k-points: persistent contraction launches whose work
+ * groups pull the work items of all problems from one queue (largest first;
+ * in FP64 up to two launches, the problems whose stage fits two work groups
+ * per CU with 24-point stages in one and the rest in the other), then one
+ * atomic-free scatter launch per element colour covering all problems.  The sequence is captured once into a HIP graph and replayed;
  * a call with different pointers, k-points, precision or dtype recaptures.
  * d_V, d_H, d_S are host arrays of n device pointers (d_S may be NULL).  The
  * contexts must outlive the batch and must not be set up again meanwhile. */
