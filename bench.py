@@ -1,19 +1,25 @@
 """Benchmark of the PUFE H/S assembly on one MI355X.
 
-Workload: the LiH-like rock-salt cell (a = 7.6 bohr, 4 Li + 4 H jittered,
-8^3 triquadratic hexes, 6^3 Gauss points + 2 geometric octree levels within
-1 bohr of a nucleus, 512 elements, 1.52 M quadrature points, N = 4888),
-Gamma point.  One step = one full assembly of H and S from V at the
-quadrature points: the fused basis-evaluation + MFMA element contraction and
-the coloured Bloch scatter into block-sparse complex128 H and S.  Inputs are
-resident in HBM before timing starts; the rule (built once per geometry) is
-set up outside the timed region.
+Headline workload: the CeAl-like CsCl cell (a = 5.8 bohr, Ce at the origin,
+Al at the body centre, 12^3 triquadratic hexes, 8^3 Gauss points + 3
+geometric octree levels within 1 bohr of a nucleus, 1728 elements, 27.3 M
+quadrature points, 41 enrichment functions per Ce-Al pair, n_loc up to 283,
+N = 37,891) at the 4 time-reversal-reduced 2x2x2 Monkhorst-Pack k-points,
+complex128 H and S, FP64, autotuned.  It is the largest configuration that
+fits one GPU.  One step = one full assembly of H and S from V at the
+quadrature points: the fused basis-evaluation + MFMA element contraction, the
+K-chunk sum and the coloured Bloch scatter into block-sparse H and S for the
+4 k-points.  Inputs are resident in HBM before timing starts; the rule (built
+once per geometry) is set up outside the timed region.
 
-Prints one JSON line (rank 0): elements/s, ms/step, the contraction kernel's
-MFMA roofline fraction (algorithmic flops per launch over its average launch
-time measured with HIP events on the launch stream), the eigenvalue error of
-the assembled matrices against the stored FP64 oracle eigenvalues, and the
-CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line (rank 0): elements/s (elements x k-points per second),
+ms/step, the contraction kernel's MFMA roofline fraction (algorithmic flops
+per launch over its average launch time measured with HIP events on the
+launch stream), the split-BF16 forms on the same inputs, and the CPU oracle
+timed on a bounded, stratified element sample of the same workload.  Further
+legs (extra): the LiH-like cell with the eigenvalue error of the assembled
+matrices against the stored FP64 oracle eigenvalues, the lattice-constant
+sweep batch and the adjoint on the 64-atom supercell.
 
 Environment: PUFE_TUNE_CACHE, an optional file where the autotuner keeps its
 choice per problem shape and device (absent: the tuner runs every time).
@@ -36,11 +42,12 @@ PEAK = {"fp64": 78.6, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}   # TFLOP/s, d
 HBM_PEAK_GBS = 8000.0
 
 
-# HBM traffic of the contraction kernel from two rocprofv3 --pmc passes
-# (FETCH_SIZE, WRITE_SIZE), scaled by what the same counters read for a plain
-# device copy of known size.  It is reported only while the sources it was
-# measured on are unchanged (their SHA-256 is recorded next to the figure).
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_f64_lih_cell_hbm_traffic.md")
+# Figures of rocprofv3 counter passes over the contraction kernel (HBM bytes
+# from FETCH_SIZE / WRITE_SIZE scaled by a plain device copy; MFMA busy cycles
+# and executed MFMA flops), per workload.  Each is reported only while the
+# kernel sources it was measured on are unchanged (their SHA-256 is recorded
+# next to the figure).
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["kernels.hip", "stage.hpp", "tables.hpp", "enrich.hpp", "basis.hpp", "device_common.hpp",
                   "capi.cpp", "plan.cpp"]
 
@@ -53,16 +60,21 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """Bytes per launch recorded for the current kernel sources, else None."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    txt = open(TRAFFIC_FILE).read()
+def recorded(fname, *keys):
+    """Values of `keys` recorded in profiles/<fname> for the current kernel
+    sources (None for each when absent or measured on other sources)."""
+    path = os.path.join(PROFILES, fname)
+    if not os.path.exists(path):
+        return [None] * len(keys)
+    txt = open(path).read()
     m_h = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", txt)
-    m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not (m_h and m_t) or m_h.group(1) != kernel_sources_digest():
-        return None
-    return float(m_t.group(1))
+    if not m_h or m_h.group(1) != kernel_sources_digest():
+        return [None] * len(keys)
+    out = []
+    for k in keys:
+        m = re.search(k + r":\s*([0-9.eE+-]+)", txt)
+        out.append(float(m.group(1)) if m else None)
+    return out
 
 
 # Lowest eigenvalues of the LiH-like cell from the FP64 CPU oracle (dense
@@ -87,24 +99,6 @@ def eig_error(P, p, H, S, ev_ref):
     except RuntimeError as e:
         return None, str(e).splitlines()[0][:120]
     return float(np.abs(ev - ev_ref).max()), None
-
-
-MFMA_FILE = os.path.join(ROOT, "profiles", "contract_f64_lih_cell_mfma_counters.md")
-
-
-def recorded_mfma():
-    """(MFMA busy fraction, executed MFMA flop per launch) of the FP64
-    contraction from the rocprofv3 counter pass recorded for the current
-    kernel sources, else (None, None)."""
-    if not os.path.exists(MFMA_FILE):
-        return None, None
-    txt = open(MFMA_FILE).read()
-    m_h = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", txt)
-    m_b = re.search(r"mfma_busy_frac:\s*([0-9.eE+-]+)", txt)
-    m_x = re.search(r"mfma_executed_flops_per_launch:\s*([0-9.eE+-]+)", txt)
-    if not (m_h and m_b and m_x) or m_h.group(1) != kernel_sources_digest():
-        return None, None
-    return float(m_b.group(1)), float(m_x.group(1))
 
 
 def copy_probe(mib=1024, reps=3):
@@ -145,27 +139,110 @@ def element_work(prob, sizes, layout, leaf_off, n3):
     return nloc, nq, flops
 
 
-def cpu_baseline(prob, budget_s=20.0):
-    """The oracle's element matrices on a strided sample of the elements, with
-    V from the input generator at the oracle's own quadrature points."""
+def time_assembly(P, p, V, kpts, precision, H, S, steps, warmup):
+    """(ms per step without per-kernel events, [contraction, scatter, chunk
+    sum] ms per launch from a second, instrumented run of the same steps)."""
+    import torch
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        P.pufe_assemble(p.ctx, V, kpts, precision, "c128", H, S)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(st)
+    for _ in range(steps):
+        P.pufe_assemble(p.ctx, V, kpts, precision, "c128", H, S)
+    t1.record(st)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    # per-kernel durations from HIP events recorded by the library around each
+    # of its kernels on the launch stream (the event records between the
+    # kernels would lower the step throughput, hence a second run)
+    P.pufe_enable_timing(p.ctx, True)
+    P.pufe_kernel_times(p.ctx, reset=True)
+    t0.record(st)
+    for _ in range(steps):
+        P.pufe_assemble(p.ctx, V, kpts, precision, "c128", H, S)
+    t1.record(st)
+    torch.cuda.synchronize()
+    ms_instr = t0.elapsed_time(t1) / steps
+    kms, kc = P.pufe_kernel_times(p.ctx, reset=True)
+    P.pufe_enable_timing(p.ctx, False)
+    per = [kms[i] / max(kc[i], 1) for i in range(4)]
+    return ms, ms_instr, {"contract_ms": per[0], "scatter_ms_per_assembly": kms[1] / steps,
+                          "chunk_reduce_ms": per[3]}
+
+
+def cpu_baseline(prob, n_k, max_threads=16):
+    """The oracle's element matrices timed on a stratified sample of the
+    workload's elements, extrapolated to the whole cell by the oracle's cost
+    per point and local-function pair of each n_loc class; single thread and
+    a thread pool over elements (the unchanged single-threaded oracle called
+    through ctypes, which releases the GIL)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import torch
     import oracle
     from workloads.potential import potential_at
     o = oracle.Oracle(prob)
     xyz, _, qp_off = o.quadrature()
-    V = potential_at(torch.from_numpy(xyz).cuda(), prob).cpu().numpy()
-    sample = list(range(0, o.n_elem, 8))
-    t0 = time.perf_counter()
-    done = 0
+    _, _, loff = o.leaves()
+    nleaf = np.diff(loff)
+    nq = np.diff(qp_off)
+    nloc = np.array([o.element_dofs(e)[0].size for e in range(o.n_elem)])
+    work = nq.astype(float) * nloc.astype(float) ** 2
+    # strata: one unrefined element of every n_loc class, and the cheapest
+    # refined element of a class when it runs in a few seconds
+    sample = []
+    for c in np.unique(nloc):
+        m = np.nonzero((nleaf == 1) & (nloc == c))[0]
+        if m.size:
+            sample.append(int(m[0]))
+    rate_guess = 8e-9
+    for c in np.unique(nloc[nleaf > 1]):
+        m = np.nonzero((nleaf > 1) & (nloc == c))[0]
+        e = int(m[np.argmin(work[m])])
+        if work[e] * rate_guess < 6.0:
+            sample.append(e)
+    Vs = {e: potential_at(torch.from_numpy(np.ascontiguousarray(xyz[qp_off[e]:qp_off[e + 1]])), prob).numpy()
+          for e in sample}
+    del xyz
+    t_el = {}
     for e in sample:
-        o.element_matrices(e, V[qp_off[e]:qp_off[e + 1]])
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"element matrices (H_e, S_e) of {done} elements, every 8th element in id order "
-                      f"(refined and plain in workload proportion), single thread, {dt:.1f} s"}
+        t0 = time.perf_counter()
+        o.element_matrices(e, Vs[e])
+        t_el[e] = time.perf_counter() - t0
+    # cost per point and pair for each (n_loc, refined) class, falling back to
+    # the unrefined rate of the same n_loc
+    rate = {}
+    for e in sample:
+        rate[(int(nloc[e]), bool(nleaf[e] > 1))] = t_el[e] / work[e]
+    T1 = 0.0
+    for e in range(o.n_elem):
+        key = (int(nloc[e]), bool(nleaf[e] > 1))
+        r = rate.get(key, rate.get((key[0], False)))
+        T1 += r * work[e]
+    t_sample = sum(t_el.values())
+    # the same sample on a pool of threads, every thread running the whole sample
+    threads = max(1, min(len(os.sched_getaffinity(0)), max_threads))
+    tasks = [e for _ in range(threads) for e in sample]
+    tasks.sort(key=lambda e: -work[e])
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda e: o.element_matrices(e, Vs[e]), tasks))
+    wall = time.perf_counter() - t0
+    speedup = threads * t_sample / wall
+    Tn = T1 / speedup
+    n_el = o.n_elem
+    desc = (f"element matrices (H_e, S_e) of {len(sample)} elements: one unrefined element of each of the "
+            f"{len(np.unique(nloc))} n_loc classes and the cheapest refined element of each refined class that "
+            f"runs in seconds ({sum(1 for e in sample if nleaf[e] > 1)} refined); every element of the cell "
+            f"extrapolated by its class's measured seconds per (point x n_loc^2) "
+            f"(EXTRAPOLATED: {T1:.0f} s single-thread for the whole cell; the sample took {t_sample:.1f} s); "
+            f"the oracle's element matrices serve all {n_k} k-points (its phase scatter is not counted)")
+    return {"value": n_el * n_k / Tn, "unit": "elements/s", "cores": threads, "kind": "oracle",
+            "sample": desc + f"; {threads} threads over the sample, {wall:.1f} s wall, speed-up {speedup:.2f}",
+            "single_thread": {"value": n_el * n_k / T1, "cores": 1, "extrapolated_s": T1,
+                              "sample_s": t_sample}}
 
 
 def bsr_rows_cols(lay):
@@ -286,50 +363,77 @@ def leg_backward(reps=3):
     return out
 
 
-def leg_ceal_cell(reps=2):
-    """One assembly of the CeAl-like cell (CsCl a = 5.8 bohr, 12^3 triquadratic
-    hexes, 8^3 Gauss + 3 octree levels within 1 bohr, 41 enrichment functions
-    per atom pair, n_loc up to 283) at 4 k-points, complex128 H and S, FP64."""
+def rel_err(A, B):
+    return float((A - B).norm() / B.norm())
+
+
+def leg_ceal_split(P, p, V, kpts, flops, H64, S64):
+    """The split-BF16 contractions on the headline inputs: kernel time, rate
+    against the effective peak and the relative Frobenius error of H and S
+    against the FP64 GPU result."""
     import torch
-    import paper_1611_00731_amd as P
-    import workloads as W
-    from workloads.potential import potential_at
-    prob = W.ceal_cell()
+    out = {}
+    H = torch.empty_like(H64)
+    S = torch.empty_like(S64)
+    for prec in ("bf16x6", "bf16x3"):
+        ms, _, k = time_assembly(P, p, V, kpts, prec, H, S, steps=3, warmup=1)
+        cms = k["contract_ms"]
+        out[prec] = {"ms_per_step": ms, "contract_ms": cms,
+                     "alg_tflops": flops / (cms * 1e-3) / 1e12,
+                     "frac_of_effective_peak": flops / (cms * 1e-3) / 1e12 / PEAK[prec],
+                     "speedup_vs_fp64_contraction": None,
+                     "H_rel_err_vs_fp64": rel_err(H, H64), "S_rel_err_vs_fp64": rel_err(S, S64)}
+    return out
+
+
+def leg_lih_cell(P, W, potential_at, steps, warmup, tune_cache, do_eig):
+    """The LiH-like cell (a = 7.6 bohr, 8^3 triquadratic hexes, 6^3 Gauss + 2
+    octree levels, 512 elements, 1.52 M points, N = 4888), Gamma, complex128:
+    assembly rate, contraction roofline and the eigenvalue error of the
+    assembled matrices against the stored FP64 oracle eigenvalues, FP64 and
+    both split forms."""
+    import torch
+    prob = W.lih_cell()
     p = P.Problem(prob).setup()
+    P.pufe_tune(p.ctx, "fp64", tune_cache)
+    sz = p.sizes
     xyz, _, _ = p.quadrature()
     V = potential_at(xyz, prob)
     del xyz
     lay = p.layout()
     _, _, leaf_off = p.leaves()
-    nloc, nq, flops = element_work(prob, p.sizes, lay, leaf_off, prob["quad"]["n"] ** 3)
+    _, _, flops = element_work(prob, sz, lay, leaf_off, prob["quad"]["n"] ** 3)
+    alg = float(flops.sum())
     kpts = prob["kpts"]
-    sz = p.sizes
     H = torch.empty((len(kpts), sz["nnz"], 2), dtype=torch.float64, device="cuda")
     S = torch.empty_like(H)
-    P.pufe_assemble(p.ctx, V, kpts, "fp64", "c128", H, S)
-    torch.cuda.synchronize()
-    P.pufe_enable_timing(p.ctx, True)
-    P.pufe_kernel_times(p.ctx, reset=True)
-    st = torch.cuda.current_stream()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record(st)
-    for _ in range(reps):
-        P.pufe_assemble(p.ctx, V, kpts, "fp64", "c128", H, S)
-    t1.record(st)
-    torch.cuda.synchronize()
-    kms, kc = P.pufe_kernel_times(p.ctx, reset=True)
-    P.pufe_enable_timing(p.ctx, False)
-    ms = t0.elapsed_time(t1) / reps
-    cms = kms[0] / max(kc[0], 1)
-    alg = float(flops.sum())
-    out = {"workload": "CeAl-like CsCl cell a=5.8 bohr, 12^3 triquadratic hexes, 8^3 Gauss + 3 octree levels, "
-                       "4 k-points, H+S complex128",
+    ev_ref = golden_eigenvalues()
+    out = {"workload": "LiH-like rock-salt cell a=7.6 bohr, 8^3 triquadratic hexes, 6^3 Gauss + 2 octree levels "
+                       "within 1 bohr, Gamma, H+S complex128",
            "n_elem": sz["n_elem"], "n_qp": sz["n_qp"], "n_dof": sz["n_dof"], "nnz": sz["nnz"],
-           "nloc_max": int(nloc.max()), "ms": ms, "elements_per_s": sz["n_elem"] * len(kpts) / (ms * 1e-3),
-           "contract_ms": cms, "alg_flops": alg, "alg_tflops_contraction": alg / (cms * 1e-3) / 1e12,
-           "frac_of_fp64_peak": alg / (cms * 1e-3) / 1e12 / PEAK["fp64"],
-           "scatter_ms_per_assembly": kms[1] / reps, "chunk_reduce_ms": kms[3] / reps}
-    del H, S
+           "alg_flops": alg}
+    eig = {"n_eig": int(len(ev_ref)), "unit": "Ha",
+           "reference": "FP64 CPU oracle, dense LAPACK solve (tests/golden/lih_cell_eigenvalues.txt)",
+           "note": "bf16x3 keeps two bf16 limbs (about 16 significant bits per operand): its H and S "
+                   "errors are near 2e-6, over the 1e-7 split target, and S loses positive "
+                   "definiteness at this size; only bf16x6 meets the split targets"}
+    for prec in ("fp64", "bf16x6", "bf16x3"):
+        ms, ms_i, k = time_assembly(P, p, V, kpts, prec, H, S, steps if prec == "fp64" else 5, warmup)
+        cms = k["contract_ms"]
+        row = {"ms_per_step": ms, "elements_per_s": sz["n_elem"] * len(kpts) / (ms * 1e-3), "contract_ms": cms,
+               "alg_tflops": alg / (cms * 1e-3) / 1e12, "frac_of_peak": alg / (cms * 1e-3) / 1e12 / PEAK[prec]}
+        if prec == "fp64":
+            row.update(k)
+            row["ms_per_step_with_kernel_events"] = ms_i
+        out[prec] = row
+        if do_eig:
+            err, why = eig_error(P, p, H, S, ev_ref)
+            eig[prec] = err
+            if why:
+                eig[prec + "_note"] = why
+            log(f"LiH-like eigenvalue error {prec}: {err}")
+    if do_eig:
+        out["eig_err"] = eig
     p.close()
     return out
 
@@ -337,13 +441,14 @@ def leg_ceal_cell(reps=2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=sorted(PEAK))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--no-rows", action="store_true",
-                    help="skip the batch (lattice sweep) and adjoint measurement legs")
+                    help="skip the LiH-like, batch (lattice sweep) and adjoint measurement legs")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 forms of the headline")
     ap.add_argument("--host-inputs", action="store_true",
                     help="evaluate the synthetic V on the host and copy it over (no torch kernels; "
                          "for hardware-counter runs); implies --no-eig")
@@ -357,10 +462,9 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: the assembly has no multi-GPU path (asked for {args.gpus}).",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU: the assembly has no multi-GPU path in this build "
+              f"(asked for {args.gpus}); run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_1611_00731_amd as P
@@ -370,81 +474,64 @@ def main():
 
     if libbuild.stale():
         log("warning: libpufe.so is older than its sources; rebuild before trusting these numbers")
+    tune_cache = os.environ.get("PUFE_TUNE_CACHE")
     dev = torch.device("cuda", 0)
-    prob = W.lih_cell()
+    prob = W.ceal_cell()
     log("setup", prob["name"])
     p = P.Problem(prob).setup()
     if not args.no_tune:
         log("autotune")
-        P.pufe_tune(p.ctx, args.precision, os.environ.get("PUFE_TUNE_CACHE"))
+        t0 = time.perf_counter()
+        P.pufe_tune(p.ctx, args.precision, tune_cache)
+        log(f"autotune {time.perf_counter() - t0:.1f} s")
     sz = p.sizes
     xyz, w, qp_off = p.quadrature()
     V = potential_at(xyz.cpu(), prob).to(dev) if args.host_inputs else potential_at(xyz, prob)
+    del xyz, w, qp_off
     lay = p.layout()
     _, _, leaf_off = p.leaves()
     nloc, nq, flops = element_work(prob, sz, lay, leaf_off, prob["quad"]["n"] ** 3)
     kpts = prob["kpts"]
-    H = torch.empty((len(kpts), sz["nnz"], 2), dtype=torch.float64, device=dev)
+    n_out = len(kpts)
+    H = torch.empty((n_out, sz["nnz"], 2), dtype=torch.float64, device=dev)
     S = torch.empty_like(H)
-    stream = torch.cuda.current_stream()
-    log(f"n_elem {sz['n_elem']} n_qp {sz['n_qp']} n_dof {sz['n_dof']} nnz {sz['nnz']}")
-    for i in range(args.warmup):
-        P.pufe_assemble(p.ctx, V, kpts, args.precision, "c128", H, S)
-    torch.cuda.synchronize()
-    log("warmup done")
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record(stream)
-    for i in range(args.steps):
-        P.pufe_assemble(p.ctx, V, kpts, args.precision, "c128", H, S)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = t0.elapsed_time(t1) / args.steps
-    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step")
-    # per-kernel durations from HIP events recorded by the library around each
-    # of its kernels on the launch stream, over a second run of the same steps
-    # (the event records between the kernels would lower the step throughput)
-    P.pufe_enable_timing(p.ctx, True)
-    P.pufe_kernel_times(p.ctx, reset=True)
-    t0.record(stream)
-    for i in range(args.steps):
-        P.pufe_assemble(p.ctx, V, kpts, args.precision, "c128", H, S)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    ms_step_instr = t0.elapsed_time(t1) / args.steps
-    kms, kcnt = P.pufe_kernel_times(p.ctx, reset=True)
-    P.pufe_enable_timing(p.ctx, False)
-    log(f"instrumented {args.steps} steps: {ms_step_instr:.4f} ms/step")
-    contract_ms = kms[0] / max(kcnt[0], 1)
-    scatter_ms = kms[1] / max(kcnt[1], 1)
-    reduce_ms = kms[3] / max(kcnt[3], 1)
+    log(f"n_elem {sz['n_elem']} n_qp {sz['n_qp']} n_dof {sz['n_dof']} nnz {sz['nnz']} k-points {n_out}")
+    ms_step, ms_instr, kern = time_assembly(P, p, V, kpts, args.precision, H, S, args.steps, args.warmup)
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (instrumented {ms_instr:.3f})")
+    contract_ms = kern["contract_ms"]
     alg_flops = float(flops.sum())
     achieved = alg_flops / (contract_ms * 1e-3) / 1e12
-    n_out = len(kpts)
     value = sz["n_elem"] * n_out / (ms_step * 1e-3)
+    tag = "contract_f64_ceal_cell"
+    traffic, = recorded(tag + "_hbm_traffic.md", "traffic_bytes_per_launch")
+    busy, executed = recorded(tag + "_mfma_counters.md", "mfma_busy_frac", "mfma_executed_flops_per_launch")
+    fp64 = args.precision == "fp64"
     out = {
         "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "vs_baseline": None, "dtype": "f64" if fp64 else args.precision,
         "data": "synthetic",
-        "config": {"workload": "LiH-like rock-salt cell a=7.6 bohr, 8^3 triquadratic hexes, 6^3 Gauss "
-                               "+ 2 octree levels within 1 bohr, Gamma, H+S complex128",
+        "config": {"workload": "CeAl-like CsCl cell a=5.8 bohr, 12^3 triquadratic hexes, 8^3 Gauss + 3 octree "
+                               "levels within 1 bohr, 4 k-points (time-reversal-reduced 2x2x2 MP), "
+                               "H+S complex128, autotuned",
                    "n_elem": sz["n_elem"], "n_qp": sz["n_qp"], "n_dof": sz["n_dof"],
-                   "nnz": sz["nnz"], "kpoints": n_out, "precision": args.precision},
+                   "nnz": sz["nnz"], "kpoints": n_out, "precision": args.precision,
+                   "nloc_min": int(nloc.min()), "nloc_max": int(nloc.max()), "nq_max": int(nq.max())},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision],
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
-                     "traffic": recorded_traffic() if args.precision == "fp64" else None,
-                     "kernel": "contract_f64_kernel", "kernel_ms": contract_ms,
-                     "alg_flops_per_launch": alg_flops},
-        "extra": {"ms_per_step_with_kernel_events": ms_step_instr,
-                  "scatter_ms": scatter_ms, "chunk_reduce_ms": reduce_ms, "gflops_step": alg_flops / (ms_step * 1e-3) / 1e9,
-                  "nloc_min": int(nloc.min()), "nloc_max": int(nloc.max()),
-                  "nq_max": int(nq.max())},
+                     "traffic": traffic if fp64 else None,
+                     "kernel": "contract_f64_kernel" if fp64 else "contract_split_kernel",
+                     "kernel_ms": contract_ms, "alg_flops_per_launch": alg_flops,
+                     "mfma_busy_frac": busy if fp64 else None,
+                     "mfma_executed_flops_per_launch": executed if fp64 else None},
+        "extra": {"ms_per_step_with_kernel_events": ms_instr,
+                  "scatter_ms_per_assembly": kern["scatter_ms_per_assembly"],
+                  "chunk_reduce_ms": kern["chunk_reduce_ms"],
+                  "gflops_step": alg_flops / (ms_step * 1e-3) / 1e9,
+                  "unique_contractions_per_s": sz["n_elem"] / (ms_step * 1e-3)},
     }
-    if out["roofline"]["traffic"] is not None:
-        # HBM side of the same kernel: measured bytes per launch over its launch time
-        gbs = out["roofline"]["traffic"] / (contract_ms * 1e-3) / 1e9
+    if traffic is not None and fp64:
+        gbs = traffic / (contract_ms * 1e-3) / 1e9
         out["roofline"]["hbm_gbs"] = gbs
         out["roofline"]["hbm_frac"] = gbs / HBM_PEAK_GBS
     # the paper's own figures, quoted as context (it gives no timings or hardware)
@@ -452,58 +539,27 @@ def main():
                             "figures are basis sizes: cubic PUFE needs about 12x (LiH) and 5x (CeAl) fewer "
                             "DOFs than plane waves at 1e-3 Ha/atom, 269 PUFE functions against 2398-4132 plane "
                             "waves in the LiH equation of state, and the overlap sparsity of its Table 1")
-    if args.precision == "fp64":
-        # MFMA pipe utilisation from the recorded counter pass (SQ_VALU_MFMA_BUSY_CYCLES
-        # over the kernel's SIMD cycles) and the executed MFMA flops, padding included
-        busy, executed = recorded_mfma()
-        out["roofline"]["mfma_busy_frac"] = busy
-        out["roofline"]["mfma_executed_flops_per_launch"] = executed
-    # eigenvalue error of the assembled matrices against the FP64 oracle
-    # (outside the timed region)
-    do_eig = not (args.no_eig or args.host_inputs)
-    ev_ref = golden_eigenvalues()
-    eig = {"n_eig": int(len(ev_ref)), "unit": "Ha",
-           "reference": "FP64 CPU oracle, dense LAPACK solve (tests/golden/lih_cell_eigenvalues.txt)"}
-    if do_eig:
-        err, why = eig_error(P, p, H, S, ev_ref)
-        eig[args.precision] = err
-        if why:
-            eig[args.precision + "_note"] = why
-        log(f"eigenvalue error {args.precision}: {err}")
-    # the split-precision forms on the same inputs (context for the FP64 line)
-    for prec in ("bf16x6", "bf16x3"):
-        if prec == args.precision:
-            continue
-        P.pufe_assemble(p.ctx, V, kpts, prec, "c128", H, S)
-        P.pufe_enable_timing(p.ctx, True)
-        P.pufe_kernel_times(p.ctx, reset=True)
-        for i in range(5):
-            P.pufe_assemble(p.ctx, V, kpts, prec, "c128", H, S)
-        kms2, kc2 = P.pufe_kernel_times(p.ctx, reset=True)
-        P.pufe_enable_timing(p.ctx, False)
-        cms = kms2[0] / max(kc2[0], 1)
-        out["extra"][f"{prec}_contract_ms"] = cms
-        out["extra"][f"{prec}_tflops"] = alg_flops / (cms * 1e-3) / 1e12
-        out["extra"][f"{prec}_frac_of_effective_peak"] = alg_flops / (cms * 1e-3) / 1e12 / PEAK[prec]
-        if do_eig:
-            err, why = eig_error(P, p, H, S, ev_ref)
-            eig[prec] = err
-            if why:
-                eig[prec + "_note"] = why
-            log(f"eigenvalue error {prec}: {err}")
-    if do_eig:
-        out["eig_err"] = eig
+    if fp64 and not args.no_split:
+        log("split-BF16 forms on the same inputs")
+        sp = leg_ceal_split(P, p, V, kpts, alg_flops, H, S)
+        for prec in sp:
+            sp[prec]["speedup_vs_fp64_contraction"] = contract_ms / sp[prec]["contract_ms"]
+        out["extra"]["split"] = sp
+    del H, S
     p.close()
-    if not args.no_rows and args.precision == "fp64":
+    do_eig = not (args.no_eig or args.host_inputs)
+    if not args.no_rows and fp64:
+        log("LiH-like cell leg")
+        out["extra"]["lih_cell"] = leg_lih_cell(P, W, potential_at, 20, 3, tune_cache, do_eig)
+        if do_eig:
+            out["eig_err"] = out["extra"]["lih_cell"].pop("eig_err")
         log("batch leg (lattice sweep)")
         out["extra"]["batch_sweep"] = leg_batch()
         log("adjoint leg (64-atom supercell)")
         out["extra"]["adjoint"] = leg_backward()
-        log("CeAl-like cell leg")
-        out["extra"]["ceal_cell"] = leg_ceal_cell()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline(prob, n_out)
     print(json.dumps(out), flush=True)
 
 

@@ -225,7 +225,10 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path);
  * atomic-free scatter launch per element colour covering all problems.  The sequence is captured once into a HIP graph and replayed;
  * a call with different pointers, k-points, precision or dtype recaptures.
  * d_V, d_H, d_S are host arrays of n device pointers (d_S may be NULL).  The
- * contexts must outlive the batch and must not be set up again meanwhile. */
+ * contexts must outlive the batch.  A context that is defined, set up or
+ * tuned again after pufe_batch_create makes pufe_batch_assemble return
+ * PUFE_ERR_STATE before anything is launched (the batch copied the work
+ * items of the plan it was created on); create a new batch instead. */
 typedef struct pufe_batch pufe_batch;
 int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n);
 int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *kpts, int n_k, int precision,

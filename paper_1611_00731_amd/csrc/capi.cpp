@@ -67,6 +67,9 @@ struct pufe_ctx {
     int tune_block = kBlockTiles;
     int contract_q = 24;            // points per LDS stage of the FP64 contraction (16, 24 or 32)
     int max_item_leaves = 1;
+    // bumped whenever the device tables or work items are rebuilt (problem,
+    // setup, tuner): a batch created earlier refuses to run on a newer plan
+    uint64_t plan_gen = 0;
     DevBuf<ElemDev> d_elems;
     DevBuf<GroupDev> d_groups;
     DevBuf<double> d_img, d_pos, d_partial;
@@ -198,6 +201,7 @@ int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], 
     ctx->have_setup = false;
     ctx->have_bw = false;
     ctx->n_leaves = ctx->n_qp = 0;
+    ++ctx->plan_gen;
     return PUFE_OK;
 }
 
@@ -406,6 +410,7 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_partial.alloc((size_t)ctx->part_slots * 512), "alloc partial tiles");
     CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
     ctx->have_setup = true;
+    ++ctx->plan_gen;
     return PUFE_OK;
 }
 
@@ -740,6 +745,7 @@ int pufe_kernel_times(pufe_ctx *ctx, double *out_ms, int64_t *counts, int reset)
 
 // Upload the element table, work items and partial buffer of the current plan.
 static int upload_items(pufe_ctx *ctx, hipStream_t st) {
+    ++ctx->plan_gen;
     CHECK_HIP(ctx, ctx->d_elems.upload(ctx->plan.elems, st), "upload elements");
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
@@ -793,38 +799,56 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
     hipEvent_t a, b;
     CHECK_HIP(ctx, hipEventCreate(&a), "event");
     CHECK_HIP(ctx, hipEventCreate(&b), "event");
-    double best = 1e300, best_items = ctx->tune_items;
-    int best_block = ctx->tune_block;
-    const double cand_items[] = {1024, 2048, 4096, 8192, 16384};
     const bool saved = ctx->timing;
     ctx->timing = false;
-    int best_q = ctx->contract_q;
-    for (int qv : {16, 24, 32})
-    for (int block = 2; block <= kBlockTiles; ++block)
-        for (double items : cand_items) {
-            ctx->contract_q = qv;
-            plan_items(ctx, items, block);
-            if (ctx->lds > kMaxDynLds || ctx->contract_q != qv) continue;
-            int rc = upload_items(ctx, nullptr);
-            if (rc != PUFE_OK) break;
-            rc = run_contraction(ctx, V.p, precision, nullptr);   // warm-up
-            if (rc != PUFE_OK) break;
-            CHECK_HIP(ctx, hipEventRecord(a, nullptr), "event");
-            for (int r = 0; r < 3; ++r) run_contraction(ctx, V.p, precision, nullptr);
-            CHECK_HIP(ctx, hipEventRecord(b, nullptr), "event");
-            CHECK_HIP(ctx, hipEventSynchronize(b), "event");
-            float ms = 0;
-            CHECK_HIP(ctx, hipEventElapsedTime(&ms, a, b), "event");
-            if (ms < best) {
-                best = ms;
-                best_items = items;
-                best_block = block;
-                best_q = qv;
-            }
+    // Coordinate descent from the current choice: the item count first, then
+    // the tile block, then the stage length, each candidate timed once after
+    // a warm-up run (a problem of a few hundred milliseconds per assembly is
+    // tuned in seconds rather than minutes).
+    double best = 1e300, best_items = ctx->tune_items;
+    int best_block = ctx->tune_block, best_q = ctx->contract_q;
+    std::vector<std::pair<double, std::pair<int, int>>> tried;   // (items, (block, q)) already timed
+    auto trial = [&](double items, int block, int qv) -> int {
+        for (auto &t : tried)
+            if (t.first == items && t.second.first == block && t.second.second == qv) return PUFE_OK;
+        tried.push_back({items, {block, qv}});
+        ctx->contract_q = qv;
+        plan_items(ctx, items, block);
+        if (ctx->lds > kMaxDynLds || ctx->contract_q != qv) return PUFE_OK;   // does not fit: skip
+        int rc = upload_items(ctx, nullptr);
+        if (rc != PUFE_OK) return rc;
+        rc = run_contraction(ctx, V.p, precision, nullptr);   // warm-up
+        if (rc != PUFE_OK) return rc;
+        CHECK_HIP(ctx, hipEventRecord(a, nullptr), "event");
+        rc = run_contraction(ctx, V.p, precision, nullptr);
+        if (rc != PUFE_OK) return rc;
+        CHECK_HIP(ctx, hipEventRecord(b, nullptr), "event");
+        CHECK_HIP(ctx, hipEventSynchronize(b), "event");
+        float ms = 0;
+        CHECK_HIP(ctx, hipEventElapsedTime(&ms, a, b), "event");
+        if (ms < best) {
+            best = ms;
+            best_items = items;
+            best_block = block;
+            best_q = qv;
         }
-    ctx->timing = saved;
+        return PUFE_OK;
+    };
+    int trc = PUFE_OK;
+    const double start_items = ctx->tune_items;
+    const int start_block = ctx->tune_block, start_q = ctx->contract_q;
+    for (double items : {1024.0, 2048.0, 4096.0, 8192.0, 16384.0})
+        if (trc == PUFE_OK) trc = trial(items, start_block, start_q);
+    for (int block = 2; block <= kBlockTiles && trc == PUFE_OK; ++block) trc = trial(best_items, block, start_q);
+    for (int qv : {16, 24, 32})
+        if (trc == PUFE_OK) trc = trial(best_items, best_block, qv);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    if (trc != PUFE_OK) {
+        ctx->timing = saved;
+        return trc;
+    }
+    ctx->timing = saved;
     ctx->tune_items = best_items;
     ctx->tune_block = best_block;
     ctx->contract_q = best_q;
@@ -835,7 +859,7 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
         // append or insert the entry into a flat JSON object
         char entry[512];
         std::snprintf(entry, sizeof entry, "\"%s\": {\"items\": %.0f, \"block\": %d, \"q\": %d, \"ms\": %.4f}", key,
-                      best_items, best_block, best_q, best / 3.0);
+                      best_items, best_block, best_q, best);
         size_t close = text.rfind('}');
         std::string out;
         if (close == std::string::npos || text.find('{') == std::string::npos)
@@ -855,6 +879,7 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
 
 struct pufe_batch {
     std::vector<pufe_ctx *> ctxs;
+    std::vector<uint64_t> gens;             // plan generation of each context at creation
     int device = 0;
     std::vector<ItemDev> items, items_split;
     std::vector<std::vector<int4>> lists;   // per colour: (problem, element, tile pair)
@@ -913,6 +938,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
             return PUFE_ERR_STATE;
         }
         b->ctxs.push_back(ctxs[i]);
+        b->gens.push_back(ctxs[i]->plan_gen);
     }
     b->device = ctxs[0]->device;
     if (hipSetDevice(b->device) != hipSuccess) { delete b; return PUFE_ERR_HIP; }
@@ -1036,6 +1062,10 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
         return bfail(b, PUFE_ERR_INVALID_ARG, "unknown precision or dtype");
     for (int i = 0; i < n; ++i)
         if (!d_V[i] || !d_H[i]) return bfail(b, PUFE_ERR_INVALID_ARG, "null V or H pointer");
+    for (int i = 0; i < n; ++i)
+        if (b->ctxs[i]->plan_gen != b->gens[i])
+            return bfail(b, PUFE_ERR_STATE, "problem " + std::to_string(i) +
+                                                " was set up or tuned again after pufe_batch_create; create the batch anew");
     for (int k = 0; k < 3 * n_k; ++k) {
         if (!std::isfinite(kpts[k])) return bfail(b, PUFE_ERR_INVALID_ARG, "non-finite k-point");
         if (out_dtype == PUFE_OUT_F64_GAMMA && std::fmod(kpts[k], 1.0) != 0.0)

@@ -130,3 +130,44 @@ def test_autotuner_cache_and_parity(tmp_path):
     assert torch.equal(H2, H)
     p.close()
     p2.close()
+
+
+def test_batch_refuses_a_context_tuned_after_creation():
+    """A batch copies the work items of the plans it was created on; tuning a
+    context afterwards re-plans it, so the batch must refuse to run (before
+    launching anything) instead of reading freed tables, and a batch created
+    anew runs and matches the oracle."""
+    base = W.small("lih", mesh=(2, 3, 2), fe_order=2, levels=1, n=3, a=5.0)
+    probs = [W.with_lattice_constant(base, a) for a in (4.8, 5.2)]
+    kpts = W.mp2()[:2]
+    say("batch after tune")
+    ps, Vs, oracles = [], [], []
+    for pr in probs:
+        o = oracle.Oracle(pr)
+        xyz, _, _ = o.quadrature()
+        oracles.append(o)
+        Vs.append(potential_at(torch.from_numpy(xyz).cuda(), pr))
+        ps.append(P.Problem(pr).setup())
+    b = P.Batch(ps)
+    Hs, Ss = b.alloc(len(kpts), device="cuda")
+    b.assemble(Vs, kpts, Hs, Ss)
+    torch.cuda.synchronize()
+    P.pufe_tune(ps[1].ctx, "fp64", None)
+    for h in Hs:
+        h.fill_(3.0)
+    with pytest.raises(P.PufeError) as err:
+        b.assemble(Vs, kpts, Hs, Ss)
+    assert err.value.code == -5   # PUFE_ERR_STATE
+    torch.cuda.synchronize()
+    assert all(bool((h == 3.0).all()) for h in Hs)   # nothing was launched
+    b.close()
+    b2 = P.Batch(ps)
+    b2.assemble(Vs, kpts, Hs, Ss)
+    torch.cuda.synchronize()
+    for i, (o, p) in enumerate(zip(oracles, ps)):
+        Ho, So = o.assemble_dense(Vs[i].cpu().numpy(), kpts[1])
+        assert rel(p.to_dense(Hs[i][1]).cpu().numpy(), Ho) < 1e-12
+        assert rel(p.to_dense(Ss[i][1]).cpu().numpy(), So) < 1e-12
+    b2.close()
+    for p in ps:
+        p.close()
