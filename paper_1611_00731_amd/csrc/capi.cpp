@@ -111,7 +111,7 @@ struct TimedRegion {
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
     TimedRegion(pufe_ctx *c_, int s, hipStream_t st_) : c(c_), slot(s), st(st_) {
-        if (!c->timing) return;
+        if (!c->timing || slot < 0) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
         (void)hipEventRecord(a, st);
     }
@@ -480,7 +480,17 @@ int pufe_get_leaves(pufe_ctx *ctx, int32_t *level, int32_t *ijk, int64_t *elem_l
     return PUFE_OK;
 }
 
-static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipStream_t st) {
+// The element contraction and the K-chunk sum into `partial` (the context's
+// partial-tile buffer, or the fixed workspace of the allocation-free entry).
+static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipStream_t st, double *partial,
+                           bool timed = true) {
+    const bool saved = ctx->timing;
+    ctx->timing = saved && timed;
+    struct Restore {
+        pufe_ctx *c;
+        bool v;
+        ~Restore() { c->timing = v; }
+    } restore{ctx, saved};
     const Plan &pl = ctx->plan;
     if (precision == PUFE_PREC_BF16X3 || precision == PUFE_PREC_BF16X6) {
         const int nl = precision == PUFE_PREC_BF16X3 ? 2 : 3;
@@ -491,24 +501,25 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
             TimedRegion tr(ctx, 0, st);
             CHECK_HIP(ctx, launch_contract_split(nl, pl.max_l, pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p,
                                                  ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
-                                                 ctx->d_leaves.p, d_V, ctx->d_partial.p, lds, st),
+                                                 ctx->d_leaves.p, d_V, partial, lds, st),
                       "split contraction");
         }
     } else {
         TimedRegion tr(ctx, 0, st);
         CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, pl.kp, (int)ctx->items.size(), ctx->d_items.p,
                                            ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
-                                           ctx->d_leaves.p, d_V, ctx->d_partial.p, ctx->lds, st),
+                                           ctx->d_leaves.p, d_V, partial, ctx->lds, st),
                   "contraction");
     }
     TimedRegion tr(ctx, 3, st);
-    CHECK_HIP(ctx, launch_chunk_reduce(ctx->d_elems.p, ctx->d_reduce.p, (int)ctx->reduce.size(), ctx->d_partial.p, st),
+    CHECK_HIP(ctx, launch_chunk_reduce(ctx->d_elems.p, ctx->d_reduce.p, (int)ctx->reduce.size(), partial, st),
               "K-chunk reduction");
     return PUFE_OK;
 }
 
-int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision, int out_dtype,
-                  void *d_H, void *d_S, void *stream) {
+// Argument checks shared by pufe_assemble and pufe_assemble_noalloc.
+static int check_assemble_args(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision,
+                               int out_dtype, void *d_H) {
     if (!ctx) return PUFE_ERR_INVALID_ARG;
     if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
     if (!d_V || !kpts || n_k < 1 || !d_H) return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer or n_k < 1");
@@ -524,12 +535,17 @@ int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k,
              std::fmod(kpts[3 * k + 2], 1.0) != 0.0))
             return fail(ctx, PUFE_ERR_INVALID_ARG, "real output needs every k-point at Gamma");
     }
-    hipStream_t st = (hipStream_t)stream;
-    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    int rc = run_contraction(ctx, d_V, precision, st);
+    return PUFE_OK;
+}
+
+// Contraction, K-chunk sum, output zero fill and coloured scatter of one
+// assembly, with the partial tiles and the phase table in the given buffers.
+static int assemble_impl(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision, int out_dtype,
+                         void *d_H, void *d_S, hipStream_t st, double *partial, double2 *ztab, bool timed) {
+    int rc = run_contraction(ctx, d_V, precision, st, partial, timed);
     if (rc != PUFE_OK) return rc;
     const Plan &pl = ctx->plan;
-    TimedRegion tr(ctx, 1, st);
+    TimedRegion tr(ctx, timed ? 1 : -1, st);
     const int64_t per = out_dtype == PUFE_OUT_F64_GAMMA ? pl.nnz : 2 * pl.nnz;
     const bool f32 = out_dtype == PUFE_OUT_C64;
     const size_t esz = f32 ? sizeof(float) : sizeof(double);
@@ -543,18 +559,28 @@ int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k,
         char *S = d_S ? (char *)d_S + (size_t)k0 * per * esz : nullptr;
         // the first pass zeroes every output (all k-points) with its phase table
         if (k0 == 0)
-            CHECK_HIP(ctx, launch_prepare_outputs(d_H, d_S, (int64_t)(per * n_k * esz), kps, ctx->d_ztab.p, st),
+            CHECK_HIP(ctx, launch_prepare_outputs(d_H, d_S, (int64_t)(per * n_k * esz), kps, ztab, st),
                       "zero outputs and phase table");
         else
-            CHECK_HIP(ctx, launch_phase_table(kps, ctx->d_ztab.p, st), "phase table");
+            CHECK_HIP(ctx, launch_phase_table(kps, ztab, st), "phase table");
         for (size_t col = 0; col + 1 < pl.scat_off.size(); ++col) {
             const int n = (int)(pl.scat_off[col + 1] - pl.scat_off[col]);
             CHECK_HIP(ctx, launch_scatter(pl.kp, ctx->d_elems.p, ctx->d_scat.p + pl.scat_off[col], n, ctx->d_edof.p,
-                                          ctx->d_partial.p, ctx->d_ztab.p, kps.nk, out_dtype, H, S, pl.nnz, st),
+                                          partial, ztab, kps.nk, out_dtype, H, S, pl.nnz, st),
                       "scatter");
         }
     }
     return PUFE_OK;
+}
+
+int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision, int out_dtype,
+                  void *d_H, void *d_S, void *stream) {
+    int rc = check_assemble_args(ctx, d_V, kpts, n_k, precision, out_dtype, d_H);
+    if (rc != PUFE_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    return assemble_impl(ctx, d_V, kpts, n_k, precision, out_dtype, d_H, d_S, st, ctx->d_partial.p, ctx->d_ztab.p,
+                         true);
 }
 
 int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int precision, double *d_He,
@@ -565,7 +591,7 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
         return fail(ctx, PUFE_ERR_INVALID_ARG, "bad element or null pointer");
     hipStream_t st = (hipStream_t)stream;
     CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    int rc = run_contraction(ctx, d_V, precision, st);
+    int rc = run_contraction(ctx, d_V, precision, st, ctx->d_partial.p);
     if (rc != PUFE_OK) return rc;
     CHECK_HIP(ctx, launch_elem_matrices(ctx->d_elems.p, elem, ctx->d_partial.p, d_He, d_Se, ctx->plan.elems[elem].nloc, st),
               "element matrices");
@@ -817,10 +843,10 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
         if (ctx->lds > kMaxDynLds || ctx->contract_q != qv) return PUFE_OK;   // does not fit: skip
         int rc = upload_items(ctx, nullptr);
         if (rc != PUFE_OK) return rc;
-        rc = run_contraction(ctx, V.p, precision, nullptr);   // warm-up
+        rc = run_contraction(ctx, V.p, precision, nullptr, ctx->d_partial.p);   // warm-up
         if (rc != PUFE_OK) return rc;
         CHECK_HIP(ctx, hipEventRecord(a, nullptr), "event");
-        rc = run_contraction(ctx, V.p, precision, nullptr);
+        rc = run_contraction(ctx, V.p, precision, nullptr, ctx->d_partial.p);
         if (rc != PUFE_OK) return rc;
         CHECK_HIP(ctx, hipEventRecord(b, nullptr), "event");
         CHECK_HIP(ctx, hipEventSynchronize(b), "event");

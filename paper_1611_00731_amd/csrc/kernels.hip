@@ -169,7 +169,7 @@ struct ContractLds {
         return sizeof(double) * ((size_t)rows * RS + 2 * (size_t)Q + (size_t)nfun * Q * 4 + (size_t)Q * GEO +
                                  (size_t)nimg * 3 + 2 * kMaxGauss) +
                sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc +
-               sizeof(uint32_t) * ((size_t)nleaf + n3 + rows + 16) + 64;
+               sizeof(uint32_t) * ((size_t)nleaf + n3 + rows + 16 + kMaxRowChunks + 4) + 64;
     }
 };
 
@@ -290,7 +290,9 @@ __device__ __forceinline__ void contract_f64_item(
     uint32_t *sLeaf = (uint32_t *)(sEd + kMaxNloc);
     uint32_t *sPt = sLeaf + (it.leaf_e - it.leaf_b);
     int *sRow = (int *)(sPt + n3);
-    int *sCS = sRow + nrow;   // [9] PU corner starts in sEd (whole-element items)
+    int *sCS = sRow + nrow;   // [9] PU corner starts in sEd
+    int *sChunk = sCS + 16;   // [kMaxRowChunks] enriched-row chunks of a partial item, and their count
+    int *sNChunk = sChunk + kMaxRowChunks;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t q_begin = it.leaf_b * (int64_t)n3, q_end = it.leaf_e * (int64_t)n3;
     const uint32_t nli = (uint32_t)(q_end - q_begin);
@@ -300,7 +302,11 @@ __device__ __forceinline__ void contract_f64_item(
     // share a point's geometry (FE functions by (a2, a3), enriched ones by
     // PU corner); other items take one row at a time
     const bool whole = diag && ti0 == 0 && 16 * it.nI >= nloc;
-    if (whole) corner_starts(gEdof + el.edof_off, nloc - nfe, sCS, tid, NT);
+    corner_starts(gEdof + el.edof_off, nloc - nfe, sCS, tid, NT);
+    // local functions of a partial item: rows [lo0, hi0) then, off the
+    // diagonal, [lo1, hi1), at LDS rows 0 and 16 nI
+    const int lo0 = 16 * ti0, hi0 = min(16 * (ti0 + it.nI), nloc);
+    const int lo1 = diag ? 0 : 16 * tj0, hi1 = diag ? 0 : min(16 * (tj0 + it.nJ), nloc);
     for (int g = tid; g < ngrp; g += NT) {
         const PUFE_GLOBAL GroupDev &Gg = gGroups[el.grp_off + g];
         GroupDev G;
@@ -436,8 +442,12 @@ __device__ __forceinline__ void contract_f64_item(
         }
     };
     __syncthreads();
+    if (!whole && tid == 0) row_chunks(sCS, nfe, lo0, hi0, lo1, hi1, Q, NT, sChunk, sNChunk);
     if (nli > 0) phase1(0, sV);
     __syncthreads();
+    // FE functions in the item's rows (grouped by (a2, a3), filtered on store)
+    const int n1 = kp.p + 1;
+    const int nfu = whole ? n1 * n1 : ((lo0 < nfe || (!diag && lo1 < nfe)) ? n1 * n1 : 0);
 
     for (uint32_t lb = 0, st = 0; lb < nli; lb += Q, st ^= 1) {
         double *sVc = sV + st * Q;
@@ -472,20 +482,34 @@ __device__ __forceinline__ void contract_f64_item(
                 };
                 pu_unit<Q>(kp, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
             }
-        } else
-#pragma unroll 2
-        for (int idx = tid; idx < nreal * Q; idx += NT) {
-            const int r = idx / Q, q = idx - r * Q;
-            const int a = sRow[r];
-            const double *g = sGeo + q;   // field f at g[f * Q]
-            double val, gx[3];
-            local_row<Q>(kp, g, sPsi + q, sEd, a, nfe, &val, gx);
-            const double s2 = g[G_SW2 * Q];
-            double *o = sB + (size_t)r * RS + q;
-            o[0] = s2 * gx[0];
-            o[Q] = s2 * gx[1];
-            o[2 * Q] = s2 * gx[2];
-            o[3 * Q] = g[G_SW * Q] * val;
+        } else {
+            // partial items: the same geometry-sharing groups, the enriched
+            // ones cut into the chunks of the item's rows (row_chunks)
+            const int nch = *sNChunk;
+            for (int idx = tid; idx < (nfu + nch) * Q; idx += NT) {
+                const int u = idx / Q, q = idx - u * Q;
+                double *o = sB + q;
+                auto put = [&](int a, double x, double y, double z, double w) {
+                    int r;
+                    if (a >= lo0 && a < hi0) r = a - lo0;
+                    else if (a >= lo1 && a < hi1) r = 16 * it.nI + (a - lo1);
+                    else return;
+                    double *rr = o + (size_t)r * RS;
+                    rr[0] = x;
+                    rr[Q] = y;
+                    rr[2 * Q] = z;
+                    rr[3 * Q] = w;
+                };
+                if (u < nfu) {
+                    if (n1 == 3)
+                        fe_unit<Q, 3>(kp, sGeo + q, u % 3, u / 3, put);
+                    else
+                        fe_unit<Q, 2>(kp, sGeo + q, u & 1, u >> 1, put);
+                } else {
+                    const int ch = sChunk[u - nfu];
+                    pu_unit<Q>(kp, sGeo + q, sPsi + q, sEd, ch & 7, (ch >> 3) & 1023, ch >> 13, nfe, put);
+                }
+            }
         }
         __syncthreads();
         // ---- phase 3: the MFMAs of this stage (V from its buffer), then

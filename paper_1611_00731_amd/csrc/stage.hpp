@@ -256,4 +256,33 @@ __device__ __forceinline__ void corner_starts(const PUFE_GLOBAL int32_t *ed, int
     }
 }
 
+// Chunks of the enriched rows of a partial work item (rows [lo0, hi0) and
+// [lo1, hi1) of the element's local functions): runs of one PU corner's
+// entries, cut to about nt / q rows' worth of (chunk, point) units so that a
+// stage's units fill the work group once; packed as corner | first entry << 3
+// | end entry << 13.  cs: corner starts (corner_starts).  One thread.
+__device__ __forceinline__ void row_chunks(const int *cs, int nfe, int lo0, int hi0, int lo1, int hi1, int q, int nt,
+                                           int *chunk, int *count) {
+    const int e0 = max(lo0 - nfe, 0), e1 = max(hi0 - nfe, 0), f0 = max(lo1 - nfe, 0), f1 = max(hi1 - nfe, 0);
+    const int total = (e1 - e0) + (f1 - f0);
+    // rows per chunk: the item's (row, point) work spread over one pass of
+    // the work group, at least 4 rows, and few enough chunks for the table
+    int ch = (total * q + nt - 1) / nt;
+    ch = max(ch, max(4, (total + kMaxRowChunks - 17) / (kMaxRowChunks - 16)));
+    int n = 0;
+    for (int r = 0; r < 2; ++r) {
+        const int b = r ? f0 : e0, e = r ? f1 : e1;
+        for (int c = 0; c < 8; ++c) {
+            int kb = max(cs[c], b);
+            const int ke = min(cs[c + 1], e);
+            while (kb < ke && n < kMaxRowChunks) {
+                const int kn = min(kb + ch, ke);
+                chunk[n++] = c | (kb << 3) | (kn << 13);
+                kb = kn;
+            }
+        }
+    }
+    *count = n;
+}
+
 }  // namespace pufe

@@ -12,6 +12,7 @@ constexpr int kTile = 16;         // MFMA tile edge
 constexpr int kBlockTiles = 4;    // tiles per row/column block of a work item
 constexpr int kMaxGauss = 12;
 constexpr int kMaxLevel = 8;
+constexpr int kMaxRowChunks = 64; // enriched-row chunks of one partial work item
 // dynamic LDS a kernel may request: the 160 KiB of a CU minus room for the
 // small static __shared__ variables some kernels also declare
 constexpr size_t kMaxDynLds = 159 * 1024;

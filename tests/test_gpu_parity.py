@@ -335,3 +335,105 @@ def test_random_small_problems(seed):
         assert rel(p.to_dense(Hs[k]).cpu().numpy(), Ho) < 1e-7, (seed, kap)
         assert rel(p.to_dense(Ss[k]).cpu().numpy(), So) < 1e-7, (seed, kap)
     p.close()
+
+
+def _golden_elements(path):
+    """Checks of oracle element matrices stored by tests/golden/make_ceal_deep_elements.py."""
+    out, cur = [], None
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        key, *vals = line.split()
+        if key == "element":
+            cur = {"e": int(vals[0]), "nloc": int(vals[1]), "nq": int(vals[2])}
+            out.append(cur)
+        elif key == "ab":
+            cur["ab"] = np.array(vals, int).reshape(-1, 2)
+        elif key.endswith("_fro"):
+            cur[key] = float(vals[0])
+        else:
+            cur[key] = np.array(vals, float)
+    return out
+
+
+def _element_checks_error(c, M, name):
+    """Largest relative error of the stored checks of one element matrix."""
+    Mx = M @ c["x"]
+    errs = [abs(np.linalg.norm(M) - c[name + "_fro"]) / c[name + "_fro"]]
+    for got, ref in ((np.diag(M), c[name + "_diag"]), (Mx, c[name + "_x"]),
+                     (M[c["ab"][:, 0], c["ab"][:, 1]], c[name + "_ab"])):
+        errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return max(errs)
+
+
+def test_ceal_cell_deepest_elements_fp64_and_split():
+    """The CeAl-like workload at full size, deepest elements: the fully
+    refined elements (262,144 and 147,456 points; hundreds of K-chunks,
+    items of several row and column blocks) with the most local functions
+    (283) and a fully refined element next to Al (99), against the oracle's
+    element matrices stored by tests/golden/make_ceal_deep_elements.py, FP64
+    (1e-12) and bf16x6 (1e-7); bf16x6 also on the unrefined element with the
+    most functions and on BSR blocks around all-unrefined vertices against
+    the oracle directly."""
+    import os
+    prob = W.ceal_cell()
+    gold = _golden_elements(os.path.join(os.path.dirname(__file__), "golden", "ceal_deep_elements.txt"))
+    say("ceal_cell deepest elements", [g["e"] for g in gold])
+    p = P.Problem(prob).setup()
+    xyz, _, qoff = p.quadrature()
+    Vd = potential_at(xyz, prob)
+    del xyz
+    qoff = qoff.cpu().numpy()
+    for prec, tol in (("fp64", TOL), ("bf16x6", 1e-7)):
+        for g in gold:
+            e = g["e"]
+            assert qoff[e + 1] - qoff[e] == g["nq"]
+            He, Se = p.element_matrices(e, Vd, precision=prec)
+            assert He.shape[0] == g["nloc"]
+            eh = _element_checks_error(g, He.cpu().numpy(), "H")
+            es = _element_checks_error(g, Se.cpu().numpy(), "S")
+            say(prec, "element", e, "H", eh, "S", es)
+            assert eh < tol and es < tol, (prec, e, eh, es)
+    # bf16x6 against the oracle on the largest unrefined element and on
+    # blocks whose elements are all unrefined (same V array on both sides)
+    o = oracle.Oracle(prob)
+    _, _, loff = o.leaves()
+    nleaf = np.diff(loff)
+    nloc = np.array([o.element_dofs(e)[0].size for e in range(o.n_elem)])
+    plain = np.flatnonzero(nleaf == 1)
+    e_big = int(plain[np.argmax(nloc[plain])])
+    Vh = Vd.cpu().numpy()
+    He, Se = p.element_matrices(e_big, Vd, precision="bf16x6")
+    Ho, So = o.element_matrices(e_big, Vh[qoff[e_big]:qoff[e_big + 1]])
+    say("bf16x6 element", e_big, "H", rel(He.cpu().numpy(), Ho), "S", rel(Se.cpu().numpy(), So))
+    assert rel(He.cpu().numpy(), Ho) < 1e-7 and rel(Se.cpu().numpy(), So) < 1e-7
+    kap = tuple(prob["kpts"][2])
+    H, S = p.assemble(Vd, [kap], precision="bf16x6")
+    lay = p.layout()
+    Hh, Sh = H[0].cpu().numpy(), S[0].cpu().numpy()
+    del H, S
+    n1, n2, n3 = prob["mesh"]
+
+    def all_plain(v):
+        i, j, k = v % n1, (v // n1) % n2, v // (n1 * n2)
+        return all(nleaf[((i - a) % n1) + n1 * (((j - b) % n2) + n2 * ((k - c) % n3))] == 1
+                   for a in (0, 1) for b in (0, 1) for c in (0, 1))
+
+    off_d = lay["dof_offset"]
+    width = np.diff(off_d)
+    cand = [v for v in range(o.n_vertex) if all_plain(v)]
+    rng = np.random.default_rng(12)
+    for v in [max(cand, key=lambda v: width[v])] + list(rng.choice(cand, 2, replace=False)):
+        v = int(v)
+        kk = lay["brow_ptr"][v]
+        wv = int(lay["bcol"][kk])
+        if not all_plain(wv):
+            continue
+        Hb, Sb = o.assemble_block(Vh, kap, v, wv)
+        b0, b1 = lay["bval_offset"][kk], lay["bval_offset"][kk + 1]
+        shape = (off_d[v + 1] - off_d[v], off_d[wv + 1] - off_d[wv])
+        Hg = (Hh[b0:b1, 0] + 1j * Hh[b0:b1, 1]).reshape(shape)
+        Sg = (Sh[b0:b1, 0] + 1j * Sh[b0:b1, 1]).reshape(shape)
+        say("bf16x6 block", v, wv, shape, rel(Hg, Hb), rel(Sg, Sb))
+        assert rel(Hg, Hb) < 1e-7 and rel(Sg, Sb) < 1e-7, (v, wv)
+    p.close()

@@ -2,8 +2,13 @@
 
 bf16x6 (three limbs, six products, FP32 MFMA accumulation flushed to FP64
 every 32 points) must meet 1e-7 relative Frobenius on H and S and 1e-6 Ha on
-the eigenvalues.  bf16x3 (two limbs, three products) is held to the bound its
-~17-bit operands allow, and its measured error is printed.
+the eigenvalues.  bf16x3 (two limbs, three products) cannot: its errors are
+near 2e-6, mostly the bias of the dropped a1 b1 product (the CPU emulation
+of the limb arithmetic in test_split_emulation.py reproduces them).  Its
+tests assert that documented outcome: errors between 1e-7 and 5e-6, and at
+the full size of the LiH-like cell an overlap matrix that is no longer
+numerically positive definite (the S error exceeds its smallest relative
+eigenvalue, about 1 / cond(S) = 1e-7).
 """
 import numpy as np
 import pytest
@@ -50,7 +55,7 @@ def test_split_small_vs_oracle(name):
         errs[prec] = (eh, es)
     say("errors", errs)
     assert max(errs["bf16x6"]) < 1e-7
-    assert max(errs["bf16x3"]) < 5e-6
+    assert 1e-7 < max(errs["bf16x3"]) < 5e-6
     p.close()
 
 
@@ -69,15 +74,17 @@ def test_split_single_atom_cube_eigenvalues():
     p.close()
 
 
-def test_split_lih_cell_full_size_eigenvalues():
-    """The LiH-like workload at full size: H/S errors of both split forms and
-    the lowest 16 eigenvalues against the oracle's dense FP64 assembly."""
+def test_lih_cell_full_size_dense_fp64_and_split():
+    """The LiH-like workload at full size against the oracle's dense FP64
+    assembly: the whole FP64 H and S at 1e-12, both split forms' H/S errors,
+    and the lowest 16 eigenvalues of bf16x6 within 1e-6 Ha."""
     prob = W.lih_cell()
-    say("split lih_cell full size (oracle dense assembly, ~1 min)")
+    say("lih_cell full size dense (oracle dense assembly, ~1 min)")
     o = oracle.Oracle(prob)
     xyz, _, _ = o.quadrature()
     V = potential_at(torch.from_numpy(xyz).cuda(), prob)
     Ho, So = o.assemble_dense(V.cpu().numpy())
+    assert np.abs(Ho.imag).max() == 0 and np.abs(So.imag).max() == 0
     Ho, So = Ho.real, So.real
     say("oracle assembled")
     Hd = torch.from_numpy(Ho).cuda()
@@ -85,24 +92,26 @@ def test_split_lih_cell_full_size_eigenvalues():
     ev_o = P.eig(Hd, Sd, 16).cpu().numpy()   # dense FP64 solve of the oracle's (real, Gamma) matrices
     say("oracle eigenvalues", ev_o[:4])
     p = P.Problem(prob).setup()
-    for prec, tol_m in (("bf16x6", 1e-7), ("bf16x3", 5e-6)):
+    H, S = p.assemble(V, precision="fp64")
+    Hc, Sc = p.to_dense(H[0]).cpu().numpy(), p.to_dense(S[0]).cpu().numpy()
+    eh, es = rel(Hc, Ho), rel(Sc, So)
+    say("fp64 H", eh, "S", es)
+    assert eh < 1e-12 and es < 1e-12
+    for prec, lo, hi in (("bf16x6", 0.0, 1e-7), ("bf16x3", 1e-7, 5e-6)):
         H, S = p.assemble(V, precision=prec)
         Hg, Sg = p.to_dense(H[0]).real.contiguous(), p.to_dense(S[0]).real.contiguous()
         eh = rel(Hg.cpu().numpy(), Ho)
         es = rel(Sg.cpu().numpy(), So)
         say(prec, "H", eh, "S", es)
-        assert eh < tol_m and es < tol_m
+        assert lo < max(eh, es) < hi
         if prec == "bf16x6":
             ev = P.eig(Hg, Sg, 16).cpu().numpy()
             de = np.abs(ev - ev_o).max()
             say(prec, "eig", de)
             assert de < 1e-6
         else:
-            # two limbs leave S with errors near 2e-6 against a condition
-            # number near 1e7: its Cholesky may break down, which is reported
-            try:
-                ev = P.eig(Hg, Sg, 16).cpu().numpy()
-                say(prec, "eig", np.abs(ev - ev_o).max())
-            except RuntimeError as e:
-                say(prec, "eig: S not positive definite at this precision:", str(e).splitlines()[0])
+            # two limbs leave S with relative errors near 2e-6 against a
+            # smallest relative eigenvalue near 1e-7: S is indefinite
+            with pytest.raises(RuntimeError):
+                P.eig(Hg, Sg, 16)
     p.close()
