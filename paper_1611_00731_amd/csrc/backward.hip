@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void backward_kernel(
                 };
                 if (u >= n1 * n1) {
                     const int c = u - n1 * n1;
-                    pu_unit<Q, 10, true>(kl, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
+                    pu_unit<Q, 10 * Q, true>(kl, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
                 } else if (n1 == 3) {
                     fe_unit<Q, 3, true>(kl, sGeo + q, u % 3, u / 3, put);
                 } else {

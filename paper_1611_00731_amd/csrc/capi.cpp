@@ -60,6 +60,12 @@ struct pufe_ctx {
     int64_t n_leaves = 0, n_qp = 0;
     std::vector<int64_t> leaf_off_h;
     std::vector<ItemDev> items, items_split;
+    // wide work items: the row and column blocks of elements of more than
+    // kWholeMaxTiles tiles, for the 8-wave kernel (wide_tiles = 0: none, those
+    // elements go to the narrow kernel)
+    std::vector<ItemDev> items_wide;
+    int wide_tiles = kWideTiles, max_rows_wide = 16, max_item_leaves_wide = 1;
+    size_t lds_wide = 0;
     size_t lds = 0;
     int max_rows = 16, max_rows_split = 16, max_item_leaves_split = 1;
     int64_t part_slots = 0;
@@ -80,7 +86,7 @@ struct pufe_ctx {
     DevBuf<double2> d_ztab;
     DevBuf<uint32_t> d_leaves;
     DevBuf<int64_t> d_leaf_count, d_leaf_off, d_bval_off, d_dof_off;
-    DevBuf<ItemDev> d_items, d_items_split;
+    DevBuf<ItemDev> d_items, d_items_split, d_items_wide;
     // adjoint
     bool have_bw = false;
     std::vector<ItemDev> bw_items;
@@ -238,14 +244,17 @@ static void plan_chunks(pufe_ctx *c, double target_items) {
 }
 
 // Work items (row block x column block of 16x16 tiles x K-chunk), largest
-// MFMA work first.
-static std::vector<ItemDev> make_items(const pufe_ctx *c, int block_tiles, int *max_rows, int *max_leaves) {
+// MFMA work first.  sel: 0 every element, 1 the elements of at most
+// kWholeMaxTiles tiles, 2 the others.
+static std::vector<ItemDev> make_items(const pufe_ctx *c, int block_tiles, int *max_rows, int *max_leaves,
+                                       int sel = 0) {
     const Plan &pl = c->plan;
     std::vector<ItemDev> items;
     std::vector<double> cost;
     for (int64_t e = 0; e < pl.nel; ++e) {
         const ElemDev &el = pl.elems[e];
         const int T = (el.nloc + 15) / 16;
+        if ((sel == 1 && T > kWholeMaxTiles) || (sel == 2 && T <= kWholeMaxTiles)) continue;
         // up to 5 tiles fit one diagonal block (15 tile pairs over 4 waves)
         const int bt = (T <= 5 && block_tiles >= 4) ? T : block_tiles;
         const int nb = (T + bt - 1) / bt;
@@ -289,10 +298,23 @@ static void plan_items(pufe_ctx *c, double target_items, int block_tiles) {
     plan_chunks(c, target_items);
     const int nfun = std::max(c->plan.max_nfun, 1);
     const int n3 = c->plan.kp.n3;
+    // wide items first: tile blocks of wide_tiles (fewer if the stage does
+    // not fit in LDS); without them every element goes to the narrow kernel
+    c->items_wide.clear();
+    bool wide = false;
+    for (int b = c->wide_tiles; b >= 2; --b) {
+        c->items_wide = make_items(c, b, &c->max_rows_wide, &c->max_item_leaves_wide, 2);
+        c->lds_wide = contract_wide_lds_bytes(c->max_rows_wide, nfun, c->plan.max_img, c->max_item_leaves_wide, n3);
+        if (c->lds_wide <= kMaxDynLds) {
+            wide = true;
+            break;
+        }
+    }
+    if (!wide) c->items_wide.clear();
     // the FP64 stage double-buffers the rows of an item: use the largest
     // tile block (and stage length) whose buffers fit in LDS
     for (int b = block_tiles; b >= 1; --b) {
-        c->items = make_items(c, b, &c->max_rows, &c->max_item_leaves);
+        c->items = make_items(c, b, &c->max_rows, &c->max_item_leaves, wide ? 1 : 0);
         c->lds = contract_lds_bytes(c->contract_q, c->max_rows, nfun, c->plan.max_img, c->max_item_leaves, n3);
         if (c->lds > kMaxDynLds && c->contract_q > 16) {   // shorter stages before smaller blocks
             c->contract_q = 16;
@@ -398,6 +420,7 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_img.upload(pl.img_cur, st), "upload images");
     CHECK_HIP(ctx, ctx->d_edof.upload(pl.edof, st), "upload enriched functions");
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
+    CHECK_HIP(ctx, ctx->d_items_wide.upload(ctx->items_wide, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_color_elems.upload(pl.color_elems, st), "upload colours");
     CHECK_HIP(ctx, ctx->d_scat.upload(pl.scat, st), "upload scatter list");
@@ -506,6 +529,11 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
         }
     } else {
         TimedRegion tr(ctx, 0, st);
+        // wide items first: they are the longest
+        CHECK_HIP(ctx, launch_contract_wide(pl.max_l, pl.kp, (int)ctx->items_wide.size(), ctx->d_items_wide.p,
+                                            ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
+                                            ctx->d_leaves.p, d_V, partial, ctx->lds_wide, st),
+                  "contraction (wide items)");
         CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, pl.kp, (int)ctx->items.size(), ctx->d_items.p,
                                            ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                            ctx->d_leaves.p, d_V, partial, ctx->lds, st),
@@ -774,6 +802,7 @@ static int upload_items(pufe_ctx *ctx, hipStream_t st) {
     ++ctx->plan_gen;
     CHECK_HIP(ctx, ctx->d_elems.upload(ctx->plan.elems, st), "upload elements");
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
+    CHECK_HIP(ctx, ctx->d_items_wide.upload(ctx->items_wide, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_reduce.upload(ctx->reduce, st), "upload chunk reduction list");
     CHECK_HIP(ctx, ctx->d_partial.alloc((size_t)ctx->part_slots * 512), "alloc partial tiles");
@@ -808,12 +837,15 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
         size_t at = text.find(pat);
         if (at != std::string::npos) {
             double items = 0;
-            int block = 0, qv = 0;
-            if (std::sscanf(text.c_str() + at + pat.size(), "%lf, \"block\": %d, \"q\": %d", &items, &block, &qv) == 3 &&
-                items > 0 && block >= 1 && block <= kBlockTiles && contract_q_supported(qv)) {
+            int block = 0, qv = 0, wide = kWideTiles;
+            const int nf = std::sscanf(text.c_str() + at + pat.size(), "%lf, \"block\": %d, \"q\": %d, \"wide\": %d",
+                                       &items, &block, &qv, &wide);
+            if (nf >= 3 && items > 0 && block >= 1 && block <= kBlockTiles && contract_q_supported(qv) &&
+                (wide == 0 || (wide >= 2 && wide <= kWideTiles))) {
                 ctx->tune_items = items;
                 ctx->tune_block = block;
                 ctx->contract_q = qv;
+                ctx->wide_tiles = wide;
                 plan_items(ctx, items, block);
                 return upload_items(ctx, nullptr);
             }
@@ -832,13 +864,18 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
     // a warm-up run (a problem of a few hundred milliseconds per assembly is
     // tuned in seconds rather than minutes).
     double best = 1e300, best_items = ctx->tune_items;
-    int best_block = ctx->tune_block, best_q = ctx->contract_q;
-    std::vector<std::pair<double, std::pair<int, int>>> tried;   // (items, (block, q)) already timed
-    auto trial = [&](double items, int block, int qv) -> int {
+    int best_block = ctx->tune_block, best_q = ctx->contract_q, best_wide = ctx->wide_tiles;
+    struct Tried {
+        double items;
+        int block, q, wide;
+    };
+    std::vector<Tried> tried;
+    auto trial = [&](double items, int block, int qv, int wide) -> int {
         for (auto &t : tried)
-            if (t.first == items && t.second.first == block && t.second.second == qv) return PUFE_OK;
-        tried.push_back({items, {block, qv}});
+            if (t.items == items && t.block == block && t.q == qv && t.wide == wide) return PUFE_OK;
+        tried.push_back({items, block, qv, wide});
         ctx->contract_q = qv;
+        ctx->wide_tiles = wide;
         plan_items(ctx, items, block);
         if (ctx->lds > kMaxDynLds || ctx->contract_q != qv) return PUFE_OK;   // does not fit: skip
         int rc = upload_items(ctx, nullptr);
@@ -857,17 +894,21 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
             best_items = items;
             best_block = block;
             best_q = qv;
+            best_wide = wide;
         }
         return PUFE_OK;
     };
     int trc = PUFE_OK;
-    const double start_items = ctx->tune_items;
-    const int start_block = ctx->tune_block, start_q = ctx->contract_q;
+    const int start_block = ctx->tune_block, start_q = ctx->contract_q, start_wide = ctx->wide_tiles;
     for (double items : {1024.0, 2048.0, 4096.0, 8192.0, 16384.0})
-        if (trc == PUFE_OK) trc = trial(items, start_block, start_q);
-    for (int block = 2; block <= kBlockTiles && trc == PUFE_OK; ++block) trc = trial(best_items, block, start_q);
+        if (trc == PUFE_OK) trc = trial(items, start_block, start_q, start_wide);
+    for (int block = 2; block <= kBlockTiles && trc == PUFE_OK; ++block)
+        trc = trial(best_items, block, start_q, start_wide);
     for (int qv : {16, 24, 32})
-        if (trc == PUFE_OK) trc = trial(best_items, best_block, qv);
+        if (trc == PUFE_OK) trc = trial(best_items, best_block, qv, start_wide);
+    if (pl.max_nloc > 16 * kWholeMaxTiles)   // elements for the wide kernel
+        for (int wide : {kWideTiles, kWideTiles - 1, 0})
+            if (trc == PUFE_OK) trc = trial(best_items, best_block, best_q, wide);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (trc != PUFE_OK) {
@@ -878,14 +919,15 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
     ctx->tune_items = best_items;
     ctx->tune_block = best_block;
     ctx->contract_q = best_q;
+    ctx->wide_tiles = best_wide;
     plan_items(ctx, best_items, best_block);
     int rc = upload_items(ctx, nullptr);
     if (rc != PUFE_OK) return rc;
     if (cache_path) {
         // append or insert the entry into a flat JSON object
         char entry[512];
-        std::snprintf(entry, sizeof entry, "\"%s\": {\"items\": %.0f, \"block\": %d, \"q\": %d, \"ms\": %.4f}", key,
-                      best_items, best_block, best_q, best);
+        std::snprintf(entry, sizeof entry, "\"%s\": {\"items\": %.0f, \"block\": %d, \"q\": %d, \"wide\": %d, \"ms\": %.4f}",
+                      key, best_items, best_block, best_q, best_wide, best);
         size_t close = text.rfind('}');
         std::string out;
         if (close == std::string::npos || text.find('{') == std::string::npos)
@@ -916,8 +958,12 @@ struct pufe_batch {
     int max_l = 0, q[2] = {24, 16};
     int grid_f64[2] = {0, 0}, grid_split[2] = {0, 0};
     int64_t item_off[3] = {0, 0, 0};
+    // wide items of all problems (8-wave persistent launch)
+    std::vector<ItemDev> items_wide;
+    size_t lds_wide = 0;
+    int grid_wide = 0;
     DevBuf<CtxDev> d_ctxs;
-    DevBuf<ItemDev> d_items, d_items_split;
+    DevBuf<ItemDev> d_items, d_items_split, d_items_wide;
     DevBuf<int4> d_lists;
     std::vector<int4> reduce;               // (problem, element, tile pair) of multi-chunk elements
     DevBuf<int4> d_reduce;
@@ -992,14 +1038,14 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
             cls[pr.second] = 0;
         }
     }
-    for (int pass = 0; pass < 3; ++pass) {
-        // pass 0, 1: FP64 items of class 0, 1; pass 2: split items
+    for (int pass = 0; pass < 4; ++pass) {
+        // pass 0, 1: FP64 items of class 0, 1; pass 2: split items; pass 3: wide FP64 items
         std::vector<std::pair<double, size_t>> order;
         std::vector<ItemDev> all;
         for (int i = 0; i < n; ++i) {
             pufe_ctx *c = ctxs[i];
             if (pass < 2 && cls[i] != pass) continue;
-            for (const ItemDev &it0 : pass < 2 ? c->items : c->items_split) {
+            for (const ItemDev &it0 : pass < 2 ? c->items : (pass == 2 ? c->items_split : c->items_wide)) {
                 ItemDev it = it0;
                 it.ctx = i;
                 order.push_back({item_cost(it, c->plan.kp.n3), all.size()});
@@ -1008,7 +1054,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         }
         std::stable_sort(order.begin(), order.end(),
                          [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &c) { return a.first > c.first; });
-        std::vector<ItemDev> &dst = pass < 2 ? b->items : b->items_split;
+        std::vector<ItemDev> &dst = pass < 2 ? b->items : (pass == 2 ? b->items_split : b->items_wide);
         for (auto &o : order) dst.push_back(all[o.second]);
         if (pass < 2) b->item_off[pass + 1] = (int64_t)b->items.size();
     }
@@ -1027,6 +1073,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         max_leaves_split = std::max(max_leaves_split, c->max_item_leaves_split);
         max_n3 = std::max(max_n3, c->plan.kp.n3);
         b->max_l = std::max(b->max_l, c->plan.max_l);
+        if (!c->items_wide.empty()) b->lds_wide = std::max(b->lds_wide, c->lds_wide);
         for (int64_t e = 0; e < c->plan.nel; ++e) {
             const int T = (c->plan.elems[e].nloc + 15) / 16;
             for (int pp = 0; pp < T * (T + 1) / 2; ++pp)
@@ -1057,8 +1104,21 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         b->lds_split[k] = split_lds_bytes(k + 2, max_rows_split, max_nfun, max_img, max_leaves_split, max_n3);
         b->grid_split[k] = ncu * persistent_blocks_per_cu(b->lds_split[k]);
     }
+    // the wide items' stage: each problem's own fits, and one wide work group
+    // per CU; the largest stage of the problems serves all of them
+    {
+        int rw = 16, lw = 1;
+        for (int i = 0; i < n; ++i)
+            if (!ctxs[i]->items_wide.empty()) {
+                rw = std::max(rw, ctxs[i]->max_rows_wide);
+                lw = std::max(lw, ctxs[i]->max_item_leaves_wide);
+            }
+        if (!b->items_wide.empty()) b->lds_wide = contract_wide_lds_bytes(rw, max_nfun, max_img, lw, max_n3);
+        b->grid_wide = ncu;
+    }
     hipStream_t st = nullptr;
     if (b->d_items.upload(b->items, st) != hipSuccess || b->d_items_split.upload(b->items_split, st) != hipSuccess ||
+        b->d_items_wide.upload(b->items_wide, st) != hipSuccess ||
         b->d_lists.upload(flat, st) != hipSuccess || b->d_reduce.upload(b->reduce, st) != hipSuccess ||
         b->d_counter.alloc(1) != hipSuccess || b->d_ctxs.alloc(n) != hipSuccess ||
         b->d_ztab.alloc(kMaxKPerLaunch * 27) != hipSuccess ||
@@ -1152,6 +1212,13 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
                 }
                 e = launch_contract_persistent(b->q[k], b->max_l, b->d_ctxs.p, b->d_items.p + b->item_off[k], cnt,
                                                b->d_counter.p, b->grid_f64[k], b->lds_f64[k], b->cap);
+            }
+            if (e == hipSuccess && !b->items_wide.empty()) {
+                if (b->lds_wide > kMaxDynLds) e = hipErrorInvalidValue;
+                else
+                    e = launch_contract_wide_persistent(b->max_l, b->d_ctxs.p, b->d_items_wide.p,
+                                                        (int)b->items_wide.size(), b->d_counter.p, b->grid_wide,
+                                                        b->lds_wide, b->cap);
             }
         } else {
             const int k = precision == PUFE_PREC_BF16X3 ? 0 : 1;

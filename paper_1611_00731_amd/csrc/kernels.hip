@@ -156,7 +156,8 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 //                   points: sqrt(w/2) d_x phi, sqrt(w/2) d_y phi,
 //                   sqrt(w/2) d_z phi, sqrt(w) phi
 //   sV[2][Q]        V at the stage points, two buffers for alternate stages
-//   sPsi[f][4][Q]   (value, gradient) of the element's enrichment functions
+//   sPsi[f][FS]     (value, gradient) of the element's enrichment functions,
+//                   component c of function f at f FS + c Q
 //   sGeo[GEO][Q]    per-point geometry, one field after the other
 //   sImg, sG, sEd   image centres, groups, enriched-function table
 //   sLeaf, sPt, sGx leaf codes of the item, Gauss point digits, Gauss rule
@@ -164,16 +165,19 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 template <int Q>
 struct ContractLds {
     static constexpr int RS = 4 * Q + 2;  // row stride (doubles): 16-byte rows, offset banks
+    static constexpr int FS = 4 * Q + 2;  // enrichment-function stride (doubles): offset banks
     static constexpr int GEO = 40;        // doubles of geometry per point
     static __host__ __device__ size_t bytes(int rows, int nfun, int nimg, int nleaf, int n3) {
-        return sizeof(double) * ((size_t)rows * RS + 2 * (size_t)Q + (size_t)nfun * Q * 4 + (size_t)Q * GEO +
+        return sizeof(double) * ((size_t)rows * RS + 2 * (size_t)Q + (size_t)nfun * FS + (size_t)Q * GEO +
                                  (size_t)nimg * 3 + 2 * kMaxGauss) +
                sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * kMaxNloc +
                sizeof(uint32_t) * ((size_t)nleaf + n3 + rows + 16 + kMaxRowChunks + 4) + 64;
     }
 };
 
-constexpr int kContractThreads = 256;
+constexpr int kContractThreads = 256;    // narrow work groups: 4 waves
+constexpr int kWideWaves = 8;            // wide work groups (elements of more than 80 functions)
+constexpr int kWideQ = 16;               // stage length of the wide work groups
 
 // MFMAs of one stage for a wave owning NU tile pairs.  Every product sums
 // k = 4 consecutive points of one operand component (lane l supplies row
@@ -251,15 +255,22 @@ __device__ __forceinline__ void mfma_tail_dispatch(int mt, const double *sB, con
     }
 }
 
-template <int Q, int LMAX>
+// NW waves per work group: 4 (narrow: up to 4 tile pairs per wave, two
+// work groups per CU where LDS allows) or 8 (wide: up to 5 pairs per wave,
+// one work group of 2 waves per SIMD, for the large row and column blocks of
+// elements of many functions, which then evaluate their enrichment functions
+// and rows for fewer items).
+template <int Q, int LMAX, int NW = 4>
 __device__ __forceinline__ void contract_f64_item(
     const KParams &kpg, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial, double *smem,
     int rot) {
     constexpr int RS = ContractLds<Q>::RS;
+    constexpr int FS = ContractLds<Q>::FS;
     constexpr int GEO = ContractLds<Q>::GEO;
-    constexpr int NT = kContractThreads;
+    constexpr int NT = 64 * NW;
+    constexpr int NUMAX = NW == 4 ? 4 : 5;   // tile pairs per wave
     const KLocal kp = load_klocal(kpg);
     // The table pointers of a batched launch are read from memory, so the
     // compiler cannot tell that they address global memory; typed as such,
@@ -281,8 +292,8 @@ __device__ __forceinline__ void contract_f64_item(
     const uint32_t n3 = (uint32_t)kp.n3, n = (uint32_t)kp.n;
     double *sB = smem;                                        // [nrow][RS]
     double *sV = sB + (size_t)nrow * RS;                      // [2][Q], alternate stages
-    double *sPsi = sV + 2 * Q;                                // [nfun][Q][4]
-    double *sGeo = sPsi + (size_t)nfun * Q * 4;               // [Q][GEO]
+    double *sPsi = sV + 2 * Q;                                // [nfun][FS]
+    double *sGeo = sPsi + (size_t)nfun * FS;                  // [GEO][Q]
     double *sImg = sGeo + (size_t)Q * GEO;
     double *sGx = sImg + 3 * (size_t)nimg, *sGs = sGx + kMaxGauss;   // square roots of the 1D Gauss weights
     GroupDev *sG = (GroupDev *)(sGs + kMaxGauss);
@@ -351,11 +362,11 @@ __device__ __forceinline__ void contract_f64_item(
     const int ntail = nloc - 16 * (T - 1);
     // (compiled for enrichments up to l = 1 only: with l up to 3 the extra
     // accumulators would push the kernel into register spills)
-    constexpr bool kTail = LMAX <= 1;
+    constexpr bool kTail = LMAX <= 1 && NW == 4;
     const int tg = (kTail && whole && T >= 2) ? (ntail <= 4 ? 1 : (ntail <= 8 ? 2 : 0)) : 0;
     const int npairs = tg ? (T - 1) * T / 2 : (diag ? it.nI * (it.nI + 1) / 2 : it.nI * it.nJ);
-    const int vw = (wave - rot) & 3;
-    const int nu = npairs > vw ? (npairs - vw + 3) / 4 : 0;   // pairs of this wave (uniform)
+    const int vw = (wave - rot + NW) % NW;
+    const int nu = npairs > vw ? (npairs - vw + NW - 1) / NW : 0;   // pairs of this wave (uniform)
     constexpr int MAXT = 3;   // tail pairs per wave (at most 5 tail pairs per item)
     int mt = 0, tl_row[MAXT] = {0, 0, 0}, tl_I[MAXT] = {0, 0, 0};
     if (tg) {
@@ -386,10 +397,10 @@ __device__ __forceinline__ void contract_f64_item(
     double tH[MAXT][2], tS[MAXT][2];
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) tH[t][0] = tH[t][1] = tS[t][0] = tS[t][1] = 0.0;
-    int pr_row[4], pr_col[4], pr_I[4], pr_J[4];
+    int pr_row[NUMAX], pr_col[NUMAX], pr_I[NUMAX], pr_J[NUMAX];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int pidx = vw + 4 * u;
+    for (int u = 0; u < NUMAX; ++u) {
+        const int pidx = vw + NW * u;
         pr_row[u] = pr_col[u] = pr_I[u] = pr_J[u] = 0;
         if (u < nu) {
             int a, b;
@@ -411,9 +422,9 @@ __device__ __forceinline__ void contract_f64_item(
             }
         }
     }
-    double4_t accH[4], accS[4];
+    double4_t accH[NUMAX], accS[NUMAX];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NUMAX; ++u) {
         accH[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
         accS[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
     }
@@ -438,7 +449,7 @@ __device__ __forceinline__ void contract_f64_item(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
+            group_eval_upto<LMAX, Q, FS>(G, sImg, x, sPsi + (size_t)G.fbase * FS + q);
         }
     };
     __syncthreads();
@@ -480,7 +491,7 @@ __device__ __forceinline__ void contract_f64_item(
                     r[2 * Q] = z;
                     r[3 * Q] = w;
                 };
-                pu_unit<Q>(kp, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
+                pu_unit<Q, FS>(kp, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
             }
         } else {
             // partial items: the same geometry-sharing groups, the enriched
@@ -507,7 +518,7 @@ __device__ __forceinline__ void contract_f64_item(
                         fe_unit<Q, 2>(kp, sGeo + q, u & 1, u >> 1, put);
                 } else {
                     const int ch = sChunk[u - nfu];
-                    pu_unit<Q>(kp, sGeo + q, sPsi + q, sEd, ch & 7, (ch >> 3) & 1023, ch >> 13, nfe, put);
+                    pu_unit<Q, FS>(kp, sGeo + q, sPsi + q, sEd, ch & 7, (ch >> 3) & 1023, ch >> 13, nfe, put);
                 }
             }
         }
@@ -517,6 +528,7 @@ __device__ __forceinline__ void contract_f64_item(
         // only the rows and V, phase 1 writes the enrichment table, the
         // geometry and the other V buffer
         switch (nu) {
+            case 5: if (NUMAX >= 5) mfma_stage<Q, 5>(sB, sVc, pr_row, pr_col, r16, k4, accH, accS); break;
             case 4: mfma_stage<Q, 4>(sB, sVc, pr_row, pr_col, r16, k4, accH, accS); break;
             case 3: mfma_stage<Q, 3>(sB, sVc, pr_row, pr_col, r16, k4, accH, accS); break;
             case 2: mfma_stage<Q, 2>(sB, sVc, pr_row, pr_col, r16, k4, accH, accS); break;
@@ -554,7 +566,7 @@ __device__ __forceinline__ void contract_f64_item(
         }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NUMAX; ++u) {
         if (u >= nu) continue;
         const int64_t pidx = (int64_t)pr_J[u] * (pr_J[u] + 1) / 2 + pr_I[u];
         PUFE_GLOBAL double *dst = gPartial + (el.part_base + (int64_t)it.chunk * P + pidx) * 512;
@@ -597,6 +609,37 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
         contract_f64_item<Q, LMAX>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem, idx & 3);
+    }
+}
+
+// Wide work groups (8 waves, one per CU) for the items of elements of more
+// than 80 functions.
+template <int LMAX>
+__global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_wide_kernel(
+    const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
+    const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
+    const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
+    extern __shared__ __attribute__((aligned(16))) double smem[];
+    const ItemDev it = items[blockIdx.x];
+    contract_f64_item<kWideQ, LMAX, kWideWaves>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
+                                                blockIdx.x & 7);
+}
+
+template <int LMAX>
+__global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_wide_persistent(
+    const CtxDev *__restrict__ ctxs, const ItemDev *__restrict__ items, int n_items, int *__restrict__ counter) {
+    extern __shared__ __attribute__((aligned(16))) double smem[];
+    __shared__ int s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= n_items) break;
+        const ItemDev it = items[idx];
+        const CtxDev &c = ctxs[it.ctx];
+        contract_f64_item<kWideQ, LMAX, kWideWaves>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V,
+                                                    c.partial, smem, idx & 7);
     }
 }
 
@@ -930,7 +973,41 @@ hipError_t init_contract_attributes() {
                           (const void *)contract_f64_persistent<24, 1>, (const void *)contract_f64_persistent<24, 3>,
                           (const void *)contract_f64_persistent<32, 1>, (const void *)contract_f64_persistent<32, 3>};
     for (const void *k : ks) PUFE_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
+    const void *kw[4] = {(const void *)contract_f64_wide_kernel<1>, (const void *)contract_f64_wide_kernel<3>,
+                         (const void *)contract_f64_wide_persistent<1>, (const void *)contract_f64_wide_persistent<3>};
+    for (const void *k : kw) PUFE_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
     return hipSuccess;
+}
+
+size_t contract_wide_lds_bytes(int rows, int nfun, int nimg, int nleaf, int n3) {
+    return ContractLds<kWideQ>::bytes(rows, nfun, nimg, nleaf, n3);
+}
+
+hipError_t launch_contract_wide(int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+                                const GroupDev *groups, const double *img, const int32_t *edof, const uint32_t *leaves,
+                                const double *V, double *partial, size_t lds, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    if (lmax <= 1)
+        hipLaunchKernelGGL((contract_f64_wide_kernel<1>), dim3(n_items), dim3(64 * kWideWaves), lds, st, kp, items,
+                           elems, groups, img, edof, leaves, V, partial);
+    else
+        hipLaunchKernelGGL((contract_f64_wide_kernel<3>), dim3(n_items), dim3(64 * kWideWaves), lds, st, kp, items,
+                           elems, groups, img, edof, leaves, V, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_wide_persistent(int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items,
+                                           int *counter, int grid, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
+    PUFE_HIP(hipGetLastError());
+    if (n_items == 0) return hipSuccess;
+    if (lmax <= 1)
+        hipLaunchKernelGGL((contract_f64_wide_persistent<1>), dim3(grid), dim3(64 * kWideWaves), lds, st, ctxs, items,
+                           n_items, counter);
+    else
+        hipLaunchKernelGGL((contract_f64_wide_persistent<3>), dim3(grid), dim3(64 * kWideWaves), lds, st, ctxs, items,
+                           n_items, counter);
+    return hipGetLastError();
 }
 
 int persistent_blocks_per_cu(size_t lds) {

@@ -32,6 +32,16 @@ hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, 
                                const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st);
+// Wide contraction (8-wave work groups, one per CU) for the items of elements
+// of more than kWholeMaxTiles tiles.
+constexpr int kWholeMaxTiles = 5;   // elements of at most 80 functions: whole-element narrow items
+constexpr int kWideTiles = 6;       // tile block of the wide items
+size_t contract_wide_lds_bytes(int rows, int nfun, int nimg, int nleaf, int n3);
+hipError_t launch_contract_wide(int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+                                const GroupDev *groups, const double *img, const int32_t *edof, const uint32_t *leaves,
+                                const double *V, double *partial, size_t lds, hipStream_t st);
+hipError_t launch_contract_wide_persistent(int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items,
+                                           int *counter, int grid, size_t lds, hipStream_t st);
 size_t split_lds_bytes(int nlimb, int rows, int nfun, int nimg, int nleaf, int n3);
 hipError_t launch_contract_split(int nlimb, int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
                                  const GroupDev *groups, const double *img, const int32_t *edof,

@@ -19,15 +19,16 @@ namespace pufe {
 //   D[d][0..2], trilinear PU values M_c and their 1D factors m_d^0, m_d^1.
 enum { G_XI = 0, G_X = 3, G_SW2 = 6, G_SW = 7, G_L = 8, G_D = 17, G_M = 26, G_M1 = 34 };
 
-// Enrichment functions of one group at one point, for groups up to LMAX.
-template <int LMAX, int Q>
+// Enrichment functions of one group at one point, for groups up to LMAX;
+// function m of the group at o[m * FS], component c at o[m * FS + c * Q].
+template <int LMAX, int Q, int FS = 4 * Q>
 __device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double *__restrict__ img, const double *x,
                                                 double *o) {
     switch (G.l) {
-        case 0: group_eval<0, 4 * Q, Q>(G, img, x, o); break;
-        case 1: if (LMAX >= 1) group_eval<1, 4 * Q, Q>(G, img, x, o); break;
-        case 2: if (LMAX >= 2) group_eval<2, 4 * Q, Q>(G, img, x, o); break;
-        default: if (LMAX >= 3) group_eval<3, 4 * Q, Q>(G, img, x, o); break;
+        case 0: group_eval<0, FS, Q>(G, img, x, o); break;
+        case 1: if (LMAX >= 1) group_eval<1, FS, Q>(G, img, x, o); break;
+        case 2: if (LMAX >= 2) group_eval<2, FS, Q>(G, img, x, o); break;
+        default: if (LMAX >= 3) group_eval<3, FS, Q>(G, img, x, o); break;
     }
 }
 
@@ -220,8 +221,8 @@ __device__ __forceinline__ void fe_unit(const KLocal &kp, const double *g, int a
 // pu_unit: the enriched functions M_c Psi_f of PU corner c, entries
 // kb .. ke - 1 of the element's enriched table (local functions nfe + k);
 // ps points to the element's enrichment table at the point (function f,
-// component c at ps[(PS f + c) * Q], value and gradient first).
-template <int Q, int PS = 4, bool MASKED = false, class Out>
+// component c at ps[FS f + c Q], value and gradient first).
+template <int Q, int FS = 4 * Q, bool MASKED = false, class Out>
 __device__ __forceinline__ void pu_unit(const KLocal &kp, const double *g, const double *ps, const int32_t *sEd, int c,
                                         int kb, int ke, int nfe, Out &&out) {
     double s2, sw;
@@ -238,7 +239,7 @@ __device__ __forceinline__ void pu_unit(const KLocal &kp, const double *g, const
     const double sM = s2 * M, wM = sw * M;
     for (int k = kb; k < ke; ++k) {
         const int f = (sEd[k] >> 3) & 255;
-        const double *pf = ps + (size_t)f * PS * Q;
+        const double *pf = ps + (size_t)f * FS;
         const double p0 = pf[0], p1 = pf[Q], p2 = pf[2 * Q], p3 = pf[3 * Q];
         out(nfe + k, jm[0] * p0 + sM * p1, jm[1] * p0 + sM * p2, jm[2] * p0 + sM * p3, wM * p0);
     }
