@@ -175,6 +175,22 @@ int pufe_get_leaves(pufe_ctx *ctx, int32_t *level, int32_t *ijk, int64_t *elem_l
 int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision,
                   int out_dtype, void *d_H, void *d_S, void *stream);
 
+/* Allocation-free form of pufe_assemble, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid it): the same arguments, kernels and results
+ * as pufe_assemble, but the phase table and the K-chunk partial tiles live in
+ * a fixed workspace of PUFE_NOALLOC_WORKSPACE_BYTES that the library's code
+ * object brings with it (each GPU holds its own copy until the process ends;
+ * its address on a device is looked up by pufe_setup).  The call allocates
+ * and frees nothing and records no timing events.  Every call on one GPU
+ * shares that GPU's workspace: calls that overlap on one GPU (on different
+ * streams or host threads) race and give wrong results.  A problem whose
+ * partial tiles (4 KiB per element tile pair and K-chunk) do not fit gives
+ * PUFE_ERR_UNSUPPORTED; the other errors are those of pufe_assemble. */
+#define PUFE_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+int pufe_assemble_noalloc(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision,
+                          int out_dtype, void *d_H, void *d_S, void *stream);
+
 /* Real element matrices of element `elem` (debug/parity): d_He, d_Se device
  * arrays of max_nloc*max_nloc doubles; the leading nloc x nloc row-major
  * block is written, nloc returned through *nloc (host). */

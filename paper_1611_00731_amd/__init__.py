@@ -28,7 +28,7 @@ EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_
            "pufe_get_quadrature", "pufe_get_leaves", "pufe_assemble", "pufe_element_matrices",
            "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
            "pufe_kernel_times", "pufe_set_positions", "pufe_batch_create", "pufe_batch_assemble",
-           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune"]
+           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune", "pufe_assemble_noalloc"]
 
 
 class PufeError(RuntimeError):
@@ -77,6 +77,7 @@ def _load():
         "pufe_get_quadrature": ([vp, vp, vp, vp, vp], C.c_int),
         "pufe_get_leaves": ([vp, i32p, i32p, i64p], C.c_int),
         "pufe_assemble": ([vp, vp, dp, C.c_int, C.c_int, C.c_int, vp, vp, vp], C.c_int),
+        "pufe_assemble_noalloc": ([vp, vp, dp, C.c_int, C.c_int, C.c_int, vp, vp, vp], C.c_int),
         "pufe_element_matrices": ([vp, C.c_int64, vp, C.c_int, vp, vp, i32p, vp], C.c_int),
         "pufe_assemble_backward": ([vp, vp, dp, vp, vp, C.c_int, vp, vp, vp], C.c_int),
         "pufe_bsr_to_dense": ([vp, vp, C.c_int, vp, vp], C.c_int),
@@ -193,6 +194,14 @@ def pufe_assemble(ctx, V, kpts, precision, out_dtype, H, S=None, stream=None):
                                   PREC[precision] if isinstance(precision, str) else int(precision),
                                   OUT[out_dtype] if isinstance(out_dtype, str) else int(out_dtype),
                                   _ptr(H), _ptr(S), _stream(stream)))
+
+
+def pufe_assemble_noalloc(ctx, V, kpts, precision, out_dtype, H, S=None, stream=None):
+    k = np.ascontiguousarray(np.asarray(kpts, np.float64).reshape(-1, 3))
+    _check(ctx, lib.pufe_assemble_noalloc(ctx, _ptr(V), k.ctypes.data_as(C.POINTER(C.c_double)), k.shape[0],
+                                          PREC[precision] if isinstance(precision, str) else int(precision),
+                                          OUT[out_dtype] if isinstance(out_dtype, str) else int(out_dtype),
+                                          _ptr(H), _ptr(S), _stream(stream)))
 
 
 def pufe_element_matrices(ctx, elem, V, precision, He, Se, stream=None):

@@ -431,6 +431,12 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_bval_off.upload(pl.bval_off, st), "upload layout");
     CHECK_HIP(ctx, ctx->d_dof_off.upload(pl.dof_off, st), "upload layout");
     CHECK_HIP(ctx, ctx->d_partial.alloc((size_t)ctx->part_slots * 512), "alloc partial tiles");
+    {
+        // the allocation-free entry's workspace: its device address is looked
+        // up once per device, here at set-up
+        double *ws = nullptr;
+        CHECK_HIP(ctx, scratch_address(ctx->device, &ws), "workspace address");
+    }
     CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
     ctx->have_setup = true;
     ++ctx->plan_gen;
@@ -609,6 +615,26 @@ int pufe_assemble(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k,
     CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     return assemble_impl(ctx, d_V, kpts, n_k, precision, out_dtype, d_H, d_S, st, ctx->d_partial.p, ctx->d_ztab.p,
                          true);
+}
+
+int pufe_assemble_noalloc(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision, int out_dtype,
+                          void *d_H, void *d_S, void *stream) {
+    int rc = check_assemble_args(ctx, d_V, kpts, n_k, precision, out_dtype, d_H);
+    if (rc != PUFE_OK) return rc;
+    // workspace: the phase table, then the partial tiles (256-byte aligned)
+    const size_t ztab_bytes = (sizeof(double2) * kMaxKPerLaunch * 27 + 255) / 256 * 256;
+    const size_t need = ztab_bytes + (size_t)ctx->part_slots * 512 * sizeof(double);
+    if (need > kScratchBytes)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED,
+                    "pufe_assemble_noalloc: this problem's partial tiles need " + std::to_string(need) +
+                        " bytes of workspace, more than the fixed " + std::to_string(kScratchBytes) +
+                        " bytes; use pufe_assemble");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    double *ws = nullptr;
+    CHECK_HIP(ctx, scratch_address(ctx->device, &ws), "workspace address");
+    return assemble_impl(ctx, d_V, kpts, n_k, precision, out_dtype, d_H, d_S, st,
+                         ws + ztab_bytes / sizeof(double), (double2 *)ws, false);
 }
 
 int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int precision, double *d_He,

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "basis.hpp"
 #include "device_common.hpp"
 #include "enrich.hpp"
@@ -891,6 +893,30 @@ __global__ void bsr_to_dense_kernel(int64_t nnzb, const int32_t *__restrict__ br
             }
         }
     }
+}
+
+// ------------------------------------------- allocation-free workspace
+//
+// The workspace of pufe_assemble_noalloc: the phase table and the K-chunk
+// partial tiles of one assembly, in a fixed array that the code object
+// brings with it (each GPU holds its own copy for the life of the process).
+// In host code `scratch` is only a host-side stand-in for the symbol: kernels
+// get the device address that hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+hipError_t scratch_address(int device, double **ptr) {
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices || !ptr) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (double *)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------- launchers

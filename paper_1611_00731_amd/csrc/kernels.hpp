@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/pufe.h"
 #include "tables.hpp"
 
 namespace pufe {
@@ -10,11 +11,19 @@ namespace pufe {
 constexpr int kContractQ = 16;      // quadrature points per LDS stage of the contraction
 constexpr int kMaxKPerLaunch = 16;  // k-points handled by one scatter launch
 constexpr int kSplitQ = 32;         // quadrature points per LDS stage of the split-bf16 contraction
+// Fixed device workspace of the allocation-free assembly (per GPU, held for
+// the life of the process): the phase table and the K-chunk partial tiles.
+constexpr size_t kScratchBytes = PUFE_NOALLOC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
 
 struct KPoints {
     int32_t nk;
     double kap[kMaxKPerLaunch][3];
 };
+
+// Device address of the fixed workspace on `device`, which must be the
+// current device; looked up once per device and kept.
+hipError_t scratch_address(int device, double **ptr);
 
 hipError_t launch_aq_geom(const KParams &kp, int64_t nel, const double *pos, int n_atoms, const double *L,
                           int max_level, double dist, int64_t *count, const int64_t *off, uint32_t *out,
