@@ -143,6 +143,20 @@ int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], 
  * The rule is built once per geometry and reused by every assembly. */
 int pufe_setup(pufe_ctx *ctx, void *stream);
 
+/* Replace the quadrature rule built by pufe_setup with a given one (debug
+ * and parity use: it lets two implementations of the error-driven rule of
+ * section "Adaptive quadrature", whose refinement decisions can flip where an
+ * error estimate sits at the tolerance, assemble on one shared rule).  Host
+ * arrays in the layout of pufe_get_leaves: level[n_leaves] (0..8),
+ * ijk[n_leaves*3] cell coordinates at that level, elem_leaf_offset[n_elem+1]
+ * (canonical leaf order inside an element: depth first, children
+ * c = c1 + 2 c2 + 4 c3).  The leaves of each element must cover its reference
+ * cube exactly once.  Re-plans the work items (a batch created before must be
+ * created anew).  Synchronous.  Errors: PUFE_ERR_STATE before pufe_setup,
+ * PUFE_ERR_INVALID_ARG for malformed leaves. */
+int pufe_set_rule(pufe_ctx *ctx, int64_t n_leaves, const int32_t *level, const int32_t *ijk,
+                  const int64_t *elem_leaf_offset, void *stream);
+
 /* Sizes (host).  Valid after pufe_set_problem; n_qp and n_leaves after setup. */
 int pufe_query(pufe_ctx *ctx, pufe_sizes *out);
 

@@ -28,7 +28,7 @@ EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_
            "pufe_get_quadrature", "pufe_get_leaves", "pufe_assemble", "pufe_element_matrices",
            "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
            "pufe_kernel_times", "pufe_set_positions", "pufe_batch_create", "pufe_batch_assemble",
-           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune", "pufe_assemble_noalloc"]
+           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune", "pufe_assemble_noalloc", "pufe_set_rule"]
 
 
 class PufeError(RuntimeError):
@@ -78,6 +78,7 @@ def _load():
         "pufe_get_leaves": ([vp, i32p, i32p, i64p], C.c_int),
         "pufe_assemble": ([vp, vp, dp, C.c_int, C.c_int, C.c_int, vp, vp, vp], C.c_int),
         "pufe_assemble_noalloc": ([vp, vp, dp, C.c_int, C.c_int, C.c_int, vp, vp, vp], C.c_int),
+        "pufe_set_rule": ([vp, C.c_int64, i32p, i32p, i64p, vp], C.c_int),
         "pufe_element_matrices": ([vp, C.c_int64, vp, C.c_int, vp, vp, i32p, vp], C.c_int),
         "pufe_assemble_backward": ([vp, vp, dp, vp, vp, C.c_int, vp, vp, vp], C.c_int),
         "pufe_bsr_to_dense": ([vp, vp, C.c_int, vp, vp], C.c_int),
@@ -186,6 +187,15 @@ def pufe_get_leaves(ctx):
     _check(ctx, lib.pufe_get_leaves(ctx, lev.ctypes.data_as(i32p), ijk.ctypes.data_as(i32p),
                                     off.ctypes.data_as(i64p)))
     return lev[:n], ijk[:3 * n].reshape(-1, 3), off
+
+
+def pufe_set_rule(ctx, level, ijk, elem_leaf_offset, stream=None):
+    lev = np.ascontiguousarray(np.asarray(level, np.int32))
+    c = np.ascontiguousarray(np.asarray(ijk, np.int32).reshape(-1))
+    off = np.ascontiguousarray(np.asarray(elem_leaf_offset, np.int64))
+    i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    _check(ctx, lib.pufe_set_rule(ctx, lev.size, lev.ctypes.data_as(i32p), c.ctypes.data_as(i32p),
+                                  off.ctypes.data_as(i64p), _stream(stream)))
 
 
 def pufe_assemble(ctx, V, kpts, precision, out_dtype, H, S=None, stream=None):
@@ -305,6 +315,10 @@ class Problem:
 
     def layout(self):
         return pufe_get_layout(self.ctx)
+
+    def set_rule(self, level, ijk, elem_leaf_offset):
+        pufe_set_rule(self.ctx, level, ijk, elem_leaf_offset)
+        self.sizes = pufe_query(self.ctx)
 
     def leaves(self):
         return pufe_get_leaves(self.ctx)

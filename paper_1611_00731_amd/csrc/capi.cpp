@@ -331,6 +331,8 @@ static void plan_items(pufe_ctx *c, double target_items, int block_tiles) {
     }
 }
 
+static int upload_items(pufe_ctx *ctx, hipStream_t st);
+
 int pufe_setup(pufe_ctx *ctx, void *stream) {
     if (!ctx) return PUFE_ERR_INVALID_ARG;
     if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "pufe_set_problem must come first");
@@ -441,6 +443,60 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     ctx->have_setup = true;
     ++ctx->plan_gen;
     return PUFE_OK;
+}
+
+int pufe_set_rule(pufe_ctx *ctx, int64_t n_leaves, const int32_t *level, const int32_t *ijk,
+                  const int64_t *elem_leaf_offset, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    Plan &pl = ctx->plan;
+    const int64_t nel = pl.nel;
+    if (n_leaves < nel || !level || !ijk || !elem_leaf_offset)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer or fewer leaves than elements");
+    if (elem_leaf_offset[0] != 0 || elem_leaf_offset[nel] != n_leaves)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "leaf offsets must run from 0 to n_leaves");
+    std::vector<uint32_t> codes(n_leaves);
+    std::vector<int32_t> lelem(n_leaves);
+    for (int64_t e = 0; e < nel; ++e) {
+        const int64_t b = elem_leaf_offset[e], en = elem_leaf_offset[e + 1];
+        if (en <= b) return fail(ctx, PUFE_ERR_INVALID_ARG, "every element needs at least one leaf");
+        // the leaves of an element tile its reference cube: their volumes,
+        // in units of the finest cell, add up to the whole
+        int64_t vol = 0;
+        for (int64_t k = b; k < en; ++k) {
+            const int lev = level[k];
+            if (lev < 0 || lev > kMaxLevel) return fail(ctx, PUFE_ERR_INVALID_ARG, "leaf level outside 0..8");
+            for (int d = 0; d < 3; ++d)
+                if (ijk[3 * k + d] < 0 || ijk[3 * k + d] >= (1 << lev))
+                    return fail(ctx, PUFE_ERR_INVALID_ARG, "leaf coordinate outside its level's range");
+            vol += (int64_t)1 << (3 * (kMaxLevel - lev));
+            codes[k] = leaf_pack(lev, ijk[3 * k], ijk[3 * k + 1], ijk[3 * k + 2]);
+            lelem[k] = (int32_t)e;
+        }
+        if (vol != (int64_t)1 << (3 * kMaxLevel))
+            return fail(ctx, PUFE_ERR_INVALID_ARG, "the leaves of an element do not cover its cell once");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
+    CHECK_HIP(ctx, ctx->d_leaves.alloc(n_leaves), "alloc leaves");
+    CHECK_HIP(ctx, ctx->d_leaf_elem.alloc(n_leaves), "alloc leaf elements");
+    CHECK_HIP(ctx, hipMemcpy(ctx->d_leaves.p, codes.data(), sizeof(uint32_t) * n_leaves, hipMemcpyHostToDevice),
+              "upload leaves");
+    CHECK_HIP(ctx, hipMemcpy(ctx->d_leaf_elem.p, lelem.data(), sizeof(int32_t) * n_leaves, hipMemcpyHostToDevice),
+              "upload leaf elements");
+    ctx->leaf_off_h.assign(elem_leaf_offset, elem_leaf_offset + nel + 1);
+    CHECK_HIP(ctx, hipMemcpy(ctx->d_leaf_off.p, ctx->leaf_off_h.data(), sizeof(int64_t) * (nel + 1),
+                             hipMemcpyHostToDevice), "upload leaf offsets");
+    ctx->n_leaves = n_leaves;
+    ctx->n_qp = n_leaves * pl.kp.n3;
+    for (int64_t e = 0; e < nel; ++e) {
+        pl.elems[e].leaf_off = ctx->leaf_off_h[e];
+        pl.elems[e].leaf_end = ctx->leaf_off_h[e + 1];
+    }
+    plan_items(ctx, ctx->tune_items, ctx->tune_block);
+    if (ctx->lds > kMaxDynLds) return fail(ctx, PUFE_ERR_UNSUPPORTED, "contraction stage does not fit in LDS");
+    return upload_items(ctx, nullptr);
 }
 
 int pufe_query(pufe_ctx *ctx, pufe_sizes *out) {

@@ -45,6 +45,7 @@ def test_input_validation():
     try:
         _expect(-5, lambda: P.pufe_setup(ctx, stream=type("S", (), {"cuda_stream": 0})()))
         _expect(-5, lambda: P.pufe_query(ctx))
+        _expect(-5, lambda: P.pufe_set_rule(ctx, [0], [[0, 0, 0]], [0, 1], stream=type("S", (), {"cuda_stream": 0})()))
         _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [1, 2, 2], 1, base["atoms"],
                                                base["species"], base["enrichments"], base["quad"]))
         _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 3, base["atoms"],

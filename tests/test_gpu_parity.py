@@ -332,8 +332,9 @@ def test_random_small_problems(seed):
         Ho, So = o.assemble_dense(V, kap)
         assert rel(p.to_dense(H[k]).cpu().numpy(), Ho) < TOL, (seed, kap)
         assert rel(p.to_dense(S[k]).cpu().numpy(), So) < TOL, (seed, kap)
-        assert rel(p.to_dense(Hs[k]).cpu().numpy(), Ho) < 1e-7, (seed, kap)
-        assert rel(p.to_dense(Ss[k]).cpu().numpy(), So) < 1e-7, (seed, kap)
+        eh, es = rel(p.to_dense(Hs[k]).cpu().numpy(), Ho), rel(p.to_dense(Ss[k]).cpu().numpy(), So)
+        say("bf16x6", seed, k, "H", eh, "S", es)
+        assert eh < 1e-7 and es < 1e-7, (seed, kap)
     p.close()
 
 
@@ -436,4 +437,73 @@ def test_ceal_cell_deepest_elements_fp64_and_split():
         Sg = (Sh[b0:b1, 0] + 1j * Sh[b0:b1, 1]).reshape(shape)
         say("bf16x6 block", v, wv, shape, rel(Hg, Hb), rel(Sg, Sb))
         assert rel(Hg, Hb) < 1e-7 and rel(Sg, Sb) < 1e-7, (v, wv)
+    p.close()
+
+
+def _rule_cells(lev, ijk, loff):
+    """Leaves and internal cells of every element's octree, as sets of (e, level, c1, c2, c3)."""
+    leaves, internal = set(), set()
+    for e in range(len(loff) - 1):
+        for k in range(loff[e], loff[e + 1]):
+            l, c = int(lev[k]), tuple(int(x) for x in ijk[k])
+            leaves.add((e, l) + c)
+            for up in range(1, l + 1):
+                internal.add((e, l - up) + tuple(x >> up for x in c))
+    return leaves, internal
+
+
+# Tie margin of the error-driven rule: two implementations may decide a cell
+# differently only where one of its error estimates |Q_n - Q_ref| lies within
+# this absolute distance of the tolerance (the estimates are differences of
+# O(1) sums and agree to ~1e-15 between the two).
+RULE_TIE = 1e-9
+
+
+ERROR_CASES = {
+    "lih-error": SMALL["lih-error"],
+    "ceal-error": SMALL["ceal-error"],
+    # the paper's triclinic CeAl cell (skewed element maps) at a small mesh
+    "ceal-triclinic": (lambda: W.ceal_triclinic(mesh=3, levels=2, n=3, n_ref=5, tol=1e-4), W.PAPER_KPTS),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ERROR_CASES))
+def test_error_rule_ties_and_assembly_on_one_shared_rule(name):
+    """The error-driven rule (section "Adaptive quadrature") built on the GPU
+    against the oracle's: any cell decided differently must be a tie (an
+    error estimate within RULE_TIE of the tolerance); then the library
+    assembles on the oracle's own rule (pufe_set_rule) and H, S match the
+    oracle at 1e-12."""
+    from test_oracle_pins_rule import _cell_errors, _element_functions
+    make, kpts = ERROR_CASES[name]
+    prob = make()
+    q = prob["quad"]
+    say("error rule ties + shared rule", name)
+    o, xyz, w, off, V = oracle_inputs(prob)
+    p = P.Problem(prob).setup()
+    glev, gijk, goff = P.pufe_get_leaves(p.ctx)
+    olev, oijk, ooff = o.leaves()
+    gl, gi = _rule_cells(glev, gijk, goff)
+    ol, oi = _rule_cells(olev, oijk, ooff)
+    decided = (gl & oi) | (ol & gi)   # a leaf in one rule, split in the other
+    for (e, l, *c) in sorted(decided):
+        near = min(min(abs(x - q["tol"]) for x in _cell_errors(o, prob, e, l, c, fn, q["n"], q["n_ref"]))
+                   for fn in _element_functions(o, prob, e))
+        assert near <= RULE_TIE, (name, e, l, c, near)
+    say("cells decided differently", len(decided))
+    p.set_rule(olev, oijk, ooff)
+    assert p.sizes["n_qp"] == o.n_qp
+    Vd = torch.from_numpy(V).cuda()
+    for kap in kpts:
+        Ho, So = o.assemble_dense(V, kap)
+        for prec, tol in (("fp64", TOL), ("bf16x6", 1e-7)):
+            H, S = p.assemble(Vd, [kap], precision=prec)
+            eh, es = rel(p.to_dense(H[0]).cpu().numpy(), Ho), rel(p.to_dense(S[0]).cpu().numpy(), So)
+            say(name, prec, kap, "H", eh, "S", es)
+            assert eh < tol and es < tol, (prec, kap)
+    # a malformed rule is refused: drop one leaf of the first element
+    with pytest.raises(P.PufeError):
+        bad = ooff.copy()
+        bad[1:] -= 1
+        P.pufe_set_rule(p.ctx, np.delete(olev, 0), np.delete(oijk, 0, axis=0), bad)
     p.close()

@@ -31,6 +31,7 @@ import numpy as np
 
 __all__ = [
     "single_atom_cube", "lih_cell", "lih_lattice_sweep", "ceal_cell", "lih_supercell", "small", "lih_table1",
+    "ceal_triclinic", "PAPER_KPTS",
     "mp2", "ceal_kpoints", "jitter", "adjoint_factor", "with_lattice_constant",
     "orthorhombic", "random_small",
 ]
@@ -190,6 +191,36 @@ def ceal_cell():
         enr,
         {"n": 8, "n_ref": 10, "levels": 3, "mode": "geom", "dist": 1.0, "tol": 1e-6},
         ceal_kpoints(), 16, "ceal_cell")
+
+
+# The two k-points of the paper's LiH and CeAl runs, read as reduced
+# coordinates (section "Self-consistent calculations").
+PAPER_KPTS = [[0.0, 0.0, 0.0], [0.12, -0.24, 0.37]]
+
+
+def ceal_triclinic(mesh: int = 12, levels: int = 2, n: int = 6, n_ref: int = 8, tol: float = 1e-5):
+    """The paper's triclinic CeAl cell (eq. ceal-primitive): primitive vectors
+    a (1.00, 0.02, -0.04), a (0.01, 0.98, 0.03), a (0.03, -0.06, 1.09), a = 5.75
+    bohr, Ce at (0.01, 0.02, 0.03) and Al at (0.51, 0.47, 0.55) in lattice
+    coordinates; its two k-points.  Skewed element maps, so the rule is the
+    paper's error-driven one (base n^3 against reference n_ref^3 Gauss on
+    Psi^2 and |grad Psi|^2, absolute tolerance tol, up to `levels` levels).
+    The enrichments, potential and radial functions are those of the
+    CeAl-like cell (the paper's own need its pseudopotential tables)."""
+    a = 5.75
+    lat = a * np.array([[1.00, 0.02, -0.04], [0.01, 0.98, 0.03], [0.03, -0.06, 1.09]])
+    red = np.array([[0.01, 0.02, 0.03], [0.51, 0.47, 0.55]])
+    enr = []
+    for l in range(4):
+        for ex in (3.0, 0.4):
+            enr.append({"species": 0, "l": l, "a": ex, "rc": 4.0, "re": 2.5})
+    for l in range(3):
+        enr.append({"species": 1, "l": l, "a": 0.6, "rc": 4.0, "re": 2.5})
+    return _problem(
+        lat, [mesh] * 3, 2, red @ lat, [0, 1],
+        [{"name": "Ce", "Z": 12.0, "rloc": 0.3}, {"name": "Al", "Z": 3.0, "rloc": 0.3}],
+        enr, {"n": n, "n_ref": n_ref, "levels": levels, "mode": "error", "dist": 0.0, "tol": tol},
+        copy.deepcopy(PAPER_KPTS), 16, f"ceal_triclinic-{mesh}")
 
 
 def lih_supercell():
