@@ -79,6 +79,9 @@ def lib():
         L.or_lagrange.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]
         L.or_solid_harmonic.argtypes = [C.c_int, C.c_int, _f64p, _f64p, _f64p, _f64p]
+        L.or_nonlocal_f.argtypes = [C.c_void_p, _f64p, C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_void_p]
+        L.or_nonlocal_f.restype = C.c_int
+        L.or_nonlocal_dense.argtypes = [C.c_void_p, _f64p, C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
         L.or_pattern_nnz.argtypes = [C.c_void_p]
         L.or_pattern_nnz.restype = C.c_int64
         _lib = L
@@ -243,6 +246,32 @@ class Oracle:
         h = np.zeros(9)
         lib().or_enrichment(self.h, atom, desc, m, np.asarray(x, np.float64), v, g, h)
         return v[0], g, h.reshape(3, 3)
+
+    def _projectors(self, projectors):
+        pr = list(projectors if projectors is not None else self.prob.get("projectors", []))
+        sp = np.array([q["species"] for q in pr] + [0], np.int32)
+        ll = np.array([q["l"] for q in pr] + [0], np.int32)
+        aa = np.array([q["a"] for q in pr] + [0], np.float64)
+        rc = np.array([q["rc"] for q in pr] + [0], np.float64)
+        hh = np.array([q["h"] for q in pr] + [0], np.float64)
+        return len(pr), sp, ll, aa, rc, hh
+
+    def nonlocal_f(self, kappa=(0.0, 0.0, 0.0), projectors=None):
+        """f_J^i of the separable nonlocal term (n_fun x N complex)."""
+        n, sp, ll, aa, rc, _ = self._projectors(projectors)
+        k = np.asarray(kappa, np.float64)
+        nf = lib().or_nonlocal_f(self.h, k, n, sp, ll, aa, rc, None)
+        F = np.zeros((max(nf, 1), self.n_dof, 2))
+        lib().or_nonlocal_f(self.h, k, n, sp, ll, aa, rc, F.ctypes.data)
+        return (F[..., 0] + 1j * F[..., 1])[:nf]
+
+    def nonlocal_dense(self, kappa=(0.0, 0.0, 0.0), projectors=None):
+        """The N x N separable nonlocal term sum_J h_J f_J^i conj(f_J^j)."""
+        n, sp, ll, aa, rc, hh = self._projectors(projectors)
+        N = self.n_dof
+        Vn = np.zeros((N, N, 2))
+        lib().or_nonlocal_dense(self.h, np.asarray(kappa, np.float64), n, sp, ll, aa, rc, hh, Vn)
+        return Vn[..., 0] + 1j * Vn[..., 1]
 
     def pattern_nnz(self):
         return int(lib().or_pattern_nnz(self.h))

@@ -1100,3 +1100,135 @@ int64_t or_pattern_nnz(const or_state *s) {
     free(L);
     return nnz;
 }
+
+/* ------------------------------------------- separable nonlocal potential */
+
+/* Projector function of descriptor d (2l+1 of them, m = -l..l) centred at
+ * the origin: v(r) = exp(-a |r|^2) (1 - |r|^2/rc^2)^3 S_lm(r) for |r| < rc,
+ * 0 beyond (the radial form of the enrichment descriptors; synthetic stand-ins
+ * for the projectors of a separable pseudopotential). */
+static double projector_value(int l, int m, double a, double rc, const double *r) {
+    double sq = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    if (sq >= rc * rc) return 0.0;
+    double c = 1.0 - sq / (rc * rc), S;
+    or_solid_harmonic(l, m, r, &S, NULL, NULL);
+    return exp(-a * sq) * c * c * c * S;
+}
+
+/* Coefficients of the separable nonlocal term (eq. disceig3d):
+ *   f_J^i = int_cell phi_i^*(x) sum_n exp(i k . a_n) v_J(x - tau_A - a_n) dx
+ * for every projector function J = (atom A of the descriptor's species,
+ * descriptor, m), in descriptor order, atoms in order, m = -l..l; with
+ * k . a_n = 2 pi kappa . n.  phi_i^* on element e is conj(p_a) N_a (the Bloch
+ * phase of local function a), so
+ *   f_J^i = sum_e sum_{a -> i} conj(p_a) sum_q w_q N_a(x_q) P_J(x_q),
+ *   P_J(x) = sum_n exp(2 pi i kappa . n) v_J(x - tau_A - a_n).
+ * F: n_fun x N complex (re, im), row J.  Returns n_fun. */
+int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int *proj_species, const int *proj_l,
+                  const double *proj_a, const double *proj_rc, double *F) {
+    /* projector functions */
+    int nfun = 0;
+    for (int d = 0; d < n_proj; ++d)
+        for (int A = 0; A < s->n_atoms; ++A)
+            if (s->species[A] == proj_species[d]) nfun += 2 * proj_l[d] + 1;
+    if (!F) return nfun;
+    int *fa = malloc(sizeof(int) * (nfun + 1)), *fd = malloc(sizeof(int) * (nfun + 1)),
+        *fm = malloc(sizeof(int) * (nfun + 1));
+    int J = 0;
+    for (int d = 0; d < n_proj; ++d)
+        for (int A = 0; A < s->n_atoms; ++A)
+            if (s->species[A] == proj_species[d])
+                for (int m = -proj_l[d]; m <= proj_l[d]; ++m) {
+                    fa[J] = A;
+                    fd[J] = d;
+                    fm[J] = m;
+                    ++J;
+                }
+    int64_t N = s->ndof;
+    memset(F, 0, sizeof(double) * 2 * (size_t)nfun * N);
+    int mx = max_locals(s);
+    loc_fn *L = malloc(sizeof(loc_fn) * mx);
+    double *val = malloc(sizeof(double) * mx), *grad = malloc(sizeof(double) * 3 * mx);
+    double *Pre = malloc(sizeof(double) * (nfun + 1)), *Pim = malloc(sizeof(double) * (nfun + 1));
+    int64_t nq3 = (int64_t)s->q_n * s->q_n * s->q_n;
+    for (int64_t e = 0; e < s->nel; ++e) {
+        int n = element_locals(s, e, L);
+        for (int64_t lf = s->leaf_off[e]; lf < s->leaf_off[e + 1]; ++lf)
+            for (int64_t j = 0; j < nq3; ++j) {
+                double xi[3], w, x[3];
+                leaf_point(s, s->leaf_level[lf], s->leaf_ijk + 3 * lf, j, xi, &w);
+                ref2phys(s, e, xi, x);
+                basis_eval(s, e, L, n, xi, val, grad);
+                /* Bloch sums of the projector functions at x */
+                double ux[3];
+                cart2red(s, x, ux);
+                for (int J2 = 0; J2 < nfun; ++J2) {
+                    const int d = fd[J2];
+                    const double *tau = s->pos + 3 * fa[J2];
+                    int lo[3], hi[3];
+                    image_range(s, tau, ux, ux, proj_rc[d], lo, hi);
+                    double re = 0.0, im = 0.0;
+                    for (int n3 = lo[2]; n3 <= hi[2]; ++n3)
+                        for (int n2 = lo[1]; n2 <= hi[1]; ++n2)
+                            for (int n1 = lo[0]; n1 <= hi[0]; ++n1) {
+                                double nn[3] = {(double)n1, (double)n2, (double)n3}, R[3], r[3];
+                                red2cart(s, nn, R);
+                                for (int c = 0; c < 3; ++c) r[c] = x[c] - tau[c] - R[c];
+                                double v = projector_value(proj_l[d], fm[J2], proj_a[d], proj_rc[d], r);
+                                if (v == 0.0) continue;
+                                double t = 2.0 * OR_PI * (kappa[0] * n1 + kappa[1] * n2 + kappa[2] * n3);
+                                re += cos(t) * v;
+                                im += sin(t) * v;
+                            }
+                    Pre[J2] = re;
+                    Pim[J2] = im;
+                }
+                for (int a = 0; a < n; ++a) {
+                    double par, pai;
+                    phase(kappa, L[a].shift, &par, &pai);
+                    /* conj(p_a) w N_a P_J */
+                    double cr = w * val[a] * par, ci = -w * val[a] * pai;
+                    for (int J2 = 0; J2 < nfun; ++J2) {
+                        double *f = F + 2 * ((size_t)J2 * N + L[a].g);
+                        f[0] += cr * Pre[J2] - ci * Pim[J2];
+                        f[1] += cr * Pim[J2] + ci * Pre[J2];
+                    }
+                }
+            }
+    }
+    free(L); free(val); free(grad); free(Pre); free(Pim); free(fa); free(fd); free(fm);
+    return nfun;
+}
+
+/* The separable nonlocal term of eq. disceig3d as a dense matrix:
+ *   Vnl_ij = sum_J h_J f_J^i conj(f_J^j),
+ * with h_J the weight of J's descriptor.  Vnl: N x N complex (re, im). */
+void or_nonlocal_dense(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
+                       const int *proj_l, const double *proj_a, const double *proj_rc, const double *proj_h,
+                       double *Vnl) {
+    int nfun = or_nonlocal_f(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, NULL);
+    int64_t N = s->ndof;
+    double *F = malloc(sizeof(double) * 2 * ((size_t)nfun * N + 1));
+    or_nonlocal_f(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, F);
+    double *h = malloc(sizeof(double) * (nfun + 1));
+    int J = 0;
+    for (int d = 0; d < n_proj; ++d)
+        for (int A = 0; A < s->n_atoms; ++A)
+            if (s->species[A] == proj_species[d])
+                for (int m = -proj_l[d]; m <= proj_l[d]; ++m) h[J++] = proj_h[d];
+    memset(Vnl, 0, sizeof(double) * 2 * (size_t)N * N);
+    for (int J2 = 0; J2 < nfun; ++J2) {
+        const double *f = F + 2 * (size_t)J2 * N;
+        for (int64_t i = 0; i < N; ++i) {
+            if (f[2 * i] == 0.0 && f[2 * i + 1] == 0.0) continue;
+            for (int64_t j = 0; j < N; ++j) {
+                /* h f_i conj(f_j) */
+                double ar = f[2 * i], ai = f[2 * i + 1], br = f[2 * j], bi = f[2 * j + 1];
+                Vnl[2 * (i * N + j)] += h[J2] * (ar * br + ai * bi);
+                Vnl[2 * (i * N + j) + 1] += h[J2] * (ai * br - ar * bi);
+            }
+        }
+    }
+    free(F);
+    free(h);
+}

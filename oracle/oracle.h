@@ -8,7 +8,8 @@
  *   - the adaptive per-element quadrature rule (section "Adaptive quadrature"),
  *   - the Galerkin matrices H and S of the discrete generalized eigenproblem
  *     (eq. disceig3d) under Bloch boundary conditions (eq. bloch, wbpspace),
- *   - the adjoint of that assembly (dL/dV and dL/dtau for L = Re<P,H> + Re<Q,S>).
+ *   - the adjoint of that assembly (dL/dV and dL/dtau for L = Re<P,H> + Re<Q,S>),
+ *   - the separable nonlocal term of H (eq. disceig3d).
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
  * load this library.  It shares no code, header or table with the HIP library.
  */
@@ -79,6 +80,15 @@ void or_enrichment(const or_state *s, int atom, int desc, int m, const double *x
 void or_gauss_legendre(int n, double *x, double *w);
 void or_lagrange(int p, int j, double t, double *val, double *der);
 void or_solid_harmonic(int l, int m, const double *r, double *val, double *grad, double *hess);
+/* separable nonlocal term (eq. disceig3d): projector descriptors (species,
+ * l, a, rc[, h]) as parallel arrays; or_nonlocal_f gives the coefficients
+ * f_J^i (n_fun x N complex; F = NULL returns n_fun only), or_nonlocal_dense
+ * the N x N complex matrix sum_J h_J f_J^i conj(f_J^j) */
+int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int *proj_species, const int *proj_l,
+                  const double *proj_a, const double *proj_rc, double *F);
+void or_nonlocal_dense(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
+                       const int *proj_l, const double *proj_a, const double *proj_rc, const double *proj_h,
+                       double *Vnl);
 /* sparsity count: number of nonzero (i,j) pairs of S over the topology */
 int64_t or_pattern_nnz(const or_state *s);
 
