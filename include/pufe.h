@@ -93,6 +93,21 @@ typedef struct {
     double re;        /* support radius, >= 0 */
 } pufe_enrichment;
 
+/* One projector descriptor of the separable nonlocal potential (eq.
+ * disceig3d): the 2l+1 projector functions
+ *   v_lm(r) = exp(-a r^2) (1 - (r/rc)^2)^3 r^l Y_lm(r_hat)   (r < rc, zero beyond)
+ * centred on every atom of `species`, with weight h (hartree): H gains
+ *   sum_J h f_J^i conj(f_J^j),  f_J^i = int phi_i^* sum_n exp(i k . a_n) v_J(x - tau - a_n) dx.
+ * (The radial form stands in for the tabulated projectors of a separable
+ * pseudopotential.) */
+typedef struct {
+    int species;
+    int l;            /* 0..3 */
+    double a;         /* Gaussian exponent, > 0 */
+    double rc;        /* cutoff radius, > 0 */
+    double h;         /* weight (hartree) */
+} pufe_projector;
+
 /* The per-element rule (section "Adaptive quadrature"): leaves of an octree
  * over the reference cube, each carrying the n_gauss^3 tensor Gauss rule. */
 typedef struct {
@@ -137,6 +152,20 @@ int pufe_destroy(pufe_ctx *ctx);
 int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], int fe_order,
                      int n_atoms, const double *pos, const int *species, int n_enr,
                      const pufe_enrichment *enr, const pufe_quad *quad);
+
+/* Add the separable nonlocal term of eq. disceig3d to H (host only; after
+ * pufe_set_problem, before pufe_setup; n = 0 removes it).  The BSR pattern of
+ * H and S then also couples every pair of vertices whose functions reach one
+ * projector image (pufe_get_layout reports it), and every assembly adds
+ * sum_J h_J f_J^i conj(f_J^j) to H at each k-point: f from the basis values
+ * and projector values at the quadrature points on FP64 MFMAs (for every
+ * precision of the contraction), gathered per DOF with the Bloch phases of the
+ * projector images and of the basis functions.  Projector centres stay at the
+ * positions given to pufe_set_problem.  Errors: PUFE_ERR_STATE after
+ * pufe_setup or before pufe_set_problem, PUFE_ERR_INVALID_ARG (l outside 0..3,
+ * a <= 0, rc <= 0, n < 0), PUFE_ERR_UNSUPPORTED (more than 64 projector
+ * columns reach one element). */
+int pufe_set_projectors(pufe_ctx *ctx, int n, const pufe_projector *proj);
 
 /* Build the adaptive rule on the device (section "Adaptive quadrature"),
  * upload the element tables and plan the contraction work.  Synchronous.
@@ -274,9 +303,11 @@ int pufe_bsr_to_dense(pufe_ctx *ctx, const void *d_bsr, int dtype, double *d_den
  * scatter phase enqueued by pufe_assemble is bracketed by HIP events on the
  * caller's stream.  pufe_kernel_times waits for the recorded events and
  * returns the summed milliseconds and launch counts of
- *   [0] the element contraction kernel, [1] the zero-fill + coloured scatter,
+ *   [0] the element contraction kernel, [1] the zero-fill + coloured scatter
+ *       (with the nonlocal gather and update when projectors are set),
  *   [2] the adjoint kernel(s), [3] the sum of the K-chunk partial tiles,
- * clearing them when reset != 0.  out_ms[4] and counts[4] are host arrays. */
+ *   [4] the projector-coefficient kernels of the nonlocal term,
+ * clearing them when reset != 0.  out_ms[5] and counts[5] are host arrays. */
 int pufe_enable_timing(pufe_ctx *ctx, int on);
 int pufe_kernel_times(pufe_ctx *ctx, double *out_ms, int64_t *counts, int reset);
 

@@ -28,7 +28,7 @@ EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_
            "pufe_get_quadrature", "pufe_get_leaves", "pufe_assemble", "pufe_element_matrices",
            "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
            "pufe_kernel_times", "pufe_set_positions", "pufe_batch_create", "pufe_batch_assemble",
-           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune", "pufe_assemble_noalloc", "pufe_set_rule"]
+           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune", "pufe_assemble_noalloc", "pufe_set_rule", "pufe_set_projectors"]
 
 
 class PufeError(RuntimeError):
@@ -40,6 +40,10 @@ class PufeError(RuntimeError):
 class pufe_enrichment(C.Structure):
     _fields_ = [("species", C.c_int), ("l", C.c_int), ("radial_kind", C.c_int),
                 ("a", C.c_double), ("rc", C.c_double), ("re", C.c_double)]
+
+
+class pufe_projector(C.Structure):
+    _fields_ = [("species", C.c_int), ("l", C.c_int), ("a", C.c_double), ("rc", C.c_double), ("h", C.c_double)]
 
 
 class pufe_quad(C.Structure):
@@ -79,6 +83,7 @@ def _load():
         "pufe_assemble": ([vp, vp, dp, C.c_int, C.c_int, C.c_int, vp, vp, vp], C.c_int),
         "pufe_assemble_noalloc": ([vp, vp, dp, C.c_int, C.c_int, C.c_int, vp, vp, vp], C.c_int),
         "pufe_set_rule": ([vp, C.c_int64, i32p, i32p, i64p, vp], C.c_int),
+        "pufe_set_projectors": ([vp, C.c_int, C.POINTER(pufe_projector)], C.c_int),
         "pufe_element_matrices": ([vp, C.c_int64, vp, C.c_int, vp, vp, i32p, vp], C.c_int),
         "pufe_assemble_backward": ([vp, vp, dp, vp, vp, C.c_int, vp, vp, vp], C.c_int),
         "pufe_bsr_to_dense": ([vp, vp, C.c_int, vp, vp], C.c_int),
@@ -149,6 +154,13 @@ def pufe_set_problem(ctx, lattice, mesh, fe_order, pos, species, enrichments, qu
         ctx, lat, msh, int(fe_order), n_atoms,
         pos.ctypes.data_as(C.POINTER(C.c_double)), spc.ctypes.data_as(C.POINTER(C.c_int)),
         len(enrichments), enr, C.byref(q)))
+
+
+def pufe_set_projectors(ctx, projectors):
+    arr = (pufe_projector * max(1, len(projectors)))()
+    for i, q in enumerate(projectors):
+        arr[i] = pufe_projector(int(q["species"]), int(q["l"]), float(q["a"]), float(q["rc"]), float(q["h"]))
+    _check(ctx, lib.pufe_set_projectors(ctx, len(projectors), arr))
 
 
 def pufe_setup(ctx, stream=None):
@@ -244,8 +256,8 @@ def pufe_enable_timing(ctx, on=True):
 
 
 def pufe_kernel_times(ctx, reset=True):
-    ms = (C.c_double * 4)()
-    cnt = (C.c_int64 * 4)()
+    ms = (C.c_double * 5)()
+    cnt = (C.c_int64 * 5)()
     _check(ctx, lib.pufe_kernel_times(ctx, ms, cnt, 1 if reset else 0))
     return list(ms), list(cnt)
 
@@ -293,6 +305,8 @@ class Problem:
         self.ctx = pufe_create(device)
         pufe_set_problem(self.ctx, prob["lattice"], prob["mesh"], prob["fe_order"], prob["atoms"],
                          prob["species"], prob["enrichments"], prob["quad"])
+        if prob.get("projectors"):
+            pufe_set_projectors(self.ctx, prob["projectors"])
         self.sizes = pufe_query(self.ctx)
         self._ready = False
 

@@ -13,6 +13,7 @@
 #include "aq_error.hpp"
 #include "backward.hpp"
 #include "kernels.hpp"
+#include "nonlocal.hpp"
 #include "plan.hpp"
 
 using namespace pufe;
@@ -94,9 +95,21 @@ struct pufe_ctx {
     DevBuf<ItemDev> d_bw_items;
     DevBuf<int64_t> d_pt_off, d_atom_ptr, d_atom_slots;
     DevBuf<double> d_Pt, d_fP, d_fQ;
+    // separable nonlocal term
+    std::vector<NlItemDev> nl_items;
+    std::vector<int32_t> nl_elems;
+    int64_t nl_doubles = 0;
+    size_t nl_lds = 0;
+    DevBuf<NlItemDev> d_nl_items;
+    DevBuf<PGroupDev> d_pgroups;
+    DevBuf<double> d_Fp, d_pfun_h;
+    DevBuf<int64_t> d_dof_el_off;
+    DevBuf<int2> d_dof_el;
+    DevBuf<int32_t> d_nl_elems, d_nl_blocks;
+    DevBuf<double2> d_nlf;
     // timing
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
     ~pufe_ctx() { clear_events(); }
     void clear_events() {
         for (auto &v : ev) {
@@ -207,6 +220,23 @@ int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], 
     ctx->have_setup = false;
     ctx->have_bw = false;
     ctx->n_leaves = ctx->n_qp = 0;
+    ++ctx->plan_gen;
+    return PUFE_OK;
+}
+
+int pufe_set_projectors(pufe_ctx *ctx, int n, const pufe_projector *proj) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "pufe_set_problem must come first");
+    if (ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "projectors are set before pufe_setup");
+    if (n < 0 || (n > 0 && !proj)) return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer or negative count");
+    Problem pr = ctx->prob;
+    pr.proj.assign(proj, proj + n);
+    Plan pl;
+    std::string err;
+    int rc = build_plan(pr, pl, err);
+    if (rc != PUFE_OK) return fail(ctx, rc, err);
+    ctx->prob = std::move(pr);
+    ctx->plan = std::move(pl);
     ++ctx->plan_gen;
     return PUFE_OK;
 }
@@ -329,9 +359,59 @@ static void plan_items(pufe_ctx *c, double target_items, int block_tiles) {
         if (split_lds_bytes(3, c->max_rows_split, nfun, c->plan.max_img, c->max_item_leaves_split, n3) <= kMaxDynLds)
             break;
     }
+    // nonlocal work items: the contraction's K-chunks of every element a
+    // projector image reaches, cut into row blocks of at most 16 tile pairs
+    // (row tiles x projector column tiles); one coefficient slot per chunk
+    c->nl_items.clear();
+    c->nl_elems.clear();
+    c->nl_doubles = 0;
+    int max_npad = 16, max_leaves = 1;
+    for (int64_t e = 0; e < c->plan.nel; ++e) {
+        ElemDev &el = c->plan.elems[e];
+        el.pf_nchunk = 0;
+        el.pf_base = 0;
+        if (el.npg == 0) continue;
+        const int T = (el.nloc + 15) / 16, TC = (el.ncol + 15) / 16, RB = std::max(1, 16 / TC);
+        const int64_t nleaf = el.leaf_end - el.leaf_off, nch = el.nchunk;
+        el.pf_nchunk = (int32_t)nch;
+        el.pf_base = c->nl_doubles;
+        c->nl_doubles += nch * (int64_t)(16 * TC) * (16 * T);
+        c->nl_elems.push_back((int32_t)e);
+        max_npad = std::max(max_npad, 16 * T);
+        for (int64_t ch = 0; ch < nch; ++ch)
+            for (int R0 = 0; R0 < T; R0 += RB) {
+                NlItemDev it{};
+                it.elem = (int32_t)e;
+                it.chunk = (int32_t)ch;
+                it.R0 = R0;
+                it.nR = std::min(RB, T - R0);
+                it.leaf_b = el.leaf_off + ch * nleaf / nch;
+                it.leaf_e = el.leaf_off + (ch + 1) * nleaf / nch;
+                max_leaves = std::max(max_leaves, (int)(it.leaf_e - it.leaf_b));
+                c->nl_items.push_back(it);
+            }
+    }
+    c->nl_lds = nl_lds_bytes(max_npad, std::max(c->plan.max_ncol, 1), nfun, c->plan.max_img, max_leaves, n3);
 }
 
 static int upload_items(pufe_ctx *ctx, hipStream_t st);
+
+// Device tables and buffers of the nonlocal term for the current plan.
+static int upload_nonlocal(pufe_ctx *ctx, hipStream_t st) {
+    const Plan &pl = ctx->plan;
+    if (pl.n_pfun == 0) return PUFE_OK;
+    if (ctx->nl_lds > kMaxDynLds) return fail(ctx, PUFE_ERR_UNSUPPORTED, "nonlocal stage does not fit in LDS");
+    CHECK_HIP(ctx, ctx->d_nl_items.upload(ctx->nl_items, st), "upload nonlocal items");
+    CHECK_HIP(ctx, ctx->d_nl_elems.upload(ctx->nl_elems, st), "upload nonlocal elements");
+    CHECK_HIP(ctx, ctx->d_pgroups.upload(pl.pgroups, st), "upload projector groups");
+    CHECK_HIP(ctx, ctx->d_pfun_h.upload(pl.pfun_h, st), "upload projector weights");
+    CHECK_HIP(ctx, ctx->d_dof_el_off.upload(pl.dof_el_off, st), "upload DOF map");
+    CHECK_HIP(ctx, ctx->d_dof_el.upload(pl.dof_el, st), "upload DOF map");
+    CHECK_HIP(ctx, ctx->d_nl_blocks.upload(pl.nl_blocks, st), "upload nonlocal blocks");
+    CHECK_HIP(ctx, ctx->d_Fp.alloc((size_t)std::max<int64_t>(ctx->nl_doubles, 1)), "alloc projector coefficients");
+    CHECK_HIP(ctx, ctx->d_nlf.alloc((size_t)kMaxKPerLaunch * pl.n_pfun * pl.dof_off[pl.nv]), "alloc projector sums");
+    return PUFE_OK;
+}
 
 int pufe_setup(pufe_ctx *ctx, void *stream) {
     if (!ctx) return PUFE_ERR_INVALID_ARG;
@@ -342,6 +422,7 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
         hipError_t ea = init_contract_attributes();
         if (ea == hipSuccess) ea = init_split_attributes();
         if (ea == hipSuccess) ea = init_backward_attributes();
+        if (ea == hipSuccess) ea = init_nonlocal_attributes();
         if (ea != hipSuccess) {
             (void)hipGetLastError();   // do not leave the error for the caller's next HIP call
             return hipfail(ctx, ea, "kernel attributes");
@@ -424,6 +505,10 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_wide.upload(ctx->items_wide, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
+    {
+        int rc = upload_nonlocal(ctx, st);
+        if (rc != PUFE_OK) return rc;
+    }
     CHECK_HIP(ctx, ctx->d_color_elems.upload(pl.color_elems, st), "upload colours");
     CHECK_HIP(ctx, ctx->d_scat.upload(pl.scat, st), "upload scatter list");
     CHECK_HIP(ctx, ctx->d_reduce.upload(ctx->reduce, st), "upload chunk reduction list");
@@ -635,6 +720,16 @@ static int assemble_impl(pufe_ctx *ctx, const double *d_V, const double *kpts, i
     int rc = run_contraction(ctx, d_V, precision, st, partial, timed);
     if (rc != PUFE_OK) return rc;
     const Plan &pl = ctx->plan;
+    if (pl.n_pfun > 0) {
+        // projector coefficients of every element a projector image reaches
+        TimedRegion tn(ctx, timed ? 4 : -1, st);
+        CHECK_HIP(ctx, launch_nl_f(pl.max_l, pl.kp, (int)ctx->nl_items.size(), ctx->d_nl_items.p, ctx->d_elems.p,
+                                   ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, ctx->d_pgroups.p,
+                                   ctx->d_Fp.p, ctx->nl_lds, st),
+                  "projector coefficients");
+        CHECK_HIP(ctx, launch_nl_reduce(ctx->d_elems.p, ctx->d_nl_elems.p, (int)ctx->nl_elems.size(), ctx->d_Fp.p, st),
+                  "projector coefficient sum");
+    }
     TimedRegion tr(ctx, timed ? 1 : -1, st);
     const int64_t per = out_dtype == PUFE_OUT_F64_GAMMA ? pl.nnz : 2 * pl.nnz;
     const bool f32 = out_dtype == PUFE_OUT_C64;
@@ -659,6 +754,18 @@ static int assemble_impl(pufe_ctx *ctx, const double *d_V, const double *kpts, i
                                           partial, ztab, kps.nk, out_dtype, H, S, pl.nnz, st),
                       "scatter");
         }
+        if (pl.n_pfun > 0) {
+            // the separable term of these k-points into H
+            const int64_t ndof = pl.dof_off[pl.nv];
+            CHECK_HIP(ctx, launch_nl_gather(pl.kp, ctx->d_elems.p, ctx->d_pgroups.p, ctx->d_edof.p,
+                                            ctx->d_dof_el_off.p, ctx->d_dof_el.p, ctx->d_Fp.p, kps, pl.n_pfun, ndof,
+                                            ctx->d_nlf.p, st),
+                      "projector sums");
+            CHECK_HIP(ctx, launch_nl_update((int)pl.nl_blocks.size(), ctx->d_nl_blocks.p, ctx->d_brow.p, ctx->d_bcol.p,
+                                            ctx->d_bval_off.p, ctx->d_dof_off.p, ctx->d_nlf.p, ctx->d_pfun_h.p,
+                                            pl.n_pfun, ndof, kps.nk, out_dtype, H, pl.nnz, st),
+                      "nonlocal update");
+        }
     }
     return PUFE_OK;
 }
@@ -677,6 +784,9 @@ int pufe_assemble_noalloc(pufe_ctx *ctx, const double *d_V, const double *kpts, 
                           void *d_H, void *d_S, void *stream) {
     int rc = check_assemble_args(ctx, d_V, kpts, n_k, precision, out_dtype, d_H);
     if (rc != PUFE_OK) return rc;
+    if (ctx->plan.n_pfun > 0)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED,
+                    "pufe_assemble_noalloc: the nonlocal term keeps its coefficients in context buffers; use pufe_assemble");
     // workspace: the phase table, then the partial tiles (256-byte aligned)
     const size_t ztab_bytes = (sizeof(double2) * kMaxKPerLaunch * 27 + 255) / 256 * 256;
     const size_t need = ztab_bytes + (size_t)ctx->part_slots * 512 * sizeof(double);
@@ -864,7 +974,7 @@ int pufe_enable_timing(pufe_ctx *ctx, int on) {
 
 int pufe_kernel_times(pufe_ctx *ctx, double *out_ms, int64_t *counts, int reset) {
     if (!ctx) return PUFE_ERR_INVALID_ARG;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
         double ms = 0.0;
         for (auto &pr : ctx->ev[k]) {
             CHECK_HIP(ctx, hipEventSynchronize(pr.second), "event sync");
@@ -889,7 +999,7 @@ static int upload_items(pufe_ctx *ctx, hipStream_t st) {
     CHECK_HIP(ctx, ctx->d_reduce.upload(ctx->reduce, st), "upload chunk reduction list");
     CHECK_HIP(ctx, ctx->d_partial.alloc((size_t)ctx->part_slots * 512), "alloc partial tiles");
     ctx->have_bw = false;
-    return PUFE_OK;
+    return upload_nonlocal(ctx, st);
 }
 
 int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
@@ -1090,6 +1200,10 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         if (!ctxs[i] || !ctxs[i]->have_setup || ctxs[i]->device != ctxs[0]->device) {
             delete b;
             return PUFE_ERR_STATE;
+        }
+        if (ctxs[i]->plan.n_pfun > 0) {   // the batch graph holds no nonlocal launches
+            delete b;
+            return PUFE_ERR_UNSUPPORTED;
         }
         b->ctxs.push_back(ctxs[i]);
         b->gens.push_back(ctxs[i]->plan_gen);

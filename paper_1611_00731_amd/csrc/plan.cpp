@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <map>
 #include <set>
 #include <tuple>
@@ -54,6 +55,10 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
         if (e.l < 0 || e.l > 3) { err = "enrichment l must be in 0..3"; return PUFE_ERR_INVALID_ARG; }
         if (!(e.a > 0) || !(e.rc > 0) || !(e.re >= 0)) { err = "enrichment needs a > 0, rc > 0, re >= 0"; return PUFE_ERR_INVALID_ARG; }
         if (e.radial_kind != 0) { err = "only the analytic radial kind 0 is supported"; return PUFE_ERR_UNSUPPORTED; }
+    }
+    for (const auto &pj : pr.proj) {
+        if (pj.l < 0 || pj.l > 3) { err = "projector l must be in 0..3"; return PUFE_ERR_INVALID_ARG; }
+        if (!(pj.a > 0) || !(pj.rc > 0) || !std::isfinite(pj.h)) { err = "projector needs a > 0, rc > 0, finite h"; return PUFE_ERR_INVALID_ARG; }
     }
     const pufe_quad &q = pr.quad;
     if (q.n_gauss < 1 || q.n_gauss > kMaxGauss) { err = "n_gauss must be in 1..12"; return PUFE_ERR_INVALID_ARG; }
@@ -126,8 +131,91 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     for (int64_t v = 0; v < pl.nv; ++v)
         pl.dof_off[v + 1] = pl.dof_off[v] + pl.nfs + (pl.vf_off[v + 1] - pl.vf_off[v]);
 
+    // ---- element geometry
+    const double lat[9] = {pr.lat[0], pr.lat[1], pr.lat[2], pr.lat[3], pr.lat[4], pr.lat[5], pr.lat[6], pr.lat[7], pr.lat[8]};
+    double E[9];
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) E[3 * d + c] = lat[3 * d + c] / mesh[d];
+    // bounding radius of one element: half its longest diagonal
+    double Re = 0;
+    for (int s2 = -1; s2 <= 1; s2 += 2)
+        for (int s3 = -1; s3 <= 1; s3 += 2) {
+            double dd[3];
+            for (int c = 0; c < 3; ++c) dd[c] = E[c] + s2 * E[3 + c] + s3 * E[6 + c];
+            Re = std::max(Re, 0.5 * std::sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
+        }
+    auto elem_centre = [&](int64_t e, double *centre) {
+        const int i0 = (int)(e % n1), i1 = (int)((e / n1) % n2), i2 = (int)(e / ((int64_t)n1 * n2));
+        for (int c = 0; c < 3; ++c) centre[c] = (i0 + 0.5) * E[c] + (i1 + 0.5) * E[3 + c] + (i2 + 0.5) * E[6 + c];
+    };
+    auto corner_vertex = [&](int64_t e, int c) -> int64_t {
+        const int i[3] = {(int)(e % n1), (int)((e / n1) % n2), (int)(e / ((int64_t)n1 * n2))};
+        int j[3];
+        for (int d = 0; d < 3; ++d) j[d] = (i[d] + ((c >> d) & 1)) % mesh[d];
+        return ((int64_t)j[2] * n2 + j[1]) * n1 + j[0];
+    };
+
+    // ---- separable nonlocal term: projector functions J = (descriptor,
+    // atom of its species, m) in that order, the projector images that
+    // reach each element (sphere of radius rc around the image within the
+    // element's bounding sphere), and the vertices each image couples
+    struct PImg {
+        int A, d, n[3];
+        double C[3];
+    };
+    std::vector<std::vector<PImg>> elem_pimg(pl.nel);
+    std::map<std::array<int, 4>, std::vector<int64_t>> img_vertices;   // (atom, image shift) -> vertices
+    std::vector<std::vector<int>> pfun_of(pr.proj.size(), std::vector<int>(n_atoms, -1));   // J of (d, A, m = -l)
+    pl.n_pfun = 0;
+    pl.pfun_h.clear();
+    for (size_t d = 0; d < pr.proj.size(); ++d)
+        for (int A = 0; A < n_atoms; ++A)
+            if (pr.species[A] == pr.proj[d].species) {
+                pfun_of[d][A] = pl.n_pfun;
+                for (int m = -pr.proj[d].l; m <= pr.proj[d].l; ++m) pl.pfun_h.push_back(pr.proj[d].h);
+                pl.n_pfun += 2 * pr.proj[d].l + 1;
+            }
+    for (int64_t e = 0; e < pl.nel && !pr.proj.empty(); ++e) {
+        double centre[3], uc[3];
+        elem_centre(e, centre);
+        for (int d = 0; d < 3; ++d) uc[d] = centre[0] * pl.inv[d] + centre[1] * pl.inv[3 + d] + centre[2] * pl.inv[6 + d];
+        for (size_t dp = 0; dp < pr.proj.size(); ++dp)
+            for (int A = 0; A < n_atoms; ++A) {
+                if (pr.species[A] != pr.proj[dp].species) continue;
+                const double *tau = &pr.pos[3 * A];
+                double ur[3];
+                for (int d = 0; d < 3; ++d) ur[d] = tau[0] * pl.inv[d] + tau[1] * pl.inv[3 + d] + tau[2] * pl.inv[6 + d];
+                const double reach = pr.proj[dp].rc + Re;
+                int lo[3], hi[3];
+                for (int d = 0; d < 3; ++d) {
+                    double rad = reach * std::sqrt(pl.inv[d] * pl.inv[d] + pl.inv[3 + d] * pl.inv[3 + d] + pl.inv[6 + d] * pl.inv[6 + d]);
+                    lo[d] = (int)std::floor(uc[d] - ur[d] - rad) - 1;
+                    hi[d] = (int)std::ceil(uc[d] - ur[d] + rad) + 1;
+                }
+                for (int m3 = lo[2]; m3 <= hi[2]; ++m3)
+                    for (int m2 = lo[1]; m2 <= hi[1]; ++m2)
+                        for (int m1 = lo[0]; m1 <= hi[0]; ++m1) {
+                            PImg pi{A, (int)dp, {m1, m2, m3}, {0, 0, 0}};
+                            for (int c = 0; c < 3; ++c) pi.C[c] = tau[c] + m1 * lat[c] + m2 * lat[3 + c] + m3 * lat[6 + c];
+                            const double dx = pi.C[0] - centre[0], dy = pi.C[1] - centre[1], dz = pi.C[2] - centre[2];
+                            if (std::sqrt(dx * dx + dy * dy + dz * dz) >= reach) continue;
+                            elem_pimg[e].push_back(pi);
+                            auto &vs = img_vertices[{A, m1, m2, m3}];
+                            for (int c = 0; c < 8; ++c) vs.push_back(corner_vertex(e, c));
+                        }
+            }
+    }
+    std::vector<std::vector<int64_t>> extra(pr.proj.empty() ? 0 : pl.nv);
+    for (auto &kv : img_vertices) {
+        auto &vs = kv.second;
+        std::sort(vs.begin(), vs.end());
+        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+        for (int64_t v : vs) extra[v].insert(extra[v].end(), vs.begin(), vs.end());
+    }
+
     // ---- block layout: vertex v couples to every vertex of the elements
-    // around it, i.e. its (wrapped) 3x3x3 neighbourhood.
+    // around it, i.e. its (wrapped) 3x3x3 neighbourhood, and to the vertices
+    // that reach a projector image with it
     auto vid = [&](int j1, int j2, int j3) -> int64_t {
         return ((int64_t)wrapi(j3, n3) * n2 + wrapi(j2, n2)) * n1 + wrapi(j1, n1);
     };
@@ -143,6 +231,7 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
         for (int d3 = -1; d3 <= 1; ++d3)
             for (int d2 = -1; d2 <= 1; ++d2)
                 for (int d1 = -1; d1 <= 1; ++d1) nb.push_back(vid(j1 + d1, j2 + d2, j3 + d3));
+        if (!extra.empty()) nb.insert(nb.end(), extra[v].begin(), extra[v].end());
         std::sort(nb.begin(), nb.end());
         nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
         int64_t bv = pl.dof_off[v + 1] - pl.dof_off[v];
@@ -161,21 +250,21 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
         auto it = std::lower_bound(b, e, (int32_t)w);
         return pl.bval_off[it - pl.bcol.begin()];
     };
+    // the blocks a projector image couples
+    pl.nl_blocks.clear();
+    for (auto &kv : img_vertices)
+        for (int64_t v : kv.second)
+            for (int64_t w : kv.second) {
+                auto b = pl.bcol.begin() + pl.brow_ptr[v], e = pl.bcol.begin() + pl.brow_ptr[v + 1];
+                pl.nl_blocks.push_back((int32_t)(std::lower_bound(b, e, (int32_t)w) - pl.bcol.begin()));
+            }
+    std::sort(pl.nl_blocks.begin(), pl.nl_blocks.end());
+    pl.nl_blocks.erase(std::unique(pl.nl_blocks.begin(), pl.nl_blocks.end()), pl.nl_blocks.end());
 
     // ---- elements
-    const double lat[9] = {pr.lat[0], pr.lat[1], pr.lat[2], pr.lat[3], pr.lat[4], pr.lat[5], pr.lat[6], pr.lat[7], pr.lat[8]};
-    double E[9];
-    for (int d = 0; d < 3; ++d)
-        for (int c = 0; c < 3; ++c) E[3 * d + c] = lat[3 * d + c] / mesh[d];
-    // bounding radius of one element: half its longest diagonal
-    double Re = 0;
-    for (int s2 = -1; s2 <= 1; s2 += 2)
-        for (int s3 = -1; s3 <= 1; s3 += 2) {
-            double dd[3];
-            for (int c = 0; c < 3; ++c) dd[c] = E[c] + s2 * E[3 + c] + s3 * E[6 + c];
-            Re = std::max(Re, 0.5 * std::sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]));
-        }
     pl.elems.assign(pl.nel, ElemDev{});
+    pl.pgroups.clear();
+    pl.max_ncol = pl.max_npg = 0;
     pl.groups.clear();
     pl.img.clear();
     pl.edof.clear();
@@ -274,6 +363,31 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
                   std::to_string(el.nloc) + ", functions " + std::to_string(nfun) + ")";
             return PUFE_ERR_UNSUPPORTED;
         }
+        // projector-image groups of the element
+        el.pg_off = (int32_t)pl.pgroups.size();
+        el.npg = (int32_t)elem_pimg[e].size();
+        el.ncol = 0;
+        el.pf_nchunk = 0;
+        el.pf_base = 0;
+        for (const PImg &pi : elem_pimg[e]) {
+            PGroupDev g{};
+            for (int c = 0; c < 3; ++c) g.c[c] = pi.C[c];
+            g.a = pr.proj[pi.d].a;
+            g.rc = pr.proj[pi.d].rc;
+            g.l = pr.proj[pi.d].l;
+            g.col0 = el.ncol;
+            g.J0 = pfun_of[pi.d][pi.A];
+            for (int d = 0; d < 3; ++d) g.n[d] = pi.n[d];
+            pl.pgroups.push_back(g);
+            el.ncol += 2 * g.l + 1;
+        }
+        if (el.ncol > kMaxProjCols || el.npg > kMaxPGroups) {
+            err = "element " + std::to_string(e) + " is reached by more projector columns than the kernels hold (" +
+                  std::to_string(el.ncol) + ")";
+            return PUFE_ERR_UNSUPPORTED;
+        }
+        pl.max_ncol = std::max(pl.max_ncol, el.ncol);
+        pl.max_npg = std::max(pl.max_npg, el.npg);
         pl.max_nloc = std::max(pl.max_nloc, el.nloc);
         pl.max_nfun = std::max(pl.max_nfun, nfun);
         pl.max_ngrp = std::max(pl.max_ngrp, el.ngrp);
@@ -285,6 +399,37 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
         by_color[el.color].push_back((int32_t)e);
     }
     pl.img_cur = pl.img;
+    // (element, local function) pairs of every DOF, element order
+    {
+        std::vector<std::vector<int2>> lists(pl.dof_off[pl.nv]);
+        for (int64_t e = 0; e < pl.nel; ++e) {
+            const ElemDev &el = pl.elems[e];
+            for (int a = 0; a < el.nloc; ++a) {
+                int corner, slot;
+                if (a < el.nfe) {
+                    if (pr.p == 1) {
+                        corner = a;
+                        slot = 0;
+                    } else {
+                        const int d0 = a % 3, d1 = (a / 3) % 3, d2 = a / 9;
+                        corner = (d0 == 2) | ((d1 == 2) << 1) | ((d2 == 2) << 2);
+                        slot = (d0 == 1) | ((d1 == 1) << 1) | ((d2 == 1) << 2);
+                    }
+                } else {
+                    const int32_t pk = pl.edof[el.edof_off + (a - el.nfe)];
+                    corner = pk & 7;
+                    slot = pk >> 11;
+                }
+                lists[pl.dof_off[corner_vertex(e, corner)] + slot].push_back(make_int2((int)e, a));
+            }
+        }
+        pl.dof_el_off.assign(lists.size() + 1, 0);
+        pl.dof_el.clear();
+        for (size_t g = 0; g < lists.size(); ++g) {
+            pl.dof_el.insert(pl.dof_el.end(), lists[g].begin(), lists[g].end());
+            pl.dof_el_off[g + 1] = (int64_t)pl.dof_el.size();
+        }
+    }
     // the scatter relies on elements of one colour sharing no vertex
     {
         std::vector<int32_t> owner(pl.nv * 27, -1);

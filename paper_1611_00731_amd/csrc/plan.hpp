@@ -18,6 +18,7 @@ struct Problem {
     std::vector<int> species;
     std::vector<pufe_enrichment> enr;
     pufe_quad quad;
+    std::vector<pufe_projector> proj;   // separable nonlocal term (may be empty)
 };
 
 struct Plan {
@@ -47,6 +48,16 @@ struct Plan {
     int max_l = 0;                  // largest angular momentum of any descriptor
     int max_img = 0;                // most image centres of one element's groups
     KParams kp;
+    // separable nonlocal term: projector functions J (atom, descriptor, m)
+    // with their weights, the projector-image groups of every element, and
+    // for every DOF the (element, local function) pairs that carry it
+    int n_pfun = 0;
+    std::vector<double> pfun_h;
+    std::vector<PGroupDev> pgroups;
+    std::vector<int64_t> dof_el_off;  // n_dof + 1
+    std::vector<int2> dof_el;         // (element, local function)
+    int max_ncol = 0, max_npg = 0;
+    std::vector<int32_t> nl_blocks;   // BSR blocks coupled through a projector image
 };
 
 // Image lists keep every image within rc + this margin of an element, so the

@@ -13,6 +13,8 @@ constexpr int kBlockTiles = 4;    // tiles per row/column block of a work item
 constexpr int kMaxGauss = 12;
 constexpr int kMaxLevel = 8;
 constexpr int kMaxRowChunks = 64; // enriched-row chunks of one partial work item
+constexpr int kMaxProjCols = 64;  // projector columns reaching one element
+constexpr int kMaxPGroups = 32;   // projector-image groups reaching one element
 // dynamic LDS a kernel may request: the 160 KiB of a CU minus room for the
 // small static __shared__ variables some kernels also declare
 constexpr size_t kMaxDynLds = 159 * 1024;
@@ -30,6 +32,26 @@ struct ElemDev {
     int64_t part_base;   // first partial tile-pair slot
     int64_t blk[64];     // value offset of BSR block (vertex of corner ca, vertex of corner cb) at ca*8+cb
     int32_t bw[8];       // width of the block column of corner c (b_w of its vertex)
+    int32_t pg_off, npg; // projector-image groups reaching the element
+    int32_t ncol;        // projector columns (sum of 2l+1 over the groups)
+    int32_t pf_nchunk;   // K-chunks of its projector coefficients (0: none)
+    int64_t pf_base;     // first double of its projector-coefficient slots, F[chunk][col][npad]
+};
+
+// Projector descriptor of one atom image that reaches an element: the 2l+1
+// columns col0 .. col0 + 2l of the element's projector coefficients, the
+// projector functions J0 .. J0 + 2l, the image centre and its lattice shift.
+struct PGroupDev {
+    double c[3];
+    double a, rc;
+    int32_t l, col0, J0, n[3];
+};
+
+// A nonlocal work item: one element, one range of its octree leaves, one row
+// block of its local functions (tiles R0 .. R0 + nR - 1).
+struct NlItemDev {
+    int32_t elem, chunk, R0, nR;
+    int64_t leaf_b, leaf_e;
 };
 
 // (atom, descriptor) group: 2l+1 functions with one radial part and the list

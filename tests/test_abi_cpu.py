@@ -158,3 +158,50 @@ def test_golden_lih_cell_eigenvalues_file():
     assert len(ev) == W.lih_cell()["n_eig"]
     assert np.all(np.diff(ev) >= 0)
     assert np.all(np.isfinite(ev))
+
+
+@pytest.mark.parametrize("kind,mesh,p", [("lih", (2, 3, 2), 2), ("one", (3, 3, 2), 1), ("ceal", (2, 2, 2), 2)])
+def test_projector_pattern_holds_the_nonlocal_term(kind, mesh, p):
+    """With projectors the BSR pattern also couples every pair of DOFs that
+    reach one projector image: every nonzero of the oracle's dense nonlocal
+    term (eq. disceig3d) lies in a stored block, and the element-coupling
+    blocks are all still there."""
+    prob = W.with_projectors(W.small(kind, mesh=mesh, fe_order=p, levels=0, n=3, a=4.6))
+    ctx = P.pufe_create(0)
+    try:
+        P.pufe_set_problem(ctx, prob["lattice"], prob["mesh"], prob["fe_order"], prob["atoms"],
+                           prob["species"], prob["enrichments"], prob["quad"])
+        lay0 = P.pufe_get_layout(ctx)
+        P.pufe_set_projectors(ctx, prob["projectors"])
+        lay = P.pufe_get_layout(ctx)
+    finally:
+        P.pufe_destroy(ctx)
+    off = lay["dof_offset"]
+    N = off[-1]
+    stored = np.zeros((N, N), bool)
+    for v in range(len(off) - 1):
+        for k in range(lay["brow_ptr"][v], lay["brow_ptr"][v + 1]):
+            w = lay["bcol"][k]
+            stored[off[v]:off[v + 1], off[w]:off[w + 1]] = True
+    for v in range(len(off) - 1):
+        cols0 = set(lay0["bcol"][lay0["brow_ptr"][v]:lay0["brow_ptr"][v + 1]])
+        assert cols0 <= set(lay["bcol"][lay["brow_ptr"][v]:lay["brow_ptr"][v + 1]])
+    o = oracle.Oracle(prob)
+    Vn = o.nonlocal_dense((0.1, -0.2, 0.3))
+    assert np.abs(Vn[~stored]).max(initial=0.0) == 0.0
+    assert np.count_nonzero(Vn) > 0
+
+
+def test_projector_input_validation():
+    base = W.small("one", mesh=(2, 2, 2), fe_order=1)
+    ctx = P.pufe_create(0)
+    try:
+        _expect(-5, lambda: P.pufe_set_projectors(ctx, [{"species": 0, "l": 0, "a": 1.0, "rc": 1.0, "h": 1.0}]))
+        P.pufe_set_problem(ctx, base["lattice"], base["mesh"], base["fe_order"], base["atoms"], base["species"],
+                           base["enrichments"], base["quad"])
+        _expect(-1, lambda: P.pufe_set_projectors(ctx, [{"species": 0, "l": 4, "a": 1.0, "rc": 1.0, "h": 1.0}]))
+        _expect(-1, lambda: P.pufe_set_projectors(ctx, [{"species": 0, "l": 1, "a": -1.0, "rc": 1.0, "h": 1.0}]))
+        P.pufe_set_projectors(ctx, [{"species": 0, "l": 1, "a": 1.0, "rc": 1.0, "h": 1.0}])
+        P.pufe_set_projectors(ctx, [])
+    finally:
+        P.pufe_destroy(ctx)

@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "single_atom_cube", "lih_cell", "lih_lattice_sweep", "ceal_cell", "lih_supercell", "small", "lih_table1",
-    "ceal_triclinic", "PAPER_KPTS",
+    "ceal_triclinic", "PAPER_KPTS", "with_projectors",
     "mp2", "ceal_kpoints", "jitter", "adjoint_factor", "with_lattice_constant",
     "orthorhombic", "random_small",
 ]
@@ -221,6 +221,31 @@ def ceal_triclinic(mesh: int = 12, levels: int = 2, n: int = 6, n_ref: int = 8, 
         [{"name": "Ce", "Z": 12.0, "rloc": 0.3}, {"name": "Al", "Z": 3.0, "rloc": 0.3}],
         enr, {"n": n, "n_ref": n_ref, "levels": levels, "mode": "error", "dist": 0.0, "tol": tol},
         copy.deepcopy(PAPER_KPTS), 16, f"ceal_triclinic-{mesh}")
+
+
+# Synthetic separable-projector sets (eq. disceig3d nonlocal term) in the
+# radial form of the enrichments: per species name, (l, a, rc, h) rows.  They
+# stand in for tabulated pseudopotential projectors (not available here).
+PROJECTORS = {
+    "Li": [(0, 1.5, 2.0, 0.8), (1, 1.2, 2.0, -0.3)],
+    "H": [(0, 2.0, 1.5, 0.5)],
+    "Ce": [(0, 2.5, 1.8, 1.1), (1, 2.0, 1.8, -0.4), (2, 1.8, 1.8, 0.3)],
+    "Al": [(0, 1.6, 1.8, 0.6), (1, 1.4, 1.8, -0.2)],
+    "X": [(0, 1.5, 1.6, 0.7), (1, 1.3, 1.6, -0.3)],
+}
+
+
+def with_projectors(prob, scale_rc: float = 1.0):
+    """A copy of prob with the synthetic projector set of each of its species
+    (cutoffs scaled by scale_rc)."""
+    out = copy.deepcopy(prob)
+    proj = []
+    for sp, info in enumerate(prob["species_info"]):
+        for l, a, rc, h in PROJECTORS[info["name"]]:
+            proj.append({"species": sp, "l": l, "a": a, "rc": rc * scale_rc, "h": h})
+    out["projectors"] = proj
+    out["name"] = prob["name"] + "+nl"
+    return out
 
 
 def lih_supercell():
