@@ -118,17 +118,36 @@ def test_autograd_function_and_finite_differences():
     p.close()
 
 
+def _golden_supercell():
+    import os
+    dR, dVs = {}, {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "lih_supercell_adjoint.txt")):
+        if line.startswith("#"):
+            continue
+        key, idx, *vals = line.split()
+        if key == "dLdR":
+            dR[int(idx)] = [float(v) for v in vals]
+        else:
+            dVs[int(idx)] = float(vals[0])
+    return np.array([dR[A] for A in sorted(dR)]), np.array([dVs[e] for e in sorted(dVs)])
+
+
 def test_backward_lih_supercell_full_size():
     """2x2x2 LiH-like supercell (64 atoms, 4096 elements, 12.1 M points),
-    rank-128 Hermitian PSD P on the pattern: dL/dV on sampled elements against
-    the oracle's per-element adjoint, dL/dR against central differences of the
-    GPU forward."""
+    rank-128 Hermitian PSD P on the pattern: dL/dR of all 64 atoms and dL/dV
+    summed over the points of every element against the oracle's full adjoint
+    (stored by tests/golden/make_lih_supercell_adjoint.py), FP64 and bf16x6;
+    dL/dV point by point on sampled elements against the oracle's
+    per-element adjoint; dL/dR against central differences of the GPU
+    forward on all 192 coordinates."""
     prob = W.lih_supercell()
     say("backward lih_supercell full size")
+    gR, gVs = _golden_supercell()
     o = oracle.Oracle(prob)
     xyz, w, qoff = o.quadrature()
     Vd = potential_at(torch.from_numpy(xyz).cuda(), prob)
     V = Vd.cpu().numpy()
+    del xyz, w
     p = P.Problem(prob).setup()
     lay = p.layout()
     N = p.sizes["n_dof"]
@@ -141,15 +160,33 @@ def test_backward_lih_supercell_full_size():
     for s in range(0, len(rows), 1 << 20):
         r, c = rows_d[s:s + (1 << 20)], cols_d[s:s + (1 << 20)]
         Pb[s:s + (1 << 20)] = (Cd[r] * Cd[c].conj()).sum(-1)
+    del Cd, rows_d, cols_d
+    qo = torch.from_numpy(qoff).cuda()
+    seg = torch.repeat_interleave(torch.arange(len(qoff) - 1, device="cuda"), qo[1:] - qo[:-1])
+
+    def elem_sums(dV):
+        return torch.zeros(len(qoff) - 1, dtype=torch.float64, device="cuda").index_add_(0, seg, dV).cpu().numpy()
+
     dV, dR = p.backward(Vd, (0.0, 0.0, 0.0), Pb, None)
+    g = dR.cpu().numpy()
+    eR = np.abs(g - gR).max() / np.abs(gR).max()
+    eV = np.abs(elem_sums(dV) - gVs).max() / np.abs(gVs).max()
+    say("fp64 vs oracle: dL/dR", eR, "dL/dV element sums", eV)
+    assert eR < 1e-11 and eV < 1e-11
     dVh = dV.cpu().numpy()
     lev, _, loff = o.leaves()
     refined = [e for e in range(o.n_elem) if loff[e + 1] - loff[e] > 1]
     for e in [refined[0], refined[len(refined) // 2], 5, 1234, o.n_elem - 1]:
-        g, _ = o.element_dofs(e)
-        Ploc = Cf[g] @ Cf[g].conj().T
+        gd, _ = o.element_dofs(e)
+        Ploc = Cf[gd] @ Cf[gd].conj().T
         dv_o, _ = o.backward_element(e, V[qoff[e]:qoff[e + 1]], (0, 0, 0), Ploc)
         assert rel(dVh[qoff[e]:qoff[e + 1]], dv_o) < 1e-11, e
+    # the split form at full size (bf16x6) against the same oracle values
+    dVs, dRs = p.backward(Vd, (0.0, 0.0, 0.0), Pb, None, precision="bf16x6")
+    eRs = np.abs(dRs.cpu().numpy() - gR).max() / np.abs(gR).max()
+    eVs = rel(dVs.cpu().numpy(), dVh)
+    say("bf16x6: dL/dR vs oracle", eRs, "dL/dV vs FP64", eVs)
+    assert eRs < SPLIT_TOL["bf16x6"] and eVs < SPLIT_TOL["bf16x6"]
     R0 = np.asarray(prob["atoms"], float)
 
     def loss(R):
@@ -157,23 +194,17 @@ def test_backward_lih_supercell_full_size():
         H, _ = p.assemble(Vd, [(0, 0, 0)], with_S=False)
         return float((Pb.conj() * torch.view_as_complex(H[0])).real.sum())
 
-    g = dR.cpu().numpy()
-    # the split form at full size (bf16x6): dL/dV against the FP64 result,
-    # dL/dR against the same central differences
-    dVs, dRs = p.backward(Vd, (0.0, 0.0, 0.0), Pb, None, precision="bf16x6")
-    es = rel(dVs.cpu().numpy(), dVh)
-    say("bf16x6 dL/dV rel. error vs FP64", es)
-    assert es < SPLIT_TOL["bf16x6"]
-    gs = dRs.cpu().numpy()
     h = 1e-4
-    for A, k in [(0, 0), (13, 1), (40, 2), (63, 0)]:
-        Rp, Rm = R0.copy(), R0.copy()
-        Rp[A, k] += h
-        Rm[A, k] -= h
-        fd = (loss(Rp) - loss(Rm)) / (2 * h)
-        assert abs(fd - g[A, k]) < 1e-6 * np.abs(g).max(), (A, k, fd, g[A, k])
-        say("bf16x6 dL/dR vs FD", A, k, abs(fd - gs[A, k]) / np.abs(g).max())
-        assert abs(fd - gs[A, k]) < 1e-6 * np.abs(g).max() + SPLIT_TOL["bf16x6"] * np.abs(g).max()
+    worst = 0.0
+    for A in range(len(R0)):
+        for k in range(3):
+            Rp, Rm = R0.copy(), R0.copy()
+            Rp[A, k] += h
+            Rm[A, k] -= h
+            fd = (loss(Rp) - loss(Rm)) / (2 * h)
+            worst = max(worst, abs(fd - g[A, k]) / np.abs(g).max())
+    say("central differences, all 192 coordinates: worst relative error", worst)
+    assert worst < 1e-6
     p.set_positions(R0)
     p.close()
 
