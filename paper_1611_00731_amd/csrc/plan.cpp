@@ -158,13 +158,15 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     // ---- separable nonlocal term: projector functions J = (descriptor,
     // atom of its species, m) in that order, the projector images that
     // reach each element (sphere of radius rc around the image within the
-    // element's bounding sphere), and the vertices each image couples
+    // element's bounding sphere), and the vertices each atom couples: a
+    // projector function is the Bloch sum over all images of its atom, so
+    // two vertices that reach different images of one atom are coupled too
     struct PImg {
         int A, d, n[3];
         double C[3];
     };
     std::vector<std::vector<PImg>> elem_pimg(pl.nel);
-    std::map<std::array<int, 4>, std::vector<int64_t>> img_vertices;   // (atom, image shift) -> vertices
+    std::vector<std::vector<int64_t>> atom_vertices(n_atoms);   // vertices of elements an image of the atom reaches
     std::vector<std::vector<int>> pfun_of(pr.proj.size(), std::vector<int>(n_atoms, -1));   // J of (d, A, m = -l)
     pl.n_pfun = 0;
     pl.pfun_h.clear();
@@ -200,14 +202,12 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
                             const double dx = pi.C[0] - centre[0], dy = pi.C[1] - centre[1], dz = pi.C[2] - centre[2];
                             if (std::sqrt(dx * dx + dy * dy + dz * dz) >= reach) continue;
                             elem_pimg[e].push_back(pi);
-                            auto &vs = img_vertices[{A, m1, m2, m3}];
-                            for (int c = 0; c < 8; ++c) vs.push_back(corner_vertex(e, c));
+                            for (int c = 0; c < 8; ++c) atom_vertices[A].push_back(corner_vertex(e, c));
                         }
             }
     }
     std::vector<std::vector<int64_t>> extra(pr.proj.empty() ? 0 : pl.nv);
-    for (auto &kv : img_vertices) {
-        auto &vs = kv.second;
+    for (auto &vs : atom_vertices) {
         std::sort(vs.begin(), vs.end());
         vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
         for (int64_t v : vs) extra[v].insert(extra[v].end(), vs.begin(), vs.end());
@@ -250,11 +250,11 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
         auto it = std::lower_bound(b, e, (int32_t)w);
         return pl.bval_off[it - pl.bcol.begin()];
     };
-    // the blocks a projector image couples
+    // the blocks a projector function couples
     pl.nl_blocks.clear();
-    for (auto &kv : img_vertices)
-        for (int64_t v : kv.second)
-            for (int64_t w : kv.second) {
+    for (const auto &vs : atom_vertices)
+        for (int64_t v : vs)
+            for (int64_t w : vs) {
                 auto b = pl.bcol.begin() + pl.brow_ptr[v], e = pl.bcol.begin() + pl.brow_ptr[v + 1];
                 pl.nl_blocks.push_back((int32_t)(std::lower_bound(b, e, (int32_t)w) - pl.bcol.begin()));
             }

@@ -160,13 +160,17 @@ def test_golden_lih_cell_eigenvalues_file():
     assert np.all(np.isfinite(ev))
 
 
-@pytest.mark.parametrize("kind,mesh,p", [("lih", (2, 3, 2), 2), ("one", (3, 3, 2), 1), ("ceal", (2, 2, 2), 2)])
-def test_projector_pattern_holds_the_nonlocal_term(kind, mesh, p):
+@pytest.mark.parametrize("kind,mesh,p,a", [("lih", (2, 3, 2), 2, 4.6), ("one", (3, 3, 2), 1, 4.6),
+                                            ("ceal", (2, 2, 2), 2, 4.6), ("ceal", (6, 5, 6), 1, 8.0),
+                                            ("one", (6, 6, 5), 1, 8.0)])
+def test_projector_pattern_holds_the_nonlocal_term(kind, mesh, p, a):
     """With projectors the BSR pattern also couples every pair of DOFs that
-    reach one projector image: every nonzero of the oracle's dense nonlocal
-    term (eq. disceig3d) lies in a stored block, and the element-coupling
-    blocks are all still there."""
-    prob = W.with_projectors(W.small(kind, mesh=mesh, fe_order=p, levels=0, n=3, a=4.6))
+    reach one projector function, i.e. any image of its atom: every nonzero
+    of the oracle's dense nonlocal term (eq. disceig3d) lies in a stored
+    block, and the element-coupling blocks are all still there.  In the
+    larger cells an atom next to a face or corner is reached through
+    different images by vertices on opposite sides of the cell."""
+    prob = W.with_projectors(W.small(kind, mesh=mesh, fe_order=p, levels=0, n=3, a=a))
     ctx = P.pufe_create(0)
     try:
         P.pufe_set_problem(ctx, prob["lattice"], prob["mesh"], prob["fe_order"], prob["atoms"],

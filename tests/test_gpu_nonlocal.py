@@ -99,3 +99,53 @@ def test_nonlocal_output_types_and_refusals():
     with pytest.raises(P.PufeError):
         P.Batch([p])
     p.close()
+
+
+def _golden_projector_coefficients():
+    """Sample functions, h_J and, per k-point, the oracle's f_J^i on the
+    sample (tests/golden/lih_cell_projector_coefficients.txt, written by
+    make_lih_cell_projector_coefficients.py from the oracle alone)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "lih_cell_projector_coefficients.txt")
+    lines = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    idx = np.array(lines[0][1:], np.int64)
+    h = np.array(lines[1][1:], float)
+    ks, Fs, i = [], [], 2
+    while i < len(lines):
+        ks.append(tuple(map(float, lines[i][1:])))
+        rows = np.array([list(map(float, r)) for r in lines[i + 1:i + 1 + len(h)]])
+        Fs.append(rows[:, 0::2] + 1j * rows[:, 1::2])
+        i += 1 + len(h)
+    return idx, h, ks, Fs
+
+
+def test_lih_cell_full_size_nonlocal_term():
+    """The LiH-like cell at full size (512 elements, 1.52 M points, N = 4888)
+    with its Li s+p and H s projectors: on a sample of 66 functions (those
+    of the vertices next to a Li and an H atom and seeded random ones), the
+    difference between the library's H with and without projectors equals
+    the stored oracle term sum_J h_J f_J^i conj(f_J^j), at Gamma and a
+    general k-point; S is bitwise unchanged."""
+    idx, h, kpts, Fs = _golden_projector_coefficients()
+    say("nonlocal lih_cell full size", len(idx), "sampled functions")
+    out = {}
+    for tag, prob in (("local", W.lih_cell()), ("nonlocal", W.with_projectors(W.lih_cell()))):
+        p = P.Problem(prob).setup()
+        xyz, _, _ = p.quadrature()
+        V = potential_at(xyz, prob)
+        del xyz
+        H, S = p.assemble(V, kpts)
+        sel = torch.from_numpy(idx).cuda()
+        out[tag] = [(p.to_dense(H[k])[sel][:, sel].cpu().numpy(), p.to_dense(S[k])[sel][:, sel].cpu().numpy())
+                    for k in range(len(kpts))]
+        del H, S, V
+        p.close()
+    for k, kap in enumerate(kpts):
+        F = Fs[k]
+        ref = (F * h[:, None]).T @ F.conj()     # [i][j] = sum_J h_J f_J^i conj(f_J^j)
+        diff = out["nonlocal"][k][0] - out["local"][k][0]
+        e = rel(diff, ref)
+        say("lih_cell", kap, "nonlocal term on the sample", e, "max |term|", np.abs(ref).max(),
+            "coupled pairs", int((np.abs(ref) > 0).sum()))
+        assert np.abs(ref).max() > 1e-4 and e < 1e-9
+        assert np.array_equal(out["nonlocal"][k][1], out["local"][k][1])
