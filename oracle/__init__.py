@@ -40,6 +40,7 @@ class _Problem(C.Structure):
         ("enr_re", C.POINTER(C.c_double)),
         ("q_n", C.c_int), ("q_nref", C.c_int), ("q_levels", C.c_int), ("q_mode", C.c_int),
         ("q_dist", C.c_double), ("q_tol", C.c_double),
+        ("enr_nrad", C.POINTER(C.c_int)), ("enr_rad", C.POINTER(C.c_double)),
     ]
 
 
@@ -113,7 +114,10 @@ class Oracle:
         ea = np.array([e["a"] for e in enr] + [0], np.float64)
         erc = np.array([e["rc"] for e in enr] + [0], np.float64)
         ere = np.array([e["re"] for e in enr] + [0], np.float64)
-        self._keep += [pos, spc, es, el, ea, erc, ere]
+        enr_rad = [np.asarray(e.get("radial", ()), np.float64).reshape(-1) for e in enr]
+        enr_n = np.array([len(r) for r in enr_rad] + [0], np.int32)
+        rad = np.ascontiguousarray(np.concatenate(enr_rad + [np.zeros(1)]))
+        self._keep += [pos, spc, es, el, ea, erc, ere, enr_n, rad]
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
         p.n_atoms = len(prob["species"])
@@ -125,6 +129,8 @@ class Oracle:
         p.enr_a = ea.ctypes.data_as(dp)
         p.enr_rc = erc.ctypes.data_as(dp)
         p.enr_re = ere.ctypes.data_as(dp)
+        p.enr_nrad = enr_n.ctypes.data_as(ip)
+        p.enr_rad = rad.ctypes.data_as(dp)
         q = prob["quad"]
         p.q_n, p.q_nref, p.q_levels = int(q["n"]), int(q["n_ref"]), int(q["levels"])
         p.q_mode = MODES[q.get("mode", "geom")]

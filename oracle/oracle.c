@@ -17,6 +17,8 @@
  *  - real, orthonormal spherical harmonics without the Condon-Shortley phase,
  *    written as solid harmonics r^l Y_lm;
  *  - radial functions r^l exp(-a r^2) (1 - (r/rc)^2)^3 for r < rc, 0 beyond,
+ *    or r^l times a cubic spline through tabulated samples times the C^3
+ *    cutoff of section "Partition of unity enrichment functions",
  *    unnormalised;
  *  - a vertex carries all 2l+1 functions of a descriptor of atom A iff its
  *    minimum-image distance to A is strictly below the support radius re;
@@ -41,6 +43,9 @@ struct or_state {
     int *species;
     int *enr_species, *enr_l;
     double *enr_a, *enr_rc, *enr_re;
+    int *enr_nrad;      /* samples of a tabulated radial, 0 = analytic */
+    double **enr_u;     /* tabulated: spline knot values u_j */
+    double **enr_M;     /* tabulated: spline second derivatives at the knots */
     int q_n, q_nref, q_levels, q_mode;
     double q_dist, q_tol;
     int64_t nel, nv, ndof, nqp, nleaves;
@@ -242,6 +247,64 @@ void or_solid_harmonic(int l, int m, const double *r, double *val, double *grad,
 
 /* ------------------------------------------------- enrichment functions */
 
+/* The C^3 cutoff function of section "Partition of unity enrichment
+ * functions": h(r, rc) = 1 + 20 x^7 - 70 x^6 + 84 x^5 - 35 x^4 with
+ * x = r/rc for r <= rc, and 0 beyond. */
+static double cutoff_c3(double r, double rc) {
+    if (r >= rc) return 0.0;
+    double x = r / rc, x2 = x * x, x4 = x2 * x2;
+    return 1.0 + 20.0 * x4 * x2 * x - 70.0 * x4 * x2 + 84.0 * x4 * x - 35.0 * x4;
+}
+
+/* Tabulated radial (section "Partition of unity enrichment functions"): the
+ * radial R(r) is the cubic spline fit of the pseudoatomic radial times the
+ * C^3 cutoff.  The samples t_j are the pseudoatomic radial divided by r^l at
+ * r_j = j rc/(n-1); the spline u interpolates u_j = t_j h(r_j, rc) with end
+ * slopes u'(0) = 0 (the radial over r^l is even) and u'(rc) = 0 (h vanishes
+ * to third order there), and R(r) = r^l u(r).  Second derivatives M_j from
+ * the clamped-spline equations
+ *   M_{j-1} + 4 M_j + M_{j+1} = 6 (u_{j+1} - 2 u_j + u_{j-1}) / d^2,
+ *   2 M_0 + M_1 = 6 (u_1 - u_0) / d^2,
+ *   M_{n-2} + 2 M_{n-1} = -6 (u_{n-1} - u_{n-2}) / d^2,
+ * solved by forward elimination and back substitution. */
+static void spline_fit(int n, double rc, const double *t, double *u, double *M) {
+    double d = rc / (n - 1);
+    for (int j = 0; j < n; ++j) u[j] = t[j] * cutoff_c3(j * d, rc);
+    double *diag = malloc(sizeof(double) * n), *rhs = malloc(sizeof(double) * n);
+    for (int j = 0; j < n; ++j) {
+        diag[j] = (j == 0 || j == n - 1) ? 2.0 : 4.0;
+        if (j == 0) rhs[j] = 6.0 * (u[1] - u[0]) / (d * d);
+        else if (j == n - 1) rhs[j] = -6.0 * (u[n - 1] - u[n - 2]) / (d * d);
+        else rhs[j] = 6.0 * (u[j + 1] - 2.0 * u[j] + u[j - 1]) / (d * d);
+    }
+    /* every off-diagonal entry is 1 */
+    for (int j = 1; j < n; ++j) {
+        double f = 1.0 / diag[j - 1];
+        diag[j] -= f;
+        rhs[j] -= f * rhs[j - 1];
+    }
+    M[n - 1] = rhs[n - 1] / diag[n - 1];
+    for (int j = n - 2; j >= 0; --j) M[j] = (rhs[j] - M[j + 1]) / diag[j];
+    free(diag);
+    free(rhs);
+}
+
+/* u, u', u'' of the spline of descriptor k at r (0 at and beyond rc), in the
+ * interval form u = A u_j + B u_{j+1} + ((A^3 - A) M_j + (B^3 - B) M_{j+1}) d^2/6
+ * with A = (r_{j+1} - r)/d, B = 1 - A. */
+static void spline_eval(const or_state *s, int k, double r, double *u, double *u1, double *u2) {
+    int n = s->enr_nrad[k];
+    double rc = s->enr_rc[k], d = rc / (n - 1);
+    if (r >= rc) { *u = *u1 = *u2 = 0.0; return; }
+    int j = (int)(r / d);
+    if (j > n - 2) j = n - 2;
+    const double *uu = s->enr_u[k], *M = s->enr_M[k];
+    double B = (r - j * d) / d, A = 1.0 - B;
+    *u = A * uu[j] + B * uu[j + 1] + ((A * A * A - A) * M[j] + (B * B * B - B) * M[j + 1]) * d * d / 6.0;
+    *u1 = (uu[j + 1] - uu[j]) / d - (3.0 * A * A - 1.0) / 6.0 * d * M[j] + (3.0 * B * B - 1.0) / 6.0 * d * M[j + 1];
+    *u2 = A * M[j] + B * M[j + 1];
+}
+
 /* Periodic enrichment function (eqs. Psitilde and Psi with f(R) = 1):
  * Psi(x) = sum over lattice translations R of g(|x - tau - R|^2) S_lm(x - tau - R),
  * g(s) = exp(-a s) (1 - s/rc^2)^3 for s < rc^2, else 0.  Every image within
@@ -265,6 +328,27 @@ void or_enrichment(const or_state *s, int atom, int desc, int m, const double *x
                 for (int c = 0; c < 3; ++c) r[c] = x[c] - tau[c] - R[c];
                 double sq = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
                 if (sq >= rc * rc) continue;
+                if (s->enr_nrad[desc] > 0) {
+                    /* tabulated: Psi~ = u(|r|) S_lm(r), with
+                     * grad u = u' r_hat and
+                     * hess u = u'' r_hat r_hat^T + (u'/|r|) (I - r_hat r_hat^T) */
+                    double rr = sqrt(sq), u, u1, u2;
+                    spline_eval(s, desc, rr, &u, &u1, &u2);
+                    double S, dS[3], hS[9], rh[3] = {0, 0, 0}, u1r = u2;   /* u'/|r| -> u''(0) at r = 0 */
+                    if (rr > 0.0) {
+                        for (int i = 0; i < 3; ++i) rh[i] = r[i] / rr;
+                        u1r = u1 / rr;
+                    }
+                    or_solid_harmonic(l, m, r, &S, dS, hS);
+                    v += u * S;
+                    for (int i = 0; i < 3; ++i) g3[i] += u1 * rh[i] * S + u * dS[i];
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j) {
+                            double hu = (u2 - u1r) * rh[i] * rh[j] + (i == j ? u1r : 0.0);
+                            h9[i * 3 + j] += hu * S + u1 * (rh[i] * dS[j] + dS[i] * rh[j]) + u * hS[i * 3 + j];
+                        }
+                    continue;
+                }
                 double e = exp(-a * sq), c = 1.0 - sq / (rc * rc);
                 double g = e * c * c * c;
                 double g1 = -a * e * c * c * c - 3.0 * e * c * c / (rc * rc);
@@ -679,6 +763,10 @@ int or_setup(const or_problem *p, or_state **out) {
     s->enr_a = malloc(sizeof(double) * ne);
     s->enr_rc = malloc(sizeof(double) * ne);
     s->enr_re = malloc(sizeof(double) * ne);
+    s->enr_nrad = calloc(ne, sizeof(int));
+    s->enr_u = calloc(ne, sizeof(double *));
+    s->enr_M = calloc(ne, sizeof(double *));
+    const double *rad = p->enr_rad;
     for (int k = 0; k < p->n_enr; ++k) {
         s->enr_species[k] = p->enr_species[k];
         s->enr_l[k] = p->enr_l[k];
@@ -686,6 +774,14 @@ int or_setup(const or_problem *p, or_state **out) {
         s->enr_rc[k] = p->enr_rc[k];
         s->enr_re[k] = p->enr_re[k];
         if (s->enr_l[k] < 0 || s->enr_l[k] > 3) { or_free(s); return -4; }
+        int n = p->enr_nrad ? p->enr_nrad[k] : 0;
+        if (n == 0) continue;
+        if (n < 4 || !rad || !(s->enr_rc[k] > 0)) { or_free(s); return -5; }
+        s->enr_nrad[k] = n;
+        s->enr_u[k] = malloc(sizeof(double) * n);
+        s->enr_M[k] = malloc(sizeof(double) * n);
+        spline_fit(n, s->enr_rc[k], rad, s->enr_u[k], s->enr_M[k]);
+        rad += n;
     }
     s->q_n = p->q_n;
     s->q_nref = p->q_nref;
@@ -769,6 +865,12 @@ int or_setup(const or_problem *p, or_state **out) {
 void or_free(or_state *s) {
     if (!s) return;
     free(s->pos); free(s->species);
+    if (s->enr_u)
+        for (int k = 0; k < s->n_enr; ++k) {
+            free(s->enr_u[k]);
+            free(s->enr_M[k]);
+        }
+    free(s->enr_u); free(s->enr_M); free(s->enr_nrad);
     free(s->enr_species); free(s->enr_l); free(s->enr_a); free(s->enr_rc); free(s->enr_re);
     free(s->vf_off); free(s->vf); free(s->dof_off);
     free(s->leaf_off); free(s->leaf_level); free(s->leaf_ijk); free(s->qp_off);

@@ -9,7 +9,10 @@
  *   - the Galerkin matrices H and S of the discrete generalized eigenproblem
  *     (eq. disceig3d) under Bloch boundary conditions (eq. bloch, wbpspace),
  *   - the adjoint of that assembly (dL/dV and dL/dtau for L = Re<P,H> + Re<Q,S>),
- *   - the separable nonlocal term of H (eq. disceig3d).
+ *   - the separable nonlocal term of H (eq. disceig3d),
+ *   - tabulated radial functions: a cubic spline through samples of the
+ *     radial times the C^3 cutoff (section "Partition of unity enrichment
+ *     functions").
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
  * load this library.  It shares no code, header or table with the HIP library.
  */
@@ -34,6 +37,10 @@ typedef struct {
     const double *enr_a, *enr_rc, *enr_re;
     int q_n, q_nref, q_levels, q_mode;  /* q_mode 0 = geometric, 1 = error-driven */
     double q_dist, q_tol;
+    /* tabulated radials (may be NULL: every descriptor analytic): enr_nrad[k]
+     * samples of descriptor k (0 = analytic radial), concatenated in enr_rad */
+    const int *enr_nrad;
+    const double *enr_rad;
 } or_problem;
 
 typedef struct or_state or_state;

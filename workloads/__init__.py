@@ -18,6 +18,10 @@ species_info list of {"name", "Z", "rloc"} (used only by the potential).
 enrichments  list of {"species", "l", "a", "rc", "re"}: each descriptor adds
              the 2l+1 functions r^l exp(-a r^2) (1-(r/rc)^2)^3 Y_lm around
              every atom of that species, on every vertex closer than re.
+             An optional "radial" (list of n >= 4 samples of the pseudoatomic
+             radial divided by r^l at r_j = j rc/(n-1)) replaces the analytic
+             radial by r^l times the cubic spline through the samples times
+             the C^3 cutoff.
 quad         {"n", "n_ref", "levels", "mode" ("geom"|"error"), "dist", "tol"}.
 kpts         list of reduced k-points kappa (k = sum kappa_i b_i).
 n_eig        number of lowest eigenpairs wanted.
@@ -31,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "single_atom_cube", "lih_cell", "lih_lattice_sweep", "ceal_cell", "lih_supercell", "small", "lih_table1",
-    "ceal_triclinic", "PAPER_KPTS", "with_projectors",
+    "ceal_triclinic", "PAPER_KPTS", "with_projectors", "with_tabulated_radials",
     "mp2", "ceal_kpoints", "jitter", "adjoint_factor", "with_lattice_constant",
     "orthorhombic", "random_small",
 ]
@@ -245,6 +249,19 @@ def with_projectors(prob, scale_rc: float = 1.0):
             proj.append({"species": sp, "l": l, "a": a, "rc": rc * scale_rc, "h": h})
     out["projectors"] = proj
     out["name"] = prob["name"] + "+nl"
+    return out
+
+
+def with_tabulated_radials(prob, n_samples: int = 48):
+    """A copy of prob whose enrichment radials are given as tables, as a
+    radial solver would output them: each descriptor gets "radial", the
+    n_samples values of its pseudoatomic radial divided by r^l, here the
+    Gaussian exp(-a r^2), at r_j = j rc / (n_samples - 1)."""
+    out = copy.deepcopy(prob)
+    for e in out["enrichments"]:
+        r = np.linspace(0.0, e["rc"], n_samples)
+        e["radial"] = np.exp(-e["a"] * r * r).tolist()
+    out["name"] = prob["name"] + "+tab"
     return out
 
 
