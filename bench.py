@@ -260,10 +260,12 @@ def bsr_rows_cols(lay):
     return np.concatenate(rows), np.concatenate(cols)
 
 
-def leg_batch(reps=5):
+def leg_batch(tune_cache, reps=5):
     """The persistent, graph-captured batch over the lattice-constant sweep
     (11 LiH-like cells a = 6.8 .. 8.4 bohr x 8 Monkhorst-Pack k-points, 88
-    complex128 H and S), FP64: replays timed with HIP events."""
+    H and S): each cell tuned first, then replays timed with HIP events, FP64
+    with complex128 outputs and bf16x6 with complex64 outputs (errors of the
+    latter against the former)."""
     import torch
     import paper_1611_00731_amd as P
     import workloads as W
@@ -272,6 +274,7 @@ def leg_batch(reps=5):
     ps, Vs, flops, nel = [], [], 0.0, 0
     for pr in probs:
         p = P.Problem(pr).setup()
+        P.pufe_tune(p.ctx, "fp64", tune_cache)
         xyz, _, _ = p.quadrature()
         Vs.append(potential_at(xyz, pr))
         lay = p.layout()
@@ -281,22 +284,31 @@ def leg_batch(reps=5):
         nel += p.sizes["n_elem"]
         ps.append(p)
     b = P.Batch(ps)
-    Hs, Ss = b.alloc(len(kpts), device="cuda")
-    b.assemble(Vs, kpts, Hs, Ss)            # capture
-    b.assemble(Vs, kpts, Hs, Ss)
-    torch.cuda.synchronize()
     st = torch.cuda.current_stream()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record(st)
-    for _ in range(reps):
-        b.assemble(Vs, kpts, Hs, Ss)
-    t1.record(st)
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
-    out = {"workload": "11 lattice constants x 8 k-points (88 outputs), one graph replay", "ms": ms,
-           "elements_per_s": nel * len(kpts) / (ms * 1e-3), "unique_contractions_per_s": nel / (ms * 1e-3),
-           "alg_tflops_whole_batch": flops / (ms * 1e-3) / 1e12,
-           "frac_of_fp64_peak_whole_batch": flops / (ms * 1e-3) / 1e12 / PEAK["fp64"]}
+    out = {"workload": "11 lattice constants x 8 k-points (88 outputs), one graph replay, each cell tuned"}
+    ref = None
+    for prec, dt in (("fp64", "c128"), ("bf16x6", "c64")):
+        Hs, Ss = b.alloc(len(kpts), out_dtype=dt, device="cuda")
+        b.assemble(Vs, kpts, Hs, Ss, precision=prec, out_dtype=dt)            # capture
+        b.assemble(Vs, kpts, Hs, Ss, precision=prec, out_dtype=dt)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(st)
+        for _ in range(reps):
+            b.assemble(Vs, kpts, Hs, Ss, precision=prec, out_dtype=dt)
+        t1.record(st)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        row = {"ms": ms, "elements_per_s": nel * len(kpts) / (ms * 1e-3),
+               "unique_contractions_per_s": nel / (ms * 1e-3),
+               "alg_tflops_whole_batch": flops / (ms * 1e-3) / 1e12,
+               "frac_of_peak_whole_batch": flops / (ms * 1e-3) / 1e12 / PEAK[prec]}
+        if ref is None:
+            ref = (Hs, Ss)
+        else:
+            row["H_rel_err_vs_fp64"] = max(rel_err(h.double(), r) for h, r in zip(Hs, ref[0]))
+            row["S_rel_err_vs_fp64"] = max(rel_err(s_.double(), r) for s_, r in zip(Ss, ref[1]))
+        out[prec + "_" + dt] = row
     b.close()
     for p in ps:
         p.close()
@@ -360,6 +372,45 @@ def leg_backward(reps=3):
                      "dLdV_rel_err_vs_fp64": float((dVs - dV).norm() / dV.norm()),
                      "dLdR_max_err_rel_vs_fp64": float((dRs - dR).abs().max() / dR.abs().max())}
     p.close()
+    return out
+
+
+def leg_nonlocal(P, W, potential_at, steps=10, warmup=2):
+    """The LiH-like cell with its synthetic separable projectors (Li: s and p,
+    H: s; eq. disceig3d): whole FP64 assembly with the nonlocal term against
+    the same assembly without it, and the projector-coefficient kernels."""
+    import torch
+    base = W.lih_cell()
+    out = {"workload": "LiH-like cell (512 elements, 1.52 M points) with Li s+p and H s projectors, Gamma, "
+                       "H+S complex128, FP64"}
+    for tag, prob in (("local", base), ("nonlocal", W.with_projectors(base))):
+        p = P.Problem(prob).setup()
+        xyz, _, _ = p.quadrature()
+        V = potential_at(xyz, prob)
+        del xyz
+        sz = p.sizes
+        kpts = prob["kpts"]
+        H = torch.empty((len(kpts), sz["nnz"], 2), dtype=torch.float64, device="cuda")
+        S = torch.empty_like(H)
+        ms, _, _ = time_assembly(P, p, V, kpts, "fp64", H, S, steps, warmup)
+        row = {"ms_per_step": ms, "nnz": sz["nnz"]}
+        if tag == "nonlocal":
+            P.pufe_enable_timing(p.ctx, True)
+            P.pufe_kernel_times(p.ctx, reset=True)
+            for _ in range(steps):
+                P.pufe_assemble(p.ctx, V, kpts, "fp64", "c128", H, S)
+            torch.cuda.synchronize()
+            kms, kc = P.pufe_kernel_times(p.ctx, reset=True)
+            P.pufe_enable_timing(p.ctx, False)
+            row["projector_coefficient_kernels_ms"] = kms[4] / steps
+            row["scatter_and_nonlocal_update_ms"] = kms[1] / steps
+            row["n_projector_functions"] = sum((2 * q["l"] + 1) * prob["species"].count(q["species"])
+                                               for q in prob["projectors"])
+        out[tag] = row
+        del H, S
+        p.close()
+    out["nonlocal_extra_ms"] = out["nonlocal"]["ms_per_step"] - out["local"]["ms_per_step"]
+    out["extra_nnz"] = out["nonlocal"]["nnz"] - out["local"]["nnz"]
     return out
 
 
@@ -520,7 +571,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.precision],
                      "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
                      "traffic": traffic if fp64 else None,
-                     "kernel": "contract_f64_kernel" if fp64 else "contract_split_kernel",
+                     "kernel": ("contract_f64_wide_kernel + contract_f64_kernel (the two launches of one "
+                                "contraction, timed as one region)") if fp64 else "contract_split_kernel",
                      "kernel_ms": contract_ms, "alg_flops_per_launch": alg_flops,
                      "mfma_busy_frac": busy if fp64 else None,
                      "mfma_executed_flops_per_launch": executed if fp64 else None},
@@ -554,9 +606,11 @@ def main():
         if do_eig:
             out["eig_err"] = out["extra"]["lih_cell"].pop("eig_err")
         log("batch leg (lattice sweep)")
-        out["extra"]["batch_sweep"] = leg_batch()
+        out["extra"]["batch_sweep"] = leg_batch(tune_cache)
         log("adjoint leg (64-atom supercell)")
         out["extra"]["adjoint"] = leg_backward()
+        log("nonlocal leg (LiH-like cell with projectors)")
+        out["extra"]["nonlocal"] = leg_nonlocal(P, W, potential_at)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob, n_out)

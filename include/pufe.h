@@ -78,19 +78,29 @@ extern "C" {
 
 typedef struct pufe_ctx pufe_ctx;
 
-/* One enrichment descriptor: the 2l+1 functions
- *   r^l exp(-a r^2) (1 - (r/rc)^2)^3 Y_lm(r_hat)   (r < rc, zero beyond),
- * real orthonormal Y_lm without Condon-Shortley phase, centred on every atom
- * of `species` and summed over lattice images (eqs. Psitilde, Psi with
+/* One enrichment descriptor: the 2l+1 functions R(r) Y_lm(r_hat), real
+ * orthonormal Y_lm without Condon-Shortley phase, centred on every atom of
+ * `species` and summed over lattice images (eqs. Psitilde, Psi with
  * f(R) = 1).  A vertex carries them iff its minimum-image distance to the
- * atom is below re (section "Partition of unity enrichment functions"). */
+ * atom is below re (section "Partition of unity enrichment functions").
+ * The radial R (zero for r >= rc):
+ *   kind 0 (analytic):  R(r) = r^l exp(-a r^2) (1 - (r/rc)^2)^3;
+ *   kind 1 (tabulated, the paper's form): R(r) = r^l u(r), u the cubic spline
+ *     fit of the pseudoatomic radial times the C^3 cutoff
+ *     h(r, rc) = 1 + 20 x^7 - 70 x^6 + 84 x^5 - 35 x^4 (x = r/rc): radial[j],
+ *     j = 0 .. n_radial-1, are samples of the pseudoatomic radial divided by
+ *     r^l at r_j = j rc/(n_radial-1); u interpolates radial[j] h(r_j, rc) with
+ *     end slopes u'(0) = 0 and u'(rc) = 0.  `a` is not used.
+ * The samples are copied by pufe_set_problem (caller-owned host memory). */
 typedef struct {
     int species;
     int l;            /* 0..3 */
-    int radial_kind;  /* 0: the analytic radial above (the only kind supported) */
-    double a;         /* Gaussian exponent, > 0 */
+    int radial_kind;  /* 0 analytic, 1 tabulated */
+    double a;         /* kind 0: Gaussian exponent, > 0 */
     double rc;        /* cutoff radius, > 0 */
     double re;        /* support radius, >= 0 */
+    const double *radial;  /* kind 1: n_radial finite samples (host), else NULL */
+    int n_radial;          /* kind 1: 4 .. 4096 */
 } pufe_enrichment;
 
 /* One projector descriptor of the separable nonlocal potential (eq.
@@ -278,10 +288,14 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path);
  * constant of an equation-of-state sweep), all set up on the same device.
  * pufe_batch_assemble runs, for every problem, the assembly of pufe_assemble
  * at the same n_k k-points: persistent contraction launches whose work
- * groups pull the work items of all problems from one queue (largest first;
- * in FP64 up to two launches, the problems whose stage fits two work groups
- * per CU with 24-point stages in one and the rest in the other), then one
- * atomic-free scatter launch per element colour covering all problems.  The sequence is captured once into a HIP graph and replayed;
+ * groups pull the work items of all problems from one queue (largest first).
+ * Each problem keeps the work items and the stage length of its own plan
+ * (those pufe_tune chose, else the defaults); in FP64 the problems of one
+ * stage length whose combined stage fits two work groups per CU share one
+ * launch and the rest another, so up to two launches per stage length, plus
+ * one for the items of elements of more than 80 functions.  Then one
+ * atomic-free scatter launch per element colour covers all problems.  The
+ * sequence is captured once into a HIP graph and replayed;
  * a call with different pointers, k-points, precision or dtype recaptures.
  * d_V, d_H, d_S are host arrays of n device pointers (d_S may be NULL).  The
  * contexts must outlive the batch.  A context that is defined, set up or

@@ -39,7 +39,8 @@ class PufeError(RuntimeError):
 
 class pufe_enrichment(C.Structure):
     _fields_ = [("species", C.c_int), ("l", C.c_int), ("radial_kind", C.c_int),
-                ("a", C.c_double), ("rc", C.c_double), ("re", C.c_double)]
+                ("a", C.c_double), ("rc", C.c_double), ("re", C.c_double),
+                ("radial", C.POINTER(C.c_double)), ("n_radial", C.c_int)]
 
 
 class pufe_projector(C.Structure):
@@ -144,9 +145,17 @@ def pufe_set_problem(ctx, lattice, mesh, fe_order, pos, species, enrichments, qu
     spc = np.ascontiguousarray(np.asarray(species, np.int32).reshape(-1))
     n_atoms = spc.size
     enr = (pufe_enrichment * max(1, len(enrichments)))()
+    keep = []   # sample arrays stay alive until the call has copied them
     for i, e in enumerate(enrichments):
-        enr[i] = pufe_enrichment(int(e["species"]), int(e["l"]), int(e.get("radial_kind", 0)),
-                                 float(e["a"]), float(e["rc"]), float(e["re"]))
+        tab = e.get("radial")
+        kind = int(e.get("radial_kind", 0 if tab is None else 1))
+        ptr, n = None, 0
+        if tab is not None:
+            arr = np.ascontiguousarray(np.asarray(tab, np.float64).reshape(-1))
+            keep.append(arr)
+            ptr, n = arr.ctypes.data_as(C.POINTER(C.c_double)), arr.size
+        enr[i] = pufe_enrichment(int(e["species"]), int(e["l"]), kind,
+                                 float(e.get("a", 1.0)), float(e["rc"]), float(e["re"]), ptr, n)
     q = pufe_quad(int(quad["n"]), int(quad.get("n_ref", quad["n"] + 1)), int(quad["levels"]),
                   QUAD_MODE[quad.get("mode", "geom")], float(quad.get("dist", 0.0)),
                   float(quad.get("tol", 1e-6)))

@@ -52,7 +52,7 @@ __device__ __forceinline__ void cell_group_test(const KParams &kp, const GroupDe
             x[c] = org[c] + 0.5 * (xi[0] + 1.0) * kp.E[c] + 0.5 * (xi[1] + 1.0) * kp.E[3 + c] +
                    0.5 * (xi[2] + 1.0) * kp.E[6 + c];
         double psi[NM], gp[3 * NM];
-        group_eval_point<L>(G, img, x, psi, gp);
+        group_eval_point<L>(G, img, kp.spl, x, psi, gp);
         const int s = base ? 0 : 1;
 #pragma unroll
         for (int m = 0; m < NM; ++m) {

@@ -59,8 +59,8 @@ __global__ __launch_bounds__(256) void gather_adjoint_kernel(const KParams kp, c
 // o[(m * 10 + c) * Q], c = 0 value, 1..3 gradient, 4..9 Hessian xx yy zz xy xz yz.
 // Hessian of g(s) S(r): 4 g'' r r^T S + 2 g' (S I + r grad S^T + grad S r^T) + g Hess S.
 template <int L, int Q>
-__device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double *__restrict__ img, const double *x,
-                                                double *o) {
+__device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double *__restrict__ img,
+                                                const double *__restrict__ spl, const double *x, double *o) {
     constexpr int NM = 2 * L + 1;
     double acc[NM][10];
 #pragma unroll
@@ -73,10 +73,15 @@ __device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double 
         const double r[3] = {x[0] - c0[3 * k], x[1] - c0[3 * k + 1], x[2] - c0[3 * k + 2]};
         const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         if (s >= rc2) continue;
-        const double ex = exp(-G.a * s), c = 1.0 - s * inv_rc2, c2 = c * c;
-        const double g0 = ex * c2 * c;
-        const double g1 = -ex * c2 * (G.a * c + 3.0 * inv_rc2);
-        const double g2 = ex * c * (G.a * G.a * c2 + 6.0 * G.a * c * inv_rc2 + 6.0 * inv_rc2 * inv_rc2);
+        double g0, g1, g2;
+        if (G.nspl > 0) {
+            spline_radial<true>(G, spl, s, g0, g1, g2);
+        } else {
+            const double ex = exp(-G.a * s), c = 1.0 - s * inv_rc2, c2 = c * c;
+            g0 = ex * c2 * c;
+            g1 = -ex * c2 * (G.a * c + 3.0 * inv_rc2);
+            g2 = ex * c * (G.a * G.a * c2 + 6.0 * G.a * c * inv_rc2 + 6.0 * inv_rc2 * inv_rc2);
+        }
         double S[7], dS[21], hS[42];
         solid_harmonics(L, r[0], r[1], r[2], S, dS);
         solid_harmonics_hess(L, r[0], r[1], r[2], hS);
@@ -381,10 +386,10 @@ __global__ __launch_bounds__(256) void backward_kernel(
                        0.5 * (xi[2] + 1.0) * kp.E[6 + d];
             double *o = sPsi + (size_t)G.fbase * 10 * Q + q;
             switch (G.l) {
-                case 0: group_eval_hess<0, Q>(G, sImg, x, o); break;
-                case 1: group_eval_hess<1, Q>(G, sImg, x, o); break;
-                case 2: group_eval_hess<2, Q>(G, sImg, x, o); break;
-                default: group_eval_hess<3, Q>(G, sImg, x, o); break;
+                case 0: group_eval_hess<0, Q>(G, sImg, kp.spl, x, o); break;
+                case 1: group_eval_hess<1, Q>(G, sImg, kp.spl, x, o); break;
+                case 2: group_eval_hess<2, Q>(G, sImg, kp.spl, x, o); break;
+                default: group_eval_hess<3, Q>(G, sImg, kp.spl, x, o); break;
             }
         }
         __syncthreads();

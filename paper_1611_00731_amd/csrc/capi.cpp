@@ -72,6 +72,7 @@ struct pufe_ctx {
     int64_t part_slots = 0;
     double tune_items = 4096.0;
     int tune_block = kBlockTiles;
+    bool tuned = false;             // item plan and stage length chosen by pufe_tune
     int contract_q = 24;            // points per LDS stage of the FP64 contraction (16, 24 or 32)
     int max_item_leaves = 1;
     // bumped whenever the device tables or work items are rebuilt (problem,
@@ -80,6 +81,7 @@ struct pufe_ctx {
     DevBuf<ElemDev> d_elems;
     DevBuf<GroupDev> d_groups;
     DevBuf<double> d_img, d_pos, d_partial;
+    DevBuf<double> d_spl;           // coefficients of the tabulated radials
     DevBuf<int32_t> d_edof, d_leaf_elem, d_color_elems, d_brow, d_bcol;
     DevBuf<int2> d_scat;
     std::vector<int2> reduce;       // (element, tile pair) of every element with several K-chunks
@@ -207,6 +209,16 @@ int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], 
     pr.pos.assign(pos, pos + 3 * (size_t)n_atoms);
     pr.species.assign(species, species + n_atoms);
     pr.enr.assign(enr, enr + n_enr);
+    pr.radial.assign(n_enr, {});
+    for (int k = 0; k < n_enr; ++k) {   // keep a copy of the samples, never the caller's pointer
+        if (enr[k].radial_kind == 1) {
+            if (!enr[k].radial || enr[k].n_radial < 0 || enr[k].n_radial > 4096)
+                return fail(ctx, PUFE_ERR_INVALID_ARG, "a tabulated radial needs 4..4096 samples");
+            pr.radial[k].assign(enr[k].radial, enr[k].radial + enr[k].n_radial);
+        }
+        pr.enr[k].radial = nullptr;
+        pr.enr[k].n_radial = (int)pr.radial[k].size();
+    }
     pr.quad = *quad;
     for (double v : pr.pos)
         if (!std::isfinite(v)) return fail(ctx, PUFE_ERR_INVALID_ARG, "non-finite atom position");
@@ -432,6 +444,8 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     const int64_t nel = pl.nel;
     const int n_atoms = (int)ctx->prob.species.size();
     CHECK_HIP(ctx, ctx->d_pos.upload(ctx->prob.pos, st), "upload positions");
+    CHECK_HIP(ctx, ctx->d_spl.upload(pl.spl, st), "upload radial tables");
+    pl.kp.spl = ctx->d_spl.p;
     CHECK_HIP(ctx, ctx->d_leaf_count.alloc(nel + 1), "alloc leaf counts");
     CHECK_HIP(ctx, ctx->d_leaf_off.alloc(nel + 1), "alloc leaf offsets");
     const double L[3] = {pl.lat[0], pl.lat[4], pl.lat[8]};
@@ -677,11 +691,11 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
     } else {
         TimedRegion tr(ctx, 0, st);
         // wide items first: they are the longest
-        CHECK_HIP(ctx, launch_contract_wide(pl.max_l, pl.kp, (int)ctx->items_wide.size(), ctx->d_items_wide.p,
+        CHECK_HIP(ctx, launch_contract_wide(pl.max_l, !pl.spl.empty(), pl.kp, (int)ctx->items_wide.size(), ctx->d_items_wide.p,
                                             ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                             ctx->d_leaves.p, d_V, partial, ctx->lds_wide, st),
                   "contraction (wide items)");
-        CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, pl.kp, (int)ctx->items.size(), ctx->d_items.p,
+        CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, !pl.spl.empty(), pl.kp, (int)ctx->items.size(), ctx->d_items.p,
                                            ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                            ctx->d_leaves.p, d_V, partial, ctx->lds, st),
                   "contraction");
@@ -1038,6 +1052,7 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
                 ctx->tune_block = block;
                 ctx->contract_q = qv;
                 ctx->wide_tiles = wide;
+                ctx->tuned = true;
                 plan_items(ctx, items, block);
                 return upload_items(ctx, nullptr);
             }
@@ -1112,6 +1127,7 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
     ctx->tune_block = best_block;
     ctx->contract_q = best_q;
     ctx->wide_tiles = best_wide;
+    ctx->tuned = true;
     plan_items(ctx, best_items, best_block);
     int rc = upload_items(ctx, nullptr);
     if (rc != PUFE_OK) return rc;
@@ -1137,19 +1153,25 @@ int pufe_tune(pufe_ctx *ctx, int precision, const char *cache_path) {
     return PUFE_OK;
 }
 
+// stage lengths of the batch's FP64 classes, longest first; each has a class
+// of problems sharing a CU two work groups at a time and one of the rest
+static const int kBatchQ[3] = {32, 24, 16};
+constexpr int kBatchClasses = 6;
+
 struct pufe_batch {
     std::vector<pufe_ctx *> ctxs;
     std::vector<uint64_t> gens;             // plan generation of each context at creation
     int device = 0;
     std::vector<ItemDev> items, items_split;
     std::vector<std::vector<int4>> lists;   // per colour: (problem, element, tile pair)
-    // FP64 items in up to two classes, each a persistent launch of its own:
-    // class 0 holds the problems whose stages fit two work groups per CU at
-    // 24 points, class 1 the rest (items [item_off[c], item_off[c + 1]))
-    size_t lds_f64[2] = {0, 0}, lds_split[2] = {0, 0};
-    int max_l = 0, q[2] = {24, 16};
-    int grid_f64[2] = {0, 0}, grid_split[2] = {0, 0};
-    int64_t item_off[3] = {0, 0, 0};
+    // FP64 items in up to kBatchClasses classes, each a persistent launch of
+    // its own (items [item_off[c], item_off[c + 1])): per stage length, the
+    // problems whose combined stage fits two work groups per CU, then the rest
+    size_t lds_f64[kBatchClasses] = {}, lds_split[2] = {0, 0};
+    int max_l = 0, q[kBatchClasses] = {};
+    bool tab = false;                       // some problem has tabulated radials
+    int grid_f64[kBatchClasses] = {}, grid_split[2] = {0, 0};
+    int64_t item_off[kBatchClasses + 1] = {};
     // wide items of all problems (8-wave persistent launch)
     std::vector<ItemDev> items_wide;
     size_t lds_wide = 0;
@@ -1212,15 +1234,19 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     if (hipSetDevice(b->device) != hipSuccess) { delete b; return PUFE_ERR_HIP; }
     int max_rows_split = 16, max_nfun = 1, max_img = 0, max_leaves_split = 1, max_n3 = 1;
     b->lists.assign(27, {});
-    // FP64 classes: problems in order of their own 24-point stage size join
-    // class 0 while the class's combined stage still fits two work groups
-    // per CU; the others form class 1
-    std::vector<int> cls(n, 1);
-    {
+    // FP64 classes.  Each problem keeps its own stage length (the one pufe_tune
+    // chose, else the library default); the problems of one length, in order of
+    // their own stage size, join that length's first class while the class's
+    // combined stage still fits two work groups per CU, the others its second.
+    std::vector<int> cls(n, 0);
+    for (int qi = 0; qi < 3; ++qi) {
+        const int qv = kBatchQ[qi];
         std::vector<std::pair<size_t, int>> by_lds;
         for (int i = 0; i < n; ++i) {
             const pufe_ctx *c = ctxs[i];
-            by_lds.push_back({contract_lds_bytes(24, c->max_rows, std::max(c->plan.max_nfun, 1), c->plan.max_img,
+            const int qc = contract_q_supported(c->contract_q) ? c->contract_q : 24;
+            if (qc != qv) continue;
+            by_lds.push_back({contract_lds_bytes(qv, c->max_rows, std::max(c->plan.max_nfun, 1), c->plan.max_img,
                                                  c->max_item_leaves, c->plan.kp.n3), i});
         }
         std::stable_sort(by_lds.begin(), by_lds.end());
@@ -1229,19 +1255,22 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
             const pufe_ctx *c = ctxs[pr.second];
             const int r2 = std::max(r, c->max_rows), f2 = std::max(f, c->plan.max_nfun), im2 = std::max(im, c->plan.max_img);
             const int lv2 = std::max(lv, c->max_item_leaves), n32 = std::max(n3, c->plan.kp.n3);
-            if (persistent_blocks_per_cu(contract_lds_bytes(24, r2, f2, im2, lv2, n32)) < 2) continue;
+            cls[pr.second] = 2 * qi + 1;
+            if (persistent_blocks_per_cu(contract_lds_bytes(qv, r2, f2, im2, lv2, n32)) < 2) continue;
             r = r2, f = f2, im = im2, lv = lv2, n3 = n32;
-            cls[pr.second] = 0;
+            cls[pr.second] = 2 * qi;
         }
     }
-    for (int pass = 0; pass < 4; ++pass) {
-        // pass 0, 1: FP64 items of class 0, 1; pass 2: split items; pass 3: wide FP64 items
+    for (int pass = 0; pass < kBatchClasses + 2; ++pass) {
+        // passes 0 .. kBatchClasses-1: FP64 items of each class; then the
+        // split items and the wide FP64 items
+        const int split_pass = kBatchClasses, wide_pass = kBatchClasses + 1;
         std::vector<std::pair<double, size_t>> order;
         std::vector<ItemDev> all;
         for (int i = 0; i < n; ++i) {
             pufe_ctx *c = ctxs[i];
-            if (pass < 2 && cls[i] != pass) continue;
-            for (const ItemDev &it0 : pass < 2 ? c->items : (pass == 2 ? c->items_split : c->items_wide)) {
+            if (pass < split_pass && cls[i] != pass) continue;
+            for (const ItemDev &it0 : pass < split_pass ? c->items : (pass == split_pass ? c->items_split : c->items_wide)) {
                 ItemDev it = it0;
                 it.ctx = i;
                 order.push_back({item_cost(it, c->plan.kp.n3), all.size()});
@@ -1250,11 +1279,13 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         }
         std::stable_sort(order.begin(), order.end(),
                          [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &c) { return a.first > c.first; });
-        std::vector<ItemDev> &dst = pass < 2 ? b->items : (pass == 2 ? b->items_split : b->items_wide);
+        std::vector<ItemDev> &dst = pass < split_pass ? b->items : (pass == split_pass ? b->items_split : b->items_wide);
         for (auto &o : order) dst.push_back(all[o.second]);
-        if (pass < 2) b->item_off[pass + 1] = (int64_t)b->items.size();
+        if (pass < split_pass) b->item_off[pass + 1] = (int64_t)b->items.size();
     }
-    int cr[2] = {16, 16}, cf[2] = {1, 1}, ci[2] = {0, 0}, cl[2] = {1, 1}, cn3[2] = {1, 1};
+    int cr[kBatchClasses], cf[kBatchClasses], ci[kBatchClasses], cl[kBatchClasses], cn3[kBatchClasses];
+    bool all_tuned[kBatchClasses];
+    for (int k = 0; k < kBatchClasses; ++k) cr[k] = 16, cf[k] = 1, ci[k] = 0, cl[k] = 1, cn3[k] = 1, all_tuned[k] = true;
     for (int i = 0; i < n; ++i) {
         pufe_ctx *c = ctxs[i];
         const int k = cls[i];
@@ -1263,12 +1294,14 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         ci[k] = std::max(ci[k], c->plan.max_img);
         cl[k] = std::max(cl[k], c->max_item_leaves);
         cn3[k] = std::max(cn3[k], c->plan.kp.n3);
+        all_tuned[k] = all_tuned[k] && c->tuned;
         max_rows_split = std::max(max_rows_split, c->max_rows_split);
         max_nfun = std::max(max_nfun, c->plan.max_nfun);
         max_img = std::max(max_img, c->plan.max_img);
         max_leaves_split = std::max(max_leaves_split, c->max_item_leaves_split);
         max_n3 = std::max(max_n3, c->plan.kp.n3);
         b->max_l = std::max(b->max_l, c->plan.max_l);
+        b->tab = b->tab || !c->plan.spl.empty();
         if (!c->items_wide.empty()) b->lds_wide = std::max(b->lds_wide, c->lds_wide);
         for (int64_t e = 0; e < c->plan.nel; ++e) {
             const int T = (c->plan.elems[e].nloc + 15) / 16;
@@ -1285,16 +1318,20 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
     }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess || ncu < 1) ncu = 256;
-    // class 0: 24-point stages, two work groups per CU; class 1: 24-point
-    // stages when two work groups still share a CU, else 16
-    for (int k = 0; k < 2; ++k) {
-        b->q[k] = 24;
-        b->lds_f64[k] = contract_lds_bytes(24, cr[k], cf[k], ci[k], cl[k], cn3[k]);
-        if (k == 1 && persistent_blocks_per_cu(b->lds_f64[k]) < 2) {
+    // a first class runs at its stage length, two work groups per CU.  A
+    // second class keeps its length when every member was tuned (the tuner
+    // timed that length against its LDS occupancy) or when two work groups
+    // still share a CU; otherwise it runs 16-point stages, two per CU.
+    for (int k = 0; k < kBatchClasses; ++k) {
+        const int qv = kBatchQ[k / 2];
+        b->q[k] = qv;
+        b->lds_f64[k] = contract_lds_bytes(qv, cr[k], cf[k], ci[k], cl[k], cn3[k]);
+        const bool keep = all_tuned[k] && b->lds_f64[k] <= kMaxDynLds;
+        if ((k & 1) && qv > 16 && !keep && persistent_blocks_per_cu(b->lds_f64[k]) < 2) {
             b->q[k] = 16;
             b->lds_f64[k] = contract_lds_bytes(16, cr[k], cf[k], ci[k], cl[k], cn3[k]);
         }
-        b->grid_f64[k] = ncu * persistent_blocks_per_cu(b->lds_f64[k]);
+        b->grid_f64[k] = ncu * std::max(persistent_blocks_per_cu(b->lds_f64[k]), 1);
     }
     for (int k = 0; k < 2; ++k) {
         b->lds_split[k] = split_lds_bytes(k + 2, max_rows_split, max_nfun, max_img, max_leaves_split, max_n3);
@@ -1399,20 +1436,20 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
         hipError_t e = hipSuccess;
         if (precision == PUFE_PREC_FP64) {
             // one persistent launch per class (the queue counter is reset by each)
-            for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            for (int k = 0; k < kBatchClasses && e == hipSuccess; ++k) {
                 const int cnt = (int)(b->item_off[k + 1] - b->item_off[k]);
                 if (cnt == 0) continue;
                 if (b->lds_f64[k] > kMaxDynLds) {
                     e = hipErrorInvalidValue;
                     break;
                 }
-                e = launch_contract_persistent(b->q[k], b->max_l, b->d_ctxs.p, b->d_items.p + b->item_off[k], cnt,
+                e = launch_contract_persistent(b->q[k], b->max_l, b->tab, b->d_ctxs.p, b->d_items.p + b->item_off[k], cnt,
                                                b->d_counter.p, b->grid_f64[k], b->lds_f64[k], b->cap);
             }
             if (e == hipSuccess && !b->items_wide.empty()) {
                 if (b->lds_wide > kMaxDynLds) e = hipErrorInvalidValue;
                 else
-                    e = launch_contract_wide_persistent(b->max_l, b->d_ctxs.p, b->d_items_wide.p,
+                    e = launch_contract_wide_persistent(b->max_l, b->tab, b->d_ctxs.p, b->d_items_wide.p,
                                                         (int)b->items_wide.size(), b->d_counter.p, b->grid_wide,
                                                         b->lds_wide, b->cap);
             }

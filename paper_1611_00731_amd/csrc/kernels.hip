@@ -262,7 +262,7 @@ __device__ __forceinline__ void mfma_tail_dispatch(int mt, const double *sB, con
 // one work group of 2 waves per SIMD, for the large row and column blocks of
 // elements of many functions, which then evaluate their enrichment functions
 // and rows for fewer items).
-template <int Q, int LMAX, int NW = 4>
+template <int Q, int LMAX, int NW = 4, bool TAB = false>
 __device__ __forceinline__ void contract_f64_item(
     const KParams &kpg, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
@@ -329,6 +329,8 @@ __device__ __forceinline__ void contract_f64_item(
         G.fbase = Gg.fbase;
         G.img_off = Gg.img_off - img0;   // rebased onto sImg
         G.nimg = Gg.nimg;
+        G.nspl = Gg.nspl;
+        G.spl_off = Gg.spl_off;
         G.a = Gg.a;
         G.rc = Gg.rc;
         sG[g] = G;
@@ -451,7 +453,7 @@ __device__ __forceinline__ void contract_f64_item(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q, FS>(G, sImg, x, sPsi + (size_t)G.fbase * FS + q);
+            group_eval_upto<LMAX, Q, FS, TAB>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * FS + q);
         }
     };
     __syncthreads();
@@ -582,21 +584,21 @@ __device__ __forceinline__ void contract_f64_item(
 }
 
 // One work group per work item.
-template <int Q, int LMAX>
+template <int Q, int LMAX, bool TAB>
 __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
     const ItemDev it = items[blockIdx.x];
-    contract_f64_item<Q, LMAX>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
+    contract_f64_item<Q, LMAX, 4, TAB>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
                                (blockIdx.x ^ (blockIdx.x >> 3) ^ (blockIdx.x >> 5) ^ (blockIdx.x >> 8)) & 3);
 }
 
 // Persistent form: a fixed grid of work groups pulls items (of several
 // problems) from one queue, largest first; every item writes its own partial
 // slots, so the result does not depend on which group ran it.
-template <int Q, int LMAX>
+template <int Q, int LMAX, bool TAB>
 __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
                                                                             const ItemDev *__restrict__ items,
                                                                             int n_items, int *__restrict__ counter) {
@@ -610,24 +612,25 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
         if (idx >= n_items) break;
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
-        contract_f64_item<Q, LMAX>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem, idx & 3);
+        contract_f64_item<Q, LMAX, 4, TAB>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem,
+                                           idx & 3);
     }
 }
 
 // Wide work groups (8 waves, one per CU) for the items of elements of more
 // than 80 functions.
-template <int LMAX>
+template <int LMAX, bool TAB>
 __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_wide_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
     const ItemDev it = items[blockIdx.x];
-    contract_f64_item<kWideQ, LMAX, kWideWaves>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
-                                                blockIdx.x & 7);
+    contract_f64_item<kWideQ, LMAX, kWideWaves, TAB>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
+                                                     blockIdx.x & 7);
 }
 
-template <int LMAX>
+template <int LMAX, bool TAB>
 __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_wide_persistent(
     const CtxDev *__restrict__ ctxs, const ItemDev *__restrict__ items, int n_items, int *__restrict__ counter) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
@@ -640,8 +643,8 @@ __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu
         if (idx >= n_items) break;
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
-        contract_f64_item<kWideQ, LMAX, kWideWaves>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V,
-                                                    c.partial, smem, idx & 7);
+        contract_f64_item<kWideQ, LMAX, kWideWaves, TAB>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V,
+                                                         c.partial, smem, idx & 7);
     }
 }
 
@@ -967,24 +970,24 @@ size_t contract_lds_bytes(int q, int rows, int nfun, int nimg, int nleaf, int n3
 
 bool contract_q_supported(int q) { return q == 16 || q == 24 || q == 32; }
 
-hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, const ItemDev *items,
+hipError_t launch_contract_f64(int q, int lmax, bool tab, const KParams &kp, int n_items, const ItemDev *items,
                                const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st) {
     if (n_items == 0) return hipSuccess;
-#define PUFE_PLAIN(QQ, LL)                                                                                       \
-    hipLaunchKernelGGL((contract_f64_kernel<QQ, LL>), dim3(n_items), dim3(kContractThreads), lds, st, kp, items, elems, groups, \
-                       img, edof, leaves, V, partial)
-    if (q == 32) {
-        if (lmax <= 1) PUFE_PLAIN(32, 1);
-        else PUFE_PLAIN(32, 3);
-    } else if (q == 24) {
-        if (lmax <= 1) PUFE_PLAIN(24, 1);
-        else PUFE_PLAIN(24, 3);
-    } else {
-        if (lmax <= 1) PUFE_PLAIN(16, 1);
-        else PUFE_PLAIN(16, 3);
-    }
+#define PUFE_PLAIN(QQ, LL, TT)                                                                                   \
+    hipLaunchKernelGGL((contract_f64_kernel<QQ, LL, TT>), dim3(n_items), dim3(kContractThreads), lds, st, kp, items, \
+                       elems, groups, img, edof, leaves, V, partial)
+#define PUFE_PLAIN_Q(QQ)                       \
+    do {                                       \
+        if (tab) PUFE_PLAIN(QQ, 3, true);      \
+        else if (lmax <= 1) PUFE_PLAIN(QQ, 1, false); \
+        else PUFE_PLAIN(QQ, 3, false);         \
+    } while (0)
+    if (q == 32) PUFE_PLAIN_Q(32);
+    else if (q == 24) PUFE_PLAIN_Q(24);
+    else PUFE_PLAIN_Q(16);
+#undef PUFE_PLAIN_Q
 #undef PUFE_PLAIN
     return hipGetLastError();
 }
@@ -992,16 +995,21 @@ hipError_t launch_contract_f64(int q, int lmax, const KParams &kp, int n_items, 
 // Dynamic LDS above the default limit must be enabled per kernel before any
 // launch (and before any graph capture).
 hipError_t init_contract_attributes() {
-    const void *ks[12] = {(const void *)contract_f64_kernel<16, 1>, (const void *)contract_f64_kernel<16, 3>,
-                          (const void *)contract_f64_kernel<24, 1>, (const void *)contract_f64_kernel<24, 3>,
-                          (const void *)contract_f64_kernel<32, 1>, (const void *)contract_f64_kernel<32, 3>,
-                          (const void *)contract_f64_persistent<16, 1>, (const void *)contract_f64_persistent<16, 3>,
-                          (const void *)contract_f64_persistent<24, 1>, (const void *)contract_f64_persistent<24, 3>,
-                          (const void *)contract_f64_persistent<32, 1>, (const void *)contract_f64_persistent<32, 3>};
+    // analytic radials (l <= 1, l <= 3) and tabulated radials (l <= 3)
+    const void *ks[] = {(const void *)contract_f64_kernel<16, 1, false>, (const void *)contract_f64_kernel<16, 3, false>,
+                        (const void *)contract_f64_kernel<16, 3, true>, (const void *)contract_f64_kernel<24, 1, false>,
+                        (const void *)contract_f64_kernel<24, 3, false>, (const void *)contract_f64_kernel<24, 3, true>,
+                        (const void *)contract_f64_kernel<32, 1, false>, (const void *)contract_f64_kernel<32, 3, false>,
+                        (const void *)contract_f64_kernel<32, 3, true>,
+                        (const void *)contract_f64_persistent<16, 1, false>, (const void *)contract_f64_persistent<16, 3, false>,
+                        (const void *)contract_f64_persistent<16, 3, true>, (const void *)contract_f64_persistent<24, 1, false>,
+                        (const void *)contract_f64_persistent<24, 3, false>, (const void *)contract_f64_persistent<24, 3, true>,
+                        (const void *)contract_f64_persistent<32, 1, false>, (const void *)contract_f64_persistent<32, 3, false>,
+                        (const void *)contract_f64_persistent<32, 3, true>,
+                        (const void *)contract_f64_wide_kernel<1, false>, (const void *)contract_f64_wide_kernel<3, false>,
+                        (const void *)contract_f64_wide_kernel<3, true>, (const void *)contract_f64_wide_persistent<1, false>,
+                        (const void *)contract_f64_wide_persistent<3, false>, (const void *)contract_f64_wide_persistent<3, true>};
     for (const void *k : ks) PUFE_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
-    const void *kw[4] = {(const void *)contract_f64_wide_kernel<1>, (const void *)contract_f64_wide_kernel<3>,
-                         (const void *)contract_f64_wide_persistent<1>, (const void *)contract_f64_wide_persistent<3>};
-    for (const void *k : kw) PUFE_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds));
     return hipSuccess;
 }
 
@@ -1009,30 +1017,32 @@ size_t contract_wide_lds_bytes(int rows, int nfun, int nimg, int nleaf, int n3) 
     return ContractLds<kWideQ>::bytes(rows, nfun, nimg, nleaf, n3);
 }
 
-hipError_t launch_contract_wide(int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
-                                const GroupDev *groups, const double *img, const int32_t *edof, const uint32_t *leaves,
-                                const double *V, double *partial, size_t lds, hipStream_t st) {
+hipError_t launch_contract_wide(int lmax, bool tab, const KParams &kp, int n_items, const ItemDev *items,
+                                const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
+                                const uint32_t *leaves, const double *V, double *partial, size_t lds, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
-    if (lmax <= 1)
-        hipLaunchKernelGGL((contract_f64_wide_kernel<1>), dim3(n_items), dim3(64 * kWideWaves), lds, st, kp, items,
-                           elems, groups, img, edof, leaves, V, partial);
-    else
-        hipLaunchKernelGGL((contract_f64_wide_kernel<3>), dim3(n_items), dim3(64 * kWideWaves), lds, st, kp, items,
-                           elems, groups, img, edof, leaves, V, partial);
+#define PUFE_WIDE(LL, TT)                                                                                           \
+    hipLaunchKernelGGL((contract_f64_wide_kernel<LL, TT>), dim3(n_items), dim3(64 * kWideWaves), lds, st, kp, items, \
+                       elems, groups, img, edof, leaves, V, partial)
+    if (tab) PUFE_WIDE(3, true);
+    else if (lmax <= 1) PUFE_WIDE(1, false);
+    else PUFE_WIDE(3, false);
+#undef PUFE_WIDE
     return hipGetLastError();
 }
 
-hipError_t launch_contract_wide_persistent(int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items,
+hipError_t launch_contract_wide_persistent(int lmax, bool tab, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                            int *counter, int grid, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
     PUFE_HIP(hipGetLastError());
     if (n_items == 0) return hipSuccess;
-    if (lmax <= 1)
-        hipLaunchKernelGGL((contract_f64_wide_persistent<1>), dim3(grid), dim3(64 * kWideWaves), lds, st, ctxs, items,
-                           n_items, counter);
-    else
-        hipLaunchKernelGGL((contract_f64_wide_persistent<3>), dim3(grid), dim3(64 * kWideWaves), lds, st, ctxs, items,
-                           n_items, counter);
+#define PUFE_WIDE_P(LL, TT)                                                                                           \
+    hipLaunchKernelGGL((contract_f64_wide_persistent<LL, TT>), dim3(grid), dim3(64 * kWideWaves), lds, st, ctxs, items, \
+                       n_items, counter)
+    if (tab) PUFE_WIDE_P(3, true);
+    else if (lmax <= 1) PUFE_WIDE_P(1, false);
+    else PUFE_WIDE_P(3, false);
+#undef PUFE_WIDE_P
     return hipGetLastError();
 }
 
@@ -1042,24 +1052,24 @@ int persistent_blocks_per_cu(size_t lds) {
     return per < 1 ? 1 : per;
 }
 
-hipError_t launch_contract_persistent(int q, int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items,
+hipError_t launch_contract_persistent(int q, int lmax, bool tab, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                       int *counter, int grid, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
     PUFE_HIP(hipGetLastError());
     if (n_items == 0) return hipSuccess;
-#define PUFE_PERSIST(QQ, LL)                                                                                      \
-    hipLaunchKernelGGL((contract_f64_persistent<QQ, LL>), dim3(grid), dim3(kContractThreads), lds, st, ctxs, items, n_items, \
-                       counter)
-    if (q == 32) {
-        if (lmax <= 1) PUFE_PERSIST(32, 1);
-        else PUFE_PERSIST(32, 3);
-    } else if (q == 24) {
-        if (lmax <= 1) PUFE_PERSIST(24, 1);
-        else PUFE_PERSIST(24, 3);
-    } else {
-        if (lmax <= 1) PUFE_PERSIST(16, 1);
-        else PUFE_PERSIST(16, 3);
-    }
+#define PUFE_PERSIST(QQ, LL, TT)                                                                                     \
+    hipLaunchKernelGGL((contract_f64_persistent<QQ, LL, TT>), dim3(grid), dim3(kContractThreads), lds, st, ctxs, items, \
+                       n_items, counter)
+#define PUFE_PERSIST_Q(QQ)                          \
+    do {                                            \
+        if (tab) PUFE_PERSIST(QQ, 3, true);         \
+        else if (lmax <= 1) PUFE_PERSIST(QQ, 1, false); \
+        else PUFE_PERSIST(QQ, 3, false);            \
+    } while (0)
+    if (q == 32) PUFE_PERSIST_Q(32);
+    else if (q == 24) PUFE_PERSIST_Q(24);
+    else PUFE_PERSIST_Q(16);
+#undef PUFE_PERSIST_Q
 #undef PUFE_PERSIST
     return hipGetLastError();
 }

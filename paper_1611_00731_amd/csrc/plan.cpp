@@ -16,6 +16,44 @@ namespace pufe {
 
 namespace {
 
+// The C^3 cutoff of section "Partition of unity enrichment functions",
+// h(r, rc) = 1 - 35 x^4 + 84 x^5 - 70 x^6 + 20 x^7 with x = r/rc (r <= rc).
+double cutoff_h(double r, double rc) {
+    const double x = std::min(r / rc, 1.0), x4 = (x * x) * (x * x);
+    return 1.0 + x4 * (-35.0 + x * (84.0 + x * (-70.0 + 20.0 * x)));
+}
+
+// Clamped cubic spline through y_j = t_j h(r_j, rc), r_j = j dr, with zero end
+// slopes, as C^2 Hermite pieces: the knot slopes s_j solve
+//   s_{j-1} + 4 s_j + s_{j+1} = 3 (y_{j+1} - y_{j-1}) / dr   (0 < j < n-1),
+// s_0 = s_{n-1} = 0; piece j in powers of tau = (r - r_j) / dr:
+//   y_j + (s_j dr) tau + (3 dy - (2 s_j + s_{j+1}) dr) tau^2
+//       + ((s_j + s_{j+1}) dr - 2 dy) tau^3,   dy = y_{j+1} - y_j.
+void radial_spline(const std::vector<double> &t, double rc, std::vector<double> &out) {
+    const int n = (int)t.size();
+    const double dr = rc / (n - 1);
+    std::vector<double> y(n), sl(n, 0.0);
+    for (int j = 0; j < n; ++j) y[j] = t[j] * cutoff_h(j * dr, rc);
+    // interior slopes: tridiagonal (1, 4, 1) system, eliminated downwards
+    const int m = n - 2;
+    std::vector<double> cp(std::max(m, 1)), dp(std::max(m, 1));
+    for (int i = 0; i < m; ++i) {
+        const int j = i + 1;
+        const double rhs = 3.0 * (y[j + 1] - y[j - 1]) / dr;
+        const double den = 4.0 - (i > 0 ? cp[i - 1] : 0.0);
+        cp[i] = 1.0 / den;
+        dp[i] = (rhs - (i > 0 ? dp[i - 1] : 0.0)) / den;
+    }
+    for (int i = m - 1; i >= 0; --i) sl[i + 1] = dp[i] - (i + 1 < m ? cp[i] * sl[i + 2] : 0.0);
+    for (int j = 0; j + 1 < n; ++j) {
+        const double dy = y[j + 1] - y[j];
+        out.push_back(y[j]);
+        out.push_back(sl[j] * dr);
+        out.push_back(3.0 * dy - (2.0 * sl[j] + sl[j + 1]) * dr);
+        out.push_back((sl[j] + sl[j + 1]) * dr - 2.0 * dy);
+    }
+}
+
 double det3(const double *m) {
     return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
            m[2] * (m[3] * m[7] - m[4] * m[6]);
@@ -53,8 +91,21 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     for (int s : pr.species) max_species = std::max(max_species, s);
     for (const auto &e : pr.enr) {
         if (e.l < 0 || e.l > 3) { err = "enrichment l must be in 0..3"; return PUFE_ERR_INVALID_ARG; }
-        if (!(e.a > 0) || !(e.rc > 0) || !(e.re >= 0)) { err = "enrichment needs a > 0, rc > 0, re >= 0"; return PUFE_ERR_INVALID_ARG; }
-        if (e.radial_kind != 0) { err = "only the analytic radial kind 0 is supported"; return PUFE_ERR_UNSUPPORTED; }
+        if (e.radial_kind != 0 && e.radial_kind != 1) { err = "radial_kind must be 0 or 1"; return PUFE_ERR_INVALID_ARG; }
+        if (!(e.rc > 0) || !(e.re >= 0) || (e.radial_kind == 0 && !(e.a > 0))) {
+            err = "enrichment needs rc > 0, re >= 0 and (analytic radial) a > 0";
+            return PUFE_ERR_INVALID_ARG;
+        }
+    }
+    if (pr.radial.size() != pr.enr.size()) { err = "radial tables do not match the descriptors"; return PUFE_ERR_INVALID_ARG; }
+    for (size_t k = 0; k < pr.enr.size(); ++k) {
+        const auto &t = pr.radial[k];
+        if (pr.enr[k].radial_kind == 0 ? !t.empty() : (t.size() < 4 || t.size() > 4096)) {
+            err = "a tabulated radial needs 4..4096 samples (none for the analytic kind)";
+            return PUFE_ERR_INVALID_ARG;
+        }
+        for (double v : t)
+            if (!std::isfinite(v)) { err = "radial samples must be finite"; return PUFE_ERR_INVALID_ARG; }
     }
     for (const auto &pj : pr.proj) {
         if (pj.l < 0 || pj.l > 3) { err = "projector l must be in 0..3"; return PUFE_ERR_INVALID_ARG; }
@@ -272,6 +323,13 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     pl.max_l = 0;
     pl.max_img = 0;
     for (const auto &en : pr.enr) pl.max_l = std::max(pl.max_l, en.l);
+    pl.spl.clear();
+    pl.spl_off.assign(pr.enr.size(), -1);
+    for (size_t k = 0; k < pr.enr.size(); ++k)
+        if (pr.enr[k].radial_kind == 1) {
+            pl.spl_off[k] = (int32_t)pl.spl.size();
+            radial_spline(pr.radial[k], pr.enr[k].rc, pl.spl);
+        }
     std::vector<std::vector<int32_t>> by_color(27);
     for (int64_t e = 0; e < pl.nel; ++e) {
         ElemDev &el = pl.elems[e];
@@ -312,6 +370,11 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
             g.fbase = nfun;
             g.a = en.a;
             g.rc = en.rc;
+            if (en.radial_kind == 1) {
+                g.nspl = (int32_t)pr.radial[k].size() - 1;
+                g.spl_off = pl.spl_off[k];
+                g.a = g.nspl / en.rc;
+            }
             g.img_off = (int32_t)(pl.img.size() / 3);
             // images whose cutoff sphere can reach the element
             const double *tau = &pr.pos[3 * A];

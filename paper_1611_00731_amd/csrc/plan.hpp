@@ -16,7 +16,8 @@ struct Problem {
     int p;
     std::vector<double> pos;  // n_atoms x 3
     std::vector<int> species;
-    std::vector<pufe_enrichment> enr;
+    std::vector<pufe_enrichment> enr;            // radial pointers cleared
+    std::vector<std::vector<double>> radial;     // samples of tabulated radials, per descriptor
     pufe_quad quad;
     std::vector<pufe_projector> proj;   // separable nonlocal term (may be empty)
 };
@@ -47,6 +48,9 @@ struct Plan {
     int max_nloc = 0, max_nfun = 0, max_ngrp = 0;
     int max_l = 0;                  // largest angular momentum of any descriptor
     int max_img = 0;                // most image centres of one element's groups
+    // tabulated radials: 4 power coefficients per interval, per descriptor
+    std::vector<double> spl;
+    std::vector<int32_t> spl_off;   // per descriptor (-1 analytic)
     KParams kp;
     // separable nonlocal term: projector functions J (atom, descriptor, m)
     // with their weights, the projector-image groups of every element, and

@@ -98,6 +98,8 @@ __device__ __forceinline__ void contract_split_item(
         G.fbase = Gg.fbase;
         G.img_off = Gg.img_off - img0;   // rebased onto sImg
         G.nimg = Gg.nimg;
+        G.nspl = Gg.nspl;
+        G.spl_off = Gg.spl_off;
         G.a = Gg.a;
         G.rc = Gg.rc;
         sG[g] = G;
@@ -172,7 +174,7 @@ __device__ __forceinline__ void contract_split_item(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q>(G, sImg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
+            group_eval_upto<LMAX, Q>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
     };
     if (nli > 0) phase1(0);

@@ -55,10 +55,13 @@ struct NlItemDev {
 };
 
 // (atom, descriptor) group: 2l+1 functions with one radial part and the list
-// of lattice images whose cutoff sphere reaches the element.
+// of lattice images whose cutoff sphere reaches the element.  A tabulated
+// radial (nspl > 0 intervals of width rc / nspl, a = nspl / rc) is the cubic
+// on interval j = floor(a r) with coefficients spl[spl_off + 4 j + 0..3] in
+// powers of tau = a r - j.
 struct GroupDev {
-    int32_t atom, desc, l, fbase, img_off, nimg;
-    double a, rc;
+    int32_t atom, desc, l, fbase, img_off, nimg, nspl, spl_off;
+    double a, rc;   // a: Gaussian exponent (analytic) or intervals per bohr (tabulated)
 };
 
 // Enriched local function: corner | element-function << 3 | vertex slot << 11
@@ -83,6 +86,7 @@ struct KParams {
     double rx[kMaxGauss], rw[kMaxGauss];   // reference rule of the error mode (nref points)
     int32_t n, n3, p, nfe, nfs, nref;
     int32_t mesh[3];
+    const double *spl;   // coefficients of the tabulated radials (device)
 };
 
 // Tables and buffers of one problem, for launches that cover several problems

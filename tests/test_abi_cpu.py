@@ -1,6 +1,7 @@
 """CPU tests of the C ABI: the library loads, exports what the header
 declares, validates its inputs, and its host-side DOF map, enriched sets and
 block layout agree with the oracle's.  No compute call is made."""
+import copy
 import os
 import re
 
@@ -207,5 +208,38 @@ def test_projector_input_validation():
         _expect(-1, lambda: P.pufe_set_projectors(ctx, [{"species": 0, "l": 1, "a": -1.0, "rc": 1.0, "h": 1.0}]))
         P.pufe_set_projectors(ctx, [{"species": 0, "l": 1, "a": 1.0, "rc": 1.0, "h": 1.0}])
         P.pufe_set_projectors(ctx, [])
+    finally:
+        P.pufe_destroy(ctx)
+
+
+def test_tabulated_radial_validation_and_layout():
+    """Tabulated radials (section "Partition of unity enrichment functions")
+    need 4..4096 finite samples and a known kind; they change the functions,
+    not the enriched sets, so the layout equals the analytic problem's."""
+    base = W.small("lih", mesh=(2, 3, 2), fe_order=2)
+    tab = W.with_tabulated_radials(base, 12)
+
+    def setp(ctx, prob):
+        P.pufe_set_problem(ctx, prob["lattice"], prob["mesh"], prob["fe_order"], prob["atoms"], prob["species"],
+                           prob["enrichments"], prob["quad"])
+
+    ctx = P.pufe_create(0)
+    try:
+        setp(ctx, base)
+        lay0 = P.pufe_get_layout(ctx)
+        setp(ctx, tab)
+        lay1 = P.pufe_get_layout(ctx)
+        for k in lay0:
+            assert np.array_equal(np.asarray(lay0[k]), np.asarray(lay1[k])), k
+        bad = copy.deepcopy(tab)
+        bad["enrichments"][0]["radial"] = [1.0, 0.5, 0.2]
+        _expect(-1, lambda: setp(ctx, bad))
+        bad = copy.deepcopy(tab)
+        bad["enrichments"][1]["radial"][3] = float("nan")
+        _expect(-1, lambda: setp(ctx, bad))
+        bad = copy.deepcopy(tab)
+        bad["enrichments"][0]["radial_kind"] = 2
+        _expect(-1, lambda: setp(ctx, bad))
+        setp(ctx, tab)   # still accepted after the refusals
     finally:
         P.pufe_destroy(ctx)

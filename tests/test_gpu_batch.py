@@ -171,3 +171,53 @@ def test_batch_refuses_a_context_tuned_after_creation():
     b2.close()
     for p in ps:
         p.close()
+
+
+def test_batch_tuned_stage_lengths_c64_and_split(tmp_path):
+    """Problems whose cached tuner choices give them different stage lengths
+    (32, 16 and 24 points per stage) run in one batch, each length in a
+    persistent launch of its own: FP64 with complex128 and complex64 outputs
+    and bf16x6 with complex64 outputs against the oracle, on three k-points."""
+    import json
+    probs = [W.small("lih", mesh=(2, 3, 2), fe_order=2, levels=1, n=3, a=5.0),
+             W.small("lih", mesh=(3, 3, 2), fe_order=2, levels=1, n=3, a=5.2),
+             W.small("ceal", mesh=(2, 2, 2), fe_order=2, levels=1, n=3, a=4.4)]
+    kpts = W.mp2()[:3]
+    say("batch tuned stage lengths, c64, bf16x6")
+    cache = tmp_path / "tune.json"
+    for pr in probs:
+        p = P.Problem(pr).setup()
+        P.pufe_tune(p.ctx, "fp64", str(cache))
+        p.close()
+    entries = json.loads(cache.read_text())
+    assert len(entries) == 3
+    for v, q in zip(entries.values(), (32, 16, 24)):
+        v["q"] = q
+    cache.write_text(json.dumps(entries))   # compact separators: the form the library parses
+    ps, Vs, oracles = [], [], []
+    for pr in probs:
+        o = oracle.Oracle(pr)
+        xyz, _, _ = o.quadrature()
+        oracles.append(o)
+        Vs.append(potential_at(torch.from_numpy(xyz).cuda(), pr))
+        p = P.Problem(pr).setup()
+        P.pufe_tune(p.ctx, "fp64", str(cache))   # applies the cached choice
+        ps.append(p)
+    assert json.loads(cache.read_text()) == entries
+    b = P.Batch(ps)
+    refs = [[o.assemble_dense(Vs[i].cpu().numpy(), kap) for kap in kpts] for i, o in enumerate(oracles)]
+    for prec, dt, tol in (("fp64", "c128", 1e-12), ("fp64", "c64", 1e-6), ("bf16x6", "c64", 1e-6)):
+        Hs, Ss = b.alloc(len(kpts), out_dtype=dt, device="cuda")
+        b.assemble(Vs, kpts, Hs, Ss, precision=prec, out_dtype=dt)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for i, p in enumerate(ps):
+            for k in range(len(kpts)):
+                Ho, So = refs[i][k]
+                worst = max(worst, rel(p.to_dense(Hs[i][k].double().contiguous()).cpu().numpy(), Ho),
+                            rel(p.to_dense(Ss[i][k].double().contiguous()).cpu().numpy(), So))
+        say(prec, dt, "worst relative error", worst)
+        assert worst < tol
+    b.close()
+    for p in ps:
+        p.close()
