@@ -421,7 +421,7 @@ typedef struct {
     int64_t g;      /* global DOF */
     int shift[3];   /* lattice shift of the node's vertex */
     int kind;       /* 0 FE node, 1 enriched */
-    int node[3];    /* FE: node index per dimension (0..p) */
+    int node[3];    /* FE: node index per dimension (0..p; serendipity: 0..3 for -1, -1/3, 1/3, 1) */
     int corner;     /* enriched: corner c = c1 + 2 c2 + 4 c3 */
     int atom, desc, m;
 } loc_fn;
@@ -472,6 +472,7 @@ static int element_locals(const or_state *s, int64_t e, loc_fn *L) {
                 if (j[d] >= s->mesh[d]) { j[d] -= s->mesh[d]; f.shift[d] = 1; }
             }
             f.g = s->dof_off[vertex_id(s, j)];
+            for (int d = 0; d < 3; ++d) f.node[d] = 3 * ((c >> d) & 1);
             L[n++] = f;
         }
         for (int d = 0; d < 3; ++d)
@@ -488,6 +489,8 @@ static int element_locals(const or_state *s, int64_t e, loc_fn *L) {
                     memset(&f, 0, sizeof f);
                     memcpy(f.shift, sh, sizeof sh);
                     f.g = s->dof_off[vertex_id(s, j)] + 1 + 2 * d + t;
+                    for (int k = 0; k < 3; ++k) f.node[k] = 3 * ((c >> k) & 1);
+                    f.node[d] = 1 + t;   /* the edge nodes at -1/3 and +1/3 */
                     L[n++] = f;
                 }
             }
@@ -542,6 +545,50 @@ static void ref_grad(const or_state *s, const double *dxi, double *g) {
     }
 }
 
+/* 32-node cubic serendipity hexahedron (the paper's classical FE in section
+ * "Self-consistent calculations"): nodes at the corners (coordinates +-1) and
+ * at +-1/3 along every edge.  With the node at (a, b, c), reference point
+ * (x, y, z):
+ *   corner:            (1 + a x)(1 + b y)(1 + c z)(9 (x^2 + y^2 + z^2) - 19) / 64,
+ *   edge along x:  9 (1 - x^2)(1 + 9 a x)(1 + b y)(1 + c z) / 64,
+ * and alike for edges along y and z.  Returns the value and the reference
+ * gradient. */
+static void serendipity(const int *node, const double *xi, double *val, double *dxi) {
+    double nc[3];
+    int edge = -1;
+    for (int d = 0; d < 3; ++d) {
+        nc[d] = -1.0 + 2.0 * node[d] / 3.0;
+        if (node[d] == 1 || node[d] == 2) edge = d;
+    }
+    if (edge < 0) {
+        double f[3], r = 9.0 * (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]) - 19.0;
+        for (int d = 0; d < 3; ++d) f[d] = 1.0 + nc[d] * xi[d];
+        *val = f[0] * f[1] * f[2] * r / 64.0;
+        for (int d = 0; d < 3; ++d) {
+            double other = 1.0;
+            for (int k = 0; k < 3; ++k)
+                if (k != d) other *= f[k];
+            dxi[d] = (nc[d] * other * r + f[0] * f[1] * f[2] * 18.0 * xi[d]) / 64.0;
+        }
+        return;
+    }
+    double f[3], df[3];
+    for (int d = 0; d < 3; ++d) {
+        if (d == edge) {
+            double t = xi[d], a = nc[d];
+            f[d] = (1.0 - t * t) * (1.0 + 9.0 * a * t);
+            df[d] = -2.0 * t * (1.0 + 9.0 * a * t) + (1.0 - t * t) * 9.0 * a;
+        } else {
+            f[d] = 1.0 + nc[d] * xi[d];
+            df[d] = nc[d];
+        }
+    }
+    *val = 9.0 * f[0] * f[1] * f[2] / 64.0;
+    dxi[0] = 9.0 * df[0] * f[1] * f[2] / 64.0;
+    dxi[1] = 9.0 * f[0] * df[1] * f[2] / 64.0;
+    dxi[2] = 9.0 * f[0] * f[1] * df[2] / 64.0;
+}
+
 /* Values and gradients of the element's PUFE basis (eq. pufebasis): classical
  * FE functions and PU functions times enrichment functions. */
 static void basis_eval(const or_state *s, int64_t e, const loc_fn *L, int nloc, const double *xi,
@@ -549,7 +596,11 @@ static void basis_eval(const or_state *s, int64_t e, const loc_fn *L, int nloc, 
     double x[3];
     ref2phys(s, e, xi, x);
     for (int a = 0; a < nloc; ++a) {
-        if (L[a].kind == 0) {
+        if (L[a].kind == 0 && s->p == 3) {
+            double dxi[3];
+            serendipity(L[a].node, xi, &val[a], dxi);
+            ref_grad(s, dxi, grad + 3 * a);
+        } else if (L[a].kind == 0) {
             double v = 1.0, dxi[3] = {1.0, 1.0, 1.0};
             for (int d = 0; d < 3; ++d) {
                 double lv, ld;
@@ -829,7 +880,7 @@ int or_setup(const or_problem *p, or_state **out) {
     s->leaf_off = malloc(sizeof(int64_t) * (s->nel + 1));
     s->qp_off = malloc(sizeof(int64_t) * (s->nel + 1));
     leaf_list ll = {0};
-    if (s->p != 3) {
+    {
         int isortho = fabs(s->lat[1]) == 0 && fabs(s->lat[2]) == 0 && fabs(s->lat[3]) == 0
                       && fabs(s->lat[5]) == 0 && fabs(s->lat[6]) == 0 && fabs(s->lat[7]) == 0;
         if (s->q_mode == 0 && s->q_levels > 0 && !isortho) { or_free(s); return -5; }
@@ -845,8 +896,6 @@ int or_setup(const or_problem *p, or_state **out) {
             }
         }
         free(fns);
-    } else {
-        for (int64_t e = 0; e < s->nel; ++e) s->leaf_off[e] = 0;
     }
     s->leaf_off[s->nel] = ll.n;
     s->nleaves = ll.n;

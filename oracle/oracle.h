@@ -28,7 +28,7 @@ extern "C" {
 typedef struct {
     double lat[9];        /* rows a_1, a_2, a_3 (bohr) */
     int mesh[3];          /* elements along each lattice vector */
-    int fe_order;         /* 1 trilinear, 2 triquadratic; 3 = 32-node serendipity topology only */
+    int fe_order;         /* 1 trilinear, 2 triquadratic, 3 32-node cubic serendipity */
     int n_atoms;
     const double *pos;    /* n_atoms x 3 Cartesian */
     const int *species;   /* n_atoms */
