@@ -70,21 +70,57 @@ __device__ __forceinline__ void group_eval_point(const GroupDev &G, const double
     }
 }
 
-// Written to o[m * MS + c * CS], c = 0 value, 1..3 gradient.
+// Written to o[m * MS + c * CS], c = 0 value, 1..3 gradient.  The sums over
+// images accumulate in place (the first image writes, later ones add), so no
+// per-function accumulators stay live in registers.
 template <int L, int MS, int CS, bool TAB = true>
 __device__ __forceinline__ void group_eval(const GroupDev &G, const double *__restrict__ img,
                                            const double *__restrict__ spl, const double *x, double *o) {
     constexpr int NM = 2 * L + 1;
-    double psi[NM], gp[3 * NM];
-    group_eval_point<L, TAB>(G, img, spl, x, psi, gp);
+    const double rc2 = G.rc * G.rc, inv_rc2 = 1.0 / rc2;
+    const double *c0 = img + 3 * G.img_off;
+    bool first = true;
+    for (int k = 0; k < G.nimg; ++k) {
+        const double rx = x[0] - c0[3 * k], ry = x[1] - c0[3 * k + 1], rz = x[2] - c0[3 * k + 2];
+        const double s = rx * rx + ry * ry + rz * rz;
+        if (s >= rc2) continue;
+        double g0, g1;
+        if (TAB && G.nspl > 0) {
+            double unused;
+            spline_radial<false>(G, spl, s, g0, g1, unused);
+        } else {
+            const double ex = exp(-G.a * s), c = 1.0 - s * inv_rc2, c2 = c * c;
+            g0 = ex * c2 * c;
+            g1 = -ex * c2 * (G.a * c + 3.0 * inv_rc2);
+        }
+        double S[7], dS[21];
+        solid_harmonics(L, rx, ry, rz, S, dS);
+        const double tx = 2.0 * g1 * rx, ty = 2.0 * g1 * ry, tz = 2.0 * g1 * rz;
 #pragma unroll
-    for (int m = 0; m < NM; ++m) {
-        double *om = o + (size_t)m * MS;
-        om[0] = psi[m];
-        om[CS] = gp[3 * m];
-        om[2 * CS] = gp[3 * m + 1];
-        om[3 * CS] = gp[3 * m + 2];
+        for (int m = 0; m < NM; ++m) {
+            double *om = o + (size_t)m * MS;
+            const double v0 = g0 * S[m], v1 = tx * S[m] + g0 * dS[3 * m], v2 = ty * S[m] + g0 * dS[3 * m + 1],
+                         v3 = tz * S[m] + g0 * dS[3 * m + 2];
+            if (first) {
+                om[0] = v0;
+                om[CS] = v1;
+                om[2 * CS] = v2;
+                om[3 * CS] = v3;
+            } else {
+                om[0] += v0;
+                om[CS] += v1;
+                om[2 * CS] += v2;
+                om[3 * CS] += v3;
+            }
+        }
+        first = false;
     }
+    if (first)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            double *om = o + (size_t)m * MS;
+            om[0] = om[CS] = om[2 * CS] = om[3 * CS] = 0.0;
+        }
 }
 
 }  // namespace pufe
