@@ -38,8 +38,10 @@
  * Canonical orders (fixed so that callers can build inputs)
  *  - Elements and vertices: id = (i3 n2 + i2) n1 + i1.
  *  - DOFs, vertex-major: for vertex v the FE slots (trilinear: 1; triquadratic:
- *    8, slot s1 + 2 s2 + 4 s3 where s_d = 1 is the +1/2 midpoint), then v's
- *    enriched functions ordered by atom, descriptor, m = -l..l.
+ *    8, slot s1 + 2 s2 + 4 s3 where s_d = 1 is the +1/2 midpoint; serendipity:
+ *    7, slot 0 the vertex and 1 + 2 d + t the node at 1/3 (t = 0) or 2/3
+ *    (t = 1) of its positive edge along d), then v's enriched functions
+ *    ordered by atom, descriptor, m = -l..l.
  *  - Quadrature points: element-major; inside an element the octree leaves
  *    depth first (children c = c1 + 2 c2 + 4 c3); inside a leaf the n^3 Gauss
  *    points with the first reference index fastest.
@@ -153,10 +155,13 @@ int pufe_destroy(pufe_ctx *ctx);
 /* Define the problem (host only, no HIP call): cell (eq. bloch: lattice rows
  * a_1..a_3), mesh of n1 x n2 x n3 parallelepiped elements (each n_d >= 2),
  * classical FE order (1 = 8-node trilinear, 2 = 27-node triquadratic
- * Lagrange), atoms (Cartesian positions and species), enrichment descriptors
+ * Lagrange, 3 = 32-node cubic serendipity, the paper's choice in section
+ * "Self-consistent calculations"), atoms (Cartesian positions and species),
+ * enrichment descriptors
  * and the quadrature rule.  Builds the DOF map, the enriched sets, the BSR
  * layout and the element colouring.  Errors: PUFE_ERR_INVALID_ARG (null
- * pointers, non-positive volume, l outside 0..3, a <= 0, rc <= 0, n_d < 2),
+ * pointers, non-positive volume, fe_order outside 1..3, l outside 0..3,
+ * a <= 0, rc <= 0, n_d < 2),
  * PUFE_ERR_UNSUPPORTED (GEOM refinement of a non-orthorhombic cell, more
  * functions on one element than the kernels hold). */
 int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], int fe_order,

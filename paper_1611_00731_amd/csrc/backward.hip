@@ -397,8 +397,8 @@ __global__ __launch_bounds__(256) void backward_kernel(
         // (zero past the item's last point), in groups sharing the point's
         // geometry: FE functions by (a2, a3), enriched ones by PU corner
         {
-            const int n1 = kp.p + 1;
-            for (int idx = tid; idx < (n1 * n1 + 8) * Q; idx += NT) {
+            const int nfu = fe_units(kl.p);
+            for (int idx = tid; idx < (nfu + 8) * Q; idx += NT) {
                 const int u = idx / Q, q = idx - u * Q;
                 double *o = sB + q;
                 auto put = [&](int a, double x, double y, double z, double w) {
@@ -408,13 +408,11 @@ __global__ __launch_bounds__(256) void backward_kernel(
                     r[2 * Q] = z;
                     r[3 * Q] = w;
                 };
-                if (u >= n1 * n1) {
-                    const int c = u - n1 * n1;
+                if (u >= nfu) {
+                    const int c = u - nfu;
                     pu_unit<Q, 10 * Q, true>(kl, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
-                } else if (n1 == 3) {
-                    fe_unit<Q, 3, true>(kl, sGeo + q, u % 3, u / 3, put);
                 } else {
-                    fe_unit<Q, 2, true>(kl, sGeo + q, u & 1, u >> 1, put);
+                    fe_unit_any<Q, true>(kl, sGeo + q, u, put);
                 }
             }
         }

@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "tables.hpp"
+
 namespace pufe {
 
 // r^l Y_lm normalisations (orthonormal real harmonics, no Condon-Shortley phase)
@@ -91,6 +93,49 @@ __device__ __forceinline__ void lagrange_1d(int p, double t, double *L, double *
         L[0] = 0.5 * t * (t - 1.0); L[1] = 1.0 - t * t; L[2] = 0.5 * t * (t + 1.0);
         D[0] = t - 0.5;             D[1] = -2.0 * t;    D[2] = t + 0.5;
     }
+}
+
+// 32-node cubic serendipity hexahedron (fe_order 3).  Local FE function a:
+// a < 8 the corner a (coordinates -1 + 2 bit_d(a)); a = 8 + 2 e + t the node
+// at -1/3 (t = 0) or +1/3 (t = 1) of edge e = 4 d + k along direction d,
+// starting at the k-th corner whose bit d is clear.  With the node at
+// (n_0, n_1, n_2):
+//   corner:          prod_d (1 + n_d xi_d) (9 |xi|^2 - 19) / 64,
+//   edge along d:  9 (1 - xi_d^2)(1 + 9 n_d xi_d) prod_{k != d} (1 + n_k xi_k) / 64.
+__device__ __forceinline__ void serendipity_fn(int a, const double *xi, double *val, double *dxi) {
+    if (a < 8) {
+        double f[3], n[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            n[d] = ((a >> d) & 1) ? 1.0 : -1.0;
+            f[d] = 1.0 + n[d] * xi[d];
+        }
+        const double r = 9.0 * (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]) - 19.0, f3 = f[0] * f[1] * f[2];
+        *val = f3 * r * (1.0 / 64.0);
+        dxi[0] = (n[0] * f[1] * f[2] * r + 18.0 * f3 * xi[0]) * (1.0 / 64.0);
+        dxi[1] = (n[1] * f[0] * f[2] * r + 18.0 * f3 * xi[1]) * (1.0 / 64.0);
+        dxi[2] = (n[2] * f[0] * f[1] * r + 18.0 * f3 * xi[2]) * (1.0 / 64.0);
+        return;
+    }
+    const int e = (a - 8) >> 1, t = (a - 8) & 1, d = e >> 2, c = serendipity_edge_corner(d, e & 3);
+    double f[3], df[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k == d) {
+            const double nd = t ? (1.0 / 3.0) : (-1.0 / 3.0), x = xi[k], g = 1.0 + 9.0 * nd * x;
+            f[k] = (1.0 - x * x) * g;
+            df[k] = -2.0 * x * g + (1.0 - x * x) * 9.0 * nd;
+        } else {
+            const double nk = ((c >> k) & 1) ? 1.0 : -1.0;
+            f[k] = 1.0 + nk * xi[k];
+            df[k] = nk;
+        }
+    }
+    constexpr double s = 9.0 / 64.0;
+    *val = s * f[0] * f[1] * f[2];
+    dxi[0] = s * df[0] * f[1] * f[2];
+    dxi[1] = s * f[0] * df[1] * f[2];
+    dxi[2] = s * f[0] * f[1] * df[2];
 }
 
 }  // namespace pufe

@@ -664,6 +664,11 @@ int pufe_get_leaves(pufe_ctx *ctx, int32_t *level, int32_t *ijk, int64_t *elem_l
     return PUFE_OK;
 }
 
+// Problems with tabulated radials or serendipity elements run the general
+// variant of the FP64 contraction kernels; the others a variant compiled for
+// analytic radials and Lagrange elements only (fewer live registers).
+static bool general_variant(const Plan &pl) { return !pl.spl.empty() || pl.kp.p == 3; }
+
 // The element contraction and the K-chunk sum into `partial` (the context's
 // partial-tile buffer, or the fixed workspace of the allocation-free entry).
 static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipStream_t st, double *partial,
@@ -691,11 +696,11 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
     } else {
         TimedRegion tr(ctx, 0, st);
         // wide items first: they are the longest
-        CHECK_HIP(ctx, launch_contract_wide(pl.max_l, !pl.spl.empty(), pl.kp, (int)ctx->items_wide.size(), ctx->d_items_wide.p,
+        CHECK_HIP(ctx, launch_contract_wide(pl.max_l, general_variant(pl), pl.kp, (int)ctx->items_wide.size(), ctx->d_items_wide.p,
                                             ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                             ctx->d_leaves.p, d_V, partial, ctx->lds_wide, st),
                   "contraction (wide items)");
-        CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, !pl.spl.empty(), pl.kp, (int)ctx->items.size(), ctx->d_items.p,
+        CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, general_variant(pl), pl.kp, (int)ctx->items.size(), ctx->d_items.p,
                                            ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                            ctx->d_leaves.p, d_V, partial, ctx->lds, st),
                   "contraction");
@@ -1169,7 +1174,7 @@ struct pufe_batch {
     // problems whose combined stage fits two work groups per CU, then the rest
     size_t lds_f64[kBatchClasses] = {}, lds_split[2] = {0, 0};
     int max_l = 0, q[kBatchClasses] = {};
-    bool tab = false;                       // some problem has tabulated radials
+    bool gen = false;                       // some problem needs the general kernel variant
     int grid_f64[kBatchClasses] = {}, grid_split[2] = {0, 0};
     int64_t item_off[kBatchClasses + 1] = {};
     // wide items of all problems (8-wave persistent launch)
@@ -1301,7 +1306,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
         max_leaves_split = std::max(max_leaves_split, c->max_item_leaves_split);
         max_n3 = std::max(max_n3, c->plan.kp.n3);
         b->max_l = std::max(b->max_l, c->plan.max_l);
-        b->tab = b->tab || !c->plan.spl.empty();
+        b->gen = b->gen || general_variant(c->plan);
         if (!c->items_wide.empty()) b->lds_wide = std::max(b->lds_wide, c->lds_wide);
         for (int64_t e = 0; e < c->plan.nel; ++e) {
             const int T = (c->plan.elems[e].nloc + 15) / 16;
@@ -1443,13 +1448,13 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
                     e = hipErrorInvalidValue;
                     break;
                 }
-                e = launch_contract_persistent(b->q[k], b->max_l, b->tab, b->d_ctxs.p, b->d_items.p + b->item_off[k], cnt,
+                e = launch_contract_persistent(b->q[k], b->max_l, b->gen, b->d_ctxs.p, b->d_items.p + b->item_off[k], cnt,
                                                b->d_counter.p, b->grid_f64[k], b->lds_f64[k], b->cap);
             }
             if (e == hipSuccess && !b->items_wide.empty()) {
                 if (b->lds_wide > kMaxDynLds) e = hipErrorInvalidValue;
                 else
-                    e = launch_contract_wide_persistent(b->max_l, b->tab, b->d_ctxs.p, b->d_items_wide.p,
+                    e = launch_contract_wide_persistent(b->max_l, b->gen, b->d_ctxs.p, b->d_items_wide.p,
                                                         (int)b->items_wide.size(), b->d_counter.p, b->grid_wide,
                                                         b->lds_wide, b->cap);
             }

@@ -28,6 +28,15 @@ __device__ __forceinline__ void local_slot(const ElemDev &el, const int32_t *edo
         if (p == 1) {
             *corner = a;
             *slot = 0;
+        } else if (p == 3) {   // serendipity: corners, then two nodes per edge (slots 1 + 2 d + t)
+            if (a < 8) {
+                *corner = a;
+                *slot = 0;
+            } else {
+                const int e = (a - 8) >> 1, d = e >> 2;
+                *corner = serendipity_edge_corner(d, e & 3);
+                *slot = 1 + 2 * d + ((a - 8) & 1);
+            }
         } else {
             int d0 = a % 3, d1 = (a / 3) % 3, d2 = a / 9;
             *corner = (d0 == 2) | ((d1 == 2) << 1) | ((d2 == 2) << 2);

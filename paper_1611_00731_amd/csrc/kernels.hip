@@ -262,7 +262,7 @@ __device__ __forceinline__ void mfma_tail_dispatch(int mt, const double *sB, con
 // one work group of 2 waves per SIMD, for the large row and column blocks of
 // elements of many functions, which then evaluate their enrichment functions
 // and rows for fewer items).
-template <int Q, int LMAX, int NW = 4, bool TAB = false>
+template <int Q, int LMAX, int NW = 4, bool GEN = false>
 __device__ __forceinline__ void contract_f64_item(
     const KParams &kpg, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
@@ -453,7 +453,7 @@ __device__ __forceinline__ void contract_f64_item(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q, FS, TAB>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * FS + q);
+            group_eval_upto<LMAX, Q, FS, GEN>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * FS + q);
         }
     };
     __syncthreads();
@@ -461,16 +461,14 @@ __device__ __forceinline__ void contract_f64_item(
     if (nli > 0) phase1(0, sV);
     __syncthreads();
     // FE functions in the item's rows (grouped by (a2, a3), filtered on store)
-    const int n1 = kp.p + 1;
-    const int nfu = whole ? n1 * n1 : ((lo0 < nfe || (!diag && lo1 < nfe)) ? n1 * n1 : 0);
+    const int nfu = (whole || lo0 < nfe || (!diag && lo1 < nfe)) ? fe_units(kp.p) : 0;
 
     for (uint32_t lb = 0, st = 0; lb < nli; lb += Q, st ^= 1) {
         double *sVc = sV + st * Q;
         // ---- phase 2: weighted local basis rows (eq. pufebasis) of the
         // item's functions (the padding rows past them stay zero)
         if (whole) {
-            const int n1 = kp.p + 1;
-            for (int idx = tid; idx < n1 * n1 * Q; idx += NT) {
+            for (int idx = tid; idx < nfu * Q; idx += NT) {
                 const int u = idx / Q, q = idx - u * Q;
                 double *o = sB + q;
                 auto put = [&](int a, double x, double y, double z, double w) {
@@ -480,10 +478,7 @@ __device__ __forceinline__ void contract_f64_item(
                     r[2 * Q] = z;
                     r[3 * Q] = w;
                 };
-                if (n1 == 3)
-                    fe_unit<Q, 3>(kp, sGeo + q, u % 3, u / 3, put);
-                else
-                    fe_unit<Q, 2>(kp, sGeo + q, u & 1, u >> 1, put);
+                fe_unit_any<Q, false, GEN>(kp, sGeo + q, u, put);
             }
             for (int idx = tid; idx < 8 * Q; idx += NT) {
                 const int c = idx / Q, q = idx - c * Q;
@@ -516,10 +511,7 @@ __device__ __forceinline__ void contract_f64_item(
                     rr[3 * Q] = w;
                 };
                 if (u < nfu) {
-                    if (n1 == 3)
-                        fe_unit<Q, 3>(kp, sGeo + q, u % 3, u / 3, put);
-                    else
-                        fe_unit<Q, 2>(kp, sGeo + q, u & 1, u >> 1, put);
+                    fe_unit_any<Q, false, GEN>(kp, sGeo + q, u, put);
                 } else {
                     const int ch = sChunk[u - nfu];
                     pu_unit<Q, FS>(kp, sGeo + q, sPsi + q, sEd, ch & 7, (ch >> 3) & 1023, ch >> 13, nfe, put);
@@ -584,21 +576,21 @@ __device__ __forceinline__ void contract_f64_item(
 }
 
 // One work group per work item.
-template <int Q, int LMAX, bool TAB>
+template <int Q, int LMAX, bool GEN>
 __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
     const ItemDev it = items[blockIdx.x];
-    contract_f64_item<Q, LMAX, 4, TAB>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
+    contract_f64_item<Q, LMAX, 4, GEN>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
                                (blockIdx.x ^ (blockIdx.x >> 3) ^ (blockIdx.x >> 5) ^ (blockIdx.x >> 8)) & 3);
 }
 
 // Persistent form: a fixed grid of work groups pulls items (of several
 // problems) from one queue, largest first; every item writes its own partial
 // slots, so the result does not depend on which group ran it.
-template <int Q, int LMAX, bool TAB>
+template <int Q, int LMAX, bool GEN>
 __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_persistent(const CtxDev *__restrict__ ctxs,
                                                                             const ItemDev *__restrict__ items,
                                                                             int n_items, int *__restrict__ counter) {
@@ -612,25 +604,25 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
         if (idx >= n_items) break;
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
-        contract_f64_item<Q, LMAX, 4, TAB>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem,
+        contract_f64_item<Q, LMAX, 4, GEN>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial, smem,
                                            idx & 3);
     }
 }
 
 // Wide work groups (8 waves, one per CU) for the items of elements of more
 // than 80 functions.
-template <int LMAX, bool TAB>
+template <int LMAX, bool GEN>
 __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_wide_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
     const ItemDev it = items[blockIdx.x];
-    contract_f64_item<kWideQ, LMAX, kWideWaves, TAB>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
+    contract_f64_item<kWideQ, LMAX, kWideWaves, GEN>(kp, it, elems, groups, img, edof, leaves, V, partial, smem,
                                                      blockIdx.x & 7);
 }
 
-template <int LMAX, bool TAB>
+template <int LMAX, bool GEN>
 __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu(2))) void contract_f64_wide_persistent(
     const CtxDev *__restrict__ ctxs, const ItemDev *__restrict__ items, int n_items, int *__restrict__ counter) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
@@ -643,7 +635,7 @@ __global__ __launch_bounds__(64 * kWideWaves) __attribute__((amdgpu_waves_per_eu
         if (idx >= n_items) break;
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
-        contract_f64_item<kWideQ, LMAX, kWideWaves, TAB>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V,
+        contract_f64_item<kWideQ, LMAX, kWideWaves, GEN>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V,
                                                          c.partial, smem, idx & 7);
     }
 }
@@ -970,7 +962,7 @@ size_t contract_lds_bytes(int q, int rows, int nfun, int nimg, int nleaf, int n3
 
 bool contract_q_supported(int q) { return q == 16 || q == 24 || q == 32; }
 
-hipError_t launch_contract_f64(int q, int lmax, bool tab, const KParams &kp, int n_items, const ItemDev *items,
+hipError_t launch_contract_f64(int q, int lmax, bool gen, const KParams &kp, int n_items, const ItemDev *items,
                                const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st) {
@@ -980,7 +972,7 @@ hipError_t launch_contract_f64(int q, int lmax, bool tab, const KParams &kp, int
                        elems, groups, img, edof, leaves, V, partial)
 #define PUFE_PLAIN_Q(QQ)                       \
     do {                                       \
-        if (tab) PUFE_PLAIN(QQ, 3, true);      \
+        if (gen) PUFE_PLAIN(QQ, 3, true);      \
         else if (lmax <= 1) PUFE_PLAIN(QQ, 1, false); \
         else PUFE_PLAIN(QQ, 3, false);         \
     } while (0)
@@ -995,7 +987,8 @@ hipError_t launch_contract_f64(int q, int lmax, bool tab, const KParams &kp, int
 // Dynamic LDS above the default limit must be enabled per kernel before any
 // launch (and before any graph capture).
 hipError_t init_contract_attributes() {
-    // analytic radials (l <= 1, l <= 3) and tabulated radials (l <= 3)
+    // analytic radials and Lagrange elements (l <= 1, l <= 3), and the general
+    // variant (tabulated radials, serendipity elements; l <= 3)
     const void *ks[] = {(const void *)contract_f64_kernel<16, 1, false>, (const void *)contract_f64_kernel<16, 3, false>,
                         (const void *)contract_f64_kernel<16, 3, true>, (const void *)contract_f64_kernel<24, 1, false>,
                         (const void *)contract_f64_kernel<24, 3, false>, (const void *)contract_f64_kernel<24, 3, true>,
@@ -1017,21 +1010,21 @@ size_t contract_wide_lds_bytes(int rows, int nfun, int nimg, int nleaf, int n3) 
     return ContractLds<kWideQ>::bytes(rows, nfun, nimg, nleaf, n3);
 }
 
-hipError_t launch_contract_wide(int lmax, bool tab, const KParams &kp, int n_items, const ItemDev *items,
+hipError_t launch_contract_wide(int lmax, bool gen, const KParams &kp, int n_items, const ItemDev *items,
                                 const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                 const uint32_t *leaves, const double *V, double *partial, size_t lds, hipStream_t st) {
     if (n_items == 0) return hipSuccess;
 #define PUFE_WIDE(LL, TT)                                                                                           \
     hipLaunchKernelGGL((contract_f64_wide_kernel<LL, TT>), dim3(n_items), dim3(64 * kWideWaves), lds, st, kp, items, \
                        elems, groups, img, edof, leaves, V, partial)
-    if (tab) PUFE_WIDE(3, true);
+    if (gen) PUFE_WIDE(3, true);
     else if (lmax <= 1) PUFE_WIDE(1, false);
     else PUFE_WIDE(3, false);
 #undef PUFE_WIDE
     return hipGetLastError();
 }
 
-hipError_t launch_contract_wide_persistent(int lmax, bool tab, const CtxDev *ctxs, const ItemDev *items, int n_items,
+hipError_t launch_contract_wide_persistent(int lmax, bool gen, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                            int *counter, int grid, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
     PUFE_HIP(hipGetLastError());
@@ -1039,7 +1032,7 @@ hipError_t launch_contract_wide_persistent(int lmax, bool tab, const CtxDev *ctx
 #define PUFE_WIDE_P(LL, TT)                                                                                           \
     hipLaunchKernelGGL((contract_f64_wide_persistent<LL, TT>), dim3(grid), dim3(64 * kWideWaves), lds, st, ctxs, items, \
                        n_items, counter)
-    if (tab) PUFE_WIDE_P(3, true);
+    if (gen) PUFE_WIDE_P(3, true);
     else if (lmax <= 1) PUFE_WIDE_P(1, false);
     else PUFE_WIDE_P(3, false);
 #undef PUFE_WIDE_P
@@ -1052,7 +1045,7 @@ int persistent_blocks_per_cu(size_t lds) {
     return per < 1 ? 1 : per;
 }
 
-hipError_t launch_contract_persistent(int q, int lmax, bool tab, const CtxDev *ctxs, const ItemDev *items, int n_items,
+hipError_t launch_contract_persistent(int q, int lmax, bool gen, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                       int *counter, int grid, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, counter);
     PUFE_HIP(hipGetLastError());
@@ -1062,7 +1055,7 @@ hipError_t launch_contract_persistent(int q, int lmax, bool tab, const CtxDev *c
                        n_items, counter)
 #define PUFE_PERSIST_Q(QQ)                          \
     do {                                            \
-        if (tab) PUFE_PERSIST(QQ, 3, true);         \
+        if (gen) PUFE_PERSIST(QQ, 3, true);         \
         else if (lmax <= 1) PUFE_PERSIST(QQ, 1, false); \
         else PUFE_PERSIST(QQ, 3, false);            \
     } while (0)

@@ -37,7 +37,7 @@ hipError_t init_contract_attributes();
 hipError_t init_split_attributes();
 size_t contract_lds_bytes(int q, int rows, int nfun, int nimg, int nleaf, int n3);
 bool contract_q_supported(int q);
-hipError_t launch_contract_f64(int q, int lmax, bool tab, const KParams &kp, int n_items, const ItemDev *items,
+hipError_t launch_contract_f64(int q, int lmax, bool gen, const KParams &kp, int n_items, const ItemDev *items,
                                const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                hipStream_t st);
@@ -46,10 +46,10 @@ hipError_t launch_contract_f64(int q, int lmax, bool tab, const KParams &kp, int
 constexpr int kWholeMaxTiles = 5;   // elements of at most 80 functions: whole-element narrow items
 constexpr int kWideTiles = 6;       // tile block of the wide items
 size_t contract_wide_lds_bytes(int rows, int nfun, int nimg, int nleaf, int n3);
-hipError_t launch_contract_wide(int lmax, bool tab, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+hipError_t launch_contract_wide(int lmax, bool gen, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
                                 const GroupDev *groups, const double *img, const int32_t *edof, const uint32_t *leaves,
                                 const double *V, double *partial, size_t lds, hipStream_t st);
-hipError_t launch_contract_wide_persistent(int lmax, bool tab, const CtxDev *ctxs, const ItemDev *items, int n_items,
+hipError_t launch_contract_wide_persistent(int lmax, bool gen, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                            int *counter, int grid, size_t lds, hipStream_t st);
 size_t split_lds_bytes(int nlimb, int rows, int nfun, int nimg, int nleaf, int n3);
 hipError_t launch_contract_split(int nlimb, int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
@@ -57,7 +57,7 @@ hipError_t launch_contract_split(int nlimb, int lmax, const KParams &kp, int n_i
                                  const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                  hipStream_t st);
 int persistent_blocks_per_cu(size_t lds);
-hipError_t launch_contract_persistent(int q, int lmax, bool tab, const CtxDev *ctxs, const ItemDev *items, int n_items,
+hipError_t launch_contract_persistent(int q, int lmax, bool gen, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                       int *counter, int grid, size_t lds, hipStream_t st);
 hipError_t launch_split_persistent(int nlimb, int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                    int grid, size_t lds, hipStream_t st);

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kNlThreads) void nl_f_kernel(
         pr_col[u] = pidx < npairs ? 16 * (pidx % TC) : -1;
         acc[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
     }
-    const int n1 = kp.p + 1;
+    const int nfu = fe_units(kp.p);
     const int r16 = lane & 15, k4 = lane >> 4;
     __syncthreads();
     for (uint32_t lb = 0; lb < nli; lb += Q) {
@@ -146,16 +146,14 @@ __global__ __launch_bounds__(kNlThreads) void nl_f_kernel(
         }
         __syncthreads();
         // ---- phase 2: sqrt(w) N_a of every local function (grouped units)
-        for (int idx = tid; idx < (n1 * n1 + 8) * Q; idx += NT) {
+        for (int idx = tid; idx < (nfu + 8) * Q; idx += NT) {
             const int u = idx / Q, q = idx - u * Q;
             auto put = [&](int a, double, double, double, double w) { sU[(size_t)a * QU + q] = w; };
-            if (u >= n1 * n1) {
-                const int c = u - n1 * n1;
+            if (u >= nfu) {
+                const int c = u - nfu;
                 pu_unit<Q>(kp, sGeo + q, sPsi + q, sEd, c, sCS[c], sCS[c + 1], nfe, put);
-            } else if (n1 == 3) {
-                fe_unit<Q, 3>(kp, sGeo + q, u % 3, u / 3, put);
             } else {
-                fe_unit<Q, 2>(kp, sGeo + q, u & 1, u >> 1, put);
+                fe_unit_any<Q>(kp, sGeo + q, u, put);
             }
         }
         __syncthreads();

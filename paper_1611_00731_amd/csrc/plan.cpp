@@ -81,7 +81,7 @@ inline int wrapi(int j, int n) { return ((j % n) + n) % n; }
 int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     const int n1 = pr.mesh[0], n2 = pr.mesh[1], n3 = pr.mesh[2];
     if (n1 < 2 || n2 < 2 || n3 < 2) { err = "every mesh dimension must be >= 2"; return PUFE_ERR_INVALID_ARG; }
-    if (pr.p != 1 && pr.p != 2) { err = "fe_order must be 1 or 2"; return PUFE_ERR_INVALID_ARG; }
+    if (pr.p < 1 || pr.p > 3) { err = "fe_order must be 1, 2 or 3 (32-node serendipity)"; return PUFE_ERR_INVALID_ARG; }
     std::memcpy(pl.lat, pr.lat, sizeof pl.lat);
     pl.vol = det3(pr.lat);
     if (!(pl.vol > 0)) { err = "lattice must be right-handed with positive volume"; return PUFE_ERR_INVALID_ARG; }
@@ -125,8 +125,11 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
 
     pl.nel = (int64_t)n1 * n2 * n3;
     pl.nv = pl.nel;
-    pl.nfs = pr.p == 1 ? 1 : 8;
-    pl.nfe = pr.p == 1 ? 8 : 27;
+    // FE slots per vertex: the vertex node; triquadratic also the midpoints
+    // of its 3 positive edges, 3 positive faces and its cell (8 in all);
+    // serendipity also the 2 nodes of each of its 3 positive edges (7)
+    pl.nfs = pr.p == 1 ? 1 : (pr.p == 2 ? 8 : 7);
+    pl.nfe = pr.p == 1 ? 8 : (pr.p == 2 ? 27 : 32);
     const int mesh[3] = {n1, n2, n3};
 
     // ---- enriched sets: for every atom image, the vertices inside its
@@ -470,9 +473,13 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
             for (int a = 0; a < el.nloc; ++a) {
                 int corner, slot;
                 if (a < el.nfe) {
-                    if (pr.p == 1) {
+                    if (pr.p == 1 || (pr.p == 3 && a < 8)) {
                         corner = a;
                         slot = 0;
+                    } else if (pr.p == 3) {   // edge node: 8 + 2 e + t, edge e = 4 d + k
+                        const int e2 = (a - 8) >> 1, d = e2 >> 2;
+                        corner = serendipity_edge_corner(d, e2 & 3);
+                        slot = 1 + 2 * d + ((a - 8) & 1);
                     } else {
                         const int d0 = a % 3, d1 = (a / 3) % 3, d2 = a / 9;
                         corner = (d0 == 2) | ((d1 == 2) << 1) | ((d2 == 2) << 2);

@@ -139,6 +139,15 @@ __device__ __forceinline__ void local_row(const KLocal &kp, const double *g, con
     *val = 0.0;
     gx[0] = gx[1] = gx[2] = 0.0;
     if (a < 0) return;
+    if (a < nfe && kp.p == 3) {
+        const double xi[3] = {g[G_XI * Q], g[(G_XI + 1) * Q], g[(G_XI + 2) * Q]};
+        double dxi[3];
+        serendipity_fn(a, xi, val, dxi);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            gx[cc] = kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2];
+        return;
+    }
     if (a < nfe) {
         int a1, a2, a3;
         if (kp.p == 2) {
@@ -218,6 +227,38 @@ __device__ __forceinline__ void fe_unit(const KLocal &kp, const double *g, int a
         out(a1 + N1 * a2 + N1 * N1 * a3, sJ[0] * x0 + sJ[1] * x1 + sJ[2] * x2, sJ[3] * x0 + sJ[4] * x1 + sJ[5] * x2,
             sJ[6] * x0 + sJ[7] * x1 + sJ[8] * x2, l1 * pw);
     }
+}
+
+// se_unit: FE functions of the 32-node serendipity element sharing one
+// point: unit u < 8 the corner u, unit 8 + e the two nodes of edge e.
+template <int Q, bool MASKED = false, class Out>
+__device__ __forceinline__ void se_unit(const KLocal &kp, const double *g, int u, Out &&out) {
+    double s2, sw;
+    row_weights<Q, MASKED>(g, &s2, &sw);
+    const double xi[3] = {g[G_XI * Q], g[(G_XI + 1) * Q], g[(G_XI + 2) * Q]};
+    const int a0 = u < 8 ? u : 8 + 2 * (u - 8), na = u < 8 ? 1 : 2;
+    for (int t = 0; t < na; ++t) {
+        double v, dxi[3];
+        serendipity_fn(a0 + t, xi, &v, dxi);
+        double gx[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            gx[cc] = s2 * (kp.Jt[3 * cc] * dxi[0] + kp.Jt[3 * cc + 1] * dxi[1] + kp.Jt[3 * cc + 2] * dxi[2]);
+        out(a0 + t, gx[0], gx[1], gx[2], sw * v);
+    }
+}
+
+// Units of FE functions per point: (p + 1)^2 tensor-product groups for the
+// Lagrange elements, 8 corners + 12 edges for the serendipity element.
+__device__ __forceinline__ int fe_units(int p) { return p == 3 ? 20 : (p + 1) * (p + 1); }
+
+// FE unit u of any element order (see fe_unit and se_unit); GEN = false
+// compiles the Lagrange orders only (kernels of problems of order 1 or 2).
+template <int Q, bool MASKED = false, bool GEN = true, class Out>
+__device__ __forceinline__ void fe_unit_any(const KLocal &kp, const double *g, int u, Out &&out) {
+    if (GEN && kp.p == 3) se_unit<Q, MASKED>(kp, g, u, out);
+    else if (kp.p == 2) fe_unit<Q, 3, MASKED>(kp, g, u % 3, u / 3, out);
+    else fe_unit<Q, 2, MASKED>(kp, g, u & 1, u >> 1, out);
 }
 
 // pu_unit: the enriched functions M_c Psi_f of PU corner c, entries

@@ -64,6 +64,13 @@ struct GroupDev {
     double a, rc;   // a: Gaussian exponent (analytic) or intervals per bohr (tabulated)
 };
 
+// Serendipity elements (fe_order 3): the k-th (k = 0..3) corner whose bit d
+// is clear, where edge 4 d + k along direction d starts.
+static inline __host__ __device__ int serendipity_edge_corner(int d, int k) {
+    const int low = k & ((1 << d) - 1);
+    return low | ((k >> d) << (d + 1));
+}
+
 // Enriched local function: corner | element-function << 3 | vertex slot << 11
 static inline __host__ __device__ int32_t edof_pack(int corner, int f, int slot) {
     return corner | (f << 3) | (slot << 11);

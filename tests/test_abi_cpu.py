@@ -49,7 +49,7 @@ def test_input_validation():
         _expect(-5, lambda: P.pufe_set_rule(ctx, [0], [[0, 0, 0]], [0, 1], stream=type("S", (), {"cuda_stream": 0})()))
         _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [1, 2, 2], 1, base["atoms"],
                                                base["species"], base["enrichments"], base["quad"]))
-        _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 3, base["atoms"],
+        _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 4, base["atoms"],
                                                base["species"], base["enrichments"], base["quad"]))
         bad = [dict(base["enrichments"][0], l=4)]
         _expect(-1, lambda: P.pufe_set_problem(ctx, base["lattice"], [2, 2, 2], 1, base["atoms"],
@@ -88,6 +88,8 @@ PROBLEMS = {
     "ceal": lambda: W.small("ceal", mesh=(3, 3, 3), fe_order=2, a=5.0, rc=3.0, re=2.1),
     "skew": lambda: W.small("lih", mesh=(3, 2, 3), fe_order=2, levels=0,
                             lattice=[[5.0, 0.3, -0.2], [0.1, 4.8, 0.25], [0.2, -0.3, 5.3]]),
+    "serendipity": lambda: W.small("lih", mesh=(3, 2, 4), fe_order=3, a=5.0),
+    "serendipity-ceal": lambda: W.small("ceal", mesh=(2, 3, 2), fe_order=3, a=4.4, rc=3.0, re=2.4),
     "random-1": lambda: W.random_small(1),
     "random-7": lambda: W.random_small(7),
 }
@@ -107,7 +109,8 @@ def test_dof_map_and_enriched_sets_match_oracle(name):
         p.close()
 
 
-@pytest.mark.parametrize("name", ["single_atom_cube", "lih-odd", "one-p1", "ceal", "skew"])
+@pytest.mark.parametrize("name", ["single_atom_cube", "lih-odd", "one-p1", "ceal", "skew", "serendipity",
+                                  "serendipity-ceal"])
 def test_block_pattern_matches_element_coupling(name):
     prob = PROBLEMS[name]()
     o = oracle.Oracle(prob)

@@ -11,7 +11,8 @@ Problem dictionary keys
 -----------------------
 lattice      3x3 nested list, rows a_1, a_2, a_3 (bohr), right-handed.
 mesh         [n1, n2, n3] hexahedral elements along a_1, a_2, a_3.
-fe_order     1 (8-node trilinear) or 2 (27-node triquadratic Lagrange).
+fe_order     1 (8-node trilinear), 2 (27-node triquadratic Lagrange) or 3
+             (32-node cubic serendipity).
 atoms        list of Cartesian positions [x, y, z] (bohr).
 species      list of species indices, one per atom.
 species_info list of {"name", "Z", "rloc"} (used only by the potential).
