@@ -688,7 +688,7 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
         if (lds > kMaxDynLds) return fail(ctx, PUFE_ERR_UNSUPPORTED, "split stage does not fit in LDS");
         {
             TimedRegion tr(ctx, 0, st);
-            CHECK_HIP(ctx, launch_contract_split(nl, pl.max_l, pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p,
+            CHECK_HIP(ctx, launch_contract_split(nl, pl.max_l, general_variant(pl), pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p,
                                                  ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                                  ctx->d_leaves.p, d_V, partial, lds, st),
                       "split contraction");
@@ -1462,7 +1462,7 @@ int pufe_batch_assemble(pufe_batch *b, const double *const *d_V, const double *k
             const int k = precision == PUFE_PREC_BF16X3 ? 0 : 1;
             if (b->lds_split[k] > kMaxDynLds) e = hipErrorInvalidValue;
             else
-                e = launch_split_persistent(k + 2, b->max_l, b->d_ctxs.p, b->d_items_split.p, (int)b->items_split.size(), b->d_counter.p,
+                e = launch_split_persistent(k + 2, b->max_l, b->gen, b->d_ctxs.p, b->d_items_split.p, (int)b->items_split.size(), b->d_counter.p,
                                             b->grid_split[k], b->lds_split[k], b->cap);
         }
         if (e == hipSuccess) e = launch_chunk_reduce_batch(b->d_ctxs.p, b->d_reduce.p, (int)b->reduce.size(), b->cap);

@@ -52,14 +52,14 @@ hipError_t launch_contract_wide(int lmax, bool gen, const KParams &kp, int n_ite
 hipError_t launch_contract_wide_persistent(int lmax, bool gen, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                            int *counter, int grid, size_t lds, hipStream_t st);
 size_t split_lds_bytes(int nlimb, int rows, int nfun, int nimg, int nleaf, int n3);
-hipError_t launch_contract_split(int nlimb, int lmax, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
+hipError_t launch_contract_split(int nlimb, int lmax, bool gen, const KParams &kp, int n_items, const ItemDev *items, const ElemDev *elems,
                                  const GroupDev *groups, const double *img, const int32_t *edof,
                                  const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                  hipStream_t st);
 int persistent_blocks_per_cu(size_t lds);
 hipError_t launch_contract_persistent(int q, int lmax, bool gen, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                       int *counter, int grid, size_t lds, hipStream_t st);
-hipError_t launch_split_persistent(int nlimb, int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
+hipError_t launch_split_persistent(int nlimb, int lmax, bool gen, const CtxDev *ctxs, const ItemDev *items, int n_items, int *counter,
                                    int grid, size_t lds, hipStream_t st);
 hipError_t launch_chunk_reduce(const ElemDev *elems, const int2 *list, int n, double *partial, hipStream_t st);
 hipError_t launch_chunk_reduce_batch(const CtxDev *ctxs, const int4 *list, int n, hipStream_t st);

@@ -48,7 +48,7 @@ struct SplitLds {
     }
 };
 
-template <int NL, int Q, int LMAX>
+template <int NL, int Q, int LMAX, bool GEN>
 __device__ __forceinline__ void contract_split_item(
     const KParams &kpg, const ItemDev &it, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
@@ -174,7 +174,7 @@ __device__ __forceinline__ void contract_split_item(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * 4 * Q + q);
+            group_eval_upto<LMAX, Q, 4 * Q, GEN>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
     };
     if (nli > 0) phase1(0);
@@ -191,7 +191,7 @@ __device__ __forceinline__ void contract_split_item(
                 const int q = q0 + t;
                 const double *g = sGeo + q;
                 double val, gx[3];
-                local_row<Q>(kp, g, sPsi + q, sEd, a, nfe, &val, gx);
+                local_row<Q, GEN>(kp, g, sPsi + q, sEd, a, nfe, &val, gx);
                 const double s2 = g[G_SW2 * Q], u = g[G_SW * Q] * val;
                 comp[t][0] = s2 * gx[0];
                 comp[t][1] = s2 * gx[1];
@@ -263,18 +263,18 @@ __device__ __forceinline__ void contract_split_item(
     }
 }
 
-template <int NL, int Q, int LMAX>
+template <int NL, int Q, int LMAX, bool GEN>
 __global__ __launch_bounds__(kSplitThreads) void contract_split_kernel(
     const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
     const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
     const uint32_t *__restrict__ leaves, const double *__restrict__ V, double *__restrict__ partial) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const ItemDev it = items[blockIdx.x];
-    contract_split_item<NL, Q, LMAX>(kp, it, elems, groups, img, edof, leaves, V, partial, smem_raw);
+    contract_split_item<NL, Q, LMAX, GEN>(kp, it, elems, groups, img, edof, leaves, V, partial, smem_raw);
 }
 
 // Persistent queue form (see contract_f64_persistent).
-template <int NL, int Q, int LMAX>
+template <int NL, int Q, int LMAX, bool GEN>
 __global__ __launch_bounds__(kSplitThreads) void contract_split_persistent(const CtxDev *__restrict__ ctxs,
                                                                            const ItemDev *__restrict__ items,
                                                                            int n_items, int *__restrict__ counter) {
@@ -288,8 +288,8 @@ __global__ __launch_bounds__(kSplitThreads) void contract_split_persistent(const
         if (idx >= n_items) break;
         const ItemDev it = items[idx];
         const CtxDev &c = ctxs[it.ctx];
-        contract_split_item<NL, Q, LMAX>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial,
-                                         smem_raw);
+        contract_split_item<NL, Q, LMAX, GEN>(c.kp, it, c.elems, c.groups, c.img, c.edof, c.leaves, c.V, c.partial,
+                                              smem_raw);
     }
 }
 
@@ -297,37 +297,45 @@ __global__ void reset_counter_split_kernel(int *counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
-#define PUFE_SPLIT_DISPATCH(KERNEL, NLIMB, LM, ...)                                      \
-    do {                                                                                \
-        if (NLIMB == 2) {                                                               \
-            if (LM <= 1) hipLaunchKernelGGL((KERNEL<2, kSplitQ, 1>), __VA_ARGS__);      \
-            else hipLaunchKernelGGL((KERNEL<2, kSplitQ, 3>), __VA_ARGS__);              \
-        } else {                                                                        \
-            if (LM <= 1) hipLaunchKernelGGL((KERNEL<3, kSplitQ, 1>), __VA_ARGS__);      \
-            else hipLaunchKernelGGL((KERNEL<3, kSplitQ, 3>), __VA_ARGS__);              \
-        }                                                                               \
+// Variants: analytic radials and Lagrange elements for l <= 1 and l <= 3, and
+// the general variant (tabulated radials, serendipity elements; l <= 3).
+#define PUFE_SPLIT_DISPATCH(KERNEL, NLIMB, LM, GEN, ...)                                      \
+    do {                                                                                     \
+        if (NLIMB == 2) {                                                                    \
+            if (GEN) hipLaunchKernelGGL((KERNEL<2, kSplitQ, 3, true>), __VA_ARGS__);          \
+            else if (LM <= 1) hipLaunchKernelGGL((KERNEL<2, kSplitQ, 1, false>), __VA_ARGS__); \
+            else hipLaunchKernelGGL((KERNEL<2, kSplitQ, 3, false>), __VA_ARGS__);             \
+        } else {                                                                             \
+            if (GEN) hipLaunchKernelGGL((KERNEL<3, kSplitQ, 3, true>), __VA_ARGS__);          \
+            else if (LM <= 1) hipLaunchKernelGGL((KERNEL<3, kSplitQ, 1, false>), __VA_ARGS__); \
+            else hipLaunchKernelGGL((KERNEL<3, kSplitQ, 3, false>), __VA_ARGS__);             \
+        }                                                                                    \
     } while (0)
 
-hipError_t launch_split_persistent(int nlimb, int lmax, const CtxDev *ctxs, const ItemDev *items, int n_items,
+hipError_t launch_split_persistent(int nlimb, int lmax, bool gen, const CtxDev *ctxs, const ItemDev *items, int n_items,
                                    int *counter, int grid, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(reset_counter_split_kernel, dim3(1), dim3(64), 0, st, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
-    PUFE_SPLIT_DISPATCH(contract_split_persistent, nlimb, lmax, dim3(grid), dim3(kSplitThreads), lds, st, ctxs,
+    PUFE_SPLIT_DISPATCH(contract_split_persistent, nlimb, lmax, gen, dim3(grid), dim3(kSplitThreads), lds, st, ctxs,
                         items, n_items, counter);
     return hipGetLastError();
 }
 
 hipError_t init_split_attributes() {
-    const void *ks[8] = {(const void *)contract_split_kernel<2, kSplitQ, 1>,
-                         (const void *)contract_split_kernel<2, kSplitQ, 3>,
-                         (const void *)contract_split_kernel<3, kSplitQ, 1>,
-                         (const void *)contract_split_kernel<3, kSplitQ, 3>,
-                         (const void *)contract_split_persistent<2, kSplitQ, 1>,
-                         (const void *)contract_split_persistent<2, kSplitQ, 3>,
-                         (const void *)contract_split_persistent<3, kSplitQ, 1>,
-                         (const void *)contract_split_persistent<3, kSplitQ, 3>};
+    const void *ks[] = {(const void *)contract_split_kernel<2, kSplitQ, 1, false>,
+                        (const void *)contract_split_kernel<2, kSplitQ, 3, false>,
+                        (const void *)contract_split_kernel<2, kSplitQ, 3, true>,
+                        (const void *)contract_split_kernel<3, kSplitQ, 1, false>,
+                        (const void *)contract_split_kernel<3, kSplitQ, 3, false>,
+                        (const void *)contract_split_kernel<3, kSplitQ, 3, true>,
+                        (const void *)contract_split_persistent<2, kSplitQ, 1, false>,
+                        (const void *)contract_split_persistent<2, kSplitQ, 3, false>,
+                        (const void *)contract_split_persistent<2, kSplitQ, 3, true>,
+                        (const void *)contract_split_persistent<3, kSplitQ, 1, false>,
+                        (const void *)contract_split_persistent<3, kSplitQ, 3, false>,
+                        (const void *)contract_split_persistent<3, kSplitQ, 3, true>};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
         if (e != hipSuccess) return e;
@@ -339,12 +347,12 @@ size_t split_lds_bytes(int nlimb, int rows, int nfun, int nimg, int nleaf, int n
     return SplitLds<kSplitQ>::bytes(nlimb, rows, nfun, nimg, nleaf, n3);
 }
 
-hipError_t launch_contract_split(int nlimb, int lmax, const KParams &kp, int n_items, const ItemDev *items,
+hipError_t launch_contract_split(int nlimb, int lmax, bool gen, const KParams &kp, int n_items, const ItemDev *items,
                                  const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
                                  const uint32_t *leaves, const double *V, double *partial, size_t lds,
                                  hipStream_t st) {
     if (n_items == 0) return hipSuccess;
-    PUFE_SPLIT_DISPATCH(contract_split_kernel, nlimb, lmax, dim3(n_items), dim3(kSplitThreads), lds, st, kp, items,
+    PUFE_SPLIT_DISPATCH(contract_split_kernel, nlimb, lmax, gen, dim3(n_items), dim3(kSplitThreads), lds, st, kp, items,
                         elems, groups, img, edof, leaves, V, partial);
     return hipGetLastError();
 }

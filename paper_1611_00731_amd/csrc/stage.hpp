@@ -133,13 +133,13 @@ __device__ __forceinline__ void point_geometry(const KLocal &kp, const double *o
 // whose geometry record starts at g (field f at g[f * Q]); ps points to the
 // element's enrichment table at that point (function f, component c at
 // ps[(4 f + c) * Q]).  a < 0 (padding row) gives zeros.
-template <int Q>
+template <int Q, bool GEN = true>
 __device__ __forceinline__ void local_row(const KLocal &kp, const double *g, const double *ps, const int32_t *sEd,
                                           int a, int nfe, double *val, double *gx) {
     *val = 0.0;
     gx[0] = gx[1] = gx[2] = 0.0;
     if (a < 0) return;
-    if (a < nfe && kp.p == 3) {
+    if (GEN && a < nfe && kp.p == 3) {
         const double xi[3] = {g[G_XI * Q], g[(G_XI + 1) * Q], g[(G_XI + 2) * Q]};
         double dxi[3];
         serendipity_fn(a, xi, val, dxi);
