@@ -267,8 +267,11 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
  * split-precision form, in which the dense product U = Pt [grad phi; phi]
  * runs on BF16 MFMAs from two or three bf16 limbs per operand with FP32 sums
  * (the rest of the adjoint stays FP64).  Elements of more than 80 local
- * functions give PUFE_ERR_UNSUPPORTED; an unknown precision
- * PUFE_ERR_INVALID_ARG. */
+ * functions (or whose block of Pt, rows and enrichment Hessians do not fit in
+ * LDS together) run a second FP64 kernel that streams the element's block of
+ * Pt through LDS in 64 x 64 blocks; with such elements the split-precision
+ * forms give PUFE_ERR_UNSUPPORTED, as does an element of more than 256
+ * enriched functions.  An unknown precision gives PUFE_ERR_INVALID_ARG. */
 int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3], const void *d_P,
                            const void *d_Q, int precision, double *d_dLdV, double *d_dLdR,
                            void *stream);

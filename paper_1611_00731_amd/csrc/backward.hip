@@ -492,6 +492,273 @@ __global__ __launch_bounds__(256) void backward_kernel(
     }
 }
 
+// Elements of more than 80 functions (FP64).  Their block of Ps does not fit
+// in LDS, so each stage walks the row blocks R of kBwBlock functions and, for
+// each, the column blocks K (R last): Ps[R][K] is copied into LDS, the rows of
+// K are evaluated, and U[R] += Ps[R][K] B[K] accumulates on the MFMAs (one
+// operand component per wave, as in backward_kernel).  With K = R last, sB
+// holds R's own rows when U[R] is complete: the value-component wave adds
+// sum_{a in R} phi_a U_a to the point's density, U of R's enriched rows goes
+// to LDS, and the force contributions of those rows follow.  Thread t owns
+// enriched row nfe + t (the host admits at most 256 enriched functions).
+//   sP  [kBwBlock][RSB]   Ps[R][K], then U of R's enriched rows
+//   sB  [kBwBlock][RSB]   B rows of K, then the force contributions sC
+//   sPsi, sGeo, sImg, sG, sEd, sCS as in backward_kernel
+template <bool QMODE>
+__global__ __launch_bounds__(256) void backward_wide_kernel(
+    const KParams kp, const ItemDev *__restrict__ items, const ElemDev *__restrict__ elems,
+    const GroupDev *__restrict__ groups, const double *__restrict__ img, const int32_t *__restrict__ edof,
+    const uint32_t *__restrict__ leaves, const double *__restrict__ V, const int64_t *__restrict__ pt_off,
+    const double *__restrict__ Pt, double *__restrict__ dLdV, double *__restrict__ fpart, int max_ngrp) {
+    extern __shared__ __attribute__((aligned(16))) double smem[];
+    constexpr int Q = kBackwardQ;
+    constexpr int RSB = BackwardLds<Q>::RSB;
+    constexpr int NT = 256, BK = kBwBlock, TB = BK / 16;
+    const ItemDev it = items[blockIdx.x];
+    const ElemDev &el = elems[it.elem];
+    const int nloc = el.nloc, nfe = el.nfe, ngrp = el.ngrp, nfun = el.nfun, nenr = nloc - nfe;
+    const int npad = 16 * ((nloc + 15) / 16), nb = (nloc + BK - 1) / BK;
+    const int img0 = ngrp > 0 ? groups[el.grp_off].img_off : 0;
+    const int nimg = ngrp > 0 ? groups[el.grp_off + ngrp - 1].img_off + groups[el.grp_off + ngrp - 1].nimg - img0 : 0;
+    double *sP = smem;
+    double *sB = sP + (size_t)BK * RSB;
+    double *sPsi = sB + (size_t)BK * RSB;
+    double *sGeo = sPsi + (size_t)nfun * Q * 10;
+    double *sImg = sGeo + (size_t)Q * BackwardLds<Q>::GEO;
+    GroupDev *sG = (GroupDev *)(sImg + 3 * (size_t)nimg);
+    int32_t *sEd = (int32_t *)(sG + kMaxGroups);
+    int *sCS = sEd + kMaxNloc;
+    double *sUe = sP;   // after a row block's column loop
+    double *sC = sB;    // [BK][Q][3], after the density has read sB
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const int n3 = kp.n3;
+    const int64_t q_begin = it.leaf_b * n3, q_end = it.leaf_e * n3;
+    const double *src = Pt + pt_off[it.elem];
+    for (int k = tid; k < nenr; k += NT) sEd[k] = edof[el.edof_off + k];
+    corner_starts((const PUFE_GLOBAL int32_t *)(edof + el.edof_off), nenr, sCS, tid, NT);
+    for (int g = tid; g < ngrp; g += NT) {
+        GroupDev G = groups[el.grp_off + g];
+        G.img_off -= img0;   // rebased onto sImg
+        sG[g] = G;
+    }
+    for (int k = tid; k < 3 * nimg; k += NT) sImg[k] = img[3 * (size_t)img0 + k];
+    const double org[3] = {el.ijk[0] * kp.E[0] + el.ijk[1] * kp.E[3] + el.ijk[2] * kp.E[6],
+                           el.ijk[0] * kp.E[1] + el.ijk[1] * kp.E[4] + el.ijk[2] * kp.E[7],
+                           el.ijk[0] * kp.E[2] + el.ijk[1] * kp.E[5] + el.ijk[2] * kp.E[8]};
+    const KLocal kl = load_klocal(kp);
+    const int nfu = fe_units(kl.p);
+    double facc[3] = {0.0, 0.0, 0.0};   // forces of enriched row nfe + tid
+    const int gq = tid - (NT - Q);
+    __syncthreads();
+
+    for (int64_t qb = q_begin; qb < q_end; qb += Q) {
+        // ---- phase 1: geometry, enrichment functions with Hessians
+        if (gq >= 0) {
+            const int64_t qg = qb + gq;
+            double xi[3] = {0.0, 0.0, 0.0}, w = 0.0, vq = 0.0;
+            if (qg < q_end) {
+                const int64_t lf = qg / n3;
+                leaf_point(kp, leaves[lf], (int)(qg - lf * n3), xi, &w);
+                vq = V[qg];
+            }
+            double *g = sGeo + gq;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                g[(B_XI + d) * Q] = xi[d];
+                g[(B_X + d) * Q] = org[d] + 0.5 * (xi[0] + 1.0) * kp.E[d] + 0.5 * (xi[1] + 1.0) * kp.E[3 + d] +
+                                   0.5 * (xi[2] + 1.0) * kp.E[6 + d];
+            }
+            g[B_W * Q] = w;
+            g[B_V * Q] = vq;
+            double Lv[9], Dv[9];
+            for (int d = 0; d < 3; ++d) lagrange_1d(kp.p, xi[d], Lv + 3 * d, Dv + 3 * d);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                g[(B_L + k) * Q] = Lv[k];
+                g[(B_D + k) * Q] = Dv[k];
+            }
+            double m[3][2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                m[d][0] = 0.5 * (1.0 - xi[d]);
+                m[d][1] = 0.5 * (1.0 + xi[d]);
+                g[(B_M1 + 2 * d) * Q] = m[d][0];
+                g[(B_M1 + 2 * d + 1) * Q] = m[d][1];
+            }
+#pragma unroll
+            for (int c8 = 0; c8 < 8; ++c8) g[(B_M + c8) * Q] = m[0][c8 & 1] * m[1][(c8 >> 1) & 1] * m[2][c8 >> 2];
+        }
+        for (int idx = tid; idx < ngrp * Q; idx += NT) {
+            const int gi = idx / Q, q = idx - gi * Q;
+            const GroupDev &G = sG[gi];
+            const int64_t qg = qb + q;
+            double xi[3] = {0.0, 0.0, 0.0}, w = 0.0, x[3];
+            if (qg < q_end) {
+                const int64_t lf = qg / n3;
+                leaf_point(kp, leaves[lf], (int)(qg - lf * n3), xi, &w);
+            }
+            for (int d = 0; d < 3; ++d)
+                x[d] = org[d] + 0.5 * (xi[0] + 1.0) * kp.E[d] + 0.5 * (xi[1] + 1.0) * kp.E[3 + d] +
+                       0.5 * (xi[2] + 1.0) * kp.E[6 + d];
+            double *o = sPsi + (size_t)G.fbase * 10 * Q + q;
+            switch (G.l) {
+                case 0: group_eval_hess<0, Q>(G, sImg, kp.spl, x, o); break;
+                case 1: group_eval_hess<1, Q>(G, sImg, kp.spl, x, o); break;
+                case 2: group_eval_hess<2, Q>(G, sImg, kp.spl, x, o); break;
+                default: group_eval_hess<3, Q>(G, sImg, kp.spl, x, o); break;
+            }
+        }
+        __syncthreads();
+        double dens = 0.0;   // wave 3: its lanes' share of phi^T Ps phi at point r16
+        for (int rb = 0; rb < nb; ++rb) {
+            const int r0 = rb * BK, r1 = min(r0 + BK, nloc);
+            double4_t acc[TB];
+#pragma unroll
+            for (int I = 0; I < TB; ++I) acc[I] = (double4_t){0.0, 0.0, 0.0, 0.0};
+            for (int j = 1; j <= nb; ++j) {
+                const int kb = (rb + j) % nb;   // the row block itself comes last
+                const int k0 = kb * BK, k1 = min(k0 + BK, nloc), nkp = 16 * ((k1 - k0 + 15) / 16);
+                // Ps[R][K] (zero past the padded block), and the rows of K (zero past k1)
+                for (int idx = tid; idx < BK * BK; idx += NT) {
+                    const int a = idx / BK, b = idx - a * BK;
+                    const int ga = r0 + a, gb = k0 + b;
+                    sP[(size_t)a * RSB + b] = (ga < npad && gb < npad) ? src[(size_t)ga * npad + gb] : 0.0;
+                }
+                for (int k = tid; k < (BK - (k1 - k0)) * RSB; k += NT) sB[(size_t)(k1 - k0) * RSB + k] = 0.0;
+                {
+                    // FE units when K holds FE rows, then the corner runs of K's enriched rows
+                    const int nu_fe = k0 < nfe ? nfu : 0;
+                    for (int idx = tid; idx < (nu_fe + 8) * Q; idx += NT) {
+                        const int u = idx / Q, q = idx - u * Q;
+                        double *o = sB + q;
+                        auto put = [&](int a, double x, double y, double z, double w) {
+                            if (a < k0 || a >= k1) return;
+                            double *r = o + (size_t)(a - k0) * RSB;
+                            r[0] = x;
+                            r[Q] = y;
+                            r[2 * Q] = z;
+                            r[3 * Q] = w;
+                        };
+                        if (u < nu_fe) {
+                            fe_unit_any<Q, true>(kl, sGeo + q, u, put);
+                        } else {
+                            const int c = u - nu_fe;
+                            const int kb0 = max(sCS[c], k0 - nfe), kb1 = min(sCS[c + 1], k1 - nfe);
+                            if (kb0 < kb1)
+                                pu_unit<Q, 10 * Q, true>(kl, sGeo + q, sPsi + q, sEd, c, kb0, kb1, nfe, put);
+                        }
+                    }
+                }
+                __syncthreads();
+                // U[R] += Ps[R][K] B[K], component `wave`
+                for (int kk = 0; kk < nkp; kk += 4) {
+                    const double b = sB[(size_t)(kk + k4) * RSB + wave * Q + r16];
+#pragma unroll
+                    for (int I = 0; I < TB; ++I) {
+                        const double a = sP[(size_t)(16 * I + r16) * RSB + kk + k4];
+                        acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[I], 0, 0, 0);
+                    }
+                }
+                __syncthreads();
+            }
+            // sB now holds R's own rows: density, then U of R's enriched rows
+            // (register r of lane l is row (l / 16) + 4 r of the tile, point l % 16)
+            if (!QMODE && wave == 3)
+#pragma unroll
+                for (int I = 0; I < TB; ++I)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * I + k4 + 4 * r;
+                        if (r0 + row < r1) dens += sB[(size_t)row * RSB + 3 * Q + r16] * acc[I][r];
+                    }
+#pragma unroll
+            for (int I = 0; I < TB; ++I)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * I + k4 + 4 * r;
+                    if (r0 + row >= nfe && r0 + row < r1) sUe[(size_t)row * RSB + wave * Q + r16] = acc[I][r];
+                }
+            __syncthreads();
+            // force contributions of every (enriched row of R, point)
+            const int e0 = max(r0, nfe);
+            for (int idx = tid; idx < (r1 - e0) * Q; idx += NT) {
+                const int ra = e0 + idx / Q, q = idx % Q, rl = ra - r0;
+                const double *g = sGeo + q;
+                const double w = g[B_W * Q];
+                double cf[3] = {0.0, 0.0, 0.0};
+                if (w != 0.0) {
+                    const int pk = sEd[ra - nfe];
+                    const int corner = pk & 7, f = (pk >> 3) & 255;
+                    const int b0 = corner & 1, b1 = (corner >> 1) & 1, b2 = corner >> 2;
+                    const double m0 = g[(B_M1 + b0) * Q], m1 = g[(B_M1 + 2 + b1) * Q], m2 = g[(B_M1 + 4 + b2) * Q];
+                    const double M = g[(B_M + corner) * Q];
+                    const double dM[3] = {(b0 ? 0.5 : -0.5) * m1 * m2, m0 * (b1 ? 0.5 : -0.5) * m2,
+                                          m0 * m1 * (b2 ? 0.5 : -0.5)};
+                    double gM[3];
+                    for (int cc = 0; cc < 3; ++cc)
+                        gM[cc] = kp.Jt[3 * cc] * dM[0] + kp.Jt[3 * cc + 1] * dM[1] + kp.Jt[3 * cc + 2] * dM[2];
+                    const double *ps = sPsi + (size_t)f * 10 * Q + q;
+                    const double gp[3] = {ps[Q], ps[2 * Q], ps[3 * Q]};
+                    const double Hs[3][3] = {{ps[4 * Q], ps[7 * Q], ps[8 * Q]},
+                                             {ps[7 * Q], ps[5 * Q], ps[9 * Q]},
+                                             {ps[8 * Q], ps[9 * Q], ps[6 * Q]}};
+                    const double *U = sUe + (size_t)rl * RSB + q;
+                    const double u = U[3 * Q];
+                    for (int k = 0; k < 3; ++k) {
+                        const double dphi = -M * gp[k];
+                        double c;
+                        if (QMODE) {
+                            c = 2.0 * dphi * u;
+                        } else {
+                            double gg = 0.0;
+                            for (int jj = 0; jj < 3; ++jj) gg += -(gM[jj] * gp[k] + M * Hs[jj][k]) * U[jj * Q];
+                            c = gg + 2.0 * g[B_V * Q] * dphi * u;
+                        }
+                        cf[k] = w * c;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sC[((size_t)rl * Q + q) * 3 + k] = cf[k];
+            }
+            __syncthreads();
+            {
+                const int ra = nfe + tid;
+                if (tid < nenr && ra >= r0 && ra < r1)
+                    for (int q = 0; q < Q; ++q)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) facc[k] += sC[((size_t)(ra - r0) * Q + q) * 3 + k];
+            }
+            __syncthreads();
+        }
+        if (!QMODE && dLdV != nullptr && wave == 3) {
+            dens += __shfl_xor(dens, 16, 64);
+            dens += __shfl_xor(dens, 32, 64);
+            const int64_t qg = qb + r16;
+            if (k4 == 0 && qg < q_end) dLdV[qg] = sGeo[B_W * Q + r16] * dens;
+        }
+        __syncthreads();
+    }
+    // per-group sums of the row forces, rows in order
+    double *sF = sB;
+    if (tid < nenr)
+        for (int k = 0; k < 3; ++k) sF[3 * tid + k] = facc[k];
+    __syncthreads();
+    if (tid < max_ngrp) {
+        double f[3] = {0.0, 0.0, 0.0};
+        if (tid < ngrp) {
+            const GroupDev G = sG[tid];
+            const int f0 = G.fbase, f1 = G.fbase + 2 * G.l + 1;
+            for (int t = 0; t < nenr; ++t) {
+                const int ff = (sEd[t] >> 3) & 255;
+                if (ff >= f0 && ff < f1)
+                    for (int k = 0; k < 3; ++k) f[k] += sF[3 * t + k];
+            }
+        }
+        for (int k = 0; k < 3; ++k) fpart[((int64_t)blockIdx.x * max_ngrp + tid) * 3 + k] = f[k];
+    }
+}
+
 // dL/dR of atom A: its partial slots summed in the order the host listed them
 // (P pass first, then Q pass).
 __global__ void force_reduce_kernel(int n_atoms, const int64_t *__restrict__ atom_ptr,
@@ -512,12 +779,14 @@ __global__ void force_reduce_kernel(int n_atoms, const int64_t *__restrict__ ato
 }
 
 hipError_t init_backward_attributes() {
-    const void *ks[6] = {(const void *)backward_kernel<kBackwardQ, false, 0>,
+    const void *ks[8] = {(const void *)backward_kernel<kBackwardQ, false, 0>,
                          (const void *)backward_kernel<kBackwardQ, true, 0>,
                          (const void *)backward_kernel<kBackwardQ, false, 2>,
                          (const void *)backward_kernel<kBackwardQ, true, 2>,
                          (const void *)backward_kernel<kBackwardQ, false, 3>,
-                         (const void *)backward_kernel<kBackwardQ, true, 3>};
+                         (const void *)backward_kernel<kBackwardQ, true, 3>,
+                         (const void *)backward_wide_kernel<false>,
+                         (const void *)backward_wide_kernel<true>};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDynLds);
         if (e != hipSuccess) return e;
@@ -527,6 +796,27 @@ hipError_t init_backward_attributes() {
 
 size_t backward_lds_bytes(int npad, int nenr, int nfun, int nimg) {
     return BackwardLds<kBackwardQ>::bytes(npad, nenr, nfun, nimg);
+}
+
+size_t backward_wide_lds_bytes(int nfun, int nimg) {
+    constexpr int Q = kBackwardQ;
+    return sizeof(double) * (2 * (size_t)kBwBlock * BackwardLds<Q>::RSB + (size_t)nfun * Q * 10 +
+                             (size_t)Q * BackwardLds<Q>::GEO + (size_t)nimg * 3) +
+           sizeof(GroupDev) * kMaxGroups + sizeof(int32_t) * (kMaxNloc + 16) + 64;
+}
+
+hipError_t launch_backward_wide(const KParams &kp, bool qmode, int n_items, const ItemDev *items,
+                                const ElemDev *elems, const GroupDev *groups, const double *img, const int32_t *edof,
+                                const uint32_t *leaves, const double *V, const int64_t *pt_off, const double *Pt,
+                                double *dLdV, double *fpart, int max_ngrp, size_t lds, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    if (qmode)
+        hipLaunchKernelGGL((backward_wide_kernel<true>), dim3(n_items), dim3(256), lds, st, kp, items, elems, groups,
+                           img, edof, leaves, V, pt_off, Pt, dLdV, fpart, max_ngrp);
+    else
+        hipLaunchKernelGGL((backward_wide_kernel<false>), dim3(n_items), dim3(256), lds, st, kp, items, elems, groups,
+                           img, edof, leaves, V, pt_off, Pt, dLdV, fpart, max_ngrp);
+    return hipGetLastError();
 }
 
 hipError_t launch_gather_adjoint(const KParams &kp, int64_t nel, const ElemDev *elems, const int32_t *edof,

@@ -92,9 +92,9 @@ struct pufe_ctx {
     DevBuf<ItemDev> d_items, d_items_split, d_items_wide;
     // adjoint
     bool have_bw = false;
-    std::vector<ItemDev> bw_items;
-    size_t bw_lds = 0;
-    DevBuf<ItemDev> d_bw_items;
+    std::vector<ItemDev> bw_items, bw_items_wide;   // elements of <= 80 functions, and the rest
+    size_t bw_lds = 0, bw_lds_wide = 0;
+    DevBuf<ItemDev> d_bw_items, d_bw_items_wide;
     DevBuf<int64_t> d_pt_off, d_atom_ptr, d_atom_slots;
     DevBuf<double> d_Pt, d_fP, d_fQ;
     // separable nonlocal term
@@ -843,39 +843,80 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
 // group partial forces in a fixed order.
 static int plan_backward(pufe_ctx *c, hipStream_t st) {
     Plan &pl = c->plan;
-    int max_npad = 16, max_nfun = 1, max_nenr = 1;
+    int max_npad = 16, max_nfun = 1, max_nenr = 1, max_nfun_wide = 1;
     std::vector<int64_t> pt_off(pl.nel + 1, 0);
+    // an element runs the block-resident kernel when it has at most 80
+    // functions and the launch's stage (sized by the largest Ps, row count and
+    // enrichment table of its elements) still fits in LDS with it: elements
+    // are taken in order of their own stage size; the others run the wide
+    // kernel
+    const int nimg = std::max(pl.max_img, 1);
+    std::vector<char> wide(pl.nel, 1);
+    {
+        std::vector<std::pair<size_t, int64_t>> order;
+        for (int64_t e = 0; e < pl.nel; ++e) {
+            const ElemDev &el = pl.elems[e];
+            if (el.nloc <= kBackwardMaxNloc)
+                order.push_back({backward_lds_bytes(16 * ((el.nloc + 15) / 16), el.nloc - el.nfe, el.nfun, nimg), e});
+        }
+        std::stable_sort(order.begin(), order.end());
+        int np = 16, ne = 1, nf = 1;
+        for (const auto &o : order) {
+            const ElemDev &el = pl.elems[o.second];
+            const int np2 = std::max(np, 16 * ((el.nloc + 15) / 16)), ne2 = std::max(ne, el.nloc - el.nfe);
+            const int nf2 = std::max(nf, el.nfun);
+            if (backward_lds_bytes(np2, ne2, nf2, nimg) > kMaxDynLds) continue;
+            np = np2, ne = ne2, nf = nf2;
+            wide[o.second] = 0;
+        }
+    }
     for (int64_t e = 0; e < pl.nel; ++e) {
         const ElemDev &el = pl.elems[e];
-        if (el.nloc > kBackwardMaxNloc)
-            return fail(c, PUFE_ERR_UNSUPPORTED, "the adjoint kernel holds elements of at most " +
-                                                     std::to_string(kBackwardMaxNloc) + " functions");
-        int npad = 16 * ((el.nloc + 15) / 16);
-        max_npad = std::max(max_npad, npad);
-        max_nfun = std::max(max_nfun, el.nfun);
-        max_nenr = std::max(max_nenr, el.nloc - el.nfe);
+        const int npad = 16 * ((el.nloc + 15) / 16);
+        if (wide[e]) {
+            if (el.nloc - el.nfe > kBackwardWideMaxEnr)
+                return fail(c, PUFE_ERR_UNSUPPORTED, "the adjoint kernels hold at most " +
+                                                         std::to_string(kBackwardWideMaxEnr) +
+                                                         " enriched functions on one element");
+            max_nfun_wide = std::max(max_nfun_wide, el.nfun);
+        } else {
+            max_npad = std::max(max_npad, npad);
+            max_nfun = std::max(max_nfun, el.nfun);
+            max_nenr = std::max(max_nenr, el.nloc - el.nfe);
+        }
         pt_off[e + 1] = pt_off[e] + (int64_t)npad * npad;
     }
-    c->bw_lds = backward_lds_bytes(max_npad, max_nenr, max_nfun, std::max(pl.max_img, 1));
-    if (c->bw_lds > kMaxDynLds) return fail(c, PUFE_ERR_UNSUPPORTED, "adjoint stage does not fit in LDS");
+    c->bw_lds = backward_lds_bytes(max_npad, max_nenr, max_nfun, nimg);
+    c->bw_lds_wide = backward_wide_lds_bytes(max_nfun_wide, nimg);
+    if (c->bw_lds > kMaxDynLds || c->bw_lds_wide > kMaxDynLds)
+        return fail(c, PUFE_ERR_UNSUPPORTED, "adjoint stage does not fit in LDS");
     c->bw_items.clear();
+    c->bw_items_wide.clear();
     const int mg = std::max(pl.max_ngrp, 1);
-    std::vector<std::vector<int64_t>> slots(c->prob.species.size());
-    for (int64_t e = 0; e < pl.nel; ++e) {
-        const ElemDev &el = pl.elems[e];
-        // twice the forward's K-chunks (at most one per leaf): the adjoint's
-        // stages cost more, and finer items balance the refined elements
-        int64_t nleaf = el.leaf_end - el.leaf_off, nch = std::min<int64_t>(2 * el.nchunk, nleaf);
-        for (int64_t ch = 0; ch < nch; ++ch) {
-            ItemDev it{};
-            it.elem = (int32_t)e;
-            it.chunk = (int32_t)ch;
-            it.leaf_b = el.leaf_off + ch * nleaf / nch;
-            it.leaf_e = el.leaf_off + (ch + 1) * nleaf / nch;
-            int64_t idx = (int64_t)c->bw_items.size();
-            c->bw_items.push_back(it);
-            for (int g = 0; g < el.ngrp; ++g) slots[pl.groups[el.grp_off + g].atom].push_back(idx * mg + g);
+    // items of elements up to 80 functions first, then the wide ones; the
+    // partial-force slots follow that order
+    for (int pass = 0; pass < 2; ++pass)
+        for (int64_t e = 0; e < pl.nel; ++e) {
+            const ElemDev &el = pl.elems[e];
+            if ((wide[e] != 0) != (pass == 1)) continue;
+            // twice the forward's K-chunks (at most one per leaf): the adjoint's
+            // stages cost more, and finer items balance the refined elements
+            int64_t nleaf = el.leaf_end - el.leaf_off, nch = std::min<int64_t>(2 * el.nchunk, nleaf);
+            for (int64_t ch = 0; ch < nch; ++ch) {
+                ItemDev it{};
+                it.elem = (int32_t)e;
+                it.chunk = (int32_t)ch;
+                it.leaf_b = el.leaf_off + ch * nleaf / nch;
+                it.leaf_e = el.leaf_off + (ch + 1) * nleaf / nch;
+                (pass == 0 ? c->bw_items : c->bw_items_wide).push_back(it);
+            }
         }
+    std::vector<std::vector<int64_t>> slots(c->prob.species.size());
+    const int64_t nn = (int64_t)c->bw_items.size(), ntot = nn + (int64_t)c->bw_items_wide.size();
+    for (int64_t idx = 0; idx < ntot; ++idx) {
+        const ItemDev &it = idx < nn ? c->bw_items[idx] : c->bw_items_wide[idx - nn];
+        const ElemDev &el = pl.elems[it.elem];
+        for (int g = 0; g < el.ngrp; ++g) slots[pl.groups[el.grp_off + g].atom].push_back(idx * mg + g);
     }
     std::vector<int64_t> aptr(slots.size() + 1, 0), aslots;
     for (size_t A = 0; A < slots.size(); ++A) {
@@ -883,12 +924,13 @@ static int plan_backward(pufe_ctx *c, hipStream_t st) {
         aptr[A + 1] = (int64_t)aslots.size();
     }
     CHECK_HIP(c, c->d_bw_items.upload(c->bw_items, st), "upload adjoint items");
+    CHECK_HIP(c, c->d_bw_items_wide.upload(c->bw_items_wide, st), "upload adjoint items");
     CHECK_HIP(c, c->d_pt_off.upload(pt_off, st), "upload adjoint offsets");
     CHECK_HIP(c, c->d_atom_ptr.upload(aptr, st), "upload atom lists");
     CHECK_HIP(c, c->d_atom_slots.upload(aslots, st), "upload atom lists");
     CHECK_HIP(c, c->d_Pt.alloc((size_t)pt_off[pl.nel]), "alloc adjoint blocks");
-    CHECK_HIP(c, c->d_fP.alloc(c->bw_items.size() * mg * 3), "alloc partial forces");
-    CHECK_HIP(c, c->d_fQ.alloc(c->bw_items.size() * mg * 3), "alloc partial forces");
+    CHECK_HIP(c, c->d_fP.alloc((size_t)ntot * mg * 3), "alloc partial forces");
+    CHECK_HIP(c, c->d_fQ.alloc((size_t)ntot * mg * 3), "alloc partial forces");
     c->have_bw = true;
     return PUFE_OK;
 }
@@ -910,15 +952,25 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
         if (rc != PUFE_OK) return rc;
     }
     const Plan &pl = ctx->plan;
+    const int nwide = (int)ctx->bw_items_wide.size();
+    if (nl != 0 && nwide > 0)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED,
+                    "the split-precision adjoint holds elements of at most " + std::to_string(kBackwardMaxNloc) +
+                        " functions (use FP64)");
     TimedRegion tr(ctx, 2, st);
     const int mg = std::max(pl.max_ngrp, 1);
     const int nit = (int)ctx->bw_items.size();
+    const size_t wide_slots = (size_t)nit * mg * 3;   // the wide items' partial forces follow the others
     if (d_P) {
         CHECK_HIP(ctx, launch_gather_adjoint(pl.kp, pl.nel, ctx->d_elems.p, ctx->d_edof.p, ctx->d_pt_off.p,
                                              (const double *)d_P, kpt, ctx->d_Pt.p, st), "gather P");
         CHECK_HIP(ctx, launch_backward(pl.kp, false, nl, nit, ctx->d_bw_items.p, ctx->d_elems.p, ctx->d_groups.p,
                                        ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_pt_off.p,
                                        ctx->d_Pt.p, d_dLdV, ctx->d_fP.p, mg, ctx->bw_lds, st), "adjoint (P)");
+        CHECK_HIP(ctx, launch_backward_wide(pl.kp, false, nwide, ctx->d_bw_items_wide.p, ctx->d_elems.p,
+                                            ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V,
+                                            ctx->d_pt_off.p, ctx->d_Pt.p, d_dLdV, ctx->d_fP.p + wide_slots, mg,
+                                            ctx->bw_lds_wide, st), "adjoint (P, wide elements)");
     } else if (d_dLdV) {
         CHECK_HIP(ctx, launch_fill_zero(d_dLdV, ctx->n_qp, false, st), "zero dLdV");
     }
@@ -928,6 +980,10 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
         CHECK_HIP(ctx, launch_backward(pl.kp, true, nl, nit, ctx->d_bw_items.p, ctx->d_elems.p, ctx->d_groups.p,
                                        ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V, ctx->d_pt_off.p,
                                        ctx->d_Pt.p, nullptr, ctx->d_fQ.p, mg, ctx->bw_lds, st), "adjoint (Q)");
+        CHECK_HIP(ctx, launch_backward_wide(pl.kp, true, nwide, ctx->d_bw_items_wide.p, ctx->d_elems.p,
+                                            ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p, d_V,
+                                            ctx->d_pt_off.p, ctx->d_Pt.p, nullptr, ctx->d_fQ.p + wide_slots, mg,
+                                            ctx->bw_lds_wide, st), "adjoint (Q, wide elements)");
     }
     if (d_dLdR)
         CHECK_HIP(ctx, launch_force_reduce((int)ctx->prob.species.size(), ctx->d_atom_ptr.p, ctx->d_atom_slots.p,

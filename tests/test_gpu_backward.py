@@ -262,3 +262,110 @@ def test_backward_random_small_problems(seed):
         say(prec, "dL/dV", ev, "dL/dR", er)
         assert ev < tol and er < tol, (seed, prec)
     p.close()
+
+
+WIDE_CASES = {
+    # 16 of 18 elements above 80 functions (up to 132: three row blocks)
+    "ceal-mixed": lambda: W.small("ceal", mesh=(3, 3, 2), fe_order=2, levels=1, n=3, a=5.4, rc=3.0, re=2.0),
+    # serendipity elements of up to 196 functions (four row blocks)
+    "ceal-serendipity": lambda: W.small("ceal", mesh=(2, 2, 2), fe_order=3, levels=1, n=3, a=4.4, rc=3.0, re=2.4),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WIDE_CASES))
+def test_backward_wide_elements_match_oracle(name):
+    """Elements of more than 80 functions (the block of Ps streamed through
+    LDS in 64 x 64 blocks): dL/dV and dL/dR against the oracle's dense
+    adjoint at a general k-point, P and Q both given; the split forms refuse
+    such elements."""
+    prob = WIDE_CASES[name]()
+    say("backward wide elements", name)
+    o = oracle.Oracle(prob)
+    xyz, w, off = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob).cpu().numpy()
+    Cp = W.adjoint_factor(o.n_dof, rank=6, seed=0)
+    Cq = W.adjoint_factor(o.n_dof, rank=3, seed=1)
+    Pd, Qd = Cp @ Cp.conj().T, Cq @ Cq.conj().T
+    kap = (0.12, -0.24, 0.37)
+    dV_o, dR_o = o.backward_dense(V, kap, Pd, Qd)
+    p = P.Problem(prob).setup()
+    rows, cols = bsr_index(p.layout())
+    Pb = torch.from_numpy(Pd[rows, cols]).cuda()
+    Qb = torch.from_numpy(Qd[rows, cols]).cuda()
+    Vd = torch.from_numpy(V).cuda()
+    dV, dR = p.backward(Vd, kap, Pb, Qb)
+    ev = rel(dV.cpu().numpy(), dV_o)
+    er = np.abs(dR.cpu().numpy() - dR_o).max() / np.abs(dR_o).max()
+    say(name, "max n_loc", p.sizes["max_nloc"], "dL/dV", ev, "dL/dR", er)
+    assert p.sizes["max_nloc"] > 80 and ev < 1e-11 and er < 1e-11
+    dV2, dR2 = p.backward(Vd, kap, Pb, Qb)
+    assert torch.equal(dV2, dV) and torch.equal(dR2, dR)
+    with pytest.raises(P.PufeError) as err:
+        p.backward(Vd, kap, Pb, Qb, precision="bf16x6")
+    assert err.value.code == -2
+    p.close()
+
+
+def test_backward_ceal_cell_full_size():
+    """The CeAl-like cell (1728 elements, 27.3 M points, n_loc up to 283) with
+    a rank-16 Hermitian PSD P on the pattern at Gamma: dL/dV point by point
+    on sampled elements (refined and not, above 80 functions) against the
+    oracle's per-element adjoint, and dL/dR of both atoms against central
+    differences of the GPU forward."""
+    prob = W.ceal_cell()
+    say("backward ceal_cell full size")
+    o = oracle.Oracle(prob)
+    p = P.Problem(prob).setup()
+    xyz, _, qoff = p.quadrature()
+    Vd = potential_at(xyz, prob)
+    del xyz
+    qoff = qoff.cpu().numpy()
+    lay = p.layout()
+    N = p.sizes["n_dof"]
+    Cf = W.adjoint_factor(N, rank=16, seed=2)
+    Cd = torch.from_numpy(Cf).cuda()
+    rows, cols = bsr_index(lay)
+    Pb = torch.empty(len(rows), dtype=torch.complex128, device="cuda")
+    for s in range(0, len(rows), 1 << 22):
+        r = torch.from_numpy(rows[s:s + (1 << 22)]).cuda()
+        c = torch.from_numpy(cols[s:s + (1 << 22)]).cuda()
+        Pb[s:s + (1 << 22)] = (Cd[r] * Cd[c].conj()).sum(-1)
+    del Cd
+    dV, dR = p.backward(Vd, (0.0, 0.0, 0.0), Pb, None)
+    dVh = dV.cpu().numpy()
+    g = dR.cpu().numpy()
+    _, _, loff = o.leaves()
+    nleaf = np.diff(loff)
+    nloc = np.array([o.element_dofs(e)[0].size for e in range(o.n_elem)])
+    wide = np.nonzero(nloc > 80)[0]
+    picks = [int(wide[np.argmax(nloc[wide] * (nleaf[wide] == 1))]),                     # widest unrefined
+             int(wide[np.argmin(np.where(nleaf[wide] > 1, nleaf[wide], 1 << 30))]),     # least refined wide
+             int(np.argmin(nloc))]                                                        # a narrow one
+    Vh = Vd.cpu().numpy()
+    for e in picks:
+        gd, _ = o.element_dofs(e)
+        Ploc = Cf[gd] @ Cf[gd].conj().T
+        dv_o, _ = o.backward_element(e, Vh[qoff[e]:qoff[e + 1]], (0, 0, 0), Ploc)
+        err = rel(dVh[qoff[e]:qoff[e + 1]], dv_o)
+        say("element", e, "n_loc", nloc[e], "leaves", nleaf[e], "dL/dV", err)
+        assert err < 1e-11
+    R0 = np.asarray(prob["atoms"], float)
+
+    def loss(R):
+        p.set_positions(R)
+        H, _ = p.assemble(Vd, [(0, 0, 0)], with_S=False)
+        return float((Pb.conj() * torch.view_as_complex(H[0])).real.sum())
+
+    h = 1e-4
+    worst = 0.0
+    for A in range(len(R0)):
+        for k in range(3):
+            Rp, Rm = R0.copy(), R0.copy()
+            Rp[A, k] += h
+            Rm[A, k] -= h
+            fd = (loss(Rp) - loss(Rm)) / (2 * h)
+            worst = max(worst, abs(fd - g[A, k]) / np.abs(g).max())
+    say("ceal dL/dR", g.tolist(), "central differences worst relative error", worst)
+    assert worst < 1e-6
+    p.set_positions(R0)
+    p.close()
