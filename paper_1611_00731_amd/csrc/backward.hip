@@ -61,14 +61,12 @@ __global__ __launch_bounds__(256) void gather_adjoint_kernel(const KParams kp, c
 template <int L, int Q>
 __device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double *__restrict__ img,
                                                 const double *__restrict__ spl, const double *x, double *o) {
+    // the sums over images accumulate in place (the first image writes, later
+    // ones add), so no per-function accumulators stay live in registers
     constexpr int NM = 2 * L + 1;
-    double acc[NM][10];
-#pragma unroll
-    for (int m = 0; m < NM; ++m)
-#pragma unroll
-        for (int c = 0; c < 10; ++c) acc[m][c] = 0.0;
     const double rc2 = G.rc * G.rc, inv_rc2 = 1.0 / rc2;
     const double *c0 = img + 3 * G.img_off;
+    bool first = true;
     for (int k = 0; k < G.nimg; ++k) {
         const double r[3] = {x[0] - c0[3 * k], x[1] - c0[3 * k + 1], x[2] - c0[3 * k + 2]};
         const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -88,22 +86,30 @@ __device__ __forceinline__ void group_eval_hess(const GroupDev &G, const double 
         const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
-            acc[m][0] += g0 * S[m];
+            double v[10];
+            v[0] = g0 * S[m];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) acc[m][1 + d] += 2.0 * g1 * r[d] * S[m] + g0 * dS[3 * m + d];
+            for (int d = 0; d < 3; ++d) v[1 + d] = 2.0 * g1 * r[d] * S[m] + g0 * dS[3 * m + d];
 #pragma unroll
             for (int t = 0; t < 6; ++t) {
                 const int i = ii[t], j = jj[t];
-                acc[m][4 + t] += 4.0 * g2 * r[i] * r[j] * S[m] +
-                                 2.0 * g1 * ((i == j ? S[m] : 0.0) + r[i] * dS[3 * m + j] + dS[3 * m + i] * r[j]) +
-                                 g0 * hS[6 * m + t];
+                v[4 + t] = 4.0 * g2 * r[i] * r[j] * S[m] +
+                           2.0 * g1 * ((i == j ? S[m] : 0.0) + r[i] * dS[3 * m + j] + dS[3 * m + i] * r[j]) +
+                           g0 * hS[6 * m + t];
+            }
+#pragma unroll
+            for (int c = 0; c < 10; ++c) {
+                double &oc = o[(size_t)(m * 10 + c) * Q];
+                oc = first ? v[c] : oc + v[c];
             }
         }
+        first = false;
     }
+    if (first)
 #pragma unroll
-    for (int m = 0; m < NM; ++m)
+        for (int m = 0; m < NM; ++m)
 #pragma unroll
-        for (int c = 0; c < 10; ++c) o[(size_t)(m * 10 + c) * Q] = acc[m][c];
+            for (int c = 0; c < 10; ++c) o[(size_t)(m * 10 + c) * Q] = 0.0;
 }
 
 // LDS map of the adjoint (per work item):
