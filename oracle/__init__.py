@@ -76,6 +76,12 @@ def lib():
         L.or_basis_at.argtypes = [C.c_void_p, C.c_int64, _f64p, _f64p, _f64p]
         L.or_enrichment.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _f64p,
                                     _f64p, _f64p, _f64p]
+        L.or_enrichment_bloch.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _f64p, _f64p,
+                                          _f64p, _f64p]
+        L.or_element_matrices_bloch.argtypes = [C.c_void_p, C.c_int64, _f64p, _f64p, _f64p, _f64p]
+        L.or_assemble_dense_bloch.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p]
+        L.or_assemble_block_bloch.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int64, C.c_int64,
+                                              _f64p, _f64p]
         L.or_gauss_legendre.argtypes = [C.c_int, _f64p, _f64p]
         L.or_lagrange.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]
@@ -252,6 +258,47 @@ class Oracle:
         h = np.zeros(9)
         lib().or_enrichment(self.h, atom, desc, m, np.asarray(x, np.float64), v, g, h)
         return v[0], g, h.reshape(3, 3)
+
+    # ---- Bloch-periodic enrichment (f(R) = exp(i k.R) in eq. Psi, periodic PU)
+    def enrichment_bloch(self, atom, desc, m, x, kappa):
+        """Psi^k and its gradient at x (complex)."""
+        v = np.zeros(2)
+        g = np.zeros(6)
+        lib().or_enrichment_bloch(self.h, atom, desc, m, np.asarray(x, np.float64),
+                                  np.asarray(kappa, np.float64), v, g)
+        return v[0] + 1j * v[1], g[:3] + 1j * g[3:]
+
+    def element_matrices_bloch(self, e, V_elem, kappa):
+        n = lib().or_element_nloc(self.h, e)
+        He = np.zeros((n, n, 2))
+        Se = np.zeros((n, n, 2))
+        lib().or_element_matrices_bloch(self.h, e, np.ascontiguousarray(V_elem, np.float64),
+                                        np.asarray(kappa, np.float64), He, Se)
+        return He[..., 0] + 1j * He[..., 1], Se[..., 0] + 1j * Se[..., 1]
+
+    def assemble_dense_bloch(self, V, kappa):
+        N = self.n_dof
+        H = np.zeros((N, N, 2))
+        S = np.zeros((N, N, 2))
+        lib().or_assemble_dense_bloch(self.h, np.ascontiguousarray(V, np.float64),
+                                      np.asarray(kappa, np.float64), H, S)
+        return H[..., 0] + 1j * H[..., 1], S[..., 0] + 1j * S[..., 1]
+
+    def assemble_block_bloch(self, V, kappa, v, w):
+        off = self.dof_offset()
+        nr, nc = off[v + 1] - off[v], off[w + 1] - off[w]
+        Hb = np.zeros((nr, nc, 2))
+        Sb = np.zeros((nr, nc, 2))
+        lib().or_assemble_block_bloch(self.h, np.ascontiguousarray(V, np.float64),
+                                      np.asarray(kappa, np.float64), v, w, Hb, Sb)
+        return Hb[..., 0] + 1j * Hb[..., 1], Sb[..., 0] + 1j * Sb[..., 1]
+
+    def assemble(self, V, kappa):
+        """Dense H, S in the problem's enrichment form ("enrichment_phase":
+        "periodic", the default, or "bloch")."""
+        if self.prob.get("enrichment_phase", "periodic") == "bloch":
+            return self.assemble_dense_bloch(V, kappa)
+        return self.assemble_dense(V, kappa)
 
     def _projectors(self, projectors):
         pr = list(projectors if projectors is not None else self.prob.get("projectors", []))

@@ -11,6 +11,9 @@
  *    periodic enrichment functions (f(R) = 1 in eq. Psi), so every element
  *    matrix is real and the k-point enters only through the boundary phases
  *    (section "Self-consistent calculations", cubic FE + trilinear PU);
+ *    the Bloch-periodic enrichment (f(R) = exp(i k.R)) goes with periodic PU
+ *    functions, and its element matrices are complex and per k-point
+ *    (the *_bloch functions);
  *  - k-points in reduced coordinates kappa: a local node whose vertex index
  *    wraps by the lattice shift n carries the phase exp(2 pi i kappa.n);
  *  - the conjugated index of H_ij and S_ij is the row index i (eq. disceig3d);
@@ -305,15 +308,64 @@ static void spline_eval(const or_state *s, int k, double r, double *u, double *u
     *u2 = A * M[j] + B * M[j + 1];
 }
 
-/* Periodic enrichment function (eqs. Psitilde and Psi with f(R) = 1):
- * Psi(x) = sum over lattice translations R of g(|x - tau - R|^2) S_lm(x - tau - R),
- * g(s) = exp(-a s) (1 - s/rc^2)^3 for s < rc^2, else 0.  Every image within
- * the cutoff is included (for the paper's cells this is its -2..2 range).
- * Returns value, gradient and Hessian. */
-void or_enrichment(const or_state *s, int atom, int desc, int m, const double *x,
-                   double *val, double *grad, double *hess) {
+/* One lattice image's term of the enrichment sum (eq. Psitilde):
+ * Psi~(r) = radial(|r|) S_lm(r) at the offset r = x - tau - R from the image
+ * centre, with its gradient and Hessian; zero at and beyond the cutoff.
+ * Analytic radial: g(s) = exp(-a s) (1 - s/rc^2)^3 in s = |r|^2; tabulated:
+ * the spline u(|r|) (already times the cutoff h). */
+static void image_term(const or_state *s, int desc, int m, const double *r, double *val, double *grad,
+                       double *hess) {
     int l = s->enr_l[desc];
     double a = s->enr_a[desc], rc = s->enr_rc[desc];
+    double sq = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    *val = 0.0;
+    for (int i = 0; i < 3; ++i) grad[i] = 0.0;
+    for (int i = 0; i < 9; ++i) hess[i] = 0.0;
+    if (sq >= rc * rc) return;
+    if (s->enr_nrad[desc] > 0) {
+        /* tabulated: Psi~ = u(|r|) S_lm(r), with
+         * grad u = u' r_hat and
+         * hess u = u'' r_hat r_hat^T + (u'/|r|) (I - r_hat r_hat^T) */
+        double rr = sqrt(sq), u, u1, u2;
+        spline_eval(s, desc, rr, &u, &u1, &u2);
+        double S, dS[3], hS[9], rh[3] = {0, 0, 0}, u1r = u2;   /* u'/|r| -> u''(0) at r = 0 */
+        if (rr > 0.0) {
+            for (int i = 0; i < 3; ++i) rh[i] = r[i] / rr;
+            u1r = u1 / rr;
+        }
+        or_solid_harmonic(l, m, r, &S, dS, hS);
+        *val = u * S;
+        for (int i = 0; i < 3; ++i) grad[i] = u1 * rh[i] * S + u * dS[i];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double hu = (u2 - u1r) * rh[i] * rh[j] + (i == j ? u1r : 0.0);
+                hess[i * 3 + j] = hu * S + u1 * (rh[i] * dS[j] + dS[i] * rh[j]) + u * hS[i * 3 + j];
+            }
+        return;
+    }
+    double e = exp(-a * sq), c = 1.0 - sq / (rc * rc);
+    double g = e * c * c * c;
+    double g1 = -a * e * c * c * c - 3.0 * e * c * c / (rc * rc);
+    double g2 = a * a * e * c * c * c + 6.0 * a * e * c * c / (rc * rc)
+              + 6.0 * e * c / (rc * rc * rc * rc);
+    double S, dS[3], hS[9];
+    or_solid_harmonic(l, m, r, &S, dS, hS);
+    *val = g * S;
+    for (int i = 0; i < 3; ++i) grad[i] = 2.0 * g1 * r[i] * S + g * dS[i];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            hess[i * 3 + j] = 4.0 * g2 * r[i] * r[j] * S
+                            + 2.0 * g1 * ((i == j ? S : 0.0) + r[i] * dS[j] + dS[i] * r[j])
+                            + g * hS[i * 3 + j];
+}
+
+/* Periodic enrichment function (eqs. Psitilde and Psi with f(R) = 1):
+ * Psi(x) = sum over lattice translations R of Psi~(x - tau - R).  Every image
+ * within the cutoff is included (for the paper's cells this is its -2..2
+ * range).  Returns value, gradient and Hessian. */
+void or_enrichment(const or_state *s, int atom, int desc, int m, const double *x,
+                   double *val, double *grad, double *hess) {
+    double rc = s->enr_rc[desc];
     const double *tau = s->pos + 3 * atom;
     double ux[3];
     cart2red(s, x, ux);
@@ -326,47 +378,49 @@ void or_enrichment(const or_state *s, int atom, int desc, int m, const double *x
                 double nn[3] = {(double)n1, (double)n2, (double)n3}, R[3], r[3];
                 red2cart(s, nn, R);
                 for (int c = 0; c < 3; ++c) r[c] = x[c] - tau[c] - R[c];
-                double sq = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                if (sq >= rc * rc) continue;
-                if (s->enr_nrad[desc] > 0) {
-                    /* tabulated: Psi~ = u(|r|) S_lm(r), with
-                     * grad u = u' r_hat and
-                     * hess u = u'' r_hat r_hat^T + (u'/|r|) (I - r_hat r_hat^T) */
-                    double rr = sqrt(sq), u, u1, u2;
-                    spline_eval(s, desc, rr, &u, &u1, &u2);
-                    double S, dS[3], hS[9], rh[3] = {0, 0, 0}, u1r = u2;   /* u'/|r| -> u''(0) at r = 0 */
-                    if (rr > 0.0) {
-                        for (int i = 0; i < 3; ++i) rh[i] = r[i] / rr;
-                        u1r = u1 / rr;
-                    }
-                    or_solid_harmonic(l, m, r, &S, dS, hS);
-                    v += u * S;
-                    for (int i = 0; i < 3; ++i) g3[i] += u1 * rh[i] * S + u * dS[i];
-                    for (int i = 0; i < 3; ++i)
-                        for (int j = 0; j < 3; ++j) {
-                            double hu = (u2 - u1r) * rh[i] * rh[j] + (i == j ? u1r : 0.0);
-                            h9[i * 3 + j] += hu * S + u1 * (rh[i] * dS[j] + dS[i] * rh[j]) + u * hS[i * 3 + j];
-                        }
-                    continue;
-                }
-                double e = exp(-a * sq), c = 1.0 - sq / (rc * rc);
-                double g = e * c * c * c;
-                double g1 = -a * e * c * c * c - 3.0 * e * c * c / (rc * rc);
-                double g2 = a * a * e * c * c * c + 6.0 * a * e * c * c / (rc * rc)
-                          + 6.0 * e * c / (rc * rc * rc * rc);
-                double S, dS[3], hS[9];
-                or_solid_harmonic(l, m, r, &S, dS, hS);
-                v += g * S;
-                for (int i = 0; i < 3; ++i) g3[i] += 2.0 * g1 * r[i] * S + g * dS[i];
-                for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j)
-                        h9[i * 3 + j] += 4.0 * g2 * r[i] * r[j] * S
-                                       + 2.0 * g1 * ((i == j ? S : 0.0) + r[i] * dS[j] + dS[i] * r[j])
-                                       + g * hS[i * 3 + j];
+                double tv, tg[3], th[9];
+                image_term(s, desc, m, r, &tv, tg, th);
+                v += tv;
+                for (int i = 0; i < 3; ++i) g3[i] += tg[i];
+                for (int i = 0; i < 9; ++i) h9[i] += th[i];
             }
     if (val) *val = v;
     if (grad) memcpy(grad, g3, sizeof g3);
     if (hess) memcpy(hess, h9, sizeof h9);
+}
+
+/* Bloch-periodic enrichment function (eq. Psi with f(R) = exp(i k.R)):
+ * Psi^k(x) = sum over R = n.a of exp(2 pi i kappa.n) Psi~(x - tau - R), tau
+ * the atom position as given (moving the atom by a lattice vector multiplies
+ * the function by a constant phase).  val[2] = (Re, Im) of the value,
+ * grad[6] = the real parts of the gradient, then the imaginary parts. */
+void or_enrichment_bloch(const or_state *s, int atom, int desc, int m, const double *x, const double *kappa,
+                         double *val, double *grad) {
+    double rc = s->enr_rc[desc];
+    const double *tau = s->pos + 3 * atom;
+    double ux[3];
+    cart2red(s, x, ux);
+    int lo[3], hi[3];
+    image_range(s, tau, ux, ux, rc, lo, hi);
+    for (int i = 0; i < 2; ++i) val[i] = 0.0;
+    for (int i = 0; i < 6; ++i) grad[i] = 0.0;
+    for (int n3 = lo[2]; n3 <= hi[2]; ++n3)
+        for (int n2 = lo[1]; n2 <= hi[1]; ++n2)
+            for (int n1 = lo[0]; n1 <= hi[0]; ++n1) {
+                double nn[3] = {(double)n1, (double)n2, (double)n3}, R[3], r[3];
+                red2cart(s, nn, R);
+                for (int c = 0; c < 3; ++c) r[c] = x[c] - tau[c] - R[c];
+                double tv, tg[3], th[9];
+                image_term(s, desc, m, r, &tv, tg, th);
+                double t = 2.0 * OR_PI * (kappa[0] * n1 + kappa[1] * n2 + kappa[2] * n3);
+                double cr = cos(t), ci = sin(t);
+                val[0] += cr * tv;
+                val[1] += ci * tv;
+                for (int i = 0; i < 3; ++i) {
+                    grad[i] += cr * tg[i];
+                    grad[3 + i] += ci * tg[i];
+                }
+            }
 }
 
 /* ----------------------------------------------------------- topology */
@@ -1110,6 +1164,135 @@ void or_assemble_block(const or_state *s, const double *V, const double *kappa, 
         }
     }
     free(L); free(He); free(Se);
+}
+
+/* ----------------------------------------- Bloch-periodic enrichment basis */
+
+/* Values and gradients, real parts vr, gr and imaginary parts vi, gi, of the
+ * element's basis when the enrichment is Bloch-periodic (eq. Psi with
+ * f(R) = exp(i k.R)): the classical FE functions as in basis_eval (real),
+ * and PU functions times Psi^k (or_enrichment_bloch).  The PU functions carry
+ * no boundary phase in this form: they are periodic, so that their product
+ * with the Bloch-periodic Psi^k is Bloch-periodic. */
+static void basis_eval_bloch(const or_state *s, int64_t e, const loc_fn *L, int nloc, const double *xi,
+                             const double *kappa, double *vr, double *vi, double *gr, double *gi) {
+    double x[3];
+    ref2phys(s, e, xi, x);
+    basis_eval(s, e, L, nloc, xi, vr, gr);   /* FE rows; enriched rows replaced below */
+    for (int a = 0; a < nloc; ++a) {
+        vi[a] = 0.0;
+        for (int c = 0; c < 3; ++c) gi[3 * a + c] = 0.0;
+        if (L[a].kind == 0) continue;
+        double M = 1.0, dxi[3] = {1.0, 1.0, 1.0};
+        for (int d = 0; d < 3; ++d) {
+            double lv, ld;
+            or_lagrange(1, (L[a].corner >> d) & 1, xi[d], &lv, &ld);
+            for (int k = 0; k < 3; ++k) dxi[k] *= (k == d) ? ld : lv;
+            M *= lv;
+        }
+        double gM[3], psi[2], gpsi[6];
+        ref_grad(s, dxi, gM);
+        or_enrichment_bloch(s, L[a].atom, L[a].desc, L[a].m, x, kappa, psi, gpsi);
+        vr[a] = M * psi[0];
+        vi[a] = M * psi[1];
+        for (int c = 0; c < 3; ++c) {
+            gr[3 * a + c] = gM[c] * psi[0] + M * gpsi[c];
+            gi[3 * a + c] = gM[c] * psi[1] + M * gpsi[3 + c];
+        }
+    }
+}
+
+/* Complex element matrices of the Bloch-enriched basis (eq. disceig3d on one
+ * element), interleaved (Re, Im), n x n:
+ *   H_e[a][b] = sum_q w_q (1/2 conj(grad phi_a) . grad phi_b + V_q conj(phi_a) phi_b),
+ *   S_e[a][b] = sum_q w_q conj(phi_a) phi_b. */
+static void elem_mats_bloch(const or_state *s, int64_t e, const loc_fn *L, int n, const double *V,
+                            const double *kappa, double *He, double *Se) {
+    double *vr = malloc(sizeof(double) * n), *vi = malloc(sizeof(double) * n);
+    double *gr = malloc(sizeof(double) * 3 * n), *gi = malloc(sizeof(double) * 3 * n);
+    memset(He, 0, sizeof(double) * 2 * n * n);
+    memset(Se, 0, sizeof(double) * 2 * n * n);
+    int64_t nq3 = (int64_t)s->q_n * s->q_n * s->q_n, q = 0;
+    for (int64_t lf = s->leaf_off[e]; lf < s->leaf_off[e + 1]; ++lf)
+        for (int64_t j = 0; j < nq3; ++j, ++q) {
+            double xi[3], w;
+            leaf_point(s, s->leaf_level[lf], s->leaf_ijk + 3 * lf, j, xi, &w);
+            basis_eval_bloch(s, e, L, n, xi, kappa, vr, vi, gr, gi);
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) {
+                    /* conj(u) v = (ur ur' + ui vi') + i (ur vi' - ui vr') */
+                    double pr = vr[a] * vr[b] + vi[a] * vi[b], pi = vr[a] * vi[b] - vi[a] * vr[b];
+                    double ggr = 0.0, ggi = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        ggr += gr[3 * a + c] * gr[3 * b + c] + gi[3 * a + c] * gi[3 * b + c];
+                        ggi += gr[3 * a + c] * gi[3 * b + c] - gi[3 * a + c] * gr[3 * b + c];
+                    }
+                    He[2 * (a * n + b)] += w * (0.5 * ggr + V[q] * pr);
+                    He[2 * (a * n + b) + 1] += w * (0.5 * ggi + V[q] * pi);
+                    Se[2 * (a * n + b)] += w * pr;
+                    Se[2 * (a * n + b) + 1] += w * pi;
+                }
+        }
+    free(vr); free(vi); free(gr); free(gi);
+}
+
+void or_element_matrices_bloch(const or_state *s, int64_t e, const double *V_elem, const double *kappa,
+                               double *He, double *Se) {
+    loc_fn *L = malloc(sizeof(loc_fn) * max_locals(s));
+    int n = element_locals(s, e, L);
+    elem_mats_bloch(s, e, L, n, V_elem, kappa, He, Se);
+    free(L);
+}
+
+/* Global matrices of the Bloch-enriched basis restricted to rows [r0, r0+nr)
+ * and columns [c0, c0+nc): H[g_a][g_b] += conj(p_a) p_b H_e[a][b] with the
+ * boundary phase p_a = exp(2 pi i kappa.n_a) of the classical FE functions
+ * and p_a = 1 for the enriched ones (periodic PU), the same for S. */
+static void assemble_bloch(const or_state *s, const double *V, const double *kappa, int64_t r0, int64_t nr,
+                           int64_t c0, int64_t nc, double *H, double *S) {
+    memset(H, 0, sizeof(double) * 2 * nr * nc);
+    memset(S, 0, sizeof(double) * 2 * nr * nc);
+    int mx = max_locals(s);
+    loc_fn *L = malloc(sizeof(loc_fn) * mx);
+    double *He = malloc(sizeof(double) * 2 * mx * mx), *Se = malloc(sizeof(double) * 2 * mx * mx);
+    for (int64_t e = 0; e < s->nel; ++e) {
+        int n = element_locals(s, e, L), hasr = 0, hasc = 0;
+        for (int a = 0; a < n; ++a) {
+            if (L[a].g >= r0 && L[a].g < r0 + nr) hasr = 1;
+            if (L[a].g >= c0 && L[a].g < c0 + nc) hasc = 1;
+        }
+        if (!hasr || !hasc) continue;
+        elem_mats_bloch(s, e, L, n, V + s->qp_off[e], kappa, He, Se);
+        for (int a = 0; a < n; ++a) {
+            if (!(L[a].g >= r0 && L[a].g < r0 + nr)) continue;
+            double par = 1.0, pai = 0.0;
+            if (L[a].kind == 0) phase(kappa, L[a].shift, &par, &pai);
+            for (int b = 0; b < n; ++b) {
+                if (!(L[b].g >= c0 && L[b].g < c0 + nc)) continue;
+                double pbr = 1.0, pbi = 0.0;
+                if (L[b].kind == 0) phase(kappa, L[b].shift, &pbr, &pbi);
+                double cr = par * pbr + pai * pbi, ci = par * pbi - pai * pbr; /* conj(pa) pb */
+                const double *h = He + 2 * (a * n + b), *sv = Se + 2 * (a * n + b);
+                int64_t idx = 2 * ((L[a].g - r0) * nc + (L[b].g - c0));
+                H[idx] += cr * h[0] - ci * h[1];
+                H[idx + 1] += cr * h[1] + ci * h[0];
+                S[idx] += cr * sv[0] - ci * sv[1];
+                S[idx + 1] += cr * sv[1] + ci * sv[0];
+            }
+        }
+    }
+    free(L); free(He); free(Se);
+}
+
+void or_assemble_dense_bloch(const or_state *s, const double *V, const double *kappa, double *H, double *S) {
+    assemble_bloch(s, V, kappa, 0, s->ndof, 0, s->ndof, H, S);
+}
+
+void or_assemble_block_bloch(const or_state *s, const double *V, const double *kappa, int64_t v, int64_t w,
+                             double *Hb, double *Sb) {
+    int64_t r0 = s->dof_off[v], nr = s->dof_off[v + 1] - r0;
+    int64_t c0 = s->dof_off[w], nc = s->dof_off[w + 1] - c0;
+    assemble_bloch(s, V, kappa, r0, nr, c0, nc, Hb, Sb);
 }
 
 /* ---------------------------------------------------------------- adjoint */

@@ -83,6 +83,17 @@ void or_basis_at(const or_state *s, int64_t e, const double *xi, double *val, do
 /* enrichment function value, gradient, Hessian at x */
 void or_enrichment(const or_state *s, int atom, int desc, int m, const double *x,
                    double *val, double *grad, double *hess);
+/* Bloch-periodic enrichment (eq. Psi with f(R) = exp(i k.R)), periodic PU:
+ * Psi^k at x (val[2] = Re, Im; grad[6] = Re parts, then Im parts); complex
+ * element matrices (n x n interleaved); dense N x N and one vertex block of
+ * the global H, S, with the boundary phase on the classical FE functions only */
+void or_enrichment_bloch(const or_state *s, int atom, int desc, int m, const double *x, const double *kappa,
+                         double *val, double *grad);
+void or_element_matrices_bloch(const or_state *s, int64_t e, const double *V_elem, const double *kappa,
+                               double *He, double *Se);
+void or_assemble_dense_bloch(const or_state *s, const double *V, const double *kappa, double *H, double *S);
+void or_assemble_block_bloch(const or_state *s, const double *V, const double *kappa, int64_t v, int64_t w,
+                             double *Hb, double *Sb);
 /* building blocks exposed for the pins */
 void or_gauss_legendre(int n, double *x, double *w);
 void or_lagrange(int p, int j, double t, double *val, double *der);

@@ -266,6 +266,16 @@ def with_tabulated_radials(prob, n_samples: int = 48):
     return out
 
 
+def with_bloch_enrichment(prob):
+    """A copy of prob whose enrichment functions are Bloch-periodic (eq. Psi
+    with f(R) = exp(i k.R)); its PU functions are then periodic and its
+    element matrices complex and per k-point."""
+    out = copy.deepcopy(prob)
+    out["enrichment_phase"] = "bloch"
+    out["name"] = prob["name"] + "+bloch"
+    return out
+
+
 def lih_supercell():
     """2x2x2 supercell of the LiH-like cell (a = 15.2, 64 atoms, jittered
     N(0, 0.05) seed 0), 16^3 triquadratic, same rule and enrichments; Gamma."""
