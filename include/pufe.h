@@ -15,7 +15,9 @@
  * quadrature".  The local potential V is an input given at the quadrature
  * points.  The FE and PU functions carry the Bloch phase at the cell boundary
  * and the enrichment is periodic (section "Self-consistent calculations"), so
- * every element matrix is real and one contraction serves all k-points.
+ * every element matrix is real and one contraction serves all k-points.  The
+ * Bloch-periodic enrichment of eq. Psi is the alternative form
+ * (pufe_set_enrichment_phase).
  *
  * Conventions
  *  - Every call returns int: PUFE_OK (0) or a negative PUFE_ERR_* code;
@@ -78,6 +80,10 @@ extern "C" {
 #define PUFE_QUAD_GEOM 0    /* split a cell while it lies within `dist` of a nucleus image */
 #define PUFE_QUAD_ERROR 1   /* the paper's rule: split while |Q_n - Q_ref| > tol for Psi^2 or |grad Psi|^2 */
 
+/* form of the enrichment functions, f(R) in eq. Psi */
+#define PUFE_ENR_PERIODIC 0 /* f(R) = 1; FE and PU functions carry the boundary phase (the default) */
+#define PUFE_ENR_BLOCH 1    /* f(R) = exp(i k.R); PU functions periodic, FE functions carry the phase */
+
 typedef struct pufe_ctx pufe_ctx;
 
 /* One enrichment descriptor: the 2l+1 functions R(r) Y_lm(r_hat), real
@@ -137,7 +143,8 @@ typedef struct {
     int64_t nnz;      /* stored complex entries of one matrix for one k-point */
     int64_t n_qp;     /* quadrature points (0 before pufe_setup) */
     int64_t n_leaves; /* octree leaves (0 before pufe_setup) */
-    int32_t max_nloc; /* largest number of functions on one element */
+    int32_t max_nloc; /* largest number of functions on one element (rows of its contraction: with the
+                         Bloch-periodic enrichment, real and imaginary parts counted apart) */
     int32_t n_colors; /* element colours of the atomic-free scatter */
     int32_t n_atoms;
     int32_t n_fe_slots;
@@ -181,6 +188,31 @@ int pufe_set_problem(pufe_ctx *ctx, const double lattice[9], const int mesh[3], 
  * a <= 0, rc <= 0, n < 0), PUFE_ERR_UNSUPPORTED (more than 64 projector
  * columns reach one element). */
 int pufe_set_projectors(pufe_ctx *ctx, int n, const pufe_projector *proj);
+
+/* Choose the form of the enrichment functions (eq. Psi; host only, after
+ * pufe_set_problem, before pufe_setup).  PUFE_ENR_PERIODIC (the default):
+ * f(R) = 1 with Bloch-periodic FE and PU functions; every element matrix is
+ * real and serves all k-points.  PUFE_ENR_BLOCH: f(R) = exp(i k.R), i.e.
+ *   Psi^k(x) = sum_n exp(2 pi i kappa.n) Psi~(x - tau - n.a)
+ * with tau the atom position as given (moving an atom by a lattice vector
+ * multiplies its functions by a constant phase), periodic PU functions and
+ * Bloch-periodic classical FE functions.  The enriched functions are then
+ * complex and depend on the k-point, so each assembly contracts every element
+ * once per k-point: each enriched function contributes a real row (images
+ * weighted by cos 2 pi kappa.n) and an imaginary row (sin), the real MFMA
+ * contraction gives the Gram matrix of both, and the scatter forms the
+ * complex element matrix conj(phi_a) phi_b from it.  The layout, the
+ * quadrature rule (built from the periodic functions in the error-driven
+ * mode) and the output types are those of the periodic form; the split
+ * precisions apply as well.  An element may hold at most 32 enriched
+ * functions (64 rows with their imaginary parts) of at most 16 groups.  With
+ * this form, pufe_set_projectors, pufe_assemble_backward,
+ * pufe_assemble_noalloc, pufe_element_matrices and the batch give
+ * PUFE_ERR_UNSUPPORTED.  Errors: PUFE_ERR_STATE after pufe_setup or before
+ * pufe_set_problem, PUFE_ERR_INVALID_ARG for an unknown form,
+ * PUFE_ERR_UNSUPPORTED (projectors set, or too many functions on an
+ * element). */
+int pufe_set_enrichment_phase(pufe_ctx *ctx, int form);
 
 /* Build the adaptive rule on the device (section "Adaptive quadrature"),
  * upload the element tables and plan the contraction work.  Synchronous.

@@ -22,13 +22,15 @@ ERRORS = {-1: "PUFE_ERR_INVALID_ARG", -2: "PUFE_ERR_UNSUPPORTED", -3: "PUFE_ERR_
 PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2}
 OUT = {"c128": 0, "c64": 1, "f64": 2}
 QUAD_MODE = {"geom": 0, "error": 1}
+ENR_PHASE = {"periodic": 0, "bloch": 1}
 
 EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_destroy",
            "pufe_set_problem", "pufe_setup", "pufe_query", "pufe_get_layout",
            "pufe_get_quadrature", "pufe_get_leaves", "pufe_assemble", "pufe_element_matrices",
            "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
            "pufe_kernel_times", "pufe_set_positions", "pufe_batch_create", "pufe_batch_assemble",
-           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune", "pufe_assemble_noalloc", "pufe_set_rule", "pufe_set_projectors"]
+           "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune", "pufe_assemble_noalloc", "pufe_set_rule", "pufe_set_projectors",
+           "pufe_set_enrichment_phase"]
 
 
 class PufeError(RuntimeError):
@@ -85,6 +87,7 @@ def _load():
         "pufe_assemble_noalloc": ([vp, vp, dp, C.c_int, C.c_int, C.c_int, vp, vp, vp], C.c_int),
         "pufe_set_rule": ([vp, C.c_int64, i32p, i32p, i64p, vp], C.c_int),
         "pufe_set_projectors": ([vp, C.c_int, C.POINTER(pufe_projector)], C.c_int),
+        "pufe_set_enrichment_phase": ([vp, C.c_int], C.c_int),
         "pufe_element_matrices": ([vp, C.c_int64, vp, C.c_int, vp, vp, i32p, vp], C.c_int),
         "pufe_assemble_backward": ([vp, vp, dp, vp, vp, C.c_int, vp, vp, vp], C.c_int),
         "pufe_bsr_to_dense": ([vp, vp, C.c_int, vp, vp], C.c_int),
@@ -170,6 +173,11 @@ def pufe_set_projectors(ctx, projectors):
     for i, q in enumerate(projectors):
         arr[i] = pufe_projector(int(q["species"]), int(q["l"]), float(q["a"]), float(q["rc"]), float(q["h"]))
     _check(ctx, lib.pufe_set_projectors(ctx, len(projectors), arr))
+
+
+def pufe_set_enrichment_phase(ctx, form):
+    """form: "periodic" (f(R) = 1) or "bloch" (f(R) = exp(i k.R)) of eq. Psi."""
+    _check(ctx, lib.pufe_set_enrichment_phase(ctx, ENR_PHASE[form]))
 
 
 def pufe_setup(ctx, stream=None):
@@ -316,6 +324,8 @@ class Problem:
                          prob["species"], prob["enrichments"], prob["quad"])
         if prob.get("projectors"):
             pufe_set_projectors(self.ctx, prob["projectors"])
+        if prob.get("enrichment_phase", "periodic") != "periodic":
+            pufe_set_enrichment_phase(self.ctx, prob["enrichment_phase"])
         self.sizes = pufe_query(self.ctx)
         self._ready = False
 

@@ -10,9 +10,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpufe.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["capi.cpp", "plan.cpp", "kernels.hip", "backward.hip", "split.hip", "aq_error.hip", "nonlocal.hip"]
+SOURCES = ["capi.cpp", "plan.cpp", "kernels.hip", "backward.hip", "split.hip", "aq_error.hip", "nonlocal.hip",
+           "bloch.hip"]
 HEADERS = ["tables.hpp", "plan.hpp", "kernels.hpp", "basis.hpp", "backward.hpp", "device_common.hpp", "enrich.hpp",
-           "aq_error.hpp", "stage.hpp", "limbs.hpp", "nonlocal.hpp"]
+           "aq_error.hpp", "stage.hpp", "limbs.hpp", "nonlocal.hpp", "bloch.hpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -12,6 +12,7 @@
 #include "../../include/pufe.h"
 #include "aq_error.hpp"
 #include "backward.hpp"
+#include "bloch.hpp"
 #include "kernels.hpp"
 #include "nonlocal.hpp"
 #include "plan.hpp"
@@ -109,6 +110,10 @@ struct pufe_ctx {
     DevBuf<int2> d_dof_el;
     DevBuf<int32_t> d_nl_elems, d_nl_blocks;
     DevBuf<double2> d_nlf;
+    // Bloch-periodic enrichment: image shifts and kinds, the per-k image
+    // weights, the partner table of the enriched entries
+    DevBuf<int32_t> d_img_nk, d_bpart;
+    DevBuf<double> d_wimg;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
@@ -243,6 +248,24 @@ int pufe_set_projectors(pufe_ctx *ctx, int n, const pufe_projector *proj) {
     if (n < 0 || (n > 0 && !proj)) return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer or negative count");
     Problem pr = ctx->prob;
     pr.proj.assign(proj, proj + n);
+    Plan pl;
+    std::string err;
+    int rc = build_plan(pr, pl, err);
+    if (rc != PUFE_OK) return fail(ctx, rc, err);
+    ctx->prob = std::move(pr);
+    ctx->plan = std::move(pl);
+    ++ctx->plan_gen;
+    return PUFE_OK;
+}
+
+int pufe_set_enrichment_phase(pufe_ctx *ctx, int form) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_problem) return fail(ctx, PUFE_ERR_STATE, "pufe_set_problem must come first");
+    if (ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "the enrichment form is set before pufe_setup");
+    if (form != PUFE_ENR_PERIODIC && form != PUFE_ENR_BLOCH)
+        return fail(ctx, PUFE_ERR_INVALID_ARG, "unknown enrichment form");
+    Problem pr = ctx->prob;
+    pr.enr_phase = form;
     Plan pl;
     std::string err;
     int rc = build_plan(pr, pl, err);
@@ -516,6 +539,9 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_groups.upload(pl.groups, st), "upload groups");
     CHECK_HIP(ctx, ctx->d_img.upload(pl.img_cur, st), "upload images");
     CHECK_HIP(ctx, ctx->d_edof.upload(pl.edof, st), "upload enriched functions");
+    CHECK_HIP(ctx, ctx->d_img_nk.upload(pl.img_nk, st), "upload image shifts");
+    CHECK_HIP(ctx, ctx->d_bpart.upload(pl.bpart, st), "upload enriched partners");
+    CHECK_HIP(ctx, ctx->d_wimg.alloc(pl.bloch ? pl.img_nk.size() / 4 : 0), "alloc image weights");
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_wide.upload(ctx->items_wide, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
@@ -664,15 +690,18 @@ int pufe_get_leaves(pufe_ctx *ctx, int32_t *level, int32_t *ijk, int64_t *elem_l
     return PUFE_OK;
 }
 
-// Problems with tabulated radials or serendipity elements run the general
-// variant of the FP64 contraction kernels; the others a variant compiled for
-// analytic radials and Lagrange elements only (fewer live registers).
-static bool general_variant(const Plan &pl) { return !pl.spl.empty() || pl.kp.p == 3; }
+// Problems with tabulated radials, serendipity elements or the Bloch-periodic
+// enrichment run the general variant of the contraction kernels; the others a
+// variant compiled for analytic radials and Lagrange elements only (fewer
+// live registers).
+static bool general_variant(const Plan &pl) { return !pl.spl.empty() || pl.kp.p == 3 || pl.bloch; }
 
 // The element contraction and the K-chunk sum into `partial` (the context's
-// partial-tile buffer, or the fixed workspace of the allocation-free entry).
+// partial-tile buffer, or the fixed workspace of the allocation-free entry);
+// wimg: image weights of the Bloch-periodic enrichment at one k-point (null
+// for the periodic form).
 static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipStream_t st, double *partial,
-                           bool timed = true) {
+                           bool timed = true, const double *wimg = nullptr) {
     const bool saved = ctx->timing;
     ctx->timing = saved && timed;
     struct Restore {
@@ -681,6 +710,8 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
         ~Restore() { c->timing = v; }
     } restore{ctx, saved};
     const Plan &pl = ctx->plan;
+    KParams kp = pl.kp;
+    kp.wimg = wimg;
     if (precision == PUFE_PREC_BF16X3 || precision == PUFE_PREC_BF16X6) {
         const int nl = precision == PUFE_PREC_BF16X3 ? 2 : 3;
         const size_t lds = split_lds_bytes(nl, ctx->max_rows_split, std::max(pl.max_nfun, 1), pl.max_img,
@@ -688,7 +719,7 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
         if (lds > kMaxDynLds) return fail(ctx, PUFE_ERR_UNSUPPORTED, "split stage does not fit in LDS");
         {
             TimedRegion tr(ctx, 0, st);
-            CHECK_HIP(ctx, launch_contract_split(nl, pl.max_l, general_variant(pl), pl.kp, (int)ctx->items_split.size(), ctx->d_items_split.p,
+            CHECK_HIP(ctx, launch_contract_split(nl, pl.max_l, general_variant(pl), kp, (int)ctx->items_split.size(), ctx->d_items_split.p,
                                                  ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                                  ctx->d_leaves.p, d_V, partial, lds, st),
                       "split contraction");
@@ -696,11 +727,11 @@ static int run_contraction(pufe_ctx *ctx, const double *d_V, int precision, hipS
     } else {
         TimedRegion tr(ctx, 0, st);
         // wide items first: they are the longest
-        CHECK_HIP(ctx, launch_contract_wide(pl.max_l, general_variant(pl), pl.kp, (int)ctx->items_wide.size(), ctx->d_items_wide.p,
+        CHECK_HIP(ctx, launch_contract_wide(pl.max_l, general_variant(pl), kp, (int)ctx->items_wide.size(), ctx->d_items_wide.p,
                                             ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                             ctx->d_leaves.p, d_V, partial, ctx->lds_wide, st),
                   "contraction (wide items)");
-        CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, general_variant(pl), pl.kp, (int)ctx->items.size(), ctx->d_items.p,
+        CHECK_HIP(ctx, launch_contract_f64(ctx->contract_q, pl.max_l, general_variant(pl), kp, (int)ctx->items.size(), ctx->d_items.p,
                                            ctx->d_elems.p, ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p,
                                            ctx->d_leaves.p, d_V, partial, ctx->lds, st),
                   "contraction");
@@ -732,10 +763,54 @@ static int check_assemble_args(pufe_ctx *ctx, const double *d_V, const double *k
     return PUFE_OK;
 }
 
+// Assembly with the Bloch-periodic enrichment: for every k-point the image
+// weights, the contraction of the real and imaginary rows, the K-chunk sum
+// and the complex scatter of each colour into that k-point's output.
+static int assemble_bloch(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision,
+                          int out_dtype, void *d_H, void *d_S, hipStream_t st) {
+    const Plan &pl = ctx->plan;
+    const int64_t per = out_dtype == PUFE_OUT_F64_GAMMA ? pl.nnz : 2 * pl.nnz;
+    const size_t esz = out_dtype == PUFE_OUT_C64 ? sizeof(float) : sizeof(double);
+    const int64_t nimg = (int64_t)(pl.img_nk.size() / 4);
+    for (int k0 = 0; k0 < n_k; k0 += kMaxKPerLaunch) {
+        KPoints kps;
+        std::memset(&kps, 0, sizeof kps);
+        kps.nk = std::min(kMaxKPerLaunch, n_k - k0);
+        for (int k = 0; k < kps.nk; ++k)
+            for (int d = 0; d < 3; ++d) kps.kap[k][d] = kpts[3 * (k0 + k) + d];
+        {
+            TimedRegion tr(ctx, 1, st);
+            if (k0 == 0)
+                CHECK_HIP(ctx, launch_prepare_outputs(d_H, d_S, (int64_t)(per * n_k * esz), kps, ctx->d_ztab.p, st),
+                          "zero outputs and phase table");
+            else
+                CHECK_HIP(ctx, launch_phase_table(kps, ctx->d_ztab.p, st), "phase table");
+        }
+        for (int k = 0; k < kps.nk; ++k) {
+            CHECK_HIP(ctx, launch_image_weights(ctx->d_img_nk.p, nimg, kps.kap[k], ctx->d_wimg.p, st),
+                      "image weights");
+            int rc = run_contraction(ctx, d_V, precision, st, ctx->d_partial.p, true, ctx->d_wimg.p);
+            if (rc != PUFE_OK) return rc;
+            TimedRegion tr(ctx, 1, st);
+            char *H = (char *)d_H + (size_t)(k0 + k) * per * esz;
+            char *S = d_S ? (char *)d_S + (size_t)(k0 + k) * per * esz : nullptr;
+            for (size_t col = 0; col + 1 < pl.scat_off.size(); ++col) {
+                const int n = (int)(pl.scat_off[col + 1] - pl.scat_off[col]);
+                CHECK_HIP(ctx, launch_scatter_bloch(pl.kp, ctx->d_elems.p, ctx->d_scat.p + pl.scat_off[col], n,
+                                                    ctx->d_edof.p, ctx->d_bpart.p, ctx->d_partial.p,
+                                                    ctx->d_ztab.p + 27 * k, out_dtype, H, S, st),
+                          "scatter");
+            }
+        }
+    }
+    return PUFE_OK;
+}
+
 // Contraction, K-chunk sum, output zero fill and coloured scatter of one
 // assembly, with the partial tiles and the phase table in the given buffers.
 static int assemble_impl(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision, int out_dtype,
                          void *d_H, void *d_S, hipStream_t st, double *partial, double2 *ztab, bool timed) {
+    if (ctx->plan.bloch) return assemble_bloch(ctx, d_V, kpts, n_k, precision, out_dtype, d_H, d_S, st);
     int rc = run_contraction(ctx, d_V, precision, st, partial, timed);
     if (rc != PUFE_OK) return rc;
     const Plan &pl = ctx->plan;
@@ -806,6 +881,10 @@ int pufe_assemble_noalloc(pufe_ctx *ctx, const double *d_V, const double *kpts, 
     if (ctx->plan.n_pfun > 0)
         return fail(ctx, PUFE_ERR_UNSUPPORTED,
                     "pufe_assemble_noalloc: the nonlocal term keeps its coefficients in context buffers; use pufe_assemble");
+    if (ctx->plan.bloch)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED,
+                    "pufe_assemble_noalloc: the Bloch-periodic enrichment keeps its image weights in context buffers; "
+                    "use pufe_assemble");
     // workspace: the phase table, then the partial tiles (256-byte aligned)
     const size_t ztab_bytes = (sizeof(double2) * kMaxKPerLaunch * 27 + 255) / 256 * 256;
     const size_t need = ztab_bytes + (size_t)ctx->part_slots * 512 * sizeof(double);
@@ -828,6 +907,9 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
     if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
     if (!d_V || !d_He || !d_Se || elem < 0 || elem >= ctx->plan.nel)
         return fail(ctx, PUFE_ERR_INVALID_ARG, "bad element or null pointer");
+    if (ctx->plan.bloch)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED, "element matrices of the Bloch-periodic enrichment are complex and per "
+                                               "k-point; use pufe_assemble");
     hipStream_t st = (hipStream_t)stream;
     CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     int rc = run_contraction(ctx, d_V, precision, st, ctx->d_partial.p);
@@ -945,6 +1027,8 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
     const int nl = precision == PUFE_PREC_BF16X3 ? 2 : (precision == PUFE_PREC_BF16X6 ? 3 : 0);
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(kpt[d])) return fail(ctx, PUFE_ERR_INVALID_ARG, "non-finite k-point");
+    if (ctx->plan.bloch)
+        return fail(ctx, PUFE_ERR_UNSUPPORTED, "the adjoint of the Bloch-periodic enrichment is not supported");
     hipStream_t st = (hipStream_t)stream;
     CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     if (!ctx->have_bw) {
@@ -1284,7 +1368,7 @@ int pufe_batch_create(pufe_batch **out, pufe_ctx *const *ctxs, int n) {
             delete b;
             return PUFE_ERR_STATE;
         }
-        if (ctxs[i]->plan.n_pfun > 0) {   // the batch graph holds no nonlocal launches
+        if (ctxs[i]->plan.n_pfun > 0 || ctxs[i]->plan.bloch) {   // no nonlocal or per-k launches in the batch graph
             delete b;
             return PUFE_ERR_UNSUPPORTED;
         }

@@ -72,10 +72,14 @@ __device__ __forceinline__ void group_eval_point(const GroupDev &G, const double
 
 // Written to o[m * MS + c * CS], c = 0 value, 1..3 gradient.  The sums over
 // images accumulate in place (the first image writes, later ones add), so no
-// per-function accumulators stay live in registers.
+// per-function accumulators stay live in registers.  With TAB, a non-null
+// wimg weights image k by wimg[G.img_off + k] (eq. Psi with
+// f(R) = exp(i k.R): the real and the imaginary part of a Bloch-periodic
+// enrichment function are two groups with cos and sin weights).
 template <int L, int MS, int CS, bool TAB = true>
 __device__ __forceinline__ void group_eval(const GroupDev &G, const double *__restrict__ img,
-                                           const double *__restrict__ spl, const double *x, double *o) {
+                                           const double *__restrict__ spl, const double *__restrict__ wimg,
+                                           const double *x, double *o) {
     constexpr int NM = 2 * L + 1;
     const double rc2 = G.rc * G.rc, inv_rc2 = 1.0 / rc2;
     const double *c0 = img + 3 * G.img_off;
@@ -92,6 +96,11 @@ __device__ __forceinline__ void group_eval(const GroupDev &G, const double *__re
             const double ex = exp(-G.a * s), c = 1.0 - s * inv_rc2, c2 = c * c;
             g0 = ex * c2 * c;
             g1 = -ex * c2 * (G.a * c + 3.0 * inv_rc2);
+        }
+        if (TAB && wimg) {
+            const double wk = wimg[G.img_off + k];
+            g0 *= wk;
+            g1 *= wk;
         }
         double S[7], dS[21];
         solid_harmonics(L, rx, ry, rz, S, dS);

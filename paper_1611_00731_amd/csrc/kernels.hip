@@ -291,6 +291,8 @@ __device__ __forceinline__ void contract_f64_item(
     const int nrow = 16 * (diag ? it.nI : it.nI + it.nJ);
     const int img0 = ngrp > 0 ? gGroups[el.grp_off].img_off : 0;
     const int nimg = ngrp > 0 ? gGroups[el.grp_off + ngrp - 1].img_off + gGroups[el.grp_off + ngrp - 1].nimg - img0 : 0;
+    // image weights of a Bloch-periodic enrichment, indexed like sImg
+    const double *wimg = (GEN && kp.wimg) ? kp.wimg + img0 : nullptr;
     const uint32_t n3 = (uint32_t)kp.n3, n = (uint32_t)kp.n;
     double *sB = smem;                                        // [nrow][RS]
     double *sV = sB + (size_t)nrow * RS;                      // [2][Q], alternate stages
@@ -453,7 +455,7 @@ __device__ __forceinline__ void contract_f64_item(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q, FS, GEN>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * FS + q);
+            group_eval_upto<LMAX, Q, FS, GEN>(G, sImg, kp.spl, wimg, x, sPsi + (size_t)G.fbase * FS + q);
         }
     };
     __syncthreads();

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kNlThreads) void nl_f_kernel(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lb + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * 4 * Q + q);
+            group_eval_upto<LMAX, Q>(G, sImg, kp.spl, nullptr, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
         for (int idx = tid; idx < npg * Q; idx += NT) {
             const int g = idx / Q, q = idx - g * Q;

@@ -111,6 +111,13 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
         if (pj.l < 0 || pj.l > 3) { err = "projector l must be in 0..3"; return PUFE_ERR_INVALID_ARG; }
         if (!(pj.a > 0) || !(pj.rc > 0) || !std::isfinite(pj.h)) { err = "projector needs a > 0, rc > 0, finite h"; return PUFE_ERR_INVALID_ARG; }
     }
+    if (pr.enr_phase != PUFE_ENR_PERIODIC && pr.enr_phase != PUFE_ENR_BLOCH) {
+        err = "unknown enrichment phase form"; return PUFE_ERR_INVALID_ARG;
+    }
+    if (pr.enr_phase == PUFE_ENR_BLOCH && !pr.proj.empty()) {
+        err = "the separable nonlocal term is not supported with Bloch-periodic enrichment";
+        return PUFE_ERR_UNSUPPORTED;
+    }
     const pufe_quad &q = pr.quad;
     if (q.n_gauss < 1 || q.n_gauss > kMaxGauss) { err = "n_gauss must be in 1..12"; return PUFE_ERR_INVALID_ARG; }
     if (q.max_level < 0 || q.max_level > kMaxLevel) { err = "max_level must be in 0..8"; return PUFE_ERR_INVALID_ARG; }
@@ -321,7 +328,10 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     pl.max_ncol = pl.max_npg = 0;
     pl.groups.clear();
     pl.img.clear();
+    pl.img_nk.clear();
     pl.edof.clear();
+    pl.bpart.clear();
+    pl.bloch = pr.enr_phase == PUFE_ENR_BLOCH;
     pl.max_nloc = pl.max_nfun = pl.max_ngrp = 0;
     pl.max_l = 0;
     pl.max_img = 0;
@@ -404,29 +414,59 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
                         pl.img.push_back(C[0]);
                         pl.img.push_back(C[1]);
                         pl.img.push_back(C[2]);
+                        const int32_t nk[4] = {m1, m2, m3, 0};
+                        pl.img_nk.insert(pl.img_nk.end(), nk, nk + 4);
                         ++nimg;
                     }
             g.nimg = nimg;
             pl.groups.push_back(g);
             nfun += 2 * en.l + 1;
         }
+        const int nfun_re = nfun;   // functions of the (real-part) groups
+        if (pl.bloch) {
+            // imaginary parts: a copy of every group, its images weighted by
+            // sin(2 pi kappa.n) instead of cos, functions nfun .. 2 nfun - 1
+            for (int g = 0; g < el.ngrp; ++g) {
+                GroupDev c = pl.groups[el.grp_off + g];
+                const int src = c.img_off;
+                c.img_off = (int32_t)(pl.img.size() / 3);
+                c.fbase += nfun_re;
+                for (int k = 0; k < c.nimg; ++k) {
+                    for (int t = 0; t < 3; ++t) pl.img.push_back(pl.img[3 * (src + k) + t]);
+                    const int32_t nk[4] = {pl.img_nk[4 * (src + k)], pl.img_nk[4 * (src + k) + 1],
+                                           pl.img_nk[4 * (src + k) + 2], 1};
+                    pl.img_nk.insert(pl.img_nk.end(), nk, nk + 4);
+                }
+                pl.groups.push_back(c);
+            }
+            el.ngrp *= 2;
+            nfun *= 2;
+        }
         el.nfun = nfun;
         if (el.ngrp > 0) pl.max_img = std::max(pl.max_img, (int)(pl.img.size() / 3) - pl.groups[el.grp_off].img_off);
-        // enriched local functions: corner by corner, vertex order
+        // enriched local functions: corner by corner, vertex order (with the
+        // Bloch-periodic enrichment, a corner's real parts, then its
+        // imaginary parts in the same order)
         el.edof_off = (int32_t)pl.edof.size();
         int nenr = 0;
-        for (int c = 0; c < 8; ++c)
-            for (int64_t t = pl.vf_off[cv[c]]; t < pl.vf_off[cv[c] + 1]; ++t) {
-                int f = gidx[{pl.vf[3 * t], pl.vf[3 * t + 1]}] + (pl.vf[3 * t + 2] + pr.enr[pl.vf[3 * t + 1]].l);
-                int slot = pl.nfs + (int)(t - pl.vf_off[cv[c]]);
-                pl.edof.push_back(edof_pack(c, f, slot));
-                ++nenr;
-            }
+        for (int c = 0; c < 8; ++c) {
+            const int64_t t0 = pl.vf_off[cv[c]], t1 = pl.vf_off[cv[c] + 1];
+            const int parts = pl.bloch ? 2 : 1;
+            for (int part = 0; part < parts; ++part)
+                for (int64_t t = t0; t < t1; ++t) {
+                    int f = gidx[{pl.vf[3 * t], pl.vf[3 * t + 1]}] + (pl.vf[3 * t + 2] + pr.enr[pl.vf[3 * t + 1]].l);
+                    int slot = pl.nfs + (int)(t - t0);
+                    pl.edof.push_back(edof_pack(c, f + part * nfun_re, slot));
+                    if (pl.bloch) pl.bpart.push_back(part == 0 ? nenr + (int32_t)(t1 - t0) : -1);
+                    ++nenr;
+                }
+        }
         el.nfe = pl.nfe;
         el.nloc = pl.nfe + nenr;
         if (el.nloc > kMaxNloc || nfun > kMaxFun || el.ngrp > kMaxGroups) {
             err = "element " + std::to_string(e) + " holds more functions than the kernels support (nloc " +
-                  std::to_string(el.nloc) + ", functions " + std::to_string(nfun) + ")";
+                  std::to_string(el.nloc) + ", functions " + std::to_string(nfun) +
+                  (pl.bloch ? ", counting real and imaginary parts of the Bloch-periodic enrichment)" : ")");
             return PUFE_ERR_UNSUPPORTED;
         }
         // projector-image groups of the element

@@ -20,6 +20,7 @@ struct Problem {
     std::vector<std::vector<double>> radial;     // samples of tabulated radials, per descriptor
     pufe_quad quad;
     std::vector<pufe_projector> proj;   // separable nonlocal term (may be empty)
+    int enr_phase = PUFE_ENR_PERIODIC;  // f(R) of eq. Psi
 };
 
 struct Plan {
@@ -41,6 +42,13 @@ struct Plan {
     std::vector<double> img;        // image centres at the planned positions, 3 per image
     std::vector<double> img_cur;    // image centres at the current positions
     std::vector<int32_t> edof;      // packed enriched local functions
+    // Bloch-periodic enrichment: every (atom, descriptor) group of an element
+    // is followed by a copy that evaluates the imaginary part (image weights
+    // sin instead of cos), and every enriched local function by its
+    // imaginary-part partner in the same PU corner
+    bool bloch = false;
+    std::vector<int32_t> img_nk;    // per image entry: lattice shift n (3), then 0 (cos weight) or 1 (sin)
+    std::vector<int32_t> bpart;     // per enriched entry: its partner's entry index (-1: an imaginary part)
     std::vector<int32_t> color_elems;
     std::vector<int32_t> color_off; // n_colors + 1
     std::vector<int2> scat;         // (element, upper tile pair), colour by colour

@@ -72,6 +72,8 @@ __device__ __forceinline__ void contract_split_item(
     const int nrow = 16 * (diag ? it.nI : it.nI + it.nJ);
     const int img0 = ngrp > 0 ? gGroups[el.grp_off].img_off : 0;
     const int nimg = ngrp > 0 ? gGroups[el.grp_off + ngrp - 1].img_off + gGroups[el.grp_off + ngrp - 1].nimg - img0 : 0;
+    // image weights of a Bloch-periodic enrichment, indexed like sImg
+    const double *wimg = (GEN && kp.wimg) ? kp.wimg + img0 : nullptr;
     const uint32_t n3 = (uint32_t)kp.n3, n = (uint32_t)kp.n;
     unsigned char *sLimb = smem_raw;                                          // [NL][nrow][RSB]
     double *sV = (double *)(smem_raw + (size_t)NL * nrow * RSB);              // [Q]
@@ -174,7 +176,7 @@ __device__ __forceinline__ void contract_split_item(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q, 4 * Q, GEN>(G, sImg, kp.spl, x, sPsi + (size_t)G.fbase * 4 * Q + q);
+            group_eval_upto<LMAX, Q, 4 * Q, GEN>(G, sImg, kp.spl, wimg, x, sPsi + (size_t)G.fbase * 4 * Q + q);
         }
     };
     if (nli > 0) phase1(0);

@@ -20,15 +20,17 @@ namespace pufe {
 enum { G_XI = 0, G_X = 3, G_SW2 = 6, G_SW = 7, G_L = 8, G_D = 17, G_M = 26, G_M1 = 34 };
 
 // Enrichment functions of one group at one point, for groups up to LMAX;
-// function m of the group at o[m * FS], component c at o[m * FS + c * Q].
+// function m of the group at o[m * FS], component c at o[m * FS + c * Q];
+// wimg: image weights (group_eval), null for the periodic enrichment.
 template <int LMAX, int Q, int FS = 4 * Q, bool TAB = true>
 __device__ __forceinline__ void group_eval_upto(const GroupDev &G, const double *__restrict__ img,
-                                                const double *__restrict__ spl, const double *x, double *o) {
+                                                const double *__restrict__ spl, const double *__restrict__ wimg,
+                                                const double *x, double *o) {
     switch (G.l) {
-        case 0: group_eval<0, FS, Q, TAB>(G, img, spl, x, o); break;
-        case 1: if (LMAX >= 1) group_eval<1, FS, Q, TAB>(G, img, spl, x, o); break;
-        case 2: if (LMAX >= 2) group_eval<2, FS, Q, TAB>(G, img, spl, x, o); break;
-        default: if (LMAX >= 3) group_eval<3, FS, Q, TAB>(G, img, spl, x, o); break;
+        case 0: group_eval<0, FS, Q, TAB>(G, img, spl, wimg, x, o); break;
+        case 1: if (LMAX >= 1) group_eval<1, FS, Q, TAB>(G, img, spl, wimg, x, o); break;
+        case 2: if (LMAX >= 2) group_eval<2, FS, Q, TAB>(G, img, spl, wimg, x, o); break;
+        default: if (LMAX >= 3) group_eval<3, FS, Q, TAB>(G, img, spl, wimg, x, o); break;
     }
 }
 
@@ -39,6 +41,7 @@ struct KLocal {
     int p, n, n3;
     bool jdiag;   // Jt diagonal (orthogonal cell axes)
     const double *spl;   // tabulated radial coefficients
+    const double *wimg;  // image weights of a Bloch-periodic enrichment (null: periodic)
 };
 
 __device__ __forceinline__ KLocal load_klocal(const KParams &kp) {
@@ -56,6 +59,7 @@ __device__ __forceinline__ KLocal load_klocal(const KParams &kp) {
     k.n = kp.n;
     k.n3 = kp.n3;
     k.spl = kp.spl;
+    k.wimg = kp.wimg;
     return k;
 }
 

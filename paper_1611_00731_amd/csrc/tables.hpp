@@ -94,6 +94,9 @@ struct KParams {
     int32_t n, n3, p, nfe, nfs, nref;
     int32_t mesh[3];
     const double *spl;   // coefficients of the tabulated radials (device)
+    // Bloch-periodic enrichment: the weight of every image entry at the
+    // k-point of the launch, cos or sin(2 pi kappa.n) (null: periodic, all 1)
+    const double *wimg;
 };
 
 // Tables and buffers of one problem, for launches that cover several problems

@@ -246,3 +246,38 @@ def test_tabulated_radial_validation_and_layout():
         setp(ctx, tab)   # still accepted after the refusals
     finally:
         P.pufe_destroy(ctx)
+
+
+def test_enrichment_phase_validation_and_layout():
+    """The Bloch-periodic enrichment (eq. Psi with f(R) = exp(i k.R)) keeps
+    the DOFs and the block layout of the periodic form; the form is set after
+    the problem and before set-up, refuses projectors, and refuses elements
+    whose real and imaginary rows exceed the kernels' function limit."""
+    base = W.small("lih", mesh=(2, 3, 2), fe_order=2)
+
+    def setp(ctx, prob):
+        P.pufe_set_problem(ctx, prob["lattice"], prob["mesh"], prob["fe_order"], prob["atoms"], prob["species"],
+                           prob["enrichments"], prob["quad"])
+
+    ctx = P.pufe_create(0)
+    try:
+        _expect(-5, lambda: P.pufe_set_enrichment_phase(ctx, "bloch"))
+        setp(ctx, base)
+        lay0 = P.pufe_get_layout(ctx)
+        P.pufe_set_enrichment_phase(ctx, "bloch")
+        lay1 = P.pufe_get_layout(ctx)
+        for k in lay0:
+            assert np.array_equal(np.asarray(lay0[k]), np.asarray(lay1[k])), k
+        assert P.pufe_query(ctx)["n_dof"] == oracle.Oracle(base).n_dof
+        _expect(-1, lambda: P._check(ctx, P.lib.pufe_set_enrichment_phase(ctx, 2)))
+        _expect(-2, lambda: P.pufe_set_projectors(ctx, W.with_projectors(base)["projectors"]))
+        P.pufe_set_enrichment_phase(ctx, "periodic")
+        P.pufe_set_projectors(ctx, W.with_projectors(base)["projectors"])
+        _expect(-2, lambda: P.pufe_set_enrichment_phase(ctx, "bloch"))
+        P.pufe_set_projectors(ctx, [])
+        P.pufe_set_enrichment_phase(ctx, "bloch")
+        ceal = W.small("ceal", mesh=(2, 2, 2), fe_order=1, rc=3.0, re=2.4)
+        setp(ctx, ceal)
+        _expect(-2, lambda: P.pufe_set_enrichment_phase(ctx, "bloch"))
+    finally:
+        P.pufe_destroy(ctx)
