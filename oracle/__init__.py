@@ -82,6 +82,12 @@ def lib():
         L.or_assemble_dense_bloch.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p]
         L.or_assemble_block_bloch.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int64, C.c_int64,
                                               _f64p, _f64p]
+        L.or_n_fe_dof.argtypes = [C.c_void_p]
+        L.or_n_fe_dof.restype = C.c_int64
+        L.or_fe_load.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.or_fe_eval.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.or_fe_stiffness.argtypes = [C.c_void_p, _f64p]
+        L.or_lda.argtypes = [C.c_int64, _f64p, _f64p, C.c_void_p]
         L.or_gauss_legendre.argtypes = [C.c_int, _f64p, _f64p]
         L.or_lagrange.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]
@@ -300,6 +306,51 @@ class Oracle:
             return self.assemble_dense_bloch(V, kappa)
         return self.assemble_dense(V, kappa)
 
+    # ---- self-consistent field pieces (section "Self-consistent calculations")
+    @property
+    def n_fe_dof(self):
+        return int(lib().or_n_fe_dof(self.h))
+
+    def fe_load(self, f):
+        """b_i = sum_q w_q phi_i(x_q) f_q over the classical FE functions."""
+        b = np.zeros(self.n_fe_dof)
+        lib().or_fe_load(self.h, np.ascontiguousarray(f, np.float64), b)
+        return b
+
+    def fe_eval(self, u):
+        """sum_i u_i phi_i at every point of the rule."""
+        out = np.zeros(self.n_qp)
+        lib().or_fe_eval(self.h, np.ascontiguousarray(u, np.float64), out)
+        return out
+
+    def fe_stiffness(self):
+        N = self.n_fe_dof
+        K = np.zeros((N, N))
+        lib().or_fe_stiffness(self.h, K)
+        return K
+
+    def hartree(self, n_qp):
+        """V_H at the rule's points for the electron density n (eq. poisson
+        for the electrons' part of the charge, whose ionic part the local
+        ionic potential carries): find v in the classical FE space with
+        int grad phi_i . grad V_H = 4 pi int phi_i (n - nbar), nbar = int n /
+        volume (the neutralising background), and int V_H = 0; a dense solve
+        of the bordered system [K m; m^T 0], m_i = int phi_i.  Returns
+        (V_H at the points, v)."""
+        _, w, _ = self.quadrature()
+        b = self.fe_load(n_qp)
+        m = self.fe_load(np.ones(self.n_qp))
+        nbar = float(np.dot(w, n_qp)) / float(np.sum(w))
+        K = self.fe_stiffness()
+        N = K.shape[0]
+        A = np.zeros((N + 1, N + 1))
+        A[:N, :N] = K
+        A[:N, N] = m
+        A[N, :N] = m
+        rhs = np.concatenate([4.0 * np.pi * (b - nbar * m), [0.0]])
+        v = np.linalg.solve(A, rhs)[:N]
+        return self.fe_eval(v), v
+
     def _projectors(self, projectors):
         pr = list(projectors if projectors is not None else self.prob.get("projectors", []))
         sp = np.array([q["species"] for q in pr] + [0], np.int32)
@@ -364,3 +415,52 @@ def potential_np(xyz, prob):
     import torch
     from workloads.potential import potential_at
     return potential_at(torch.from_numpy(np.ascontiguousarray(xyz)), prob).numpy()
+
+
+def lda(rho):
+    """LDA exchange-correlation potential and energy per electron at the
+    electron densities rho (or_lda)."""
+    rho = np.ascontiguousarray(rho, np.float64)
+    v = np.zeros_like(rho)
+    e = np.zeros_like(rho)
+    lib().or_lda(rho.size, rho, v, e.ctypes.data)
+    return v, e
+
+
+def scf(prob, n_iter, alpha=0.3, n_extra=2):
+    """Fixed-point iteration of fig. scf on the oracle (periodic enrichment):
+    from V_in = V_ion (the local ionic potential at the rule's points), per
+    iteration: H, S at every k-point of prob (eq. disceig3d), the lowest
+    n_el / 2 states of each doubly occupied with weight 2 / n_k, the electron
+    density n at the points from the adjoint's dL/dV with P = sum f c c^H
+    (eq. rhoe), V_out = V_ion + V_H[n] + V_xc[n] (eqs. veff, poisson), and the
+    linear mix V_in += alpha (V_out - V_in).  Returns V_in after n_iter
+    iterations and per iteration the lowest n_el/2 + n_extra eigenvalues of
+    every k-point and the residual (int (V_out - V_in)^2)^(1/2)."""
+    import scipy.linalg as sl
+    o = Oracle(prob)
+    xyz, w, _ = o.quadrature()
+    V_ion = potential_np(xyz, prob)
+    n_el = sum(prob["species_info"][s]["Z"] for s in prob["species"])
+    n_occ = int(round(n_el / 2))
+    assert abs(2 * n_occ - n_el) < 1e-12, "an even number of electrons is assumed"
+    kpts = [tuple(k) for k in prob["kpts"]]
+    V = V_ion.copy()
+    hist = []
+    for _ in range(n_iter):
+        dens = np.zeros(o.n_qp)
+        evs = []
+        for kap in kpts:
+            H, S = o.assemble_dense(V, kap)
+            eps, Cv = sl.eigh(H, S)
+            evs.append(eps[:n_occ + n_extra])
+            Co = Cv[:, :n_occ]
+            Pk = (2.0 / len(kpts)) * (Co @ Co.conj().T)
+            dV, _ = o.backward_dense(V, kap, Pk)
+            dens += dV / w
+        vh, _ = o.hartree(dens)
+        vxc, _ = lda(dens)
+        Vout = V_ion + vh + vxc
+        hist.append((np.array(evs), float(np.sqrt(np.dot(w, (Vout - V) ** 2)))))
+        V = V + alpha * (Vout - V)
+    return V, hist

@@ -473,6 +473,7 @@ static double min_image_distance(const or_state *s, const double *x, const doubl
 /* Local functions of one element. */
 typedef struct {
     int64_t g;      /* global DOF */
+    int64_t fe;     /* FE node: index v * nfs + slot in the classical FE space */
     int shift[3];   /* lattice shift of the node's vertex */
     int kind;       /* 0 FE node, 1 enriched */
     int node[3];    /* FE: node index per dimension (0..p; serendipity: 0..3 for -1, -1/3, 1/3, 1) */
@@ -514,6 +515,7 @@ static int element_locals(const or_state *s, int64_t e, loc_fn *L) {
                     }
                     f.kind = 0;
                     f.g = s->dof_off[vertex_id(s, j)] + slot;
+                    f.fe = vertex_id(s, j) * s->nfs + slot;
                     L[n++] = f;
                 }
     } else { /* 32-node serendipity topology: corners, then 2 nodes per edge */
@@ -526,6 +528,7 @@ static int element_locals(const or_state *s, int64_t e, loc_fn *L) {
                 if (j[d] >= s->mesh[d]) { j[d] -= s->mesh[d]; f.shift[d] = 1; }
             }
             f.g = s->dof_off[vertex_id(s, j)];
+            f.fe = vertex_id(s, j) * s->nfs;
             for (int d = 0; d < 3; ++d) f.node[d] = 3 * ((c >> d) & 1);
             L[n++] = f;
         }
@@ -543,6 +546,7 @@ static int element_locals(const or_state *s, int64_t e, loc_fn *L) {
                     memset(&f, 0, sizeof f);
                     memcpy(f.shift, sh, sizeof sh);
                     f.g = s->dof_off[vertex_id(s, j)] + 1 + 2 * d + t;
+                    f.fe = vertex_id(s, j) * s->nfs + 1 + 2 * d + t;
                     for (int k = 0; k < 3; ++k) f.node[k] = 3 * ((c >> k) & 1);
                     f.node[d] = 1 + t;   /* the edge nodes at -1/3 and +1/3 */
                     L[n++] = f;
@@ -645,25 +649,33 @@ static void serendipity(const int *node, const double *xi, double *val, double *
 
 /* Values and gradients of the element's PUFE basis (eq. pufebasis): classical
  * FE functions and PU functions times enrichment functions. */
+/* Value and Cartesian gradient of one classical FE function (serendipity,
+ * or the tensor product of 1D Lagrange factors). */
+static void fe_function(const or_state *s, const loc_fn *f, const double *xi, double *val, double *grad) {
+    if (s->p == 3) {
+        double dxi[3];
+        serendipity(f->node, xi, val, dxi);
+        ref_grad(s, dxi, grad);
+        return;
+    }
+    double v = 1.0, dxi[3] = {1.0, 1.0, 1.0};
+    for (int d = 0; d < 3; ++d) {
+        double lv, ld;
+        or_lagrange(s->p, f->node[d], xi[d], &lv, &ld);
+        for (int k = 0; k < 3; ++k) dxi[k] *= (k == d) ? ld : lv;
+        v *= lv;
+    }
+    *val = v;
+    ref_grad(s, dxi, grad);
+}
+
 static void basis_eval(const or_state *s, int64_t e, const loc_fn *L, int nloc, const double *xi,
                        double *val, double *grad) {
     double x[3];
     ref2phys(s, e, xi, x);
     for (int a = 0; a < nloc; ++a) {
-        if (L[a].kind == 0 && s->p == 3) {
-            double dxi[3];
-            serendipity(L[a].node, xi, &val[a], dxi);
-            ref_grad(s, dxi, grad + 3 * a);
-        } else if (L[a].kind == 0) {
-            double v = 1.0, dxi[3] = {1.0, 1.0, 1.0};
-            for (int d = 0; d < 3; ++d) {
-                double lv, ld;
-                or_lagrange(s->p, L[a].node[d], xi[d], &lv, &ld);
-                for (int k = 0; k < 3; ++k) dxi[k] *= (k == d) ? ld : lv;
-                v *= lv;
-            }
-            val[a] = v;
-            ref_grad(s, dxi, grad + 3 * a);
+        if (L[a].kind == 0) {
+            fe_function(s, &L[a], xi, &val[a], grad + 3 * a);
         } else {
             double M = 1.0, dxi[3] = {1.0, 1.0, 1.0};
             for (int d = 0; d < 3; ++d) {
@@ -1565,4 +1577,131 @@ void or_nonlocal_dense(const or_state *s, const double *kappa, int n_proj, const
     }
     free(F);
     free(h);
+}
+
+
+/* ------------------------------------------- self-consistent field pieces */
+
+/* Section "Self-consistent calculations" and eqs. poisson, veff: the
+ * Coulomb potential is the solution of a Poisson problem, here posed on the
+ * classical FE functions (periodic, Gamma: no boundary phase); its vectors are
+ * indexed v * nfs + slot. */
+int64_t or_n_fe_dof(const or_state *s) { return s->nv * s->nfs; }
+
+/* b_i = sum_q w_q phi_i(x_q) f(x_q) over the classical FE functions, f given at
+ * the rule's points in canonical order. */
+void or_fe_load(const or_state *s, const double *f, double *b) {
+    memset(b, 0, sizeof(double) * s->nv * s->nfs);
+    int mx = max_locals(s);
+    loc_fn *L = malloc(sizeof(loc_fn) * mx);
+    int64_t nq3 = (int64_t)s->q_n * s->q_n * s->q_n;
+    for (int64_t e = 0; e < s->nel; ++e) {
+        int n = element_locals(s, e, L);
+        int64_t q = s->qp_off[e];
+        for (int64_t lf = s->leaf_off[e]; lf < s->leaf_off[e + 1]; ++lf)
+            for (int64_t j = 0; j < nq3; ++j, ++q) {
+                double xi[3], w;
+                leaf_point(s, s->leaf_level[lf], s->leaf_ijk + 3 * lf, j, xi, &w);
+                for (int a = 0; a < n; ++a) {
+                    if (L[a].kind != 0) continue;
+                    double v, g[3];
+                    fe_function(s, &L[a], xi, &v, g);
+                    b[L[a].fe] += w * v * f[q];
+                }
+            }
+    }
+    free(L);
+}
+
+/* u_h(x_q) = sum_i u_i phi_i(x_q) at every point of the rule. */
+void or_fe_eval(const or_state *s, const double *u, double *out) {
+    int mx = max_locals(s);
+    loc_fn *L = malloc(sizeof(loc_fn) * mx);
+    int64_t nq3 = (int64_t)s->q_n * s->q_n * s->q_n;
+    for (int64_t e = 0; e < s->nel; ++e) {
+        int n = element_locals(s, e, L);
+        int64_t q = s->qp_off[e];
+        for (int64_t lf = s->leaf_off[e]; lf < s->leaf_off[e + 1]; ++lf)
+            for (int64_t j = 0; j < nq3; ++j, ++q) {
+                double xi[3], w, acc = 0.0;
+                leaf_point(s, s->leaf_level[lf], s->leaf_ijk + 3 * lf, j, xi, &w);
+                for (int a = 0; a < n; ++a) {
+                    if (L[a].kind != 0) continue;
+                    double v, g[3];
+                    fe_function(s, &L[a], xi, &v, g);
+                    acc += u[L[a].fe] * v;
+                }
+                out[q] = acc;
+            }
+    }
+    free(L);
+}
+
+/* K_ij = sum_q w_q grad phi_i . grad phi_j over the classical FE functions
+ * (dense, row-major, n_fe_dof x n_fe_dof). */
+void or_fe_stiffness(const or_state *s, double *K) {
+    int64_t N = s->nv * s->nfs;
+    memset(K, 0, sizeof(double) * N * N);
+    int mx = max_locals(s);
+    loc_fn *L = malloc(sizeof(loc_fn) * mx);
+    double *val = malloc(sizeof(double) * mx), *grad = malloc(sizeof(double) * 3 * mx);
+    int64_t nq3 = (int64_t)s->q_n * s->q_n * s->q_n;
+    for (int64_t e = 0; e < s->nel; ++e) {
+        int n = element_locals(s, e, L);
+        for (int64_t lf = s->leaf_off[e]; lf < s->leaf_off[e + 1]; ++lf)
+            for (int64_t j = 0; j < nq3; ++j) {
+                double xi[3], w;
+                leaf_point(s, s->leaf_level[lf], s->leaf_ijk + 3 * lf, j, xi, &w);
+                for (int a = 0; a < n; ++a)
+                    if (L[a].kind == 0) fe_function(s, &L[a], xi, &val[a], grad + 3 * a);
+                for (int a = 0; a < n; ++a) {
+                    if (L[a].kind != 0) continue;
+                    for (int b = 0; b < n; ++b) {
+                        if (L[b].kind != 0) continue;
+                        K[L[a].fe * N + L[b].fe] += w * (grad[3 * a] * grad[3 * b] + grad[3 * a + 1] * grad[3 * b + 1]
+                                                         + grad[3 * a + 2] * grad[3 * b + 2]);
+                    }
+                }
+            }
+    }
+    free(L); free(val); free(grad);
+}
+
+/* Local-density exchange-correlation of the unpolarised electron gas (the
+ * LDA the paper names in section "Kohn-Sham density functional theory"): at
+ * electron density n (bohr^-3), r_s = (3 / (4 pi n))^(1/3),
+ *   exchange (Slater):  e_x = -(3/4) (3 n / pi)^(1/3),  v_x = (4/3) e_x;
+ *   correlation: the Perdew-Zunger (1981) fit of the Ceperley-Alder data,
+ *     r_s >= 1:  e_c = g / (1 + b1 sqrt(r_s) + b2 r_s),
+ *                v_c = e_c (1 + 7/6 b1 sqrt(r_s) + 4/3 b2 r_s) / (1 + b1 sqrt(r_s) + b2 r_s),
+ *     r_s <  1:  e_c = A ln r_s + B + C r_s ln r_s + D r_s,
+ *                v_c = A ln r_s + (B - A/3) + 2/3 C r_s ln r_s + (2 D - C)/3 r_s,
+ *   g = -0.1423, b1 = 1.0529, b2 = 0.3334, A = 0.0311, B = -0.048, C = 0.0020,
+ *   D = -0.0116 (hartree).  exc is the energy per electron, vxc = d(n exc)/dn;
+ * n <= 1e-30 gives zero. */
+void or_lda(int64_t n, const double *rho, double *vxc, double *exc) {
+    for (int64_t i = 0; i < n; ++i) {
+        double d = rho[i];
+        if (!(d > 1e-30)) {
+            vxc[i] = 0.0;
+            if (exc) exc[i] = 0.0;
+            continue;
+        }
+        double rs = cbrt(3.0 / (4.0 * OR_PI * d));
+        double ex = -0.75 * cbrt(3.0 * d / OR_PI), vx = 4.0 / 3.0 * ex;
+        double ec, vc;
+        if (rs >= 1.0) {
+            const double g = -0.1423, b1 = 1.0529, b2 = 0.3334;
+            double sr = sqrt(rs), den = 1.0 + b1 * sr + b2 * rs;
+            ec = g / den;
+            vc = ec * (1.0 + 7.0 / 6.0 * b1 * sr + 4.0 / 3.0 * b2 * rs) / den;
+        } else {
+            const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+            double lr = log(rs);
+            ec = A * lr + B + C * rs * lr + D * rs;
+            vc = A * lr + (B - A / 3.0) + 2.0 / 3.0 * C * rs * lr + (2.0 * D - C) / 3.0 * rs;
+        }
+        vxc[i] = vx + vc;
+        if (exc) exc[i] = ex + ec;
+    }
 }

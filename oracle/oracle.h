@@ -94,6 +94,15 @@ void or_element_matrices_bloch(const or_state *s, int64_t e, const double *V_ele
 void or_assemble_dense_bloch(const or_state *s, const double *V, const double *kappa, double *H, double *S);
 void or_assemble_block_bloch(const or_state *s, const double *V, const double *kappa, int64_t v, int64_t w,
                              double *Hb, double *Sb);
+/* self-consistent field pieces (section "Self-consistent calculations",
+ * eqs. poisson, veff): classical FE space vectors indexed v * nfs + slot,
+ * periodic (Gamma); load vector b_i = sum_q w_q phi_i f_q, evaluation
+ * u_h(x_q), dense stiffness matrix, and the LDA exchange-correlation */
+int64_t or_n_fe_dof(const or_state *s);
+void or_fe_load(const or_state *s, const double *f, double *b);
+void or_fe_eval(const or_state *s, const double *u, double *out);
+void or_fe_stiffness(const or_state *s, double *K);
+void or_lda(int64_t n, const double *rho, double *vxc, double *exc);
 /* building blocks exposed for the pins */
 void or_gauss_legendre(int n, double *x, double *w);
 void or_lagrange(int p, int j, double t, double *val, double *der);
