@@ -315,6 +315,51 @@ int pufe_assemble_backward(pufe_ctx *ctx, const double *d_V, const double kpt[3]
  * pufe_set_problem (PUFE_ERR_INVALID_ARG otherwise).  Synchronous. */
 int pufe_set_positions(pufe_ctx *ctx, const double *pos);
 
+/* ---- Self-consistent field pieces (section "Self-consistent calculations",
+ * eqs. poisson, veff, rhoe).  Vectors of the classical FE space have
+ * n_fe_dof = n_vertex * n_fe_slots entries, index v * n_fe_slots + slot (the
+ * FE part of the canonical DOF order); the functions are periodic (no
+ * boundary phase).  Point arrays follow the rule's canonical order.  The
+ * electron density at the points is w_q-weighted output of
+ * pufe_assemble_backward with P = sum_i f_i c_i c_i^H (d_dLdV / w). */
+
+/* b_i = sum_q w_q phi_i(x_q) f(x_q) over the classical FE functions: d_f[n_qp],
+ * d_b[n_fe_dof] (device).  Per-element sums in a fixed order, then one sum
+ * per DOF over its elements in element order (deterministic).  Errors:
+ * PUFE_ERR_STATE before pufe_setup, PUFE_ERR_INVALID_ARG for null pointers. */
+int pufe_fe_load(pufe_ctx *ctx, const double *d_f, double *d_b, void *stream);
+
+/* d_out[q] = sum_i d_u[i] phi_i(x_q) at every point of the rule.  Errors as
+ * pufe_fe_load. */
+int pufe_fe_eval(pufe_ctx *ctx, const double *d_u, double *d_out, void *stream);
+
+/* Hartree potential of the electron density (eq. poisson for the electrons'
+ * part of the charge; the local ionic potential carries the ionic part):
+ * V_H in the classical FE space with
+ *   int grad phi_i . grad V_H = 4 pi int phi_i (n - nbar),  int V_H = 0,
+ * nbar = int n / int 1 the neutralising background.  d_n[n_qp] is the
+ * electron density at the points (electrons per bohr^3), d_vh[n_qp] receives
+ * V_H at the points and d_v[n_fe_dof] (may be NULL) its FE coefficients.  The
+ * stiffness matrix is taken once per rule from the kinetic term of an
+ * assembly at Gamma with V = 0 (its FE rows and columns, without the separable
+ * term) and kept in the context; conjugate gradients from zero until the
+ * residual falls below tol times the first (at most max_iter iterations; the
+ * iterations and the final relative residual are returned through iters and
+ * resid, either may be NULL).  Synchronous (the iteration reads its scalars
+ * back).  Errors: PUFE_ERR_STATE before pufe_setup, PUFE_ERR_INVALID_ARG for
+ * null pointers, tol <= 0 or max_iter < 1. */
+int pufe_hartree(pufe_ctx *ctx, const double *d_n, double *d_vh, double *d_v, double tol, int max_iter,
+                 int *iters, double *resid, void *stream);
+
+/* LDA exchange-correlation of the unpolarised electron gas at n electron
+ * densities d_rho (bohr^-3): d_vxc = d(n e_xc)/dn and (d_exc may be NULL) the
+ * energy per electron e_xc; Slater exchange and the Perdew-Zunger (1981) fit
+ * of the Ceperley-Alder correlation, zero where the density is <= 1e-30 (the
+ * paper names the LDA, not its parametrisation).  Errors:
+ * PUFE_ERR_INVALID_ARG for n < 0 or null pointers, PUFE_ERR_HIP for a failed
+ * launch. */
+int pufe_lda_xc(int64_t n, const double *d_rho, double *d_vxc, double *d_exc, void *stream);
+
 /* Autotuner: time the contraction of this problem for candidate work-item
  * granularities (number of K-chunk items), tile-block sizes (2..4 tiles of
  * 16 rows per work item side) and stage lengths (16, 24 or 32 quadrature

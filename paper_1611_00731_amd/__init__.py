@@ -30,7 +30,7 @@ EXPORTS = ["pufe_error_string", "pufe_last_error_message", "pufe_create", "pufe_
            "pufe_assemble_backward", "pufe_bsr_to_dense", "pufe_enable_timing",
            "pufe_kernel_times", "pufe_set_positions", "pufe_batch_create", "pufe_batch_assemble",
            "pufe_batch_destroy", "pufe_batch_last_error_message", "pufe_tune", "pufe_assemble_noalloc", "pufe_set_rule", "pufe_set_projectors",
-           "pufe_set_enrichment_phase"]
+           "pufe_set_enrichment_phase", "pufe_fe_load", "pufe_fe_eval", "pufe_hartree", "pufe_lda_xc"]
 
 
 class PufeError(RuntimeError):
@@ -88,6 +88,10 @@ def _load():
         "pufe_set_rule": ([vp, C.c_int64, i32p, i32p, i64p, vp], C.c_int),
         "pufe_set_projectors": ([vp, C.c_int, C.POINTER(pufe_projector)], C.c_int),
         "pufe_set_enrichment_phase": ([vp, C.c_int], C.c_int),
+        "pufe_fe_load": ([vp, vp, vp, vp], C.c_int),
+        "pufe_fe_eval": ([vp, vp, vp, vp], C.c_int),
+        "pufe_hartree": ([vp, vp, vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int), dp, vp], C.c_int),
+        "pufe_lda_xc": ([C.c_int64, vp, vp, vp, vp], C.c_int),
         "pufe_element_matrices": ([vp, C.c_int64, vp, C.c_int, vp, vp, i32p, vp], C.c_int),
         "pufe_assemble_backward": ([vp, vp, dp, vp, vp, C.c_int, vp, vp, vp], C.c_int),
         "pufe_bsr_to_dense": ([vp, vp, C.c_int, vp, vp], C.c_int),
@@ -268,6 +272,29 @@ def pufe_set_positions(ctx, pos):
     _check(ctx, lib.pufe_set_positions(ctx, p.ctypes.data_as(C.POINTER(C.c_double))))
 
 
+def pufe_fe_load(ctx, f, b, stream=None):
+    _check(ctx, lib.pufe_fe_load(ctx, _ptr(f), _ptr(b), _stream(stream)))
+
+
+def pufe_fe_eval(ctx, u, out, stream=None):
+    _check(ctx, lib.pufe_fe_eval(ctx, _ptr(u), _ptr(out), _stream(stream)))
+
+
+def pufe_hartree(ctx, n, vh, v=None, tol=1e-13, max_iter=5000, stream=None):
+    """Returns (CG iterations, final relative residual)."""
+    it = C.c_int(0)
+    res = C.c_double(0.0)
+    _check(ctx, lib.pufe_hartree(ctx, _ptr(n), _ptr(vh), _ptr(v), float(tol), int(max_iter), C.byref(it),
+                                 C.byref(res), _stream(stream)))
+    return it.value, res.value
+
+
+def pufe_lda_xc(rho, vxc, exc=None, stream=None):
+    rc = lib.pufe_lda_xc(rho.numel(), _ptr(rho), _ptr(vxc), _ptr(exc), _stream(stream))
+    if rc != PUFE_OK:
+        raise PufeError(rc, "pufe_lda_xc")
+
+
 def pufe_enable_timing(ctx, on=True):
     _check(ctx, lib.pufe_enable_timing(ctx, 1 if on else 0))
 
@@ -402,6 +429,28 @@ class Problem:
                                None if Q is None else Q.contiguous(), precision, dV, dR)
         return dV, dR
 
+    # self-consistent field pieces: vectors of the classical FE space have
+    # n_vertex * n_fe_slots entries
+    def fe_load(self, f):
+        import torch
+        b = torch.empty(self.sizes["n_vertex"] * self.sizes["n_fe_slots"], dtype=torch.float64, device=f.device)
+        pufe_fe_load(self.ctx, f.contiguous(), b)
+        return b
+
+    def fe_eval(self, u):
+        import torch
+        out = torch.empty(self.sizes["n_qp"], dtype=torch.float64, device=u.device)
+        pufe_fe_eval(self.ctx, u.contiguous(), out)
+        return out
+
+    def hartree(self, n, tol=1e-13, max_iter=5000):
+        """(V_H at the points, its FE coefficients, CG iterations, relative residual)."""
+        import torch
+        vh = torch.empty(self.sizes["n_qp"], dtype=torch.float64, device=n.device)
+        v = torch.empty(self.sizes["n_vertex"] * self.sizes["n_fe_slots"], dtype=torch.float64, device=n.device)
+        it, res = pufe_hartree(self.ctx, n.contiguous(), vh, v, tol, max_iter)
+        return vh, v, it, res
+
     def to_dense(self, bsr, dtype="c128"):
         import torch
         n = self.sizes["n_dof"]
@@ -501,6 +550,19 @@ def _tril_inverse(L, base=256):
     out[h:, h:] = Ci
     out[h:, :h] = -(Ci @ (L[h:, :h] @ Ai))
     return out
+
+
+def eigh(H, S):
+    """All eigenpairs of H c = eps S c (eq. disceig3d) on the device in FP64,
+    by the reduction of eig: eigenvalues ascending, eigenvectors as columns,
+    normalised so that c^H S c = 1."""
+    import torch
+    Lc = torch.linalg.cholesky(0.5 * (S + S.mH))
+    Li = _tril_inverse(Lc)
+    A = Li @ H @ Li.mH
+    A = 0.5 * (A + A.mH)
+    e, Y = torch.linalg.eigh(A)
+    return e, Li.mH @ Y
 
 
 def eig(H, S, m):

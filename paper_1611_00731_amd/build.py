@@ -11,9 +11,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpufe.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["capi.cpp", "plan.cpp", "kernels.hip", "backward.hip", "split.hip", "aq_error.hip", "nonlocal.hip",
-           "bloch.hip"]
+           "bloch.hip", "scf.hip"]
 HEADERS = ["tables.hpp", "plan.hpp", "kernels.hpp", "basis.hpp", "backward.hpp", "device_common.hpp", "enrich.hpp",
-           "aq_error.hpp", "stage.hpp", "limbs.hpp", "nonlocal.hpp", "bloch.hpp"]
+           "aq_error.hpp", "stage.hpp", "limbs.hpp", "nonlocal.hpp", "bloch.hpp", "scf.hpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

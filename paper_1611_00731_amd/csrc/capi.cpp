@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "nonlocal.hpp"
 #include "plan.hpp"
+#include "scf.hpp"
 
 using namespace pufe;
 
@@ -114,6 +115,12 @@ struct pufe_ctx {
     // weights, the partner table of the enriched entries
     DevBuf<int32_t> d_img_nk, d_bpart;
     DevBuf<double> d_wimg;
+    // self-consistent field pieces: per-element load sums, the classical FE
+    // blocks of the stiffness matrix, the FE integrals m_i, CG workspace
+    DevBuf<double> d_fe_be, d_Kfe, d_mfe, d_fe_ones, d_cg, d_dot;
+    DevBuf<int64_t> d_brow_ptr;
+    bool have_poisson = false;
+    double m_sum = 0.0;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
@@ -545,6 +552,11 @@ int pufe_setup(pufe_ctx *ctx, void *stream) {
     CHECK_HIP(ctx, ctx->d_items.upload(ctx->items, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_wide.upload(ctx->items_wide, st), "upload work items");
     CHECK_HIP(ctx, ctx->d_items_split.upload(ctx->items_split, st), "upload work items");
+    // tables of the self-consistent field pieces belong to the previous plan
+    ctx->d_dof_el_off.release();
+    ctx->d_dof_el.release();
+    ctx->d_fe_be.release();
+    ctx->have_poisson = false;
     {
         int rc = upload_nonlocal(ctx, st);
         if (rc != PUFE_OK) return rc;
@@ -809,12 +821,14 @@ static int assemble_bloch(pufe_ctx *ctx, const double *d_V, const double *kpts, 
 // Contraction, K-chunk sum, output zero fill and coloured scatter of one
 // assembly, with the partial tiles and the phase table in the given buffers.
 static int assemble_impl(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision, int out_dtype,
-                         void *d_H, void *d_S, hipStream_t st, double *partial, double2 *ztab, bool timed) {
+                         void *d_H, void *d_S, hipStream_t st, double *partial, double2 *ztab, bool timed,
+                         bool nonlocal = true) {
     if (ctx->plan.bloch) return assemble_bloch(ctx, d_V, kpts, n_k, precision, out_dtype, d_H, d_S, st);
     int rc = run_contraction(ctx, d_V, precision, st, partial, timed);
     if (rc != PUFE_OK) return rc;
     const Plan &pl = ctx->plan;
-    if (pl.n_pfun > 0) {
+    const bool with_nl = nonlocal && pl.n_pfun > 0;
+    if (with_nl) {
         // projector coefficients of every element a projector image reaches
         TimedRegion tn(ctx, timed ? 4 : -1, st);
         CHECK_HIP(ctx, launch_nl_f(pl.max_l, pl.kp, (int)ctx->nl_items.size(), ctx->d_nl_items.p, ctx->d_elems.p,
@@ -848,7 +862,7 @@ static int assemble_impl(pufe_ctx *ctx, const double *d_V, const double *kpts, i
                                           partial, ztab, kps.nk, out_dtype, H, S, pl.nnz, st),
                       "scatter");
         }
-        if (pl.n_pfun > 0) {
+        if (with_nl) {
             // the separable term of these k-points into H
             const int64_t ndof = pl.dof_off[pl.nv];
             CHECK_HIP(ctx, launch_nl_gather(pl.kp, ctx->d_elems.p, ctx->d_pgroups.p, ctx->d_edof.p,
@@ -918,6 +932,173 @@ int pufe_element_matrices(pufe_ctx *ctx, int64_t elem, const double *d_V, int pr
               "element matrices");
     if (nloc) *nloc = ctx->plan.elems[elem].nloc;
     return PUFE_OK;
+}
+
+// ------------------------------------------------ self-consistent field pieces
+
+static bool dev_scalar(pufe_ctx *ctx, const double *d, double *h, hipStream_t st) {
+    return hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
+           hipStreamSynchronize(st) == hipSuccess;
+}
+
+// The (element, local function) pairs of every DOF and the per-element load
+// sums, for the classical FE space's load vector.
+static int ensure_fe_map(pufe_ctx *ctx, hipStream_t st) {
+    const Plan &pl = ctx->plan;
+    if (!ctx->d_dof_el_off.p) CHECK_HIP(ctx, ctx->d_dof_el_off.upload(pl.dof_el_off, st), "upload DOF map");
+    if (!ctx->d_dof_el.p) CHECK_HIP(ctx, ctx->d_dof_el.upload(pl.dof_el, st), "upload DOF map");
+    if (!ctx->d_fe_be.p) CHECK_HIP(ctx, ctx->d_fe_be.alloc((size_t)pl.nel * 32), "alloc load sums");
+    return PUFE_OK;
+}
+
+static int fe_load_impl(pufe_ctx *ctx, const double *d_f, double *d_b, hipStream_t st) {
+    const Plan &pl = ctx->plan;
+    CHECK_HIP(ctx, launch_fe_load(pl.kp, ctx->d_elems.p, pl.nel, ctx->d_leaves.p, d_f, ctx->d_fe_be.p, pl.nv, pl.nfs,
+                                  ctx->d_dof_off.p, ctx->d_dof_el_off.p, ctx->d_dof_el.p, d_b, st),
+              "FE load vector");
+    return PUFE_OK;
+}
+
+int pufe_fe_load(pufe_ctx *ctx, const double *d_f, double *d_b, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    if (!d_f || !d_b) return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    int rc = ensure_fe_map(ctx, st);
+    if (rc != PUFE_OK) return rc;
+    return fe_load_impl(ctx, d_f, d_b, st);
+}
+
+int pufe_fe_eval(pufe_ctx *ctx, const double *d_u, double *d_out, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    if (!d_u || !d_out) return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    CHECK_HIP(ctx, launch_fe_eval(ctx->plan.kp, ctx->d_elems.p, ctx->d_edof.p, ctx->d_leaves.p, ctx->d_leaf_elem.p,
+                                  ctx->n_qp, d_u, d_out, st),
+              "FE evaluation");
+    return PUFE_OK;
+}
+
+// The Poisson operator of the classical FE space: K = 2 H restricted to the
+// FE rows and columns of an assembly at Gamma with V = 0 (the kinetic term
+// 1/2 int grad phi_i . grad phi_j of eq. disceig3d), without the separable
+// term; and m_i = int phi_i.
+static int build_poisson(pufe_ctx *ctx, hipStream_t st) {
+    const Plan &pl = ctx->plan;
+    const int64_t nfe = pl.nv * pl.nfs, nnzb = (int64_t)pl.bcol.size();
+    {
+        DevBuf<double> zeroV, Hfull;
+        CHECK_HIP(ctx, zeroV.alloc((size_t)std::max<int64_t>(ctx->n_qp, 1)), "alloc zero potential");
+        CHECK_HIP(ctx, launch_fill_zero(zeroV.p, ctx->n_qp, false, st), "zero potential");
+        CHECK_HIP(ctx, Hfull.alloc((size_t)pl.nnz), "alloc kinetic matrix");
+        const double gamma[3] = {0.0, 0.0, 0.0};
+        int rc = assemble_impl(ctx, zeroV.p, gamma, 1, PUFE_PREC_FP64, PUFE_OUT_F64_GAMMA, Hfull.p, nullptr, st,
+                               ctx->d_partial.p, ctx->d_ztab.p, false, false);
+        if (rc != PUFE_OK) return rc;
+        CHECK_HIP(ctx, ctx->d_Kfe.alloc((size_t)(nnzb * pl.nfs * pl.nfs)), "alloc FE stiffness");
+        CHECK_HIP(ctx, launch_fe_blocks(nnzb, pl.nfs, ctx->d_bcol.p, ctx->d_bval_off.p, ctx->d_dof_off.p, Hfull.p, 2.0,
+                                        ctx->d_Kfe.p, st),
+                  "FE stiffness blocks");
+        CHECK_HIP(ctx, hipStreamSynchronize(st), "sync");
+    }
+    CHECK_HIP(ctx, ctx->d_brow_ptr.upload(pl.brow_ptr, st), "upload block rows");
+    CHECK_HIP(ctx, ctx->d_mfe.alloc((size_t)nfe), "alloc FE integrals");
+    CHECK_HIP(ctx, ctx->d_fe_ones.alloc((size_t)std::max<int64_t>(nfe, ctx->n_qp)), "alloc ones");
+    {
+        std::vector<double> ones((size_t)std::max<int64_t>(nfe, ctx->n_qp), 1.0);
+        CHECK_HIP(ctx, ctx->d_fe_ones.upload(ones, st), "upload ones");
+    }
+    int rc = fe_load_impl(ctx, ctx->d_fe_ones.p, ctx->d_mfe.p, st);
+    if (rc != PUFE_OK) return rc;
+    CHECK_HIP(ctx, ctx->d_cg.alloc((size_t)(5 * nfe)), "alloc CG workspace");
+    CHECK_HIP(ctx, ctx->d_dot.alloc((size_t)(dot_partial_slots() + 1)), "alloc dot workspace");
+    double *out = ctx->d_dot.p + dot_partial_slots();
+    CHECK_HIP(ctx, launch_dot(nfe, ctx->d_mfe.p, ctx->d_fe_ones.p, ctx->d_dot.p, out, st), "dot");
+    if (!dev_scalar(ctx, out, &ctx->m_sum, st)) return fail(ctx, PUFE_ERR_HIP, "read FE integral sum");
+    ctx->have_poisson = true;
+    return PUFE_OK;
+}
+
+int pufe_hartree(pufe_ctx *ctx, const double *d_n, double *d_vh, double *d_v, double tol, int max_iter,
+                 int *iters, double *resid, void *stream) {
+    if (!ctx) return PUFE_ERR_INVALID_ARG;
+    if (!ctx->have_setup) return fail(ctx, PUFE_ERR_STATE, "pufe_setup must come first");
+    if (!d_n || !d_vh) return fail(ctx, PUFE_ERR_INVALID_ARG, "null pointer");
+    if (!(tol > 0.0) || max_iter < 1) return fail(ctx, PUFE_ERR_INVALID_ARG, "need tol > 0 and max_iter >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    int rc = ensure_fe_map(ctx, st);
+    if (rc != PUFE_OK) return rc;
+    if (!ctx->have_poisson) {
+        rc = build_poisson(ctx, st);
+        if (rc != PUFE_OK) return rc;
+    }
+    const Plan &pl = ctx->plan;
+    const int64_t n = pl.nv * pl.nfs;
+    double *b = ctx->d_cg.p, *r = b + n, *p = r + n, *Ap = p + n, *x = Ap + n;
+    double *part = ctx->d_dot.p, *out = part + dot_partial_slots();
+    auto dot = [&](const double *a, const double *c, double *h) -> int {
+        CHECK_HIP(ctx, launch_dot(n, a, c, part, out, st), "dot");
+        if (!dev_scalar(ctx, out, h, st)) return fail(ctx, PUFE_ERR_HIP, "read dot product");
+        return PUFE_OK;
+    };
+    // right-hand side 4 pi (b - nbar m), nbar = int n / int 1 (the neutralising background)
+    rc = fe_load_impl(ctx, d_n, b, st);
+    if (rc != PUFE_OK) return rc;
+    double bsum = 0.0;
+    if ((rc = dot(b, ctx->d_fe_ones.p, &bsum)) != PUFE_OK) return rc;
+    const double nbar = bsum / ctx->m_sum;
+    CHECK_HIP(ctx, launch_scaled_diff(n, 4.0 * M_PI, b, nbar, ctx->d_mfe.p, r, st), "right-hand side");
+    // conjugate gradients on K x = r from x = 0 (K is singular with the
+    // constants as its kernel; r is orthogonal to them)
+    CHECK_HIP(ctx, launch_fill_zero(x, n, false, st), "zero solution");
+    CHECK_HIP(ctx, hipMemcpyAsync(p, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "copy residual");
+    double rr = 0.0;
+    if ((rc = dot(r, r, &rr)) != PUFE_OK) return rc;
+    const double r0 = std::sqrt(rr);
+    int it = 0;
+    double rel = 0.0;
+    if (r0 > 0.0) {
+        for (; it < max_iter; ++it) {
+            CHECK_HIP(ctx, launch_fe_spmv(pl.nv, pl.nfs, ctx->d_brow_ptr.p, ctx->d_bcol.p, ctx->d_Kfe.p, p, Ap, st),
+                      "FE stiffness product");
+            double pAp = 0.0;
+            if ((rc = dot(p, Ap, &pAp)) != PUFE_OK) return rc;
+            if (!(pAp > 0.0)) break;
+            const double alpha = rr / pAp;
+            CHECK_HIP(ctx, launch_axpby(n, alpha, p, 1.0, x, st), "CG update");
+            CHECK_HIP(ctx, launch_axpby(n, -alpha, Ap, 1.0, r, st), "CG update");
+            double rn = 0.0;
+            if ((rc = dot(r, r, &rn)) != PUFE_OK) return rc;
+            rel = std::sqrt(rn) / r0;
+            if (rel <= tol) {
+                ++it;
+                break;
+            }
+            CHECK_HIP(ctx, launch_axpby(n, 1.0, r, rn / rr, p, st), "CG direction");
+            rr = rn;
+        }
+    }
+    // zero mean: int V_H = sum_i x_i m_i = 0
+    double mx = 0.0;
+    if ((rc = dot(ctx->d_mfe.p, x, &mx)) != PUFE_OK) return rc;
+    CHECK_HIP(ctx, launch_axpby(n, -mx / ctx->m_sum, ctx->d_fe_ones.p, 1.0, x, st), "zero mean");
+    if (d_v) CHECK_HIP(ctx, hipMemcpyAsync(d_v, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "copy solution");
+    CHECK_HIP(ctx, launch_fe_eval(pl.kp, ctx->d_elems.p, ctx->d_edof.p, ctx->d_leaves.p, ctx->d_leaf_elem.p,
+                                  ctx->n_qp, x, d_vh, st),
+              "Hartree potential at the points");
+    if (iters) *iters = it;
+    if (resid) *resid = rel;
+    return PUFE_OK;
+}
+
+int pufe_lda_xc(int64_t n, const double *d_rho, double *d_vxc, double *d_exc, void *stream) {
+    if (n < 0 || (n > 0 && (!d_rho || !d_vxc))) return PUFE_ERR_INVALID_ARG;
+    hipError_t e = launch_lda_xc(n, d_rho, d_vxc, d_exc, (hipStream_t)stream);
+    return e == hipSuccess ? PUFE_OK : PUFE_ERR_HIP;
 }
 
 // Plan the adjoint: one work item per (element, K-chunk of the forward
@@ -1158,6 +1339,7 @@ static int upload_items(pufe_ctx *ctx, hipStream_t st) {
     CHECK_HIP(ctx, ctx->d_reduce.upload(ctx->reduce, st), "upload chunk reduction list");
     CHECK_HIP(ctx, ctx->d_partial.alloc((size_t)ctx->part_slots * 512), "alloc partial tiles");
     ctx->have_bw = false;
+    ctx->have_poisson = false;
     return upload_nonlocal(ctx, st);
 }
 
