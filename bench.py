@@ -454,6 +454,58 @@ def leg_bloch(P, W, potential_at, steps=5, warmup=1):
     return out
 
 
+def leg_scf(P, W, potential_at, n_iter=3):
+    """Fixed-point iterations (fig. scf) on the LiH-like cell at Gamma: the
+    time per iteration and its pieces (assembly, dense eigensolve, density
+    from the adjoint, Hartree solve, LDA) from a separately timed pass."""
+    import time
+
+    import torch
+    from paper_1611_00731_amd.scf import bsr_index, run_scf
+    prob = W.lih_cell()
+    p = P.Problem(prob).setup()
+    xyz, w, _ = p.quadrature()
+    V = potential_at(xyz, prob)
+    del xyz
+    n_el = sum(prob["species_info"][s]["Z"] for s in prob["species"])
+    kpts = prob["kpts"]
+    run_scf(p, V, n_el, kpts, 1)   # warm-up (builds the Poisson operator)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, hist = run_scf(p, V, n_el, kpts, n_iter)
+    torch.cuda.synchronize()
+    ms_iter = (time.perf_counter() - t0) * 1e3 / n_iter
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t) * 1e3
+
+    (H, S), t_asm = timed(lambda: p.assemble(V, [tuple(kpts[0])]))
+    (e, Cv), t_eig = timed(lambda: P.eigh(p.to_dense(H[0]), p.to_dense(S[0])))
+    r, c = bsr_index(p.layout())
+    rows, cols = torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()
+    n_occ = int(round(n_el / 2))
+    Pk = 2.0 * (Cv[:, :n_occ] @ Cv[:, :n_occ].mH)
+    Pb = Pk[rows, cols].contiguous()
+    (dV, _), t_den = timed(lambda: p.backward(V, tuple(kpts[0]), Pb, want_dR=False))
+    dens = dV / w
+    (vh, _, it, res), t_h = timed(lambda: p.hartree(dens))
+    vxc = torch.empty_like(dens)
+    _, t_xc = timed(lambda: P.pufe_lda_xc(dens, vxc))
+    out = {"workload": "LiH-like cell (512 elements, 1.52 M points, %d DOFs), Gamma, %d electrons"
+                       % (p.sizes["n_dof"], int(n_el)),
+           "ms_per_iteration": ms_iter, "residuals": [h[1] for h in hist],
+           "pieces_ms": {"assemble": t_asm, "dense_eigensolve": t_eig, "density_adjoint": t_den,
+                         "hartree": t_h, "lda": t_xc},
+           "hartree_cg_iterations": it, "hartree_rel_residual": res,
+           "electrons_from_density": float(torch.dot(w, dens))}
+    p.close()
+    return out
+
+
 def rel_err(A, B):
     return float((A - B).norm() / B.norm())
 
@@ -653,6 +705,8 @@ def main():
         out["extra"]["nonlocal"] = leg_nonlocal(P, W, potential_at)
         log("Bloch-periodic enrichment leg (LiH-like cell, 4 k-points)")
         out["extra"]["bloch"] = leg_bloch(P, W, potential_at)
+        log("self-consistent field leg (LiH-like cell)")
+        out["extra"]["scf"] = leg_scf(P, W, potential_at)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prob, n_out)

@@ -555,13 +555,23 @@ def _tril_inverse(L, base=256):
 def eigh(H, S):
     """All eigenpairs of H c = eps S c (eq. disceig3d) on the device in FP64,
     by the reduction of eig: eigenvalues ascending, eigenvectors as columns,
-    normalised so that c^H S c = 1."""
+    normalised so that c^H S c = 1.  A reduced matrix with no imaginary part
+    (Gamma) goes to the real symmetric solver: the device's complex Hermitian
+    solver has returned non-finite eigenvectors for such matrices of a few
+    thousand rows.  Non-finite results raise."""
     import torch
     Lc = torch.linalg.cholesky(0.5 * (S + S.mH))
     Li = _tril_inverse(Lc)
     A = Li @ H @ Li.mH
     A = 0.5 * (A + A.mH)
-    e, Y = torch.linalg.eigh(A)
+    if A.is_complex() and int(torch.count_nonzero(A.imag)) == 0:
+        e, Yr = torch.linalg.eigh(A.real.contiguous())
+        Y = Yr.to(A.dtype)
+    else:
+        e, Y = torch.linalg.eigh(A)
+    Yv = torch.view_as_real(Y) if Y.is_complex() else Y
+    if not bool(torch.isfinite(Yv).all()) or not bool(torch.isfinite(e).all()):
+        raise RuntimeError("the dense eigensolver returned non-finite eigenpairs")
     return e, Li.mH @ Y
 
 
