@@ -600,6 +600,9 @@ def main():
                          "solver library does not run under hardware-counter collection)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (scale for the PMC byte counters)")
+    ap.add_argument("--workload", default="ceal", choices=["ceal", "lih"],
+                    help="configuration of the headline line: the CeAl-like cell (the default, the largest "
+                         "single-GPU configuration) or the LiH-like cell (for its own counter profiles)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -619,7 +622,7 @@ def main():
         log("warning: libpufe.so is older than its sources; rebuild before trusting these numbers")
     tune_cache = os.environ.get("PUFE_TUNE_CACHE")
     dev = torch.device("cuda", 0)
-    prob = W.ceal_cell()
+    prob = W.ceal_cell() if args.workload == "ceal" else W.lih_cell()
     log("setup", prob["name"])
     p = P.Problem(prob).setup()
     if not args.no_tune:
@@ -645,7 +648,7 @@ def main():
     alg_flops = float(flops.sum())
     achieved = alg_flops / (contract_ms * 1e-3) / 1e12
     value = sz["n_elem"] * n_out / (ms_step * 1e-3)
-    tag = "contract_f64_ceal_cell"
+    tag = "contract_f64_ceal_cell" if args.workload == "ceal" else "contract_f64_lih_cell"
     traffic, = recorded(tag + "_hbm_traffic.md", "traffic_bytes_per_launch")
     busy, executed = recorded(tag + "_mfma_counters.md", "mfma_busy_frac", "mfma_executed_flops_per_launch")
     fp64 = args.precision == "fp64"
@@ -654,9 +657,11 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if fp64 else args.precision,
         "data": "synthetic",
-        "config": {"workload": "CeAl-like CsCl cell a=5.8 bohr, 12^3 triquadratic hexes, 8^3 Gauss + 3 octree "
-                               "levels within 1 bohr, 4 k-points (time-reversal-reduced 2x2x2 MP), "
-                               "H+S complex128, autotuned",
+        "config": {"workload": ("CeAl-like CsCl cell a=5.8 bohr, 12^3 triquadratic hexes, 8^3 Gauss + 3 octree "
+                                "levels within 1 bohr, 4 k-points (time-reversal-reduced 2x2x2 MP), "
+                                "H+S complex128, autotuned") if args.workload == "ceal" else
+                               ("LiH-like rock-salt cell a=7.6 bohr, 8^3 triquadratic hexes, 6^3 Gauss + 2 octree "
+                                "levels within 1 bohr, Gamma, H+S complex128, autotuned"),
                    "n_elem": sz["n_elem"], "n_qp": sz["n_qp"], "n_dof": sz["n_dof"],
                    "nnz": sz["nnz"], "kpoints": n_out, "precision": args.precision,
                    "nloc_min": int(nloc.min()), "nloc_max": int(nloc.max()), "nq_max": int(nq.max())},

@@ -180,3 +180,30 @@ def test_lih_cell_bloch_full_size_sampled_blocks():
             say("block", int(v), wv, "H", eh, "S", es, "bf16x6", e6)
             assert eh < TOL and es < TOL and e6 < 1e-7, (v, wv)
     p.close()
+
+
+def test_bloch_error_rule():
+    """Error-driven rule with the Bloch-periodic enrichment: the library
+    builds the same rule as for the periodic form (the rule is built from the
+    periodic functions; the imaginary-part copies test the same functions),
+    and on the oracle's rule the matrices match the oracle's."""
+    base = W.small("lih", mesh=(2, 2, 3), fe_order=2, a=4.8, re=1.6, rc=2.0)
+    base["quad"] = {"n": 3, "n_ref": 6, "levels": 3, "mode": "error", "dist": 0.0, "tol": 1e-6}
+    prob = B(base)
+    say("bloch error rule")
+    q = P.Problem(base).setup()
+    p = P.Problem(prob).setup()
+    for a, b in zip(P.pufe_get_leaves(p.ctx), P.pufe_get_leaves(q.ctx)):
+        assert np.array_equal(a, b)
+    q.close()
+    o = oracle.Oracle(prob)
+    lev, ijk, off = o.leaves()
+    p.set_rule(lev, ijk, off)
+    xyz, _, _ = o.quadrature()
+    V = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    H, S = p.assemble(V, [KAP])
+    Ho, So = o.assemble_dense_bloch(V.cpu().numpy(), KAP)
+    eh, es = rel(p.to_dense(H[0]).cpu().numpy(), Ho), rel(p.to_dense(S[0]).cpu().numpy(), So)
+    say("bloch error rule H", eh, "S", es)
+    assert eh < TOL and es < TOL
+    p.close()
