@@ -204,8 +204,11 @@ int pufe_set_projectors(pufe_ctx *ctx, int n, const pufe_projector *proj);
  * complex element matrix conj(phi_a) phi_b from it.  The layout, the
  * quadrature rule (built from the periodic functions in the error-driven
  * mode) and the output types are those of the periodic form; the split
- * precisions apply as well.  An element may hold at most 32 enriched
- * functions (64 rows with their imaginary parts) of at most 16 groups.  With
+ * precisions apply as well.  The imaginary parts double an element's
+ * enrichment functions and groups, so an element may be reached by at most
+ * 32 enrichment functions (2l+1 per (atom, descriptor) group) in at most 16
+ * groups, and hold at most 512 rows in all (FE functions plus twice its
+ * enriched local functions).  With
  * this form, pufe_set_projectors, pufe_assemble_backward,
  * pufe_assemble_noalloc, pufe_element_matrices and the batch give
  * PUFE_ERR_UNSUPPORTED.  Errors: PUFE_ERR_STATE after pufe_setup or before
