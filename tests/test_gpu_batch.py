@@ -65,6 +65,39 @@ def test_batch_small_sweep_vs_oracle():
         p.close()
 
 
+def test_batch_general_variant_problems_vs_oracle():
+    """A batch of problems that need the general kernel variants (cubic
+    serendipity elements, tabulated radials, wide elements) next to an
+    analytic/Lagrange one: every output against the oracle, FP64 and bf16x6."""
+    probs = [W.small("one", mesh=(2, 3, 2), fe_order=3, levels=1, n=3, a=4.6),
+             W.with_tabulated_radials(W.small("lih", mesh=(3, 2, 2), fe_order=1, levels=1, n=3, a=5.0), 40),
+             W.small("ceal", mesh=(2, 2, 2), fe_order=2, levels=1, n=3, a=4.4, rc=3.0, re=2.4)]
+    kpts = W.mp2()[:2]
+    say("batch general-variant problems")
+    oracles, Vs, ps = [], [], []
+    for pr in probs:
+        o = oracle.Oracle(pr)
+        xyz, _, _ = o.quadrature()
+        oracles.append(o)
+        Vs.append(potential_at(torch.from_numpy(xyz).cuda(), pr))
+        ps.append(P.Problem(pr).setup())
+    b = P.Batch(ps)
+    for prec, tol in (("fp64", 1e-12), ("bf16x6", 1e-7)):
+        Hs, Ss = b.alloc(len(kpts), device="cuda")
+        b.assemble(Vs, kpts, Hs, Ss, precision=prec)
+        torch.cuda.synchronize()
+        for i, (o, p) in enumerate(zip(oracles, ps)):
+            for k, kap in enumerate(kpts):
+                Ho, So = o.assemble_dense(Vs[i].cpu().numpy(), kap)
+                eh = rel(p.to_dense(Hs[i][k]).cpu().numpy(), Ho)
+                es = rel(p.to_dense(Ss[i][k]).cpu().numpy(), So)
+                say(prec, probs[i]["name"], kap, "H", eh, "S", es)
+                assert eh < tol and es < tol
+    b.close()
+    for p in ps:
+        p.close()
+
+
 def test_batch_lih_lattice_sweep_full_size_sampled():
     """The 11 lattice constants x 8 k-points sweep (88 assemblies in one
     persistent launch): sampled BSR blocks against the oracle."""
