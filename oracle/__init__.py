@@ -427,35 +427,65 @@ def lda(rho):
     return v, e
 
 
-def scf(prob, n_iter, alpha=0.3, n_extra=2):
+def fermi_level(eps, n_el, sigma, weights):
+    """Chemical potential mu with sum_k weights[k] sum_i 2 f((eps[k][i] - mu) /
+    sigma) = n_el, f(x) = 1 / (1 + e^x) (Fermi-Dirac smearing of width sigma),
+    by 200 bisection steps on [min eps - 40 sigma, max eps + 40 sigma]; returns
+    mu and the occupations (weights included) per k-point."""
+    def occ(mu):
+        return [wk * (1.0 - np.tanh((e - mu) / (2.0 * sigma))) for e, wk in zip(eps, weights)]
+
+    lo = min(float(e.min()) for e in eps) - 40.0 * sigma
+    hi = max(float(e.max()) for e in eps) + 40.0 * sigma
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if sum(float(o.sum()) for o in occ(mid)) < n_el:
+            lo = mid
+        else:
+            hi = mid
+    mu = 0.5 * (lo + hi)
+    return mu, occ(mu)
+
+
+def scf(prob, n_iter, alpha=0.3, n_extra=2, smearing=None):
     """Fixed-point iteration of fig. scf on the oracle (periodic enrichment):
     from V_in = V_ion (the local ionic potential at the rule's points), per
-    iteration: H, S at every k-point of prob (eq. disceig3d), the lowest
-    n_el / 2 states of each doubly occupied with weight 2 / n_k, the electron
+    iteration: H, S at every k-point of prob (eq. disceig3d), the states
+    occupied with weight 2 / n_k (the lowest n_el / 2 of each k-point, or with
+    smearing > 0 the Fermi-Dirac occupations of fermi_level), the electron
     density n at the points from the adjoint's dL/dV with P = sum f c c^H
     (eq. rhoe), V_out = V_ion + V_H[n] + V_xc[n] (eqs. veff, poisson), and the
     linear mix V_in += alpha (V_out - V_in).  Returns V_in after n_iter
-    iterations and per iteration the lowest n_el/2 + n_extra eigenvalues of
-    every k-point and the residual (int (V_out - V_in)^2)^(1/2)."""
+    iterations and per iteration the lowest ceil(n_el/2) + n_extra eigenvalues
+    of every k-point and the residual (int (V_out - V_in)^2)^(1/2)."""
     import scipy.linalg as sl
     o = Oracle(prob)
     xyz, w, _ = o.quadrature()
     V_ion = potential_np(xyz, prob)
     n_el = sum(prob["species_info"][s]["Z"] for s in prob["species"])
-    n_occ = int(round(n_el / 2))
-    assert abs(2 * n_occ - n_el) < 1e-12, "an even number of electrons is assumed"
+    n_occ = int(np.ceil(n_el / 2 - 1e-12))
+    if not smearing:
+        assert abs(2 * n_occ - n_el) < 1e-12, "an even number of electrons is assumed without smearing"
     kpts = [tuple(k) for k in prob["kpts"]]
     V = V_ion.copy()
     hist = []
     for _ in range(n_iter):
         dens = np.zeros(o.n_qp)
         evs = []
+        sols = []
         for kap in kpts:
             H, S = o.assemble_dense(V, kap)
             eps, Cv = sl.eigh(H, S)
             evs.append(eps[:n_occ + n_extra])
-            Co = Cv[:, :n_occ]
-            Pk = (2.0 / len(kpts)) * (Co @ Co.conj().T)
+            sols.append((eps, Cv))
+        if smearing:
+            _, occ = fermi_level([e for e, _ in sols], n_el, smearing, [1.0 / len(kpts)] * len(kpts))
+        else:
+            occ = [np.where(np.arange(len(e)) < n_occ, 2.0 / len(kpts), 0.0) for e, _ in sols]
+        for kap, (eps, Cv), f in zip(kpts, sols, occ):
+            keep = f > 1e-14 * f.max()
+            Co = Cv[:, keep] * f[keep]
+            Pk = Co @ Cv[:, keep].conj().T
             dV, _ = o.backward_dense(V, kap, Pk)
             dens += dV / w
         vh, _ = o.hartree(dens)

@@ -153,3 +153,26 @@ def test_lih_cell_density_full_size():
     _, hist = run_scf(p, V, 16.0, [(0.0, 0.0, 0.0)], 1)
     assert np.isfinite(hist[0][1]) and hist[0][1] > 0
     p.close()
+
+
+def test_scf_smearing_matches_oracle():
+    """Three fixed-point iterations with Fermi-Dirac smearing (width 0.02 Ha)
+    on a small CeAl-like cell (15 electrons, s to f enrichments) at two
+    k-points against the oracle's iteration."""
+    prob = W.small("ceal", mesh=(2, 2, 2), fe_order=1, levels=1, n=3, a=4.4,
+                   kpts=((0.0, 0.0, 0.0), (0.25, 0.25, -0.25)))
+    say("scf smearing")
+    n_iter = 3
+    Vo, ho = oracle.scf(prob, n_iter, alpha=0.3, smearing=0.02)
+    o = oracle.Oracle(prob)
+    xyz, w, _ = o.quadrature()
+    p = P.Problem(prob).setup()
+    V_ion = potential_at(torch.from_numpy(xyz).cuda(), prob)
+    n_el = sum(prob["species_info"][s]["Z"] for s in prob["species"])
+    assert n_el == 15.0
+    V, h = run_scf(p, V_ion, n_el, prob["kpts"], n_iter, alpha=0.3, smearing=0.02)
+    for i, ((e, r), (eo, ro)) in enumerate(zip(h, ho)):
+        say("iteration", i, "eig diff", np.abs(e - eo).max(), "residual", r, ro)
+        assert np.abs(e - eo).max() < 1e-8 and abs(r - ro) < 1e-8 * max(1.0, ro)
+    assert rel(V.cpu().numpy(), Vo) < 1e-10
+    p.close()

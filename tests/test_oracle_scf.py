@@ -12,7 +12,10 @@ calculations", eqs. poisson, veff, rhoe):
 - LDA: v_xc = d(n e_xc)/dn by central differences on both sides of r_s = 1,
   the Slater exchange constant at r_s = 1, continuity of the correlation fit;
 - the fixed-point iteration: the density integrates to the electron count and
-  the residual falls."""
+  the residual falls;
+- Fermi-Dirac smearing: the occupations hold the electron count, a small
+  width on an insulator reproduces the integer filling, and an odd electron
+  count iterates with a falling residual."""
 import itertools
 
 import numpy as np
@@ -185,3 +188,24 @@ def test_scf_density_count_and_residual():
     dV, _ = o.backward_dense(V, (0.0, 0.0, 0.0), 2.0 * Co @ Co.conj().T)
     assert abs(dV.sum() - 16.0) < 1e-10
     assert np.all(dV / w > -1e-12)
+
+
+def test_fermi_smearing():
+    """Fermi-Dirac occupations: they hold the electron count, a small width on
+    an insulator reproduces the integer filling of the lowest states, and a
+    metal-like (odd) electron count runs with smearing, its density
+    integrating to that count."""
+    rng = np.random.default_rng(5)
+    eps = [np.sort(rng.normal(size=30)) for _ in range(3)]
+    for n_el, sig in ((15.0, 0.05), (20.0, 0.01), (7.0, 0.3)):
+        mu, occ = oracle.fermi_level(eps, n_el, sig, [1.0 / 3] * 3)
+        assert abs(sum(o.sum() for o in occ) - n_el) < 1e-10
+        assert all(np.all((o >= 0) & (o <= 2.0 / 3 + 1e-15)) for o in occ)
+    prob = W.small("lih", mesh=(2, 2, 2), fe_order=1, levels=1, n=3, a=4.6)
+    V0, h0 = oracle.scf(prob, 2)
+    V1, h1 = oracle.scf(prob, 2, smearing=1e-3)
+    assert np.abs(V1 - V0).max() < 1e-10
+    pc = W.small("ceal", mesh=(2, 2, 2), fe_order=1, levels=1, n=3, a=4.4,
+                 kpts=((0.0, 0.0, 0.0), (0.25, 0.25, -0.25)))
+    V, h = oracle.scf(pc, 2, smearing=0.02)
+    assert h[1][1] < h[0][1]
