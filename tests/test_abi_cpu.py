@@ -281,3 +281,25 @@ def test_enrichment_phase_validation_and_layout():
         _expect(-2, lambda: P.pufe_set_enrichment_phase(ctx, "bloch"))
     finally:
         P.pufe_destroy(ctx)
+
+
+def test_element_function_limits():
+    """64 enrichment functions on an element are accepted and 65 refused; with
+    the Bloch-periodic enrichment 32 are accepted and 33 refused (their
+    imaginary parts double them)."""
+    def try_plan(prob, bloch=False):
+        ctx = P.pufe_create(0)
+        try:
+            P.pufe_set_problem(ctx, prob["lattice"], prob["mesh"], prob["fe_order"], prob["atoms"],
+                               prob["species"], prob["enrichments"], prob["quad"])
+            if bloch:
+                P.pufe_set_enrichment_phase(ctx, "bloch")
+            return P.pufe_query(ctx)["max_nloc"]
+        finally:
+            P.pufe_destroy(ctx)
+
+    assert try_plan(W.limit_cell(2)) == 8 + 64
+    _expect(-2, lambda: try_plan(W.limit_cell(2, extra_h=True)))
+    assert try_plan(W.limit_cell(1), bloch=True) == 8 + 64
+    _expect(-2, lambda: try_plan(W.limit_cell(1, extra_h=True), bloch=True))
+    assert oracle.Oracle(W.limit_cell(2)).element_dofs(0)[0].size == 8 + 64

@@ -266,6 +266,28 @@ def with_tabulated_radials(prob, n_samples: int = 48):
     return out
 
 
+def limit_cell(n_ce: int = 2, extra_h: bool = False):
+    """A 2^3 trilinear cube (a = 4.4, every element's corners are all 8
+    vertices) with n_ce Ce-like atoms, each right next to its own vertex and
+    carrying 32 functions (s, p, d, f x 2 exponents, rc = 3, re = 0.5), so
+    every element is reached by 32 n_ce enrichment functions in 8 n_ce
+    groups; extra_h adds an H-like atom with one s function next to a third
+    vertex (one function over the limit when n_ce = 2)."""
+    a = 4.4
+    pos = [[0.05, 0.03, 0.02], [2.25, 2.18, 2.23]][:n_ce]
+    spc = [0] * n_ce
+    enr = [{"species": 0, "l": l, "a": ex, "rc": 3.0, "re": 0.5} for l in range(4) for ex in (3.0, 0.4)]
+    info = [{"name": "Ce", "Z": 12.0, "rloc": 0.3}]
+    if extra_h:
+        pos.append([2.22, 0.04, 0.03])
+        spc.append(1)
+        enr.append({"species": 1, "l": 0, "a": 0.8, "rc": 3.0, "re": 0.5})
+        info.append({"name": "H", "Z": 1.0, "rloc": 0.4})
+    return _problem(cubic(a), (2, 2, 2), 1, pos, spc, info, enr,
+                    {"n": 3, "n_ref": 6, "levels": 1, "mode": "geom", "dist": 0.6, "tol": 1e-6},
+                    [[0.0, 0.0, 0.0]], 4, "limit_cell_%d%s" % (n_ce, "_h" if extra_h else ""))
+
+
 def with_bloch_enrichment(prob):
     """A copy of prob whose enrichment functions are Bloch-periodic (eq. Psi
     with f(R) = exp(i k.R)); its PU functions are then periodic and its
