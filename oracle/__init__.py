@@ -95,6 +95,9 @@ def lib():
         L.or_nonlocal_f.argtypes = [C.c_void_p, _f64p, C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_void_p]
         L.or_nonlocal_f.restype = C.c_int
         L.or_nonlocal_dense.argtypes = [C.c_void_p, _f64p, C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
+        L.or_nonlocal_f_bloch.argtypes = L.or_nonlocal_f.argtypes
+        L.or_nonlocal_f_bloch.restype = C.c_int
+        L.or_nonlocal_dense_bloch.argtypes = L.or_nonlocal_dense.argtypes
         L.or_pattern_nnz.argtypes = [C.c_void_p]
         L.or_pattern_nnz.restype = C.c_int64
         _lib = L
@@ -360,21 +363,24 @@ class Oracle:
         hh = np.array([q["h"] for q in pr] + [0], np.float64)
         return len(pr), sp, ll, aa, rc, hh
 
-    def nonlocal_f(self, kappa=(0.0, 0.0, 0.0), projectors=None):
-        """f_J^i of the separable nonlocal term (n_fun x N complex)."""
+    def nonlocal_f(self, kappa=(0.0, 0.0, 0.0), projectors=None, bloch=False):
+        """f_J^i of the separable nonlocal term (n_fun x N complex), over the
+        basis of the periodic or (bloch) the Bloch-periodic enrichment."""
         n, sp, ll, aa, rc, _ = self._projectors(projectors)
         k = np.asarray(kappa, np.float64)
-        nf = lib().or_nonlocal_f(self.h, k, n, sp, ll, aa, rc, None)
+        fn = lib().or_nonlocal_f_bloch if bloch else lib().or_nonlocal_f
+        nf = fn(self.h, k, n, sp, ll, aa, rc, None)
         F = np.zeros((max(nf, 1), self.n_dof, 2))
-        lib().or_nonlocal_f(self.h, k, n, sp, ll, aa, rc, F.ctypes.data)
+        fn(self.h, k, n, sp, ll, aa, rc, F.ctypes.data)
         return (F[..., 0] + 1j * F[..., 1])[:nf]
 
-    def nonlocal_dense(self, kappa=(0.0, 0.0, 0.0), projectors=None):
+    def nonlocal_dense(self, kappa=(0.0, 0.0, 0.0), projectors=None, bloch=False):
         """The N x N separable nonlocal term sum_J h_J f_J^i conj(f_J^j)."""
         n, sp, ll, aa, rc, hh = self._projectors(projectors)
         N = self.n_dof
         Vn = np.zeros((N, N, 2))
-        lib().or_nonlocal_dense(self.h, np.asarray(kappa, np.float64), n, sp, ll, aa, rc, hh, Vn)
+        fn = lib().or_nonlocal_dense_bloch if bloch else lib().or_nonlocal_dense
+        fn(self.h, np.asarray(kappa, np.float64), n, sp, ll, aa, rc, hh, Vn)
         return Vn[..., 0] + 1j * Vn[..., 1]
 
     def pattern_nnz(self):

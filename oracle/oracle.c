@@ -1470,8 +1470,12 @@ static double projector_value(int l, int m, double a, double rc, const double *r
  *   f_J^i = sum_e sum_{a -> i} conj(p_a) sum_q w_q N_a(x_q) P_J(x_q),
  *   P_J(x) = sum_n exp(2 pi i kappa . n) v_J(x - tau_A - a_n).
  * F: n_fun x N complex (re, im), row J.  Returns n_fun. */
-int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int *proj_species, const int *proj_l,
-                  const double *proj_a, const double *proj_rc, double *F) {
+/* f_J^i over the basis of the periodic (bloch = 0) or the Bloch-periodic
+ * (bloch = 1) enrichment: the conjugate of p_a phi_a, with the boundary phase
+ * p_a on the classical FE functions (and, in the periodic form, on the PU
+ * functions too), times the Bloch sum of the projector function. */
+static int nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int *proj_species, const int *proj_l,
+                      const double *proj_a, const double *proj_rc, double *F, int bloch) {
     /* projector functions */
     int nfun = 0;
     for (int d = 0; d < n_proj; ++d)
@@ -1495,6 +1499,7 @@ int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int 
     int mx = max_locals(s);
     loc_fn *L = malloc(sizeof(loc_fn) * mx);
     double *val = malloc(sizeof(double) * mx), *grad = malloc(sizeof(double) * 3 * mx);
+    double *vim = calloc(mx, sizeof(double)), *gim = malloc(sizeof(double) * 3 * mx);
     double *Pre = malloc(sizeof(double) * (nfun + 1)), *Pim = malloc(sizeof(double) * (nfun + 1));
     int64_t nq3 = (int64_t)s->q_n * s->q_n * s->q_n;
     for (int64_t e = 0; e < s->nel; ++e) {
@@ -1504,7 +1509,10 @@ int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int 
                 double xi[3], w, x[3];
                 leaf_point(s, s->leaf_level[lf], s->leaf_ijk + 3 * lf, j, xi, &w);
                 ref2phys(s, e, xi, x);
-                basis_eval(s, e, L, n, xi, val, grad);
+                if (bloch)
+                    basis_eval_bloch(s, e, L, n, xi, kappa, val, vim, grad, gim);
+                else
+                    basis_eval(s, e, L, n, xi, val, grad);
                 /* Bloch sums of the projector functions at x */
                 double ux[3];
                 cart2red(s, x, ux);
@@ -1530,10 +1538,11 @@ int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int 
                     Pim[J2] = im;
                 }
                 for (int a = 0; a < n; ++a) {
-                    double par, pai;
-                    phase(kappa, L[a].shift, &par, &pai);
-                    /* conj(p_a) w N_a P_J */
-                    double cr = w * val[a] * par, ci = -w * val[a] * pai;
+                    double par = 1.0, pai = 0.0;
+                    if (!bloch || L[a].kind == 0) phase(kappa, L[a].shift, &par, &pai);
+                    /* w conj(p_a phi_a) P_J */
+                    double qr = par * val[a] - pai * vim[a], qi = par * vim[a] + pai * val[a];
+                    double cr = w * qr, ci = -w * qi;
                     for (int J2 = 0; J2 < nfun; ++J2) {
                         double *f = F + 2 * ((size_t)J2 * N + L[a].g);
                         f[0] += cr * Pre[J2] - ci * Pim[J2];
@@ -1542,20 +1551,30 @@ int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int 
                 }
             }
     }
-    free(L); free(val); free(grad); free(Pre); free(Pim); free(fa); free(fd); free(fm);
+    free(L); free(val); free(grad); free(vim); free(gim); free(Pre); free(Pim); free(fa); free(fd); free(fm);
     return nfun;
+}
+
+int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int *proj_species, const int *proj_l,
+                  const double *proj_a, const double *proj_rc, double *F) {
+    return nonlocal_f(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, F, 0);
+}
+
+int or_nonlocal_f_bloch(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
+                        const int *proj_l, const double *proj_a, const double *proj_rc, double *F) {
+    return nonlocal_f(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, F, 1);
 }
 
 /* The separable nonlocal term of eq. disceig3d as a dense matrix:
  *   Vnl_ij = sum_J h_J f_J^i conj(f_J^j),
  * with h_J the weight of J's descriptor.  Vnl: N x N complex (re, im). */
-void or_nonlocal_dense(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
-                       const int *proj_l, const double *proj_a, const double *proj_rc, const double *proj_h,
-                       double *Vnl) {
-    int nfun = or_nonlocal_f(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, NULL);
+static void nonlocal_dense(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
+                           const int *proj_l, const double *proj_a, const double *proj_rc, const double *proj_h,
+                           double *Vnl, int bloch) {
+    int nfun = nonlocal_f(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, NULL, bloch);
     int64_t N = s->ndof;
     double *F = malloc(sizeof(double) * 2 * ((size_t)nfun * N + 1));
-    or_nonlocal_f(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, F);
+    nonlocal_f(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, F, bloch);
     double *h = malloc(sizeof(double) * (nfun + 1));
     int J = 0;
     for (int d = 0; d < n_proj; ++d)
@@ -1577,6 +1596,18 @@ void or_nonlocal_dense(const or_state *s, const double *kappa, int n_proj, const
     }
     free(F);
     free(h);
+}
+
+void or_nonlocal_dense(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
+                       const int *proj_l, const double *proj_a, const double *proj_rc, const double *proj_h,
+                       double *Vnl) {
+    nonlocal_dense(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, proj_h, Vnl, 0);
+}
+
+void or_nonlocal_dense_bloch(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
+                             const int *proj_l, const double *proj_a, const double *proj_rc, const double *proj_h,
+                             double *Vnl) {
+    nonlocal_dense(s, kappa, n_proj, proj_species, proj_l, proj_a, proj_rc, proj_h, Vnl, 1);
 }
 
 

@@ -116,6 +116,12 @@ int or_nonlocal_f(const or_state *s, const double *kappa, int n_proj, const int 
 void or_nonlocal_dense(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
                        const int *proj_l, const double *proj_a, const double *proj_rc, const double *proj_h,
                        double *Vnl);
+/* the same over the basis of the Bloch-periodic enrichment */
+int or_nonlocal_f_bloch(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
+                        const int *proj_l, const double *proj_a, const double *proj_rc, double *F);
+void or_nonlocal_dense_bloch(const or_state *s, const double *kappa, int n_proj, const int *proj_species,
+                             const int *proj_l, const double *proj_a, const double *proj_rc, const double *proj_h,
+                             double *Vnl);
 /* sparsity count: number of nonzero (i,j) pairs of S over the topology */
 int64_t or_pattern_nnz(const or_state *s);
 

@@ -14,7 +14,9 @@ functions keep their boundary phases):
   H(-kappa) = conj(H(kappa));
 - zone folding: the eigenvalues of a cell tripled along a_1 at Gamma are the
   union of the primitive cell's at kappa_1 = 0, 1/3, 2/3 (a geometry where no
-  PU support sees two images of one atom)."""
+  PU support sees two images of one atom);
+- the separable term's projector coefficients over this basis against the
+  global basis functions and the projectors' Bloch sums written out."""
 import numpy as np
 import pytest
 import scipy.linalg as sl
@@ -186,3 +188,48 @@ def test_zone_folding(fe_order):
     ep = np.sort(np.concatenate(ep))
     m = 40
     assert np.abs(ep[:m] - es[:m]).max() < 1e-8 * max(1.0, np.abs(es[:m]).max())
+
+
+def test_nonlocal_coefficients_against_global_functions():
+    """Projector coefficients of the separable term over the Bloch-periodic
+    basis: f_J^i = sum_q w_q conj(Phi_i(x_q)) P_J(x_q) with the global basis
+    functions written out as in test_matrices_against_global_functions and the
+    projector's Bloch sum P_J = sum_n exp(2 pi i kappa.n) v_J(x - tau - n.a),
+    v = exp(-a r^2)(1 - r^2/rc^2)^3 S_lm (the synthetic projector); the FE
+    rows equal those of the periodic form's coefficients."""
+    prob = W.with_projectors(overlapping())
+    o = oracle.Oracle(prob)
+    xyz, w, _ = o.quadrature()
+    lat = np.array(prob["lattice"])
+    inv = np.linalg.inv(lat)
+    n = np.array(prob["mesh"])
+    u = xyz @ inv
+    off = o.dof_offset()
+    Fb = o.nonlocal_f(KAP, bloch=True)
+    Fp = o.nonlocal_f(KAP)
+    fe = np.concatenate([np.arange(off[v], off[v] + 1) for v in range(o.n_vertex)])
+    assert np.abs(Fb[:, fe] - Fp[:, fe]).max() == 0.0
+    # projector functions J in the oracle's order: descriptor, atom, m
+    tau = np.array(prob["atoms"][0])
+    Pj = []
+    for q in prob["projectors"]:
+        for m in range(-q["l"], q["l"] + 1):
+            val = np.zeros(len(u), complex)
+            for img in np.ndindex(5, 5, 5):
+                nn = np.array(img) - 2
+                r = xyz - tau - nn @ lat
+                sq = np.sum(r * r, 1)
+                inside = sq < q["rc"] ** 2
+                S = np.array([oracle.solid_harmonic(q["l"], m, rr)[0] if ok else 0.0 for rr, ok in zip(r, inside)])
+                v = np.where(inside, np.exp(-q["a"] * sq) * np.clip(1 - sq / q["rc"] ** 2, 0, None) ** 3 * S, 0.0)
+                val += np.exp(2j * np.pi * np.dot(KAP, nn)) * v
+            Pj.append(val)
+    v = [v for v in range(len(off) - 1) if off[v + 1] - off[v] > 1][0]
+    j = (v % n[0], (v // n[0]) % n[1], v // (n[0] * n[1]))
+    M, _ = _global_hat(u, j, n, np.zeros(3), inv)
+    for s, (atom, desc, m) in enumerate(o.vertex_functions(v)):
+        psi = np.array([o.enrichment_bloch(int(atom), int(desc), int(m), x, KAP)[0] for x in xyz])
+        phi = M * psi
+        for J, P in enumerate(Pj):
+            want = np.sum(w * np.conj(phi) * P)
+            assert abs(Fb[J, off[v] + 1 + s] - want) < 1e-12 * max(1.0, abs(want))
