@@ -208,13 +208,13 @@ int pufe_set_projectors(pufe_ctx *ctx, int n, const pufe_projector *proj);
  * enrichment functions and groups, so an element may be reached by at most
  * 32 enrichment functions (2l+1 per (atom, descriptor) group) in at most 16
  * groups, and hold at most 512 rows in all (FE functions plus twice its
- * enriched local functions).  With
- * this form, pufe_set_projectors, pufe_assemble_backward,
+ * enriched local functions).  The separable nonlocal term (pufe_set_projectors)
+ * follows the form: its projector coefficients come from the same real and
+ * imaginary rows, per k-point.  With this form pufe_assemble_backward,
  * pufe_assemble_noalloc, pufe_element_matrices and the batch give
  * PUFE_ERR_UNSUPPORTED.  Errors: PUFE_ERR_STATE after pufe_setup or before
  * pufe_set_problem, PUFE_ERR_INVALID_ARG for an unknown form,
- * PUFE_ERR_UNSUPPORTED (projectors set, or too many functions on an
- * element). */
+ * PUFE_ERR_UNSUPPORTED (too many functions on an element). */
 int pufe_set_enrichment_phase(pufe_ctx *ctx, int form);
 
 /* Build the adaptive rule on the device (section "Adaptive quadrature"),

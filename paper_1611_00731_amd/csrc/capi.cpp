@@ -776,10 +776,11 @@ static int check_assemble_args(pufe_ctx *ctx, const double *d_V, const double *k
 }
 
 // Assembly with the Bloch-periodic enrichment: for every k-point the image
-// weights, the contraction of the real and imaginary rows, the K-chunk sum
-// and the complex scatter of each colour into that k-point's output.
+// weights, the contraction of the real and imaginary rows, the K-chunk sum,
+// the projector coefficients of those rows (with projectors), the complex
+// scatter of each colour into that k-point's output and the separable term.
 static int assemble_bloch(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision,
-                          int out_dtype, void *d_H, void *d_S, hipStream_t st) {
+                          int out_dtype, void *d_H, void *d_S, hipStream_t st, bool nonlocal) {
     const Plan &pl = ctx->plan;
     const int64_t per = out_dtype == PUFE_OUT_F64_GAMMA ? pl.nnz : 2 * pl.nnz;
     const size_t esz = out_dtype == PUFE_OUT_C64 ? sizeof(float) : sizeof(double);
@@ -803,6 +804,20 @@ static int assemble_bloch(pufe_ctx *ctx, const double *d_V, const double *kpts, 
                       "image weights");
             int rc = run_contraction(ctx, d_V, precision, st, ctx->d_partial.p, true, ctx->d_wimg.p);
             if (rc != PUFE_OK) return rc;
+            const bool with_nl = nonlocal && pl.n_pfun > 0;
+            if (with_nl) {
+                // projector coefficients of this k-point's rows
+                TimedRegion tn(ctx, 4, st);
+                KParams kp = pl.kp;
+                kp.wimg = ctx->d_wimg.p;
+                CHECK_HIP(ctx, launch_nl_f(pl.max_l, kp, (int)ctx->nl_items.size(), ctx->d_nl_items.p, ctx->d_elems.p,
+                                           ctx->d_groups.p, ctx->d_img.p, ctx->d_edof.p, ctx->d_leaves.p,
+                                           ctx->d_pgroups.p, ctx->d_Fp.p, ctx->nl_lds, st),
+                          "projector coefficients");
+                CHECK_HIP(ctx, launch_nl_reduce(ctx->d_elems.p, ctx->d_nl_elems.p, (int)ctx->nl_elems.size(),
+                                                ctx->d_Fp.p, st),
+                          "projector coefficient sum");
+            }
             TimedRegion tr(ctx, 1, st);
             char *H = (char *)d_H + (size_t)(k0 + k) * per * esz;
             char *S = d_S ? (char *)d_S + (size_t)(k0 + k) * per * esz : nullptr;
@@ -812,6 +827,22 @@ static int assemble_bloch(pufe_ctx *ctx, const double *d_V, const double *kpts, 
                                                     ctx->d_edof.p, ctx->d_bpart.p, ctx->d_partial.p,
                                                     ctx->d_ztab.p + 27 * k, out_dtype, H, S, st),
                           "scatter");
+            }
+            if (with_nl) {
+                // the separable term of this k-point into its H
+                KPoints one;
+                std::memset(&one, 0, sizeof one);
+                one.nk = 1;
+                for (int d = 0; d < 3; ++d) one.kap[0][d] = kps.kap[k][d];
+                const int64_t ndof = pl.dof_off[pl.nv];
+                CHECK_HIP(ctx, launch_nl_gather(pl.kp, ctx->d_elems.p, ctx->d_pgroups.p, ctx->d_edof.p, ctx->d_bpart.p,
+                                                ctx->d_dof_el_off.p, ctx->d_dof_el.p, ctx->d_Fp.p, one, pl.n_pfun,
+                                                ndof, ctx->d_nlf.p, st),
+                          "projector sums");
+                CHECK_HIP(ctx, launch_nl_update((int)pl.nl_blocks.size(), ctx->d_nl_blocks.p, ctx->d_brow.p,
+                                                ctx->d_bcol.p, ctx->d_bval_off.p, ctx->d_dof_off.p, ctx->d_nlf.p,
+                                                ctx->d_pfun_h.p, pl.n_pfun, ndof, 1, out_dtype, H, pl.nnz, st),
+                          "nonlocal update");
             }
         }
     }
@@ -823,7 +854,7 @@ static int assemble_bloch(pufe_ctx *ctx, const double *d_V, const double *kpts, 
 static int assemble_impl(pufe_ctx *ctx, const double *d_V, const double *kpts, int n_k, int precision, int out_dtype,
                          void *d_H, void *d_S, hipStream_t st, double *partial, double2 *ztab, bool timed,
                          bool nonlocal = true) {
-    if (ctx->plan.bloch) return assemble_bloch(ctx, d_V, kpts, n_k, precision, out_dtype, d_H, d_S, st);
+    if (ctx->plan.bloch) return assemble_bloch(ctx, d_V, kpts, n_k, precision, out_dtype, d_H, d_S, st, nonlocal);
     int rc = run_contraction(ctx, d_V, precision, st, partial, timed);
     if (rc != PUFE_OK) return rc;
     const Plan &pl = ctx->plan;
@@ -865,7 +896,7 @@ static int assemble_impl(pufe_ctx *ctx, const double *d_V, const double *kpts, i
         if (with_nl) {
             // the separable term of these k-points into H
             const int64_t ndof = pl.dof_off[pl.nv];
-            CHECK_HIP(ctx, launch_nl_gather(pl.kp, ctx->d_elems.p, ctx->d_pgroups.p, ctx->d_edof.p,
+            CHECK_HIP(ctx, launch_nl_gather(pl.kp, ctx->d_elems.p, ctx->d_pgroups.p, ctx->d_edof.p, nullptr,
                                             ctx->d_dof_el_off.p, ctx->d_dof_el.p, ctx->d_Fp.p, kps, pl.n_pfun, ndof,
                                             ctx->d_nlf.p, st),
                       "projector sums");

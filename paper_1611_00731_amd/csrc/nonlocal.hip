@@ -7,7 +7,11 @@
 //           exp(2 pi i kappa . n) F_e[a][col(J, n)],
 //   F_e[a][c] = sum_q w_q N_a(x_q) v_c(x_q)          (real, k-independent)
 // F_e is a contraction of the element's basis values with its projector
-// values over the quadrature points, on FP64 MFMA (nl_f_kernel); the
+// values over the quadrature points, on FP64 MFMA (nl_f_kernel); with the
+// Bloch-periodic enrichment the element's rows are its real rows and the
+// imaginary parts of its enriched functions (images weighted per k-point), so
+// F_e is per k-point and the gather takes conj(phi) = real - i imaginary, with
+// the boundary phase on the classical FE rows only; the
 // phases and the sum over the elements of a DOF are a gather per (J, DOF)
 // (nl_gather_kernel), and the low-rank update runs per BSR block that a
 // projector image couples (nl_update_kernel).  No atomics; fixed order.
@@ -125,7 +129,8 @@ __global__ __launch_bounds__(kNlThreads) void nl_f_kernel(
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lb + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
-            group_eval_upto<LMAX, Q>(G, sImg, kp.spl, nullptr, x, sPsi + (size_t)G.fbase * 4 * Q + q);
+            group_eval_upto<LMAX, Q>(G, sImg, kp.spl, kp.wimg ? kp.wimg + img0 : nullptr, x,
+                                     sPsi + (size_t)G.fbase * 4 * Q + q);
         }
         for (int idx = tid; idx < npg * Q; idx += NT) {
             const int g = idx / Q, q = idx - g * Q;
@@ -201,10 +206,13 @@ __global__ __launch_bounds__(256) void nl_reduce_kernel(const ElemDev *__restric
 
 // f_J^i for the k-points of kps: one thread per (J, DOF i); the DOF's
 // (element, local function) pairs in element order, each element's
-// projector images of J in group order.
+// projector images of J in group order.  bpart (Bloch-periodic enrichment,
+// one k-point; null otherwise): the partner table of the enriched rows, -1
+// marking an imaginary part, which enters conj(phi) with the factor -i.
 __global__ __launch_bounds__(256) void nl_gather_kernel(const KParams kp, const ElemDev *__restrict__ elems,
                                                         const PGroupDev *__restrict__ pgroups,
                                                         const int32_t *__restrict__ edof,
+                                                        const int32_t *__restrict__ bpart,
                                                         const int64_t *__restrict__ dof_el_off,
                                                         const int2 *__restrict__ dof_el,
                                                         const double *__restrict__ Fp, const KPoints kps,
@@ -222,6 +230,11 @@ __global__ __launch_bounds__(256) void nl_gather_kernel(const KParams kp, const 
         const int npad = 16 * ((el.nloc + 15) / 16);
         int corner, slot;
         local_slot(el, edof, kp.p, ea.y, &corner, &slot);
+        const bool enr = ea.y >= el.nfe;
+        // Bloch-periodic enrichment: periodic PU (no boundary phase on the
+        // enriched rows), imaginary parts with the factor -i
+        const bool imag = bpart && enr && bpart[el.edof_off + (ea.y - el.nfe)] < 0;
+        const int sh_on = (bpart && enr) ? 0 : 1;
         const double *F = Fp + el.pf_base;
         for (int g = 0; g < el.npg; ++g) {
             const PGroupDev &G = pgroups[el.pg_off + g];
@@ -232,11 +245,16 @@ __global__ __launch_bounds__(256) void nl_gather_kernel(const KParams kp, const 
                 // conj(p_a) exp(2 pi i kappa . n): phase of kappa . (n - shift_a)
                 double t2 = 0.0;
                 for (int d = 0; d < 3; ++d)
-                    t2 += kps.kap[k][d] * (double)(G.n[d] - ((el.shifts >> (3 * corner + d)) & 1));
+                    t2 += kps.kap[k][d] * (double)(G.n[d] - sh_on * ((el.shifts >> (3 * corner + d)) & 1));
                 double sn, cs;
                 sincos(2.0 * M_PI * t2, &sn, &cs);
-                acc[k].x += cs * val;
-                acc[k].y += sn * val;
+                if (imag) {   // (cs + i sn)(-i val)
+                    acc[k].x += sn * val;
+                    acc[k].y -= cs * val;
+                } else {
+                    acc[k].x += cs * val;
+                    acc[k].y += sn * val;
+                }
             }
         }
     }
@@ -320,12 +338,12 @@ hipError_t launch_nl_reduce(const ElemDev *elems, const int32_t *nl_elems, int n
 }
 
 hipError_t launch_nl_gather(const KParams &kp, const ElemDev *elems, const PGroupDev *pgroups, const int32_t *edof,
-                            const int64_t *dof_el_off, const int2 *dof_el, const double *Fp, const KPoints &kps,
-                            int n_pfun, int64_t n_dof, double2 *f, hipStream_t st) {
+                            const int32_t *bpart, const int64_t *dof_el_off, const int2 *dof_el, const double *Fp,
+                            const KPoints &kps, int n_pfun, int64_t n_dof, double2 *f, hipStream_t st) {
     const int64_t n = (int64_t)n_pfun * n_dof;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(nl_gather_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, kp, elems, pgroups, edof,
-                       dof_el_off, dof_el, Fp, kps, n_pfun, n_dof, f);
+                       bpart, dof_el_off, dof_el, Fp, kps, n_pfun, n_dof, f);
     return hipGetLastError();
 }
 

@@ -14,9 +14,11 @@ hipError_t launch_nl_f(int lmax, const KParams &kp, int n_items, const NlItemDev
                        const GroupDev *groups, const double *img, const int32_t *edof, const uint32_t *leaves,
                        const PGroupDev *pgroups, double *Fp, size_t lds, hipStream_t st);
 hipError_t launch_nl_reduce(const ElemDev *elems, const int32_t *nl_elems, int n, double *Fp, hipStream_t st);
+// bpart: the partner table of the Bloch-periodic enrichment's rows (null for
+// the periodic form)
 hipError_t launch_nl_gather(const KParams &kp, const ElemDev *elems, const PGroupDev *pgroups, const int32_t *edof,
-                            const int64_t *dof_el_off, const int2 *dof_el, const double *Fp, const KPoints &kps,
-                            int n_pfun, int64_t n_dof, double2 *f, hipStream_t st);
+                            const int32_t *bpart, const int64_t *dof_el_off, const int2 *dof_el, const double *Fp,
+                            const KPoints &kps, int n_pfun, int64_t n_dof, double2 *f, hipStream_t st);
 hipError_t launch_nl_update(int n_blocks, const int32_t *nl_blocks, const int32_t *brow, const int32_t *bcol,
                             const int64_t *bval_off, const int64_t *dof_off, const double2 *f, const double *pfun_h,
                             int n_pfun, int64_t n_dof, int nk, int out_dtype, void *H, int64_t nnz, hipStream_t st);

@@ -114,10 +114,6 @@ int build_plan(const Problem &pr, Plan &pl, std::string &err) {
     if (pr.enr_phase != PUFE_ENR_PERIODIC && pr.enr_phase != PUFE_ENR_BLOCH) {
         err = "unknown enrichment phase form"; return PUFE_ERR_INVALID_ARG;
     }
-    if (pr.enr_phase == PUFE_ENR_BLOCH && !pr.proj.empty()) {
-        err = "the separable nonlocal term is not supported with Bloch-periodic enrichment";
-        return PUFE_ERR_UNSUPPORTED;
-    }
     const pufe_quad &q = pr.quad;
     if (q.n_gauss < 1 || q.n_gauss > kMaxGauss) { err = "n_gauss must be in 1..12"; return PUFE_ERR_INVALID_ARG; }
     if (q.max_level < 0 || q.max_level > kMaxLevel) { err = "max_level must be in 0..8"; return PUFE_ERR_INVALID_ARG; }
