@@ -166,7 +166,13 @@ __global__ void elem_qp_offset_kernel(const KParams kp, int64_t nel, const int64
 //   sRow            local function of each item row (-1: padding)
 template <int Q>
 struct ContractLds {
-    static constexpr int RS = 4 * Q + 2;  // row stride (doubles): 16-byte rows, offset banks
+    // row stride (doubles), odd: the MFMA operand reads (lane l at row l % 16,
+    // point l / 16) then meet 16 distinct even bank pairs in each 16-lane
+    // quarter of the wave; with an even stride (4 Q + 2) rows j and j + 8 met
+    // on one bank pair and these reads carried every bank conflict of the
+    // kernel (the row and enrichment phases, 16 consecutive points per unit,
+    // have none)
+    static constexpr int RS = 4 * Q + 1;
     static constexpr int FS = 4 * Q + 2;  // enrichment-function stride (doubles): offset banks
     static constexpr int GEO = 40;        // doubles of geometry per point
     static __host__ __device__ size_t bytes(int rows, int nfun, int nimg, int nleaf, int n3) {
