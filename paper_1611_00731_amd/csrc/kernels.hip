@@ -184,8 +184,31 @@ struct ContractLds {
 };
 
 constexpr int kContractThreads = 256;    // narrow work groups: 4 waves
+
+// Enrichment slots of a wide work group (8 waves, 16-point stages): slot
+// 4 p + s, s = lane / 16, of the p-th wave in the order of fewest tile pairs
+// evaluates group slot[4 p + s] at the 16 stage points (-1: none).  Groups of
+// one l fill waves of their own while the waves suffice, so each wave runs a
+// single l branch of the evaluation, the heaviest (largest l) on the waves
+// with the fewest MFMAs; otherwise the groups are packed by l.  One thread.
+__device__ __forceinline__ void enrichment_slots(const PUFE_GLOBAL GroupDev *grp, int ngrp, int nw, int *slot) {
+    int cnt[4] = {0, 0, 0, 0};
+    for (int g = 0; g < ngrp; ++g) ++cnt[min(max(grp[g].l, 0), 3)];
+    int need = 0;
+    for (int l = 0; l < 4; ++l) need += (cnt[l] + 3) / 4;
+    const bool own = need <= nw;
+    for (int k = 0; k < 4 * nw; ++k) slot[k] = -1;
+    int k = 0;
+    for (int l = 3; l >= 0; --l) {
+        if (own) k = (k + 3) & ~3;
+        for (int g = 0; g < ngrp; ++g)
+            if (min(max(grp[g].l, 0), 3) == l && k < 4 * nw) slot[k++] = g;
+    }
+}
+
 constexpr int kWideWaves = 8;            // wide work groups (elements of more than 80 functions)
 constexpr int kWideQ = 16;               // stage length of the wide work groups
+static_assert(kMaxGroups <= 4 * kWideWaves, "every group has an enrichment slot in a wide work group");
 
 // MFMAs of one stage for a wave owning NU tile pairs.  Every product sums
 // k = 4 consecutive points of one operand component (lane l supplies row
@@ -314,6 +337,8 @@ __device__ __forceinline__ void contract_f64_item(
     int *sCS = sRow + nrow;   // [9] PU corner starts in sEd
     int *sChunk = sCS + 16;   // [kMaxRowChunks] enriched-row chunks of a partial item, and their count
     int *sNChunk = sChunk + kMaxRowChunks;
+    int *sSlot = sNChunk + 4;   // [4 NW] enrichment slots of a wide work group (beyond ContractLds::bytes)
+    constexpr bool kSlots = NW == 8 && Q == 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t q_begin = it.leaf_b * (int64_t)n3, q_end = it.leaf_e * (int64_t)n3;
     const uint32_t nli = (uint32_t)(q_end - q_begin);
@@ -343,6 +368,7 @@ __device__ __forceinline__ void contract_f64_item(
         G.rc = Gg.rc;
         sG[g] = G;
     }
+    if (kSlots && tid == 0) enrichment_slots(gGroups + el.grp_off, ngrp, NW, sSlot);
     for (int k = tid; k < 3 * nimg; k += NT) sImg[k] = gImg[3 * (size_t)img0 + k];
     for (int64_t k = tid; k < it.leaf_e - it.leaf_b; k += NT) sLeaf[k] = gLeaves[it.leaf_b + k];
     for (uint32_t j = tid; j < n3; j += NT) sPt[j] = (j % n) | (((j / n) % n) << 8) | ((j / (n * n)) << 16);
@@ -441,8 +467,11 @@ __device__ __forceinline__ void contract_f64_item(
         accS[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
     }
     const int r16 = lane & 15, k4 = lane >> 4;
-    // the last Q threads build the geometry; V is read one stage ahead
-    const int gq = tid - (NT - Q);
+    // the last Q threads build the geometry (a wide work group: the last 16
+    // lanes of its wave of the fewest-MFMA order's fourth place, whose slots
+    // hold the lightest groups, l = 0 where the element has four l); V is read
+    // one stage ahead
+    const int gq = kSlots ? (vw == NW - 4 ? lane - (64 - Q) : -1) : tid - (NT - Q);
     double v = (gq >= 0 && (uint32_t)gq < nli) ? gV[q_begin + gq] : 0.0;
     // phase 1 of the stage starting at lbx: enrichment functions (eq. Psi,
     // f(R) = 1) and geometry, and V of that stage into the buffer vb
@@ -455,21 +484,32 @@ __device__ __forceinline__ void contract_f64_item(
             vb[gq] = v;
             v = vn;
         }
-        for (int idx = tid; idx < ngrp * Q; idx += NT) {
-            const int g = idx / Q, q = idx - g * Q;
+        auto eval = [&](int g, int q) {
             const GroupDev &G = sG[g];
             double xi[3], sw, x[3];
             item_point(kp, sLeaf, sPt, sGx, sGs, lbx + q, nli, n3, xi, &sw);
             point_position(kp, org, xi, x);
             group_eval_upto<LMAX, Q, FS, GEN>(G, sImg, kp.spl, wimg, x, sPsi + (size_t)G.fbase * FS + q);
+        };
+        if constexpr (kSlots) {
+            // one pass: the wave's slot of 16 lanes, waves taken by fewest tile pairs
+            const int g = sSlot[4 * (NW - 1 - vw) + (lane >> 4)];
+            if (g >= 0) eval(g, lane & 15);
+        } else {
+            for (int idx = tid; idx < ngrp * Q; idx += NT) {
+                const int g = idx / Q;
+                eval(g, idx - g * Q);
+            }
         }
     };
     __syncthreads();
-    if (!whole && tid == 0) row_chunks(sCS, nfe, lo0, hi0, lo1, hi1, Q, NT, sChunk, sNChunk);
-    if (nli > 0) phase1(0, sV);
-    __syncthreads();
     // FE functions in the item's rows (grouped by (a2, a3), filtered on store)
     const int nfu = (whole || lo0 < nfe || (!diag && lo1 < nfe)) ? fe_units(kp.p) : 0;
+    // (the one-pass widening pays on the wide work groups only: 0.8 % slower
+    // on the narrow ones of the LiH-like cell)
+    if (!whole && tid == 0) row_chunks(sCS, nfe, lo0, hi0, lo1, hi1, Q, NT, NW == 8 ? nfu : -1, sChunk, sNChunk);
+    if (nli > 0) phase1(0, sV);
+    __syncthreads();
 
     for (uint32_t lb = 0, st = 0; lb < nli; lb += Q, st ^= 1) {
         double *sVc = sV + st * Q;
@@ -1015,7 +1055,7 @@ hipError_t init_contract_attributes() {
 }
 
 size_t contract_wide_lds_bytes(int rows, int nfun, int nimg, int nleaf, int n3) {
-    return ContractLds<kWideQ>::bytes(rows, nfun, nimg, nleaf, n3);
+    return ContractLds<kWideQ>::bytes(rows, nfun, nimg, nleaf, n3) + sizeof(int) * 4 * kWideWaves;
 }
 
 hipError_t launch_contract_wide(int lmax, bool gen, const KParams &kp, int n_items, const ItemDev *items,

@@ -308,15 +308,36 @@ __device__ __forceinline__ void corner_starts(const PUFE_GLOBAL int32_t *ed, int
 // [lo1, hi1) of the element's local functions): runs of one PU corner's
 // entries, cut to about nt / q rows' worth of (chunk, point) units so that a
 // stage's units fill the work group once; packed as corner | first entry << 3
-// | end entry << 13.  cs: corner starts (corner_starts).  One thread.
+// | end entry << 13.  cs: corner starts (corner_starts); nfu: FE units of the
+// item, which take the first units of a pass (-1: no one-pass widening).
+// One thread.
 __device__ __forceinline__ void row_chunks(const int *cs, int nfe, int lo0, int hi0, int lo1, int hi1, int q, int nt,
-                                           int *chunk, int *count) {
+                                           int nfu, int *chunk, int *count) {
     const int e0 = max(lo0 - nfe, 0), e1 = max(hi0 - nfe, 0), f0 = max(lo1 - nfe, 0), f1 = max(hi1 - nfe, 0);
     const int total = (e1 - e0) + (f1 - f0);
     // rows per chunk: the item's (row, point) work spread over one pass of
     // the work group, at least 4 rows, and few enough chunks for the table
     int ch = (total * q + nt - 1) / nt;
     ch = max(ch, max(4, (total + kMaxRowChunks - 17) / (kMaxRowChunks - 16)));
+    // The runs are cut per PU corner, so these chunks can overflow one pass
+    // (nt / q units, nfu of them the FE units) by a few: a second pass then
+    // doubles the stage's row time for a handful of units.  With nfu >= 0,
+    // longer chunks, up to twice as long, that fit one pass are taken
+    // instead (nfu < 0 keeps the chunks as cut).
+    auto chunks_of = [&](int len) {
+        int m = 0;
+        for (int r = 0; r < 2; ++r) {
+            const int b = r ? f0 : e0, e = r ? f1 : e1;
+            for (int c = 0; c < 8; ++c) m += (max(min(cs[c + 1], e) - max(cs[c], b), 0) + len - 1) / len;
+        }
+        return m;
+    };
+    const int room = min(nt / q - nfu, kMaxRowChunks);
+    if (nfu >= 0 && total > 0 && room > 0 && chunks_of(ch) > room) {
+        int c2 = ch + 1;
+        while (c2 < 2 * ch && chunks_of(c2) > room) ++c2;
+        if (c2 < 2 * ch) ch = c2;
+    }
     int n = 0;
     for (int r = 0; r < 2; ++r) {
         const int b = r ? f0 : e0, e = r ? f1 : e1;
