@@ -305,3 +305,6 @@ def test_element_function_limits():
     assert try_plan(W.limit_cell(1), bloch=True) == 8 + 64
     _expect(-2, lambda: try_plan(W.limit_cell(1, extra_h=True), bloch=True))
     assert oracle.Oracle(W.limit_cell(2)).element_dofs(0)[0].size == 8 + 64
+    # 24 groups of mixed l on every element (44 functions on each of two vertices)
+    assert try_plan(W.many_groups_cell()) == 8 + 88
+    assert oracle.Oracle(W.many_groups_cell()).element_dofs(0)[0].size == 8 + 88

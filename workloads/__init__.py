@@ -288,6 +288,26 @@ def limit_cell(n_ce: int = 2, extra_h: bool = False):
                     [[0.0, 0.0, 0.0]], 4, "limit_cell_%d%s" % (n_ce, "_h" if extra_h else ""))
 
 
+def many_groups_cell():
+    """A 2^3 trilinear cube (a = 4.4) with one atom halfway between two
+    vertices (re = 1.2 reaches both and no other) carrying 24 enrichment
+    descriptors: 17 of l = 0, 5 of l = 1 and one each of l = 2 and 3
+    (exponents spread over 0.3-3.0), so every element holds 24 groups and 44
+    functions on each of two vertices, n_loc = 96 (six 16-row tiles).  Four
+    waves' worth of groups per l would need nine waves of four 16-lane
+    slots: the case where a wide work group packs its enrichment groups
+    without giving each l waves of its own."""
+    a = 4.4
+    enr = []
+    for l, m in ((0, 17), (1, 5), (2, 1), (3, 1)):
+        for ex in np.geomspace(0.3, 3.0, m) if m > 1 else [1.0]:
+            enr.append({"species": 0, "l": l, "a": float(ex), "rc": 3.0, "re": 1.2})
+    return _problem(cubic(a), (2, 2, 2), 1, [[1.1, 0.03, 0.02]], [0],
+                    [{"name": "X", "Z": 4.0, "rloc": 0.4}], enr,
+                    {"n": 3, "n_ref": 6, "levels": 1, "mode": "geom", "dist": 0.6, "tol": 1e-6},
+                    [[0.0, 0.0, 0.0]], 4, "many_groups_cell")
+
+
 def with_bloch_enrichment(prob):
     """A copy of prob whose enrichment functions are Bloch-periodic (eq. Psi
     with f(R) = exp(i k.R)); its PU functions are then periodic and its
