@@ -293,10 +293,10 @@ def many_groups_cell():
     vertices (re = 1.2 reaches both and no other) carrying 24 enrichment
     descriptors: 17 of l = 0, 5 of l = 1 and one each of l = 2 and 3
     (exponents spread over 0.3-3.0), so every element holds 24 groups and 44
-    functions on each of two vertices, n_loc = 96 (six 16-row tiles).  Four
-    waves' worth of groups per l would need nine waves of four 16-lane
-    slots: the case where a wide work group packs its enrichment groups
-    without giving each l waves of its own."""
+    functions on each of two vertices, n_loc = 96 (six 16-row tiles).  Giving
+    each l waves of its own would take nine waves of four 16-lane slots, one
+    more than a wide work group has: the case where its enrichment schedule
+    packs the groups instead."""
     a = 4.4
     enr = []
     for l, m in ((0, 17), (1, 5), (2, 1), (3, 1)):
