@@ -608,7 +608,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: the assembly has no multi-GPU path in this build "
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path "
               f"(asked for {args.gpus}); run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
